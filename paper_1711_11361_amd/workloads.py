@@ -1,0 +1,214 @@
+"""Seeded synthetic workloads shaped like the paper's tests (input construction only).
+
+Nothing here computes any part of the cut-cell method: it only builds grids, body polygons
+(in the body frame), prescribed motions and primitive initial fields.  Both the GPU tests
+and the CPU oracle read workloads from this module, so that the two sides always see
+identical inputs.
+
+Workloads (non-dimensional stand-ins for the paper's SI set-ups):
+
+* ``piston``   -- a half-plane piston inclined at 30 degrees driven into gas at rest
+                  (the set-up of the paper's shock-tube piston, Sec. 3.5, made planar);
+* ``cylinder`` -- a circular cylinder crossing a stationary Mach-2 shock (Sec. 3.2);
+* ``triangle`` -- an equilateral-triangle cylinder crossing the same shock (Sec. 3.3),
+                  orientation and speed drawn per seed;
+* ``naca``     -- a NACA 0012 aerofoil pitching about its quarter chord in a Mach-0.7
+                  free stream (Sec. 3.4);
+* ``serving_request`` -- the mixed request population of the serving benchmark.
+"""
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+# --------------------------------------------------------------------------- grids / fields
+def grid(nx, ny, x_lo, x_hi, y_lo, y_hi, bc=(0, 0, 0, 0), gamma=GAMMA):
+    return {"nx": int(nx), "ny": int(ny), "x_lo": float(x_lo), "x_hi": float(x_hi),
+            "y_lo": float(y_lo), "y_hi": float(y_hi), "bc": tuple(int(b) for b in bc),
+            "gamma": float(gamma)}
+
+
+def cell_centres(g):
+    hx = (g["x_hi"] - g["x_lo"]) / g["nx"]
+    hy = (g["y_hi"] - g["y_lo"]) / g["ny"]
+    xc = g["x_lo"] + (np.arange(g["nx"]) + 0.5) * hx
+    yc = g["y_lo"] + (np.arange(g["ny"]) + 0.5) * hy
+    return np.meshgrid(xc, yc)
+
+
+def uniform_prim(g, rho, u, v, p):
+    prim = np.empty((4, g["ny"], g["nx"]))
+    prim[0], prim[1], prim[2], prim[3] = rho, u, v, p
+    return prim
+
+
+def split_prim(g, x_split, left, right):
+    """Two primitive states (rho, u, v, p) separated by the vertical line x = x_split,
+    assigned by cell centre."""
+    X, _ = cell_centres(g)
+    prim = np.empty((4, g["ny"], g["nx"]))
+    lm = X < x_split
+    for k in range(4):
+        prim[k] = np.where(lm, left[k], right[k])
+    return prim
+
+
+def mach2_stationary_shock(gamma=GAMMA):
+    """Upstream (rho=1, p=1, Mach 2) and the Rankine-Hugoniot downstream state of a
+    stationary normal shock, as (rho, u, v, p) tuples."""
+    rho1, p1 = 1.0, 1.0
+    u1 = 2.0 * math.sqrt(gamma * p1 / rho1)
+    M2 = 4.0
+    r = (gamma + 1.0) * M2 / ((gamma - 1.0) * M2 + 2.0)
+    pr = 1.0 + 2.0 * gamma * (M2 - 1.0) / (gamma + 1.0)
+    return (rho1, u1, 0.0, p1), (rho1 * r, u1 / r, 0.0, p1 * pr)
+
+
+# --------------------------------------------------------------------------- body polygons
+def circle(r, n=1024):
+    """Regular n-gon inscribed in a circle of radius r, counter-clockwise."""
+    k = np.arange(n)
+    a = 2.0 * np.pi * k / n
+    return np.stack([r * np.cos(a), r * np.sin(a)], axis=1)
+
+
+def triangle(side):
+    """Equilateral triangle with its centroid at the origin, counter-clockwise."""
+    R = side / math.sqrt(3.0)
+    a = np.deg2rad(np.array([90.0, 210.0, 330.0]))
+    return np.stack([R * np.cos(a), R * np.sin(a)], axis=1)
+
+
+def naca00(thickness, chord=1.0, n_side=512, pivot=0.25):
+    """Symmetric NACA 4-digit section with a closed trailing edge (reading: last
+    coefficient -0.1036), leading edge at x = -pivot*chord, body-frame origin at the pivot.
+    Cosine-spaced, n_side points per surface (shared leading and trailing edges),
+    counter-clockwise (upper surface from trailing to leading edge, then lower)."""
+    k = np.arange(n_side)
+    x = 0.5 * (1.0 + np.cos(np.pi * k / (n_side - 1)))  # 1 -> 0
+    t = thickness
+    yt = 5.0 * t * (0.2969 * np.sqrt(x) - 0.1260 * x - 0.3516 * x ** 2 + 0.2843 * x ** 3
+                    - 0.1036 * x ** 4)
+    yt[0] = 0.0
+    yt[-1] = 0.0
+    upper = np.stack([x, yt], axis=1)
+    lower = np.stack([x[::-1][1:-1], -yt[::-1][1:-1]], axis=1)
+    pts = np.concatenate([upper, lower], axis=0)
+    pts[:, 0] = (pts[:, 0] - pivot) * chord
+    pts[:, 1] = pts[:, 1] * chord
+    return pts
+
+
+def half_plane_quad(L=2.0):
+    """A large quad standing in for the half-plane {x_b <= 0} of the body frame."""
+    return np.array([[-L, -L], [0.0, -L], [0.0, L], [-L, L]])
+
+
+def body(verts, ref=(0.0, 0.0), theta0=0.0, vel=(0.0, 0.0), pitch_amp=0.0, pitch_omega=0.0):
+    return {"verts": np.ascontiguousarray(verts, dtype=np.float64), "ref": tuple(map(float, ref)),
+            "theta0": float(theta0), "vel": tuple(map(float, vel)),
+            "pitch_amp": float(pitch_amp), "pitch_omega": float(pitch_omega)}
+
+
+# --------------------------------------------------------------------------- workloads
+def piston(nx=200, ny=20, angle_deg=30.0, speed=0.3, face=(0.1, 0.05), bc=(0, 0, 0, 0)):
+    """Inclined piston into quiescent gas: domain [0,1]x[0,0.1], rho=1, u=v=0, p=1; the
+    piston face passes through `face` with normal at `angle_deg` and moves along it."""
+    g = grid(nx, ny, 0.0, 1.0, 0.0, 0.1, bc=bc)
+    th = math.radians(angle_deg)
+    n = (math.cos(th), math.sin(th))
+    b = body(half_plane_quad(2.0), ref=face, theta0=th, vel=(speed * n[0], speed * n[1]))
+    return {"name": "piston", "grid": g, "body": b, "prim": uniform_prim(g, 1.0, 0.0, 0.0, 1.0),
+            "cfl": 0.8, "t_end": 0.5, "normal": n, "speed": speed, "face": face}
+
+
+def cylinder(nx=1024, ny=512, radius=0.1, centre=(0.5, 0.5), speed=1.0, n_poly=1024):
+    """Circular cylinder crossing a stationary Mach-2 shock at x = 1 on [0,2]x[0,1]."""
+    g = grid(nx, ny, 0.0, 2.0, 0.0, 1.0)
+    up, down = mach2_stationary_shock()
+    b = body(circle(radius, n_poly), ref=centre, vel=(speed, 0.0))
+    return {"name": "cylinder", "grid": g, "body": b, "prim": split_prim(g, 1.0, up, down),
+            "cfl": 0.8, "steps": 2000}
+
+
+def triangle_case(seed, nx=2048, ny=1024, side=0.2, centre=(0.5, 0.5)):
+    """Equilateral triangle crossing the Mach-2 stationary shock; orientation uniform in
+    [0, 60) degrees and speed uniform in [0.5, 1.5] drawn from the seed."""
+    rng = np.random.default_rng(seed)
+    ang = math.radians(rng.uniform(0.0, 60.0))
+    spd = rng.uniform(0.5, 1.5)
+    g = grid(nx, ny, 0.0, 2.0, 0.0, 1.0)
+    up, down = mach2_stationary_shock()
+    b = body(triangle(side), ref=centre, theta0=ang, vel=(spd, 0.0))
+    return {"name": "triangle", "grid": g, "body": b, "prim": split_prim(g, 1.0, up, down),
+            "cfl": 0.8, "steps": 2000, "seed": seed}
+
+
+def naca(nx=4096, ny=4096, amp_deg=2.0, reduced_freq=0.1, mach=0.7, n_side=512):
+    """NACA 0012, chord 1, leading edge at the origin, pitching about the quarter chord
+    theta(t) = amp sin(omega t), omega = 2 k U / c, in a free stream rho=1, p=1/gamma."""
+    g = grid(nx, ny, -2.0, 4.0, -3.0, 3.0)
+    U = mach
+    omega = 2.0 * reduced_freq * U / 1.0
+    b = body(naca00(0.12, 1.0, n_side, 0.25), ref=(0.25, 0.0), pitch_amp=math.radians(amp_deg),
+             pitch_omega=omega)
+    period = 2.0 * math.pi / omega
+    return {"name": "naca", "grid": g, "body": b,
+            "prim": uniform_prim(g, 1.0, U, 0.0, 1.0 / GAMMA), "cfl": 0.8,
+            "t_end": 3.0 * period}
+
+
+SERVING_GRIDS = ((64, 64), (256, 128), (512, 512), (1024, 512))
+
+
+def serving_request(k):
+    """Request k of the serving mix, drawn from numpy's default_rng(1000 + k).
+
+    Grid from SERVING_GRIDS (square cells: domain [0, nx/ny] x [0, 1]); body one of circle,
+    triangle, NACA 00t (chord 0.3) or inclined piston, centred at (0.25 x_extent, 0.5);
+    motion a translation along +x (speed in [0.2, 1.5]) or a pitch oscillation (amplitude
+    1-4 degrees, reduced frequency 0.05-0.2); initial state quiescent or the Mach-2
+    stationary shock at x_extent/2.  500 steps each."""
+    rng = np.random.default_rng(1000 + k)
+    nx, ny = SERVING_GRIDS[rng.integers(len(SERVING_GRIDS))]
+    xe = nx / ny
+    g = grid(nx, ny, 0.0, xe, 0.0, 1.0)
+    kind = ["circle", "triangle", "naca", "piston"][rng.integers(4)]
+    motion = ["translate", "pitch"][rng.integers(2)]
+    centre = (0.25 * xe, 0.5)
+    speed = rng.uniform(0.2, 1.5)
+    amp = math.radians(rng.uniform(1.0, 4.0))
+    kred = rng.uniform(0.05, 0.2)
+    if kind == "circle":
+        verts = circle(rng.uniform(0.05, 0.15), 256)
+        chord = 0.3
+    elif kind == "triangle":
+        verts = triangle(rng.uniform(0.1, 0.25))
+        chord = 0.25
+    elif kind == "naca":
+        chord = 0.3
+        verts = naca00(rng.uniform(0.09, 0.15), chord, 128, 0.25)
+    else:
+        chord = 0.3
+        verts = half_plane_quad(4.0)
+        centre = (0.1 * xe, 0.5)
+    theta0 = 0.0
+    if kind == "piston":
+        theta0 = math.radians(rng.uniform(0.0, 60.0))
+    shock = bool(rng.integers(2))
+    if motion == "translate":
+        vel = (speed, 0.0) if kind != "piston" else (speed * math.cos(theta0), speed * math.sin(theta0))
+        b = body(verts, ref=centre, theta0=theta0, vel=vel)
+    else:
+        U = 1.0
+        b = body(verts, ref=centre, theta0=theta0, pitch_amp=amp,
+                 pitch_omega=2.0 * kred * U / chord)
+    if shock:
+        up, down = mach2_stationary_shock()
+        prim = split_prim(g, 0.5 * xe, up, down)
+    else:
+        prim = uniform_prim(g, 1.0, 0.0, 0.0, 1.0)
+    return {"name": f"req{k}", "grid": g, "body": b, "prim": prim, "cfl": 0.8, "steps": 500,
+            "kind": kind, "motion": motion}
