@@ -1,0 +1,141 @@
+/*
+ * cc.h -- C ABI of the MI355X cut-cell library (libcutcell.so).
+ *
+ * One dimensionally split finite-volume step of the 2D Euler equations on a uniform
+ * Cartesian grid around a rigid convex body that moves every step, with the moving-
+ * boundary flux stabilisation of Bennett, Nikiforakis & Klein (arXiv:1711.11361):
+ *   - cut-cell geometry of the body at the old, intermediate and new time levels
+ *     (Sec. 2.1: volume fractions; Sec. 2.2: face apertures and shielded volumes;
+ *      Sec. 2.3.4: time-averaged apertures, Eq. timeAveragedBeta);
+ *   - per sweep: MUSCL-Hancock + HLLC "standard" fluxes on every face, a moving-wall
+ *     Riemann problem per cut cell (Eq. riemann_wallvel), the stabilised shielded fluxes
+ *     (Eqs. Klein2shieldedFluxMethod2, ModifiedBoundaryFluxMethod2,
+ *      Klein2DtotalfluxaMethod2), the conservative update
+ *     (Eqs. Klein2DcompleteMovingMethod2a/b) and the treatment of cells that are
+ *     uncovered or covered (Eqs. volumeWeighting ... cutCellCoverDonation, Sec. 2.3.5);
+ *   - sweeps alternate x-y / y-x from step to step (Sec. 2.3.4, end);
+ *   - a global CFL time step from the regular cell size (Sec. 4).
+ *
+ * Conventions
+ *   Memory: the caller allocates every device byte.  cc_workspace_bytes() gives the exact
+ *     size of the workspace passed to cc_create(); the library never allocates device
+ *     memory.  Host pointers are read only during the call.
+ *   Layout: fields are structure-of-arrays planes of nx*ny values, row-major (index
+ *     j*nx + i, cell (i, j) spans [x_lo + i hx, x_lo + (i+1) hx] x [...]).  Conserved
+ *     planes are (rho, rho u, rho v, E) per unit CELL volume (U = alpha Q); primitive
+ *     planes are (rho, u, v, p).
+ *   Streams: every call is asynchronous on the stream given to cc_create() unless it
+ *     returns host data (cc_cfl_dt, cc_totals, cc_info, cc_timing_read), which
+ *     synchronises that stream.
+ *   Errors: functions return cc_status and never abort.  Argument errors are detected
+ *     synchronously; device-detected state errors (no donor for a cell that becomes
+ *     fluid, non-finite or non-physical states) are reported by the next synchronising
+ *     call.  cc_last_error() gives a message.
+ *   Threads: one context must not be used from two host threads at once.
+ */
+#ifndef CC_H
+#define CC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cc_ctx cc_ctx; /* opaque */
+
+typedef enum {
+    CC_OK = 0,
+    CC_ERR_ARG = 1,         /* invalid argument or call order */
+    CC_ERR_DEVICE = 2,      /* HIP runtime error */
+    CC_ERR_WORKSPACE = 3,   /* workspace too small, or the body outgrew the staging capacity */
+    CC_ERR_STATE = 4,       /* non-finite/non-physical state or a cell without donors */
+    CC_ERR_MOTION = 5,      /* the body moves one cell or more within a sweep, or dt <= 0 */
+    CC_ERR_UNSUPPORTED = 6
+} cc_status;
+
+typedef enum { CC_FP64 = 0, CC_FP32_GEOM64 = 1 } cc_precision;
+typedef enum { CC_BC_TRANSMISSIVE = 0, CC_BC_REFLECTIVE = 1 } cc_bc;
+
+typedef struct {
+    int32_t nx, ny;
+    int32_t bc[4];      /* W, E, S, N (cc_bc) */
+    int32_t precision;  /* cc_precision: FP64 state, or FP32 state and dense fluxes with FP64
+                           geometry and FP64 cut-cell arithmetic */
+    int32_t reserved;   /* must be 0 */
+    double x_lo, x_hi, y_lo, y_hi;
+    double gamma;       /* ratio of specific heats (perfect gas, Sec. 2.1) */
+} cc_config;
+
+typedef struct {
+    int32_t nverts;      /* 0: no body */
+    int32_t pad_;
+    const double* verts; /* body-frame convex polygon, counter-clockwise, (x, y) pairs; host */
+    double ref_x, ref_y; /* position of the body-frame origin at t = 0 */
+    double theta0;       /* body angle at t = 0 (radians, counter-clockwise) */
+    double vx, vy;       /* constant translation velocity */
+    double pitch_amp, pitch_omega; /* theta(t) = theta0 + pitch_amp sin(pitch_omega t) */
+} cc_body;
+
+/* Exact device bytes needed by cc_create() for this grid and body (state, three geometry
+ * levels, staging for the body's region, reductions). */
+size_t cc_workspace_bytes(const cc_config* cfg, const cc_body* body);
+
+/* Create a context on the current device.  d_ws: device workspace of ws_bytes (>=
+ * cc_workspace_bytes), 256-byte aligned, owned by the caller until cc_destroy().
+ * hip_stream: a hipStream_t (NULL = default stream). */
+cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_t ws_bytes, void* hip_stream,
+                    cc_ctx** out);
+cc_status cc_destroy(cc_ctx* ctx);
+
+/* Initial state: body posed at time t0, level-n geometry built, U = alpha Q(prim).
+ * d_prim: device, 4 planes (rho, u, v, p) of nx*ny doubles. */
+cc_status cc_set_state(cc_ctx* ctx, const double* d_prim, double t0);
+/* Replace the conserved state (device, 4 planes of nx*ny doubles, per unit cell volume). */
+cc_status cc_set_u(cc_ctx* ctx, const double* d_u);
+/* Copy the level-n state out: what = 0 primitive (rho, u, v, p; zeros in solid or empty
+ * cells), what = 1 conserved U.  d_out: device, 4*nx*ny doubles. */
+cc_status cc_get_state(cc_ctx* ctx, double* d_out, int32_t what);
+
+/* Cut-cell geometry of the body posed at time t into a level: level 0 = level n (the one
+ * the state refers to), 1 = stage level, 2 = level n+1. */
+cc_status cc_geometry(cc_ctx* ctx, double t, int32_t level);
+/* Copy a level out (device pointers, any may be NULL): vertex classes (int8,
+ * (ny+1)*(nx+1), 1 = solid), volume fractions (nx*ny), x-face apertures (ny*(nx+1)),
+ * y-face apertures ((ny+1)*nx). */
+cc_status cc_geometry_dump(cc_ctx* ctx, int32_t level, int8_t* d_vcls, double* d_alpha, double* d_bx,
+                           double* d_by);
+
+/* Split step in parts: cc_begin_step poses the body at t + dt and builds the stage level
+ * (the first sweep's direction moves the polygon, the other coordinate stays) and level
+ * n+1; cc_sweep runs the next sweep (dir 0 = x, 1 = y; x first on even steps, y first on
+ * odd steps); cc_end_step makes level n+1 the new level n and advances time. */
+cc_status cc_begin_step(cc_ctx* ctx, double dt);
+cc_status cc_sweep(cc_ctx* ctx, int32_t dir, double dt);
+cc_status cc_end_step(cc_ctx* ctx);
+/* One full split step of size dt. */
+cc_status cc_step(cc_ctx* ctx, double dt);
+
+/* Global time step dt = cfl * min(hx / Sx, hy / Sy), S the largest signal speed |u|+a
+ * over live cells and |u_wall| over the body's vertices.  Synchronises; h_dt: host. */
+cc_status cc_cfl_dt(cc_ctx* ctx, double cfl, double* h_dt);
+
+/* Conservation totals sum(U) hx hy per component, FP64, deterministic order.  Host out. */
+cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
+
+/* Host info vector (n entries used, up to 8): time, steps, parity, device status bits,
+ * collapsed-cell count, sweep box cells of the last sweep, staging capacity, spare. */
+cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
+
+/* Per-kernel timing with HIP events on the context's stream.  cc_timing(ctx, 1) starts
+ * recording; cc_timing_read returns, since the last read, pairs (total ms, launches) for:
+ * dense x, dense y, box kernels, geometry (8 doubles). */
+cc_status cc_timing(cc_ctx* ctx, int32_t enable);
+cc_status cc_timing_read(cc_ctx* ctx, double* h_out, int32_t n);
+
+const char* cc_last_error(const cc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CC_H */

@@ -1,0 +1,298 @@
+"""ctypes binding of libcutcell.so (C ABI in include/cc.h), with the same function names.
+
+Only argument marshalling happens here: device memory comes from torch tensors (their
+data pointers and the current HIP stream are passed through); every step of the method
+runs in the library's kernels.  Importing fails loudly when the library is missing.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libcutcell.so")
+
+CC_OK, CC_ERR_ARG, CC_ERR_DEVICE, CC_ERR_WORKSPACE, CC_ERR_STATE, CC_ERR_MOTION, CC_ERR_UNSUPPORTED = range(7)
+CC_FP64, CC_FP32_GEOM64 = 0, 1
+STATUS_NAMES = {0: "CC_OK", 1: "CC_ERR_ARG", 2: "CC_ERR_DEVICE", 3: "CC_ERR_WORKSPACE", 4: "CC_ERR_STATE",
+                5: "CC_ERR_MOTION", 6: "CC_ERR_UNSUPPORTED"}
+
+
+class cc_config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4), ("precision", C.c_int32),
+                ("reserved", C.c_int32), ("x_lo", C.c_double), ("x_hi", C.c_double), ("y_lo", C.c_double),
+                ("y_hi", C.c_double), ("gamma", C.c_double)]
+
+
+class cc_body(C.Structure):
+    _fields_ = [("nverts", C.c_int32), ("pad_", C.c_int32), ("verts", C.POINTER(C.c_double)),
+                ("ref_x", C.c_double), ("ref_y", C.c_double), ("theta0", C.c_double), ("vx", C.c_double),
+                ("vy", C.c_double), ("pitch_amp", C.c_double), ("pitch_omega", C.c_double)]
+
+
+class CCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"libcutcell.so not built ({LIBPATH}); run paper_1711_11361_amd/build.py")
+
+_lib = C.CDLL(LIBPATH)
+_vp, _d, _i32 = C.c_void_p, C.c_double, C.c_int32
+_sig = {
+    "cc_workspace_bytes": (C.c_size_t, [C.POINTER(cc_config), C.POINTER(cc_body)]),
+    "cc_create": (C.c_int, [C.POINTER(cc_config), C.POINTER(cc_body), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "cc_destroy": (C.c_int, [_vp]),
+    "cc_set_state": (C.c_int, [_vp, _vp, _d]),
+    "cc_set_u": (C.c_int, [_vp, _vp]),
+    "cc_get_state": (C.c_int, [_vp, _vp, _i32]),
+    "cc_geometry": (C.c_int, [_vp, _d, _i32]),
+    "cc_geometry_dump": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "cc_begin_step": (C.c_int, [_vp, _d]),
+    "cc_sweep": (C.c_int, [_vp, _i32, _d]),
+    "cc_end_step": (C.c_int, [_vp]),
+    "cc_step": (C.c_int, [_vp, _d]),
+    "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
+    "cc_totals": (C.c_int, [_vp, C.POINTER(_d)]),
+    "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
+    "cc_timing": (C.c_int, [_vp, _i32]),
+    "cc_timing_read": (C.c_int, [_vp, C.POINTER(_d), _i32]),
+    "cc_last_error": (C.c_char_p, [_vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def _check(ctx, st):
+    if st != CC_OK:
+        msg = _lib.cc_last_error(ctx).decode() if ctx else ""
+        raise CCError(st, msg)
+
+
+def make_config(grid, precision=CC_FP64):
+    c = cc_config()
+    c.nx, c.ny = grid["nx"], grid["ny"]
+    for k, v in enumerate(grid.get("bc", (0, 0, 0, 0))):
+        c.bc[k] = v
+    c.precision = precision
+    c.reserved = 0
+    c.x_lo, c.x_hi, c.y_lo, c.y_hi = grid["x_lo"], grid["x_hi"], grid["y_lo"], grid["y_hi"]
+    c.gamma = grid.get("gamma", 1.4)
+    return c
+
+
+def make_body(body):
+    b = cc_body()
+    keep = None
+    if body is not None and len(body["verts"]) > 0:
+        keep = np.ascontiguousarray(np.asarray(body["verts"], dtype=np.float64).reshape(-1))
+        b.nverts = len(keep) // 2
+        b.verts = keep.ctypes.data_as(C.POINTER(C.c_double))
+        b.ref_x, b.ref_y = body.get("ref", (0.0, 0.0))
+        b.theta0 = body.get("theta0", 0.0)
+        b.vx, b.vy = body.get("vel", (0.0, 0.0))
+        b.pitch_amp = body.get("pitch_amp", 0.0)
+        b.pitch_omega = body.get("pitch_omega", 0.0)
+    return b, keep
+
+
+# ----------------------------------------------------------------- C-ABI mirrors
+def cc_workspace_bytes(cfg, body):
+    return _lib.cc_workspace_bytes(C.byref(cfg), C.byref(body))
+
+
+def cc_create(cfg, body, d_ws, ws_bytes, stream):
+    out = _vp()
+    _check(None, _lib.cc_create(C.byref(cfg), C.byref(body), _vp(d_ws), ws_bytes, _vp(stream), C.byref(out)))
+    return out
+
+
+def cc_destroy(ctx):
+    _check(None, _lib.cc_destroy(ctx))
+
+
+def cc_set_state(ctx, d_prim, t0):
+    _check(ctx, _lib.cc_set_state(ctx, _vp(d_prim), t0))
+
+
+def cc_set_u(ctx, d_u):
+    _check(ctx, _lib.cc_set_u(ctx, _vp(d_u)))
+
+
+def cc_get_state(ctx, d_out, what):
+    _check(ctx, _lib.cc_get_state(ctx, _vp(d_out), what))
+
+
+def cc_geometry(ctx, t, level):
+    _check(ctx, _lib.cc_geometry(ctx, t, level))
+
+
+def cc_geometry_dump(ctx, level, d_vcls, d_alpha, d_bx, d_by):
+    _check(ctx, _lib.cc_geometry_dump(ctx, level, _vp(d_vcls), _vp(d_alpha), _vp(d_bx), _vp(d_by)))
+
+
+def cc_begin_step(ctx, dt):
+    _check(ctx, _lib.cc_begin_step(ctx, dt))
+
+
+def cc_sweep(ctx, d, dt):
+    _check(ctx, _lib.cc_sweep(ctx, d, dt))
+
+
+def cc_end_step(ctx):
+    _check(ctx, _lib.cc_end_step(ctx))
+
+
+def cc_step(ctx, dt):
+    _check(ctx, _lib.cc_step(ctx, dt))
+
+
+def cc_cfl_dt(ctx, cfl):
+    out = _d()
+    _check(ctx, _lib.cc_cfl_dt(ctx, cfl, C.byref(out)))
+    return out.value
+
+
+def cc_totals(ctx):
+    out = (_d * 4)()
+    _check(ctx, _lib.cc_totals(ctx, out))
+    return np.array(out[:])
+
+
+def cc_info(ctx):
+    out = (_d * 8)()
+    _check(ctx, _lib.cc_info(ctx, out, 8))
+    v = out[:]
+    return {"t": v[0], "steps": int(v[1]), "parity": int(v[2]), "status": int(v[3]), "collapses": int(v[4]),
+            "box_cells": int(v[5]), "capacity": int(v[6])}
+
+
+def cc_timing(ctx, enable):
+    _check(ctx, _lib.cc_timing(ctx, int(enable)))
+
+
+def cc_timing_read(ctx):
+    out = (_d * 8)()
+    _check(ctx, _lib.cc_timing_read(ctx, out, 8))
+    v = out[:]
+    return {"dense_x": (v[0], v[1]), "dense_y": (v[2], v[3]), "box": (v[4], v[5]), "geometry": (v[6], v[7])}
+
+
+# ----------------------------------------------------------------- torch-backed solver
+class Solver:
+    """A simulation context whose device memory (workspace, I/O buffers) is owned by torch
+    on `device`, launched on torch's current stream for that device."""
+
+    def __init__(self, grid, body=None, precision=CC_FP64, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.grid = dict(grid)
+        self.nx, self.ny = grid["nx"], grid["ny"]
+        self.device = torch.device(device)
+        self._cfg = make_config(grid, precision)
+        self._body, self._verts = make_body(body)
+        self.ws_bytes = cc_workspace_bytes(self._cfg, self._body)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = cc_create(self._cfg, self._body, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        self._io = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            cc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_prim(self, prim, t0=0.0):
+        self._io.copy_(self.torch.as_tensor(np.asarray(prim, dtype=np.float64).reshape(4, self.ny, self.nx)))
+        cc_set_state(self.ctx, self._io.data_ptr(), t0)
+
+    def set_u(self, U):
+        self._io.copy_(self.torch.as_tensor(np.asarray(U, dtype=np.float64).reshape(4, self.ny, self.nx)))
+        cc_set_u(self.ctx, self._io.data_ptr())
+
+    def get_u_tensor(self):
+        out = self.torch.empty((4, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+        cc_get_state(self.ctx, out.data_ptr(), 1)
+        return out
+
+    def get_u(self):
+        return self.get_u_tensor().cpu().numpy()
+
+    def get_prim(self):
+        out = self.torch.empty((4, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+        cc_get_state(self.ctx, out.data_ptr(), 0)
+        return out.cpu().numpy()
+
+    def geometry(self, t, level=0):
+        cc_geometry(self.ctx, t, level)
+
+    def geometry_dump(self, level=0):
+        t = self.torch
+        nx, ny = self.nx, self.ny
+        vc = t.empty((ny + 1, nx + 1), dtype=t.int8, device=self.device)
+        al = t.empty((ny, nx), dtype=t.float64, device=self.device)
+        bx = t.empty((ny, nx + 1), dtype=t.float64, device=self.device)
+        by = t.empty((ny + 1, nx), dtype=t.float64, device=self.device)
+        cc_geometry_dump(self.ctx, level, vc.data_ptr(), al.data_ptr(), bx.data_ptr(), by.data_ptr())
+        return {"vcls": vc.cpu().numpy(), "alpha": al.cpu().numpy(), "bx": bx.cpu().numpy(), "by": by.cpu().numpy()}
+
+    def begin_step(self, dt):
+        cc_begin_step(self.ctx, dt)
+
+    def sweep(self, d, dt):
+        cc_sweep(self.ctx, d, dt)
+
+    def end_step(self):
+        cc_end_step(self.ctx)
+
+    def step(self, dt):
+        cc_step(self.ctx, dt)
+
+    def cfl_dt(self, cfl):
+        return cc_cfl_dt(self.ctx, cfl)
+
+    def totals(self):
+        return cc_totals(self.ctx)
+
+    def info(self):
+        return cc_info(self.ctx)
+
+    @property
+    def parity(self):
+        return self.info()["parity"]
+
+    def run(self, cfl, nsteps=None, t_end=None, dts=None):
+        used = []
+        k = 0
+        while True:
+            if dts is not None:
+                if k >= len(dts):
+                    break
+                dt = dts[k]
+            else:
+                if nsteps is not None and k >= nsteps:
+                    break
+                dt = self.cfl_dt(cfl)
+                if t_end is not None:
+                    t = self.info()["t"]
+                    if t >= t_end * (1 - 1e-14):
+                        break
+                    dt = min(dt, t_end - t)
+            self.step(dt)
+            used.append(dt)
+            k += 1
+        return used

@@ -1,0 +1,172 @@
+// Device-side data views and numerical building blocks of the cut-cell split step.
+//
+// Gas model (Sec. 2.1): Q = (rho, rho u, rho v, E), p = (gamma-1)(E - |m|^2 / (2 rho)).
+// Numerical flux (Sec. 2.3.5 end): MUSCL-Hancock with a van Leer limiter on the
+// conserved variables, HLLC with Davis wave-speed estimates.
+// Geometry (Sec. 2.1-2.2): vertex classes, face solid intervals, cut-cell volume
+// fractions of a convex polygon on a uniform Cartesian grid.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cc {
+
+enum { FLUID = 0, SOLID = 1 };
+
+struct Grid {
+    int nx, ny;
+    int bc[4];  // W, E, S, N: 0 zero-gradient, 1 reflective
+    double x_lo, y_lo, hx, hy;
+    double gamma;
+};
+
+// Cell index box, half-open [i0, i1) x [j0, j1).
+struct Box {
+    int i0, i1, j0, j1;
+    __host__ __device__ int w() const { return i1 - i0; }
+    __host__ __device__ int h() const { return j1 - j0; }
+    __host__ __device__ bool has(int i, int j) const { return i >= i0 && i < i1 && j >= j0 && j < j1; }
+};
+
+// Posed convex polygon of one level (device copy) and quick-test data.
+struct Poly {
+    const double* v;  // 2*m, counter-clockwise
+    int m;
+    double xmin, xmax, ymin, ymax;  // bounding box
+    double cx, cy, rin2, rout2;     // certificate disc radii about (cx, cy); rin2 < 0: unused
+};
+
+// One level: vertex classes, face solid intervals (lo, hi) measured from the face's
+// low-index vertex, volume fractions.
+struct Level {
+    int8_t* vcls;  // (ny+1)*(nx+1)
+    double2* fx;   // ny*(nx+1): x-face (i, j) from vertex (i, j) to (i, j+1)
+    double2* fy;   // (ny+1)*nx: y-face (i, j) from vertex (i, j) to (i+1, j)
+    double* alpha; // ny*nx
+    Poly poly;
+};
+
+__device__ __forceinline__ double vx_of(const Grid& g, int i) { return g.x_lo + (double)i * g.hx; }
+__device__ __forceinline__ double vy_of(const Grid& g, int j) { return g.y_lo + (double)j * g.hy; }
+
+__device__ __forceinline__ double interval_beta(double2 iv) { return iv.y > iv.x ? 1.0 - (iv.y - iv.x) : 1.0; }
+
+__device__ __forceinline__ double beta_x(const Grid& g, const Level& L, int i, int j) {
+    return interval_beta(L.fx[(size_t)j * (g.nx + 1) + i]);
+}
+__device__ __forceinline__ double beta_y(const Grid& g, const Level& L, int i, int j) {
+    return interval_beta(L.fy[(size_t)j * g.nx + i]);
+}
+__device__ __forceinline__ double alpha_of(const Grid& g, const Level& L, int i, int j) {
+    return L.alpha[(size_t)j * g.nx + i];
+}
+
+__device__ __forceinline__ double orient(double ax, double ay, double bx, double by, double px, double py) {
+    return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+// ------------------------------------------------------------------------------ gas model
+template <typename T>
+__device__ __forceinline__ T pressure(const T q[4], T g) {
+    return (g - T(1)) * (q[3] - T(0.5) * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void euler_flux(const T q[4], T g, T f[4]) {
+    constexpr int n = 1 + D, t = 2 - D;
+    T p = pressure(q, g);
+    T un = q[n] / q[0];
+    f[0] = q[n];
+    f[n] = q[n] * un + p;
+    f[t] = q[t] * un;
+    f[3] = un * (q[3] + p);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void hllc(const T ql[4], const T qr[4], T g, T f[4]) {
+    constexpr int n = 1 + D, t = 2 - D;
+    T rl = ql[0], rr = qr[0];
+    T ul = ql[n] / rl, ur = qr[n] / rr;
+    T pl = pressure(ql, g), pr = pressure(qr, g);
+    T al = sqrt(g * pl / rl), ar = sqrt(g * pr / rr);
+    T sl = fmin(ul - al, ur - ar);
+    T sr = fmax(ul + al, ur + ar);
+    T ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) / (rl * (sl - ul) - rr * (sr - ur));
+    if (T(0) <= sl) {
+        euler_flux<T, D>(ql, g, f);
+    } else if (T(0) <= ss) {
+        T fl[4];
+        euler_flux<T, D>(ql, g, fl);
+        T c = rl * (sl - ul) / (sl - ss);
+        T us[4];
+        us[0] = c;
+        us[n] = c * ss;
+        us[t] = c * (ql[t] / rl);
+        us[3] = c * (ql[3] / rl + (ss - ul) * (ss + pl / (rl * (sl - ul))));
+#pragma unroll
+        for (int k = 0; k < 4; k++) f[k] = fl[k] + sl * (us[k] - ql[k]);
+    } else if (T(0) <= sr) {
+        T fr[4];
+        euler_flux<T, D>(qr, g, fr);
+        T c = rr * (sr - ur) / (sr - ss);
+        T us[4];
+        us[0] = c;
+        us[n] = c * ss;
+        us[t] = c * (qr[t] / rr);
+        us[3] = c * (qr[3] / rr + (ss - ur) * (ss + pr / (rr * (sr - ur))));
+#pragma unroll
+        for (int k = 0; k < 4; k++) f[k] = fr[k] + sr * (us[k] - qr[k]);
+    } else {
+        euler_flux<T, D>(qr, g, f);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T vanleer(T a, T b) {
+    return a * b > T(0) ? T(2) * a * b / (a + b) : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ bool admissible(const T q[4], T g) {
+    if (!(q[0] > T(0))) return false;
+    return pressure(q, g) > T(0);
+}
+
+// MUSCL-Hancock reconstruction and half-step evolution of one cell; el/er are the
+// evolved states at the cell's low and high faces.  Positivity fallback: drop the slope.
+template <typename T, int D>
+__device__ __forceinline__ void muscl(const T qm[4], const T q[4], const T qp[4], bool slope_ok, T lam, T g,
+                                      T el[4], T er[4]) {
+    T dl[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) dl[k] = slope_ok ? vanleer(q[k] - qm[k], qp[k] - q[k]) : T(0);
+    bool ok = true;
+    {
+        T ql[4], qr[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            ql[k] = q[k] - T(0.5) * dl[k];
+            qr[k] = q[k] + T(0.5) * dl[k];
+        }
+        ok = admissible(ql, g) && admissible(qr, g);
+        if (ok) {
+            T fl[4], fr[4];
+            euler_flux<T, D>(ql, g, fl);
+            euler_flux<T, D>(qr, g, fr);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                T c = T(0.5) * lam * (fl[k] - fr[k]);
+                el[k] = ql[k] + c;
+                er[k] = qr[k] + c;
+            }
+            ok = admissible(el, g) && admissible(er, g);
+        }
+    }
+    if (!ok) {
+        // flat profile: the half-step evolution of a constant state is the state itself
+#pragma unroll
+        for (int k = 0; k < 4; k++) el[k] = er[k] = q[k];
+    }
+}
+
+}  // namespace cc

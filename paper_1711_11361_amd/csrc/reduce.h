@@ -1,0 +1,145 @@
+// State conversion, global time-step reduction and conservation totals.
+#pragma once
+#include "cc_device.h"
+
+namespace cc {
+
+// U = alpha Q from primitive fields (rho, u, v, p), SoA planes of nx*ny doubles.
+template <typename R>
+__global__ void k_prim_to_u(Grid g, const double* __restrict__ alpha, const double* __restrict__ prim,
+                            R* __restrict__ U) {
+    size_t nc = (size_t)g.nx * g.ny;
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    double r = prim[k], u = prim[nc + k], v = prim[2 * nc + k], p = prim[3 * nc + k];
+    double a = alpha[k];
+    double q[4] = {r, r * u, r * v, p / (g.gamma - 1.0) + 0.5 * r * (u * u + v * v)};
+#pragma unroll
+    for (int m = 0; m < 4; m++) U[m * nc + k] = (R)(a * q[m]);
+}
+
+__global__ void k_fill_f64(size_t n, double v, double* __restrict__ p) {
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+// Apertures of a level's faces from their solid intervals.
+__global__ void k_interval_beta(size_t n, const double2* __restrict__ iv, double* __restrict__ beta) {
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) beta[k] = interval_beta(iv[k]);
+}
+
+template <typename R>
+__global__ void k_copy_u(size_t n, const double* __restrict__ src, R* __restrict__ dst) {
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = (R)src[k];
+}
+
+template <typename R>
+__global__ void k_u_to_f64(size_t n, const R* __restrict__ src, double* __restrict__ dst) {
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = (double)src[k];
+}
+
+// Primitive fields of the level-n state; solid or emptied cells give zeros.
+template <typename R>
+__global__ void k_u_to_prim(Grid g, const double* __restrict__ alpha, const R* __restrict__ U,
+                            double* __restrict__ prim) {
+    size_t nc = (size_t)g.nx * g.ny;
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    double a = alpha[k];
+    double q[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k];
+    if (a > 0.0 && q[0] > 0.0) {
+#pragma unroll
+        for (int m = 0; m < 4; m++) q[m] = q[m] / a;
+        prim[k] = q[0];
+        prim[nc + k] = q[1] / q[0];
+        prim[2 * nc + k] = q[2] / q[0];
+        prim[3 * nc + k] = pressure(q, g.gamma);
+    } else {
+        prim[k] = prim[nc + k] = prim[2 * nc + k] = prim[3 * nc + k] = 0.0;
+    }
+}
+
+// Maximum signal speeds max(|u|+a), max(|v|+a) over live cells.  Non-negative doubles
+// order like their bit patterns, so the maximum is an exact, order-independent integer
+// atomic max; a non-finite or negative-pressure cell produces a NaN pattern above every
+// finite speed, which the host reports as a state error.
+__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cfl(Grid g, const double* __restrict__ alpha, const R* __restrict__ U,
+                                             unsigned long long* __restrict__ smax) {
+    size_t nc = (size_t)g.nx * g.ny;
+    unsigned long long mx = 0ull, my = 0ull;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += (size_t)gridDim.x * blockDim.x) {
+        double a = alpha[k];
+        double r = (double)U[k];
+        if (!(a > 0.0) || !(r > 0.0)) continue;
+        double q[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k] / a;
+        double u = q[1] / q[0], v = q[2] / q[0];
+        double c = sqrt(g.gamma * pressure(q, g.gamma) / q[0]);
+        double sx = fabs(u) + c, sy = fabs(v) + c;
+        unsigned long long bx = __double_as_longlong(sx), by = __double_as_longlong(sy);
+        if (sx != sx) bx = 0x7ff8000000000000ull;
+        if (sy != sy) by = 0x7ff8000000000000ull;
+        mx = bx > mx ? bx : mx;
+        my = by > my ? by : my;
+    }
+    mx = wave_max64(mx);
+    my = wave_max64(my);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&smax[0], mx);
+        atomicMax(&smax[1], my);
+    }
+}
+
+// Deterministic sums: each block reduces a fixed contiguous chunk with a fixed tree; a
+// second single-block pass adds the partials in block order.
+constexpr int RT = 256;
+
+template <typename R>
+__global__ __launch_bounds__(RT) void k_sum_partial(size_t n, int comps, const R* __restrict__ U, size_t chunk,
+                                                    double* __restrict__ part) {
+    __shared__ double s[RT];
+    int c = blockIdx.y;
+    size_t b0 = (size_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+    double acc = 0.0;
+    for (size_t k = b0 + threadIdx.x; k < b1; k += RT) acc += (double)U[(size_t)c * n + k];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = RT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)c * gridDim.x + blockIdx.x] = s[0];
+    (void)comps;
+}
+
+__global__ __launch_bounds__(RT) void k_sum_final(int nblocks, const double* __restrict__ part,
+                                                  double* __restrict__ out) {
+    __shared__ double s[RT];
+    int c = blockIdx.x;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += RT) acc += part[(size_t)c * nblocks + k];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = RT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = s[0];
+}
+
+}  // namespace cc

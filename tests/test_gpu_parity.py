@@ -1,0 +1,153 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
+
+* geometry: vertex classes bit-exact, apertures and volume fractions to round-off;
+* per sweep from identical inputs: relative L-infinity of U <= 1e-12 (FP64);
+* end time (config 1, the inclined piston, 200 x 20 to t = 0.5): relative L1 <= 1e-9,
+  with the oracle's time steps;
+* the CFL time step to 1e-12; conservation totals to round-off;
+* FP32 state with FP64 geometry against the FP64 oracle: relative L1 of density <= 1e-4;
+* full-size workloads (1024 x 512 cylinder, 2048 x 1024 triangle, 4096 x 4096 aerofoil):
+  one step each, in the launch configuration the benchmark uses.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from oracle import ref  # noqa: E402
+from paper_1711_11361_amd import cc  # noqa: E402
+from paper_1711_11361_amd import workloads as W  # noqa: E402
+
+FP64_TOL = 1e-12
+
+
+def pair(w, precision=cc.CC_FP64, prim=None):
+    o = ref.Oracle(w["grid"], w["body"])
+    s = cc.Solver(w["grid"], w["body"], precision=precision)
+    p = w["prim"] if prim is None else prim
+    o.set_prim(p)
+    s.set_prim(p)
+    return o, s
+
+
+def rel_linf(a, b):
+    """max over components of max|a-b| / max|b| (components with max|b| = 0 use 1)."""
+    out = 0.0
+    for k in range(4):
+        sc = np.abs(b[k]).max()
+        sc = sc if sc > 0 else 1.0
+        out = max(out, np.abs(a[k] - b[k]).max() / sc)
+    return out
+
+
+def geometry_cases():
+    yield "piston30", W.piston()
+    yield "piston_ragged", W.piston(nx=37, ny=23, angle_deg=47.0, face=(0.3, 0.04))
+    yield "cylinder", W.cylinder(nx=128, ny=64)
+    for seed in (0, 5):
+        yield f"triangle{seed}", W.triangle_case(seed, nx=96, ny=48)
+    w = W.naca(nx=96, ny=96)
+    yield "naca", w
+    for k in (0, 1, 2, 3, 7, 11):
+        r = W.serving_request(k)
+        yield f"req{k}", r
+
+
+@pytest.mark.parametrize("name,w", list(geometry_cases()), ids=[c[0] for c in geometry_cases()])
+def test_geometry_matches_oracle(name, w):
+    o = ref.Oracle(w["grid"], w["body"])
+    s = cc.Solver(w["grid"], w["body"])
+    for t in (0.0, 0.0123, 0.37):
+        o.geometry(t, 0)
+        s.geometry(t, 0)
+        a, b = s.geometry_dump(0), o.geometry_dump(0)
+        assert np.array_equal(a["vcls"], b["vcls"]), name
+        for key in ("alpha", "bx", "by"):
+            assert np.abs(a[key] - b[key]).max() <= 1e-13, (name, key, np.abs(a[key] - b[key]).max())
+            # open / closed classification of faces and cells is exact
+            assert np.array_equal(a[key] == 1.0, b[key] == 1.0) and np.array_equal(a[key] == 0.0, b[key] == 0.0)
+
+
+def sweep_cases():
+    yield "piston30", W.piston(), 6
+    yield "piston_reflective", W.piston(nx=64, ny=16, bc=(1, 1, 1, 1)), 6
+    yield "cylinder", W.cylinder(nx=128, ny=64), 6
+    yield "triangle", W.triangle_case(2, nx=96, ny=48), 6
+    w = W.naca(nx=96, ny=96)
+    w["body"]["pitch_amp"] = math.radians(8.0)
+    w["body"]["pitch_omega"] = 2.0
+    yield "naca_pitch", w, 6
+    yield "nobody_ragged", {**W.cylinder(nx=61, ny=29), "body": None}, 4
+    for k in (0, 3, 7):
+        yield f"req{k}", W.serving_request(k), 4
+
+
+@pytest.mark.parametrize("name,w,nsteps", list(sweep_cases()), ids=[c[0] for c in sweep_cases()])
+def test_sweeps_match_oracle_from_identical_inputs(name, w, nsteps):
+    o, s = pair(w)
+    worst = 0.0
+    for k in range(nsteps):
+        dt = o.cfl_dt(w["cfl"])
+        dg = s.cfl_dt(w["cfl"])
+        assert abs(dg - dt) <= 1e-12 * dt, (name, dg, dt)
+        o.begin_step(dt)
+        s.begin_step(dt)
+        for sw in range(2):
+            d = o.parity if sw == 0 else 1 - o.parity
+            s.set_u(o.get_u())  # identical inputs
+            o.sweep(d, dt)
+            s.sweep(d, dt)
+            e = rel_linf(s.get_u(), o.get_u())
+            worst = max(worst, e)
+            assert e <= FP64_TOL, (name, k, sw, e)
+        o.end_step()
+        s.end_step()
+    assert s.info()["status"] == 0
+
+
+def test_end_time_parity_config1():
+    w = W.piston()
+    o, s = pair(w)
+    dts = o.run(w["cfl"], t_end=w["t_end"])
+    s.run(w["cfl"], dts=dts)
+    Ug, Uo = s.get_u(), o.get_u()
+    for k in range(4):
+        den = np.abs(Uo[k]).sum()
+        if den > 0:
+            assert np.abs(Ug[k] - Uo[k]).sum() / den <= 1e-9, k
+    To, Tg = o.totals(), s.totals()
+    assert np.abs(Tg - To).max() <= 1e-12 * np.abs(To).max()
+
+
+def test_fp32_state_against_fp64_oracle():
+    w = W.cylinder(nx=256, ny=128)
+    o, s = pair(w, precision=cc.CC_FP32_GEOM64)
+    dts = o.run(w["cfl"], nsteps=60)
+    s.run(w["cfl"], dts=dts)
+    Po, Pg = o.get_prim(), s.get_prim()
+    al = o.geometry_dump(0)["alpha"]
+    l1 = (al * np.abs(Pg[0] - Po[0])).sum() / (al * np.abs(Po[0])).sum()
+    assert l1 <= 1e-4, l1
+
+
+@pytest.mark.parametrize("which", ["cylinder_1024x512", "triangle_2048x1024", "naca_4096x4096"])
+def test_full_size_one_step(which):
+    if which.startswith("cylinder"):
+        w = W.cylinder()
+    elif which.startswith("triangle"):
+        w = W.triangle_case(0)
+    else:
+        w = W.naca()
+    o, s = pair(w)
+    dt = o.cfl_dt(w["cfl"])
+    assert abs(s.cfl_dt(w["cfl"]) - dt) <= 1e-12 * dt
+    o.step(dt)
+    s.step(dt)
+    e = rel_linf(s.get_u(), o.get_u())
+    assert e <= FP64_TOL, e
