@@ -39,6 +39,10 @@ class CCError(RuntimeError):
 if not os.path.exists(LIBPATH):
     raise ImportError(f"libcutcell.so not built ({LIBPATH}); run paper_1711_11361_amd/build.py")
 
+# torch brings its own HIP runtime; load it first so that the library binds to the same
+# runtime instance (a second instance would not see the device).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIBPATH)
 _vp, _d, _i32 = C.c_void_p, C.c_double, C.c_int32
 _sig = {
@@ -71,8 +75,8 @@ EXPORTED = tuple(_sig)
 
 def _check(ctx, st):
     if st != CC_OK:
-        msg = _lib.cc_last_error(ctx).decode() if ctx else ""
-        raise CCError(st, msg)
+        raw = _lib.cc_last_error(ctx)
+        raise CCError(st, raw.decode() if raw else "")
 
 
 def make_config(grid, precision=CC_FP64):

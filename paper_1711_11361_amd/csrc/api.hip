@@ -142,8 +142,16 @@ struct cc_ctx {
 
 namespace {
 
+thread_local std::string g_create_err;  // message of the last failed cc_create on this thread
+
 cc_status fail(cc_ctx* c, cc_status s, const std::string& msg) {
     if (c) c->err = msg;
+    return s;
+}
+
+cc_status create_fail(cc_ctx* c, cc_status s, const std::string& msg) {
+    g_create_err = msg;
+    if (c) cc_destroy(c);
     return s;
 }
 
@@ -390,16 +398,18 @@ size_t cc_workspace_bytes(const cc_config* cfg, const cc_body* body) {
 
 cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_t ws_bytes, void* hip_stream,
                     cc_ctx** out) {
-    if (!out) return CC_ERR_ARG;
+    if (!out) return create_fail(nullptr, CC_ERR_ARG, "null output pointer");
     *out = nullptr;
     if (!cfg || cfg->nx < 1 || cfg->ny < 1 || !(cfg->x_hi > cfg->x_lo) || !(cfg->y_hi > cfg->y_lo) ||
         !(cfg->gamma > 1.0) || cfg->reserved != 0 || (cfg->precision != CC_FP64 && cfg->precision != CC_FP32_GEOM64))
-        return CC_ERR_ARG;
+        return create_fail(nullptr, CC_ERR_ARG, "invalid configuration");
     for (int k = 0; k < 4; k++)
-        if (cfg->bc[k] != CC_BC_TRANSMISSIVE && cfg->bc[k] != CC_BC_REFLECTIVE) return CC_ERR_ARG;
-    if (body && body->nverts > 0 && !body->verts) return CC_ERR_ARG;
+        if (cfg->bc[k] != CC_BC_TRANSMISSIVE && cfg->bc[k] != CC_BC_REFLECTIVE)
+            return create_fail(nullptr, CC_ERR_ARG, "invalid boundary condition");
+    if (body && body->nverts > 0 && !body->verts) return create_fail(nullptr, CC_ERR_ARG, "body without vertices");
     Layout lay = make_layout(cfg, body);
-    if (!d_ws || ws_bytes < lay.total || ((uintptr_t)d_ws % ALIGN) != 0) return CC_ERR_WORKSPACE;
+    if (!d_ws || ws_bytes < lay.total || ((uintptr_t)d_ws % ALIGN) != 0)
+        return create_fail(nullptr, CC_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
     cc_ctx* c = new cc_ctx();
     c->cfg = *cfg;
     c->lay = lay;
@@ -441,34 +451,34 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         c->hpoly[s] = nullptr;
         c->poly_ev_valid[s] = false;
         if (c->m > 0) {
-            if (hipHostMalloc((void**)&c->hpoly[s], sizeof(double) * 2 * c->m, hipHostMallocDefault) != hipSuccess ||
-                hipEventCreateWithFlags(&c->poly_ev[s], hipEventDisableTiming) != hipSuccess) {
-                cc_destroy(c);
-                return CC_ERR_DEVICE;
+            hipError_t e1 = hipHostMalloc((void**)&c->hpoly[s], sizeof(double) * 2 * c->m, hipHostMallocDefault);
+            if (e1 != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e1));
+            hipError_t e2 = hipEventCreateWithFlags(&c->poly_ev[s], hipEventDisableTiming);
+            if (e2 != hipSuccess) {
+                (void)hipHostFree(c->hpoly[s]);
+                c->hpoly[s] = nullptr;
+                return create_fail(c, CC_ERR_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e2));
             }
         }
     }
     // all-fluid levels, clean reductions, stamps that match no step
-    bool ok = true;
-    for (int s = 0; s < 3 && ok; s++) {
-        ok &= hipMemsetAsync(c->lev[s].vcls, 0, lay.nvx, c->stream) == hipSuccess;
-        ok &= hipMemsetAsync(c->lev[s].fx, 0, lay.nfx * 16, c->stream) == hipSuccess;
-        ok &= hipMemsetAsync(c->lev[s].fy, 0, lay.nfy * 16, c->stream) == hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < 3 && e == hipSuccess; s++) {
+        if (e == hipSuccess) e = hipMemsetAsync(c->lev[s].vcls, 0, lay.nvx, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->lev[s].fx, 0, lay.nfx * 16, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->lev[s].fy, 0, lay.nfy * 16, c->stream);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_fill_f64, dim3(nblk(lay.nc)), dim3(TPB), 0, c->stream, (size_t)lay.nc, 1.0,
+                               c->lev[s].alpha);
+            e = hipGetLastError();
+        }
     }
-    for (int s = 0; s < 3 && ok; s++) {
-        hipLaunchKernelGGL(k_fill_f64, dim3(nblk(lay.nc)), dim3(TPB), 0, c->stream, (size_t)lay.nc, 1.0,
-                           c->lev[s].alpha);
-        ok &= hipGetLastError() == hipSuccess;
-    }
-    if (ok && c->m > 0) ok &= hipMemsetAsync(at<int32_t>(c, lay.off_stamp), 0xff, lay.nc * 4, c->stream) == hipSuccess;
-    if (ok) ok &= hipMemsetAsync(c->ws + lay.off_smax, 0, 16, c->stream) == hipSuccess;
-    if (ok) ok &= hipMemsetAsync(c->ws + lay.off_status, 0, 4, c->stream) == hipSuccess;
-    if (ok) ok &= hipMemsetAsync(c->ws + lay.off_ncol, 0, 4, c->stream) == hipSuccess;
-    ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
-    if (!ok) {
-        cc_destroy(c);
-        return CC_ERR_DEVICE;
-    }
+    if (e == hipSuccess && c->m > 0) e = hipMemsetAsync(at<int32_t>(c, lay.off_stamp), 0xff, lay.nc * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_smax, 0, 16, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_status, 0, 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_ncol, 0, 4, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
     *out = c;
     return CC_OK;
 }
@@ -495,7 +505,7 @@ cc_status cc_destroy(cc_ctx* c) {
     return CC_OK;
 }
 
-const char* cc_last_error(const cc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* cc_last_error(const cc_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 cc_status cc_geometry(cc_ctx* c, double t, int32_t level) {
     if (!c || level < 0 || level > 2) return fail(c, CC_ERR_ARG, "bad level");

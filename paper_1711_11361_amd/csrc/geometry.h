@@ -79,6 +79,7 @@ __device__ double clip_area(const Poly& P, double ox, double oy, double w, doubl
         if (fmax(ax, bx) < 0.0 || fmin(ax, bx) > w || fmax(ay, by) < 0.0 || fmin(ay, by) > h) continue;
         double dx = bx - ax, dy = by - ay;
         double t0 = 0.0, t1 = 1.0;
+        int s0 = -1, s1 = -1;  // rectangle side that set t0 / t1
         double pq[4][2] = {{-dx, ax}, {dx, w - ax}, {-dy, ay}, {dy, h - ay}};
         bool rej = false;
 #pragma unroll
@@ -89,15 +90,29 @@ __device__ double clip_area(const Poly& P, double ox, double oy, double w, doubl
             } else {
                 double t = q / p;
                 if (p < 0.0) {
-                    if (t > t0) t0 = t;
+                    if (t > t0) {
+                        t0 = t;
+                        s0 = s;
+                    }
                 } else {
-                    if (t < t1) t1 = t;
+                    if (t < t1) {
+                        t1 = t;
+                        s1 = s;
+                    }
                 }
             }
         }
         if (rej || !(t0 < t1)) continue;
+        // clipped end points; the coordinate fixed by the clipping side is set exactly
         double x0 = ax + t0 * dx, y0 = ay + t0 * dy;
         double x1 = ax + t1 * dx, y1 = ay + t1 * dy;
+        const double side[4] = {0.0, w, 0.0, h};
+        if (s0 >= 0) {
+            if (s0 < 2) x0 = side[s0]; else y0 = side[s0];
+        }
+        if (s1 >= 0) {
+            if (s1 < 2) x1 = side[s1]; else y1 = side[s1];
+        }
         acc += 0.5 * (x0 + x1) * (y1 - y0);
     }
     return acc + w * right_solid;

@@ -119,7 +119,7 @@ def piston(nx=200, ny=20, angle_deg=30.0, speed=0.3, face=(0.1, 0.05), bc=(0, 0,
     g = grid(nx, ny, 0.0, 1.0, 0.0, 0.1, bc=bc)
     th = math.radians(angle_deg)
     n = (math.cos(th), math.sin(th))
-    b = body(half_plane_quad(2.0), ref=face, theta0=th, vel=(speed * n[0], speed * n[1]))
+    b = body(half_plane_quad(0.6), ref=face, theta0=th, vel=(speed * n[0], speed * n[1]))
     return {"name": "piston", "grid": g, "body": b, "prim": uniform_prim(g, 1.0, 0.0, 0.0, 1.0),
             "cfl": 0.8, "t_end": 0.5, "normal": n, "speed": speed, "face": face}
 
