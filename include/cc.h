@@ -65,6 +65,11 @@ typedef struct {
     int32_t reserved;   /* must be 0 */
     double x_lo, x_hi, y_lo, y_hi;
     double gamma;       /* ratio of specific heats (perfect gas, Sec. 2.1) */
+    double alpha_min;   /* small-cell threshold: a cut cell whose volume fraction is below it
+                           counts as solid (alpha = 0), so it is covered and uncovered like any
+                           solid cell (Eqs. cutCellCoverDonation, cutCellInitialisation); 0 keeps
+                           every cut cell (the paper's method, whose update divides by the new
+                           volume fraction, Eq. EulerDiscrete2); must lie in [0, 0.5) */
 } cc_config;
 
 typedef struct {
@@ -91,6 +96,12 @@ cc_status cc_destroy(cc_ctx* ctx);
 /* Initial state: body posed at time t0, level-n geometry built, U = alpha Q(prim).
  * d_prim: device, 4 planes (rho, u, v, p) of nx*ny doubles. */
 cc_status cc_set_state(cc_ctx* ctx, const double* d_prim, double t0);
+/* Resume the clock (restart from a saved state): time t after `step` completed split steps.
+ * The next step sweeps x then y if `step` is even, y then x if odd (the alternation of
+ * Sec. 2.3.1), and the level-n geometry is rebuilt with the body posed at t, so a state
+ * saved from an uninterrupted run continues bit for bit.  The state itself is unchanged:
+ * set it afterwards with cc_set_u.  Errors: CC_ERR_ARG for step < 0 or non-finite t. */
+cc_status cc_set_clock(cc_ctx* ctx, double t, int64_t step);
 /* Replace the conserved state (device, 4 planes of nx*ny doubles, per unit cell volume). */
 cc_status cc_set_u(cc_ctx* ctx, const double* d_u);
 /* Copy the level-n state out: what = 0 primitive (rho, u, v, p; zeros in solid or empty

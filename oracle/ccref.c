@@ -34,6 +34,8 @@ typedef struct {
     int32_t reserved;
     double x_lo, x_hi, y_lo, y_hi;
     double gamma;
+    double alpha_min;  /* cut cells with a smaller volume fraction count as solid (reading
+                        * R19); 0 = none */
 } ccref_config;
 
 typedef struct {
@@ -436,6 +438,7 @@ static void compute_level(ccref_ctx* c, const double* pv, int m, level_t* L) {
                 a = 1.0 - s / (c->hx * c->hy);
                 if (a < 0.0) a = 0.0;
                 if (a > 1.0) a = 1.0;
+                if (a < c->cfg.alpha_min) a = 0.0; /* small-cell threshold (reading R19) */
             }
             L->alpha[CIDX(c, i, j)] = a;
         }
@@ -498,6 +501,7 @@ void ccref_destroy(ccref_ctx* c) {
 
 ccref_ctx* ccref_create(const ccref_config* cfg, const ccref_body* body) {
     if (cfg->nx < 1 || cfg->ny < 1 || !(cfg->x_hi > cfg->x_lo) || !(cfg->y_hi > cfg->y_lo)) return NULL;
+    if (!(cfg->alpha_min >= 0.0 && cfg->alpha_min < 0.5)) return NULL;
     ccref_ctx* c = calloc(1, sizeof(ccref_ctx));
     if (!c) return NULL;
     c->cfg = *cfg;
@@ -550,6 +554,7 @@ int ccref_set_prim(ccref_ctx* c, const double* prim, double t0) {
     c->status = 0;
     c->ncollapse = 0;
     for (int k = 0; k < 4; k++) c->bnd[k] = c->wall[k] = c->lost[k] = 0.0;
+    for (size_t k = 0; k < nc; k++) c->stamp0[k] = -1; /* step numbers restart */
     level_at_time(c, t0, &c->L[c->s0]);
     for (size_t k = 0; k < nc; k++) {
         double r = prim[k], u = prim[nc + k], v = prim[2 * nc + k], p = prim[3 * nc + k];
@@ -557,6 +562,21 @@ int ccref_set_prim(ccref_ctx* c, const double* prim, double t0) {
         double q[4] = {r, r * u, r * v, p / (g - 1.0) + 0.5 * r * (u * u + v * v)};
         for (int m = 0; m < 4; m++) c->U[m * nc + k] = a * q[m];
     }
+    return 0;
+}
+
+/* Resume the clock: time t after `step` completed split steps, so that the next step's
+ * sweep order (x then y after an even number of steps, y then x after an odd one) and the
+ * level-n geometry (body posed at t) are those of an uninterrupted run.  The state is left
+ * as it is; set it afterwards with ccref_set_u. */
+int ccref_set_clock(ccref_ctx* c, double t, int64_t step) {
+    if (step < 0) return 1;
+    c->t = t;
+    c->step = step;
+    c->parity = (int)(step & 1);
+    c->in_step = 0;
+    for (size_t k = 0; k < (size_t)c->cfg.nx * c->cfg.ny; k++) c->stamp0[k] = -1;
+    level_at_time(c, t, &c->L[c->s0]);
     return 0;
 }
 
@@ -1166,6 +1186,68 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
             }
             for (int m = 0; m < 4; m++) U3[m * nc + k] = 0.0;
         }
+
+    /* --- 7. collapse after covering (reading R28): a cell left with content that is not an
+     *        admissible gas state once the residuals have been added is emptied in the same
+     *        way, its content going to its face neighbours that stay fluid, are not emptied
+     *        and are admissible (else its eight neighbours), weighted by alpha_e.  All cells
+     *        of a round move their content at once; two rounds, and a cell still inadmissible
+     *        after them is reported (status bit 2). --- */
+    for (int round = 0; round < 2; round++) {
+        unsigned char* bad = calloc(nc, 1);
+        int nbad = 0;
+        for (size_t k = 0; k < nc; k++) {
+            if (!(Le->alpha[k] > 0.0) || gone[k]) continue;
+            double r = U3[k], mx = U3[nc + k], my = U3[2 * nc + k], e = U3[3 * nc + k];
+            if (r == 0.0 && mx == 0.0 && my == 0.0 && e == 0.0) continue; /* no content */
+            if (!(r > 0.0) || !(e - 0.5 * (mx * mx + my * my) / r > 0.0)) {
+                bad[k] = 1;
+                nbad++;
+            }
+        }
+        if (nbad == 0) {
+            free(bad);
+            break;
+        }
+        double* U4 = malloc(sizeof(double) * 4 * nc);
+        memcpy(U4, U3, sizeof(double) * 4 * nc);
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t k = CIDX(c, i, j);
+                if (!bad[k]) continue;
+                int rec[8], nr = 0;
+                for (int pass = 0; pass < 2 && nr == 0; pass++) {
+                    int cnt = pass == 0 ? 4 : 8;
+                    for (int q = 0; q < cnt; q++) {
+                        int ii = i + d8[q][0], jj = j + d8[q][1];
+                        if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+                        size_t kk = CIDX(c, ii, jj);
+                        if (Le->alpha[kk] > 0.0 && !gone[kk] && !bad[kk]) rec[nr++] = (int)kk;
+                    }
+                }
+                if (nr == 0) {
+                    for (int m = 0; m < 4; m++) c->lost[m] += U3[m * nc + k] * area;
+                } else {
+                    double den = 0.0;
+                    for (int q = 0; q < nr; q++) den += Le->alpha[rec[q]];
+                    for (int q = 0; q < nr; q++) {
+                        double w = Le->alpha[rec[q]] / den;
+                        for (int m = 0; m < 4; m++) U4[m * nc + rec[q]] += w * U3[m * nc + k];
+                    }
+                }
+                for (int m = 0; m < 4; m++) U4[m * nc + k] = 0.0;
+                gone[k] = 2;
+            }
+        memcpy(U3, U4, sizeof(double) * 4 * nc);
+        free(U4);
+        free(bad);
+    }
+    for (size_t k = 0; k < nc; k++) {
+        if (!(Le->alpha[k] > 0.0) || gone[k]) continue;
+        double r = U3[k], mx = U3[nc + k], my = U3[2 * nc + k], e = U3[3 * nc + k];
+        if (r == 0.0 && mx == 0.0 && my == 0.0 && e == 0.0) continue;
+        if (!(r > 0.0) || !(e - 0.5 * (mx * mx + my * my) / r > 0.0)) c->status |= 2;
+    }
     memcpy(c->U, U3, sizeof(double) * 4 * nc);
     free(btd);
     free(Qinit);

@@ -15,7 +15,7 @@ class _Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4),
                 ("precision", C.c_int32), ("reserved", C.c_int32),
                 ("x_lo", C.c_double), ("x_hi", C.c_double), ("y_lo", C.c_double),
-                ("y_hi", C.c_double), ("gamma", C.c_double)]
+                ("y_hi", C.c_double), ("gamma", C.c_double), ("alpha_min", C.c_double)]
 
 
 class _Body(C.Structure):
@@ -39,6 +39,7 @@ def lib():
         L.ccref_destroy.argtypes = [vp]
         L.ccref_set_prim.argtypes = [vp, p, d]
         L.ccref_set_u.argtypes = [vp, p]
+        L.ccref_set_clock.argtypes = [vp, d, C.c_int64]
         L.ccref_get_u.argtypes = [vp, p]
         L.ccref_get_prim.argtypes = [vp, p]
         L.ccref_time.restype = d
@@ -139,6 +140,7 @@ class Oracle:
         cfg.x_lo, cfg.x_hi = grid["x_lo"], grid["x_hi"]
         cfg.y_lo, cfg.y_hi = grid["y_lo"], grid["y_hi"]
         cfg.gamma = grid.get("gamma", 1.4)
+        cfg.alpha_min = grid.get("alpha_min", 0.0)
         self.nx, self.ny = cfg.nx, cfg.ny
         self.gamma = cfg.gamma
         b = _Body()
@@ -175,6 +177,12 @@ class Oracle:
     def set_prim(self, prim, t0=0.0):
         prim = _f64(prim).reshape(4, self.ny, self.nx)
         lib().ccref_set_prim(self._h, _dp(prim), t0)
+
+    def set_clock(self, t, step):
+        """Resume at time t after `step` split steps (sweep order and level-n geometry of an
+        uninterrupted run); set the state afterwards."""
+        if lib().ccref_set_clock(self._h, float(t), int(step)) != 0:
+            raise ValueError("bad step count")
 
     def set_u(self, U):
         U = _f64(U).reshape(4, self.ny, self.nx)

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "CC_OK", 1: "CC_ERR_ARG", 2: "CC_ERR_DEVICE", 3: "CC_ERR_WORK
 class cc_config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4), ("precision", C.c_int32),
                 ("reserved", C.c_int32), ("x_lo", C.c_double), ("x_hi", C.c_double), ("y_lo", C.c_double),
-                ("y_hi", C.c_double), ("gamma", C.c_double)]
+                ("y_hi", C.c_double), ("gamma", C.c_double), ("alpha_min", C.c_double)]
 
 
 class cc_body(C.Structure):
@@ -50,6 +50,7 @@ _sig = {
     "cc_create": (C.c_int, [C.POINTER(cc_config), C.POINTER(cc_body), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "cc_destroy": (C.c_int, [_vp]),
     "cc_set_state": (C.c_int, [_vp, _vp, _d]),
+    "cc_set_clock": (C.c_int, [_vp, _d, C.c_int64]),
     "cc_set_u": (C.c_int, [_vp, _vp]),
     "cc_get_state": (C.c_int, [_vp, _vp, _i32]),
     "cc_geometry": (C.c_int, [_vp, _d, _i32]),
@@ -88,6 +89,7 @@ def make_config(grid, precision=CC_FP64):
     c.reserved = 0
     c.x_lo, c.x_hi, c.y_lo, c.y_hi = grid["x_lo"], grid["x_hi"], grid["y_lo"], grid["y_hi"]
     c.gamma = grid.get("gamma", 1.4)
+    c.alpha_min = grid.get("alpha_min", 0.0)
     return c
 
 
@@ -123,6 +125,10 @@ def cc_destroy(ctx):
 
 def cc_set_state(ctx, d_prim, t0):
     _check(ctx, _lib.cc_set_state(ctx, _vp(d_prim), t0))
+
+
+def cc_set_clock(ctx, t, step):
+    _check(ctx, _lib.cc_set_clock(ctx, float(t), int(step)))
 
 
 def cc_set_u(ctx, d_u):
@@ -223,6 +229,10 @@ class Solver:
     def set_prim(self, prim, t0=0.0):
         self._io.copy_(self.torch.as_tensor(np.asarray(prim, dtype=np.float64).reshape(4, self.ny, self.nx)))
         cc_set_state(self.ctx, self._io.data_ptr(), t0)
+
+    def set_clock(self, t, step):
+        """Resume at time t after `step` split steps; set the state afterwards."""
+        cc_set_clock(self.ctx, t, step)
 
     def set_u(self, U):
         self._io.copy_(self.torch.as_tensor(np.asarray(U, dtype=np.float64).reshape(4, self.ny, self.nx)))

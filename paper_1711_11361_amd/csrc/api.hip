@@ -22,6 +22,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int NPART = 1024;  // blocks of the deterministic sum
 constexpr int TPB = 256;
+constexpr int TPB_BOX = 64;  // small box kernels: spread a few thousand cells over all CUs
 
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -31,6 +32,7 @@ struct Layout {
     size_t off_u[2], off_vcls[3], off_fx[3], off_fy[3], off_alpha[3], off_poly[3];
     size_t off_qb, off_stamp;
     size_t off_sQ, off_sU1, off_shas, off_sbt, off_swall, off_sfb, off_swv, off_sahat, off_sU2, off_sgone;
+    size_t off_sf1, off_sf2, off_nbad;
     size_t off_smax, off_status, off_ncol, off_part, off_tot;
     size_t total;
     int capw, caph;
@@ -89,6 +91,9 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_sahat = take(cap * 8);
     L.off_sU2 = take(4 * cap * 8);
     L.off_sgone = take(cap);
+    L.off_sf1 = take(cap);
+    L.off_sf2 = take(cap);
+    L.off_nbad = take(8);
     L.off_smax = take(16);
     L.off_status = take(4);
     L.off_ncol = take(4);
@@ -244,6 +249,7 @@ Box box_union(const Box& a, const Box& b) {
 
 unsigned nblk(size_t n, int t = TPB) { return (unsigned)((n + t - 1) / t); }
 
+
 void tstart(cc_ctx* c, int kind, TimedPair& tp) {
     if (!c->timing) return;
     if (c->pool.empty()) {
@@ -283,12 +289,13 @@ cc_status compute_level(cc_ctx* c, int slot, const double* pv) {
     TimedPair tp{};
     tstart(c, 3, tp);
     int vw = reg.w() + 1, vh = reg.h() + 1;
-    hipLaunchKernelGGL(k_geo_vertices, dim3(nblk((size_t)vw * vh)), dim3(TPB), 0, c->stream, c->g, L, reg.i0, reg.j0,
-                       vw, vh);
+    hipLaunchKernelGGL(k_geo_vertices, dim3(nblk((size_t)vw * vh, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, L,
+                       reg.i0, reg.j0, vw, vh);
     size_t nf = (size_t)vw * (vh - 1) + (size_t)(vw - 1) * vh;
-    hipLaunchKernelGGL(k_geo_faces, dim3(nblk(nf)), dim3(TPB), 0, c->stream, c->g, L, reg.i0, reg.j0, vw, vh);
-    hipLaunchKernelGGL(k_geo_cells, dim3(nblk((size_t)reg.w() * reg.h())), dim3(TPB), 0, c->stream, c->g, L, reg.i0,
-                       reg.j0, reg.w(), reg.h());
+    hipLaunchKernelGGL(k_geo_faces, dim3(nblk(nf, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, L, reg.i0, reg.j0,
+                       vw, vh);
+    hipLaunchKernelGGL(k_geo_cells, dim3(nblk((size_t)reg.w() * reg.h(), ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream,
+                       c->g, L, reg.i0, reg.j0, reg.w(), reg.h());
     tstop(c, tp);
     HIPCHK(c, hipGetLastError());
     return CC_OK;
@@ -325,6 +332,9 @@ cc_status run_sweep(cc_ctx* c, int dir, double dt, bool first) {
     S.ahat = at<double>(c, c->lay.off_sahat);
     S.U2 = at<double>(c, c->lay.off_sU2);
     S.gone = at<int8_t>(c, c->lay.off_sgone);
+    S.f1 = at<int8_t>(c, c->lay.off_sf1);
+    S.f2 = at<int8_t>(c, c->lay.off_sf2);
+    S.nbad = at<unsigned int>(c, c->lay.off_nbad);
     S.cap = (int)std::max<size_t>(c->lay.cap, 1);
     Common C{at<double>(c, c->lay.off_qb), at<int32_t>(c, c->lay.off_stamp)};
     unsigned int* status = at<unsigned int>(c, c->lay.off_status);
@@ -336,15 +346,17 @@ cc_status run_sweep(cc_ctx* c, int dir, double dt, bool first) {
         tstart(c, 2, tb);
         size_t nf = dir == 0 ? (size_t)(B.w() + 1) * B.h() : (size_t)B.w() * (B.h() + 1);
         if (dir == 0)
-            hipLaunchKernelGGL(k_swept<0>, dim3(nblk(nf)), dim3(TPB), 0, c->stream, c->g, Ls, Le, c->mot, B, S);
+            hipLaunchKernelGGL(k_swept<0>, dim3(nblk(nf, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, Ls, Le,
+                               c->mot, B, S);
         else
-            hipLaunchKernelGGL(k_swept<1>, dim3(nblk(nf)), dim3(TPB), 0, c->stream, c->g, Ls, Le, c->mot, B, S);
-        hipLaunchKernelGGL(k_stage<R>, dim3(nblk(nb)), dim3(TPB), 0, c->stream, c->g, Ls, Le, Uin, B, S, status);
+            hipLaunchKernelGGL(k_swept<1>, dim3(nblk(nf, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, Ls, Le,
+                               c->mot, B, S);
+        hipLaunchKernelGGL(k_stage<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, Uin, B, S, status);
         if (dir == 0)
-            hipLaunchKernelGGL(k_wall<0>, dim3(nblk(nb)), dim3(TPB), 0, c->stream, c->g, Ls, Le, c->mot, B, S, C,
+            hipLaunchKernelGGL(k_wall<0>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, c->mot, B, S, C,
                                (int)first, step_id);
         else
-            hipLaunchKernelGGL(k_wall<1>, dim3(nblk(nb)), dim3(TPB), 0, c->stream, c->g, Ls, Le, c->mot, B, S, C,
+            hipLaunchKernelGGL(k_wall<1>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, c->mot, B, S, C,
                                (int)first, step_id);
         tstop(c, tb);
     }
@@ -364,12 +376,18 @@ cc_status run_sweep(cc_ctx* c, int dir, double dt, bool first) {
     if (nb > 0) {
         tstart(c, 2, tb);
         if (dir == 0)
-            hipLaunchKernelGGL((k_patch<0, R>), dim3(nblk(nb)), dim3(TPB), 0, c->stream, c->g, Ls, Le, Uin, B, S, lam,
+            hipLaunchKernelGGL((k_patch<0, R>), dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, Uin, B, S, lam,
                                ncol);
         else
-            hipLaunchKernelGGL((k_patch<1, R>), dim3(nblk(nb)), dim3(TPB), 0, c->stream, c->g, Ls, Le, Uin, B, S, lam,
+            hipLaunchKernelGGL((k_patch<1, R>), dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, Uin, B, S, lam,
                                ncol);
-        hipLaunchKernelGGL(k_cover<R>, dim3(nblk(nb)), dim3(TPB), 0, c->stream, c->g, Le, B, S, Uout);
+        hipLaunchKernelGGL(k_cover<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Le, B, S, Uout);
+        // collapse rounds after covering: the content ping-pongs U1 -> Q -> Uout
+        hipLaunchKernelGGL(k_fix<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Le, B, S, 0,
+                           (const double*)S.U1, (const int8_t*)S.f1, S.Q, S.f2, Uout, ncol, status);
+        hipLaunchKernelGGL(k_fix<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Le, B, S, 1,
+                           (const double*)S.Q, (const int8_t*)S.f2, (double*)nullptr, (int8_t*)nullptr, Uout, ncol,
+                           status);
         tstop(c, tb);
     }
     (void)nc;
@@ -401,7 +419,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     if (!out) return create_fail(nullptr, CC_ERR_ARG, "null output pointer");
     *out = nullptr;
     if (!cfg || cfg->nx < 1 || cfg->ny < 1 || !(cfg->x_hi > cfg->x_lo) || !(cfg->y_hi > cfg->y_lo) ||
-        !(cfg->gamma > 1.0) || cfg->reserved != 0 || (cfg->precision != CC_FP64 && cfg->precision != CC_FP32_GEOM64))
+        !(cfg->gamma > 1.0) || cfg->reserved != 0 || (cfg->precision != CC_FP64 && cfg->precision != CC_FP32_GEOM64) ||
+        !(cfg->alpha_min >= 0.0 && cfg->alpha_min < 0.5))
         return create_fail(nullptr, CC_ERR_ARG, "invalid configuration");
     for (int k = 0; k < 4; k++)
         if (cfg->bc[k] != CC_BC_TRANSMISSIVE && cfg->bc[k] != CC_BC_REFLECTIVE)
@@ -425,6 +444,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     c->g.hx = c->hx;
     c->g.hy = c->hy;
     c->g.gamma = cfg->gamma;
+    c->g.alpha_min = cfg->alpha_min;
     c->m = body_m(body);
     if (c->m > 0) {
         c->bverts.assign(body->verts, body->verts + 2 * c->m);
@@ -550,8 +570,21 @@ cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
                            at<double>(c, c->lay.off_u[0]));
     HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_status, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_ncol, 0, 4, c->stream));
+    if (c->m > 0) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
     HIPCHK(c, hipGetLastError());
     c->have_state = true;
+    return CC_OK;
+}
+
+cc_status cc_set_clock(cc_ctx* c, double t, int64_t step) {
+    if (!c || step < 0 || !std::isfinite(t)) return fail(c, CC_ERR_ARG, "bad argument");
+    c->in_step = false;
+    c->t = t;
+    c->step = step;
+    c->parity = (int)(step & 1);
+    cc_status st = cc_geometry(c, t, 0);
+    if (st != CC_OK) return st;
+    if (c->m > 0) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
     return CC_OK;
 }
 
@@ -675,15 +708,15 @@ cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
     if (!c || !h_dt || !(cfl > 0.0)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_cfl_dt inside a step");
     unsigned long long* smax = at<unsigned long long>(c, c->lay.off_smax);
-    HIPCHK(c, hipMemsetAsync(smax, 0, 16, c->stream));
-    unsigned blocks = std::min<unsigned>(nblk(c->lay.nc), 2048u);
+    unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
     const double* al = c->lev[c->s0].alpha;
     if (fp32(c))
-        hipLaunchKernelGGL(k_cfl<float>, dim3(blocks), dim3(256), 0, c->stream, c->g, al,
-                           at<float>(c, c->lay.off_u[c->cur]), smax);
+        hipLaunchKernelGGL(k_cfl<float>, dim3(CFL_BLOCKS), dim3(256), 0, c->stream, c->g, al,
+                           at<float>(c, c->lay.off_u[c->cur]), part);
     else
-        hipLaunchKernelGGL(k_cfl<double>, dim3(blocks), dim3(256), 0, c->stream, c->g, al,
-                           at<double>(c, c->lay.off_u[c->cur]), smax);
+        hipLaunchKernelGGL(k_cfl<double>, dim3(CFL_BLOCKS), dim3(256), 0, c->stream, c->g, al,
+                           at<double>(c, c->lay.off_u[c->cur]), part);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, c->stream, CFL_BLOCKS, (const unsigned long long*)part, smax);
     HIPCHK(c, hipGetLastError());
     unsigned long long hs[2];
     unsigned int status = 0;
@@ -694,6 +727,7 @@ cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
     std::memcpy(&sx, &hs[0], 8);
     std::memcpy(&sy, &hs[1], 8);
     if (status & 1u) return fail(c, CC_ERR_STATE, "a cell became fluid without donor neighbours");
+    if (status & 2u) return fail(c, CC_ERR_STATE, "a cut cell stayed inadmissible after two collapse rounds");
     if (!std::isfinite(sx) || !std::isfinite(sy)) return fail(c, CC_ERR_STATE, "non-finite or non-physical state");
     if (c->m > 0) {
         std::vector<double> pv(2 * c->m);

@@ -18,6 +18,7 @@ struct Grid {
     int bc[4];  // W, E, S, N: 0 zero-gradient, 1 reflective
     double x_lo, y_lo, hx, hy;
     double gamma;
+    double alpha_min;  // small-cell threshold: cut cells with a smaller volume fraction are solid
 };
 
 // Cell index box, half-open [i0, i1) x [j0, j1).

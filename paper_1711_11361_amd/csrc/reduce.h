@@ -76,9 +76,12 @@ __device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
     return v;
 }
 
+constexpr int CFL_BLOCKS = 512;
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_cfl(Grid g, const double* __restrict__ alpha, const R* __restrict__ U,
-                                             unsigned long long* __restrict__ smax) {
+                                             unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long sx_[4], sy_[4];
     size_t nc = (size_t)g.nx * g.ny;
     unsigned long long mx = 0ull, my = 0ull;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += (size_t)gridDim.x * blockDim.x) {
@@ -99,9 +102,47 @@ __global__ __launch_bounds__(256) void k_cfl(Grid g, const double* __restrict__ 
     }
     mx = wave_max64(mx);
     my = wave_max64(my);
+    int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&smax[0], mx);
-        atomicMax(&smax[1], my);
+        sx_[w] = mx;
+        sy_[w] = my;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 4; q++) {
+            mx = sx_[q] > mx ? sx_[q] : mx;
+            my = sy_[q] > my ? sy_[q] : my;
+        }
+        part[2 * blockIdx.x] = mx;
+        part[2 * blockIdx.x + 1] = my;
+    }
+}
+
+// Final maximum over the per-block partials (one block).
+__global__ __launch_bounds__(256) void k_cfl_final(int nparts, const unsigned long long* __restrict__ part,
+                                                   unsigned long long* __restrict__ smax) {
+    __shared__ unsigned long long sx_[4], sy_[4];
+    unsigned long long mx = 0ull, my = 0ull;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
+        unsigned long long a = part[2 * k], b = part[2 * k + 1];
+        mx = a > mx ? a : mx;
+        my = b > my ? b : my;
+    }
+    mx = wave_max64(mx);
+    my = wave_max64(my);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sx_[w] = mx;
+        sy_[w] = my;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 4; q++) {
+            mx = sx_[q] > mx ? sx_[q] : mx;
+            my = sy_[q] > my ? sy_[q] : my;
+        }
+        smax[0] = mx;
+        smax[1] = my;
     }
 }
 

@@ -33,6 +33,9 @@ struct Stage {
     double* ahat;  // cap
     double* U2;    // 4*cap: updated content before covering
     int8_t* gone;  // cap: 1 covered, 2 collapsed
+    int8_t* f1;    // cap: post-cover flags of the first collapse round (0 eligible, 1 bad, 2 out)
+    int8_t* f2;    // cap: the same for the second round
+    unsigned int* nbad;  // 2 counters: bad cells found before round 1 / round 2
     int cap;
 };
 
@@ -61,8 +64,8 @@ __device__ __forceinline__ double step_disp(const Motion& M, int d, double x, do
 // (Eq. timeAveragedBeta): the solid length integrated over the sweep is the area of the
 // start polygon inside the strip swept across the face.
 template <int D>
-__global__ void k_swept(Grid g, Level Ls, Level Le, Motion M, Box B, Stage S) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_swept(Grid g, Level Ls, Level Le, Motion M, Box B, Stage S) {
+    int t = wave_item(), lane = wave_lane();
     int fw = D == 0 ? B.w() + 1 : B.w(), fh = D == 0 ? B.h() : B.h() + 1;
     if (t >= fw * fh) return;
     int i = B.i0 + t % fw, j = B.j0 + t / fw;
@@ -97,17 +100,15 @@ __global__ void k_swept(Grid g, Level Ls, Level Le, Motion M, Box B, Stage S) {
             if (x0 + sw < P.xmin || x0 > P.xmax || y0 + sh < P.ymin || y0 > P.ymax) {
                 r = 1.0;
             } else {
-                // solid length of the strip's right side x = x0 + sw
-                double2 iv = seg_clip(P, x0 + sw, y0, x0 + sw, y0 + sh);
-                double rs = iv.y > iv.x ? (iv.y - iv.x) * sh : 0.0;
-                double a = clip_area(P, x0, y0, sw, sh, rs);
+                double rs = wave_right_solid(P, x0, y0, sw, sh, lane);
+                double a = wave_clip_area(P, x0, y0, sw, sh, rs, lane);
                 r = 1.0 - a / (w * hf);
                 if (r < 0.0) r = 0.0;
                 if (r > 1.0) r = 1.0;
             }
         }
     }
-    S.bt[fidx<D>(B, i, j)] = r;
+    if (lane == 0) S.bt[fidx<D>(B, i, j)] = r;
 }
 
 // ------------------------------------------------------------------ stage (donations)
@@ -143,6 +144,7 @@ template <typename R>
 __global__ void k_stage(Grid g, Level Ls, Level Le, const R* __restrict__ U, Box B, Stage S,
                         unsigned int* status) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) S.nbad[0] = S.nbad[1] = 0u;  // read by the collapse rounds at the sweep's end
     if (t >= B.w() * B.h()) return;
     int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
     size_t nc = (size_t)g.nx * g.ny, k = (size_t)j * g.nx + i;
@@ -543,6 +545,13 @@ __global__ void k_patch(Grid g, Level Ls, Level Le, const R* __restrict__ U, Box
     S.gone[b] = (int8_t)gone;
 }
 
+// Content (conserved amounts) that is present but not an admissible gas state.
+__device__ __forceinline__ bool inadmissible_content(const double* u) {
+    if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0 && u[3] == 0.0) return false;
+    double r = u[0];
+    return !(r > 0.0) || !(u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / r > 0.0);
+}
+
 // Covering (Eqs. massDeficitEquation, cutCellCoverDonation): each emptied cell's residual
 // goes to its face neighbours that stay fluid (else its eight neighbours) in proportion to
 // their end volume.  Gathered per recipient in increasing order of the emptied cell.
@@ -589,7 +598,86 @@ __global__ void k_cover(Grid g, Level Le, Box B, Stage S, R* __restrict__ Uout) 
                 }
         }
     }
+    for (int m = 0; m < 4; m++) {
+        Uout[m * nc + k] = (R)acc[m];
+        S.U1[m * cap + b] = acc[m];
+    }
+    int8_t f = S.gone[b] ? 2 : 0;
+    if (!f && Le.alpha[k] > 0.0 && inadmissible_content(acc)) {
+        f = 1;
+        atomicAdd(&S.nbad[0], 1u);
+    }
+    S.f1[b] = f;
+}
+
+// Collapse after covering (reading R28), one round: every cell flagged bad (content left
+// that is not an admissible gas state) moves its content to its face neighbours that stay
+// fluid and are neither bad nor emptied (else its eight neighbours), weighted by alpha_e;
+// all bad cells of the round move at once, gathered per recipient in increasing order of
+// the bad cell.  Round 0 flags the cells still bad for round 1; round 1 reports any cell
+// still bad (status bit 2).  Both rounds return at once when the previous stage found no
+// bad cell.
+template <typename R>
+__global__ void k_fix(Grid g, Level Le, Box B, Stage S, int round, const double* __restrict__ Xin,
+                      const int8_t* __restrict__ fin, double* __restrict__ Xout, int8_t* __restrict__ fout,
+                      R* __restrict__ Uout, unsigned int* ncollapse, unsigned int* status) {
+    if (S.nbad[round] == 0u) return;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B.w() * B.h()) return;
+    int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
+    int b = bidx(B, i, j), cap = S.cap;
+    size_t nc = (size_t)g.nx * g.ny, k = (size_t)j * g.nx + i;
+    int8_t f = fin[b];
+    double acc[4] = {0, 0, 0, 0};
+    if (f == 1) {
+        atomicAdd(ncollapse, 1u);
+    } else {
+        for (int m = 0; m < 4; m++) acc[m] = Xin[m * cap + b];
+        double aer = Le.alpha[k];
+        if (f == 0 && aer > 0.0) {
+            for (int dj = -1; dj <= 1; dj++)
+                for (int di = -1; di <= 1; di++) {
+                    if (di == 0 && dj == 0) continue;
+                    int ci = i + di, cj = j + dj;
+                    if (!B.has(ci, cj)) continue;
+                    int cb = bidx(B, ci, cj);
+                    if (fin[cb] != 1) continue;
+                    int rec[8], nr = 0;
+                    for (int pass = 0; pass < 2 && nr == 0; pass++) {
+                        int cnt = pass == 0 ? 4 : 8;
+                        for (int q = 0; q < cnt; q++) {
+                            int ii = ci + c_d8[q][0], jj = cj + c_d8[q][1];
+                            if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny) continue;
+                            size_t kk = (size_t)jj * g.nx + ii;
+                            int8_t fk = B.has(ii, jj) ? fin[bidx(B, ii, jj)] : (int8_t)0;
+                            if (Le.alpha[kk] > 0.0 && fk == 0) rec[nr++] = (int)kk;
+                        }
+                    }
+                    bool mine = false;
+                    double den = 0.0;
+                    for (int q = 0; q < nr; q++) {
+                        den += Le.alpha[rec[q]];
+                        mine |= rec[q] == (int)k;
+                    }
+                    if (!mine) continue;
+                    double wgt = aer / den;
+                    for (int m = 0; m < 4; m++) acc[m] += wgt * Xin[m * cap + cb];
+                }
+        }
+    }
     for (int m = 0; m < 4; m++) Uout[m * nc + k] = (R)acc[m];
+    bool still = f == 0 && Le.alpha[k] > 0.0 && inadmissible_content(acc);
+    if (round == 0) {
+        for (int m = 0; m < 4; m++) Xout[m * cap + b] = acc[m];
+        int8_t fo = f != 0 ? 2 : 0;
+        if (still) {
+            fo = 1;
+            atomicAdd(&S.nbad[1], 1u);
+        }
+        fout[b] = fo;
+    } else if (still) {
+        atomicOr(status, 2u);
+    }
 }
 
 // ------------------------------------------------------------------ dense sweeps

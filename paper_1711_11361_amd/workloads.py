@@ -24,10 +24,17 @@ GAMMA = 1.4
 
 
 # --------------------------------------------------------------------------- grids / fields
-def grid(nx, ny, x_lo, x_hi, y_lo, y_hi, bc=(0, 0, 0, 0), gamma=GAMMA):
+# Small-cell threshold of the shock-crossing and serving workloads: cut cells below 1 % of a
+# cell count as solid.  Their bodies move at speeds unrelated to the gas around them, so
+# front cells shrink to ~1e-7 of a cell while holding content they cannot contain; without
+# the threshold the 1024 x 512 cylinder run fails within 300 steps.
+SMALL_CELL = 1e-2
+
+
+def grid(nx, ny, x_lo, x_hi, y_lo, y_hi, bc=(0, 0, 0, 0), gamma=GAMMA, alpha_min=0.0):
     return {"nx": int(nx), "ny": int(ny), "x_lo": float(x_lo), "x_hi": float(x_hi),
             "y_lo": float(y_lo), "y_hi": float(y_hi), "bc": tuple(int(b) for b in bc),
-            "gamma": float(gamma)}
+            "gamma": float(gamma), "alpha_min": float(alpha_min)}
 
 
 def cell_centres(g):
@@ -124,22 +131,22 @@ def piston(nx=200, ny=20, angle_deg=30.0, speed=0.3, face=(0.1, 0.05), bc=(0, 0,
             "cfl": 0.8, "t_end": 0.5, "normal": n, "speed": speed, "face": face}
 
 
-def cylinder(nx=1024, ny=512, radius=0.1, centre=(0.5, 0.5), speed=1.0, n_poly=1024):
+def cylinder(nx=1024, ny=512, radius=0.1, centre=(0.5, 0.5), speed=1.0, n_poly=1024, alpha_min=SMALL_CELL):
     """Circular cylinder crossing a stationary Mach-2 shock at x = 1 on [0,2]x[0,1]."""
-    g = grid(nx, ny, 0.0, 2.0, 0.0, 1.0)
+    g = grid(nx, ny, 0.0, 2.0, 0.0, 1.0, alpha_min=alpha_min)
     up, down = mach2_stationary_shock()
     b = body(circle(radius, n_poly), ref=centre, vel=(speed, 0.0))
     return {"name": "cylinder", "grid": g, "body": b, "prim": split_prim(g, 1.0, up, down),
             "cfl": 0.8, "steps": 2000}
 
 
-def triangle_case(seed, nx=2048, ny=1024, side=0.2, centre=(0.5, 0.5)):
+def triangle_case(seed, nx=2048, ny=1024, side=0.2, centre=(0.5, 0.5), alpha_min=SMALL_CELL):
     """Equilateral triangle crossing the Mach-2 stationary shock; orientation uniform in
     [0, 60) degrees and speed uniform in [0.5, 1.5] drawn from the seed."""
     rng = np.random.default_rng(seed)
     ang = math.radians(rng.uniform(0.0, 60.0))
     spd = rng.uniform(0.5, 1.5)
-    g = grid(nx, ny, 0.0, 2.0, 0.0, 1.0)
+    g = grid(nx, ny, 0.0, 2.0, 0.0, 1.0, alpha_min=alpha_min)
     up, down = mach2_stationary_shock()
     b = body(triangle(side), ref=centre, theta0=ang, vel=(spd, 0.0))
     return {"name": "triangle", "grid": g, "body": b, "prim": split_prim(g, 1.0, up, down),
@@ -174,7 +181,7 @@ def serving_request(k):
     rng = np.random.default_rng(1000 + k)
     nx, ny = SERVING_GRIDS[rng.integers(len(SERVING_GRIDS))]
     xe = nx / ny
-    g = grid(nx, ny, 0.0, xe, 0.0, 1.0)
+    g = grid(nx, ny, 0.0, xe, 0.0, 1.0, alpha_min=SMALL_CELL)
     kind = ["circle", "triangle", "naca", "piston"][rng.integers(4)]
     motion = ["translate", "pitch"][rng.integers(2)]
     centre = (0.25 * xe, 0.5)

@@ -93,22 +93,34 @@ def test_geometry_matches_oracle(name, w):
 
 
 def sweep_cases():
-    yield "piston30", W.piston(), 6
-    yield "piston_reflective", W.piston(nx=64, ny=16, bc=(1, 1, 1, 1)), 6
-    yield "cylinder", W.cylinder(nx=128, ny=64), 6
-    yield "triangle", W.triangle_case(2, nx=96, ny=48), 6
+    """(name, workload, oracle-only steps before the comparison, compared steps)."""
+    yield "piston30", W.piston(), 0, 6
+    yield "piston_reflective", W.piston(nx=64, ny=16, bc=(1, 1, 1, 1)), 0, 6
+    yield "cylinder", W.cylinder(nx=128, ny=64), 0, 6
+    yield "cylinder_no_threshold", W.cylinder(nx=128, ny=64, alpha_min=0.0), 0, 4
+    # cut cells collapse before (from step 64) and after covering (step 99)
+    yield "cylinder_collapses", W.cylinder(nx=128, ny=64), 60, 45
+    yield "triangle", W.triangle_case(2, nx=96, ny=48), 0, 6
     w = W.naca(nx=96, ny=96)
     w["body"]["pitch_amp"] = math.radians(8.0)
     w["body"]["pitch_omega"] = 2.0
-    yield "naca_pitch", w, 6
-    yield "nobody_ragged", {**W.cylinder(nx=61, ny=29), "body": None}, 4
+    yield "naca_pitch", w, 0, 6
+    yield "nobody_ragged", {**W.cylinder(nx=61, ny=29), "body": None}, 0, 4
     for k in (0, 3, 7):
-        yield f"req{k}", W.serving_request(k), 4
+        yield f"req{k}", W.serving_request(k), 0, 4
+    # impulsive starts: collapses before and after covering in the first step
+    for k in (4, 10):
+        yield f"req{k}_impulsive", W.serving_request(k), 0, 2
 
 
-@pytest.mark.parametrize("name,w,nsteps", list(sweep_cases()), ids=[c[0] for c in sweep_cases()])
-def test_sweeps_match_oracle_from_identical_inputs(name, w, nsteps):
+@pytest.mark.parametrize("name,w,skip,nsteps", list(sweep_cases()), ids=[c[0] for c in sweep_cases()])
+def test_sweeps_match_oracle_from_identical_inputs(name, w, skip, nsteps):
     o, s = pair(w)
+    for _ in range(skip):
+        o.step(o.cfl_dt(w["cfl"]))
+    if skip:
+        s.set_clock(o.t, o.steps)
+    c0 = o.collapses
     worst = 0.0
     for k in range(nsteps):
         dt = o.cfl_dt(w["cfl"])
@@ -133,7 +145,8 @@ def test_sweeps_match_oracle_from_identical_inputs(name, w, nsteps):
                                      f"alpha_s {gs:.3e} alpha_e {ge:.3e} gpu {Ug[:, j, i]} oracle {Uo[:, j, i]}")
         o.end_step()
         s.end_step()
-    assert s.info()["status"] == 0
+    assert s.info()["status"] == 0 and o.status == 0
+    assert s.info()["collapses"] == o.collapses - c0
 
 
 def test_end_time_parity_config1():
@@ -176,3 +189,26 @@ def test_full_size_one_step(which):
     s.step(dt)
     e = rel_linf(s.get_u(), o.get_u())
     assert e <= FP64_TOL, e
+
+
+def test_restart_from_saved_state_is_bit_exact():
+    """cc_set_clock + cc_set_u resume a saved (t, step count, U) bit for bit."""
+    w = W.cylinder(nx=128, ny=64)
+    s = cc.Solver(w["grid"], w["body"])
+    s.set_prim(w["prim"])
+    dts, saved = [], None
+    for k in range(9):
+        if k == 4:
+            saved = (s.get_u(), s.info()["t"])
+        dt = s.cfl_dt(w["cfl"])
+        dts.append(dt)
+        s.step(dt)
+    r = cc.Solver(w["grid"], w["body"])
+    r.set_prim(w["prim"])
+    r.run(w["cfl"], dts=[0.6 * dt for dt in dts[:6]])
+    r.set_clock(saved[1], 4)
+    r.set_u(saved[0])
+    for dt in dts[4:]:
+        r.step(dt)
+    assert r.info()["steps"] == 9
+    assert np.array_equal(r.get_u(), s.get_u())

@@ -42,21 +42,28 @@ def test_rest_gas_static_body_is_exact():
         assert np.abs(P[3][m] - 1.0).max() < 1e-13 and o.collapses == 0
 
 
-@pytest.mark.parametrize("kind", ["circle", "triangle", "piston30", "naca_translating"])
-def test_body_moving_with_the_flow_keeps_it_uniform(kind):
+def moving_with_flow(kind, alpha_min=0.0):
     if kind == "circle":
-        w = W.cylinder(nx=96, ny=48, speed=0.5)
+        w = W.cylinder(nx=96, ny=48, speed=0.5, alpha_min=alpha_min)
         u = (0.5, 0.0)
     elif kind == "triangle":
-        w = W.triangle_case(7, nx=96, ny=48)
+        w = W.triangle_case(7, nx=96, ny=48, alpha_min=alpha_min)
         u = w["body"]["vel"]
     elif kind == "piston30":
         w = W.piston(speed=0.3)
+        w["grid"]["alpha_min"] = alpha_min
         u = (0.3 * w["normal"][0], 0.3 * w["normal"][1])
     else:
-        w = W.cylinder(nx=96, ny=48)
+        w = W.cylinder(nx=96, ny=48, alpha_min=alpha_min)
         w["body"] = W.body(W.naca00(0.12, 0.6, 128, 0.25), ref=(0.5, 0.5), theta0=0.2, vel=(0.6, 0.2))
         u = (0.6, 0.2)
+    return w, u
+
+
+@pytest.mark.parametrize("kind", ["circle", "triangle", "piston30", "naca_translating"])
+def test_body_moving_with_the_flow_keeps_it_uniform(kind):
+    """Paper's method as printed (no small-cell threshold)."""
+    w, u = moving_with_flow(kind)
     o = make(w, W.uniform_prim(w["grid"], 1.3, u[0], u[1], 0.9))
     o.run(0.8, nsteps=25)
     P, m = live_prim(o)
@@ -72,18 +79,26 @@ def test_body_moving_with_the_flow_keeps_it_uniform(kind):
     assert o.status == 0
 
 
-@pytest.mark.parametrize("case", ["piston", "cylinder", "naca_pitch"])
+@pytest.mark.parametrize("case", ["piston", "cylinder", "cylinder_no_threshold", "impulsive_collapses", "naca_pitch"])
 def test_conservation_budget_per_sweep(case):
+    nsteps = 12
     if case == "piston":
         w = W.piston()
     elif case == "cylinder":
         w = W.cylinder(nx=96, ny=48)
+    elif case == "cylinder_no_threshold":
+        w = W.cylinder(nx=96, ny=48, alpha_min=0.0)
+    elif case == "impulsive_collapses":
+        # a cylinder started impulsively in a Mach-2 stream: cut cells collapse in the first
+        # step, before and after covering
+        w = W.serving_request(10)
+        nsteps = 2
     else:
         w = W.naca(nx=96, ny=96)
         w["body"]["pitch_amp"] = math.radians(8.0)
         w["body"]["pitch_omega"] = 2.0
     o = make(w)
-    for _ in range(12):
+    for _ in range(nsteps):
         dt = o.cfl_dt(0.8)
         o.begin_step(dt)
         for d in (o.parity, 1 - o.parity):
@@ -95,8 +110,32 @@ def test_conservation_budget_per_sweep(case):
             T1 = o.totals()
             b1, w1, l1 = o.budget()
             resid = (T1 - T0) - (b1 - b0) - (w1 - w0) + (l1 - l0)
-            assert (np.abs(resid) <= 64 * 2.2e-16 * scale).all(), (resid, scale)
+            # round-off of the totals (sums over all cells) grows like sqrt(cells)
+            bound = 64 * 2.2e-16 * scale * max(1.0, math.sqrt(o.nx * o.ny) / 64)
+            assert (np.abs(resid) <= bound).all(), (resid, scale)
         o.end_step()
+    assert o.status == 0
+    if case == "impulsive_collapses":
+        assert o.collapses > 0
+
+
+def test_small_cell_threshold_keeps_uniform_flow_nearly_uniform():
+    """Reading R19: cut cells below alpha_min = 1e-2 count as solid.  A body moving with a
+    uniform flow then disturbs it only where cells cross the threshold: the volume-weighted
+    L1 error stays below 1e-3 (the paper-literal method keeps it to round-off, see
+    test_body_moving_with_the_flow_keeps_it_uniform), and nothing collapses."""
+    for kind in ("circle", "triangle", "piston30", "naca_translating"):
+        w, u = moving_with_flow(kind, alpha_min=1e-2)
+        o = make(w, W.uniform_prim(w["grid"], 1.3, u[0], u[1], 0.9))
+        o.run(0.8, nsteps=25)
+        P, m = live_prim(o)
+        al = o.geometry_dump(0)["alpha"]
+        assert al[(al > 0) & (al < 1e-2)].size == 0
+        ref_state = (1.3, u[0], u[1], 0.9)
+        for k in range(4):
+            err = np.abs(P[k][m] - ref_state[k])
+            assert (al[m] * err).sum() / al[m].sum() < 1e-3, (kind, k)
+        assert o.status == 0
 
 
 def sod(nx, ny=3):
@@ -178,3 +217,31 @@ def test_static_body_in_flow_stays_bounded():
     P, m = live_prim(o)
     assert o.collapses == 0 and o.status == 0
     assert 0.85 < P[0][m].min() and P[0][m].max() < 1.15
+
+
+def test_restart_from_saved_state_is_bit_exact():
+    """Resuming from a saved (t, step count, U) continues the uninterrupted run bit for bit:
+    the sweep order alternates with the step count (Sec. 2.3.1) and the level-n geometry is
+    rebuilt from the body pose at t; re-initialising a used context reproduces a fresh run."""
+    w = W.cylinder(nx=64, ny=32)
+    o = make(w)
+    dts = o.run(0.8, nsteps=7)
+    U_mid, t_mid = None, None
+    o2 = make(w)
+    for k, dt in enumerate(dts):
+        if k == 3:
+            U_mid, t_mid = o2.get_u(), o2.t
+        o2.step(dt)
+    assert np.array_equal(o2.get_u(), o.get_u())
+    r = make(w)
+    r.run(0.8, dts=[0.6 * dt for dt in dts[:5]])  # other body positions in steps 0-4
+    r.set_clock(t_mid, 3)
+    r.set_u(U_mid)
+    for dt in dts[3:]:
+        r.step(dt)
+    assert r.steps == 7 and r.t == o.t
+    assert np.array_equal(r.get_u(), o.get_u())
+    r.set_prim(w["prim"])
+    for dt in dts:
+        r.step(dt)
+    assert np.array_equal(r.get_u(), o.get_u())
