@@ -134,17 +134,71 @@ cc_status cc_cfl_dt(cc_ctx* ctx, double cfl, double* h_dt);
 /* Conservation totals sum(U) hx hy per component, FP64, deterministic order.  Host out. */
 cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
 
-/* Host info vector (n entries used, up to 8): time, steps, parity, device status bits,
- * collapsed-cell count, sweep box cells of the last sweep, staging capacity, spare. */
+/* Host info vector (n entries used, up to 9): time, steps, parity, device status bits
+ * (1: a cell became fluid without donors; 2: a cell stayed inadmissible after collapsing),
+ * collapsed-cell count, sweep box cells of the last sweep, staging capacity, rows per block
+ * of the dense x-sweep, rows per tile of the dense y-sweep.  Synchronizes. */
 cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
 
-/* Per-kernel timing with HIP events on the context's stream.  cc_timing(ctx, 1) starts
- * recording; cc_timing_read returns, since the last read, pairs (total ms, launches) for:
- * dense x, dense y, box kernels, geometry (8 doubles). */
-cc_status cc_timing(cc_ctx* ctx, int32_t enable);
+/* Tile tuner for the dense sweeps (the regular cells): times every tile shape of both
+ * sweeps on this grid, reps launches each, from the current state into the spare state
+ * buffer, and keeps the fastest for this context.  h_choice (nullable, host, 2 entries)
+ * receives the chosen variant indices.  Needs a state and no open step (CC_ERR_ARG).
+ * Synchronizes; results do not depend on the choice (every shape computes the same
+ * values, bit for bit). */
+cc_status cc_autotune(cc_ctx* ctx, int32_t reps, int32_t* h_choice);
+/* Set the dense-sweep tile variants directly: tile_x indexes rows per x-sweep block
+ * {1, 2, 4, 8}, tile_y rows per y-sweep tile {8, 12, 16, 24} (16 and 24 only with FP32
+ * state: the tile lives in 64 KiB of LDS).  CC_ERR_ARG for an index out of range. */
+cc_status cc_set_tiles(cc_ctx* ctx, int32_t tile_x, int32_t tile_y);
+
+/* Timing with HIP events on the context's stream.  mode bit 0: each dense-sweep launch
+ * records its own start/stop events (no extra stream commands, so the interval is the
+ * kernel's execution); bit 1: events bracket the box-kernel and geometry phases (extra
+ * stream commands).  0 stops recording.  cc_timing_read returns, since the last read,
+ * pairs (total ms, count) for: dense x, dense y, box phases, geometry (8 doubles). */
+cc_status cc_timing(cc_ctx* ctx, int32_t mode);
 cc_status cc_timing_read(cc_ctx* ctx, double* h_out, int32_t n);
 
 const char* cc_last_error(const cc_ctx* ctx);
+
+/* ------------------------------------------------------------------------- batches
+ * A batch steps many contexts of one precision together: every phase of the split step
+ * is one kernel launch over all members (grids sized from each member's capacities, so a
+ * whole step is one captured HIP graph, replayed while the membership is unchanged).
+ * Members keep their own workspaces, state, clock and step order; a context in a batch
+ * is stepped only through it (cc_step, cc_begin_step and cc_autotune refuse).
+ * Membership may change between steps (continuous batching). */
+typedef struct cc_batch cc_batch; /* opaque */
+
+/* Device bytes for a batch of up to max_instances members (argument blocks, launch
+ * tables, read-back areas). */
+size_t cc_batch_workspace_bytes(int32_t max_instances);
+/* Create on the given stream (a hipStream_t, not the null stream, so that steps can be
+ * captured).  d_ws: device, >= cc_batch_workspace_bytes, 256-byte aligned, owned by the
+ * caller.  precision: cc_precision of every member.  CC_ERR_ARG / CC_ERR_WORKSPACE /
+ * CC_ERR_DEVICE on failure. */
+cc_status cc_batch_create(int32_t max_instances, int32_t precision, void* d_ws, size_t ws_bytes, void* hip_stream,
+                          cc_batch** out);
+cc_status cc_batch_destroy(cc_batch* b);
+/* Add a context with a state set and no open step (synchronizes its stream); CC_ERR_ARG
+ * if it is in a batch or of another precision, CC_ERR_WORKSPACE if the batch is full. */
+cc_status cc_batch_add(cc_batch* b, cc_ctx* ctx);
+cc_status cc_batch_remove(cc_batch* b, cc_ctx* ctx);
+int32_t cc_batch_size(const cc_batch* b);
+/* Dense-sweep tile variants used by every member (as cc_set_tiles). */
+cc_status cc_batch_set_tiles(cc_batch* b, int32_t tile_x, int32_t tile_y);
+/* One split step of every member, member k with time step h_dt[k] (host, in membership
+ * order).  Also reduces each member's wave speeds for its next step and gathers the
+ * status words; synchronizes.  h_status (nullable, host): each member's status bits. */
+cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status);
+/* Next time steps from the wave speeds the last cc_batch_step reduced (no device work);
+ * a member whose state is not finite or whose status is set gets 0 and its bits in
+ * h_status (nullable). */
+cc_status cc_batch_last_dt(cc_batch* b, double cfl, double* h_dt, int32_t* h_status);
+/* Time steps from each member's current state (cc_cfl_dt per member). */
+cc_status cc_batch_cfl_dt(cc_batch* b, double cfl, double* h_dt);
+const char* cc_batch_last_error(const cc_batch* b);
 
 #ifdef __cplusplus
 }

@@ -62,9 +62,22 @@ _sig = {
     "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
     "cc_totals": (C.c_int, [_vp, C.POINTER(_d)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
+    "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
+    "cc_set_tiles": (C.c_int, [_vp, _i32, _i32]),
     "cc_timing": (C.c_int, [_vp, _i32]),
     "cc_timing_read": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_last_error": (C.c_char_p, [_vp]),
+    "cc_batch_workspace_bytes": (C.c_size_t, [_i32]),
+    "cc_batch_create": (C.c_int, [_i32, _i32, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "cc_batch_destroy": (C.c_int, [_vp]),
+    "cc_batch_add": (C.c_int, [_vp, _vp]),
+    "cc_batch_remove": (C.c_int, [_vp, _vp]),
+    "cc_batch_size": (_i32, [_vp]),
+    "cc_batch_set_tiles": (C.c_int, [_vp, _i32, _i32]),
+    "cc_batch_step": (C.c_int, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
+    "cc_batch_last_dt": (C.c_int, [_vp, _d, C.POINTER(_d), C.POINTER(_i32)]),
+    "cc_batch_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
+    "cc_batch_last_error": (C.c_char_p, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -176,11 +189,21 @@ def cc_totals(ctx):
 
 
 def cc_info(ctx):
-    out = (_d * 8)()
-    _check(ctx, _lib.cc_info(ctx, out, 8))
+    out = (_d * 9)()
+    _check(ctx, _lib.cc_info(ctx, out, 9))
     v = out[:]
     return {"t": v[0], "steps": int(v[1]), "parity": int(v[2]), "status": int(v[3]), "collapses": int(v[4]),
-            "box_cells": int(v[5]), "capacity": int(v[6])}
+            "box_cells": int(v[5]), "capacity": int(v[6]), "tile_x_rows": int(v[7]), "tile_y_rows": int(v[8])}
+
+
+def cc_set_tiles(ctx, tile_x, tile_y):
+    _check(ctx, _lib.cc_set_tiles(ctx, int(tile_x), int(tile_y)))
+
+
+def cc_autotune(ctx, reps=20):
+    out = (_i32 * 2)()
+    _check(ctx, _lib.cc_autotune(ctx, int(reps), out))
+    return out[0], out[1]
 
 
 def cc_timing(ctx, enable):
@@ -194,26 +217,87 @@ def cc_timing_read(ctx):
     return {"dense_x": (v[0], v[1]), "dense_y": (v[2], v[3]), "box": (v[4], v[5]), "geometry": (v[6], v[7])}
 
 
+def _bcheck(b, st):
+    if st != CC_OK:
+        raw = _lib.cc_batch_last_error(b)
+        raise CCError(st, raw.decode() if raw else "")
+
+
+def cc_batch_workspace_bytes(max_instances):
+    return _lib.cc_batch_workspace_bytes(int(max_instances))
+
+
+def cc_batch_create(max_instances, precision, d_ws, ws_bytes, stream):
+    out = _vp()
+    _bcheck(None, _lib.cc_batch_create(int(max_instances), int(precision), _vp(d_ws), ws_bytes, _vp(stream),
+                                       C.byref(out)))
+    return out
+
+
+def cc_batch_destroy(b):
+    _bcheck(b, _lib.cc_batch_destroy(b))
+
+
+def cc_batch_add(b, ctx):
+    _bcheck(b, _lib.cc_batch_add(b, ctx))
+
+
+def cc_batch_remove(b, ctx):
+    _bcheck(b, _lib.cc_batch_remove(b, ctx))
+
+
+def cc_batch_size(b):
+    return int(_lib.cc_batch_size(b))
+
+
+def cc_batch_set_tiles(b, tile_x, tile_y):
+    _bcheck(b, _lib.cc_batch_set_tiles(b, int(tile_x), int(tile_y)))
+
+
+def cc_batch_step(b, dts):
+    n = len(dts)
+    d = (_d * max(n, 1))(*dts)
+    st = (_i32 * max(n, 1))()
+    _bcheck(b, _lib.cc_batch_step(b, d, st))
+    return list(st[:n])
+
+
+def cc_batch_last_dt(b, cfl, n):
+    d = (_d * max(n, 1))()
+    st = (_i32 * max(n, 1))()
+    _bcheck(b, _lib.cc_batch_last_dt(b, cfl, d, st))
+    return list(d[:n]), list(st[:n])
+
+
+def cc_batch_cfl_dt(b, cfl, n):
+    d = (_d * max(n, 1))()
+    _bcheck(b, _lib.cc_batch_cfl_dt(b, cfl, d))
+    return list(d[:n])
+
+
 # ----------------------------------------------------------------- torch-backed solver
 class Solver:
     """A simulation context whose device memory (workspace, I/O buffers) is owned by torch
-    on `device`, launched on torch's current stream for that device."""
+    on `device`.  It runs on a stream of its own (a captured step needs a stream other than
+    the null stream); the binding's tensor copies run on that stream too."""
 
     def __init__(self, grid, body=None, precision=CC_FP64, device="cuda:0"):
         import torch
         self.torch = torch
         self.grid = dict(grid)
         self.nx, self.ny = grid["nx"], grid["ny"]
+        self.precision = precision
         self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)
         self._cfg = make_config(grid, precision)
         self._body, self._verts = make_body(body)
         self.ws_bytes = cc_workspace_bytes(self._cfg, self._body)
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            self._io = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=self.device)
         base = self.ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        self.stream = torch.cuda.current_stream(self.device)
         self.ctx = cc_create(self._cfg, self._body, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
-        self._io = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=self.device)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -226,30 +310,39 @@ class Solver:
         except Exception:
             pass
 
+    def _on_stream(self):
+        return self.torch.cuda.stream(self.stream)
+
     def set_prim(self, prim, t0=0.0):
-        self._io.copy_(self.torch.as_tensor(np.asarray(prim, dtype=np.float64).reshape(4, self.ny, self.nx)))
-        cc_set_state(self.ctx, self._io.data_ptr(), t0)
+        with self._on_stream():
+            self._io.copy_(self.torch.as_tensor(np.asarray(prim, dtype=np.float64).reshape(4, self.ny, self.nx)))
+            cc_set_state(self.ctx, self._io.data_ptr(), t0)
 
     def set_clock(self, t, step):
         """Resume at time t after `step` split steps; set the state afterwards."""
         cc_set_clock(self.ctx, t, step)
 
     def set_u(self, U):
-        self._io.copy_(self.torch.as_tensor(np.asarray(U, dtype=np.float64).reshape(4, self.ny, self.nx)))
-        cc_set_u(self.ctx, self._io.data_ptr())
+        with self._on_stream():
+            self._io.copy_(self.torch.as_tensor(np.asarray(U, dtype=np.float64).reshape(4, self.ny, self.nx)))
+            cc_set_u(self.ctx, self._io.data_ptr())
 
     def get_u_tensor(self):
-        out = self.torch.empty((4, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
-        cc_get_state(self.ctx, out.data_ptr(), 1)
+        """Conserved state as an FP64 tensor, valid on this solver's stream."""
+        with self._on_stream():
+            out = self.torch.empty((4, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+            cc_get_state(self.ctx, out.data_ptr(), 1)
         return out
 
     def get_u(self):
-        return self.get_u_tensor().cpu().numpy()
+        with self._on_stream():
+            return self.get_u_tensor().cpu().numpy()
 
     def get_prim(self):
-        out = self.torch.empty((4, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
-        cc_get_state(self.ctx, out.data_ptr(), 0)
-        return out.cpu().numpy()
+        with self._on_stream():
+            out = self.torch.empty((4, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+            cc_get_state(self.ctx, out.data_ptr(), 0)
+            return out.cpu().numpy()
 
     def geometry(self, t, level=0):
         cc_geometry(self.ctx, t, level)
@@ -257,12 +350,14 @@ class Solver:
     def geometry_dump(self, level=0):
         t = self.torch
         nx, ny = self.nx, self.ny
-        vc = t.empty((ny + 1, nx + 1), dtype=t.int8, device=self.device)
-        al = t.empty((ny, nx), dtype=t.float64, device=self.device)
-        bx = t.empty((ny, nx + 1), dtype=t.float64, device=self.device)
-        by = t.empty((ny + 1, nx), dtype=t.float64, device=self.device)
-        cc_geometry_dump(self.ctx, level, vc.data_ptr(), al.data_ptr(), bx.data_ptr(), by.data_ptr())
-        return {"vcls": vc.cpu().numpy(), "alpha": al.cpu().numpy(), "bx": bx.cpu().numpy(), "by": by.cpu().numpy()}
+        with self._on_stream():
+            vc = t.empty((ny + 1, nx + 1), dtype=t.int8, device=self.device)
+            al = t.empty((ny, nx), dtype=t.float64, device=self.device)
+            bx = t.empty((ny, nx + 1), dtype=t.float64, device=self.device)
+            by = t.empty((ny + 1, nx), dtype=t.float64, device=self.device)
+            cc_geometry_dump(self.ctx, level, vc.data_ptr(), al.data_ptr(), bx.data_ptr(), by.data_ptr())
+            return {"vcls": vc.cpu().numpy(), "alpha": al.cpu().numpy(), "bx": bx.cpu().numpy(),
+                    "by": by.cpu().numpy()}
 
     def begin_step(self, dt):
         cc_begin_step(self.ctx, dt)
@@ -284,6 +379,13 @@ class Solver:
 
     def info(self):
         return cc_info(self.ctx)
+
+    def set_tiles(self, tile_x, tile_y):
+        cc_set_tiles(self.ctx, tile_x, tile_y)
+
+    def autotune(self, reps=20):
+        """Pick the fastest dense-sweep tile shapes for this grid (needs a state)."""
+        return cc_autotune(self.ctx, reps)
 
     @property
     def parity(self):
@@ -310,3 +412,56 @@ class Solver:
             used.append(dt)
             k += 1
         return used
+
+
+class Batch:
+    """Contexts of one precision stepped together (continuous batching): one launch per
+    phase over all members, a captured graph per membership.  Device memory is owned by
+    torch; the batch runs on a stream of its own."""
+
+    def __init__(self, max_instances, precision=CC_FP64, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.max_instances = int(max_instances)
+        nbytes = cc_batch_workspace_bytes(max_instances)
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.b = cc_batch_create(max_instances, precision, ptr, nbytes, self.stream.cuda_stream)
+        self.members = []
+
+    def close(self):
+        if getattr(self, "b", None):
+            cc_batch_destroy(self.b)
+            self.b = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, solver):
+        cc_batch_add(self.b, solver.ctx)
+        self.members.append(solver)
+
+    def remove(self, solver):
+        cc_batch_remove(self.b, solver.ctx)
+        self.members.remove(solver)
+
+    def set_tiles(self, tile_x, tile_y):
+        cc_batch_set_tiles(self.b, tile_x, tile_y)
+
+    def step(self, dts):
+        """One step of every member (member k with dts[k]); returns the status words."""
+        return cc_batch_step(self.b, list(dts))
+
+    def last_dt(self, cfl):
+        """Next time steps from the speeds reduced by the last step, and status words."""
+        return cc_batch_last_dt(self.b, cfl, len(self.members))
+
+    def cfl_dt(self, cfl):
+        return cc_batch_cfl_dt(self.b, cfl, len(self.members))

@@ -1,6 +1,7 @@
-// Host side of the cut-cell library: context, workspace carving, body posing, level
-// bookkeeping and kernel launches for the split step.
+// Host side of the cut-cell library: contexts, batches, workspace carving, body posing,
+// level bookkeeping, per-step argument blocks and the launch sequence of the split step.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -11,6 +12,7 @@
 
 #include "../../include/cc.h"
 #include "cc_device.h"
+#include "engine.h"
 #include "geometry.h"
 #include "reduce.h"
 #include "sweep.h"
@@ -22,20 +24,47 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int NPART = 1024;  // blocks of the deterministic sum
 constexpr int TPB = 256;
-constexpr int TPB_BOX = 64;  // small box kernels: spread a few thousand cells over all CUs
+constexpr int CFL_MAX_BLOCKS = 512;
 
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+// Dense-sweep tile variants: rows per block of the x-sweep, rows per tile of the y-sweep
+// (the y tile lives in LDS: (2 TR + 7) x 64 x 4 values, kept within 64 KiB).
+constexpr int NX_VARIANTS = 4, NY_VARIANTS = 4;
+constexpr int X_RB[NX_VARIANTS] = {1, 2, 4, 8};
+constexpr int Y_TR[NY_VARIANTS] = {8, 12, 16, 24};
+
+bool dense_variant_ok(int prec, int dir, int v) {
+    size_t rs = prec == CC_FP32_GEOM64 ? 4 : 8;
+    if (dir == 0) return v >= 0 && v < NX_VARIANTS;
+    if (v < 0 || v >= NY_VARIANTS) return false;
+    return (size_t)(2 * Y_TR[v] + 7) * 64 * 4 * rs <= 65536;
+}
+int dense_blocks(int dir, int v, int nx, int ny) {
+    if (dir == 0) {
+        int rb = X_RB[v];
+        return ((nx + DX_OUT - 1) / DX_OUT) * ((ny + rb - 1) / rb);
+    }
+    int tr = Y_TR[v];
+    return ((nx + 63) / 64) * ((ny + tr - 1) / tr);
+}
+
+// --------------------------------------------------------------------------- workspace
 struct Layout {
     size_t nc, nvx, nfx, nfy, cap, capf;
     size_t u_bytes;
     size_t off_u[2], off_vcls[3], off_fx[3], off_fy[3], off_alpha[3], off_poly[3];
+    size_t off_body;
     size_t off_qb, off_stamp;
     size_t off_sQ, off_sU1, off_shas, off_sbt, off_swall, off_sfb, off_swv, off_sahat, off_sU2, off_sgone;
     size_t off_sf1, off_sf2, off_nbad;
+    size_t off_glist[2], off_gcnt, off_slist, off_scnt;
+    size_t off_args, off_offs, off_cflout, off_gather;
     size_t off_smax, off_status, off_ncol, off_part, off_tot;
     size_t total;
-    int capw, caph;
+    int capw, caph;  // sweep-box capacity (cells)
+    int gw, gh;      // geometry-region capacity (cells)
+    size_t glist_cap, slist_cap;
 };
 
 int body_m(const cc_body* b) { return b && b->nverts > 0 && b->verts ? b->nverts : 0; }
@@ -50,7 +79,7 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.nfy = (ny + 1) * nx;
     size_t rs = c->precision == CC_FP32_GEOM64 ? sizeof(float) : sizeof(double);
     L.u_bytes = 4 * L.nc * rs;
-    // staging capacity: the body stays inside a disc of radius R about its moving origin
+    // capacities: the body stays inside a disc of radius R about its moving origin
     double R = 0.0;
     for (int k = 0; k < m; k++) R = std::max(R, std::hypot(b->verts[2 * k], b->verts[2 * k + 1]));
     double hx = (c->x_hi - c->x_lo) / c->nx, hy = (c->y_hi - c->y_lo) / c->ny;
@@ -58,15 +87,20 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
         double cw = std::ceil(2.0 * R / hx) + 16.0, ch = std::ceil(2.0 * R / hy) + 16.0;
         L.capw = (int)std::min<double>(cw, (double)nx);
         L.caph = (int)std::min<double>(ch, (double)ny);
+        L.gw = (int)std::min<double>(cw + 4.0, (double)nx);
+        L.gh = (int)std::min<double>(ch + 4.0, (double)ny);
     } else {
-        L.capw = L.caph = 0;
+        L.capw = L.caph = L.gw = L.gh = 0;
     }
     L.cap = (size_t)L.capw * L.caph;
     L.capf = m > 0 ? (size_t)(L.capw + 1) * (L.caph + 1) : 0;
+    size_t gf = (size_t)(L.gw + 1) * L.gh + (size_t)L.gw * (L.gh + 1);
+    L.glist_cap = std::max<size_t>(gf, (size_t)(L.gw + 1) * (L.gh + 1));
+    L.slist_cap = L.capf;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
-        o += up(bytes);
+        o += up(std::max<size_t>(bytes, 1));
         return r;
     };
     L.off_u[0] = take(L.u_bytes);
@@ -78,6 +112,7 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
         L.off_alpha[s] = take(L.nc * 8);
         L.off_poly[s] = take((size_t)std::max(m, 1) * 16);
     }
+    L.off_body = take((size_t)std::max(m, 1) * 16);
     L.off_qb = take(m > 0 ? 4 * L.nc * 8 : 8);
     L.off_stamp = take(m > 0 ? L.nc * 4 : 4);
     size_t cap = std::max<size_t>(L.cap, 1), capf = std::max<size_t>(L.capf, 1);
@@ -94,10 +129,19 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_sf1 = take(cap);
     L.off_sf2 = take(cap);
     L.off_nbad = take(8);
+    L.off_glist[0] = take(std::max<size_t>(L.glist_cap, 1) * 4);
+    L.off_glist[1] = take(std::max<size_t>(L.glist_cap, 1) * 4);
+    L.off_gcnt = take(6 * 4);
+    L.off_slist = take(std::max<size_t>(L.slist_cap, 1) * 4);
+    L.off_scnt = take(4);
+    L.off_args = take(sizeof(StepArgs));
+    L.off_offs = take((size_t)NKINDS * 3 * 4);
+    L.off_cflout = take(16);
+    L.off_gather = take(16);
     L.off_smax = take(16);
     L.off_status = take(4);
     L.off_ncol = take(4);
-    L.off_part = take(4 * NPART * 8);
+    L.off_part = take(std::max<size_t>(4 * NPART * 8, 2 * CFL_MAX_BLOCKS * 8));
     L.off_tot = take(4 * 8);
     L.total = o;
     return L;
@@ -106,6 +150,30 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
 struct TimedPair {
     hipEvent_t a, b;
     int kind;
+};
+
+// --------------------------------------------------------------------------- engine
+// Launch plan for the members of a batch (one member for a context's own calls): per-step
+// argument blocks (two pinned host buffers, one device array), per-launch offset tables and
+// the captured graphs of a whole step.
+struct Engine {
+    int prec = CC_FP64;
+    int cap_n = 0;
+    std::vector<cc_ctx*> mem;
+    StepArgs* h_args[2] = {nullptr, nullptr};
+    StepArgs* d_args = nullptr;
+    int* d_off = nullptr;  // NKINDS tables of (units + 1) entries, stride 2 cap_n + 1
+    std::vector<int> h_off[NKINDS];
+    unsigned long long* d_cflout = nullptr;  // 2 per member
+    unsigned long long* h_cflout = nullptr;  // pinned
+    unsigned int* d_gather = nullptr;        // status and collapse count per member
+    unsigned int* h_gather = nullptr;        // pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};   // last use of host buffer b
+    bool ev_used[2] = {false, false};
+    int buf = 0;
+    int tile_x = 0, tile_y = 1;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gkey[2] = {-1, -1};
 };
 
 }  // namespace
@@ -119,14 +187,9 @@ struct cc_ctx {
     int m;
     std::vector<double> bverts;
     double ref_x, ref_y, theta0, vx, vy, amp, omega;
-    // state
-    int cur;  // U[cur] holds the level-n (or current) state
-    // levels
+    int cur;  // U[cur] holds the level-n state
     Level lev[3];
-    Box lbox[3];        // region of each slot that may differ from all-fluid
-    double* hpoly[3];   // pinned host copies of the posed polygons
-    hipEvent_t poly_ev[3];
-    bool poly_ev_valid[3];
+    Box lbox[3];  // region of each slot that may differ from all-fluid
     int s0, sm, s1;
     double t;
     int64_t step;
@@ -137,11 +200,18 @@ struct cc_ctx {
     Motion mot;
     double hx, hy;
     Box last_sweep_box;
-    // timing
-    bool timing;
+    Engine eng;  // launch plan of this context's own calls
+    cc_batch* batch;  // batch this context belongs to, if any
+    // timing: bit 0 dense sweeps, bit 1 box and geometry phases
+    int timing;
     std::vector<TimedPair> pending, pool;
-    double tsum[4];
-    double tcnt[4];
+    std::string err;
+};
+
+struct cc_batch {
+    Engine eng;
+    hipStream_t stream;
+    char* ws;
     std::string err;
 };
 
@@ -151,6 +221,10 @@ thread_local std::string g_create_err;  // message of the last failed cc_create 
 
 cc_status fail(cc_ctx* c, cc_status s, const std::string& msg) {
     if (c) c->err = msg;
+    return s;
+}
+cc_status bfail(cc_batch* b, cc_status s, const std::string& msg) {
+    if (b) b->err = msg;
     return s;
 }
 
@@ -165,6 +239,11 @@ cc_status create_fail(cc_ctx* c, cc_status s, const std::string& msg) {
         hipError_t e_ = (expr);                                                             \
         if (e_ != hipSuccess) return fail(ctx, CC_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
+#define BHIPCHK(b, expr)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return bfail(b, CC_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
 
 template <typename T>
 T* at(cc_ctx* c, size_t off) {
@@ -173,14 +252,20 @@ T* at(cc_ctx* c, size_t off) {
 
 bool fp32(const cc_ctx* c) { return c->cfg.precision == CC_FP32_GEOM64; }
 
-void pose(const cc_ctx* c, double t, double* out) {
+// Rigid pose at time t: rotation by theta(t) about the body-frame origin, then the origin
+// at ref + v t.  The device poses with the same formula from (cs, sn, cx, cy).
+struct Pose {
+    double cs, sn, cx, cy;
+};
+Pose pose_at(const cc_ctx* c, double t) {
     double th = c->theta0 + c->amp * std::sin(c->omega * t);
-    double cs = std::cos(th), sn = std::sin(th);
-    double cx = c->ref_x + c->vx * t, cy = c->ref_y + c->vy * t;
+    return Pose{std::cos(th), std::sin(th), c->ref_x + c->vx * t, c->ref_y + c->vy * t};
+}
+void pose_xy(const cc_ctx* c, const Pose& px, const Pose& py, double* out) {
     for (int k = 0; k < c->m; k++) {
         double bx = c->bverts[2 * k], by = c->bverts[2 * k + 1];
-        out[2 * k] = (cs * bx - sn * by) + cx;
-        out[2 * k + 1] = (sn * bx + cs * by) + cy;
+        out[2 * k] = (px.cs * bx - px.sn * by) + px.cx;
+        out[2 * k + 1] = (py.sn * bx + py.cs * by) + py.cy;
     }
 }
 
@@ -247,11 +332,12 @@ Box box_union(const Box& a, const Box& b) {
     return Box{std::min(a.i0, b.i0), std::max(a.i1, b.i1), std::min(a.j0, b.j0), std::max(a.j1, b.j1)};
 }
 
+bool geo_fits(const cc_ctx* c, const Box& r) { return box_empty(r) || (r.w() <= c->lay.gw && r.h() <= c->lay.gh); }
+
 unsigned nblk(size_t n, int t = TPB) { return (unsigned)((n + t - 1) / t); }
 
-
 void tstart(cc_ctx* c, int kind, TimedPair& tp) {
-    if (!c->timing) return;
+    if (!(c->timing & 2)) return;
     if (c->pool.empty()) {
         TimedPair p;
         (void)hipEventCreate(&p.a);
@@ -264,64 +350,26 @@ void tstart(cc_ctx* c, int kind, TimedPair& tp) {
     (void)hipEventRecord(tp.a, c->stream);
 }
 void tstop(cc_ctx* c, TimedPair& tp) {
-    if (!c->timing) return;
+    if (!(c->timing & 2)) return;
     (void)hipEventRecord(tp.b, c->stream);
     c->pending.push_back(tp);
 }
 
-// Compute the geometry of a posed polygon into a slot (device), over the union of the
-// slot's previous region and the polygon's box.
-cc_status compute_level(cc_ctx* c, int slot, const double* pv) {
-    Level& L = c->lev[slot];
-    Box cells;
-    poly_info(c, pv, L.poly, cells);
-    if (c->m > 0) {
-        if (c->poly_ev_valid[slot]) HIPCHK(c, hipEventSynchronize(c->poly_ev[slot]));
-        std::memcpy(c->hpoly[slot], pv, sizeof(double) * 2 * c->m);
-        HIPCHK(c, hipMemcpyAsync((void*)L.poly.v, c->hpoly[slot], sizeof(double) * 2 * c->m, hipMemcpyHostToDevice,
-                                 c->stream));
-        HIPCHK(c, hipEventRecord(c->poly_ev[slot], c->stream));
-        c->poly_ev_valid[slot] = true;
+cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vector<double>& p1) {
+    for (int k = 0; k < c->m; k++) {
+        double dx = std::fabs(p1[2 * k] - p0[2 * k]), dy = std::fabs(p1[2 * k + 1] - p0[2 * k + 1]);
+        if (!(dx < c->hx) || !(dy < c->hy))
+            return fail(c, CC_ERR_MOTION, "the body moves a cell or more within one sweep");
     }
-    Box reg = box_union(c->lbox[slot], cells);
-    c->lbox[slot] = cells;
-    if (box_empty(reg)) return CC_OK;
-    TimedPair tp{};
-    tstart(c, 3, tp);
-    int vw = reg.w() + 1, vh = reg.h() + 1;
-    hipLaunchKernelGGL(k_geo_vertices, dim3(nblk((size_t)vw * vh, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, L,
-                       reg.i0, reg.j0, vw, vh);
-    size_t nf = (size_t)vw * (vh - 1) + (size_t)(vw - 1) * vh;
-    hipLaunchKernelGGL(k_geo_faces, dim3(nblk(nf, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, L, reg.i0, reg.j0,
-                       vw, vh);
-    hipLaunchKernelGGL(k_geo_cells, dim3(nblk((size_t)reg.w() * reg.h(), ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream,
-                       c->g, L, reg.i0, reg.j0, reg.w(), reg.h());
-    tstop(c, tp);
-    HIPCHK(c, hipGetLastError());
     return CC_OK;
 }
 
-template <typename R>
-cc_status run_sweep(cc_ctx* c, int dir, double dt, bool first) {
-    const Level& Ls = c->lev[first ? c->s0 : c->sm];
-    const Level& Le = c->lev[first ? c->sm : c->s1];
-    Box ub = box_union(c->lbox[first ? c->s0 : c->sm], c->lbox[first ? c->sm : c->s1]);
-    Box B{0, 0, 0, 0};
-    if (!box_empty(ub)) {
-        B.i0 = std::max(ub.i0 - 3, 0);
-        B.i1 = std::min(ub.i1 + 3, c->g.nx);
-        B.j0 = std::max(ub.j0 - 3, 0);
-        B.j1 = std::min(ub.j1 + 3, c->g.ny);
-        if ((size_t)B.w() > (size_t)c->lay.capw || (size_t)B.h() > (size_t)c->lay.caph)
-            return fail(c, CC_ERR_WORKSPACE, "sweep region exceeds the staging capacity");
-    }
-    c->last_sweep_box = B;
-    size_t nc = c->lay.nc;
-    const R* Uin = at<R>(c, c->lay.off_u[c->cur]);
-    R* Uout = at<R>(c, c->lay.off_u[1 - c->cur]);
-    double h = dir == 0 ? c->hx : c->hy;
-    double lam = dt / h;
-    Stage S;
+// ------------------------------------------------------------------ argument blocks
+// Constant part of an instance's arguments (pointers into its workspace).
+void base_args(cc_ctx* c, StepArgs& a) {
+    std::memset(&a, 0, sizeof(a));
+    a.g = c->g;
+    Stage& S = a.S;
     S.Q = at<double>(c, c->lay.off_sQ);
     S.U1 = at<double>(c, c->lay.off_sU1);
     S.has = at<int8_t>(c, c->lay.off_shas);
@@ -336,73 +384,370 @@ cc_status run_sweep(cc_ctx* c, int dir, double dt, bool first) {
     S.f2 = at<int8_t>(c, c->lay.off_sf2);
     S.nbad = at<unsigned int>(c, c->lay.off_nbad);
     S.cap = (int)std::max<size_t>(c->lay.cap, 1);
-    Common C{at<double>(c, c->lay.off_qb), at<int32_t>(c, c->lay.off_stamp)};
-    unsigned int* status = at<unsigned int>(c, c->lay.off_status);
-    unsigned int* ncol = at<unsigned int>(c, c->lay.off_ncol);
-    size_t nb = (size_t)B.w() * B.h();
-    int32_t step_id = (int32_t)(c->step & 0x7fffffff);
-    TimedPair tb{};
-    if (nb > 0) {
-        tstart(c, 2, tb);
-        size_t nf = dir == 0 ? (size_t)(B.w() + 1) * B.h() : (size_t)B.w() * (B.h() + 1);
-        if (dir == 0)
-            hipLaunchKernelGGL(k_swept<0>, dim3(nblk(nf, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, Ls, Le,
-                               c->mot, B, S);
-        else
-            hipLaunchKernelGGL(k_swept<1>, dim3(nblk(nf, ITEMS_PER_BLOCK)), dim3(TPB), 0, c->stream, c->g, Ls, Le,
-                               c->mot, B, S);
-        hipLaunchKernelGGL(k_stage<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, Uin, B, S, status);
-        if (dir == 0)
-            hipLaunchKernelGGL(k_wall<0>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, c->mot, B, S, C,
-                               (int)first, step_id);
-        else
-            hipLaunchKernelGGL(k_wall<1>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, c->mot, B, S, C,
-                               (int)first, step_id);
-        tstop(c, tb);
+    a.C.qb = at<double>(c, c->lay.off_qb);
+    a.C.stamp = at<int32_t>(c, c->lay.off_stamp);
+    a.status = at<unsigned int>(c, c->lay.off_status);
+    a.ncol = at<unsigned int>(c, c->lay.off_ncol);
+    a.slist = at<int>(c, c->lay.off_slist);
+    a.scnt = at<unsigned int>(c, c->lay.off_scnt);
+    a.cfl_part = at<unsigned long long>(c, c->lay.off_part);
+    a.cfl_out = at<unsigned long long>(c, c->lay.off_cflout);
+    for (int k = 0; k < 2; k++) {
+        GeoJob& J = a.geo[k];
+        J.list = at<int>(c, c->lay.off_glist[k]);
+        J.cnt = at<unsigned int>(c, c->lay.off_gcnt) + 3 * k;
+        J.body = at<double>(c, c->lay.off_body);
     }
-    TimedPair td{};
-    tstart(c, dir, td);
-    if (dir == 0) {
-        dim3 grid((unsigned)((c->g.nx + DX_OUT - 1) / DX_OUT), (unsigned)c->g.ny);
-        hipLaunchKernelGGL((k_dense_x<R, R>), grid, dim3(DX_T), 0, c->stream, c->g, Uin, Uout, B, (R)lam);
-    } else {
-        // rows per thread: enough column segments to give every CU several wavefronts
-        long long cells = (long long)c->g.nx * c->g.ny;
-        int rows = (int)std::max<long long>(4, std::min<long long>(64, cells / (256LL * 256 * 4)));
-        dim3 grid((unsigned)((c->g.nx + 255) / 256), (unsigned)((c->g.ny + rows - 1) / rows));
-        hipLaunchKernelGGL((k_dense_y<R, R>), grid, dim3(256), 0, c->stream, c->g, Uin, Uout, B, (R)lam, rows);
+}
+
+void set_geo(cc_ctx* c, GeoJob& J, int slot, const Box& reg, const Pose& px, const Pose& py) {
+    J.L = c->lev[slot];
+    J.reg = reg;
+    J.cs_x = px.cs;
+    J.sn_x = px.sn;
+    J.cx_x = px.cx;
+    J.cs_y = py.cs;
+    J.sn_y = py.sn;
+    J.cy_y = py.cy;
+    J.active = c->m > 0 && !box_empty(reg);
+}
+
+Box sweep_box(cc_ctx* c, const Box& a, const Box& b) {
+    Box ub = box_union(a, b);
+    Box B{0, 0, 0, 0};
+    if (!box_empty(ub)) {
+        B.i0 = std::max(ub.i0 - 3, 0);
+        B.i1 = std::min(ub.i1 + 3, c->g.nx);
+        B.j0 = std::max(ub.j0 - 3, 0);
+        B.j1 = std::min(ub.j1 + 3, c->g.ny);
     }
-    tstop(c, td);
-    if (nb > 0) {
-        tstart(c, 2, tb);
-        if (dir == 0)
-            hipLaunchKernelGGL((k_patch<0, R>), dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, Uin, B, S, lam,
-                               ncol);
-        else
-            hipLaunchKernelGGL((k_patch<1, R>), dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Ls, Le, Uin, B, S, lam,
-                               ncol);
-        hipLaunchKernelGGL(k_cover<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Le, B, S, Uout);
-        // collapse rounds after covering: the content ping-pongs U1 -> Q -> Uout
-        hipLaunchKernelGGL(k_fix<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Le, B, S, 0,
-                           (const double*)S.U1, (const int8_t*)S.f1, S.Q, S.f2, Uout, ncol, status);
-        hipLaunchKernelGGL(k_fix<R>, dim3(nblk(nb, TPB_BOX)), dim3(TPB_BOX), 0, c->stream, c->g, Le, B, S, 1,
-                           (const double*)S.Q, (const int8_t*)S.f2, (double*)nullptr, (int8_t*)nullptr, Uout, ncol,
-                           status);
-        tstop(c, tb);
+    return B;
+}
+
+void set_sweep(cc_ctx* c, SweepJob& J, int s, double dt) {
+    int first = s == 0;
+    int sl = first ? c->s0 : c->sm, el = first ? c->sm : c->s1;
+    J.Ls = c->lev[sl];
+    J.Le = c->lev[el];
+    J.B = sweep_box(c, c->lbox[sl], c->lbox[el]);
+    J.dir = first ? c->parity : 1 - c->parity;
+    J.first = first;
+    J.lam = dt / (J.dir == 0 ? c->hx : c->hy);
+    int rin = first ? c->cur : 1 - c->cur;
+    J.Uin = c->ws + c->lay.off_u[rin];
+    J.Uout = c->ws + c->lay.off_u[1 - rin];
+}
+
+// Host part of a step: poses, level boxes, regions, sweep boxes and motion; fills the
+// instance's argument block.  The context's level bookkeeping is updated as if the step's
+// geometry had run (the launches follow in stream order).
+cc_status prepare_step(cc_ctx* c, double dt, StepArgs& a) {
+    if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "step already begun");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, CC_ERR_MOTION, "dt must be positive");
+    double t1 = c->t + dt;
+    base_args(c, a);
+    if (c->m > 0) {
+        int m = c->m;
+        Pose q0 = pose_at(c, c->t), q1 = pose_at(c, t1);
+        std::vector<double> p0(2 * m), p1(2 * m), pm(2 * m);
+        pose_xy(c, q0, q0, p0.data());
+        pose_xy(c, q1, q1, p1.data());
+        // stage polygon: the first sweep's coordinate at t^{n+1}, the other at t^n
+        Pose mx = c->parity == 0 ? q1 : q0, my = c->parity == 0 ? q0 : q1;
+        pose_xy(c, mx, my, pm.data());
+        cc_status st = check_motion(c, p0, p1);
+        if (st != CC_OK) return st;
+        Poly Pm = c->lev[c->sm].poly, P1 = c->lev[c->s1].poly;
+        Box cm, c1;
+        poly_info(c, pm.data(), Pm, cm);
+        poly_info(c, p1.data(), P1, c1);
+        Box rm = box_union(c->lbox[c->sm], cm), r1 = box_union(c->lbox[c->s1], c1);
+        if (!geo_fits(c, rm) || !geo_fits(c, r1)) return fail(c, CC_ERR_WORKSPACE, "geometry region exceeds capacity");
+        c->lev[c->sm].poly = Pm;
+        c->lev[c->s1].poly = P1;
+        c->lbox[c->sm] = cm;
+        c->lbox[c->s1] = c1;
+        set_geo(c, a.geo[0], c->sm, rm, mx, my);
+        set_geo(c, a.geo[1], c->s1, r1, q1, q1);
+        // rigid map of the step and the wall velocity at mid-step
+        double th0 = c->theta0 + c->amp * std::sin(c->omega * c->t);
+        double th1 = c->theta0 + c->amp * std::sin(c->omega * t1);
+        Motion& M = c->mot;
+        M.cosd = std::cos(th1 - th0);
+        M.sind = std::sin(th1 - th0);
+        M.c0x = c->ref_x + c->vx * c->t;
+        M.c0y = c->ref_y + c->vy * c->t;
+        M.c1x = c->ref_x + c->vx * t1;
+        M.c1y = c->ref_y + c->vy * t1;
+        double th = c->t + 0.5 * dt;
+        M.vx = c->vx;
+        M.vy = c->vy;
+        M.thd = c->amp * c->omega * std::cos(c->omega * th);
+        M.chx = c->ref_x + c->vx * th;
+        M.chy = c->ref_y + c->vy * th;
     }
-    (void)nc;
-    HIPCHK(c, hipGetLastError());
-    c->cur = 1 - c->cur;
+    a.mot = c->mot;
+    for (int s = 0; s < 2; s++) {
+        set_sweep(c, a.sw[s], s, dt);
+        const Box& B = a.sw[s].B;
+        if (!box_empty(B) && ((size_t)B.w() > (size_t)c->lay.capw || (size_t)B.h() > (size_t)c->lay.caph))
+            return fail(c, CC_ERR_WORKSPACE, "sweep region exceeds the staging capacity");
+    }
+    a.step_id = (int32_t)(c->step & 0x7fffffff);
+    a.cfl_alpha = c->lev[c->s1].alpha;
+    a.cfl_U = c->ws + c->lay.off_u[c->cur];
+    c->step_dt = dt;
+    c->last_sweep_box = a.sw[1].B;
     return CC_OK;
 }
 
-cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vector<double>& p1) {
-    for (int k = 0; k < c->m; k++) {
-        double dx = std::fabs(p1[2 * k] - p0[2 * k]), dy = std::fabs(p1[2 * k + 1] - p0[2 * k + 1]);
-        if (!(dx < c->hx) || !(dy < c->hy))
-            return fail(c, CC_ERR_MOTION, "the body moves a cell or more within one sweep");
+// Geometry-only argument block: the level `slot` posed at time t, in up to two jobs (the
+// slot's previous region and the new one, when their union exceeds the capacity).
+cc_status prepare_geometry(cc_ctx* c, double t, int slot, StepArgs& a) {
+    base_args(c, a);
+    if (c->m == 0) return CC_OK;
+    Pose q = pose_at(c, t);
+    std::vector<double> pv(2 * c->m);
+    pose_xy(c, q, q, pv.data());
+    Box cells;
+    poly_info(c, pv.data(), c->lev[slot].poly, cells);
+    Box reg = box_union(c->lbox[slot], cells);
+    if (geo_fits(c, reg)) {
+        set_geo(c, a.geo[0], slot, reg, q, q);
+    } else {
+        set_geo(c, a.geo[0], slot, c->lbox[slot], q, q);
+        set_geo(c, a.geo[1], slot, cells, q, q);
     }
+    c->lbox[slot] = cells;
     return CC_OK;
+}
+
+// ------------------------------------------------------------------ engine bookkeeping
+int units_of(int kind, int n) { return kind <= L_C2 ? 2 * n : n; }
+
+int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
+    const Layout& L = c->lay;
+    size_t gv = (size_t)(L.gw + 1) * (L.gh + 1);
+    size_t gf = (size_t)(L.gw + 1) * L.gh + (size_t)L.gw * (L.gh + 1);
+    size_t gc = (size_t)L.gw * L.gh;
+    size_t sf = std::max((size_t)(L.capw + 1) * L.caph, (size_t)L.capw * (L.caph + 1));
+    // phase-2 wavefronts: about one per boundary item of a large body
+    int p2 = (int)std::min<size_t>(256, std::max<size_t>(4, (size_t)(L.gw + L.gh)));
+    int m = c->m;
+    if (m == 0 && kind <= L_BOX) return 0;
+    switch (kind) {
+        case L_POSE: return (int)nblk((size_t)m, T_WIDE);
+        case L_V1: return (int)nblk(gv, T_WIDE);
+        case L_F1: return (int)nblk(gf, T_WIDE);
+        case L_C1: return (int)nblk(gc, T_WIDE);
+        case L_V2: case L_F2: case L_C2: case L_S2: return m > SMALL_POLY ? p2 : 0;
+        case L_S1: return (int)nblk(sf, T_WIDE);
+        case L_BOX: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
+        case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
+        case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
+        case L_CFL: return (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(L.nc, T_WIDE));
+        case L_CFLF: return 1;
+    }
+    return 0;
+}
+
+void drop_graphs(Engine& E) {
+    for (int b = 0; b < 2; b++) {
+        if (E.gexec[b]) (void)hipGraphExecDestroy(E.gexec[b]);
+        E.gexec[b] = nullptr;
+        E.gkey[b] = -1;
+    }
+}
+
+// Offsets of every launch kind for the current members; uploads them (stream-ordered,
+// from pageable memory, so the call returns after the copy has been staged).
+hipError_t engine_plan(Engine& E, hipStream_t stream) {
+    int n = (int)E.mem.size();
+    int stride = 2 * E.cap_n + 1;
+    std::vector<int> all((size_t)NKINDS * stride, 0);
+    for (int k = 0; k < NKINDS; k++) {
+        int nu = units_of(k, n);
+        E.h_off[k].assign(nu + 1, 0);
+        for (int u = 0; u < nu; u++) {
+            const cc_ctx* c = E.mem[k <= L_C2 ? u >> 1 : u];
+            E.h_off[k][u + 1] = E.h_off[k][u] + kind_blocks(c, E, k);
+        }
+        std::copy(E.h_off[k].begin(), E.h_off[k].end(), all.begin() + (size_t)k * stride);
+    }
+    drop_graphs(E);
+    hipError_t e = hipMemcpyAsync(E.d_off, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return e;
+}
+
+const int* koff(const Engine& E, int kind) { return E.d_off + (size_t)kind * (2 * E.cap_n + 1); }
+int ktotal(const Engine& E, int kind) { return E.h_off[kind].empty() ? 0 : E.h_off[kind].back(); }
+
+// Waits until host buffer b may be rewritten.
+hipError_t engine_hostbuf(Engine& E, int b) {
+    if (E.ev_used[b]) return hipEventSynchronize(E.ev[b]);
+    return hipSuccess;
+}
+
+template <typename K, typename... Args>
+void klaunch(K kern, int blocks, int threads, hipStream_t s, Args... args) {
+    if (blocks > 0) hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, args...);
+}
+
+void launch_geometry(const Engine& E, hipStream_t s) {
+    int n = (int)E.mem.size(), nu = 2 * n;
+    const StepArgs* A = E.d_args;
+    klaunch(kb_geo_pose, ktotal(E, L_POSE), T_WIDE, s, A, koff(E, L_POSE), nu);
+    klaunch(kb_geo_p1<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), nu);
+    klaunch(kb_geo_p2<0>, ktotal(E, L_V2), T_WIDE, s, A, koff(E, L_V2), nu);
+    klaunch(kb_geo_p1<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), nu);
+    klaunch(kb_geo_p2<1>, ktotal(E, L_F2), T_WIDE, s, A, koff(E, L_F2), nu);
+    klaunch(kb_geo_p1<2>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), nu);
+    klaunch(kb_geo_p2<2>, ktotal(E, L_C2), T_WIDE, s, A, koff(E, L_C2), nu);
+}
+
+// Dense launches of sweep sw: bit 0 of `which` the x-sweep kernel, bit 1 the y-sweep
+// kernel (a member's direction in this sweep picks which one does its work).  ta/tb:
+// events recorded by the launch itself around its execution (one kernel only), or null.
+template <typename R>
+void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t ta, hipEvent_t tb) {
+    int n = (int)E.mem.size();
+    const StepArgs* A = E.d_args;
+    for (int d = 0; d < 2; d++) {
+        if (!((which >> d) & 1)) continue;
+        int kind = d == 0 ? L_DX : L_DY;
+        int blocks = ktotal(E, kind);
+        if (blocks == 0) continue;
+        const int* off = koff(E, kind);
+        auto go = [&](auto kern, int threads) {
+            if (ta) hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, ta, tb, 0, A, off, n, sw);
+            else hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, A, off, n, sw);
+        };
+        if (d == 0) {
+            switch (E.tile_x) {
+                case 0: go(kb_dense_x<R, 1>, DX_T); break;
+                case 1: go(kb_dense_x<R, 2>, DX_T); break;
+                case 2: go(kb_dense_x<R, 4>, DX_T); break;
+                default: go(kb_dense_x<R, 8>, DX_T); break;
+            }
+        } else {
+            switch (E.tile_y) {
+                case 0: go(kb_dense_y<R, 8>, 256); break;
+                case 1: go(kb_dense_y<R, 12>, 256); break;
+                default:
+                    if constexpr (sizeof(R) == 4) {
+                        if (E.tile_y == 2) go(kb_dense_y<R, 16>, 256);
+                        else go(kb_dense_y<R, 24>, 256);
+                    }
+                    break;
+            }
+        }
+    }
+}
+
+// Box phases before the dense sweep.
+template <typename R>
+void launch_box_pre(const Engine& E, hipStream_t s, int sw) {
+    int n = (int)E.mem.size();
+    const StepArgs* A = E.d_args;
+    klaunch(kb_swept1, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
+    klaunch(kb_swept2, ktotal(E, L_S2), T_WIDE, s, A, koff(E, L_S2), n, sw);
+    klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
+}
+// Box phases after the dense sweep (`which` as for the dense launches).
+template <typename R>
+void launch_box_post(const Engine& E, hipStream_t s, int sw, int which) {
+    int n = (int)E.mem.size();
+    const StepArgs* A = E.d_args;
+    int nb = ktotal(E, L_BOX);
+    const int* ob = koff(E, L_BOX);
+    if (which & 1) klaunch(kb_patch<0, R>, nb, T_BOX, s, A, ob, n, sw);
+    if (which & 2) klaunch(kb_patch<1, R>, nb, T_BOX, s, A, ob, n, sw);
+    klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw);
+    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 0);
+    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 1);
+}
+
+template <typename R>
+void launch_cfl(const Engine& E, hipStream_t s) {
+    int n = (int)E.mem.size();
+    const StepArgs* A = E.d_args;
+    klaunch(kb_cfl<R>, ktotal(E, L_CFL), T_WIDE, s, A, koff(E, L_CFL), n);
+    klaunch(kb_cfl_final, n, T_WIDE, s, A, koff(E, L_CFL), n);
+}
+
+hipError_t engine_upload(Engine& E, hipStream_t s, int b) {
+    return hipMemcpyAsync(E.d_args, E.h_args[b], E.mem.size() * sizeof(StepArgs), hipMemcpyHostToDevice, s);
+}
+
+hipError_t engine_alloc_host(Engine& E) {
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2 && e == hipSuccess; b++) {
+        e = hipHostMalloc((void**)&E.h_args[b], sizeof(StepArgs) * E.cap_n, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&E.ev[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, 16 * E.cap_n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_gather, 8 * E.cap_n, hipHostMallocDefault);
+    return e;
+}
+
+void engine_free(Engine& E) {
+    drop_graphs(E);
+    for (int b = 0; b < 2; b++) {
+        if (E.h_args[b]) (void)hipHostFree(E.h_args[b]);
+        if (E.ev[b]) (void)hipEventDestroy(E.ev[b]);
+        E.h_args[b] = nullptr;
+        E.ev[b] = nullptr;
+    }
+    if (E.h_cflout) (void)hipHostFree(E.h_cflout);
+    if (E.h_gather) (void)hipHostFree(E.h_gather);
+    E.h_cflout = nullptr;
+    E.h_gather = nullptr;
+}
+
+// Whole step of every member, argument blocks in host buffer b: upload, both geometry
+// levels, both sweeps and, for batches, the next time step's reduction, status gather and
+// their read-back.  `dirs` (single member): the direction of its first sweep, so that only
+// the matching dense kernel is launched.
+template <typename R>
+void step_sequence(Engine& E, hipStream_t s, int b, int dir0, bool batch) {
+    (void)engine_upload(E, s, b);
+    launch_geometry(E, s);
+    for (int sw = 0; sw < 2; sw++) {
+        int which = dir0 < 0 ? 3 : 1 << (sw == 0 ? dir0 : 1 - dir0);
+        launch_box_pre<R>(E, s, sw);
+        launch_dense<R>(E, s, sw, which, nullptr, nullptr);
+        launch_box_post<R>(E, s, sw, which);
+    }
+    if (batch) {
+        int n = (int)E.mem.size();
+        launch_cfl<R>(E, s);
+        hipLaunchKernelGGL(kb_gather, dim3(nblk(n, 64)), dim3(64), 0, s, (const StepArgs*)E.d_args, n, E.d_gather);
+        (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
+        (void)hipMemcpyAsync(E.h_gather, E.d_gather, 8 * (size_t)n, hipMemcpyDeviceToHost, s);
+    }
+}
+
+// Launches the captured step graph of host buffer b (capturing it first if needed).
+template <typename R>
+hipError_t engine_graph_step(Engine& E, hipStream_t s, int b, int dir0, bool batch) {
+    int key = dir0 + 1;
+    if (!E.gexec[b] || E.gkey[b] != key) {
+        if (E.gexec[b]) (void)hipGraphExecDestroy(E.gexec[b]);
+        E.gexec[b] = nullptr;
+        hipGraph_t gr;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        step_sequence<R>(E, s, b, dir0, batch);
+        e = hipStreamEndCapture(s, &gr);
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(&E.gexec[b], gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return e;
+        E.gkey[b] = key;
+    }
+    return hipGraphLaunch(E.gexec[b], s);
 }
 
 }  // namespace
@@ -460,29 +805,40 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     c->s0 = 0;
     c->sm = 1;
     c->s1 = 2;
+    c->timing = 0;
+    c->batch = nullptr;
+    c->in_step = c->have_state = false;
+    c->t = 0.0;
+    c->step = 0;
+    c->parity = 0;
+    c->last_sweep_box = Box{0, 0, 0, 0};
+    std::memset(&c->mot, 0, sizeof(c->mot));
     for (int s = 0; s < 3; s++) {
         Level& L = c->lev[s];
         L.vcls = at<int8_t>(c, lay.off_vcls[s]);
         L.fx = at<double2>(c, lay.off_fx[s]);
         L.fy = at<double2>(c, lay.off_fy[s]);
         L.alpha = at<double>(c, lay.off_alpha[s]);
-        L.poly = Poly{at<double>(c, lay.off_poly[s]), 0, 0, 0, 0, 0, 0, 0, -1.0, 0.0};
+        L.poly = Poly{};
+        L.poly.v = at<double>(c, lay.off_poly[s]);
+        L.poly.m = 0;
+        L.poly.rin2 = -1.0;
         c->lbox[s] = Box{0, 0, 0, 0};
-        c->hpoly[s] = nullptr;
-        c->poly_ev_valid[s] = false;
-        if (c->m > 0) {
-            hipError_t e1 = hipHostMalloc((void**)&c->hpoly[s], sizeof(double) * 2 * c->m, hipHostMallocDefault);
-            if (e1 != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e1));
-            hipError_t e2 = hipEventCreateWithFlags(&c->poly_ev[s], hipEventDisableTiming);
-            if (e2 != hipSuccess) {
-                (void)hipHostFree(c->hpoly[s]);
-                c->hpoly[s] = nullptr;
-                return create_fail(c, CC_ERR_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e2));
-            }
-        }
     }
-    // all-fluid levels, clean reductions, stamps that match no step
-    hipError_t e = hipSuccess;
+    // own launch plan (one member)
+    Engine& E = c->eng;
+    E.prec = cfg->precision;
+    E.cap_n = 1;
+    E.mem = {c};
+    E.d_args = at<StepArgs>(c, lay.off_args);
+    E.d_off = at<int>(c, lay.off_offs);
+    E.d_cflout = at<unsigned long long>(c, lay.off_cflout);
+    E.d_gather = at<unsigned int>(c, lay.off_gather);
+    E.tile_x = 0;  // one row per x-sweep block
+    E.tile_y = 1;  // 12-row y-sweep tiles
+    hipError_t e = engine_alloc_host(E);
+    if (e != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("host buffers: ") + hipGetErrorString(e));
+    // all-fluid levels, clean reductions and lists, stamps that match no step, body vertices
     for (int s = 0; s < 3 && e == hipSuccess; s++) {
         if (e == hipSuccess) e = hipMemsetAsync(c->lev[s].vcls, 0, lay.nvx, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->lev[s].fx, 0, lay.nfx * 16, c->stream);
@@ -494,25 +850,27 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         }
     }
     if (e == hipSuccess && c->m > 0) e = hipMemsetAsync(at<int32_t>(c, lay.off_stamp), 0xff, lay.nc * 4, c->stream);
+    if (e == hipSuccess && c->m > 0)
+        e = hipMemcpyAsync(at<double>(c, lay.off_body), c->bverts.data(), 16 * (size_t)c->m, hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_gcnt, 0, 24, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_scnt, 0, 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_nbad, 0, 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_smax, 0, 16, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_status, 0, 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_ncol, 0, 4, c->stream);
+    if (e == hipSuccess) e = engine_plan(E, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
     *out = c;
     return CC_OK;
 }
 
-
 cc_status cc_destroy(cc_ctx* c) {
     if (!c) return CC_ERR_ARG;
+    if (c->batch) cc_batch_remove(c->batch, c);
     (void)hipStreamSynchronize(c->stream);
-    for (int s = 0; s < 3; s++) {
-        if (c->hpoly[s]) {
-            (void)hipHostFree(c->hpoly[s]);
-            (void)hipEventDestroy(c->poly_ev[s]);
-        }
-    }
+    engine_free(c->eng);
     for (auto& p : c->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -527,13 +885,51 @@ cc_status cc_destroy(cc_ctx* c) {
 
 const char* cc_last_error(const cc_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
+}  // extern "C"
+
+namespace {
+
+// Uploads argument block `a` through the context's next host buffer.
+cc_status own_upload(cc_ctx* c, const StepArgs& a) {
+    Engine& E = c->eng;
+    int b = E.buf;
+    HIPCHK(c, engine_hostbuf(E, b));
+    E.h_args[b][0] = a;
+    HIPCHK(c, engine_upload(E, c->stream, b));
+    HIPCHK(c, hipEventRecord(E.ev[b], c->stream));
+    E.ev_used[b] = true;
+    E.buf = 1 - b;
+    return CC_OK;
+}
+
+cc_status geometry_at(cc_ctx* c, double t, int slot) {
+    StepArgs a;
+    cc_status st = prepare_geometry(c, t, slot, a);
+    if (st != CC_OK) return st;
+    if (c->m == 0) return CC_OK;
+    if ((st = own_upload(c, a)) != CC_OK) return st;
+    TimedPair tp{};
+    tstart(c, 3, tp);
+    launch_geometry(c->eng, c->stream);
+    tstop(c, tp);
+    HIPCHK(c, hipGetLastError());
+    return CC_OK;
+}
+
+cc_status not_in_batch(cc_ctx* c) {
+    if (c->batch) return fail(c, CC_ERR_ARG, "the context is stepped by a batch");
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 cc_status cc_geometry(cc_ctx* c, double t, int32_t level) {
     if (!c || level < 0 || level > 2) return fail(c, CC_ERR_ARG, "bad level");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_geometry inside a step");
     int slot = level == 0 ? c->s0 : level == 1 ? c->sm : c->s1;
-    std::vector<double> pv(2 * std::max(c->m, 1));
-    pose(c, t, pv.data());
-    return compute_level(c, slot, pv.data());
+    return geometry_at(c, t, slot);
 }
 
 cc_status cc_geometry_dump(cc_ctx* c, int32_t level, int8_t* d_vcls, double* d_alpha, double* d_bx, double* d_by) {
@@ -559,7 +955,7 @@ cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
     c->step = 0;
     c->parity = 0;
     c->cur = 0;
-    cc_status st = cc_geometry(c, t0, 0);
+    cc_status st = geometry_at(c, t0, c->s0);
     if (st != CC_OK) return st;
     const double* al = c->lev[c->s0].alpha;
     if (fp32(c))
@@ -582,7 +978,7 @@ cc_status cc_set_clock(cc_ctx* c, double t, int64_t step) {
     c->t = t;
     c->step = step;
     c->parity = (int)(step & 1);
-    cc_status st = cc_geometry(c, t, 0);
+    cc_status st = geometry_at(c, t, c->s0);
     if (st != CC_OK) return st;
     if (c->m > 0) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
     return CC_OK;
@@ -626,50 +1022,59 @@ cc_status cc_get_state(cc_ctx* c, double* d_out, int32_t what) {
 
 cc_status cc_begin_step(cc_ctx* c, double dt) {
     if (!c) return CC_ERR_ARG;
-    if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
-    if (c->in_step) return fail(c, CC_ERR_ARG, "step already begun");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, CC_ERR_MOTION, "dt must be positive");
-    double t1 = c->t + dt;
-    int m = std::max(c->m, 1);
-    std::vector<double> p0(2 * m), p1(2 * m), pm(2 * m);
-    pose(c, c->t, p0.data());
-    pose(c, t1, p1.data());
-    for (int k = 0; k < c->m; k++) {
-        if (c->parity == 0) {
-            pm[2 * k] = p1[2 * k];
-            pm[2 * k + 1] = p0[2 * k + 1];
-        } else {
-            pm[2 * k] = p0[2 * k];
-            pm[2 * k + 1] = p1[2 * k + 1];
-        }
-    }
-    cc_status st = check_motion(c, p0, p1);
+    cc_status st = not_in_batch(c);
     if (st != CC_OK) return st;
-    st = compute_level(c, c->sm, pm.data());
-    if (st != CC_OK) return st;
-    st = compute_level(c, c->s1, p1.data());
-    if (st != CC_OK) return st;
-    // rigid map of the step and the wall velocity at mid-step
-    double th0 = c->theta0 + c->amp * std::sin(c->omega * c->t);
-    double th1 = c->theta0 + c->amp * std::sin(c->omega * t1);
-    Motion& M = c->mot;
-    M.cosd = std::cos(th1 - th0);
-    M.sind = std::sin(th1 - th0);
-    M.c0x = c->ref_x + c->vx * c->t;
-    M.c0y = c->ref_y + c->vy * c->t;
-    M.c1x = c->ref_x + c->vx * t1;
-    M.c1y = c->ref_y + c->vy * t1;
-    double th = c->t + 0.5 * dt;
-    M.vx = c->vx;
-    M.vy = c->vy;
-    M.thd = c->amp * c->omega * std::cos(c->omega * th);
-    M.chx = c->ref_x + c->vx * th;
-    M.chy = c->ref_y + c->vy * th;
+    StepArgs a;
+    if ((st = prepare_step(c, dt, a)) != CC_OK) return st;
+    if ((st = own_upload(c, a)) != CC_OK) return st;
+    TimedPair tp{};
+    tstart(c, 3, tp);
+    launch_geometry(c->eng, c->stream);
+    tstop(c, tp);
+    HIPCHK(c, hipGetLastError());
     c->in_step = true;
     c->sweeps_done = 0;
-    c->step_dt = dt;
     return CC_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+template <typename R>
+cc_status own_sweep(cc_ctx* c, int s) {
+    Engine& E = c->eng;
+    int dir = s == 0 ? c->parity : 1 - c->parity;
+    TimedPair tb{};
+    tstart(c, 2, tb);
+    launch_box_pre<R>(E, c->stream, s);
+    tstop(c, tb);
+    hipEvent_t ta = nullptr, tz = nullptr;
+    if (c->timing & 1) {
+        if (c->pool.empty()) {
+            TimedPair p;
+            (void)hipEventCreate(&p.a);
+            (void)hipEventCreate(&p.b);
+            c->pool.push_back(p);
+        }
+        TimedPair tp = c->pool.back();
+        c->pool.pop_back();
+        tp.kind = dir;
+        ta = tp.a;
+        tz = tp.b;
+        c->pending.push_back(tp);
+    }
+    launch_dense<R>(E, c->stream, s, 1 << dir, ta, tz);
+    tstart(c, 2, tb);
+    launch_box_post<R>(E, c->stream, s, 1 << dir);
+    tstop(c, tb);
+    HIPCHK(c, hipGetLastError());
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 cc_status cc_sweep(cc_ctx* c, int32_t dir, double dt) {
     if (!c) return CC_ERR_ARG;
@@ -677,10 +1082,11 @@ cc_status cc_sweep(cc_ctx* c, int32_t dir, double dt) {
     int want = c->sweeps_done == 0 ? c->parity : 1 - c->parity;
     if (dir != want) return fail(c, CC_ERR_ARG, "sweep direction out of order");
     if (dt != c->step_dt) return fail(c, CC_ERR_ARG, "dt differs from cc_begin_step");
-    bool first = c->sweeps_done == 0;
-    cc_status st = fp32(c) ? run_sweep<float>(c, dir, dt, first) : run_sweep<double>(c, dir, dt, first);
+    int s = c->sweeps_done;
+    cc_status st = fp32(c) ? own_sweep<float>(c, s) : own_sweep<double>(c, s);
     if (st != CC_OK) return st;
     c->sweeps_done++;
+    c->cur = 1 - c->cur;  // the sweep's output is the current state (both sweeps: unchanged)
     return CC_OK;
 }
 
@@ -695,43 +1101,65 @@ cc_status cc_end_step(cc_ctx* c) {
     return CC_OK;
 }
 
-cc_status cc_step(cc_ctx* c, double dt) {
-    cc_status st = cc_begin_step(c, dt);
+}  // extern "C"
+
+namespace {
+
+// Whole step through the context's own captured graph.
+template <typename R>
+cc_status own_graph_step(cc_ctx* c, double dt) {
+    Engine& E = c->eng;
+    int b = E.buf;
+    HIPCHK(c, engine_hostbuf(E, b));
+    cc_status st = prepare_step(c, dt, E.h_args[b][0]);
     if (st != CC_OK) return st;
-    int d1 = c->parity, d2 = 1 - c->parity;
-    if ((st = cc_sweep(c, d1, dt)) != CC_OK) return st;
-    if ((st = cc_sweep(c, d2, dt)) != CC_OK) return st;
+    int dir0 = E.h_args[b][0].sw[0].dir;
+    HIPCHK(c, engine_graph_step<R>(E, c->stream, b, dir0, false));
+    HIPCHK(c, hipEventRecord(E.ev[b], c->stream));
+    E.ev_used[b] = true;
+    E.buf = 1 - b;
+    c->in_step = true;
+    c->sweeps_done = 2;
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_step(cc_ctx* c, double dt) {
+    if (!c) return CC_ERR_ARG;
+    cc_status st = not_in_batch(c);
+    if (st != CC_OK) return st;
+    if (c->timing) {  // timing needs the individual launches
+        if ((st = cc_begin_step(c, dt)) != CC_OK) return st;
+        int d1 = c->parity, d2 = 1 - c->parity;
+        if ((st = cc_sweep(c, d1, dt)) != CC_OK) return st;
+        if ((st = cc_sweep(c, d2, dt)) != CC_OK) return st;
+        return cc_end_step(c);
+    }
+    if (!c->stream) {  // the null stream cannot be captured: individual launches
+        if ((st = cc_begin_step(c, dt)) != CC_OK) return st;
+        int d1 = c->parity, d2 = 1 - c->parity;
+        if ((st = cc_sweep(c, d1, dt)) != CC_OK) return st;
+        if ((st = cc_sweep(c, d2, dt)) != CC_OK) return st;
+        return cc_end_step(c);
+    }
+    st = fp32(c) ? own_graph_step<float>(c, dt) : own_graph_step<double>(c, dt);
+    if (st != CC_OK) return st;
     return cc_end_step(c);
 }
 
-cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
-    if (!c || !h_dt || !(cfl > 0.0)) return fail(c, CC_ERR_ARG, "bad argument");
-    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_cfl_dt inside a step");
-    unsigned long long* smax = at<unsigned long long>(c, c->lay.off_smax);
-    unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
-    const double* al = c->lev[c->s0].alpha;
-    if (fp32(c))
-        hipLaunchKernelGGL(k_cfl<float>, dim3(CFL_BLOCKS), dim3(256), 0, c->stream, c->g, al,
-                           at<float>(c, c->lay.off_u[c->cur]), part);
-    else
-        hipLaunchKernelGGL(k_cfl<double>, dim3(CFL_BLOCKS), dim3(256), 0, c->stream, c->g, al,
-                           at<double>(c, c->lay.off_u[c->cur]), part);
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, c->stream, CFL_BLOCKS, (const unsigned long long*)part, smax);
-    HIPCHK(c, hipGetLastError());
-    unsigned long long hs[2];
-    unsigned int status = 0;
-    HIPCHK(c, hipMemcpyAsync(hs, smax, 16, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&status, c->ws + c->lay.off_status, 4, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    double sx, sy;
-    std::memcpy(&sx, &hs[0], 8);
-    std::memcpy(&sy, &hs[1], 8);
-    if (status & 1u) return fail(c, CC_ERR_STATE, "a cell became fluid without donor neighbours");
-    if (status & 2u) return fail(c, CC_ERR_STATE, "a cut cell stayed inadmissible after two collapse rounds");
-    if (!std::isfinite(sx) || !std::isfinite(sy)) return fail(c, CC_ERR_STATE, "non-finite or non-physical state");
+}  // extern "C"
+
+namespace {
+
+// Wave speeds (bit patterns from the reduction) plus the body's vertex speeds -> dt.
+double dt_from_speeds(cc_ctx* c, double cfl, double sx, double sy) {
     if (c->m > 0) {
         std::vector<double> pv(2 * c->m);
-        pose(c, c->t, pv.data());
+        Pose q = pose_at(c, c->t);
+        pose_xy(c, q, q, pv.data());
         double thd = c->amp * c->omega * std::cos(c->omega * c->t);
         double cx = c->ref_x + c->vx * c->t, cy = c->ref_y + c->vy * c->t;
         for (int k = 0; k < c->m; k++) {
@@ -741,7 +1169,47 @@ cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
             sy = std::fmax(sy, std::fabs(uy));
         }
     }
-    *h_dt = cfl * std::fmin(c->hx / sx, c->hy / sy);
+    return cfl * std::fmin(c->hx / sx, c->hy / sy);
+}
+
+cc_status status_error(cc_ctx* c, unsigned int status, double sx, double sy) {
+    if (status & 1u) return fail(c, CC_ERR_STATE, "a cell became fluid without donor neighbours");
+    if (status & 2u) return fail(c, CC_ERR_STATE, "a cut cell stayed inadmissible after two collapse rounds");
+    if (!std::isfinite(sx) || !std::isfinite(sy)) return fail(c, CC_ERR_STATE, "non-finite or non-physical state");
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
+    if (!c || !h_dt || !(cfl > 0.0)) return fail(c, CC_ERR_ARG, "bad argument");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_cfl_dt inside a step");
+    unsigned long long* smax = at<unsigned long long>(c, c->lay.off_smax);
+    unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
+    const double* al = c->lev[c->s0].alpha;
+    int blocks = (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(c->lay.nc));
+    if (fp32(c))
+        hipLaunchKernelGGL(k_cfl<float>, dim3(blocks), dim3(256), 0, c->stream, c->g, al,
+                           at<float>(c, c->lay.off_u[c->cur]), part);
+    else
+        hipLaunchKernelGGL(k_cfl<double>, dim3(blocks), dim3(256), 0, c->stream, c->g, al,
+                           at<double>(c, c->lay.off_u[c->cur]), part);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, c->stream, blocks, (const unsigned long long*)part, smax);
+    HIPCHK(c, hipGetLastError());
+    // one read-back: the two maxima and the status word are adjacent
+    unsigned long long hs[3];
+    HIPCHK(c, hipMemcpyAsync(hs, smax, 16, hipMemcpyDeviceToHost, c->stream));
+    unsigned int status = 0;
+    HIPCHK(c, hipMemcpyAsync(&status, c->ws + c->lay.off_status, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sx, sy;
+    std::memcpy(&sx, &hs[0], 8);
+    std::memcpy(&sy, &hs[1], 8);
+    cc_status st = status_error(c, status, sx, sy);
+    if (st != CC_OK) return st;
+    *h_dt = dt_from_speeds(c, cfl, sx, sy);
     return CC_OK;
 }
 
@@ -773,15 +1241,107 @@ cc_status cc_info(cc_ctx* c, double* h_out, int32_t n) {
     HIPCHK(c, hipMemcpyAsync(&dev[0], c->ws + c->lay.off_status, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&dev[1], c->ws + c->lay.off_ncol, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double v[8] = {c->t, (double)c->step, (double)c->parity, (double)dev[0], (double)dev[1],
-                   (double)c->last_sweep_box.w() * c->last_sweep_box.h(), (double)c->lay.cap, 0.0};
-    for (int k = 0; k < n && k < 8; k++) h_out[k] = v[k];
+    double v[9] = {c->t, (double)c->step, (double)c->parity, (double)dev[0], (double)dev[1],
+                   (double)c->last_sweep_box.w() * c->last_sweep_box.h(), (double)c->lay.cap,
+                   (double)X_RB[c->eng.tile_x], (double)Y_TR[c->eng.tile_y]};
+    for (int k = 0; k < n && k < 9; k++) h_out[k] = v[k];
+    return CC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Times every valid tile variant of both dense sweeps on this grid (reps launches each,
+// from the current state into the spare state buffer, which the next sweep overwrites)
+// and keeps the fastest.
+template <typename R>
+cc_status tune_dense(cc_ctx* c, int reps) {
+    Engine& E = c->eng;
+    StepArgs a;
+    base_args(c, a);
+    for (int s = 0; s < 2; s++) {
+        SweepJob& J = a.sw[s];
+        J.B = Box{0, 0, 0, 0};
+        J.dir = s;
+        J.lam = 0.25 * std::min(c->hx, c->hy) / std::max(c->hx, c->hy);
+        J.Uin = c->ws + c->lay.off_u[c->cur];
+        J.Uout = c->ws + c->lay.off_u[1 - c->cur];
+    }
+    cc_status st = own_upload(c, a);
+    if (st != CC_OK) return st;
+    hipEvent_t ea, eb;
+    HIPCHK(c, hipEventCreate(&ea));
+    HIPCHK(c, hipEventCreate(&eb));
+    int keep[2] = {E.tile_x, E.tile_y};
+    for (int dir = 0; dir < 2 && st == CC_OK; dir++) {
+        int nv = dir == 0 ? NX_VARIANTS : NY_VARIANTS, best = -1;
+        float best_ms = 0.0f;
+        for (int v = 0; v < nv; v++) {
+            if (!dense_variant_ok(E.prec, dir, v)) continue;
+            (dir == 0 ? E.tile_x : E.tile_y) = v;
+            if (engine_plan(E, c->stream) != hipSuccess) {
+                st = fail(c, CC_ERR_DEVICE, "tile plan");
+                break;
+            }
+            launch_dense<R>(E, c->stream, dir, 1 << dir, nullptr, nullptr);  // warm-up
+            float ms = 0.0f;
+            if (hipEventRecord(ea, c->stream) != hipSuccess) {
+                st = fail(c, CC_ERR_DEVICE, "event record");
+                break;
+            }
+            for (int r = 0; r < reps; r++) launch_dense<R>(E, c->stream, dir, 1 << dir, nullptr, nullptr);
+            if (hipEventRecord(eb, c->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+                hipEventElapsedTime(&ms, ea, eb) != hipSuccess || hipGetLastError() != hipSuccess) {
+                st = fail(c, CC_ERR_DEVICE, "tile timing failed");
+                break;
+            }
+            if (best < 0 || ms < best_ms) {
+                best = v;
+                best_ms = ms;
+            }
+        }
+        keep[dir] = best >= 0 ? best : keep[dir];
+        (dir == 0 ? E.tile_x : E.tile_y) = keep[dir];
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (engine_plan(E, c->stream) != hipSuccess) return fail(c, CC_ERR_DEVICE, "tile plan");
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_autotune(cc_ctx* c, int32_t reps, int32_t* h_choice) {
+    if (!c || reps < 1) return fail(c, CC_ERR_ARG, "bad argument");
+    if (c->in_step || !c->have_state) return fail(c, CC_ERR_ARG, "cc_autotune needs a state and no open step");
+    cc_status st = not_in_batch(c);
+    if (st != CC_OK) return st;
+    st = fp32(c) ? tune_dense<float>(c, reps) : tune_dense<double>(c, reps);
+    if (st != CC_OK) return st;
+    if (h_choice) {
+        h_choice[0] = c->eng.tile_x;
+        h_choice[1] = c->eng.tile_y;
+    }
+    return CC_OK;
+}
+
+cc_status cc_set_tiles(cc_ctx* c, int32_t tile_x, int32_t tile_y) {
+    if (!c) return CC_ERR_ARG;
+    if (!dense_variant_ok(c->eng.prec, 0, tile_x) || !dense_variant_ok(c->eng.prec, 1, tile_y))
+        return fail(c, CC_ERR_ARG, "tile variant out of range for this precision");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_set_tiles inside a step");
+    c->eng.tile_x = tile_x;
+    c->eng.tile_y = tile_y;
+    HIPCHK(c, engine_plan(c->eng, c->stream));
     return CC_OK;
 }
 
 cc_status cc_timing(cc_ctx* c, int32_t enable) {
     if (!c) return CC_ERR_ARG;
-    c->timing = enable != 0;
+    c->timing = enable & 3;
     return CC_OK;
 }
 
@@ -803,5 +1363,158 @@ cc_status cc_timing_read(cc_ctx* c, double* h_out, int32_t n) {
     }
     return CC_OK;
 }
+
+// ------------------------------------------------------------------------------ batches
+
+size_t cc_batch_workspace_bytes(int32_t max_instances) {
+    if (max_instances < 1) return 0;
+    size_t n = (size_t)max_instances;
+    return up(n * sizeof(StepArgs)) + up((size_t)NKINDS * (2 * n + 1) * sizeof(int)) + up(16 * n) + up(8 * n);
+}
+
+cc_status cc_batch_create(int32_t max_instances, int32_t precision, void* d_ws, size_t ws_bytes, void* hip_stream,
+                          cc_batch** out) {
+    if (!out || max_instances < 1 || (precision != CC_FP64 && precision != CC_FP32_GEOM64)) return CC_ERR_ARG;
+    *out = nullptr;
+    size_t need = cc_batch_workspace_bytes(max_instances);
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws % ALIGN) != 0) return CC_ERR_WORKSPACE;
+    cc_batch* b = new cc_batch();
+    b->stream = (hipStream_t)hip_stream;
+    b->ws = (char*)d_ws;
+    Engine& E = b->eng;
+    E.prec = precision;
+    E.cap_n = max_instances;
+    size_t n = (size_t)max_instances, o = 0;
+    E.d_args = (StepArgs*)(b->ws + o);
+    o += up(n * sizeof(StepArgs));
+    E.d_off = (int*)(b->ws + o);
+    o += up((size_t)NKINDS * (2 * n + 1) * sizeof(int));
+    E.d_cflout = (unsigned long long*)(b->ws + o);
+    o += up(16 * n);
+    E.d_gather = (unsigned int*)(b->ws + o);
+    E.tile_x = 0;
+    E.tile_y = 1;
+    if (engine_alloc_host(E) != hipSuccess) {
+        engine_free(E);
+        delete b;
+        return CC_ERR_DEVICE;
+    }
+    *out = b;
+    return CC_OK;
+}
+
+cc_status cc_batch_destroy(cc_batch* b) {
+    if (!b) return CC_ERR_ARG;
+    (void)hipStreamSynchronize(b->stream);
+    for (cc_ctx* c : b->eng.mem) c->batch = nullptr;
+    engine_free(b->eng);
+    delete b;
+    return CC_OK;
+}
+
+cc_status cc_batch_add(cc_batch* b, cc_ctx* c) {
+    if (!b || !c) return CC_ERR_ARG;
+    Engine& E = b->eng;
+    if (c->batch) return bfail(b, CC_ERR_ARG, "context already in a batch");
+    if (c->cfg.precision != E.prec) return bfail(b, CC_ERR_ARG, "precision differs from the batch's");
+    if ((int)E.mem.size() >= E.cap_n) return bfail(b, CC_ERR_WORKSPACE, "batch is full");
+    if (!c->have_state || c->in_step) return bfail(b, CC_ERR_ARG, "context needs a state and no open step");
+    BHIPCHK(b, hipStreamSynchronize(c->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    E.mem.push_back(c);
+    c->batch = b;
+    BHIPCHK(b, engine_plan(E, b->stream));
+    return CC_OK;
+}
+
+cc_status cc_batch_remove(cc_batch* b, cc_ctx* c) {
+    if (!b || !c) return CC_ERR_ARG;
+    Engine& E = b->eng;
+    auto it = std::find(E.mem.begin(), E.mem.end(), c);
+    if (it == E.mem.end()) return bfail(b, CC_ERR_ARG, "context not in this batch");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    E.mem.erase(it);
+    c->batch = nullptr;
+    BHIPCHK(b, engine_plan(E, b->stream));
+    return CC_OK;
+}
+
+cc_status cc_batch_set_tiles(cc_batch* b, int32_t tile_x, int32_t tile_y) {
+    if (!b) return CC_ERR_ARG;
+    if (!dense_variant_ok(b->eng.prec, 0, tile_x) || !dense_variant_ok(b->eng.prec, 1, tile_y))
+        return bfail(b, CC_ERR_ARG, "tile variant out of range for this precision");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->eng.tile_x = tile_x;
+    b->eng.tile_y = tile_y;
+    BHIPCHK(b, engine_plan(b->eng, b->stream));
+    return CC_OK;
+}
+
+int32_t cc_batch_size(const cc_batch* b) { return b ? (int32_t)b->eng.mem.size() : 0; }
+
+cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
+    if (!b || !h_dt) return CC_ERR_ARG;
+    Engine& E = b->eng;
+    int n = (int)E.mem.size();
+    if (n == 0) return CC_OK;
+    int buf = E.buf;
+    BHIPCHK(b, engine_hostbuf(E, buf));
+    for (int k = 0; k < n; k++) {
+        cc_ctx* c = E.mem[k];
+        cc_status st = prepare_step(c, h_dt[k], E.h_args[buf][k]);
+        if (st != CC_OK) {
+            b->err = "member " + std::to_string(k) + ": " + c->err;
+            return st;
+        }
+        // the members' results land in the batch's gather arrays
+        E.h_args[buf][k].cfl_out = E.d_cflout + 2 * k;
+    }
+    hipError_t e = E.prec == CC_FP32_GEOM64 ? engine_graph_step<float>(E, b->stream, buf, -1, true)
+                                            : engine_graph_step<double>(E, b->stream, buf, -1, true);
+    if (e != hipSuccess) return bfail(b, CC_ERR_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
+    BHIPCHK(b, hipEventRecord(E.ev[buf], b->stream));
+    E.ev_used[buf] = true;
+    E.buf = 1 - buf;
+    BHIPCHK(b, hipEventSynchronize(E.ev[buf]));
+    for (int k = 0; k < n; k++) {
+        cc_ctx* c = E.mem[k];
+        c->in_step = true;
+        c->sweeps_done = 2;
+        cc_end_step(c);
+        if (h_status) h_status[k] = (int32_t)E.h_gather[2 * k];
+    }
+    return CC_OK;
+}
+
+cc_status cc_batch_cfl_dt(cc_batch* b, double cfl, double* h_dt) {
+    if (!b || !h_dt || !(cfl > 0.0)) return CC_ERR_ARG;
+    Engine& E = b->eng;
+    for (size_t k = 0; k < E.mem.size(); k++) {
+        cc_status st = cc_cfl_dt(E.mem[k], cfl, &h_dt[k]);
+        if (st != CC_OK) {
+            b->err = "member " + std::to_string(k) + ": " + E.mem[k]->err;
+            return st;
+        }
+    }
+    return CC_OK;
+}
+
+cc_status cc_batch_last_dt(cc_batch* b, double cfl, double* h_dt, int32_t* h_status) {
+    if (!b || !h_dt || !(cfl > 0.0)) return CC_ERR_ARG;
+    Engine& E = b->eng;
+    for (size_t k = 0; k < E.mem.size(); k++) {
+        cc_ctx* c = E.mem[k];
+        double sx, sy;
+        std::memcpy(&sx, &E.h_cflout[2 * k], 8);
+        std::memcpy(&sy, &E.h_cflout[2 * k + 1], 8);
+        unsigned int st = E.h_gather[2 * k];
+        if (h_status) h_status[k] = (int32_t)st;
+        cc_status r = status_error(c, st, sx, sy);
+        h_dt[k] = r == CC_OK ? dt_from_speeds(c, cfl, sx, sy) : 0.0;
+    }
+    return CC_OK;
+}
+
+const char* cc_batch_last_error(const cc_batch* b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

@@ -67,64 +67,83 @@ __device__ __forceinline__ double orient(double ax, double ay, double bx, double
 }
 
 // ------------------------------------------------------------------------------ gas model
+// Division and square root.  FP64 (the reference arithmetic, also used for every cut-cell
+// quantity in both precision modes) uses correctly rounded IEEE operations in the written
+// order.  The FP32 state mode uses the hardware reciprocal and square root (about 1 ulp):
+// an IEEE FP32 division expands to ~10 instructions and these sweeps are bound by vector
+// ALU issue, not by memory.
+template <typename T>
+__device__ __forceinline__ T qdiv(T a, T b) {
+    return a / b;
+}
+template <>
+__device__ __forceinline__ float qdiv<float>(float a, float b) {
+    return a * __builtin_amdgcn_rcpf(b);
+}
+template <typename T>
+__device__ __forceinline__ T qsqrt(T a) {
+    return sqrt(a);
+}
+template <>
+__device__ __forceinline__ float qsqrt<float>(float a) {
+    return __builtin_amdgcn_sqrtf(a);
+}
+
 template <typename T>
 __device__ __forceinline__ T pressure(const T q[4], T g) {
-    return (g - T(1)) * (q[3] - T(0.5) * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+    return (g - T(1)) * (q[3] - qdiv(T(0.5) * (q[1] * q[1] + q[2] * q[2]), q[0]));
 }
 
 template <typename T, int D>
 __device__ __forceinline__ void euler_flux(const T q[4], T g, T f[4]) {
     constexpr int n = 1 + D, t = 2 - D;
     T p = pressure(q, g);
-    T un = q[n] / q[0];
+    T un = qdiv(q[n], q[0]);
     f[0] = q[n];
     f[n] = q[n] * un + p;
     f[t] = q[t] * un;
     f[3] = un * (q[3] + p);
 }
 
+// HLLC flux with Davis wave-speed estimates.  The two star-region cases share one code
+// path on the upwind side's values (same operations as writing them out per side).
 template <typename T, int D>
 __device__ __forceinline__ void hllc(const T ql[4], const T qr[4], T g, T f[4]) {
     constexpr int n = 1 + D, t = 2 - D;
     T rl = ql[0], rr = qr[0];
-    T ul = ql[n] / rl, ur = qr[n] / rr;
+    T ul = qdiv(ql[n], rl), ur = qdiv(qr[n], rr);
     T pl = pressure(ql, g), pr = pressure(qr, g);
-    T al = sqrt(g * pl / rl), ar = sqrt(g * pr / rr);
+    T al = qsqrt(qdiv(g * pl, rl)), ar = qsqrt(qdiv(g * pr, rr));
     T sl = fmin(ul - al, ur - ar);
     T sr = fmax(ul + al, ur + ar);
-    T ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) / (rl * (sl - ul) - rr * (sr - ur));
-    if (T(0) <= sl) {
-        euler_flux<T, D>(ql, g, f);
-    } else if (T(0) <= ss) {
-        T fl[4];
-        euler_flux<T, D>(ql, g, fl);
-        T c = rl * (sl - ul) / (sl - ss);
-        T us[4];
-        us[0] = c;
-        us[n] = c * ss;
-        us[t] = c * (ql[t] / rl);
-        us[3] = c * (ql[3] / rl + (ss - ul) * (ss + pl / (rl * (sl - ul))));
+    T ss = qdiv(pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur), rl * (sl - ul) - rr * (sr - ur));
+    // 0: F_L (0 <= S_L); 1: star L (0 <= S*); 2: star R (0 <= S_R); 3: F_R
+    int kc = T(0) <= sl ? 0 : (T(0) <= ss ? 1 : (T(0) <= sr ? 2 : 3));
+    bool left = kc <= 1;
+    T q[4];  // upwind state, selected by value (a selected pointer would force both arrays to memory)
 #pragma unroll
-        for (int k = 0; k < 4; k++) f[k] = fl[k] + sl * (us[k] - ql[k]);
-    } else if (T(0) <= sr) {
-        T fr[4];
-        euler_flux<T, D>(qr, g, fr);
-        T c = rr * (sr - ur) / (sr - ss);
-        T us[4];
-        us[0] = c;
-        us[n] = c * ss;
-        us[t] = c * (qr[t] / rr);
-        us[3] = c * (qr[3] / rr + (ss - ur) * (ss + pr / (rr * (sr - ur))));
-#pragma unroll
-        for (int k = 0; k < 4; k++) f[k] = fr[k] + sr * (us[k] - qr[k]);
-    } else {
-        euler_flux<T, D>(qr, g, f);
+    for (int k = 0; k < 4; k++) q[k] = left ? ql[k] : qr[k];
+    if (kc == 0 || kc == 3) {
+        euler_flux<T, D>(q, g, f);  // supersonic: the upwind state's flux
+        return;
     }
+    // star region on the upwind side K: F_K + S_K (U*_K - U_K)
+    T rk = left ? rl : rr, uk = left ? ul : ur, pk = left ? pl : pr, sk = left ? sl : sr;
+    T fk[4];
+    euler_flux<T, D>(q, g, fk);
+    T c = qdiv(rk * (sk - uk), sk - ss);
+    T us[4];
+    us[0] = c;
+    us[n] = c * ss;
+    us[t] = c * qdiv(q[t], rk);
+    us[3] = c * (qdiv(q[3], rk) + (ss - uk) * (ss + qdiv(pk, rk * (sk - uk))));
+#pragma unroll
+    for (int k = 0; k < 4; k++) f[k] = fk[k] + sk * (us[k] - q[k]);
 }
 
 template <typename T>
 __device__ __forceinline__ T vanleer(T a, T b) {
-    return a * b > T(0) ? T(2) * a * b / (a + b) : T(0);
+    return a * b > T(0) ? qdiv(T(2) * a * b, a + b) : T(0);
 }
 
 template <typename T>

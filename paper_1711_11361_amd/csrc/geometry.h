@@ -1,19 +1,23 @@
-// Cut-cell geometry kernels for one level (Sec. 2.1 volume fractions, Sec. 2.2 face
-// apertures, Sec. 2.3.4 time-averaged apertures).  The body is a convex polygon.
+// Cut-cell geometry of one level (Sec. 2.1 volume fractions, Sec. 2.2 face apertures) and
+// the polygon clipping used by the exact time-averaged apertures (Sec. 2.3.4).  The body is
+// a convex polygon.
 //
-// Work is restricted to the polygon's bounding box (plus the region the level slot
-// occupied before, which is reset to fluid): vertices outside the box are fluid, faces
-// outside it are open, cells outside it are regular.
+// Every quantity is computed in two phases.  Phase 1 gives one thread per item (vertex,
+// face, cell) and settles it when a cheap exact test suffices: outside the polygon's
+// bounding box, inside the inscribed or outside the circumscribed certificate disc, both
+// face end points solid, all four cell faces open or closed, or a polygon of a few edges
+// (then the thread runs the full test itself).  The remaining items, those near the
+// boundary of a many-sided polygon, are appended to a work list, and phase 2 gives each one
+// a 64-lane wavefront that splits the polygon's edges across its lanes.  Both paths
+// evaluate the same formulas; only the order of the area sum differs, and it is fixed per
+// polygon size.
 #pragma once
 #include "cc_device.h"
 
 namespace cc {
 
-// ------------------------------------------------------------ wave-parallel variants
-// One 64-lane wavefront handles one face / cell / vertex; the polygon's edges are split
-// across the lanes and combined with exact (order-independent) max/min/any reductions, or
-// a fixed xor tree for sums, so the O(m) loops run 64x shorter.
 constexpr int WAVE = 64;
+constexpr int SMALL_POLY = 16;  // polygons with at most this many edges are done per thread
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -31,12 +35,77 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Closed-polygon membership: solid iff on or left of every edge (boundary is solid);
-// outside the bounding box fluid.  The certificate discs (inscribed / circumscribed about
-// (cx, cy), shrunk and grown by a relative 1e-6) decide points whose orientation signs
-// cannot be affected by rounding, so the result is that of testing every edge; the
-// any-negative vote over the lanes is order-independent.
-__device__ __forceinline__ int wave_classify(const Poly& P, double px, double py, int lane) {
+// Reductions over the lanes that share an item: a whole wavefront (S = WAVE) or the
+// thread alone (S = 1).
+template <int S>
+__device__ __forceinline__ double red_max(double v) {
+    if constexpr (S == 1) return v; else return wave_max(v);
+}
+template <int S>
+__device__ __forceinline__ double red_min(double v) {
+    if constexpr (S == 1) return v; else return wave_min(v);
+}
+template <int S>
+__device__ __forceinline__ double red_sum(double v) {
+    if constexpr (S == 1) return v; else return wave_sum(v);
+}
+template <int S>
+__device__ __forceinline__ bool red_any(bool v) {
+    if constexpr (S == 1) return v; else return __any(v);
+}
+
+// Appends `value` for every lane with `want` to a work list with one atomic per
+// wavefront (ballot, then each lane's rank among the requesting lanes).  Must be reached by
+// all lanes of the wavefront together.
+__device__ __forceinline__ void list_append(int* list, unsigned int* cnt, bool want, int value) {
+    unsigned long long mask = __ballot(want);
+    if (mask == 0ull) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    int leader = __ffsll((long long)mask) - 1;
+    unsigned int base = 0u;
+    if (lane == leader) base = atomicAdd(cnt, (unsigned int)__popcll(mask));
+    base = __shfl(base, leader, WAVE);
+    if (want) list[base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull))] = value;
+}
+
+// ------------------------------------------------------------------ certificate discs
+// The posed polygon lies inside the disc of squared radius rout2 about (cx, cy) and
+// contains the disc of squared radius rin2 (both widened by a relative 1e-6, so that
+// rounding cannot turn a test around); rin2 < 0: no discs.
+__device__ __forceinline__ bool seg_outside_disc(const Poly& P, double ax, double ay, double bx, double by) {
+    if (P.rin2 < 0.0) return false;
+    double dx = bx - ax, dy = by - ay;
+    double l2 = dx * dx + dy * dy;
+    double t = l2 > 0.0 ? ((P.cx - ax) * dx + (P.cy - ay) * dy) / l2 : 0.0;
+    t = fmin(fmax(t, 0.0), 1.0);
+    double ex = ax + t * dx - P.cx, ey = ay + t * dy - P.cy;
+    return ex * ex + ey * ey > P.rout2;
+}
+__device__ __forceinline__ bool rect_outside_disc(const Poly& P, double x0, double y0, double w, double h) {
+    if (P.rin2 < 0.0) return false;
+    double ex = fmin(fmax(P.cx, x0), x0 + w) - P.cx, ey = fmin(fmax(P.cy, y0), y0 + h) - P.cy;
+    return ex * ex + ey * ey > P.rout2;
+}
+
+// ------------------------------------------------------------------ per-item tests
+// Closed-polygon membership: solid iff on or left of every edge (boundary is solid).  The
+// any-negative vote over the edges is order-independent.
+template <int S>
+__device__ __forceinline__ int poly_classify(const Poly& P, double px, double py, int lane) {
+    const double* v = P.v;
+    int neg = 0;
+    for (int k = lane; k < P.m; k += S) {
+        int k1 = k + 1 == P.m ? 0 : k + 1;
+        if (orient(v[2 * k], v[2 * k + 1], v[2 * k1], v[2 * k1 + 1], px, py) < 0.0) {
+            neg = 1;
+            break;
+        }
+    }
+    return red_any<S>(neg) ? FLUID : SOLID;
+}
+
+// Decided without the edge loop, or -1.
+__device__ __forceinline__ int classify_quick(const Poly& P, double px, double py) {
     if (P.m == 0) return FLUID;
     if (px < P.xmin || px > P.xmax || py < P.ymin || py > P.ymax) return FLUID;
     if (P.rin2 >= 0.0) {
@@ -45,27 +114,18 @@ __device__ __forceinline__ int wave_classify(const Poly& P, double px, double py
         if (d2 < P.rin2) return SOLID;
         if (d2 > P.rout2) return FLUID;
     }
-    const double* v = P.v;
-    int neg = 0;
-    for (int k = lane; k < P.m; k += WAVE) {
-        int k1 = k + 1 == P.m ? 0 : k + 1;
-        if (orient(v[2 * k], v[2 * k + 1], v[2 * k1], v[2 * k1 + 1], px, py) < 0.0) {
-            neg = 1;
-            break;
-        }
-    }
-    return __any(neg) ? FLUID : SOLID;
+    return -1;
 }
 
 // Solid parameter interval of the segment A->B (Cyrus-Beck against the half-planes):
-// empty if some edge has both end points outside, else [max entering t, min leaving t];
-// the max/min over the lanes are exact.
-__device__ __forceinline__ double2 wave_seg_clip(const Poly& P, double ax, double ay, double bx, double by,
+// empty if some edge has both end points outside, else [max entering t, min leaving t].
+template <int S>
+__device__ __forceinline__ double2 poly_seg_clip(const Poly& P, double ax, double ay, double bx, double by,
                                                   int lane) {
     double tl = 0.0, th = 1.0;
     int rej = 0;
     const double* v = P.v;
-    for (int k = lane; k < P.m; k += WAVE) {
+    for (int k = lane; k < P.m; k += S) {
         int k1 = k + 1 == P.m ? 0 : k + 1;
         double ex = v[2 * k], ey = v[2 * k + 1], fx = v[2 * k1], fy = v[2 * k1 + 1];
         double g0 = orient(ex, ey, fx, fy, ax, ay), g1 = orient(ex, ey, fx, fy, bx, by);
@@ -81,20 +141,30 @@ __device__ __forceinline__ double2 wave_seg_clip(const Poly& P, double ax, doubl
             if (t < th) th = t;
         }
     }
-    if (__any(rej)) return make_double2(0.0, 0.0);
-    tl = wave_max(tl);
-    th = wave_min(th);
+    if (red_any<S>(rej)) return make_double2(0.0, 0.0);
+    tl = red_max<S>(tl);
+    th = red_min<S>(th);
     if (!(tl < th)) return make_double2(0.0, 0.0);
     return make_double2(tl, th);
 }
 
-__device__ __forceinline__ double2 wave_face_interval(const Poly& P, double ax, double ay, int ca, double bx,
-                                                      double by, int cb, int lane) {
-    if (P.m == 0) return make_double2(0.0, 0.0);
-    if (ca == SOLID && cb == SOLID) return make_double2(0.0, 1.0);
-    if (fmax(ax, bx) < P.xmin || fmin(ax, bx) > P.xmax || fmax(ay, by) < P.ymin || fmin(ay, by) > P.ymax)
-        return make_double2(0.0, 0.0);
-    return wave_seg_clip(P, ax, ay, bx, by, lane);
+// Solid interval of a face decided without the edge loop: 1 = set, 0 = needs the loop.
+__device__ __forceinline__ int face_quick(const Poly& P, double ax, double ay, int ca, double bx, double by,
+                                          int cb, double2& iv) {
+    if (P.m == 0) {
+        iv = make_double2(0.0, 0.0);
+        return 1;
+    }
+    if (ca == SOLID && cb == SOLID) {  // convex body: the whole segment is solid
+        iv = make_double2(0.0, 1.0);
+        return 1;
+    }
+    if (fmax(ax, bx) < P.xmin || fmin(ax, bx) > P.xmax || fmax(ay, by) < P.ymin || fmin(ay, by) > P.ymax ||
+        seg_outside_disc(P, ax, ay, bx, by)) {
+        iv = make_double2(0.0, 0.0);
+        return 1;
+    }
+    return 0;
 }
 
 // Solid length of the right side {w} x [0, h] of a rectangle (coordinates relative to its
@@ -103,11 +173,12 @@ __device__ __forceinline__ double2 wave_face_interval(const Poly& P, double ax, 
 // are computed exactly as the edge clipping computes them (t = (w - ax)/dx,
 // y = ay + t dy), so the area's edge sum and this side term use the same points and their
 // rounding cancels, also where the line is nearly tangent to the body.
-__device__ double wave_right_solid(const Poly& P, double ox, double oy, double w, double h, int lane) {
+template <int S>
+__device__ double poly_right_solid(const Poly& P, double ox, double oy, double w, double h, int lane) {
     double yb = -INFINITY, yt = INFINITY;
     int found = 0;
     const double* v = P.v;
-    for (int k = lane; k < P.m; k += WAVE) {
+    for (int k = lane; k < P.m; k += S) {
         int k1 = k + 1 == P.m ? 0 : k + 1;
         double ax = v[2 * k] - ox, ay = v[2 * k + 1] - oy;
         double bx = v[2 * k1] - ox, by = v[2 * k1 + 1] - oy;
@@ -119,9 +190,9 @@ __device__ double wave_right_solid(const Poly& P, double ox, double oy, double w
         if (dx > 0.0) yb = fmax(yb, y);
         else yt = fmin(yt, y);
     }
-    if (!__any(found)) return 0.0;
-    yb = wave_max(yb);
-    yt = wave_min(yt);
+    if (!red_any<S>(found)) return 0.0;
+    yb = red_max<S>(yb);
+    yt = red_min<S>(yt);
     double lo = fmax(0.0, yb), hi = fmin(h, yt);
     return hi > lo ? hi - lo : 0.0;
 }
@@ -130,13 +201,14 @@ __device__ double wave_right_solid(const Poly& P, double ox, double oy, double w
 // the integral of x dy over the part of the polygon boundary inside the rectangle (each
 // edge clipped with Liang-Barsky in coordinates relative to (ox, oy); the coordinate of a
 // clipped end point that lies on a rectangle side is set exactly) plus w times the solid
-// length of the rectangle's right side (the bottom, top and left sides contribute nothing).
-// The edge sum is split across the lanes and added with a fixed xor tree.
-__device__ double wave_clip_area(const Poly& P, double ox, double oy, double w, double h, double right_solid,
-                                 int lane) {
+// length of the rectangle's right side (the bottom, top and left sides contribute nothing;
+// an edge lying on the right side is left to that term).
+template <int S>
+__device__ double poly_clip_area(const Poly& P, double ox, double oy, double w, double h, int lane) {
+    double right_solid = poly_right_solid<S>(P, ox, oy, w, h, lane);
     double acc = 0.0;
     const double* v = P.v;
-    for (int k = lane; k < P.m; k += WAVE) {
+    for (int k = lane; k < P.m; k += S) {
         int k1 = k + 1 == P.m ? 0 : k + 1;
         double ax = v[2 * k] - ox, ay = v[2 * k + 1] - oy;
         double bx = v[2 * k1] - ox, by = v[2 * k1 + 1] - oy;
@@ -150,8 +222,6 @@ __device__ double wave_clip_area(const Poly& P, double ox, double oy, double w, 
         for (int s = 0; s < 4; s++) {
             double p = pq[s][0], q = pq[s][1];
             if (p == 0.0) {
-                // parallel to this side: outside, or lying on the right side, whose solid
-                // part the right-side term already counts
                 if (q < 0.0 || (s == 1 && q == 0.0)) rej = true;
             } else {
                 double t = q / p;
@@ -180,57 +250,127 @@ __device__ double wave_clip_area(const Poly& P, double ox, double oy, double w, 
         }
         acc += 0.5 * (x0 + x1) * (y1 - y0);
     }
-    return wave_sum(acc) + w * right_solid;
+    return red_sum<S>(acc) + w * right_solid;
 }
 
-// ---------------------------------------------------------------------------- kernels
-// Launch shape of the wave-per-item kernels: 256 threads = 4 items per block.
-constexpr int ITEMS_PER_BLOCK = 4;
+// ------------------------------------------------------------------ one level
+// Geometry job of one level: the destination slot and the cell region recomputed (its
+// vertices and faces are those of the region's closure).  The vertices are posed on the
+// device: x from one rigid pose, y from another (the stage polygon of a split step mixes
+// the poses at the step's start and end), with the host's formula and operation order.
+struct GeoJob {
+    Level L;
+    Box reg;
+    int* list;      // work list of the items left to phase 2
+    unsigned* cnt;  // [0] vertices, [1] faces, [2] cells left to phase 2
+    const double* body;             // body-frame vertices (2 m)
+    double cs_x, sn_x, cx_x;        // pose giving the x coordinates: cs bx - sn by + cx
+    double cs_y, sn_y, cy_y;        // pose giving the y coordinates: sn bx + cs by + cy
+    int active;
+};
 
-__device__ __forceinline__ int wave_item() { return blockIdx.x * ITEMS_PER_BLOCK + (threadIdx.x >> 6); }
-__device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
-
-// Vertex classes over vertices [vi0, vi0+vw) x [vj0, vj0+vh).
-__global__ __launch_bounds__(256) void k_geo_vertices(Grid g, Level L, int vi0, int vj0, int vw, int vh) {
-    int t = wave_item(), lane = wave_lane();
-    if (t >= vw * vh) return;
-    int i = vi0 + t % vw, j = vj0 + t / vw;
-    int c = wave_classify(L.poly, vx_of(g, i), vy_of(g, j), lane);
-    if (lane == 0) L.vcls[(size_t)j * (g.nx + 1) + i] = (int8_t)c;
+__device__ __forceinline__ void geo_pose(const GeoJob& J, int t) {
+    if (t >= J.L.poly.m) return;
+    double bx = J.body[2 * t], by = J.body[2 * t + 1];
+    double* v = const_cast<double*>(J.L.poly.v);
+    v[2 * t] = (J.cs_x * bx - J.sn_x * by) + J.cx_x;
+    v[2 * t + 1] = (J.sn_y * bx + J.cs_y * by) + J.cy_y;
 }
 
-// Face solid intervals.  x-faces: i in [vi0, vi0+vw), j in [vj0, vj0+vh-1);
-// y-faces: i in [vi0, vi0+vw-1), j in [vj0, vj0+vh).
-__global__ __launch_bounds__(256) void k_geo_faces(Grid g, Level L, int vi0, int vj0, int vw, int vh) {
-    int t = wave_item(), lane = wave_lane();
-    int nfx = vw * (vh - 1), nfy = (vw - 1) * vh;
-    if (t >= nfx + nfy) return;
-    const int8_t* vc = L.vcls;
+__device__ __forceinline__ int geo_nverts(const Box& r) { return (r.w() + 1) * (r.h() + 1); }
+__device__ __forceinline__ int geo_nfaces(const Box& r) { return (r.w() + 1) * r.h() + r.w() * (r.h() + 1); }
+
+// Phase 1 of the vertex classes: thread t of the job; true = left to phase 2.
+__device__ __forceinline__ bool geo_vertices1(const Grid& g, const GeoJob& J, int t) {
+    int vw = J.reg.w() + 1;
+    if (t >= geo_nverts(J.reg)) return false;
+    int i = J.reg.i0 + t % vw, j = J.reg.j0 + t / vw;
+    double px = vx_of(g, i), py = vy_of(g, j);
+    int c = classify_quick(J.L.poly, px, py);
+    if (c < 0 && J.L.poly.m <= SMALL_POLY) c = poly_classify<1>(J.L.poly, px, py, 0);
+    if (c < 0) return true;
+    J.L.vcls[(size_t)j * (g.nx + 1) + i] = (int8_t)c;
+    return false;
+}
+__device__ __forceinline__ void geo_vertices2(const Grid& g, const GeoJob& J, const Poly& P, int item, int lane) {
+    int t = J.list[item];
+    int vw = J.reg.w() + 1;
+    int i = J.reg.i0 + t % vw, j = J.reg.j0 + t / vw;
+    int c = poly_classify<WAVE>(P, vx_of(g, i), vy_of(g, j), lane);
+    if (lane == 0) J.L.vcls[(size_t)j * (g.nx + 1) + i] = (int8_t)c;
+}
+
+// Face t of the region closure: x-faces first, then y-faces.
+__device__ __forceinline__ void geo_face_ends(const Grid& g, const GeoJob& J, int t, bool& xf, int& i, int& j,
+                                              double& ax, double& ay, int& ca, double& bx, double& by, int& cb) {
+    int vw = J.reg.w() + 1, vh = J.reg.h() + 1;
+    int nfx = vw * (vh - 1);
+    const int8_t* vc = J.L.vcls;
     int W1 = g.nx + 1;
-    if (t < nfx) {
-        int i = vi0 + t % vw, j = vj0 + t / vw;
-        double x = vx_of(g, i);
-        double2 iv = wave_face_interval(L.poly, x, vy_of(g, j), vc[(size_t)j * W1 + i], x, vy_of(g, j + 1),
-                                        vc[(size_t)(j + 1) * W1 + i], lane);
-        if (lane == 0) L.fx[(size_t)j * W1 + i] = iv;
+    xf = t < nfx;
+    if (xf) {
+        i = J.reg.i0 + t % vw;
+        j = J.reg.j0 + t / vw;
+        ax = bx = vx_of(g, i);
+        ay = vy_of(g, j);
+        by = vy_of(g, j + 1);
+        ca = vc[(size_t)j * W1 + i];
+        cb = vc[(size_t)(j + 1) * W1 + i];
     } else {
         t -= nfx;
-        int i = vi0 + t % (vw - 1), j = vj0 + t / (vw - 1);
-        double y = vy_of(g, j);
-        double2 iv = wave_face_interval(L.poly, vx_of(g, i), y, vc[(size_t)j * W1 + i], vx_of(g, i + 1), y,
-                                        vc[(size_t)j * W1 + i + 1], lane);
-        if (lane == 0) L.fy[(size_t)j * g.nx + i] = iv;
+        i = J.reg.i0 + t % (vw - 1);
+        j = J.reg.j0 + t / (vw - 1);
+        ax = vx_of(g, i);
+        bx = vx_of(g, i + 1);
+        ay = by = vy_of(g, j);
+        ca = vc[(size_t)j * W1 + i];
+        cb = vc[(size_t)j * W1 + i + 1];
     }
 }
+__device__ __forceinline__ void geo_store_face(const Grid& g, const GeoJob& J, bool xf, int i, int j, double2 iv) {
+    if (xf) J.L.fx[(size_t)j * (g.nx + 1) + i] = iv;
+    else J.L.fy[(size_t)j * g.nx + i] = iv;
+}
+__device__ __forceinline__ bool geo_faces1(const Grid& g, const GeoJob& J, int t) {
+    if (t >= geo_nfaces(J.reg)) return false;
+    bool xf;
+    int i, j, ca, cb;
+    double ax, ay, bx, by;
+    geo_face_ends(g, J, t, xf, i, j, ax, ay, ca, bx, by, cb);
+    double2 iv;
+    if (!face_quick(J.L.poly, ax, ay, ca, bx, by, cb, iv)) {
+        if (J.L.poly.m > SMALL_POLY) return true;
+        iv = poly_seg_clip<1>(J.L.poly, ax, ay, bx, by, 0);
+    }
+    geo_store_face(g, J, xf, i, j, iv);
+    return false;
+}
+__device__ __forceinline__ void geo_faces2(const Grid& g, const GeoJob& J, const Poly& P, int item, int lane) {
+    int t = J.list[item];
+    bool xf;
+    int i, j, ca, cb;
+    double ax, ay, bx, by;
+    geo_face_ends(g, J, t, xf, i, j, ax, ay, ca, bx, by, cb);
+    double2 iv = poly_seg_clip<WAVE>(P, ax, ay, bx, by, lane);
+    if (lane == 0) geo_store_face(g, J, xf, i, j, iv);
+}
 
-// Volume fractions over cells [ci0, ci0+cw) x [cj0, cj0+ch): open when all four faces are
-// open, closed when all four are closed, otherwise 1 - (polygon area in the cell)/(hx hy).
-__global__ __launch_bounds__(256) void k_geo_cells(Grid g, Level L, int ci0, int cj0, int cw, int ch) {
-    int t = wave_item(), lane = wave_lane();
-    if (t >= cw * ch) return;
-    int i = ci0 + t % cw, j = cj0 + t / cw;
-    double2 ivE = L.fx[(size_t)j * (g.nx + 1) + i + 1];
-    double b[4] = {beta_x(g, L, i, j), interval_beta(ivE), beta_y(g, L, i, j), beta_y(g, L, i, j + 1)};
+// Volume fractions: open when all four faces are open, closed when all four are closed,
+// otherwise 1 - (polygon area in the cell)/(hx hy); cut cells below the small-cell
+// threshold count as solid.
+__device__ __forceinline__ double alpha_of_area(const Grid& g, double s) {
+    double a = 1.0 - s / (g.hx * g.hy);
+    if (a < 0.0) a = 0.0;
+    if (a > 1.0) a = 1.0;
+    if (a < g.alpha_min) a = 0.0;
+    return a;
+}
+__device__ __forceinline__ bool geo_cells1(const Grid& g, const GeoJob& J, int t) {
+    int cw = J.reg.w();
+    if (t >= cw * J.reg.h()) return false;
+    int i = J.reg.i0 + t % cw, j = J.reg.j0 + t / cw;
+    const Level& L = J.L;
+    double b[4] = {beta_x(g, L, i, j), beta_x(g, L, i + 1, j), beta_y(g, L, i, j), beta_y(g, L, i, j + 1)};
     int ones = 0, zeros = 0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
@@ -242,16 +382,20 @@ __global__ __launch_bounds__(256) void k_geo_cells(Grid g, Level L, int ci0, int
         a = 1.0;
     } else if (zeros == 4) {
         a = 0.0;
+    } else if (L.poly.m > SMALL_POLY) {
+        return true;
     } else {
-        double ox = vx_of(g, i), oy = vy_of(g, j);
-        double rs = wave_right_solid(L.poly, ox, oy, g.hx, g.hy, lane);
-        double s = wave_clip_area(L.poly, ox, oy, g.hx, g.hy, rs, lane);
-        a = 1.0 - s / (g.hx * g.hy);
-        if (a < 0.0) a = 0.0;
-        if (a > 1.0) a = 1.0;
-        if (a < g.alpha_min) a = 0.0;  // small-cell threshold: counts as solid
+        a = alpha_of_area(g, poly_clip_area<1>(L.poly, vx_of(g, i), vy_of(g, j), g.hx, g.hy, 0));
     }
-    if (lane == 0) L.alpha[(size_t)j * g.nx + i] = a;
+    L.alpha[(size_t)j * g.nx + i] = a;
+    return false;
+}
+__device__ __forceinline__ void geo_cells2(const Grid& g, const GeoJob& J, const Poly& P, int item, int lane) {
+    int t = J.list[item];
+    int cw = J.reg.w();
+    int i = J.reg.i0 + t % cw, j = J.reg.j0 + t / cw;
+    double a = alpha_of_area(g, poly_clip_area<WAVE>(P, vx_of(g, i), vy_of(g, j), g.hx, g.hy, lane));
+    if (lane == 0) J.L.alpha[(size_t)j * g.nx + i] = a;
 }
 
 }  // namespace cc

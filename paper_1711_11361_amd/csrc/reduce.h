@@ -78,13 +78,17 @@ __device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
 
 constexpr int CFL_BLOCKS = 512;
 
+// Time-step reduction: block lb of nb grid-strides over the cells and writes its maxima of
+// |u|+a along x and y over the live cells (alpha > 0 with content) to part[2 lb .. 2 lb + 1]
+// as bit patterns (non-negative doubles order like their bit patterns; NaN is mapped above
+// infinity, so a non-finite state surfaces in the maximum).
 template <typename R>
-__global__ __launch_bounds__(256) void k_cfl(Grid g, const double* __restrict__ alpha, const R* __restrict__ U,
-                                             unsigned long long* __restrict__ part) {
+__device__ void cfl_block(const Grid& g, const double* __restrict__ alpha, const R* __restrict__ U,
+                          unsigned long long* __restrict__ part, int lb, int nb) {
     __shared__ unsigned long long sx_[4], sy_[4];
     size_t nc = (size_t)g.nx * g.ny;
     unsigned long long mx = 0ull, my = 0ull;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nc; k += (size_t)gridDim.x * blockDim.x) {
+    for (size_t k = (size_t)lb * blockDim.x + threadIdx.x; k < nc; k += (size_t)nb * blockDim.x) {
         double a = alpha[k];
         double r = (double)U[k];
         if (!(a > 0.0) || !(r > 0.0)) continue;
@@ -109,18 +113,18 @@ __global__ __launch_bounds__(256) void k_cfl(Grid g, const double* __restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 1; q < 4; q++) {
+        for (int q = 1; q < (int)(blockDim.x >> 6); q++) {
             mx = sx_[q] > mx ? sx_[q] : mx;
             my = sy_[q] > my ? sy_[q] : my;
         }
-        part[2 * blockIdx.x] = mx;
-        part[2 * blockIdx.x + 1] = my;
+        part[2 * lb] = mx;
+        part[2 * lb + 1] = my;
     }
 }
 
-// Final maximum over the per-block partials (one block).
-__global__ __launch_bounds__(256) void k_cfl_final(int nparts, const unsigned long long* __restrict__ part,
-                                                   unsigned long long* __restrict__ smax) {
+// Maximum over nparts block partials (one block of 256 threads).
+__device__ void cfl_combine(int nparts, const unsigned long long* __restrict__ part,
+                            unsigned long long* __restrict__ out) {
     __shared__ unsigned long long sx_[4], sy_[4];
     unsigned long long mx = 0ull, my = 0ull;
     for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
@@ -137,13 +141,24 @@ __global__ __launch_bounds__(256) void k_cfl_final(int nparts, const unsigned lo
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 1; q < 4; q++) {
+        for (int q = 1; q < (int)(blockDim.x >> 6); q++) {
             mx = sx_[q] > mx ? sx_[q] : mx;
             my = sy_[q] > my ? sy_[q] : my;
         }
-        smax[0] = mx;
-        smax[1] = my;
+        out[0] = mx;
+        out[1] = my;
     }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cfl(Grid g, const double* __restrict__ alpha, const R* __restrict__ U,
+                                             unsigned long long* __restrict__ part) {
+    cfl_block<R>(g, alpha, U, part, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_cfl_final(int nparts, const unsigned long long* __restrict__ part,
+                                                   unsigned long long* __restrict__ smax) {
+    cfl_combine(nparts, part, smax);
 }
 
 // Deterministic sums: each block reduces a fixed contiguous chunk with a fixed tree; a

@@ -4,17 +4,19 @@
 // covering of cells that become solid.
 //
 // Split of the work:
-//   * dense kernels update every cell outside the sweep box (the bodies' region grown by
-//     three cells): there all stencil cells are regular, so the plain MUSCL-Hancock/HLLC
+//   * the dense kernels update every cell outside the sweep box (the bodies' region grown
+//     by three cells): there all stencil cells are regular, so the plain MUSCL-Hancock/HLLC
 //     update applies; they stream the state once (read U_in, write U_out);
-//   * the box kernels (stage, swept apertures, wall, patch, cover) handle every cell of the
-//     sweep box with the general cut-cell formulas, through box-local staging arrays.
+//   * the box phases (swept apertures, stage and wall, patch, cover, collapse rounds)
+//     handle every cell of the sweep box with the general cut-cell formulas, through
+//     box-local staging arrays.
+// The phases are written as per-thread bodies; the launch wrappers map blocks of one
+// launch onto the instances of a batch.
 #pragma once
 #include "cc_device.h"
 #include "geometry.h"
 
 namespace cc {
-
 // Rigid map of the step restricted to one sweep direction and the body motion data.
 struct Motion {
     double cosd, sind, c0x, c0y, c1x, c1y;  // M(X) = R (X - c0) + c1
@@ -59,55 +61,107 @@ __device__ __forceinline__ double step_disp(const Motion& M, int d, double x, do
     return ((M.sind * dx + M.cosd * dy) + M.c1y) - y;
 }
 
+// One sweep of one instance.
+struct SweepJob {
+    Level Ls, Le;   // start and end levels
+    Box B;          // sweep box (empty: no cut cells)
+    const void* Uin;
+    void* Uout;
+    double lam;     // dt / h in the sweep direction
+    int dir, first; // direction; 1 for the step's first sweep
+};
+
 // --------------------------------------------------------------- time-averaged apertures
 // Exact average over the sweep of the aperture of a face normal to the sweep direction
 // (Eq. timeAveragedBeta): the solid length integrated over the sweep is the area of the
 // start polygon inside the strip swept across the face.
+struct Strip {
+    double x0, y0, sw, sh, w, hf;
+};
+
+// Settles face (i, j) without the polygon loop when possible (returns 1 with r set), else
+// returns 0 with the strip to clip.
 template <int D>
-__global__ __launch_bounds__(256) void k_swept(Grid g, Level Ls, Level Le, Motion M, Box B, Stage S) {
-    int t = wave_item(), lane = wave_lane();
-    int fw = D == 0 ? B.w() + 1 : B.w(), fh = D == 0 ? B.h() : B.h() + 1;
-    if (t >= fw * fh) return;
-    int i = B.i0 + t % fw, j = B.j0 + t / fw;
+__device__ __forceinline__ int swept_quick(const Grid& g, const SweepJob& J, const Motion& M, int i, int j,
+                                           double& r, Strip& st) {
+    const Level& Ls = J.Ls;
     double bs = D == 0 ? beta_x(g, Ls, i, j) : beta_y(g, Ls, i, j);
-    double be = D == 0 ? beta_x(g, Le, i, j) : beta_y(g, Le, i, j);
-    double r;
+    double be = D == 0 ? beta_x(g, J.Le, i, j) : beta_y(g, J.Le, i, j);
     if (bs == 0.0 && be == 0.0) {
         r = 0.0;
-    } else if (Ls.poly.m == 0) {
-        r = 0.5 * (bs + be);
-    } else {
-        const Poly& P = Ls.poly;
-        double X = vx_of(g, i), Y = vy_of(g, j);
-        double h = D == 0 ? g.hx : g.hy, hf = D == 0 ? g.hy : g.hx;
-        double Dd = D == 0 ? step_disp(M, 0, X, Y + 0.5 * g.hy) : step_disp(M, 1, X + 0.5 * g.hx, Y);
-        if (!(fabs(Dd) > 1e-12 * h)) {
-            r = 0.5 * (bs + be);
-        } else {
-            double w = fabs(Dd);
-            double x0, y0, sw, sh;
-            if (D == 0) {
-                x0 = Dd > 0.0 ? X - Dd : X;
-                y0 = Y;
-                sw = w;
-                sh = hf;
-            } else {
-                x0 = X;
-                y0 = Dd > 0.0 ? Y - Dd : Y;
-                sw = hf;
-                sh = w;
-            }
-            if (x0 + sw < P.xmin || x0 > P.xmax || y0 + sh < P.ymin || y0 > P.ymax) {
-                r = 1.0;
-            } else {
-                double rs = wave_right_solid(P, x0, y0, sw, sh, lane);
-                double a = wave_clip_area(P, x0, y0, sw, sh, rs, lane);
-                r = 1.0 - a / (w * hf);
-                if (r < 0.0) r = 0.0;
-                if (r > 1.0) r = 1.0;
-            }
-        }
+        return 1;
     }
+    const Poly& P = Ls.poly;
+    if (P.m == 0) {
+        r = 0.5 * (bs + be);
+        return 1;
+    }
+    double X = vx_of(g, i), Y = vy_of(g, j);
+    double h = D == 0 ? g.hx : g.hy, hf = D == 0 ? g.hy : g.hx;
+    double Dd = D == 0 ? step_disp(M, 0, X, Y + 0.5 * g.hy) : step_disp(M, 1, X + 0.5 * g.hx, Y);
+    if (!(fabs(Dd) > 1e-12 * h)) {
+        r = 0.5 * (bs + be);
+        return 1;
+    }
+    double w = fabs(Dd);
+    if (D == 0) {
+        st.x0 = Dd > 0.0 ? X - Dd : X;
+        st.y0 = Y;
+        st.sw = w;
+        st.sh = hf;
+    } else {
+        st.x0 = X;
+        st.y0 = Dd > 0.0 ? Y - Dd : Y;
+        st.sw = hf;
+        st.sh = w;
+    }
+    st.w = w;
+    st.hf = hf;
+    if (st.x0 + st.sw < P.xmin || st.x0 > P.xmax || st.y0 + st.sh < P.ymin || st.y0 > P.ymax ||
+        rect_outside_disc(P, st.x0, st.y0, st.sw, st.sh)) {
+        r = 1.0;
+        return 1;
+    }
+    return 0;
+}
+
+__device__ __forceinline__ double strip_beta(double a, const Strip& st) {
+    double r = 1.0 - a / (st.w * st.hf);
+    if (r < 0.0) r = 0.0;
+    if (r > 1.0) r = 1.0;
+    return r;
+}
+
+// Phase 1: thread t over the box's faces normal to the sweep direction; true = left to
+// phase 2.
+template <int D>
+__device__ bool swept1(const Grid& g, const SweepJob& J, const Motion& M, const Stage& S, int t) {
+    const Box& B = J.B;
+    int fw = D == 0 ? B.w() + 1 : B.w(), fh = D == 0 ? B.h() : B.h() + 1;
+    if (t >= fw * fh) return false;
+    int i = B.i0 + t % fw, j = B.j0 + t / fw;
+    double r;
+    Strip st;
+    if (!swept_quick<D>(g, J, M, i, j, r, st)) {
+        if (J.Ls.poly.m > SMALL_POLY) return true;
+        r = strip_beta(poly_clip_area<1>(J.Ls.poly, st.x0, st.y0, st.sw, st.sh, 0), st);
+    }
+    S.bt[fidx<D>(B, i, j)] = r;
+    return false;
+}
+
+// Phase 2: one wavefront per listed face (P: the start polygon, possibly staged in LDS).
+template <int D>
+__device__ void swept2(const Grid& g, const SweepJob& J, const Poly& P, const Motion& M, const Stage& S,
+                       const int* list, int item, int lane) {
+    const Box& B = J.B;
+    int fw = D == 0 ? B.w() + 1 : B.w();
+    int t = list[item];
+    int i = B.i0 + t % fw, j = B.j0 + t / fw;
+    double r;
+    Strip st;
+    swept_quick<D>(g, J, M, i, j, r, st);
+    r = strip_beta(poly_clip_area<WAVE>(P, st.x0, st.y0, st.sw, st.sh, lane), st);
     if (lane == 0) S.bt[fidx<D>(B, i, j)] = r;
 }
 
@@ -133,90 +187,6 @@ __device__ int donors(const Grid& g, const Level& Ls, const R* U, int i, int j, 
         }
     }
     return nd;
-}
-
-// States of the box cells before the sweep (Eqs. volumeWeighting, cutCellInitialisation,
-// cutCellInitialisationDonorCellUpdate as read for exact time averages):
-//   uncovered (alpha_s = 0 < alpha_e): state = donors' volume-weighted average, no content;
-//   emptied (alpha_s > 0, no content): content sigma * sum(donor content);
-//   donors of emptied cells keep the fraction (1 - sum sigma) of their content.
-template <typename R>
-__global__ void k_stage(Grid g, Level Ls, Level Le, const R* __restrict__ U, Box B, Stage S,
-                        unsigned int* status) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) S.nbad[0] = S.nbad[1] = 0u;  // read by the collapse rounds at the sweep's end
-    if (t >= B.w() * B.h()) return;
-    int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
-    size_t nc = (size_t)g.nx * g.ny, k = (size_t)j * g.nx + i;
-    int cap = S.cap;
-    double as = Ls.alpha[k], ae = Le.alpha[k];
-    double u[4];
-#pragma unroll
-    for (int m = 0; m < 4; m++) u[m] = (double)U[m * nc + k];
-    bool uncovered = as == 0.0 && ae > 0.0;
-    bool emptied = as > 0.0 && ae > 0.0 && !(u[0] > 0.0);
-    double q[4] = {0, 0, 0, 0};
-    double u1[4] = {u[0], u[1], u[2], u[3]};
-    int has = 0;
-    if (uncovered || emptied) {
-        int don[8];
-        int nd = donors(g, Ls, U, i, j, don);
-        if (nd == 0) {
-            atomicOr(status, 1u);
-        } else {
-            double sa = 0.0;
-            for (int qd = 0; qd < nd; qd++) sa += Ls.alpha[don[qd]];
-            if (uncovered) {
-                for (int m = 0; m < 4; m++) {
-                    double su = 0.0;
-                    for (int qd = 0; qd < nd; qd++) su += (double)U[m * nc + don[qd]];
-                    q[m] = su / sa;
-                }
-                has = 1;
-                u1[0] = u1[1] = u1[2] = u1[3] = 0.0;
-            } else {
-                double sig = as / (as + sa);
-                for (int m = 0; m < 4; m++) {
-                    double su = 0.0;
-                    for (int qd = 0; qd < nd; qd++) su += (double)U[m * nc + don[qd]];
-                    u1[m] = sig * su;
-                }
-            }
-        }
-    } else if (as > 0.0 && u[0] > 0.0) {
-        // a live cell may donate to emptied neighbours (visited in increasing cell order)
-        double take = 0.0;
-        for (int dj = -1; dj <= 1; dj++)
-            for (int di = -1; di <= 1; di++) {
-                if (di == 0 && dj == 0) continue;
-                int li = i + di, lj = j + dj;
-                if (li < 0 || li >= g.nx || lj < 0 || lj >= g.ny) continue;
-                size_t l = (size_t)lj * g.nx + li;
-                double asl = Ls.alpha[l], ael = Le.alpha[l];
-                if (!(asl > 0.0 && ael > 0.0 && !((double)U[l] > 0.0))) continue;
-                int don[8];
-                int nd = donors(g, Ls, U, li, lj, don);
-                bool mine = false;
-                double sa = 0.0;
-                for (int qd = 0; qd < nd; qd++) {
-                    sa += Ls.alpha[don[qd]];
-                    mine |= don[qd] == (int)k;
-                }
-                if (mine) take += asl / (asl + sa);
-            }
-        if (take > 0.0)
-            for (int m = 0; m < 4; m++) u1[m] = u[m] * (1.0 - take);
-    }
-    if (!has && as > 0.0 && u1[0] > 0.0) {
-        has = 1;
-        for (int m = 0; m < 4; m++) q[m] = u1[m] / as;
-    }
-    int b = bidx(B, i, j);
-    for (int m = 0; m < 4; m++) {
-        S.Q[m * cap + b] = q[m];
-        S.U1[m * cap + b] = u1[m];
-    }
-    S.has[b] = (int8_t)has;
 }
 
 // ------------------------------------------------------------------ wall quantities
@@ -292,17 +262,94 @@ __device__ __forceinline__ void wall_riemann(const double q[4], double nx, doubl
     *rst = rs;
 }
 
-// Per box cell: wall flag, shielded volume, boundary flux F^B (advective part from the
-// step's common boundary state, pressure part from this stage) and F^B - u_wall^d Q^B.
-template <int D>
-__global__ void k_wall(Grid g, Level Ls, Level Le, Motion M, Box B, Stage S, Common C, int first,
-                       int32_t step_id) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+// States of the box cells before the sweep (Eqs. volumeWeighting, cutCellInitialisation,
+// cutCellInitialisationDonorCellUpdate as read for exact time averages):
+//   uncovered (alpha_s = 0 < alpha_e): state = donors' volume-weighted average, no content;
+//   emptied (alpha_s > 0, no content): content sigma * sum(donor content);
+//   donors of emptied cells keep the fraction (1 - sum sigma) of their content.
+// Then the cell's wall quantities: wall flag, shielded volume, boundary flux F^B (advective
+// part from the step's common boundary state, pressure part from this stage) and
+// F^B - u_wall^d Q^B.
+template <int D, typename R>
+__device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, const Stage& S, const Common& C,
+                          unsigned int* status, int32_t step_id, int t) {
+    const Level& Ls = J.Ls;
+    const Level& Le = J.Le;
+    const Box& B = J.B;
+    const R* U = (const R*)J.Uin;
+    int first = J.first;
     if (t >= B.w() * B.h()) return;
     int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
-    int cap = S.cap, b = bidx(B, i, j);
     size_t nc = (size_t)g.nx * g.ny, k = (size_t)j * g.nx + i;
+    int cap = S.cap;
     double as = Ls.alpha[k], ae = Le.alpha[k];
+    double u[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) u[m] = (double)U[m * nc + k];
+    bool uncovered = as == 0.0 && ae > 0.0;
+    bool emptied = as > 0.0 && ae > 0.0 && !(u[0] > 0.0);
+    double q[4] = {0, 0, 0, 0};
+    double u1[4] = {u[0], u[1], u[2], u[3]};
+    int has = 0;
+    if (uncovered || emptied) {
+        int don[8];
+        int nd = donors(g, Ls, U, i, j, don);
+        if (nd == 0) {
+            atomicOr(status, 1u);
+        } else {
+            double sa = 0.0;
+            for (int qd = 0; qd < nd; qd++) sa += Ls.alpha[don[qd]];
+            if (uncovered) {
+                for (int m = 0; m < 4; m++) {
+                    double su = 0.0;
+                    for (int qd = 0; qd < nd; qd++) su += (double)U[m * nc + don[qd]];
+                    q[m] = su / sa;
+                }
+                has = 1;
+                u1[0] = u1[1] = u1[2] = u1[3] = 0.0;
+            } else {
+                double sig = as / (as + sa);
+                for (int m = 0; m < 4; m++) {
+                    double su = 0.0;
+                    for (int qd = 0; qd < nd; qd++) su += (double)U[m * nc + don[qd]];
+                    u1[m] = sig * su;
+                }
+            }
+        }
+    } else if (as > 0.0 && u[0] > 0.0) {
+        // a live cell may donate to emptied neighbours (visited in increasing cell order)
+        double take = 0.0;
+        for (int dj = -1; dj <= 1; dj++)
+            for (int di = -1; di <= 1; di++) {
+                if (di == 0 && dj == 0) continue;
+                int li = i + di, lj = j + dj;
+                if (li < 0 || li >= g.nx || lj < 0 || lj >= g.ny) continue;
+                size_t l = (size_t)lj * g.nx + li;
+                double asl = Ls.alpha[l], ael = Le.alpha[l];
+                if (!(asl > 0.0 && ael > 0.0 && !((double)U[l] > 0.0))) continue;
+                int don[8];
+                int nd = donors(g, Ls, U, li, lj, don);
+                bool mine = false;
+                double sa = 0.0;
+                for (int qd = 0; qd < nd; qd++) {
+                    sa += Ls.alpha[don[qd]];
+                    mine |= don[qd] == (int)k;
+                }
+                if (mine) take += asl / (asl + sa);
+            }
+        if (take > 0.0)
+            for (int m = 0; m < 4; m++) u1[m] = u[m] * (1.0 - take);
+    }
+    if (!has && as > 0.0 && u1[0] > 0.0) {
+        has = 1;
+        for (int m = 0; m < 4; m++) q[m] = u1[m] / as;
+    }
+    int b = bidx(B, i, j);
+    for (int m = 0; m < 4; m++) {
+        S.Q[m * cap + b] = q[m];
+        S.U1[m * cap + b] = u1[m];
+    }
+    S.has[b] = (int8_t)has;
     double ab = 0.5 * (as + ae);
     double bw, be, bs, bn;
     if (D == 0) {
@@ -344,9 +391,7 @@ __global__ void k_wall(Grid g, Level Ls, Level Le, Motion M, Box B, Stage S, Com
         if (ah < 0.0) ah = 0.0;
         if (ah > sh) ah = sh;
         ahat = ah;
-        if (S.has[b]) {
-            double q[4];
-            for (int m = 0; m < 4; m++) q[m] = S.Q[m * cap + b];
+        if (has) {
             double pst, rst;
             wall_riemann(q, nxu, nyu, uwx, uwy, g.gamma, &pst, &rst);
             double u = q[1] / q[0], v = q[2] / q[0];
@@ -394,8 +439,8 @@ struct CellData {
 // State of the cell at line position p (ghost cells beyond the domain: zero-gradient copy
 // or mirror with negated normal momentum).
 template <int D, typename R>
-__device__ void fetch_cell(const Grid& g, const R* U, const Box& B, const Stage& S, int line, int p, int n,
-                           CellData& c) {
+__device__ __forceinline__ void fetch_cell(const Grid& g, const R* U, const Box& B, const Stage& S, int line, int p,
+                                           int n, CellData& c) {
     int bc = p < 0 ? g.bc[D == 0 ? 0 : 2] : g.bc[D == 0 ? 1 : 3];
     int src = p;
     bool mirror = false;
@@ -410,21 +455,32 @@ __device__ void fetch_cell(const Grid& g, const R* U, const Box& B, const Stage&
     if (src >= n) src = n - 1;
     int i = D == 0 ? src : line, j = D == 0 ? line : src;
     size_t nc = (size_t)g.nx * g.ny;
-    if (B.has(i, j)) {
-        int b = bidx(B, i, j);
-        c.has = S.has[b] != 0;
+    // values are selected, not stored conditionally, so that the cell records stay in
+    // registers
+    bool in = B.has(i, j);
+    int b = in ? bidx(B, i, j) : 0;
+    size_t k = (size_t)j * g.nx + i;
+    bool has = in ? S.has[b] != 0 : true;
+    double q[4], u1[4];
+    if (in) {
+#pragma unroll
         for (int m = 0; m < 4; m++) {
-            c.q[m] = S.Q[m * S.cap + b];
-            c.u1[m] = S.U1[m * S.cap + b];
+            q[m] = S.Q[m * S.cap + b];
+            u1[m] = S.U1[m * S.cap + b];
         }
     } else {
-        size_t k = (size_t)j * g.nx + i;
-        c.has = true;
-        for (int m = 0; m < 4; m++) c.q[m] = c.u1[m] = (double)U[m * nc + k];
+#pragma unroll
+        for (int m = 0; m < 4; m++) q[m] = u1[m] = (double)U[m * nc + k];
     }
-    if (!c.has)
-        for (int m = 0; m < 4; m++) c.q[m] = 0.0;
-    if (mirror) c.q[1 + D] = -c.q[1 + D];
+#pragma unroll
+    for (int m = 0; m < 4; m++) q[m] = has ? q[m] : 0.0;
+    if (mirror) q[1 + D] = -q[1 + D];
+    c.has = has;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        c.q[m] = q[m];
+        c.u1[m] = u1[m];
+    }
 }
 
 template <int D>
@@ -442,7 +498,7 @@ struct WallData {
 };
 
 template <int D>
-__device__ void fetch_wall(const Box& B, const Stage& S, int line, int p, int n, WallData& w) {
+__device__ __forceinline__ void fetch_wall(const Box& B, const Stage& S, int line, int p, int n, WallData& w) {
     w.wall = false;
     if (p < 0 || p >= n) return;
     int i = D == 0 ? p : line, j = D == 0 ? line : p;
@@ -460,7 +516,7 @@ __device__ void fetch_wall(const Box& B, const Stage& S, int line, int p, int n,
 // Klein2DtotalfluxaMethod2 in division-free form, shielded flux of the same face):
 // Phi = bt F - kap (s_L - ahat_L)(F - FB_L) - kap (s_R - ahat_R)(F - FB_R).
 template <int D>
-__device__ void face_phi(double bt, double btm, double btp, const double* er_l, const double* el_r, bool act,
+__device__ __forceinline__ void face_phi(double bt, double btm, double btp, const double* er_l, const double* el_r, bool act,
                          const WallData& L, const WallData& Rw, bool l_in, bool r_in, double gam, double* phi) {
     if (!act) {
         for (int m = 0; m < 4; m++) phi[m] = 0.0;
@@ -493,9 +549,12 @@ __device__ void face_phi(double bt, double btm, double btp, const double* er_l, 
 // dt/h (Phi_lo - Phi_hi + W), W = (beta_hi - beta_lo)(F^B - u_wall^d Q^B) for wall cells;
 // then covered cells and collapsed cells (inadmissible update) are marked for emptying.
 template <int D, typename R>
-__global__ void k_patch(Grid g, Level Ls, Level Le, const R* __restrict__ U, Box B, Stage S, double lam,
-                        unsigned int* ncollapse) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void patch(const Grid& g, const SweepJob& J, const Stage& S, unsigned int* ncollapse, int t) {
+    const Level& Ls = J.Ls;
+    const Level& Le = J.Le;
+    const Box& B = J.B;
+    const R* U = (const R*)J.Uin;
+    double lam = J.lam;
     if (t >= B.w() * B.h()) return;
     int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
     int n = D == 0 ? g.nx : g.ny;
@@ -508,16 +567,20 @@ __global__ void k_patch(Grid g, Level Ls, Level Le, const R* __restrict__ U, Box
     bool has_c = S.has[b] != 0;
     if (has_c) {
         CellData c[5];
+        // fully unrolled, so that the small arrays stay in registers
+#pragma unroll
         for (int s = 0; s < 5; s++) fetch_cell<D>(g, U, B, S, line, p - 2 + s, n, c[s]);
         double el[3][4], er[3][4];
+#pragma unroll
         for (int s = 1; s <= 3; s++) {
-            if (!c[s].has) continue;
             bool ok = c[s - 1].has && c[s + 1].has;
-            muscl<double, D>(c[s - 1].q, c[s].q, c[s + 1].q, ok, lam, gam, el[s - 1], er[s - 1]);
+            if (c[s].has) muscl<double, D>(c[s - 1].q, c[s].q, c[s + 1].q, ok, lam, gam, el[s - 1], er[s - 1]);
         }
         double bt[4];  // faces p-1, p, p+1, p+2
+#pragma unroll
         for (int s = 0; s < 4; s++) bt[s] = face_bt<D>(B, S, line, p - 1 + s);
         WallData w[3];
+#pragma unroll
         for (int s = 0; s < 3; s++) fetch_wall<D>(B, S, line, p - 1 + s, n, w[s]);
         double plo[4], phi_hi[4];
         bool act_lo = bt[1] > 0.0 && c[1].has && c[2].has;
@@ -545,6 +608,7 @@ __global__ void k_patch(Grid g, Level Ls, Level Le, const R* __restrict__ U, Box
     S.gone[b] = (int8_t)gone;
 }
 
+
 // Content (conserved amounts) that is present but not an admissible gas state.
 __device__ __forceinline__ bool inadmissible_content(const double* u) {
     if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0 && u[3] == 0.0) return false;
@@ -556,8 +620,10 @@ __device__ __forceinline__ bool inadmissible_content(const double* u) {
 // goes to its face neighbours that stay fluid (else its eight neighbours) in proportion to
 // their end volume.  Gathered per recipient in increasing order of the emptied cell.
 template <typename R>
-__global__ void k_cover(Grid g, Level Le, Box B, Stage S, R* __restrict__ Uout) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t) {
+    const Level& Le = J.Le;
+    const Box& B = J.B;
+    R* Uout = (R*)J.Uout;
     if (t >= B.w() * B.h()) return;
     int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
     int b = bidx(B, i, j), cap = S.cap;
@@ -618,11 +684,17 @@ __global__ void k_cover(Grid g, Level Le, Box B, Stage S, R* __restrict__ Uout) 
 // still bad (status bit 2).  Both rounds return at once when the previous stage found no
 // bad cell.
 template <typename R>
-__global__ void k_fix(Grid g, Level Le, Box B, Stage S, int round, const double* __restrict__ Xin,
-                      const int8_t* __restrict__ fin, double* __restrict__ Xout, int8_t* __restrict__ fout,
-                      R* __restrict__ Uout, unsigned int* ncollapse, unsigned int* status) {
+__device__ void fix(const Grid& g, const SweepJob& J, const Stage& S, int round, unsigned int* ncollapse,
+                    unsigned int* status, int t) {
+    const Level& Le = J.Le;
+    const Box& B = J.B;
+    R* Uout = (R*)J.Uout;
+    // content ping-pongs U1 -> Q -> U_out through the two rounds
+    const double* Xin = round == 0 ? S.U1 : S.Q;
+    const int8_t* fin = round == 0 ? S.f1 : S.f2;
+    double* Xout = S.Q;
+    int8_t* fout = S.f2;
     if (S.nbad[round] == 0u) return;
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= B.w() * B.h()) return;
     int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
     int b = bidx(B, i, j), cap = S.cap;
@@ -681,129 +753,189 @@ __global__ void k_fix(Grid g, Level Le, Box B, Stage S, int round, const double*
 }
 
 // ------------------------------------------------------------------ dense sweeps
-// x-sweep of regular cells: one thread per cell, 256-cell tiles with a two-cell halo on
-// each side exchanged through LDS (slopes, evolved face states, face fluxes).
+// Regular cells outside the sweep box: plain MUSCL-Hancock + HLLC update, U streamed once
+// (read U_in, write U_out).  Both kernels are templated on the tile shape, chosen per grid
+// by the tile tuner.
+
+// Ghost-cell source index along a line of n cells (two layers; zero gradient or mirror).
+__device__ __forceinline__ int ghost_src(int p, int n, int bclo, int bchi, bool& mir) {
+    mir = false;
+    int src = p;
+    if (p < 0) {
+        src = bclo == 1 ? -1 - p : 0;
+        mir = bclo == 1;
+    } else if (p >= n) {
+        src = bchi == 1 ? 2 * n - 1 - p : n - 1;
+        mir = bchi == 1;
+    }
+    return src < 0 ? 0 : (src >= n ? n - 1 : src);
+}
+
+// x-sweep: a block covers DX_OUT = 252 cells of RB consecutive rows (one thread per cell
+// plus a two-cell halo each side); the evolved face states and face fluxes are exchanged
+// through LDS; the next row is loaded while the current one is computed.
 constexpr int DX_T = 256;
 constexpr int DX_OUT = DX_T - 4;
 
-template <typename R, typename T>
-__global__ __launch_bounds__(DX_T) void k_dense_x(Grid g, const R* __restrict__ U, R* __restrict__ Uout, Box B,
-                                                   T lam) {
+template <int RB>
+__host__ __device__ constexpr int dense_x_blocks(int nx, int ny) {
+    return ((nx + DX_OUT - 1) / DX_OUT) * ((ny + RB - 1) / RB);
+}
+
+template <typename R, typename T, int RB>
+__device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U, R* __restrict__ Uout, Box B, T lam,
+                                        int lb) {
     __shared__ T sq[4][DX_T];
     __shared__ T ser[4][DX_T];
     __shared__ T sf[4][DX_T];
     int tid = threadIdx.x;
-    int j = blockIdx.y;
-    int nx = g.nx;
-    int i = blockIdx.x * DX_OUT - 2 + tid;
-    size_t nc = (size_t)nx * g.ny;
-    bool rowbox = j >= B.j0 && j < B.j1;
-    // ghost mapping
-    int src = i;
-    bool mir = false;
-    if (i < 0) {
-        src = g.bc[0] == 1 ? -1 - i : 0;
-        mir = g.bc[0] == 1;
-    } else if (i >= nx) {
-        src = g.bc[1] == 1 ? 2 * nx - 1 - i : nx - 1;
-        mir = g.bc[1] == 1;
+    int nx = g.nx, ny = g.ny;
+    int gx = (nx + DX_OUT - 1) / DX_OUT;
+    int i = (lb % gx) * DX_OUT - 2 + tid;
+    int j0 = (lb / gx) * RB;
+    size_t nc = (size_t)nx * ny;
+    bool mir;
+    int src = ghost_src(i, nx, g.bc[0], g.bc[1], mir);
+    bool writer = tid >= 2 && tid < DX_T - 2 && i >= 0 && i < nx;
+    bool colbox = i >= B.i0 && i < B.i1;
+    T gam = (T)g.gamma;
+    T qn[4];
+    {
+        size_t kk = (size_t)j0 * nx + src;
+#pragma unroll
+        for (int m = 0; m < 4; m++) qn[m] = (T)U[m * nc + kk];
     }
-    src = src < 0 ? 0 : (src >= nx ? nx - 1 : src);
-    T q[4];
-    size_t kk = (size_t)j * nx + src;
+    for (int r = 0; r < RB; r++) {
+        int j = j0 + r;
+        if (j >= ny) break;  // uniform over the block
+        T q[4];
 #pragma unroll
-    for (int m = 0; m < 4; m++) q[m] = (T)U[m * nc + kk];
-    if (mir) q[1] = -q[1];
+        for (int m = 0; m < 4; m++) q[m] = qn[m];
+        if (r + 1 < RB && j + 1 < ny) {
+            size_t kk = (size_t)(j + 1) * nx + src;
 #pragma unroll
-    for (int m = 0; m < 4; m++) sq[m][tid] = q[m];
-    __syncthreads();
-    T el[4], er[4];
-    if (tid >= 1 && tid < DX_T - 1) {
-        T qm[4], qp[4];
-#pragma unroll
-        for (int m = 0; m < 4; m++) {
-            qm[m] = sq[m][tid - 1];
-            qp[m] = sq[m][tid + 1];
+            for (int m = 0; m < 4; m++) qn[m] = (T)U[m * nc + kk];
         }
-        muscl<T, 0>(qm, q, qp, true, lam, (T)g.gamma, el, er);
+        if (mir) q[1] = -q[1];
 #pragma unroll
-        for (int m = 0; m < 4; m++) ser[m][tid] = er[m];
-    }
-    __syncthreads();
-    if (tid >= 2 && tid < DX_T - 1) {
-        T erl[4], F[4];
+        for (int m = 0; m < 4; m++) sq[m][tid] = q[m];
+        __syncthreads();
+        T el[4], er[4];
+        if (tid >= 1 && tid < DX_T - 1) {
+            T qm[4], qp[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++) erl[m] = ser[m][tid - 1];
-        hllc<T, 0>(erl, el, (T)g.gamma, F);
+            for (int m = 0; m < 4; m++) {
+                qm[m] = sq[m][tid - 1];
+                qp[m] = sq[m][tid + 1];
+            }
+            muscl<T, 0>(qm, q, qp, true, lam, gam, el, er);
 #pragma unroll
-        for (int m = 0; m < 4; m++) sf[m][tid] = F[m];
-    }
-    __syncthreads();
-    if (tid >= 2 && tid < DX_T - 2 && i >= 0 && i < nx) {
-        if (rowbox && i >= B.i0 && i < B.i1) return;
-        size_t k = (size_t)j * nx + i;
+            for (int m = 0; m < 4; m++) ser[m][tid] = er[m];
+        }
+        __syncthreads();
+        if (tid >= 2 && tid < DX_T - 1) {
+            T erl[4], F[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++) Uout[m * nc + k] = (R)(q[m] + lam * (sf[m][tid] - sf[m][tid + 1]));
+            for (int m = 0; m < 4; m++) erl[m] = ser[m][tid - 1];
+            hllc<T, 0>(erl, el, gam, F);
+#pragma unroll
+            for (int m = 0; m < 4; m++) sf[m][tid] = F[m];
+        }
+        __syncthreads();
+        if (writer && !(colbox && j >= B.j0 && j < B.j1)) {
+            size_t k = (size_t)j * nx + i;
+#pragma unroll
+            for (int m = 0; m < 4; m++) Uout[m * nc + k] = (R)(q[m] + lam * (sf[m][tid] - sf[m][tid + 1]));
+        }
     }
 }
 
-// y-sweep of regular cells: one thread per column segment of DY_ROWS rows, marching up
-// the column with a register window (coalesced row-wise loads across the wavefront).
-template <typename R, typename T>
-__global__ __launch_bounds__(256) void k_dense_y(Grid g, const R* __restrict__ U, R* __restrict__ Uout, Box B,
-                                                 T lam, int rows) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// y-sweep: a block covers 64 columns x TR rows.  The tile and its two-row halos (TR + 4
+// rows, each a coalesced 64-wide access per component) are staged in LDS; then, as in the
+// x-sweep, every cell's reconstruction, every face's flux and every cell's update is
+// computed once, in three phases separated by barriers (rows spread over the four
+// wavefronts).  The face fluxes reuse the staged states' LDS space.
+template <typename T, int TR>
+struct DenseYTile {
+    static constexpr int ROWS = TR + 4;  // staged rows: tile rows 0 .. TR+3 (outputs 2 .. TR+1)
+    static constexpr int ITS = (TR + 2 + 3) / 4;  // reconstructed rows 1 .. TR+2 per wavefront
+    static constexpr size_t lds_bytes = (size_t)(ROWS + TR + 3) * 64 * 4 * sizeof(T);
+};
+
+template <int TR>
+__host__ __device__ constexpr int dense_y_blocks(int nx, int ny) {
+    return ((nx + 63) / 64) * ((ny + TR - 1) / TR);
+}
+
+template <typename R, typename T, int TR>
+__device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, R* __restrict__ Uout, Box B, T lam,
+                                        int lb) {
+    using Tile = DenseYTile<T, TR>;
+    constexpr int ROWS = Tile::ROWS, ITS = Tile::ITS;
+    __shared__ T sq[4][ROWS][64];    // staged states; then face fluxes (row r: face below cell r)
+    __shared__ T ser[4][TR + 3][64];  // evolved states at the upper face of each cell
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int nx = g.nx, ny = g.ny;
-    if (i >= nx) return;
-    int j0 = blockIdx.y * rows;
-    int j1 = min(j0 + rows, ny);
+    int gx = (nx + 63) / 64;
+    int i = (lb % gx) * 64 + lane;
+    int jt = (lb / gx) * TR;  // grid row of tile row 2
     size_t nc = (size_t)nx * ny;
-    bool colbox = i >= B.i0 && i < B.i1;
-    auto load = [&](int jj, T* q) {
-        int src = jj;
-        bool mir = false;
-        if (jj < 0) {
-            src = g.bc[2] == 1 ? -1 - jj : 0;
-            mir = g.bc[2] == 1;
-        } else if (jj >= ny) {
-            src = g.bc[3] == 1 ? 2 * ny - 1 - jj : ny - 1;
-            mir = g.bc[3] == 1;
-        }
-        src = src < 0 ? 0 : (src >= ny ? ny - 1 : src);
-        size_t k = (size_t)src * nx + i;
+    int ic = i < nx ? i : nx - 1;
+    for (int r = w; r < ROWS; r += 4) {
+        bool mir;
+        int src = ghost_src(jt - 2 + r, ny, g.bc[2], g.bc[3], mir);
+        size_t k = (size_t)src * nx + ic;
+        T v[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++) q[m] = (T)U[m * nc + k];
-        if (mir) q[2] = -q[2];
-    };
-    T qa[4], qb[4], qc[4];  // cells s-1, s, s+1
-    load(j0 - 2, qa);
-    load(j0 - 1, qb);
-    T er_prev[4], F_prev[4], q_prev[4];
-    for (int s = j0 - 1; s <= j1; s++) {
-        load(s + 1, qc);
-        T el[4], er[4];
-        muscl<T, 1>(qa, qb, qc, true, lam, (T)g.gamma, el, er);
-        if (s >= j0) {
-            T F[4];
-            hllc<T, 1>(er_prev, el, (T)g.gamma, F);  // face s, between cells s-1 and s
-            if (s - 1 >= j0) {
-                int jj = s - 1;
-                if (!(colbox && jj >= B.j0 && jj < B.j1)) {
-                    size_t k = (size_t)jj * nx + i;
+        for (int m = 0; m < 4; m++) v[m] = (T)U[m * nc + k];
+        if (mir) v[2] = -v[2];
 #pragma unroll
-                    for (int m = 0; m < 4; m++) Uout[m * nc + k] = (R)(q_prev[m] + lam * (F_prev[m] - F[m]));
-                }
-            }
+        for (int m = 0; m < 4; m++) sq[m][r][lane] = v[m];
+    }
+    __syncthreads();
+    T gam = (T)g.gamma;
+    T qc[ITS][4], el[ITS][4];
 #pragma unroll
-            for (int m = 0; m < 4; m++) F_prev[m] = F[m];
-        }
+    for (int it = 0; it < ITS; it++) {
+        int r = 1 + w + 4 * it;
+        if (r > TR + 2) break;
+        T qm[4], qp[4], er[4];
 #pragma unroll
         for (int m = 0; m < 4; m++) {
-            er_prev[m] = er[m];
-            q_prev[m] = qb[m];
-            qa[m] = qb[m];
-            qb[m] = qc[m];
+            qm[m] = sq[m][r - 1][lane];
+            qc[it][m] = sq[m][r][lane];
+            qp[m] = sq[m][r + 1][lane];
         }
+        muscl<T, 1>(qm, qc[it], qp, true, lam, gam, el[it], er);
+#pragma unroll
+        for (int m = 0; m < 4; m++) ser[m][r][lane] = er[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITS; it++) {
+        int r = 1 + w + 4 * it;
+        if (r > TR + 2) break;
+        if (r < 2) continue;
+        T erl[4], F[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) erl[m] = ser[m][r - 1][lane];
+        hllc<T, 1>(erl, el[it], gam, F);
+#pragma unroll
+        for (int m = 0; m < 4; m++) sq[m][r][lane] = F[m];
+    }
+    __syncthreads();
+    if (i >= nx) return;
+    bool colbox = i >= B.i0 && i < B.i1;
+#pragma unroll
+    for (int it = 0; it < ITS; it++) {
+        int r = 1 + w + 4 * it;
+        if (r > TR + 1) break;
+        if (r < 2) continue;
+        int jj = jt + r - 2;
+        if (jj >= ny || (colbox && jj >= B.j0 && jj < B.j1)) continue;
+        size_t k = (size_t)jj * nx + i;
+#pragma unroll
+        for (int m = 0; m < 4; m++) Uout[m * nc + k] = (R)(qc[it][m] + lam * (sq[m][r][lane] - sq[m][r + 1][lane]));
     }
 }
 

@@ -1,0 +1,115 @@
+"""Batched stepping (one launch per phase over many contexts, one captured graph per
+membership) against contexts stepped alone, and the captured single-context step against
+its individual launches: bit-identical states, with members joining and leaving between
+steps (continuous batching)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1711_11361_amd import cc  # noqa: E402
+from paper_1711_11361_amd import workloads as W  # noqa: E402
+
+
+def small_requests():
+    out = []
+    for k in range(40):
+        r = W.serving_request(k)
+        if r["grid"]["nx"] * r["grid"]["ny"] <= 256 * 128:
+            out.append(r)
+        if len(out) == 6:
+            break
+    return out
+
+
+def solver(w, precision):
+    s = cc.Solver(w["grid"], w["body"], precision=precision)
+    s.set_prim(w["prim"])
+    return s
+
+
+def test_graph_step_equals_individual_launches():
+    w = W.cylinder(nx=128, ny=64)
+    a, b = solver(w, cc.CC_FP64), solver(w, cc.CC_FP64)
+    for _ in range(7):
+        dt = a.cfl_dt(w["cfl"])
+        a.step(dt)  # captured graph
+        b.begin_step(dt)
+        for d in (b.parity, 1 - b.parity):
+            b.sweep(d, dt)
+        b.end_step()
+    assert np.array_equal(a.get_u(), b.get_u())
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+def test_batch_equals_members_alone(precision):
+    reqs = small_requests()
+    alone = [solver(w, precision) for w in reqs]
+    mem = [solver(w, precision) for w in reqs]
+    dts = []
+    for s, w in zip(alone, reqs):
+        d = []
+        for _ in range(6):
+            dt = s.cfl_dt(w["cfl"])
+            s.step(dt)
+            d.append(dt)
+        dts.append(d)
+    B = cc.Batch(8, precision)
+    for s in mem:
+        B.add(s)
+    for k in range(6):
+        st = B.step([d[k] for d in dts])
+        assert st == [0] * len(mem)
+    for a, m in zip(alone, mem):
+        assert np.array_equal(a.get_u(), m.get_u())
+        assert a.info()["steps"] == m.info()["steps"] == 6
+    # the speeds the batch reduced give the same next time steps as each member's own
+    nxt, status = B.last_dt(reqs[0]["cfl"])
+    own = [m.cfl_dt(w["cfl"]) for m, w in zip(mem, reqs)]
+    assert status == [0] * len(mem)
+    np.testing.assert_allclose(nxt, own, rtol=0, atol=0)
+
+
+def test_members_join_and_leave():
+    reqs = small_requests()
+    p = cc.CC_FP32_GEOM64
+    alone = [solver(w, p) for w in reqs]
+    mem = [solver(w, p) for w in reqs]
+    # member k joins at step k and leaves after 4 steps; the batch steps 9 times
+    B = cc.Batch(4, p)
+    active = []
+    for step in range(9):
+        for k in range(len(reqs)):
+            if k == step and len(active) < 4:
+                B.add(mem[k])
+                active.append(k)
+        dts = [alone[k].cfl_dt(reqs[k]["cfl"]) for k in active]
+        for k, dt in zip(active, dts):
+            alone[k].step(dt)
+        B.step(dts)
+        for k in list(active):
+            if mem[k].info()["steps"] == 4:
+                B.remove(mem[k])
+                active.remove(k)
+    for a, m in zip(alone, mem):
+        assert np.array_equal(a.get_u(), m.get_u())
+    # a removed member steps on its own again
+    mem[0].step(mem[0].cfl_dt(reqs[0]["cfl"]))
+
+
+def test_batch_refuses_misuse():
+    reqs = small_requests()
+    s64 = solver(reqs[0], cc.CC_FP64)
+    s32 = solver(reqs[1], cc.CC_FP32_GEOM64)
+    B = cc.Batch(1, cc.CC_FP64)
+    with pytest.raises(cc.CCError):
+        B.add(s32)  # other precision
+    B.add(s64)
+    with pytest.raises(cc.CCError):
+        B.add(solver(reqs[2], cc.CC_FP64))  # full
+    with pytest.raises(cc.CCError):
+        s64.step(1e-4)  # stepped by its batch
