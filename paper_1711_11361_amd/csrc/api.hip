@@ -174,6 +174,8 @@ struct Engine {
     int tile_x = 0, tile_y = 1;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gkey[2] = {-1, -1};
+    hipStream_t side = nullptr;  // second stream of the captured step's fork/join
+    hipEvent_t fe[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -205,6 +207,9 @@ struct cc_ctx {
     // timing: bit 0 dense sweeps, bit 1 box and geometry phases
     int timing;
     std::vector<TimedPair> pending, pool;
+    // wave speeds of the current state, reduced and read back by the last captured step
+    bool speeds_ready;
+    int speeds_buf;
     std::string err;
 };
 
@@ -524,7 +529,7 @@ cc_status prepare_geometry(cc_ctx* c, double t, int slot, StepArgs& a) {
 }
 
 // ------------------------------------------------------------------ engine bookkeeping
-int units_of(int kind, int n) { return kind <= L_C2 ? 2 * n : n; }
+int units_of(int, int n) { return n; }
 
 int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     const Layout& L = c->lay;
@@ -570,7 +575,7 @@ hipError_t engine_plan(Engine& E, hipStream_t stream) {
         int nu = units_of(k, n);
         E.h_off[k].assign(nu + 1, 0);
         for (int u = 0; u < nu; u++) {
-            const cc_ctx* c = E.mem[k <= L_C2 ? u >> 1 : u];
+            const cc_ctx* c = E.mem[u];
             E.h_off[k][u + 1] = E.h_off[k][u] + kind_blocks(c, E, k);
         }
         std::copy(E.h_off[k].begin(), E.h_off[k].end(), all.begin() + (size_t)k * stride);
@@ -595,16 +600,21 @@ void klaunch(K kern, int blocks, int threads, hipStream_t s, Args... args) {
     if (blocks > 0) hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, args...);
 }
 
-void launch_geometry(const Engine& E, hipStream_t s) {
-    int n = (int)E.mem.size(), nu = 2 * n;
+// Geometry of level job `lev` of every member.
+void launch_geometry(const Engine& E, hipStream_t s, int lev) {
+    int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    klaunch(kb_geo_pose, ktotal(E, L_POSE), T_WIDE, s, A, koff(E, L_POSE), nu);
-    klaunch(kb_geo_p1<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), nu);
-    klaunch(kb_geo_p2<0>, ktotal(E, L_V2), T_WIDE, s, A, koff(E, L_V2), nu);
-    klaunch(kb_geo_p1<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), nu);
-    klaunch(kb_geo_p2<1>, ktotal(E, L_F2), T_WIDE, s, A, koff(E, L_F2), nu);
-    klaunch(kb_geo_p1<2>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), nu);
-    klaunch(kb_geo_p2<2>, ktotal(E, L_C2), T_WIDE, s, A, koff(E, L_C2), nu);
+    klaunch(kb_geo_pose, ktotal(E, L_POSE), T_WIDE, s, A, koff(E, L_POSE), n, lev);
+    klaunch(kb_geo_p1<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n, lev);
+    klaunch(kb_geo_p2<0>, ktotal(E, L_V2), T_WIDE, s, A, koff(E, L_V2), n, lev);
+    klaunch(kb_geo_p1<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n, lev);
+    klaunch(kb_geo_p2<1>, ktotal(E, L_F2), T_WIDE, s, A, koff(E, L_F2), n, lev);
+    klaunch(kb_geo_p1<2>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), n, lev);
+    klaunch(kb_geo_p2<2>, ktotal(E, L_C2), T_WIDE, s, A, koff(E, L_C2), n, lev);
+}
+void launch_geometry(const Engine& E, hipStream_t s) {
+    launch_geometry(E, s, 0);
+    launch_geometry(E, s, 1);
 }
 
 // Dense launches of sweep sw: bit 0 of `which` the x-sweep kernel, bit 1 the y-sweep
@@ -689,6 +699,8 @@ hipError_t engine_alloc_host(Engine& E) {
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, 16 * E.cap_n, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_gather, 8 * E.cap_n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&E.side, hipStreamNonBlocking);
+    for (int k = 0; k < 4 && e == hipSuccess; k++) e = hipEventCreateWithFlags(&E.fe[k], hipEventDisableTiming);
     return e;
 }
 
@@ -704,34 +716,51 @@ void engine_free(Engine& E) {
     if (E.h_gather) (void)hipHostFree(E.h_gather);
     E.h_cflout = nullptr;
     E.h_gather = nullptr;
+    for (int k = 0; k < 4; k++) {
+        if (E.fe[k]) (void)hipEventDestroy(E.fe[k]);
+        E.fe[k] = nullptr;
+    }
+    if (E.side) (void)hipStreamDestroy(E.side);
+    E.side = nullptr;
 }
 
-// Whole step of every member, argument blocks in host buffer b: upload, both geometry
-// levels, both sweeps and, for batches, the next time step's reduction, status gather and
-// their read-back.  `dirs` (single member): the direction of its first sweep, so that only
-// the matching dense kernel is launched.
+// Whole step of every member, argument blocks in host buffer b, as captured into a graph:
+// upload; then on the main stream the stage level's geometry and the first sweep's box
+// phases, while a second stream runs the first dense sweep (it reads the start state and
+// writes only cells outside the sweep boxes) and the end level's geometry (a slot the first
+// sweep does not touch); join; the second sweep the same way; then the next time step's
+// wave speeds, the status words and their read-back into pinned host memory.
+// dir0: the single member's first direction (only its dense kernels are launched), or -1.
 template <typename R>
-void step_sequence(Engine& E, hipStream_t s, int b, int dir0, bool batch) {
+void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
+    int which0 = dir0 < 0 ? 3 : 1 << dir0, which1 = dir0 < 0 ? 3 : 1 << (1 - dir0);
+    int n = (int)E.mem.size();
     (void)engine_upload(E, s, b);
-    launch_geometry(E, s);
-    for (int sw = 0; sw < 2; sw++) {
-        int which = dir0 < 0 ? 3 : 1 << (sw == 0 ? dir0 : 1 - dir0);
-        launch_box_pre<R>(E, s, sw);
-        launch_dense<R>(E, s, sw, which, nullptr, nullptr);
-        launch_box_post<R>(E, s, sw, which);
-    }
-    if (batch) {
-        int n = (int)E.mem.size();
-        launch_cfl<R>(E, s);
-        hipLaunchKernelGGL(kb_gather, dim3(nblk(n, 64)), dim3(64), 0, s, (const StepArgs*)E.d_args, n, E.d_gather);
-        (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
-        (void)hipMemcpyAsync(E.h_gather, E.d_gather, 8 * (size_t)n, hipMemcpyDeviceToHost, s);
-    }
+    (void)hipEventRecord(E.fe[0], s);
+    (void)hipStreamWaitEvent(E.side, E.fe[0], 0);
+    launch_dense<R>(E, E.side, 0, which0, nullptr, nullptr);
+    launch_geometry(E, E.side, 1);
+    (void)hipEventRecord(E.fe[1], E.side);
+    launch_geometry(E, s, 0);
+    launch_box_pre<R>(E, s, 0);
+    launch_box_post<R>(E, s, 0, which0);
+    (void)hipStreamWaitEvent(s, E.fe[1], 0);
+    (void)hipEventRecord(E.fe[2], s);
+    (void)hipStreamWaitEvent(E.side, E.fe[2], 0);
+    launch_dense<R>(E, E.side, 1, which1, nullptr, nullptr);
+    (void)hipEventRecord(E.fe[3], E.side);
+    launch_box_pre<R>(E, s, 1);
+    launch_box_post<R>(E, s, 1, which1);
+    (void)hipStreamWaitEvent(s, E.fe[3], 0);
+    launch_cfl<R>(E, s);
+    hipLaunchKernelGGL(kb_gather, dim3(nblk(n, 64)), dim3(64), 0, s, (const StepArgs*)E.d_args, n, E.d_gather);
+    (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(E.h_gather, E.d_gather, 8 * (size_t)n, hipMemcpyDeviceToHost, s);
 }
 
 // Launches the captured step graph of host buffer b (capturing it first if needed).
 template <typename R>
-hipError_t engine_graph_step(Engine& E, hipStream_t s, int b, int dir0, bool batch) {
+hipError_t engine_graph_step(Engine& E, hipStream_t s, int b, int dir0) {
     int key = dir0 + 1;
     if (!E.gexec[b] || E.gkey[b] != key) {
         if (E.gexec[b]) (void)hipGraphExecDestroy(E.gexec[b]);
@@ -739,7 +768,7 @@ hipError_t engine_graph_step(Engine& E, hipStream_t s, int b, int dir0, bool bat
         hipGraph_t gr;
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        step_sequence<R>(E, s, b, dir0, batch);
+        step_sequence<R>(E, s, b, dir0);
         e = hipStreamEndCapture(s, &gr);
         if (e != hipSuccess) return e;
         e = hipGraphInstantiate(&E.gexec[b], gr, nullptr, nullptr, 0);
@@ -806,6 +835,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     c->sm = 1;
     c->s1 = 2;
     c->timing = 0;
+    c->speeds_ready = false;
+    c->speeds_buf = 0;
     c->batch = nullptr;
     c->in_step = c->have_state = false;
     c->t = 0.0;
@@ -903,6 +934,7 @@ cc_status own_upload(cc_ctx* c, const StepArgs& a) {
 }
 
 cc_status geometry_at(cc_ctx* c, double t, int slot) {
+    c->speeds_ready = false;
     StepArgs a;
     cc_status st = prepare_geometry(c, t, slot, a);
     if (st != CC_OK) return st;
@@ -950,6 +982,7 @@ cc_status cc_geometry_dump(cc_ctx* c, int32_t level, int8_t* d_vcls, double* d_a
 
 cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
     if (!c || !d_prim) return fail(c, CC_ERR_ARG, "null argument");
+    c->speeds_ready = false;
     c->in_step = false;
     c->t = t0;
     c->step = 0;
@@ -974,6 +1007,7 @@ cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
 
 cc_status cc_set_clock(cc_ctx* c, double t, int64_t step) {
     if (!c || step < 0 || !std::isfinite(t)) return fail(c, CC_ERR_ARG, "bad argument");
+    c->speeds_ready = false;
     c->in_step = false;
     c->t = t;
     c->step = step;
@@ -986,6 +1020,7 @@ cc_status cc_set_clock(cc_ctx* c, double t, int64_t step) {
 
 cc_status cc_set_u(cc_ctx* c, const double* d_u) {
     if (!c || !d_u) return fail(c, CC_ERR_ARG, "null argument");
+    c->speeds_ready = false;
     size_t n = 4 * c->lay.nc;
     if (fp32(c))
         hipLaunchKernelGGL(k_copy_u<float>, dim3(nblk(n)), dim3(TPB), 0, c->stream, n, d_u,
@@ -1025,6 +1060,7 @@ cc_status cc_begin_step(cc_ctx* c, double dt) {
     cc_status st = not_in_batch(c);
     if (st != CC_OK) return st;
     StepArgs a;
+    c->speeds_ready = false;
     if ((st = prepare_step(c, dt, a)) != CC_OK) return st;
     if ((st = own_upload(c, a)) != CC_OK) return st;
     TimedPair tp{};
@@ -1114,10 +1150,12 @@ cc_status own_graph_step(cc_ctx* c, double dt) {
     cc_status st = prepare_step(c, dt, E.h_args[b][0]);
     if (st != CC_OK) return st;
     int dir0 = E.h_args[b][0].sw[0].dir;
-    HIPCHK(c, engine_graph_step<R>(E, c->stream, b, dir0, false));
+    HIPCHK(c, engine_graph_step<R>(E, c->stream, b, dir0));
     HIPCHK(c, hipEventRecord(E.ev[b], c->stream));
     E.ev_used[b] = true;
     E.buf = 1 - b;
+    c->speeds_ready = true;
+    c->speeds_buf = b;
     c->in_step = true;
     c->sweeps_done = 2;
     return CC_OK;
@@ -1186,6 +1224,16 @@ extern "C" {
 cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
     if (!c || !h_dt || !(cfl > 0.0)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_cfl_dt inside a step");
+    if (c->speeds_ready && !c->batch) {  // reduced and read back by the last captured step
+        HIPCHK(c, hipEventSynchronize(c->eng.ev[c->speeds_buf]));
+        double sx, sy;
+        std::memcpy(&sx, &c->eng.h_cflout[0], 8);
+        std::memcpy(&sy, &c->eng.h_cflout[1], 8);
+        cc_status st = status_error(c, c->eng.h_gather[0], sx, sy);
+        if (st != CC_OK) return st;
+        *h_dt = dt_from_speeds(c, cfl, sx, sy);
+        return CC_OK;
+    }
     unsigned long long* smax = at<unsigned long long>(c, c->lay.off_smax);
     unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
     const double* al = c->lev[c->s0].alpha;
@@ -1469,8 +1517,8 @@ cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
         // the members' results land in the batch's gather arrays
         E.h_args[buf][k].cfl_out = E.d_cflout + 2 * k;
     }
-    hipError_t e = E.prec == CC_FP32_GEOM64 ? engine_graph_step<float>(E, b->stream, buf, -1, true)
-                                            : engine_graph_step<double>(E, b->stream, buf, -1, true);
+    hipError_t e = E.prec == CC_FP32_GEOM64 ? engine_graph_step<float>(E, b->stream, buf, -1)
+                                            : engine_graph_step<double>(E, b->stream, buf, -1);
     if (e != hipSuccess) return bfail(b, CC_ERR_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
     BHIPCHK(b, hipEventRecord(E.ev[buf], b->stream));
     E.ev_used[buf] = true;
@@ -1480,6 +1528,7 @@ cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
         cc_ctx* c = E.mem[k];
         c->in_step = true;
         c->sweeps_done = 2;
+        c->speeds_ready = false;
         cc_end_step(c);
         if (h_status) h_status[k] = (int32_t)E.h_gather[2 * k];
     }

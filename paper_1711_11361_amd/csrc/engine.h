@@ -33,8 +33,8 @@ struct StepArgs {
 
 // Launch kinds and their block sizes.
 enum LaunchKind {
-    L_POSE, L_V1, L_V2, L_F1, L_F2, L_C1, L_C2,  // geometry, 2 units (levels) per instance
-    L_S1, L_S2, L_BOX, L_DX, L_DY, L_CFL, L_CFLF,  // sweeps and time step, 1 unit per instance
+    L_POSE, L_V1, L_V2, L_F1, L_F2, L_C1, L_C2,  // geometry of one level
+    L_S1, L_S2, L_BOX, L_DX, L_DY, L_CFL, L_CFLF,  // sweeps and time step
     NKINDS
 };
 constexpr int T_WIDE = 256;  // phase 1, phase 2 (4 wavefronts), dense, time step
@@ -63,10 +63,11 @@ __device__ __forceinline__ Unit unit_of(const int* __restrict__ off, int n) {
 }
 
 // ------------------------------------------------------------------ geometry
+// Geometry launches work on one level job (lev) of every member.
 __global__ __launch_bounds__(T_WIDE) void kb_geo_pose(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                      int n) {
+                                                      int n, int lev) {
     Unit w = unit_of(off, n);
-    const GeoJob& J = A[w.u >> 1].geo[w.u & 1];
+    const GeoJob& J = A[w.u].geo[lev];
     if (!J.active) return;
     int t = w.lb * T_WIDE + threadIdx.x;
     if (t == 0) J.cnt[0] = J.cnt[1] = J.cnt[2] = 0u;  // lists of this level's phases
@@ -75,10 +76,10 @@ __global__ __launch_bounds__(T_WIDE) void kb_geo_pose(const StepArgs* __restrict
 
 template <int K>
 __global__ __launch_bounds__(T_WIDE) void kb_geo_p1(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                    int n) {
+                                                    int n, int lev) {
     Unit w = unit_of(off, n);
-    const StepArgs& a = A[w.u >> 1];
-    const GeoJob& J = a.geo[w.u & 1];
+    const StepArgs& a = A[w.u];
+    const GeoJob& J = a.geo[lev];
     if (!J.active) return;
     int t = w.lb * T_WIDE + threadIdx.x;
     bool need;
@@ -103,11 +104,11 @@ __device__ __forceinline__ Poly stage_poly(const Poly& P, double* spoly) {
 
 template <int K>
 __global__ __launch_bounds__(T_WIDE) void kb_geo_p2(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                    int n) {
+                                                    int n, int lev) {
     __shared__ double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
-    const StepArgs& a = A[w.u >> 1];
-    const GeoJob& J = a.geo[w.u & 1];
+    const StepArgs& a = A[w.u];
+    const GeoJob& J = a.geo[lev];
     if (!J.active) return;
     int items = (int)J.cnt[K];
     if (w.lb * ITEMS_PER_BLOCK >= items) return;  // no item for this block
