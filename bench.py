@@ -88,22 +88,107 @@ def cpu_baseline(w, budget_s=15.0):
                       f"{T:.1f} s)"}
 
 
+def serving(n, budget_gib, slots):
+    """The serving mix: n requests (Poisson arrivals at 50/s, 500 steps each) served once
+    batched in FP32 state / FP64 geometry and once as plain per-request FP64 launches."""
+    import numpy as np
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import serving as S
+
+    # first use of both modes (module load, graph capture paths) outside the measured runs
+    for mode in ("batched", "plain"):
+        S.Server(mode, slots=4).run(S.make_requests(4, rate=1e9, steps=3, seed=99, first=10000))
+    check = set(range(0, n, 16))  # requests whose end states are compared between the modes
+    out = {}
+    res = {}
+    for mode in ("batched", "plain"):
+        reqs = S.make_requests(n, rate=50.0, steps=500, seed=0)
+        srv = S.Server(mode, budget_bytes=budget_gib * (1 << 30), slots=slots, keep_results=check)
+        out[mode] = srv.run(reqs)
+        res[mode] = {r.rid: r.result[0] for r in reqs if r.result is not None}
+    l1 = []
+    for rid in sorted(res["plain"]):
+        a, b = res["batched"][rid].astype(np.float64), res["plain"][rid]
+        l1.append(float(np.abs(a - b).sum() / np.abs(b).sum()))
+    out["fp32_vs_fp64_l1_density"] = {"max": max(l1), "requests_compared": len(l1)}
+    out["speedup_cell_updates"] = out["batched"]["cell_updates_per_s"] / out["plain"]["cell_updates_per_s"]
+    out["config"] = {"requests": n, "arrivals_per_s": 50.0, "steps_each": 500, "budget_gib": budget_gib,
+                     "slots": slots}
+    return out
+
+
+def probe():
+    """Dispatches for counter runs (one process, eager launches): every dense-sweep tile
+    variant on the 1024x512 cylinder in both precisions, then a plain 16 MiB fill and a
+    16 MiB device copy whose counter readings scale FETCH_SIZE and WRITE_SIZE to bytes."""
+    import torch
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    w = W.cylinder()
+    for prec in (cc.CC_FP32_GEOM64, cc.CC_FP64):
+        s = cc.Solver(w["grid"], w["body"], precision=prec)
+        s.set_prim(w["prim"])
+        for _ in range(10):
+            s.step(s.cfl_dt(w["cfl"]))
+        cc.cc_timing(s.ctx, 1)  # individual launches: one dispatch per dense sweep
+        ny_variants = 4 if prec == cc.CC_FP32_GEOM64 else 2
+        for v in range(4):
+            s.set_tiles(v, min(v, ny_variants - 1))
+            for _ in range(2):
+                s.step(s.cfl_dt(w["cfl"]))
+        cc.cc_timing_read(s.ctx)
+        cc.cc_timing(s.ctx, 0)
+        print("probe", "fp32" if prec == cc.CC_FP32_GEOM64 else "fp64", s.info(), flush=True)
+        s.close()
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("probe done", flush=True)
+
+
+COPY_BYTES = 16 << 20
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "dense_sweep_1024x512_hbm_traffic.md")
+
+
+def traffic_table():
+    """Per-dispatch HBM bytes of every dense-sweep kernel variant, from the committed counter
+    summary (the JSON block in it), or {} when it is absent."""
+    try:
+        txt = open(TRAFFIC_TABLE).read()
+        return json.loads(txt.split("```json")[1].split("```")[0])["kernels"]
+    except (OSError, IndexError, KeyError, ValueError):
+        return {}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="requests of the serving mix (0: skip; off by default, see the design notes)")
+    ap.add_argument("--probe", action="store_true", help="dispatches for rocprofv3 counter runs only")
+    ap.add_argument("--budget-gib", type=float, default=16.0)
+    ap.add_argument("--slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.probe:
+        probe()
+        return
     import numpy as np
     from paper_1711_11361_amd import cc
     from paper_1711_11361_amd import workloads as W
 
     w = W.cylinder()
+    table = traffic_table()
     nx, ny = w["grid"]["nx"], w["grid"]["ny"]
     r32 = run_mode(cc.CC_FP32_GEOM64, args.steps, args.warmup, w)
     r64 = run_mode(cc.CC_FP64, args.steps, args.warmup, w)
@@ -115,8 +200,13 @@ def main():
         avg_s = ms / cnt / 1e3
         alg = nx * ny * 4 * 2 * bytes_per_value  # read + write of the state, one sweep
         ach = alg / avg_s / 1e9
-        return {"bound": "hbm", "kernel": f"k_{kern}", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+        rows = r["tiles"]["x_rows_per_block"] if kern == "dense_x" else r["tiles"]["y_rows_per_tile"]
+        name = f"kb_{kern}<{'float' if bytes_per_value == 4 else 'double'}, {rows}>"
+        t = table.get(name)
+        return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None if t is None else t["fetch_bytes"] + t["write_bytes"],
+                "algorithmic_bytes": alg,
                 "avg_launch_us": round(avg_s * 1e6, 2),
                 "other_dense_us": round(1e3 * tim["dense_y" if kern == "dense_x" else "dense_x"][0] /
                                         max(tim["dense_y" if kern == "dense_x" else "dense_x"][1], 1), 2),
@@ -147,6 +237,8 @@ def main():
         "roofline": roofline(r32, 4),
         "sim_time_reached": r32["t_end"],
     }
+    if args.serving > 0:
+        out["serving"] = serving(args.serving, args.budget_gib, args.slots)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

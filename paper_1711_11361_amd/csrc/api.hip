@@ -1316,6 +1316,9 @@ cc_status tune_dense(cc_ctx* c, int reps) {
         J.Uin = c->ws + c->lay.off_u[c->cur];
         J.Uout = c->ws + c->lay.off_u[1 - c->cur];
     }
+    // the launch plan is rebuilt below, which destroys the captured step graphs: let every
+    // launch of them finish first
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     cc_status st = own_upload(c, a);
     if (st != CC_OK) return st;
     hipEvent_t ea, eb;
@@ -1381,6 +1384,7 @@ cc_status cc_set_tiles(cc_ctx* c, int32_t tile_x, int32_t tile_y) {
     if (!dense_variant_ok(c->eng.prec, 0, tile_x) || !dense_variant_ok(c->eng.prec, 1, tile_y))
         return fail(c, CC_ERR_ARG, "tile variant out of range for this precision");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_set_tiles inside a step");
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the captured graphs are about to be destroyed
     c->eng.tile_x = tile_x;
     c->eng.tile_y = tile_y;
     HIPCHK(c, engine_plan(c->eng, c->stream));
