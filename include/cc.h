@@ -135,7 +135,8 @@ cc_status cc_cfl_dt(cc_ctx* ctx, double cfl, double* h_dt);
 cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
 
 /* Host info vector (n entries used, up to 9): time, steps, parity, device status bits
- * (1: a cell became fluid without donors; 2: a cell stayed inadmissible after collapsing),
+ * (1: a cell became fluid without donors; 2: a cell stayed inadmissible after collapsing;
+ * 8: a grid-barrier wait of a persistent launch ran out),
  * collapsed-cell count, sweep box cells of the last sweep, staging capacity, rows per block
  * of the dense x-sweep, rows per tile of the dense y-sweep.  Synchronizes. */
 cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
@@ -151,6 +152,16 @@ cc_status cc_autotune(cc_ctx* ctx, int32_t reps, int32_t* h_choice);
  * {1, 2, 4, 8}, tile_y rows per y-sweep tile {8, 12, 16, 24} (16 and 24 only with FP32
  * state: the tile lives in 64 KiB of LDS).  CC_ERR_ARG for an index out of range. */
 cc_status cc_set_tiles(cc_ctx* ctx, int32_t tile_x, int32_t tile_y);
+
+/* How cc_step launches a whole step (results are identical, bit for bit, in both modes).
+ * CC_LAUNCH_PER_PHASE (default): every phase is one kernel launch, the step one captured
+ * HIP graph.  CC_LAUNCH_PERSISTENT: one launch per sweep whose phases are separated by
+ * grid-wide barriers, the dense tiles overlapping the cut-cell phases (tile variants 0-1
+ * only; other variants fall back to the per-phase launches).  Each barrier wait is bounded
+ * in time; a wait that runs out sets status bit 8 and the step reports CC_ERR_DEVICE.
+ * CC_ERR_ARG for an unknown mode or inside a step.  Synchronizes. */
+typedef enum { CC_LAUNCH_PER_PHASE = 0, CC_LAUNCH_PERSISTENT = 1 } cc_launch_mode;
+cc_status cc_set_launch_mode(cc_ctx* ctx, int32_t mode);
 
 /* Timing with HIP events on the context's stream.  mode bit 0: each dense-sweep launch
  * records its own start/stop events (no extra stream commands, so the interval is the
@@ -188,6 +199,8 @@ cc_status cc_batch_remove(cc_batch* b, cc_ctx* ctx);
 int32_t cc_batch_size(const cc_batch* b);
 /* Dense-sweep tile variants used by every member (as cc_set_tiles). */
 cc_status cc_batch_set_tiles(cc_batch* b, int32_t tile_x, int32_t tile_y);
+/* Launch mode of the batch's steps (as cc_set_launch_mode). */
+cc_status cc_batch_set_launch_mode(cc_batch* b, int32_t mode);
 /* One split step of every member, member k with time step h_dt[k] (host, in membership
  * order).  Also reduces each member's wave speeds for its next step and gathers the
  * status words; synchronizes.  h_status (nullable, host): each member's status bits. */

@@ -64,6 +64,7 @@ _sig = {
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
     "cc_set_tiles": (C.c_int, [_vp, _i32, _i32]),
+    "cc_set_launch_mode": (C.c_int, [_vp, _i32]),
     "cc_timing": (C.c_int, [_vp, _i32]),
     "cc_timing_read": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_last_error": (C.c_char_p, [_vp]),
@@ -74,6 +75,7 @@ _sig = {
     "cc_batch_remove": (C.c_int, [_vp, _vp]),
     "cc_batch_size": (_i32, [_vp]),
     "cc_batch_set_tiles": (C.c_int, [_vp, _i32, _i32]),
+    "cc_batch_set_launch_mode": (C.c_int, [_vp, _i32]),
     "cc_batch_step": (C.c_int, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
     "cc_batch_last_dt": (C.c_int, [_vp, _d, C.POINTER(_d), C.POINTER(_i32)]),
     "cc_batch_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
@@ -204,6 +206,17 @@ def cc_autotune(ctx, reps=20):
     out = (_i32 * 2)()
     _check(ctx, _lib.cc_autotune(ctx, int(reps), out))
     return out[0], out[1]
+
+
+CC_LAUNCH_PER_PHASE, CC_LAUNCH_PERSISTENT = 0, 1
+
+
+def cc_set_launch_mode(ctx, mode):
+    _check(ctx, _lib.cc_set_launch_mode(ctx, int(mode)))
+
+
+def cc_batch_set_launch_mode(b, mode):
+    _bcheck(b, _lib.cc_batch_set_launch_mode(b, int(mode)))
 
 
 def cc_timing(ctx, enable):
@@ -383,6 +396,9 @@ class Solver:
     def set_tiles(self, tile_x, tile_y):
         cc_set_tiles(self.ctx, tile_x, tile_y)
 
+    def set_launch_mode(self, mode):
+        cc_set_launch_mode(self.ctx, mode)
+
     def autotune(self, reps=20):
         """Pick the fastest dense-sweep tile shapes for this grid (needs a state)."""
         return cc_autotune(self.ctx, reps)
@@ -454,6 +470,9 @@ class Batch:
 
     def set_tiles(self, tile_x, tile_y):
         cc_batch_set_tiles(self.b, tile_x, tile_y)
+
+    def set_launch_mode(self, mode):
+        cc_batch_set_launch_mode(self.b, mode)
 
     def step(self, dts):
         """One step of every member (member k with dts[k]); returns the status words."""

@@ -13,6 +13,7 @@
 #include "../../include/cc.h"
 #include "cc_device.h"
 #include "engine.h"
+#include "persist.h"
 #include "geometry.h"
 #include "reduce.h"
 #include "sweep.h"
@@ -56,11 +57,11 @@ struct Layout {
     size_t off_u[2], off_vcls[3], off_fx[3], off_fy[3], off_alpha[3], off_poly[3];
     size_t off_body;
     size_t off_qb, off_stamp;
-    size_t off_sQ, off_sU1, off_shas, off_sbt, off_swall, off_sfb, off_swv, off_sahat, off_sU2, off_sgone;
+    size_t off_sQ, off_sU1, off_shas, off_sbt[2], off_swall, off_sfb, off_swv, off_sahat, off_sU2, off_sgone;
     size_t off_sf1, off_sf2, off_nbad;
-    size_t off_glist[2], off_gcnt, off_slist, off_scnt;
+    size_t off_glist[2], off_gcnt, off_slist[2], off_scnt, off_sync;
     size_t off_args, off_offs, off_cflout, off_gather;
-    size_t off_smax, off_status, off_ncol, off_part, off_tot;
+    size_t off_smax, off_status, off_ncol, off_part, off_tot, off_spd;
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
     int gw, gh;      // geometry-region capacity (cells)
@@ -119,7 +120,8 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_sQ = take(4 * cap * 8);
     L.off_sU1 = take(4 * cap * 8);
     L.off_shas = take(cap);
-    L.off_sbt = take(capf * 8);
+    L.off_sbt[0] = take(capf * 8);
+    L.off_sbt[1] = take(capf * 8);
     L.off_swall = take(cap);
     L.off_sfb = take(4 * cap * 8);
     L.off_swv = take(4 * cap * 8);
@@ -132,8 +134,10 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_glist[0] = take(std::max<size_t>(L.glist_cap, 1) * 4);
     L.off_glist[1] = take(std::max<size_t>(L.glist_cap, 1) * 4);
     L.off_gcnt = take(6 * 4);
-    L.off_slist = take(std::max<size_t>(L.slist_cap, 1) * 4);
-    L.off_scnt = take(4);
+    L.off_slist[0] = take(std::max<size_t>(L.slist_cap, 1) * 4);
+    L.off_slist[1] = take(std::max<size_t>(L.slist_cap, 1) * 4);
+    L.off_scnt = take(8);
+    L.off_sync = take(sizeof(GridSync));
     L.off_args = take(sizeof(StepArgs));
     L.off_offs = take((size_t)NKINDS * 3 * 4);
     L.off_cflout = take(16);
@@ -143,6 +147,7 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_ncol = take(4);
     L.off_part = take(std::max<size_t>(4 * NPART * 8, 2 * CFL_MAX_BLOCKS * 8));
     L.off_tot = take(4 * 8);
+    L.off_spd = take(2 * SPEED_SLOTS * 8 + 8);
     L.total = o;
     return L;
 }
@@ -174,8 +179,9 @@ struct Engine {
     int tile_x = 0, tile_y = 1;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gkey[2] = {-1, -1};
-    hipStream_t side = nullptr;  // second stream of the captured step's fork/join
-    hipEvent_t fe[4] = {nullptr, nullptr, nullptr, nullptr};
+    int mode = 0;                       // 0: one launch per phase; 1: one persistent launch per sweep
+    GridSync* d_sync = nullptr;         // barrier counters of the persistent sweep launches
+    unsigned long long wait_ticks = 0;  // barrier wait limit (wall-clock ticks)
 };
 
 }  // namespace
@@ -378,7 +384,7 @@ void base_args(cc_ctx* c, StepArgs& a) {
     S.Q = at<double>(c, c->lay.off_sQ);
     S.U1 = at<double>(c, c->lay.off_sU1);
     S.has = at<int8_t>(c, c->lay.off_shas);
-    S.bt = at<double>(c, c->lay.off_sbt);
+    S.bt = at<double>(c, c->lay.off_sbt[0]);
     S.wall = at<int8_t>(c, c->lay.off_swall);
     S.fb = at<double>(c, c->lay.off_sfb);
     S.wv = at<double>(c, c->lay.off_swv);
@@ -393,10 +399,15 @@ void base_args(cc_ctx* c, StepArgs& a) {
     a.C.stamp = at<int32_t>(c, c->lay.off_stamp);
     a.status = at<unsigned int>(c, c->lay.off_status);
     a.ncol = at<unsigned int>(c, c->lay.off_ncol);
-    a.slist = at<int>(c, c->lay.off_slist);
-    a.scnt = at<unsigned int>(c, c->lay.off_scnt);
+    for (int k = 0; k < 2; k++) {
+        a.bt[k] = at<double>(c, c->lay.off_sbt[k]);
+        a.slist[k] = at<int>(c, c->lay.off_slist[k]);
+        a.scnt[k] = at<unsigned int>(c, c->lay.off_scnt) + k;
+    }
     a.cfl_part = at<unsigned long long>(c, c->lay.off_part);
     a.cfl_out = at<unsigned long long>(c, c->lay.off_cflout);
+    a.spd = at<unsigned long long>(c, c->lay.off_spd);
+    a.spd_done = reinterpret_cast<unsigned int*>(a.spd + 2 * SPEED_SLOTS);
     for (int k = 0; k < 2; k++) {
         GeoJob& J = a.geo[k];
         J.list = at<int>(c, c->lay.off_glist[k]);
@@ -553,6 +564,7 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
         case L_CFL: return (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(L.nc, T_WIDE));
         case L_CFLF: return 1;
+        case L_BSPD: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
     }
     return 0;
 }
@@ -621,7 +633,7 @@ void launch_geometry(const Engine& E, hipStream_t s) {
 // kernel (a member's direction in this sweep picks which one does its work).  ta/tb:
 // events recorded by the launch itself around its execution (one kernel only), or null.
 template <typename R>
-void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t ta, hipEvent_t tb) {
+void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t ta, hipEvent_t tb, int fold = 0) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
     for (int d = 0; d < 2; d++) {
@@ -631,8 +643,8 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
         if (blocks == 0) continue;
         const int* off = koff(E, kind);
         auto go = [&](auto kern, int threads) {
-            if (ta) hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, ta, tb, 0, A, off, n, sw);
-            else hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, A, off, n, sw);
+            if (ta) hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, ta, tb, 0, A, off, n, sw, fold);
+            else hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, A, off, n, sw, fold);
         };
         if (d == 0) {
             switch (E.tile_x) {
@@ -699,8 +711,10 @@ hipError_t engine_alloc_host(Engine& E) {
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, 16 * E.cap_n, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_gather, 8 * E.cap_n, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&E.side, hipStreamNonBlocking);
-    for (int k = 0; k < 4 && e == hipSuccess; k++) e = hipEventCreateWithFlags(&E.fe[k], hipEventDisableTiming);
+    int dev = 0, khz = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    E.wait_ticks = (unsigned long long)(khz > 0 ? khz : 100000) * 250ull;  // a quarter of a second
     return e;
 }
 
@@ -716,44 +730,76 @@ void engine_free(Engine& E) {
     if (E.h_gather) (void)hipHostFree(E.h_gather);
     E.h_cflout = nullptr;
     E.h_gather = nullptr;
-    for (int k = 0; k < 4; k++) {
-        if (E.fe[k]) (void)hipEventDestroy(E.fe[k]);
-        E.fe[k] = nullptr;
+}
+
+// One persistent launch of sweep `sw` (tile variants: 1 or 2 rows per x tile, 8 or 12 rows
+// per y tile).  The grid is what the device keeps resident at once, so that every block of
+// the launch runs concurrently (the barriers between phases rely on it).
+template <typename R, int RB, int TR>
+hipError_t persist_one(const Engine& E, hipStream_t s, int sw) {
+    static int grid = -1;
+    if (grid < 0) {
+        int per = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kb_sweep<R, RB, TR>, 256, 0);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        if (per < 1 || cus < 1) return hipErrorLaunchOutOfResources;
+        grid = per * cus;
     }
-    if (E.side) (void)hipStreamDestroy(E.side);
-    E.side = nullptr;
+    PArgs p;
+    p.A = E.d_args;
+    p.off = E.d_off;
+    p.n = (int)E.mem.size();
+    p.stride = 2 * E.cap_n + 1;
+    p.gs = E.d_sync;
+    p.gather = E.d_gather;
+    p.wait_ticks = E.wait_ticks;
+    p.s = sw;
+    hipLaunchKernelGGL((kb_sweep<R, RB, TR>), dim3(grid), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+bool persist_ok(const Engine& E) {
+    return E.mode == 1 && E.tile_x >= 0 && E.tile_x <= 1 && E.tile_y >= 0 && E.tile_y <= 1;
+}
+
+template <typename R>
+hipError_t launch_persist(const Engine& E, hipStream_t s, int sw) {
+    switch (E.tile_x * 2 + E.tile_y) {
+        case 0: return persist_one<R, 1, 8>(E, s, sw);
+        case 1: return persist_one<R, 1, 12>(E, s, sw);
+        case 2: return persist_one<R, 2, 8>(E, s, sw);
+        default: return persist_one<R, 2, 12>(E, s, sw);
+    }
 }
 
 // Whole step of every member, argument blocks in host buffer b, as captured into a graph:
-// upload; then on the main stream the stage level's geometry and the first sweep's box
-// phases, while a second stream runs the first dense sweep (it reads the start state and
-// writes only cells outside the sweep boxes) and the end level's geometry (a slot the first
-// sweep does not touch); join; the second sweep the same way; then the next time step's
-// wave speeds, the status words and their read-back into pinned host memory.
-// dir0: the single member's first direction (only its dense kernels are launched), or -1.
+// upload; one persistent launch per sweep (or, for tile variants without one, every phase
+// as its own launch); then the read-back of the wave speeds and status words into pinned
+// host memory.  dir0: the single member's first direction (only its dense kernels are
+// launched on the per-phase path), or -1.
 template <typename R>
 void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
     int which0 = dir0 < 0 ? 3 : 1 << dir0, which1 = dir0 < 0 ? 3 : 1 << (1 - dir0);
     int n = (int)E.mem.size();
     (void)engine_upload(E, s, b);
-    (void)hipEventRecord(E.fe[0], s);
-    (void)hipStreamWaitEvent(E.side, E.fe[0], 0);
-    launch_dense<R>(E, E.side, 0, which0, nullptr, nullptr);
-    launch_geometry(E, E.side, 1);
-    (void)hipEventRecord(E.fe[1], E.side);
-    launch_geometry(E, s, 0);
-    launch_box_pre<R>(E, s, 0);
-    launch_box_post<R>(E, s, 0, which0);
-    (void)hipStreamWaitEvent(s, E.fe[1], 0);
-    (void)hipEventRecord(E.fe[2], s);
-    (void)hipStreamWaitEvent(E.side, E.fe[2], 0);
-    launch_dense<R>(E, E.side, 1, which1, nullptr, nullptr);
-    (void)hipEventRecord(E.fe[3], E.side);
-    launch_box_pre<R>(E, s, 1);
-    launch_box_post<R>(E, s, 1, which1);
-    (void)hipStreamWaitEvent(s, E.fe[3], 0);
-    launch_cfl<R>(E, s);
-    hipLaunchKernelGGL(kb_gather, dim3(nblk(n, 64)), dim3(64), 0, s, (const StepArgs*)E.d_args, n, E.d_gather);
+    if (persist_ok(E)) {
+        (void)launch_persist<R>(E, s, 0);
+        (void)launch_persist<R>(E, s, 1);
+    } else {
+        launch_geometry(E, s, 0);
+        launch_geometry(E, s, 1);
+        // the first sweep's dense kernel clears the time-step maxima, the second folds the
+        // new state's wave speeds into them; the box cells follow in their own launch
+        for (int sw = 0; sw < 2; sw++) {
+            launch_box_pre<R>(E, s, sw);
+            launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw == 0 ? 1 : 2);
+            launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1);
+        }
+        klaunch(kb_box_speeds<R>, ktotal(E, L_BSPD), T_BOX, s, (const StepArgs*)E.d_args, koff(E, L_BSPD), n,
+                E.d_gather);
+    }
     (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(E.h_gather, E.d_gather, 8 * (size_t)n, hipMemcpyDeviceToHost, s);
 }
@@ -865,6 +911,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     E.d_off = at<int>(c, lay.off_offs);
     E.d_cflout = at<unsigned long long>(c, lay.off_cflout);
     E.d_gather = at<unsigned int>(c, lay.off_gather);
+    E.d_sync = at<GridSync>(c, lay.off_sync);
     E.tile_x = 0;  // one row per x-sweep block
     E.tile_y = 1;  // 12-row y-sweep tiles
     hipError_t e = engine_alloc_host(E);
@@ -885,7 +932,9 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         e = hipMemcpyAsync(at<double>(c, lay.off_body), c->bverts.data(), 16 * (size_t)c->m, hipMemcpyHostToDevice,
                            c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_gcnt, 0, 24, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_scnt, 0, 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_scnt, 0, 8, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_sync, 0, sizeof(GridSync), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_spd, 0, 2 * SPEED_SLOTS * 8 + 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_nbad, 0, 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_smax, 0, 16, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_status, 0, 4, c->stream);
@@ -1213,6 +1262,7 @@ double dt_from_speeds(cc_ctx* c, double cfl, double sx, double sy) {
 cc_status status_error(cc_ctx* c, unsigned int status, double sx, double sy) {
     if (status & 1u) return fail(c, CC_ERR_STATE, "a cell became fluid without donor neighbours");
     if (status & 2u) return fail(c, CC_ERR_STATE, "a cut cell stayed inadmissible after two collapse rounds");
+    if (status & 8u) return fail(c, CC_ERR_DEVICE, "a grid barrier of the persistent sweep timed out");
     if (!std::isfinite(sx) || !std::isfinite(sy)) return fail(c, CC_ERR_STATE, "non-finite or non-physical state");
     return CC_OK;
 }
@@ -1379,6 +1429,16 @@ cc_status cc_autotune(cc_ctx* c, int32_t reps, int32_t* h_choice) {
     return CC_OK;
 }
 
+cc_status cc_set_launch_mode(cc_ctx* c, int32_t mode) {
+    if (!c) return CC_ERR_ARG;
+    if (mode != CC_LAUNCH_PER_PHASE && mode != CC_LAUNCH_PERSISTENT) return fail(c, CC_ERR_ARG, "unknown launch mode");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_set_launch_mode inside a step");
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the captured graphs are about to be destroyed
+    c->eng.mode = mode;
+    HIPCHK(c, engine_plan(c->eng, c->stream));
+    return CC_OK;
+}
+
 cc_status cc_set_tiles(cc_ctx* c, int32_t tile_x, int32_t tile_y) {
     if (!c) return CC_ERR_ARG;
     if (!dense_variant_ok(c->eng.prec, 0, tile_x) || !dense_variant_ok(c->eng.prec, 1, tile_y))
@@ -1421,7 +1481,8 @@ cc_status cc_timing_read(cc_ctx* c, double* h_out, int32_t n) {
 size_t cc_batch_workspace_bytes(int32_t max_instances) {
     if (max_instances < 1) return 0;
     size_t n = (size_t)max_instances;
-    return up(n * sizeof(StepArgs)) + up((size_t)NKINDS * (2 * n + 1) * sizeof(int)) + up(16 * n) + up(8 * n);
+    return up(n * sizeof(StepArgs)) + up((size_t)NKINDS * (2 * n + 1) * sizeof(int)) + up(16 * n) + up(8 * n) +
+           up(sizeof(GridSync));
 }
 
 cc_status cc_batch_create(int32_t max_instances, int32_t precision, void* d_ws, size_t ws_bytes, void* hip_stream,
@@ -1444,9 +1505,12 @@ cc_status cc_batch_create(int32_t max_instances, int32_t precision, void* d_ws, 
     E.d_cflout = (unsigned long long*)(b->ws + o);
     o += up(16 * n);
     E.d_gather = (unsigned int*)(b->ws + o);
+    o += up(8 * n);
+    E.d_sync = (GridSync*)(b->ws + o);
     E.tile_x = 0;
     E.tile_y = 1;
-    if (engine_alloc_host(E) != hipSuccess) {
+    if (engine_alloc_host(E) != hipSuccess || hipMemsetAsync(E.d_sync, 0, sizeof(GridSync), b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
         engine_free(E);
         delete b;
         return CC_ERR_DEVICE;
@@ -1503,6 +1567,15 @@ cc_status cc_batch_set_tiles(cc_batch* b, int32_t tile_x, int32_t tile_y) {
 }
 
 int32_t cc_batch_size(const cc_batch* b) { return b ? (int32_t)b->eng.mem.size() : 0; }
+
+cc_status cc_batch_set_launch_mode(cc_batch* b, int32_t mode) {
+    if (!b) return CC_ERR_ARG;
+    if (mode != CC_LAUNCH_PER_PHASE && mode != CC_LAUNCH_PERSISTENT) return bfail(b, CC_ERR_ARG, "unknown launch mode");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->eng.mode = mode;
+    BHIPCHK(b, engine_plan(b->eng, b->stream));
+    return CC_OK;
+}
 
 cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
     if (!b || !h_dt) return CC_ERR_ARG;
@@ -1569,5 +1642,12 @@ cc_status cc_batch_last_dt(cc_batch* b, double cfl, double* h_dt, int32_t* h_sta
 }
 
 const char* cc_batch_last_error(const cc_batch* b) { return b ? b->err.c_str() : ""; }
+
+#ifdef CC_PHASE_TRACE
+// Development aid: the phase clock of the last persistent sweep launches (2 x 18 ticks).
+int cc_phase_trace(unsigned long long* h_out) {
+    return hipMemcpyFromSymbol(h_out, HIP_SYMBOL(g_phase_trace), sizeof(g_phase_trace)) == hipSuccess ? 0 : 2;
+}
+#endif
 
 }  // extern "C"

@@ -105,10 +105,114 @@ __device__ __forceinline__ void euler_flux(const T q[4], T g, T f[4]) {
     f[3] = un * (q[3] + p);
 }
 
+// ------------------------------------------------------------- FP32 state arithmetic
+// The FP32 state mode evaluates the same formulas with one hardware reciprocal of the
+// density per state (velocity, pressure, sound speed and flux all reuse it) and fused
+// multiply-adds; the FP64 path below keeps every division and the written order.
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// (gamma - 1) (E - |m|^2 / (2 rho)), with ir = 1 / rho
+__device__ __forceinline__ float pressure32(const float q[4], float ir, float gm1) {
+    float ke = __builtin_fmaf(q[1], q[1], q[2] * q[2]) * (0.5f * ir);
+    return gm1 * (q[3] - ke);
+}
+
+template <int D>
+__device__ __forceinline__ void euler_flux32(const float q[4], float un, float p, float f[4]) {
+    constexpr int n = 1 + D, t = 2 - D;
+    f[0] = q[n];
+    f[n] = __builtin_fmaf(q[n], un, p);
+    f[t] = q[t] * un;
+    f[3] = un * (q[3] + p);
+}
+
+template <int D>
+__device__ __forceinline__ void hllc32(const float ql[4], const float qr[4], float g, float f[4]) {
+    constexpr int n = 1 + D, t = 2 - D;
+    float gm1 = g - 1.0f;
+    float rl = ql[0], rr = qr[0];
+    float irl = rcp32(rl), irr = rcp32(rr);
+    float ul = ql[n] * irl, ur = qr[n] * irr;
+    float pl = pressure32(ql, irl, gm1), pr = pressure32(qr, irr, gm1);
+    float al = __builtin_amdgcn_sqrtf(g * pl * irl), ar = __builtin_amdgcn_sqrtf(g * pr * irr);
+    float sl = fminf(ul - al, ur - ar);
+    float sr = fmaxf(ul + al, ur + ar);
+    float dl = sl - ul, dr = sr - ur;
+    float ml = rl * dl, mr = rr * dr;  // mass fluxes relative to the outer waves
+    float ss = __builtin_fmaf(ml, ul, __builtin_fmaf(-mr, ur, pr - pl)) * rcp32(ml - mr);
+    int kc = 0.0f <= sl ? 0 : (0.0f <= ss ? 1 : (0.0f <= sr ? 2 : 3));
+    bool left = kc <= 1;
+    float q[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = left ? ql[k] : qr[k];
+    float irk = left ? irl : irr, uk = left ? ul : ur, pk = left ? pl : pr, sk = left ? sl : sr;
+    float mk = left ? ml : mr;
+    float fk[4];
+    euler_flux32<D>(q, uk, pk, fk);
+    if (kc == 0 || kc == 3) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) f[k] = fk[k];
+        return;
+    }
+    // star state on the upwind side: c = rho_K (S_K - u_K) / (S_K - S*)
+    float c = mk * rcp32(sk - ss);
+    float us[4];
+    us[0] = c;
+    us[n] = c * ss;
+    us[t] = c * (q[t] * irk);
+    us[3] = c * __builtin_fmaf(ss - uk, __builtin_fmaf(pk, rcp32(mk), ss), q[3] * irk);
+#pragma unroll
+    for (int k = 0; k < 4; k++) f[k] = __builtin_fmaf(sk, us[k] - q[k], fk[k]);
+}
+
+__device__ __forceinline__ float vanleer32(float a, float b) {
+    float ab = a * b;
+    return ab > 0.0f ? (ab + ab) * rcp32(a + b) : 0.0f;
+}
+
+template <int D>
+__device__ __forceinline__ void muscl32(const float qm[4], const float q[4], const float qp[4], bool slope_ok,
+                                        float lam, float g, float el[4], float er[4]) {
+    constexpr int n = 1 + D;
+    float gm1 = g - 1.0f;
+    float ql[4], qr[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        float d = slope_ok ? vanleer32(q[k] - qm[k], qp[k] - q[k]) : 0.0f;
+        ql[k] = __builtin_fmaf(-0.5f, d, q[k]);
+        qr[k] = __builtin_fmaf(0.5f, d, q[k]);
+    }
+    float irl = rcp32(ql[0]), irr = rcp32(qr[0]);
+    float pl = pressure32(ql, irl, gm1), pr = pressure32(qr, irr, gm1);
+    bool ok = ql[0] > 0.0f && pl > 0.0f && qr[0] > 0.0f && pr > 0.0f;
+    if (ok) {
+        float fl[4], fr[4];
+        euler_flux32<D>(ql, ql[n] * irl, pl, fl);
+        euler_flux32<D>(qr, qr[n] * irr, pr, fr);
+        float hl = 0.5f * lam;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            float c = hl * (fl[k] - fr[k]);
+            el[k] = ql[k] + c;
+            er[k] = qr[k] + c;
+        }
+        float pel = pressure32(el, rcp32(el[0]), gm1), per = pressure32(er, rcp32(er[0]), gm1);
+        ok = el[0] > 0.0f && pel > 0.0f && er[0] > 0.0f && per > 0.0f;
+    }
+    if (!ok) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) el[k] = er[k] = q[k];
+    }
+}
+
 // HLLC flux with Davis wave-speed estimates.  The two star-region cases share one code
 // path on the upwind side's values (same operations as writing them out per side).
 template <typename T, int D>
 __device__ __forceinline__ void hllc(const T ql[4], const T qr[4], T g, T f[4]) {
+    if constexpr (sizeof(T) == 4) {
+        hllc32<D>(ql, qr, g, f);
+        return;
+    }
     constexpr int n = 1 + D, t = 2 - D;
     T rl = ql[0], rr = qr[0];
     T ul = qdiv(ql[n], rl), ur = qdiv(qr[n], rr);
@@ -157,6 +261,10 @@ __device__ __forceinline__ bool admissible(const T q[4], T g) {
 template <typename T, int D>
 __device__ __forceinline__ void muscl(const T qm[4], const T q[4], const T qp[4], bool slope_ok, T lam, T g,
                                       T el[4], T er[4]) {
+    if constexpr (sizeof(T) == 4) {
+        muscl32<D>(qm, q, qp, slope_ok, lam, g, el, er);
+        return;
+    }
     T dl[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) dl[k] = slope_ok ? vanleer(q[k] - qm[k], qp[k] - q[k]) : T(0);

@@ -757,6 +757,13 @@ __device__ void fix(const Grid& g, const SweepJob& J, const Stage& S, int round,
 // (read U_in, write U_out).  Both kernels are templated on the tile shape, chosen per grid
 // by the tile tuner.
 
+// Conservative update of a regular cell from its two face fluxes (fused in FP32).
+template <typename T>
+__device__ __forceinline__ T update(T q, T lam, T flo, T fhi) {
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(lam, flo - fhi, q);
+    return q + lam * (flo - fhi);
+}
+
 // Ghost-cell source index along a line of n cells (two layers; zero gradient or mirror).
 __device__ __forceinline__ int ghost_src(int p, int n, int bclo, int bchi, bool& mir) {
     mir = false;
@@ -782,12 +789,58 @@ __host__ __device__ constexpr int dense_x_blocks(int nx, int ny) {
     return ((nx + DX_OUT - 1) / DX_OUT) * ((ny + RB - 1) / RB);
 }
 
+template <typename T>
+__host__ __device__ constexpr size_t dense_x_lds() { return (size_t)12 * DX_T * sizeof(T); }
+
+// Speeds |u|+a and |v|+a of a stored regular-cell state (volume fraction 1) as ordered bit
+// patterns; 0 for cells without gas.  The time-step reduction uses the same formula.
+template <typename R>
+__device__ __forceinline__ void cell_speeds(const R* u, double gam, unsigned long long& bx, unsigned long long& by) {
+    double r = (double)u[0];
+    bx = by = 0ull;
+    if (!(r > 0.0)) return;
+    double q[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) q[m] = (double)u[m] / 1.0;
+    double uu = q[1] / q[0], vv = q[2] / q[0];
+    double c = sqrt(gam * pressure(q, gam) / q[0]);
+    double sx = fabs(uu) + c, sy = fabs(vv) + c;
+    bx = __double_as_longlong(sx);
+    by = __double_as_longlong(sy);
+    if (sx != sx) bx = 0x7ff8000000000000ull;
+    if (sy != sy) by = 0x7ff8000000000000ull;
+}
+
+// Speed maxima are folded into SPEED_SLOTS pairs per instance (one pair per group of
+// wavefronts, which keeps the atomics on any one address few); the pairs are combined
+// once all contributions are in.
+constexpr int SPEED_SLOTS = 64;
+
+// Wavefront maximum of a per-lane bit-pattern pair, then one atomic pair per wavefront
+// into the wavefront's slot.
+__device__ __forceinline__ void speeds_to_max(unsigned long long bx, unsigned long long by,
+                                              unsigned long long* slots) {
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long ox = __shfl_xor(bx, off, 64), oy = __shfl_xor(by, off, 64);
+        bx = ox > bx ? ox : bx;
+        by = oy > by ? oy : by;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        int k = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % SPEED_SLOTS);
+        if (bx) atomicMax(&slots[2 * k], bx);
+        if (by) atomicMax(&slots[2 * k + 1], by);
+    }
+}
+
+// lds: dense_x_lds<T>() bytes; cfl: when not null, the maxima of the written cells' speeds
+// are folded into these speed slots.
 template <typename R, typename T, int RB>
 __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U, R* __restrict__ Uout, Box B, T lam,
-                                        int lb) {
-    __shared__ T sq[4][DX_T];
-    __shared__ T ser[4][DX_T];
-    __shared__ T sf[4][DX_T];
+                                        int lb, T* lds, unsigned long long* cfl) {
+    T(*sq)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds);
+    T(*ser)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds + 4 * DX_T);
+    T(*sf)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds + 8 * DX_T);
+    unsigned long long cx = 0ull, cy = 0ull;
     int tid = threadIdx.x;
     int nx = g.nx, ny = g.ny;
     int gx = (nx + DX_OUT - 1) / DX_OUT;
@@ -844,10 +897,21 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U, 
         __syncthreads();
         if (writer && !(colbox && j >= B.j0 && j < B.j1)) {
             size_t k = (size_t)j * nx + i;
+            R un[4];
 #pragma unroll
-            for (int m = 0; m < 4; m++) Uout[m * nc + k] = (R)(q[m] + lam * (sf[m][tid] - sf[m][tid + 1]));
+            for (int m = 0; m < 4; m++) un[m] = (R)update(q[m], lam, sf[m][tid], sf[m][tid + 1]);
+#pragma unroll
+            for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
+            if (cfl) {
+                unsigned long long bx, by;
+                cell_speeds(un, g.gamma, bx, by);
+                cx = bx > cx ? bx : cx;
+                cy = by > cy ? by : cy;
+            }
         }
     }
+    if (cfl) speeds_to_max(cx, cy, cfl);
+    __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
 // y-sweep: a block covers 64 columns x TR rows.  The tile and its two-row halos (TR + 4
@@ -869,11 +933,13 @@ __host__ __device__ constexpr int dense_y_blocks(int nx, int ny) {
 
 template <typename R, typename T, int TR>
 __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, R* __restrict__ Uout, Box B, T lam,
-                                        int lb) {
+                                        int lb, T* lds, unsigned long long* cfl) {
     using Tile = DenseYTile<T, TR>;
     constexpr int ROWS = Tile::ROWS, ITS = Tile::ITS;
-    __shared__ T sq[4][ROWS][64];    // staged states; then face fluxes (row r: face below cell r)
-    __shared__ T ser[4][TR + 3][64];  // evolved states at the upper face of each cell
+    // staged states, then face fluxes (row r: face below cell r); evolved states at the
+    // upper face of each cell
+    T(*sq)[ROWS][64] = reinterpret_cast<T(*)[ROWS][64]>(lds);
+    T(*ser)[TR + 3][64] = reinterpret_cast<T(*)[TR + 3][64]>(lds + 4 * ROWS * 64);
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int nx = g.nx, ny = g.ny;
     int gx = (nx + 63) / 64;
@@ -924,7 +990,7 @@ __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, 
         for (int m = 0; m < 4; m++) sq[m][r][lane] = F[m];
     }
     __syncthreads();
-    if (i >= nx) return;
+    unsigned long long cx = 0ull, cy = 0ull;
     bool colbox = i >= B.i0 && i < B.i1;
 #pragma unroll
     for (int it = 0; it < ITS; it++) {
@@ -932,11 +998,22 @@ __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, 
         if (r > TR + 1) break;
         if (r < 2) continue;
         int jj = jt + r - 2;
-        if (jj >= ny || (colbox && jj >= B.j0 && jj < B.j1)) continue;
+        if (i >= nx || jj >= ny || (colbox && jj >= B.j0 && jj < B.j1)) continue;
         size_t k = (size_t)jj * nx + i;
+        R un[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++) Uout[m * nc + k] = (R)(qc[it][m] + lam * (sq[m][r][lane] - sq[m][r + 1][lane]));
+        for (int m = 0; m < 4; m++) un[m] = (R)update(qc[it][m], lam, sq[m][r][lane], sq[m][r + 1][lane]);
+#pragma unroll
+        for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
+        if (cfl) {
+            unsigned long long bx, by;
+            cell_speeds(un, g.gamma, bx, by);
+            cx = bx > cx ? bx : cx;
+            cy = by > cy ? by : cy;
+        }
     }
+    if (cfl) speeds_to_max(cx, cy, cfl);
+    __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
 }  // namespace cc

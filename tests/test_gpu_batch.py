@@ -32,21 +32,27 @@ def solver(w, precision):
     return s
 
 
-def test_graph_step_equals_individual_launches():
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+@pytest.mark.parametrize("mode", [cc.CC_LAUNCH_PER_PHASE, cc.CC_LAUNCH_PERSISTENT])
+def test_graph_step_equals_individual_launches(precision, mode):
     w = W.cylinder(nx=128, ny=64)
-    a, b = solver(w, cc.CC_FP64), solver(w, cc.CC_FP64)
+    a, b = solver(w, precision), solver(w, precision)
+    a.set_launch_mode(mode)
     for _ in range(7):
-        dt = a.cfl_dt(w["cfl"])
+        dt = a.cfl_dt(w["cfl"])  # from the speeds the captured step folded in
+        assert dt == b.cfl_dt(w["cfl"])  # from a separate reduction of the state
         a.step(dt)  # captured graph
         b.begin_step(dt)
         for d in (b.parity, 1 - b.parity):
             b.sweep(d, dt)
         b.end_step()
     assert np.array_equal(a.get_u(), b.get_u())
+    assert a.info()["status"] == 0
 
 
 @pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
-def test_batch_equals_members_alone(precision):
+@pytest.mark.parametrize("mode", [cc.CC_LAUNCH_PER_PHASE, cc.CC_LAUNCH_PERSISTENT])
+def test_batch_equals_members_alone(precision, mode):
     reqs = small_requests()
     alone = [solver(w, precision) for w in reqs]
     mem = [solver(w, precision) for w in reqs]
@@ -59,6 +65,7 @@ def test_batch_equals_members_alone(precision):
             d.append(dt)
         dts.append(d)
     B = cc.Batch(8, precision)
+    B.set_launch_mode(mode)
     for s in mem:
         B.add(s)
     for k in range(6):
