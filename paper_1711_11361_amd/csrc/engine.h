@@ -31,7 +31,6 @@ struct StepArgs {
     unsigned long long* cfl_part;  // 2 per block
     unsigned long long* cfl_out;   // 2: max (|u|+a) along x and y, as bit patterns
     unsigned long long* spd;       // 2 x SPEED_SLOTS: the same maxima folded in by a captured step
-    unsigned int* spd_done;        // blocks of the final combining launch that are done
 };
 
 // Launch kinds and their block sizes.
@@ -60,7 +59,7 @@ struct Unit {
 };
 __device__ __forceinline__ Unit unit_of(const int* __restrict__ off, int n) {
     Unit r;
-    r.u = find_unit(off, n, blockIdx.x);
+    r.u = n == 1 ? 0 : find_unit(off, n, blockIdx.x);
     r.lb = blockIdx.x - off[r.u];
     r.nb = off[r.u + 1] - off[r.u];
     return r;
@@ -240,27 +239,10 @@ __global__ __launch_bounds__(T_BOX) void kb_fix(const StepArgs* __restrict__ A, 
 // step); 2 folds the speeds of the written cells into them (second sweep).
 __device__ __forceinline__ void clear_speeds(const StepArgs& a) {
     for (int k = threadIdx.x; k < 2 * SPEED_SLOTS; k += blockDim.x) a.spd[k] = 0ull;
-    if (threadIdx.x == 0) *a.spd_done = 0u;
 }
 __device__ __forceinline__ unsigned long long* fold_target(const StepArgs& a, int lb, int fold) {
     if (fold == 1 && lb == 0) clear_speeds(a);
     return fold == 2 ? a.spd : nullptr;
-}
-
-// Combines a member's speed slots into its time-step maxima (one wavefront).
-__device__ __forceinline__ void combine_speeds(const StepArgs& a) {
-    int l = threadIdx.x & 63;
-    unsigned long long bx = __hip_atomic_load(&a.spd[2 * l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long by = __hip_atomic_load(&a.spd[2 * l + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long ox = __shfl_xor(bx, off, 64), oy = __shfl_xor(by, off, 64);
-        bx = ox > bx ? ox : bx;
-        by = oy > by ? oy : by;
-    }
-    if (l == 0) {
-        a.cfl_out[0] = bx;
-        a.cfl_out[1] = by;
-    }
 }
 
 template <typename R, int RB>
@@ -316,29 +298,18 @@ __device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t) {
     speeds_to_max(bx, by, a.spd);
 }
 
-// After the second sweep of a captured step: the box cells' wave speeds; the member's last
-// block to finish combines the speed slots into the time-step maxima and gathers the status
-// word and collapse count for one read-back.
+// After the second sweep of a captured step: the box cells' wave speeds (the host takes
+// the maximum over the speed slots it reads back), and the status word and collapse count
+// of each member gathered for the same read-back.
 template <typename R>
 __global__ __launch_bounds__(T_BOX) void kb_box_speeds(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                        int n, unsigned int* __restrict__ gather) {
-    __shared__ int s_last;
     Unit w = unit_of(off, n);
     const StepArgs& a = A[w.u];
     box_speeds<R>(a, 1, w.lb * T_BOX + threadIdx.x);
-    __threadfence();
-    if (threadIdx.x == 0) {
-        unsigned int old = __hip_atomic_fetch_add(a.spd_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = old == (unsigned int)(w.nb - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    combine_speeds(a);
-    if (threadIdx.x == 0) {
+    if (w.lb == 0 && threadIdx.x == 0) {
         gather[2 * w.u] = *a.status;
         gather[2 * w.u + 1] = *a.ncol;
-        *a.spd_done = 0u;
     }
 }
 

@@ -266,7 +266,6 @@ __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
 #endif
     if (s == 1) {
         unsigned int err = __hip_atomic_load(&p.gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 8u : 0u;
-        for (int u = tid >> 6; u < p.n; u += blockDim.x >> 6) combine_speeds(p.A[u]);
         for (int u = tid; u < p.n; u += blockDim.x) {
             p.gather[2 * u] = *p.A[u].status | err;
             p.gather[2 * u + 1] = *p.A[u].ncol;
