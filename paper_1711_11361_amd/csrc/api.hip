@@ -60,13 +60,12 @@ struct Layout {
     size_t off_qb, off_stamp;
     size_t off_sQ, off_sU1, off_shas, off_sbt[2], off_swall, off_sfb, off_swv, off_sahat, off_sU2, off_sgone;
     size_t off_sf1, off_sf2, off_nbad;
-    size_t off_glist[2], off_gcnt, off_slist[2], off_scnt, off_sync;
+    size_t off_sync;
     size_t off_args, off_offs, off_cflout, off_gather;
     size_t off_smax, off_status, off_ncol, off_part, off_tot, off_spd;
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
     int gw, gh;      // geometry-region capacity (cells)
-    size_t glist_cap, slist_cap;
 };
 
 int body_m(const cc_body* b) { return b && b->nverts > 0 && b->verts ? b->nverts : 0; }
@@ -96,9 +95,6 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     }
     L.cap = (size_t)L.capw * L.caph;
     L.capf = m > 0 ? (size_t)(L.capw + 1) * (L.caph + 1) : 0;
-    size_t gf = (size_t)(L.gw + 1) * L.gh + (size_t)L.gw * (L.gh + 1);
-    L.glist_cap = std::max<size_t>(gf, (size_t)(L.gw + 1) * (L.gh + 1));
-    L.slist_cap = L.capf;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
@@ -132,12 +128,6 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_sf1 = take(cap);
     L.off_sf2 = take(cap);
     L.off_nbad = take(8);
-    L.off_glist[0] = take(std::max<size_t>(L.glist_cap, 1) * 4);
-    L.off_glist[1] = take(std::max<size_t>(L.glist_cap, 1) * 4);
-    L.off_gcnt = take(6 * 4);
-    L.off_slist[0] = take(std::max<size_t>(L.slist_cap, 1) * 4);
-    L.off_slist[1] = take(std::max<size_t>(L.slist_cap, 1) * 4);
-    L.off_scnt = take(8);
     L.off_sync = take(sizeof(GridSync));
     L.off_args = take(sizeof(StepArgs));
     L.off_offs = take((size_t)NKINDS * 3 * 4);
@@ -293,6 +283,13 @@ void poly_info(const cc_ctx* c, const double* pv, Poly& P, Box& cells) {
         P.ymin = std::fmin(P.ymin, pv[2 * k + 1]);
         P.ymax = std::fmax(P.ymax, pv[2 * k + 1]);
     }
+    P.ib = P.it = P.il = P.ir = 0;
+    for (int k = 1; k < m; k++) {
+        if (pv[2 * k + 1] < pv[2 * P.ib + 1]) P.ib = k;
+        if (pv[2 * k + 1] > pv[2 * P.it + 1]) P.it = k;
+        if (pv[2 * k] < pv[2 * P.il]) P.il = k;
+        if (pv[2 * k] > pv[2 * P.ir]) P.ir = k;
+    }
     P.rin2 = -1.0;
     P.rout2 = 0.0;
     P.cx = P.cy = 0.0;
@@ -402,16 +399,12 @@ void base_args(cc_ctx* c, StepArgs& a) {
     a.ncol = at<unsigned int>(c, c->lay.off_ncol);
     for (int k = 0; k < 2; k++) {
         a.bt[k] = at<double>(c, c->lay.off_sbt[k]);
-        a.slist[k] = at<int>(c, c->lay.off_slist[k]);
-        a.scnt[k] = at<unsigned int>(c, c->lay.off_scnt) + k;
     }
     a.cfl_part = at<unsigned long long>(c, c->lay.off_part);
     a.cfl_out = at<unsigned long long>(c, c->lay.off_cflout);
     a.spd = at<unsigned long long>(c, c->lay.off_spd);
     for (int k = 0; k < 2; k++) {
         GeoJob& J = a.geo[k];
-        J.list = at<int>(c, c->lay.off_glist[k]);
-        J.cnt = at<unsigned int>(c, c->lay.off_gcnt) + 3 * k;
         J.body = at<double>(c, c->lay.off_body);
     }
 }
@@ -548,17 +541,18 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     size_t gf = (size_t)(L.gw + 1) * L.gh + (size_t)L.gw * (L.gh + 1);
     size_t gc = (size_t)L.gw * L.gh;
     size_t sf = std::max((size_t)(L.capw + 1) * L.caph, (size_t)L.capw * (L.caph + 1));
-    // phase-2 wavefronts: about one per boundary item of a large body
-    int p2 = (int)std::min<size_t>(256, std::max<size_t>(4, (size_t)(L.gw + L.gh)));
     int m = c->m;
     if (m == 0 && kind <= L_BOX) return 0;
+    // stages whose boundary items (about gw + gh of them for a many-sided body) each take a
+    // wavefront's chain search: enough wavefronts that most of them get at most one
+    size_t walkers = m > SMALL_POLY ? std::min<size_t>(256, (size_t)(L.gw + L.gh)) : 0;
+    auto stage = [&](size_t items) { return (int)std::max<size_t>(nblk(items, T_WIDE), walkers); };
     switch (kind) {
         case L_POSE: return (int)nblk((size_t)m, T_WIDE);
-        case L_V1: return (int)nblk(gv, T_WIDE);
-        case L_F1: return (int)nblk(gf, T_WIDE);
-        case L_C1: return (int)nblk(gc, T_WIDE);
-        case L_V2: case L_F2: case L_C2: case L_S2: return m > SMALL_POLY ? p2 : 0;
-        case L_S1: return (int)nblk(sf, T_WIDE);
+        case L_V1: return stage(gv);
+        case L_F1: return stage(gf);
+        case L_C1: return stage(gc);
+        case L_S1: return stage(sf);
         case L_BOX: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
@@ -612,21 +606,15 @@ void klaunch(K kern, int blocks, int threads, hipStream_t s, Args... args) {
     if (blocks > 0) hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, args...);
 }
 
-// Geometry of level job `lev` of every member.
-void launch_geometry(const Engine& E, hipStream_t s, int lev) {
+// Geometry of both level jobs of every member: pose, vertex classes, face intervals,
+// volume fractions.
+void launch_geometry(const Engine& E, hipStream_t s) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    klaunch(kb_geo_pose, ktotal(E, L_POSE), T_WIDE, s, A, koff(E, L_POSE), n, lev);
-    klaunch(kb_geo_p1<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n, lev);
-    klaunch(kb_geo_p2<0>, ktotal(E, L_V2), T_WIDE, s, A, koff(E, L_V2), n, lev);
-    klaunch(kb_geo_p1<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n, lev);
-    klaunch(kb_geo_p2<1>, ktotal(E, L_F2), T_WIDE, s, A, koff(E, L_F2), n, lev);
-    klaunch(kb_geo_p1<2>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), n, lev);
-    klaunch(kb_geo_p2<2>, ktotal(E, L_C2), T_WIDE, s, A, koff(E, L_C2), n, lev);
-}
-void launch_geometry(const Engine& E, hipStream_t s) {
-    launch_geometry(E, s, 0);
-    launch_geometry(E, s, 1);
+    klaunch(kb_geo_pose, ktotal(E, L_POSE), T_WIDE, s, A, koff(E, L_POSE), n);
+    klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
+    klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
+    klaunch(kb_geo<2>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), n);
 }
 
 // Dense launches of sweep sw: bit 0 of `which` the x-sweep kernel, bit 1 the y-sweep
@@ -673,8 +661,7 @@ template <typename R>
 void launch_box_pre(const Engine& E, hipStream_t s, int sw) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    klaunch(kb_swept1, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
-    klaunch(kb_swept2, ktotal(E, L_S2), T_WIDE, s, A, koff(E, L_S2), n, sw);
+    klaunch(kb_swept, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
     klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
 }
 // Box phases after the dense sweep (`which` as for the dense launches).
@@ -788,8 +775,7 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
         (void)launch_persist<R>(E, s, 0);
         (void)launch_persist<R>(E, s, 1);
     } else {
-        launch_geometry(E, s, 0);
-        launch_geometry(E, s, 1);
+        launch_geometry(E, s);
         // the first sweep's dense kernel clears the time-step maxima, the second folds the
         // new state's wave speeds into them; the box cells follow in their own launch
         for (int sw = 0; sw < 2; sw++) {
@@ -931,8 +917,6 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     if (e == hipSuccess && c->m > 0)
         e = hipMemcpyAsync(at<double>(c, lay.off_body), c->bverts.data(), 16 * (size_t)c->m, hipMemcpyHostToDevice,
                            c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_gcnt, 0, 24, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_scnt, 0, 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_sync, 0, sizeof(GridSync), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_spd, 0, 2 * SPEED_SLOTS * 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_nbad, 0, 8, c->stream);

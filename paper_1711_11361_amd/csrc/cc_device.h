@@ -35,6 +35,10 @@ struct Poly {
     int m;
     double xmin, xmax, ymin, ymax;  // bounding box
     double cx, cy, rin2, rout2;     // certificate disc radii about (cx, cy); rin2 < 0: unused
+    // Vertices of least and greatest y (ib, it) and x (il, ir).  Counter-clockwise, y does
+    // not decrease from ib to it and x does not decrease from il to ir (the other way round
+    // on the remaining chain), so the edges meeting a line or a strip are found by bisection.
+    int ib, it, il, ir;
 };
 
 // One level: vertex classes, face solid intervals (lo, hi) measured from the face's

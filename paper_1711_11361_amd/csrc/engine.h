@@ -21,9 +21,7 @@ struct StepArgs {
     Common C;
     unsigned int* status;
     unsigned int* ncol;
-    double* bt[2];          // time-averaged apertures of each sweep (box-local faces)
-    int* slist[2];          // work lists of the swept apertures left to phase 2, per sweep
-    unsigned int* scnt[2];  // their lengths
+    double* bt[2];  // time-averaged apertures of each sweep (box-local faces)
     int32_t step_id;
     // time-step reduction of the state after the step
     const double* cfl_alpha;
@@ -35,14 +33,13 @@ struct StepArgs {
 
 // Launch kinds and their block sizes.
 enum LaunchKind {
-    L_POSE, L_V1, L_V2, L_F1, L_F2, L_C1, L_C2,  // geometry of one level
-    L_S1, L_S2, L_BOX, L_DX, L_DY, L_CFL, L_CFLF,  // sweeps and time step
+    L_POSE, L_V1, L_F1, L_C1,  // geometry stages (both level jobs)
+    L_S1, L_BOX, L_DX, L_DY, L_CFL, L_CFLF,  // sweeps and time step
     L_BSPD,  // wave speeds of the box cells after the step (at least one block per member)
     NKINDS
 };
-constexpr int T_WIDE = 256;  // phase 1, phase 2 (4 wavefronts), dense, time step
+constexpr int T_WIDE = 256;  // geometry and aperture stages, dense, time step
 constexpr int T_BOX = 64;    // box phases: a few thousand cells spread over all CUs
-constexpr int ITEMS_PER_BLOCK = T_WIDE / WAVE;
 
 __device__ __forceinline__ int find_unit(const int* __restrict__ off, int n, int b) {
     int lo = 0, hi = n - 1;
@@ -66,21 +63,17 @@ __device__ __forceinline__ Unit unit_of(const int* __restrict__ off, int n) {
 }
 
 // ------------------------------------------------------------------ geometry
-// Geometry launches work on one level job (lev) of every member.
-// Level job lev: pose the polygon; the first thread also clears the job's phase-2 list
-// lengths (and, for the first job, those of both sweeps' aperture lists).
+// Level job lev: pose the polygon (thread t of its vertices).
 __device__ __forceinline__ void pose_body(const StepArgs& a, int lev, int t) {
     const GeoJob& J = a.geo[lev];
-    if (t == 0 && lev == 0) *a.scnt[0] = *a.scnt[1] = 0u;
     if (!J.active) return;
-    if (t == 0) J.cnt[0] = J.cnt[1] = J.cnt[2] = 0u;
     geo_pose(J, t);
 }
 
 __global__ __launch_bounds__(T_WIDE) void kb_geo_pose(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                      int n, int lev) {
+                                                      int n) {
     Unit w = unit_of(off, n);
-    pose_body(A[w.u], lev, w.lb * T_WIDE + threadIdx.x);
+    for (int lev = 0; lev < 2; lev++) pose_body(A[w.u], lev, w.lb * T_WIDE + threadIdx.x);
 }
 
 // Stage arrays of sweep s (the apertures are per sweep, the rest is shared).
@@ -90,23 +83,8 @@ __device__ __forceinline__ Stage stage_of(const StepArgs& a, int s) {
     return S;
 }
 
-template <int K>
-__global__ __launch_bounds__(T_WIDE) void kb_geo_p1(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                    int n, int lev) {
-    Unit w = unit_of(off, n);
-    const StepArgs& a = A[w.u];
-    const GeoJob& J = a.geo[lev];
-    if (!J.active) return;
-    int t = w.lb * T_WIDE + threadIdx.x;
-    bool need;
-    if (K == 0) need = geo_vertices1(a.g, J, t);
-    if (K == 1) need = geo_faces1(a.g, J, t);
-    if (K == 2) need = geo_cells1(a.g, J, t);
-    list_append(J.list, &J.cnt[K], need, t);
-}
-
-// The polygon of a phase-2 block, staged in LDS when it fits (every wavefront of the block
-// walks all its edges for each of its items).
+// The polygon of a block, staged in LDS when it fits (every wavefront of the block walks
+// all its edges for each of its items).
 constexpr int LDS_VERTS = 2048;
 constexpr size_t POLY_LDS = (size_t)2 * LDS_VERTS * sizeof(double);
 __device__ __forceinline__ Poly stage_poly(const Poly& P, double* spoly) {
@@ -119,71 +97,82 @@ __device__ __forceinline__ Poly stage_poly(const Poly& P, double* spoly) {
     return Q;
 }
 
-// Phase-2 items of virtual block lb (of nb) of a level job: one wavefront per item, the
-// polygon staged in LDS.  Every thread of the block calls it (it synchronises the block).
+// Items of one block left to a polygon walk: each wavefront walks its own lanes' items one
+// at a time, all 64 lanes sharing the polygon's edges.  walk(item, lane).
+template <class W>
+__device__ __forceinline__ void walk_left(bool need, int t, W&& walk) {
+    int lane = threadIdx.x & (WAVE - 1);
+    unsigned long long mask = __ballot(need);
+    while (mask) {
+        int l = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        walk(__shfl(t, l, WAVE), lane);
+    }
+}
+
+// Item of lane l of wavefront w among the W wavefronts of a job's nb blocks: lanes take
+// items W apart, so items next to each other (the items left to walks cluster along the
+// boundary) fall to different wavefronts.
+__device__ __forceinline__ int spread_item(int lb, int nb) {
+    int waves = nb * (T_WIDE / WAVE);
+    return (int)(threadIdx.x & (WAVE - 1)) * waves + lb * (T_WIDE / WAVE) + (int)(threadIdx.x / WAVE);
+}
+
+// Stage K of level job lev (0: vertex classes, 1: face intervals, 2: volume fractions; each
+// needs the previous one), block lb of the job's nb: one thread per item.  Items the quick
+// tests leave open on a many-sided polygon are finished by the wavefront that holds them,
+// with the polygon staged in LDS: faces and cells by chain search, vertex classes by walks
+// over all edges.  The whole block calls it.
 template <int K>
-__device__ __forceinline__ void geo_p2_block(const StepArgs& a, int lev, int lb, int nb, double* spoly) {
+__device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int lb, int nb, double* spoly) {
     const GeoJob& J = a.geo[lev];
     if (!J.active) return;
-    int items = (int)J.cnt[K];
-    if (lb * ITEMS_PER_BLOCK >= items) return;  // no item for this block
+    int t = spread_item(lb, nb);
+    bool need = K == 0 ? geo_vertices1(a.g, J, t) : (K == 1 ? geo_faces1(a.g, J, t) : geo_cells1(a.g, J, t));
+    if (!__syncthreads_or(need)) return;
     Poly P = stage_poly(J.L.poly, spoly);
-    int lane = threadIdx.x & (WAVE - 1);
-    for (int it = lb * ITEMS_PER_BLOCK + (threadIdx.x >> 6); it < items; it += nb * ITEMS_PER_BLOCK) {
-        if (K == 0) geo_vertices2(a.g, J, P, it, lane);
-        if (K == 1) geo_faces2(a.g, J, P, it, lane);
-        if (K == 2) geo_cells2(a.g, J, P, it, lane);
-    }
+    walk_left(need, t, [&](int item, int lane) {
+        if (K == 0) geo_vertex_walk(a.g, J, P, item, lane);
+        if (K == 1) geo_face_chain(a.g, J, P, item, lane);
+        if (K == 2) geo_cell_chain(a.g, J, P, item, lane);
+    });
     __syncthreads();  // the staged polygon may be overwritten next
 }
 
+// Stage K of both level jobs of every member.
 template <int K>
-__global__ __launch_bounds__(T_WIDE) void kb_geo_p2(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                    int n, int lev) {
+__global__ __launch_bounds__(T_WIDE) void kb_geo(const StepArgs* __restrict__ A, const int* __restrict__ off, int n) {
     __shared__ double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
-    geo_p2_block<K>(A[w.u], lev, w.lb, w.nb, spoly);
+    for (int lev = 0; lev < 2; lev++) geo_stage_block<K>(A[w.u], lev, w.lb, w.nb, spoly);
 }
 
 // ------------------------------------------------------------------ sweeps
 __device__ __forceinline__ bool box_empty_dev(const Box& B) { return B.i0 >= B.i1 || B.j0 >= B.j1; }
 
-// Swept apertures of sweep s, phase 1 (thread t of the member).
-__device__ __forceinline__ void swept1_body(const StepArgs& a, int s, int t) {
+// Time-averaged apertures of sweep s over the faces of block lb (of nb) of the sweep box;
+// faces left open by the quick tests on a many-sided polygon by their wavefront's chain
+// search.
+__device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, int nb, double* spoly) {
     const SweepJob& J = a.sw[s];
     if (box_empty_dev(J.B)) return;
     Stage S = stage_of(a, s);
+    int t = spread_item(lb, nb);
     bool need = J.dir == 0 ? swept1<0>(a.g, J, a.mot, S, t) : swept1<1>(a.g, J, a.mot, S, t);
-    list_append(a.slist[s], a.scnt[s], need, t);
-}
-
-// Swept apertures of sweep s, phase 2 (virtual block lb of nb; the whole block calls it).
-__device__ __forceinline__ void swept2_block(const StepArgs& a, int s, int lb, int nb, double* spoly) {
-    const SweepJob& J = a.sw[s];
-    if (box_empty_dev(J.B)) return;
-    int items = (int)*a.scnt[s];
-    if (lb * ITEMS_PER_BLOCK >= items) return;  // no item for this block
-    Stage S = stage_of(a, s);
+    if (!__syncthreads_or(need)) return;
     Poly P = stage_poly(J.Ls.poly, spoly);
-    int lane = threadIdx.x & (WAVE - 1);
-    for (int it = lb * ITEMS_PER_BLOCK + (threadIdx.x >> 6); it < items; it += nb * ITEMS_PER_BLOCK) {
-        if (J.dir == 0) swept2<0>(a.g, J, P, a.mot, S, a.slist[s], it, lane);
-        else swept2<1>(a.g, J, P, a.mot, S, a.slist[s], it, lane);
-    }
+    walk_left(need, t, [&](int item, int lane) {
+        if (J.dir == 0) swept_chain<0>(a.g, J, P, a.mot, S, item, lane);
+        else swept_chain<1>(a.g, J, P, a.mot, S, item, lane);
+    });
     __syncthreads();  // the staged polygon may be overwritten next
 }
 
-__global__ __launch_bounds__(T_WIDE) void kb_swept1(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                    int n, int s) {
-    Unit w = unit_of(off, n);
-    swept1_body(A[w.u], s, w.lb * T_WIDE + threadIdx.x);
-}
-
-__global__ __launch_bounds__(T_WIDE) void kb_swept2(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                    int n, int s) {
+__global__ __launch_bounds__(T_WIDE) void kb_swept(const StepArgs* __restrict__ A, const int* __restrict__ off,
+                                                   int n, int s) {
     __shared__ double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
-    swept2_block(A[w.u], s, w.lb, w.nb, spoly);
+    swept_block(A[w.u], s, w.lb, w.nb, spoly);
 }
 
 template <typename R>

@@ -2,15 +2,15 @@
 // the polygon clipping used by the exact time-averaged apertures (Sec. 2.3.4).  The body is
 // a convex polygon.
 //
-// Every quantity is computed in two phases.  Phase 1 gives one thread per item (vertex,
-// face, cell) and settles it when a cheap exact test suffices: outside the polygon's
-// bounding box, inside the inscribed or outside the circumscribed certificate disc, both
-// face end points solid, all four cell faces open or closed, or a polygon of a few edges
-// (then the thread runs the full test itself).  The remaining items, those near the
-// boundary of a many-sided polygon, are appended to a work list, and phase 2 gives each one
-// a 64-lane wavefront that splits the polygon's edges across its lanes.  Both paths
-// evaluate the same formulas; only the order of the area sum differs, and it is fixed per
-// polygon size.
+// One thread per item (vertex, face, cell) settles it when a cheap exact test suffices:
+// outside the polygon's bounding box, inside the inscribed or outside the circumscribed
+// certificate disc, both face end points solid, all four cell faces open or closed.
+// Otherwise a polygon of a few edges is tested edge by edge by the same thread.  For a
+// many-sided polygon the item goes to its thread's wavefront: faces and areas find the few
+// edges that can matter on the polygon's monotone chains (a 64-way search) and share them
+// across the lanes; vertex classes left undecided are walked over all edges.  All paths
+// evaluate the same per-edge formulas; only the order of the area sum differs, and it is
+// fixed per polygon size.
 #pragma once
 #include "cc_device.h"
 
@@ -52,20 +52,6 @@ __device__ __forceinline__ double red_sum(double v) {
 template <int S>
 __device__ __forceinline__ bool red_any(bool v) {
     if constexpr (S == 1) return v; else return __any(v);
-}
-
-// Appends `value` for every lane with `want` to a work list with one atomic per
-// wavefront (ballot, then each lane's rank among the requesting lanes).  Must be reached by
-// all lanes of the wavefront together.
-__device__ __forceinline__ void list_append(int* list, unsigned int* cnt, bool want, int value) {
-    unsigned long long mask = __ballot(want);
-    if (mask == 0ull) return;
-    int lane = threadIdx.x & (WAVE - 1);
-    int leader = __ffsll((long long)mask) - 1;
-    unsigned int base = 0u;
-    if (lane == leader) base = atomicAdd(cnt, (unsigned int)__popcll(mask));
-    base = __shfl(base, leader, WAVE);
-    if (want) list[base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull))] = value;
 }
 
 // ------------------------------------------------------------------ certificate discs
@@ -197,6 +183,51 @@ __device__ double poly_right_solid(const Poly& P, double ox, double oy, double w
     return hi > lo ? hi - lo : 0.0;
 }
 
+// Contribution of edge (a, b) (coordinates relative to the rectangle's corner) to the
+// integral of x dy over the part of the polygon boundary inside the rectangle [0, w] x
+// [0, h]: the edge clipped with Liang-Barsky, a clipped end point that lies on a rectangle
+// side set exactly to that side; 0 for an edge outside (or lying on the right side, which
+// the side term covers).
+__device__ __forceinline__ double edge_area(double ax, double ay, double bx, double by, double w, double h) {
+    if (fmax(ax, bx) < 0.0 || fmin(ax, bx) > w || fmax(ay, by) < 0.0 || fmin(ay, by) > h) return 0.0;
+    double dx = bx - ax, dy = by - ay;
+    double t0 = 0.0, t1 = 1.0;
+    int s0 = -1, s1 = -1;
+    double pq[4][2] = {{-dx, ax}, {dx, w - ax}, {-dy, ay}, {dy, h - ay}};
+    bool rej = false;
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        double p = pq[s][0], q = pq[s][1];
+        if (p == 0.0) {
+            if (q < 0.0 || (s == 1 && q == 0.0)) rej = true;
+        } else {
+            double t = q / p;
+            if (p < 0.0) {
+                if (t > t0) {
+                    t0 = t;
+                    s0 = s;
+                }
+            } else {
+                if (t < t1) {
+                    t1 = t;
+                    s1 = s;
+                }
+            }
+        }
+    }
+    if (rej || !(t0 < t1)) return 0.0;
+    double x0 = ax + t0 * dx, y0 = ay + t0 * dy;
+    double x1 = ax + t1 * dx, y1 = ay + t1 * dy;
+    const double side[4] = {0.0, w, 0.0, h};
+    if (s0 >= 0) {
+        if (s0 < 2) x0 = side[s0]; else y0 = side[s0];
+    }
+    if (s1 >= 0) {
+        if (s1 < 2) x1 = side[s1]; else y1 = side[s1];
+    }
+    return 0.5 * (x0 + x1) * (y1 - y0);
+}
+
 // Area of the polygon inside the rectangle [ox, ox+w] x [oy, oy+h] by Green's theorem:
 // the integral of x dy over the part of the polygon boundary inside the rectangle (each
 // edge clipped with Liang-Barsky in coordinates relative to (ox, oy); the coordinate of a
@@ -210,47 +241,146 @@ __device__ double poly_clip_area(const Poly& P, double ox, double oy, double w, 
     const double* v = P.v;
     for (int k = lane; k < P.m; k += S) {
         int k1 = k + 1 == P.m ? 0 : k + 1;
-        double ax = v[2 * k] - ox, ay = v[2 * k + 1] - oy;
-        double bx = v[2 * k1] - ox, by = v[2 * k1 + 1] - oy;
-        if (fmax(ax, bx) < 0.0 || fmin(ax, bx) > w || fmax(ay, by) < 0.0 || fmin(ay, by) > h) continue;
-        double dx = bx - ax, dy = by - ay;
-        double t0 = 0.0, t1 = 1.0;
-        int s0 = -1, s1 = -1;
-        double pq[4][2] = {{-dx, ax}, {dx, w - ax}, {-dy, ay}, {dy, h - ay}};
-        bool rej = false;
-#pragma unroll
-        for (int s = 0; s < 4; s++) {
-            double p = pq[s][0], q = pq[s][1];
-            if (p == 0.0) {
-                if (q < 0.0 || (s == 1 && q == 0.0)) rej = true;
-            } else {
-                double t = q / p;
-                if (p < 0.0) {
-                    if (t > t0) {
-                        t0 = t;
-                        s0 = s;
-                    }
-                } else {
-                    if (t < t1) {
-                        t1 = t;
-                        s1 = s;
-                    }
-                }
-            }
-        }
-        if (rej || !(t0 < t1)) continue;
-        double x0 = ax + t0 * dx, y0 = ay + t0 * dy;
-        double x1 = ax + t1 * dx, y1 = ay + t1 * dy;
-        const double side[4] = {0.0, w, 0.0, h};
-        if (s0 >= 0) {
-            if (s0 < 2) x0 = side[s0]; else y0 = side[s0];
-        }
-        if (s1 >= 0) {
-            if (s1 < 2) x1 = side[s1]; else y1 = side[s1];
-        }
-        acc += 0.5 * (x0 + x1) * (y1 - y0);
+        acc += edge_area(v[2 * k] - ox, v[2 * k + 1] - oy, v[2 * k1] - ox, v[2 * k1 + 1] - oy, w, h);
     }
     return red_sum<S>(acc) + w * right_solid;
+}
+
+// ------------------------------------------------------------------ chains of a polygon
+// Position p of the chain that starts at vertex a: vertex (a + p) mod m.
+__device__ __forceinline__ int chain_vertex(const Poly& P, int a, int p) {
+    int k = a + p;
+    return k >= P.m ? k - P.m : k;
+}
+__device__ __forceinline__ int chain_edges(const Poly& P, int a, int b) {
+    int d = b - a;
+    return d < 0 ? d + P.m : d;
+}
+// First position q in [0, len] of the chain from vertex a at which pred(vertex) holds, for
+// a predicate that is false and then true along the chain; len + 1 when it never holds.
+// The 64 lanes of the wavefront test 64 positions per round and narrow the range to the
+// gap between the last false and the first true one (two or three rounds for a polygon of
+// up to 4096 vertices).  Every lane of the wavefront calls it with the same arguments.
+template <class F>
+__device__ __forceinline__ int chain_first(const Poly& P, int a, int len, int lane, F&& pred) {
+    int lo = 0, hi = len + 1;  // the answer lies in [lo, hi]; hi stands for "true"
+    while (lo < hi) {
+        int span = hi - lo;
+        int step = (span + WAVE - 1) / WAVE;
+        int p = lo + lane * step;
+        bool t = p < hi && pred(chain_vertex(P, a, p));
+        unsigned long long mask = __ballot(t);
+        int tested = (span - 1) / step;  // highest lane with a position below hi
+        if (mask == 0ull) {
+            lo = lo + tested * step + 1;
+        } else {
+            int f = __ffsll((long long)mask) - 1;
+            int pf = lo + f * step;
+            lo = f == 0 ? lo : lo + (f - 1) * step + 1;
+            hi = pf;
+        }
+    }
+    return lo;
+}
+
+// poly_clip_area of a many-sided polygon by one wavefront: only the edges whose y-range
+// meets the rectangle's can contribute to the edge integral (the others give exactly 0),
+// and on each y-monotone chain they form one run, found by the same tests; the lanes
+// share the run's edges.  The right side's crossings are the one sign change of x < w on
+// each x-monotone chain.  Every lane calls it; all get the area.
+__device__ double poly_clip_area_chains(const Poly& P, double ox, double oy, double w, double h, int lane) {
+    const double* v = P.v;
+    auto X = [&](int k) { return v[2 * k] - ox; };
+    auto Y = [&](int k) { return v[2 * k + 1] - oy; };
+    // right side: lower chain il -> ir (x rising), upper chain ir -> il (x falling)
+    double yb = -INFINITY, yt = INFINITY;
+    int found = 0;
+    for (int chain = 0; chain < 2; chain++) {
+        int a = chain == 0 ? P.il : P.ir, b = chain == 0 ? P.ir : P.il;
+        int len = chain_edges(P, a, b);
+        int q = chain_first(P, a, len, lane, [&](int k) { return chain == 0 ? !(X(k) < w) : X(k) < w; });
+        if (q > 0 && q <= len) {
+            int k = chain_vertex(P, a, q - 1), k1 = chain_vertex(P, a, q);
+            double ax = X(k), ay = Y(k), dx = X(k1) - ax, dy = Y(k1) - ay;
+            double t = (w - ax) / dx;
+            double y = ay + t * dy;
+            found = 1;
+            if (dx > 0.0) yb = fmax(yb, y);
+            else yt = fmin(yt, y);
+        }
+    }
+    double right_solid = 0.0;
+    if (found) {
+        double lo = fmax(0.0, yb), hi = fmin(h, yt);
+        right_solid = hi > lo ? hi - lo : 0.0;
+    }
+    double acc = 0.0;
+    for (int chain = 0; chain < 2; chain++) {
+        // right chain ib -> it (y rising): from the first edge whose end reaches y >= 0 to the
+        // last whose start has y <= h; left chain it -> ib (y falling): from the first edge
+        // whose end has y <= h to the last whose start has y >= 0
+        int a = chain == 0 ? P.ib : P.it, b = chain == 0 ? P.it : P.ib;
+        int len = chain_edges(P, a, b);
+        int q0 = chain_first(P, a, len, lane, [&](int k) { return chain == 0 ? !(Y(k) < 0.0) : !(Y(k) > h); });
+        int q1 = chain_first(P, a, len, lane, [&](int k) { return chain == 0 ? Y(k) > h : Y(k) < 0.0; });
+        int p0 = q0 > 0 ? q0 - 1 : 0, p1 = q1 - 1 < len - 1 ? q1 - 1 : len - 1;
+        for (int p = p0 + lane; p <= p1; p += WAVE) {
+            int k = chain_vertex(P, a, p), k1 = chain_vertex(P, a, p + 1);
+            acc += edge_area(X(k), Y(k), X(k1), Y(k1), w, h);
+        }
+    }
+    return red_sum<WAVE>(acc) + w * right_solid;
+}
+
+// poly_seg_clip of a many-sided polygon and an axis-aligned segment (a face) by one
+// wavefront: the binding edges are those where the segment's line crosses the boundary
+// (the sign change of the coordinate test on each monotone chain) and their neighbours;
+// when the line meets no chain there (it touches the polygon's extreme side), the full
+// edge loop decides.  Every lane calls it; all get the interval.
+__device__ double2 poly_seg_clip_chains(const Poly& P, double ax, double ay, double bx, double by, int lane) {
+    const double* v = P.v;
+    bool vertical = ax == bx;  // x-face: the line x = ax; y-face: the line y = ay
+    double c = vertical ? ax : ay;
+    int cand[2] = {-1, -1};
+    for (int chain = 0; chain < 2; chain++) {
+        int a, b;
+        if (vertical) {
+            a = chain == 0 ? P.il : P.ir;
+            b = chain == 0 ? P.ir : P.il;
+        } else {
+            a = chain == 0 ? P.ib : P.it;
+            b = chain == 0 ? P.it : P.ib;
+        }
+        int len = chain_edges(P, a, b);
+        int q = chain_first(P, a, len, lane, [&](int k) {
+            bool below = (vertical ? v[2 * k] : v[2 * k + 1]) < c;
+            return chain == 0 ? !below : below;
+        });
+        if (q > 0 && q <= len) cand[chain] = chain_vertex(P, a, q - 1);
+    }
+    if (cand[0] < 0 && cand[1] < 0) return poly_seg_clip<WAVE>(P, ax, ay, bx, by, lane);
+    // lanes 0-2: the crossing edge of the first chain and its neighbours; lanes 3-5: the second
+    double tl = 0.0, th = 1.0;
+    int rej = 0;
+    if (lane < 6 && cand[lane / 3] >= 0) {
+        int k = cand[lane / 3] + (lane % 3) - 1;
+        k = k < 0 ? k + P.m : (k >= P.m ? k - P.m : k);
+        int k1 = k + 1 == P.m ? 0 : k + 1;
+        double ex = v[2 * k], ey = v[2 * k + 1], fx = v[2 * k1], fy = v[2 * k1 + 1];
+        double g0 = orient(ex, ey, fx, fy, ax, ay), g1 = orient(ex, ey, fx, fy, bx, by);
+        if (g0 < 0.0 && g1 < 0.0) {
+            rej = 1;
+        } else if (!(g0 >= 0.0 && g1 >= 0.0)) {
+            double t = g0 / (g0 - g1);
+            if (g0 < 0.0) tl = t;
+            else th = t;
+        }
+    }
+    if (red_any<WAVE>(rej)) return make_double2(0.0, 0.0);
+    tl = red_max<WAVE>(tl);
+    th = red_min<WAVE>(th);
+    if (!(tl < th)) return make_double2(0.0, 0.0);
+    return make_double2(tl, th);
 }
 
 // ------------------------------------------------------------------ one level
@@ -261,8 +391,6 @@ __device__ double poly_clip_area(const Poly& P, double ox, double oy, double w, 
 struct GeoJob {
     Level L;
     Box reg;
-    int* list;      // work list of the items left to phase 2
-    unsigned* cnt;  // [0] vertices, [1] faces, [2] cells left to phase 2
     const double* body;             // body-frame vertices (2 m)
     double cs_x, sn_x, cx_x;        // pose giving the x coordinates: cs bx - sn by + cx
     double cs_y, sn_y, cy_y;        // pose giving the y coordinates: sn bx + cs by + cy
@@ -292,8 +420,8 @@ __device__ __forceinline__ bool geo_vertices1(const Grid& g, const GeoJob& J, in
     J.L.vcls[(size_t)j * (g.nx + 1) + i] = (int8_t)c;
     return false;
 }
-__device__ __forceinline__ void geo_vertices2(const Grid& g, const GeoJob& J, const Poly& P, int item, int lane) {
-    int t = J.list[item];
+// Phase 2 of item t (one wavefront walks the polygon; the lanes share its edges).
+__device__ __forceinline__ void geo_vertex_walk(const Grid& g, const GeoJob& J, const Poly& P, int t, int lane) {
     int vw = J.reg.w() + 1;
     int i = J.reg.i0 + t % vw, j = J.reg.j0 + t / vw;
     int c = poly_classify<WAVE>(P, vx_of(g, i), vy_of(g, j), lane);
@@ -331,6 +459,7 @@ __device__ __forceinline__ void geo_store_face(const Grid& g, const GeoJob& J, b
     if (xf) J.L.fx[(size_t)j * (g.nx + 1) + i] = iv;
     else J.L.fy[(size_t)j * g.nx + i] = iv;
 }
+// Face interval of item t: true = left to the chain search of a many-sided polygon.
 __device__ __forceinline__ bool geo_faces1(const Grid& g, const GeoJob& J, int t) {
     if (t >= geo_nfaces(J.reg)) return false;
     bool xf;
@@ -345,19 +474,20 @@ __device__ __forceinline__ bool geo_faces1(const Grid& g, const GeoJob& J, int t
     geo_store_face(g, J, xf, i, j, iv);
     return false;
 }
-__device__ __forceinline__ void geo_faces2(const Grid& g, const GeoJob& J, const Poly& P, int item, int lane) {
-    int t = J.list[item];
+// The same face by one wavefront's chain search on P (the polygon, possibly staged in LDS;
+// every lane calls it).
+__device__ __forceinline__ void geo_face_chain(const Grid& g, const GeoJob& J, const Poly& P, int t, int lane) {
     bool xf;
     int i, j, ca, cb;
     double ax, ay, bx, by;
     geo_face_ends(g, J, t, xf, i, j, ax, ay, ca, bx, by, cb);
-    double2 iv = poly_seg_clip<WAVE>(P, ax, ay, bx, by, lane);
+    double2 iv = poly_seg_clip_chains(P, ax, ay, bx, by, lane);
     if (lane == 0) geo_store_face(g, J, xf, i, j, iv);
 }
 
 // Volume fractions: open when all four faces are open, closed when all four are closed,
 // otherwise 1 - (polygon area in the cell)/(hx hy); cut cells below the small-cell
-// threshold count as solid.
+// threshold count as solid.  true = left to the chain search of a many-sided polygon.
 __device__ __forceinline__ double alpha_of_area(const Grid& g, double s) {
     double a = 1.0 - s / (g.hx * g.hy);
     if (a < 0.0) a = 0.0;
@@ -390,12 +520,12 @@ __device__ __forceinline__ bool geo_cells1(const Grid& g, const GeoJob& J, int t
     L.alpha[(size_t)j * g.nx + i] = a;
     return false;
 }
-__device__ __forceinline__ void geo_cells2(const Grid& g, const GeoJob& J, const Poly& P, int item, int lane) {
-    int t = J.list[item];
+// The same cell by one wavefront's chain search on P (every lane calls it).
+__device__ __forceinline__ void geo_cell_chain(const Grid& g, const GeoJob& J, const Poly& P, int t, int lane) {
     int cw = J.reg.w();
     int i = J.reg.i0 + t % cw, j = J.reg.j0 + t / cw;
-    double a = alpha_of_area(g, poly_clip_area<WAVE>(P, vx_of(g, i), vy_of(g, j), g.hx, g.hy, lane));
-    if (lane == 0) J.L.alpha[(size_t)j * g.nx + i] = a;
+    double s = poly_clip_area_chains(P, vx_of(g, i), vy_of(g, j), g.hx, g.hy, lane);
+    if (lane == 0) J.L.alpha[(size_t)j * g.nx + i] = alpha_of_area(g, s);
 }
 
 }  // namespace cc

@@ -1,10 +1,9 @@
 // One persistent launch per sweep over every member of a batch.  The launch's blocks are all
 // resident at once (the host sizes the grid from the kernel's occupancy), so the phases of
 // a sweep are separated by grid-wide barriers instead of kernel boundaries:
-//   sweep 0: pose both level jobs | vertex classes (quick) | vertex classes (polygon walks)
-//            | faces (quick) | faces (walks) | cells (quick) + swept apertures of both sweeps
-//            (quick) | cells (walks) + swept apertures (walks) | stage and wall | patch |
-//            cover | collapse round 1 | collapse round 2
+//   sweep 0: pose both level jobs | vertex classes | face intervals | volume fractions and
+//            the swept apertures of both sweeps | stage and wall | patch | cover | collapse
+//            round 1 | collapse round 2
 //   sweep 1: stage and wall | patch | cover | collapse rounds | wave speeds of the box cells
 // Each barrier has its own arrival counter.  Only the leading blocks that have work in the
 // next phase wait at a barrier; every other block arrives and moves on.  The dense tiles of
@@ -186,42 +185,16 @@ __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
             each_wide(p, L_POSE, [&](const StepArgs& a, int lb, int) { pose_body(a, lev, lb * T_WIDE + tid); });
         { int nx_ = busy(wide_ext(p, L_V1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
         for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_V1, [&](const StepArgs& a, int lb, int) {
-                const GeoJob& J = a.geo[lev];
-                if (!J.active) return;
-                int t = lb * T_WIDE + tid;
-                list_append(J.list, &J.cnt[0], geo_vertices1(a.g, J, t), t);
-            });
-        { int nx_ = busy(wide_ext(p, L_V2)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
-        for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_V2, [&](const StepArgs& a, int lb, int nb) { geo_p2_block<0>(a, lev, lb, nb, spoly); });
+            each_wide(p, L_V1, [&](const StepArgs& a, int lb, int nb) { geo_stage_block<0>(a, lev, lb, nb, spoly); });
         { int nx_ = busy(wide_ext(p, L_F1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
         for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_F1, [&](const StepArgs& a, int lb, int) {
-                const GeoJob& J = a.geo[lev];
-                if (!J.active) return;
-                int t = lb * T_WIDE + tid;
-                list_append(J.list, &J.cnt[1], geo_faces1(a.g, J, t), t);
-            });
-        { int nx_ = busy(wide_ext(p, L_F2)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
-        for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_F2, [&](const StepArgs& a, int lb, int nb) { geo_p2_block<1>(a, lev, lb, nb, spoly); });
+            each_wide(p, L_F1, [&](const StepArgs& a, int lb, int nb) { geo_stage_block<1>(a, lev, lb, nb, spoly); });
         { int nx_ = busy(imax(wide_ext(p, L_C1), wide_ext(p, L_S1))); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
         // cells, and the apertures of both sweeps (they need the faces of all three levels)
         for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_C1, [&](const StepArgs& a, int lb, int) {
-                const GeoJob& J = a.geo[lev];
-                if (!J.active) return;
-                int t = lb * T_WIDE + tid;
-                list_append(J.list, &J.cnt[2], geo_cells1(a.g, J, t), t);
-            });
+            each_wide(p, L_C1, [&](const StepArgs& a, int lb, int nb) { geo_stage_block<2>(a, lev, lb, nb, spoly); });
         for (int sw = 0; sw < 2; sw++)
-            each_wide(p, L_S1, [&](const StepArgs& a, int lb, int) { swept1_body(a, sw, lb * T_WIDE + tid); });
-        { int nx_ = busy(imax(wide_ext(p, L_C2), wide_ext(p, L_S2))); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
-        for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_C2, [&](const StepArgs& a, int lb, int nb) { geo_p2_block<2>(a, lev, lb, nb, spoly); });
-        for (int sw = 0; sw < 2; sw++)
-            each_wide(p, L_S2, [&](const StepArgs& a, int lb, int nb) { swept2_block(a, sw, lb, nb, spoly); });
+            each_wide(p, L_S1, [&](const StepArgs& a, int lb, int nb) { swept_block(a, sw, lb, nb, spoly); });
         { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
     }
     each_box(p, [&](const StepArgs& a, int t) { stagewall_body<R>(a, s, t); });

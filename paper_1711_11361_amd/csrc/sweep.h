@@ -132,8 +132,8 @@ __device__ __forceinline__ double strip_beta(double a, const Strip& st) {
     return r;
 }
 
-// Phase 1: thread t over the box's faces normal to the sweep direction; true = left to
-// phase 2.
+// Thread t over the box's faces normal to the sweep direction; true = left to the chain
+// search of a many-sided polygon.
 template <int D>
 __device__ bool swept1(const Grid& g, const SweepJob& J, const Motion& M, const Stage& S, int t) {
     const Box& B = J.B;
@@ -150,19 +150,19 @@ __device__ bool swept1(const Grid& g, const SweepJob& J, const Motion& M, const 
     return false;
 }
 
-// Phase 2: one wavefront per listed face (P: the start polygon, possibly staged in LDS).
+// The same face of a many-sided start polygon P (possibly staged in LDS) by one
+// wavefront's chain search (every lane calls it).
 template <int D>
-__device__ void swept2(const Grid& g, const SweepJob& J, const Poly& P, const Motion& M, const Stage& S,
-                       const int* list, int item, int lane) {
+__device__ void swept_chain(const Grid& g, const SweepJob& J, const Poly& P, const Motion& M, const Stage& S, int t,
+                            int lane) {
     const Box& B = J.B;
     int fw = D == 0 ? B.w() + 1 : B.w();
-    int t = list[item];
     int i = B.i0 + t % fw, j = B.j0 + t / fw;
     double r;
     Strip st;
     swept_quick<D>(g, J, M, i, j, r, st);
-    r = strip_beta(poly_clip_area<WAVE>(P, st.x0, st.y0, st.sw, st.sh, lane), st);
-    if (lane == 0) S.bt[fidx<D>(B, i, j)] = r;
+    double a = poly_clip_area_chains(P, st.x0, st.y0, st.sw, st.sh, lane);
+    if (lane == 0) S.bt[fidx<D>(B, i, j)] = strip_beta(a, st);
 }
 
 // ------------------------------------------------------------------ stage (donations)
