@@ -547,11 +547,13 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     // wavefront's chain search: enough wavefronts that most of them get at most one
     size_t walkers = m > SMALL_POLY ? std::min<size_t>(256, (size_t)(L.gw + L.gh)) : 0;
     auto stage = [&](size_t items) { return (int)std::max<size_t>(nblk(items, T_WIDE), walkers); };
+    // the geometry stages run both level jobs side by side, each on its own half
+    auto both = [&](size_t items) { return 2 * stage(items); };
     switch (kind) {
         case L_POSE: return (int)nblk((size_t)m, T_WIDE);
-        case L_V1: return stage(gv);
-        case L_F1: return stage(gf);
-        case L_C1: return stage(gc);
+        case L_V1: return both(gv);
+        case L_F1: return both(gf);
+        case L_C1: return both(gc);
         case L_S1: return stage(sf);
         case L_BOX: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);

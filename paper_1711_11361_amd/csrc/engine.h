@@ -139,12 +139,21 @@ __device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int 
     __syncthreads();  // the staged polygon may be overwritten next
 }
 
+// Stage K of both level jobs of a member: the first half of its nb blocks works on level
+// job 0, the second half on job 1 (the whole block calls it).
+template <int K>
+__device__ __forceinline__ void geo_stage_split(const StepArgs& a, int lb, int nb, double* spoly) {
+    int half = nb >> 1;
+    int lev = lb >= half ? 1 : 0;
+    geo_stage_block<K>(a, lev, lb - lev * half, half, spoly);
+}
+
 // Stage K of both level jobs of every member.
 template <int K>
 __global__ __launch_bounds__(T_WIDE) void kb_geo(const StepArgs* __restrict__ A, const int* __restrict__ off, int n) {
     __shared__ double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
-    for (int lev = 0; lev < 2; lev++) geo_stage_block<K>(A[w.u], lev, w.lb, w.nb, spoly);
+    geo_stage_split<K>(A[w.u], w.lb, w.nb, spoly);
 }
 
 // ------------------------------------------------------------------ sweeps

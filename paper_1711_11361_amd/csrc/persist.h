@@ -184,15 +184,12 @@ __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
         for (int lev = 0; lev < 2; lev++)
             each_wide(p, L_POSE, [&](const StepArgs& a, int lb, int) { pose_body(a, lev, lb * T_WIDE + tid); });
         { int nx_ = busy(wide_ext(p, L_V1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
-        for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_V1, [&](const StepArgs& a, int lb, int nb) { geo_stage_block<0>(a, lev, lb, nb, spoly); });
+        each_wide(p, L_V1, [&](const StepArgs& a, int lb, int nb) { geo_stage_split<0>(a, lb, nb, spoly); });
         { int nx_ = busy(wide_ext(p, L_F1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
-        for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_F1, [&](const StepArgs& a, int lb, int nb) { geo_stage_block<1>(a, lev, lb, nb, spoly); });
+        each_wide(p, L_F1, [&](const StepArgs& a, int lb, int nb) { geo_stage_split<1>(a, lb, nb, spoly); });
         { int nx_ = busy(imax(wide_ext(p, L_C1), wide_ext(p, L_S1))); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
         // cells, and the apertures of both sweeps (they need the faces of all three levels)
-        for (int lev = 0; lev < 2; lev++)
-            each_wide(p, L_C1, [&](const StepArgs& a, int lb, int nb) { geo_stage_block<2>(a, lev, lb, nb, spoly); });
+        each_wide(p, L_C1, [&](const StepArgs& a, int lb, int nb) { geo_stage_split<2>(a, lb, nb, spoly); });
         for (int sw = 0; sw < 2; sw++)
             each_wide(p, L_S1, [&](const StepArgs& a, int lb, int nb) { swept_block(a, sw, lb, nb, spoly); });
         { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
