@@ -26,7 +26,6 @@ constexpr size_t ALIGN = 256;
 constexpr int NPART = 1024;  // blocks of the deterministic sum
 constexpr int TPB = 256;
 constexpr int CFL_MAX_BLOCKS = 512;
-constexpr size_t SPEED_BYTES = 2 * SPEED_SLOTS * sizeof(unsigned long long);  // speed slots of one instance
 
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -65,6 +64,7 @@ struct Layout {
     size_t off_smax, off_status, off_ncol, off_part, off_tot, off_spd;
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
+    int spd_dense;   // partial speed pairs reserved for dense tiles (the most any tile shape uses)
     int gw, gh;      // geometry-region capacity (cells)
 };
 
@@ -138,7 +138,8 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_ncol = take(4);
     L.off_part = take(std::max<size_t>(4 * NPART * 8, 2 * CFL_MAX_BLOCKS * 8));
     L.off_tot = take(4 * 8);
-    L.off_spd = take(2 * SPEED_SLOTS * 8);
+    L.spd_dense = std::max(dense_blocks(0, 0, c->nx, c->ny), dense_blocks(1, 0, c->nx, c->ny));
+    L.off_spd = take((size_t)2 * 8 * ((size_t)L.spd_dense + (std::max<size_t>(L.cap, 1) + T_BOX - 1) / T_BOX));
     L.total = o;
     return L;
 }
@@ -403,6 +404,7 @@ void base_args(cc_ctx* c, StepArgs& a) {
     a.cfl_part = at<unsigned long long>(c, c->lay.off_part);
     a.cfl_out = at<unsigned long long>(c, c->lay.off_cflout);
     a.spd = at<unsigned long long>(c, c->lay.off_spd);
+    a.spd_dense = c->lay.spd_dense;
     for (int k = 0; k < 2; k++) {
         GeoJob& J = a.geo[k];
         J.body = at<double>(c, c->lay.off_body);
@@ -698,7 +700,7 @@ hipError_t engine_alloc_host(Engine& E) {
         e = hipHostMalloc((void**)&E.h_args[b], sizeof(StepArgs) * E.cap_n, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&E.ev[b], hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, SPEED_BYTES * E.cap_n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, 16 * E.cap_n, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_gather, 8 * E.cap_n, hipHostMallocDefault);
     int dev = 0, khz = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
@@ -778,17 +780,18 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
         (void)launch_persist<R>(E, s, 1);
     } else {
         launch_geometry(E, s);
-        // the first sweep's dense kernel clears the time-step maxima, the second folds the
-        // new state's wave speeds into them; the box cells follow in their own launch
+        // the second sweep's dense tiles and the box blocks leave partial maxima of the new
+        // state's wave speeds; one block per member combines them
         for (int sw = 0; sw < 2; sw++) {
             launch_box_pre<R>(E, s, sw);
-            launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw == 0 ? 1 : 2);
+            launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw);
             launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1);
         }
-        klaunch(kb_box_speeds<R>, ktotal(E, L_BSPD), T_BOX, s, (const StepArgs*)E.d_args, koff(E, L_BSPD), n,
-                E.d_gather);
+        klaunch(kb_box_speeds<R>, ktotal(E, L_BSPD), T_BOX, s, (const StepArgs*)E.d_args, koff(E, L_BSPD), n);
+        klaunch(kb_speed_combine, n, 256, s, (const StepArgs*)E.d_args, koff(E, L_DX), koff(E, L_DY),
+                koff(E, L_BSPD), E.d_gather);
     }
-    (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, SPEED_BYTES * (size_t)n, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(E.h_gather, E.d_gather, 8 * (size_t)n, hipMemcpyDeviceToHost, s);
 }
 
@@ -897,7 +900,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     E.mem = {c};
     E.d_args = at<StepArgs>(c, lay.off_args);
     E.d_off = at<int>(c, lay.off_offs);
-    E.d_cflout = at<unsigned long long>(c, lay.off_spd);
+    E.d_cflout = at<unsigned long long>(c, lay.off_cflout);
     E.d_gather = at<unsigned int>(c, lay.off_gather);
     E.d_sync = at<GridSync>(c, lay.off_sync);
     E.tile_x = 0;  // one row per x-sweep block
@@ -920,7 +923,6 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         e = hipMemcpyAsync(at<double>(c, lay.off_body), c->bverts.data(), 16 * (size_t)c->m, hipMemcpyHostToDevice,
                            c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_sync, 0, sizeof(GridSync), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_spd, 0, 2 * SPEED_SLOTS * 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_nbad, 0, 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_smax, 0, 16, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_status, 0, 4, c->stream);
@@ -1227,18 +1229,6 @@ cc_status cc_step(cc_ctx* c, double dt) {
 
 namespace {
 
-// Maximum over an instance's speed slots read back by a captured step (bit patterns of
-// non-negative doubles order like the values).
-void slot_speeds(const unsigned long long* slots, double& sx, double& sy) {
-    unsigned long long bx = 0ull, by = 0ull;
-    for (int k = 0; k < SPEED_SLOTS; k++) {
-        bx = std::max(bx, slots[2 * k]);
-        by = std::max(by, slots[2 * k + 1]);
-    }
-    std::memcpy(&sx, &bx, 8);
-    std::memcpy(&sy, &by, 8);
-}
-
 // Wave speeds (bit patterns from the reduction) plus the body's vertex speeds -> dt.
 double dt_from_speeds(cc_ctx* c, double cfl, double sx, double sy) {
     if (c->m > 0) {
@@ -1275,7 +1265,8 @@ cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
     if (c->speeds_ready && !c->batch) {  // reduced and read back by the last captured step
         HIPCHK(c, hipEventSynchronize(c->eng.ev[c->speeds_buf]));
         double sx, sy;
-        slot_speeds(c->eng.h_cflout, sx, sy);
+        std::memcpy(&sx, &c->eng.h_cflout[0], 8);
+        std::memcpy(&sy, &c->eng.h_cflout[1], 8);
         cc_status st = status_error(c, c->eng.h_gather[0], sx, sy);
         if (st != CC_OK) return st;
         *h_dt = dt_from_speeds(c, cfl, sx, sy);
@@ -1478,7 +1469,7 @@ cc_status cc_timing_read(cc_ctx* c, double* h_out, int32_t n) {
 size_t cc_batch_workspace_bytes(int32_t max_instances) {
     if (max_instances < 1) return 0;
     size_t n = (size_t)max_instances;
-    return up(n * sizeof(StepArgs)) + up((size_t)NKINDS * (2 * n + 1) * sizeof(int)) + up(SPEED_BYTES * n) + up(8 * n) +
+    return up(n * sizeof(StepArgs)) + up((size_t)NKINDS * (2 * n + 1) * sizeof(int)) + up(16 * n) + up(8 * n) +
            up(sizeof(GridSync));
 }
 
@@ -1500,7 +1491,7 @@ cc_status cc_batch_create(int32_t max_instances, int32_t precision, void* d_ws, 
     E.d_off = (int*)(b->ws + o);
     o += up((size_t)NKINDS * (2 * n + 1) * sizeof(int));
     E.d_cflout = (unsigned long long*)(b->ws + o);
-    o += up(SPEED_BYTES * n);
+    o += up(16 * n);
     E.d_gather = (unsigned int*)(b->ws + o);
     o += up(8 * n);
     E.d_sync = (GridSync*)(b->ws + o);
@@ -1589,7 +1580,7 @@ cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
             return st;
         }
         // the members' results land in the batch's gather arrays
-        E.h_args[buf][k].spd = E.d_cflout + 2 * SPEED_SLOTS * k;
+        E.h_args[buf][k].cfl_out = E.d_cflout + 2 * k;
     }
     hipError_t e = E.prec == CC_FP32_GEOM64 ? engine_graph_step<float>(E, b->stream, buf, -1)
                                             : engine_graph_step<double>(E, b->stream, buf, -1);
@@ -1628,7 +1619,8 @@ cc_status cc_batch_last_dt(cc_batch* b, double cfl, double* h_dt, int32_t* h_sta
     for (size_t k = 0; k < E.mem.size(); k++) {
         cc_ctx* c = E.mem[k];
         double sx, sy;
-        slot_speeds(E.h_cflout + 2 * SPEED_SLOTS * k, sx, sy);
+        std::memcpy(&sx, &E.h_cflout[2 * k], 8);
+        std::memcpy(&sy, &E.h_cflout[2 * k + 1], 8);
         unsigned int st = E.h_gather[2 * k];
         if (h_status) h_status[k] = (int32_t)st;
         cc_status r = status_error(c, st, sx, sy);

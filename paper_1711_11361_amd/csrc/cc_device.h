@@ -209,6 +209,38 @@ __device__ __forceinline__ void muscl32(const float qm[4], const float q[4], con
     }
 }
 
+// Signal speeds |u|+a and |v|+a of a stored state u (conserved per cell volume) with volume
+// fraction alpha, as bit patterns of non-negative doubles (they order like the values; NaN
+// maps above infinity); 0 for cells without gas.  A regular cell (alpha 1) is evaluated in
+// the state's precision, a cut cell in FP64 from U / alpha.  Every time-step reduction uses
+// this one rule, so their maxima agree bit for bit.
+template <typename R>
+__device__ __forceinline__ void speed_bits(const R u[4], double alpha, double gam, unsigned long long& bx,
+                                           unsigned long long& by) {
+    bx = by = 0ull;
+    if (!(alpha > 0.0) || !((double)u[0] > 0.0)) return;
+    double sx, sy;
+    if (alpha == 1.0) {
+        R g = (R)gam;
+        R uu = qdiv(u[1], u[0]), vv = qdiv(u[2], u[0]);
+        R c = qsqrt(qdiv(g * pressure(u, g), u[0]));
+        sx = (double)(fabs(uu) + c);
+        sy = (double)(fabs(vv) + c);
+    } else {
+        double q[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) q[m] = (double)u[m] / alpha;
+        double uu = q[1] / q[0], vv = q[2] / q[0];
+        double c = sqrt(gam * pressure(q, gam) / q[0]);
+        sx = fabs(uu) + c;
+        sy = fabs(vv) + c;
+    }
+    bx = __double_as_longlong(sx);
+    by = __double_as_longlong(sy);
+    if (sx != sx) bx = 0x7ff8000000000000ull;
+    if (sy != sy) by = 0x7ff8000000000000ull;
+}
+
 // HLLC flux with Davis wave-speed estimates.  The two star-region cases share one code
 // path on the upwind side's values (same operations as writing them out per side).
 template <typename T, int D>

@@ -28,7 +28,8 @@ struct StepArgs {
     const void* cfl_U;
     unsigned long long* cfl_part;  // 2 per block
     unsigned long long* cfl_out;   // 2: max (|u|+a) along x and y, as bit patterns
-    unsigned long long* spd;       // 2 x SPEED_SLOTS: the same maxima folded in by a captured step
+    unsigned long long* spd;       // partial maxima of a captured step: a pair per dense tile of
+    int spd_dense;                 // the second sweep, then (from pair spd_dense on) per box block
 };
 
 // Launch kinds and their block sizes.
@@ -233,14 +234,10 @@ __global__ __launch_bounds__(T_BOX) void kb_fix(const StepArgs* __restrict__ A, 
     fix<R>(a.g, J, a.S, round, a.ncol, a.status, w.lb * T_BOX + threadIdx.x);
 }
 
-// fold: 0 plain sweep; 1 also clears the member's speed slots (first sweep of a captured
-// step); 2 folds the speeds of the written cells into them (second sweep).
-__device__ __forceinline__ void clear_speeds(const StepArgs& a) {
-    for (int k = threadIdx.x; k < 2 * SPEED_SLOTS; k += blockDim.x) a.spd[k] = 0ull;
-}
-__device__ __forceinline__ unsigned long long* fold_target(const StepArgs& a, int lb, int fold) {
-    if (fold == 1 && lb == 0) clear_speeds(a);
-    return fold == 2 ? a.spd : nullptr;
+// fold: 1 when the sweep is the last of a captured step: every tile also writes the
+// maxima of its cells' speeds to its partial pair.
+__device__ __forceinline__ unsigned long long* fold_target(const StepArgs& a, int fold) {
+    return fold ? a.spd : nullptr;
 }
 
 template <typename R, int RB>
@@ -251,7 +248,7 @@ __global__ __launch_bounds__(DX_T) void kb_dense_x(const StepArgs* __restrict__ 
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     if (J.dir != 0 || w.lb >= dense_x_blocks<RB>(a.g.nx, a.g.ny)) return;
-    unsigned long long* cfl = fold_target(a, w.lb, fold);
+    unsigned long long* cfl = fold_target(a, fold);
     dense_x<R, R, RB>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl);
 }
 
@@ -263,12 +260,13 @@ __global__ __launch_bounds__(256) void kb_dense_y(const StepArgs* __restrict__ A
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     if (J.dir != 1 || w.lb >= dense_y_blocks<TR>(a.g.nx, a.g.ny)) return;
-    unsigned long long* cfl = fold_target(a, w.lb, fold);
+    unsigned long long* cfl = fold_target(a, fold);
     dense_y<R, R, TR>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl);
 }
 
-// Wave speeds of box cell t of the member's sweep s (end level, state as stored), folded
-// into its time-step maxima.  Every lane of the wavefront calls it.
+// Wave speeds of box cell t of the member's sweep s (end level, state as stored); the
+// wavefront's maxima go to the member's partial pair of box block t / 64.  Every lane of
+// the wavefront calls it.
 template <typename R>
 __device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t) {
     const SweepJob& J = a.sw[s];
@@ -278,37 +276,56 @@ __device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t) {
         int i = J.B.i0 + t % w, j = J.B.j0 + t / w;
         size_t nc = (size_t)a.g.nx * a.g.ny, k = (size_t)j * a.g.nx + i;
         const R* U = (const R*)J.Uout;
-        double al = J.Le.alpha[k];
-        double r = (double)U[k];
-        if (al > 0.0 && r > 0.0) {
-            double q[4];
+        R u[4];
 #pragma unroll
-            for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k] / al;
-            double uu = q[1] / q[0], vv = q[2] / q[0];
-            double c = sqrt(a.g.gamma * pressure(q, a.g.gamma) / q[0]);
-            double sx = fabs(uu) + c, sy = fabs(vv) + c;
-            bx = __double_as_longlong(sx);
-            by = __double_as_longlong(sy);
-            if (sx != sx) bx = 0x7ff8000000000000ull;
-            if (sy != sy) by = 0x7ff8000000000000ull;
-        }
+        for (int m = 0; m < 4; m++) u[m] = U[m * nc + k];
+        speed_bits(u, J.Le.alpha[k], a.g.gamma, bx, by);
     }
-    speeds_to_max(bx, by, a.spd);
+    wave_max_pair(bx, by);
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long* out = a.spd + 2 * (a.spd_dense + (t >> 6));
+        out[0] = bx;
+        out[1] = by;
+    }
 }
 
-// After the second sweep of a captured step: the box cells' wave speeds (the host takes
-// the maximum over the speed slots it reads back), and the status word and collapse count
-// of each member gathered for the same read-back.
+// After the second sweep of a captured step: the box cells' wave speeds.
 template <typename R>
 __global__ __launch_bounds__(T_BOX) void kb_box_speeds(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                       int n, unsigned int* __restrict__ gather) {
+                                                       int n) {
     Unit w = unit_of(off, n);
-    const StepArgs& a = A[w.u];
-    box_speeds<R>(a, 1, w.lb * T_BOX + threadIdx.x);
-    if (w.lb == 0 && threadIdx.x == 0) {
-        gather[2 * w.u] = *a.status;
-        gather[2 * w.u + 1] = *a.ncol;
+    box_speeds<R>(A[w.u], 1, w.lb * T_BOX + threadIdx.x);
+}
+
+// Member u's time-step maxima from its partial pairs (the dense tiles of the step's last
+// sweep, then its box blocks), and its status word and collapse count gathered for one
+// read-back.  Every thread of the block calls it.
+__device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, int nbox, unsigned int* gather, int u) {
+    unsigned long long bx = 0ull, by = 0ull;
+    for (int k = threadIdx.x; k < ndense + nbox; k += blockDim.x) {
+        int q = k < ndense ? k : a.spd_dense + (k - ndense);
+        unsigned long long x = a.spd[2 * q], y = a.spd[2 * q + 1];
+        bx = x > bx ? x : bx;
+        by = y > by ? y : by;
     }
+    __shared__ unsigned long long res[2];
+    block_max_to(bx, by, res);
+    if (threadIdx.x == 0) {
+        a.cfl_out[0] = res[0];
+        a.cfl_out[1] = res[1];
+        gather[2 * u] = *a.status;
+        gather[2 * u + 1] = *a.ncol;
+    }
+}
+
+// One block per member.
+__global__ __launch_bounds__(256) void kb_speed_combine(const StepArgs* __restrict__ A, const int* __restrict__ off_dx,
+                                                        const int* __restrict__ off_dy, const int* __restrict__ off_box,
+                                                        unsigned int* __restrict__ gather) {
+    int u = blockIdx.x;
+    const StepArgs& a = A[u];
+    const int* od = a.sw[1].dir == 0 ? off_dx : off_dy;
+    combine_speeds(a, od[u + 1] - od[u], off_box[u + 1] - off_box[u], gather, u);
 }
 
 // ------------------------------------------------------------------ time step

@@ -178,9 +178,6 @@ __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
     int prv = busy(s == 0 ? wide_ext(p, L_POSE) : box_ext(p));
     PHASE_MARK(s, 0);
     if (s == 0) {
-        // the step's time-step maxima are folded in by the second sweep
-        if (blockIdx.x == 0)
-            for (int u = 0; u < p.n; u++) clear_speeds(p.A[u]);
         for (int lev = 0; lev < 2; lev++)
             each_wide(p, L_POSE, [&](const StepArgs& a, int lb, int) { pose_body(a, lev, lb * T_WIDE + tid); });
         { int nx_ = busy(wide_ext(p, L_V1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
@@ -235,11 +232,16 @@ __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
     if (tid == 0) g_phase_trace[s][MAX_BARRIERS + 1] = wall_clock64();
 #endif
     if (s == 1) {
-        unsigned int err = __hip_atomic_load(&p.gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 8u : 0u;
-        for (int u = tid; u < p.n; u += blockDim.x) {
-            p.gather[2 * u] = *p.A[u].status | err;
-            p.gather[2 * u + 1] = *p.A[u].ncol;
+        const int* od = ptab(p, L_DX);
+        const int* oy = ptab(p, L_DY);
+        const int* ob = ptab(p, L_BOX);
+        for (int u = 0; u < p.n; u++) {
+            const int* o = p.A[u].sw[1].dir == 0 ? od : oy;
+            combine_speeds(p.A[u], o[u + 1] - o[u], ob[u + 1] - ob[u], p.gather, u);
         }
+        __syncthreads();
+        if (__hip_atomic_load(&p.gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            for (int u = tid; u < p.n; u += blockDim.x) p.gather[2 * u] |= 8u;
     }
     if (tid < MAX_BARRIERS) p.gs->arrived[s][tid] = 0u;
     if (tid == 0) {

@@ -89,18 +89,11 @@ __device__ void cfl_block(const Grid& g, const double* __restrict__ alpha, const
     size_t nc = (size_t)g.nx * g.ny;
     unsigned long long mx = 0ull, my = 0ull;
     for (size_t k = (size_t)lb * blockDim.x + threadIdx.x; k < nc; k += (size_t)nb * blockDim.x) {
-        double a = alpha[k];
-        double r = (double)U[k];
-        if (!(a > 0.0) || !(r > 0.0)) continue;
-        double q[4];
+        R u[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k] / a;
-        double u = q[1] / q[0], v = q[2] / q[0];
-        double c = sqrt(g.gamma * pressure(q, g.gamma) / q[0]);
-        double sx = fabs(u) + c, sy = fabs(v) + c;
-        unsigned long long bx = __double_as_longlong(sx), by = __double_as_longlong(sy);
-        if (sx != sx) bx = 0x7ff8000000000000ull;
-        if (sy != sy) by = 0x7ff8000000000000ull;
+        for (int m = 0; m < 4; m++) u[m] = U[m * nc + k];
+        unsigned long long bx, by;
+        speed_bits(u, alpha[k], g.gamma, bx, by);
         mx = bx > mx ? bx : mx;
         my = by > my ? by : my;
     }

@@ -792,48 +792,39 @@ __host__ __device__ constexpr int dense_x_blocks(int nx, int ny) {
 template <typename T>
 __host__ __device__ constexpr size_t dense_x_lds() { return (size_t)12 * DX_T * sizeof(T); }
 
-// Speeds |u|+a and |v|+a of a stored regular-cell state (volume fraction 1) as ordered bit
-// patterns; 0 for cells without gas.  The time-step reduction uses the same formula.
-template <typename R>
-__device__ __forceinline__ void cell_speeds(const R* u, double gam, unsigned long long& bx, unsigned long long& by) {
-    double r = (double)u[0];
-    bx = by = 0ull;
-    if (!(r > 0.0)) return;
-    double q[4];
-#pragma unroll
-    for (int m = 0; m < 4; m++) q[m] = (double)u[m] / 1.0;
-    double uu = q[1] / q[0], vv = q[2] / q[0];
-    double c = sqrt(gam * pressure(q, gam) / q[0]);
-    double sx = fabs(uu) + c, sy = fabs(vv) + c;
-    bx = __double_as_longlong(sx);
-    by = __double_as_longlong(sy);
-    if (sx != sx) bx = 0x7ff8000000000000ull;
-    if (sy != sy) by = 0x7ff8000000000000ull;
-}
-
-// Speed maxima are folded into SPEED_SLOTS pairs per instance (one pair per group of
-// wavefronts, which keeps the atomics on any one address few); the pairs are combined
-// once all contributions are in.
-constexpr int SPEED_SLOTS = 64;
-
-// Wavefront maximum of a per-lane bit-pattern pair, then one atomic pair per wavefront
-// into the wavefront's slot.
-__device__ __forceinline__ void speeds_to_max(unsigned long long bx, unsigned long long by,
-                                              unsigned long long* slots) {
+// Maximum of a per-lane bit-pattern pair over the wavefront (every lane gets it).
+__device__ __forceinline__ void wave_max_pair(unsigned long long& bx, unsigned long long& by) {
     for (int off = 32; off > 0; off >>= 1) {
         unsigned long long ox = __shfl_xor(bx, off, 64), oy = __shfl_xor(by, off, 64);
         bx = ox > bx ? ox : bx;
         by = oy > by ? oy : by;
     }
+}
+
+// Block maximum of a per-thread bit-pattern pair, written by thread 0 to out[0..1] (a
+// block's own slot: no atomics).  Every thread of the block calls it.
+__device__ __forceinline__ void block_max_to(unsigned long long bx, unsigned long long by, unsigned long long* out) {
+    __shared__ unsigned long long sx_[16], sy_[16];
+    wave_max_pair(bx, by);
+    int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        int k = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % SPEED_SLOTS);
-        if (bx) atomicMax(&slots[2 * k], bx);
-        if (by) atomicMax(&slots[2 * k + 1], by);
+        sx_[w] = bx;
+        sy_[w] = by;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < (int)(blockDim.x >> 6); q++) {
+            bx = sx_[q] > bx ? sx_[q] : bx;
+            by = sy_[q] > by ? sy_[q] : by;
+        }
+        out[0] = bx;
+        out[1] = by;
+    }
+    __syncthreads();
 }
 
 // lds: dense_x_lds<T>() bytes; cfl: when not null, the maxima of the written cells' speeds
-// are folded into these speed slots.
+// go to this block's partial pair cfl[2 lb .. 2 lb + 1].
 template <typename R, typename T, int RB>
 __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U, R* __restrict__ Uout, Box B, T lam,
                                         int lb, T* lds, unsigned long long* cfl) {
@@ -904,13 +895,13 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U, 
             for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
             if (cfl) {
                 unsigned long long bx, by;
-                cell_speeds(un, g.gamma, bx, by);
+                speed_bits(un, 1.0, g.gamma, bx, by);
                 cx = bx > cx ? bx : cx;
                 cy = by > cy ? by : cy;
             }
         }
     }
-    if (cfl) speeds_to_max(cx, cy, cfl);
+    if (cfl) block_max_to(cx, cy, cfl + 2 * lb);
     __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
@@ -1007,12 +998,12 @@ __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, 
         for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
         if (cfl) {
             unsigned long long bx, by;
-            cell_speeds(un, g.gamma, bx, by);
+            speed_bits(un, 1.0, g.gamma, bx, by);
             cx = bx > cx ? bx : cx;
             cy = by > cy ? by : cy;
         }
     }
-    if (cfl) speeds_to_max(cx, cy, cfl);
+    if (cfl) block_max_to(cx, cy, cfl + 2 * lb);
     __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
