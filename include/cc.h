@@ -75,7 +75,8 @@ typedef struct {
 typedef struct {
     int32_t nverts;      /* 0: no body */
     int32_t pad_;
-    const double* verts; /* body-frame convex polygon, counter-clockwise, (x, y) pairs; host */
+    const double* verts; /* body-frame convex polygon, counter-clockwise, (x, y) pairs, at most
+                            2048 vertices (CC_ERR_UNSUPPORTED beyond); host */
     double ref_x, ref_y; /* position of the body-frame origin at t = 0 */
     double theta0;       /* body angle at t = 0 (radians, counter-clockwise) */
     double vx, vy;       /* constant translation velocity */

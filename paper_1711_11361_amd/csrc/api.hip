@@ -344,7 +344,8 @@ Box box_union(const Box& a, const Box& b) {
 
 bool geo_fits(const cc_ctx* c, const Box& r) { return box_empty(r) || (r.w() <= c->lay.gw && r.h() <= c->lay.gh); }
 
-unsigned nblk(size_t n, int t = TPB) { return (unsigned)((n + t - 1) / t); }
+unsigned nblk(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
+unsigned nblk(size_t n) { return nblk(n, TPB); }
 
 void tstart(cc_ctx* c, int kind, TimedPair& tp) {
     if (!(c->timing & 2)) return;
@@ -372,6 +373,26 @@ cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vect
             return fail(c, CC_ERR_MOTION, "the body moves a cell or more within one sweep");
     }
     return CC_OK;
+}
+
+// Blocks of a geometry or aperture stage launch of one context (0 without a body): one
+// thread per item, and for a many-sided body at least about one wavefront per boundary
+// item of the region (those take a wavefront's chain search each); the geometry stages run
+// both level jobs side by side, each on its own half.
+enum GeoStage { GEO_VERTS, GEO_FACES, GEO_CELLS, GEO_SWEPT };
+int geo_blocks(const cc_ctx* c, GeoStage st) {
+    const Layout& L = c->lay;
+    if (c->m == 0) return 0;
+    size_t items;
+    switch (st) {
+        case GEO_VERTS: items = (size_t)(L.gw + 1) * (L.gh + 1); break;
+        case GEO_FACES: items = (size_t)(L.gw + 1) * L.gh + (size_t)L.gw * (L.gh + 1); break;
+        case GEO_CELLS: items = (size_t)L.gw * L.gh; break;
+        default: items = std::max((size_t)(L.capw + 1) * L.caph, (size_t)L.capw * (L.caph + 1)); break;
+    }
+    size_t walkers = c->m > SMALL_POLY ? std::min<size_t>(256, (size_t)(L.gw + L.gh)) : 0;
+    int b = (int)std::max<size_t>(nblk(items, T_WIDE), walkers);
+    return st == GEO_SWEPT ? b : 2 * b;
 }
 
 // ------------------------------------------------------------------ argument blocks
@@ -403,6 +424,8 @@ void base_args(cc_ctx* c, StepArgs& a) {
     }
     a.cfl_part = at<unsigned long long>(c, c->lay.off_part);
     a.cfl_out = at<unsigned long long>(c, c->lay.off_cflout);
+    a.nb_cells = geo_blocks(c, GEO_CELLS);
+    a.nb_swept = geo_blocks(c, GEO_SWEPT);
     a.spd = at<unsigned long long>(c, c->lay.off_spd);
     a.spd_dense = c->lay.spd_dense;
     for (int k = 0; k < 2; k++) {
@@ -539,30 +562,20 @@ int units_of(int, int n) { return n; }
 
 int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     const Layout& L = c->lay;
-    size_t gv = (size_t)(L.gw + 1) * (L.gh + 1);
-    size_t gf = (size_t)(L.gw + 1) * L.gh + (size_t)L.gw * (L.gh + 1);
-    size_t gc = (size_t)L.gw * L.gh;
-    size_t sf = std::max((size_t)(L.capw + 1) * L.caph, (size_t)L.capw * (L.caph + 1));
     int m = c->m;
-    if (m == 0 && kind <= L_BOX) return 0;
-    // stages whose boundary items (about gw + gh of them for a many-sided body) each take a
-    // wavefront's chain search: enough wavefronts that most of them get at most one
-    size_t walkers = m > SMALL_POLY ? std::min<size_t>(256, (size_t)(L.gw + L.gh)) : 0;
-    auto stage = [&](size_t items) { return (int)std::max<size_t>(nblk(items, T_WIDE), walkers); };
-    // the geometry stages run both level jobs side by side, each on its own half
-    auto both = [&](size_t items) { return 2 * stage(items); };
+    if (m == 0 && (kind <= L_BOX || kind == L_CS)) return 0;
     switch (kind) {
         case L_POSE: return (int)nblk((size_t)m, T_WIDE);
-        case L_V1: return both(gv);
-        case L_F1: return both(gf);
-        case L_C1: return both(gc);
-        case L_S1: return stage(sf);
+        case L_V1: return geo_blocks(c, GEO_VERTS);
+        case L_F1: return geo_blocks(c, GEO_FACES);
+        case L_C1: return geo_blocks(c, GEO_CELLS);
+        case L_S1: return geo_blocks(c, GEO_SWEPT);
+        case L_CS: return geo_blocks(c, GEO_CELLS) + 2 * geo_blocks(c, GEO_SWEPT);
         case L_BOX: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
         case L_CFL: return (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(L.nc, T_WIDE));
         case L_CFLF: return 1;
-        case L_BSPD: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
     }
     return 0;
 }
@@ -610,12 +623,11 @@ void klaunch(K kern, int blocks, int threads, hipStream_t s, Args... args) {
     if (blocks > 0) hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, args...);
 }
 
-// Geometry of both level jobs of every member: pose, vertex classes, face intervals,
-// volume fractions.
+// Geometry of both level jobs of every member: vertex classes (and the posed polygons),
+// face intervals, volume fractions.
 void launch_geometry(const Engine& E, hipStream_t s) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    klaunch(kb_geo_pose, ktotal(E, L_POSE), T_WIDE, s, A, koff(E, L_POSE), n);
     klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
     klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
     klaunch(kb_geo<2>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), n);
@@ -662,15 +674,16 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
 
 // Box phases before the dense sweep.
 template <typename R>
-void launch_box_pre(const Engine& E, hipStream_t s, int sw) {
+void launch_box_pre(const Engine& E, hipStream_t s, int sw, bool swept = true) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    klaunch(kb_swept, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
+    if (swept) klaunch(kb_swept, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
     klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
 }
-// Box phases after the dense sweep (`which` as for the dense launches).
+// Box phases after the dense sweep (`which` as for the dense launches); speeds: the last
+// collapse round also leaves the box cells' wave-speed partials.
 template <typename R>
-void launch_box_post(const Engine& E, hipStream_t s, int sw, int which) {
+void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int speeds = 0) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
     int nb = ktotal(E, L_BOX);
@@ -678,8 +691,8 @@ void launch_box_post(const Engine& E, hipStream_t s, int sw, int which) {
     if (which & 1) klaunch(kb_patch<0, R>, nb, T_BOX, s, A, ob, n, sw);
     if (which & 2) klaunch(kb_patch<1, R>, nb, T_BOX, s, A, ob, n, sw);
     klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw);
-    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 0);
-    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 1);
+    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 0, 0);
+    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 1, speeds);
 }
 
 template <typename R>
@@ -779,17 +792,18 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
         (void)launch_persist<R>(E, s, 0);
         (void)launch_persist<R>(E, s, 1);
     } else {
-        launch_geometry(E, s);
-        // the second sweep's dense tiles and the box blocks leave partial maxima of the new
-        // state's wave speeds; one block per member combines them
+        const StepArgs* A = E.d_args;
+        klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
+        klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
+        klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
+        // the second sweep's dense tiles and its last collapse round leave partial maxima of
+        // the new state's wave speeds; one block per member combines them
         for (int sw = 0; sw < 2; sw++) {
-            launch_box_pre<R>(E, s, sw);
+            launch_box_pre<R>(E, s, sw, false);
             launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw);
-            launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1);
+            launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1, sw);
         }
-        klaunch(kb_box_speeds<R>, ktotal(E, L_BSPD), T_BOX, s, (const StepArgs*)E.d_args, koff(E, L_BSPD), n);
-        klaunch(kb_speed_combine, n, 256, s, (const StepArgs*)E.d_args, koff(E, L_DX), koff(E, L_DY),
-                koff(E, L_BSPD), E.d_gather);
+        klaunch(kb_speed_combine, n, 256, s, A, koff(E, L_DX), koff(E, L_DY), koff(E, L_BOX), E.d_gather);
     }
     (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(E.h_gather, E.d_gather, 8 * (size_t)n, hipMemcpyDeviceToHost, s);
@@ -837,6 +851,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         if (cfg->bc[k] != CC_BC_TRANSMISSIVE && cfg->bc[k] != CC_BC_REFLECTIVE)
             return create_fail(nullptr, CC_ERR_ARG, "invalid boundary condition");
     if (body && body->nverts > 0 && !body->verts) return create_fail(nullptr, CC_ERR_ARG, "body without vertices");
+    if (body && body->nverts > LDS_VERTS)
+        return create_fail(nullptr, CC_ERR_UNSUPPORTED, "body polygon with more than 2048 vertices");
     Layout lay = make_layout(cfg, body);
     if (!d_ws || ws_bytes < lay.total || ((uintptr_t)d_ws % ALIGN) != 0)
         return create_fail(nullptr, CC_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");

@@ -22,6 +22,7 @@ struct StepArgs {
     unsigned int* status;
     unsigned int* ncol;
     double* bt[2];  // time-averaged apertures of each sweep (box-local faces)
+    int nb_cells, nb_swept;  // blocks of the cell stage (both levels) and of one sweep's apertures
     int32_t step_id;
     // time-step reduction of the state after the step
     const double* cfl_alpha;
@@ -36,7 +37,7 @@ struct StepArgs {
 enum LaunchKind {
     L_POSE, L_V1, L_F1, L_C1,  // geometry stages (both level jobs)
     L_S1, L_BOX, L_DX, L_DY, L_CFL, L_CFLF,  // sweeps and time step
-    L_BSPD,  // wave speeds of the box cells after the step (at least one block per member)
+    L_CS,  // volume fractions of both levels and the apertures of both sweeps
     NKINDS
 };
 constexpr int T_WIDE = 256;  // geometry and aperture stages, dense, time step
@@ -71,12 +72,6 @@ __device__ __forceinline__ void pose_body(const StepArgs& a, int lev, int t) {
     geo_pose(J, t);
 }
 
-__global__ __launch_bounds__(T_WIDE) void kb_geo_pose(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                      int n) {
-    Unit w = unit_of(off, n);
-    for (int lev = 0; lev < 2; lev++) pose_body(A[w.u], lev, w.lb * T_WIDE + threadIdx.x);
-}
-
 // Stage arrays of sweep s (the apertures are per sweep, the rest is shared).
 __device__ __forceinline__ Stage stage_of(const StepArgs& a, int s) {
     Stage S = a.S;
@@ -95,6 +90,20 @@ __device__ __forceinline__ Poly stage_poly(const Poly& P, double* spoly) {
         __syncthreads();
         Q.v = spoly;
     }
+    return Q;
+}
+
+// The polygon of level job J posed in LDS (at most LDS_VERTS vertices, which cc_create
+// checks), with the same formula as the copy in the level.
+__device__ __forceinline__ Poly pose_lds(const GeoJob& J, double* spoly) {
+    Poly Q = J.L.poly;
+    for (int k = threadIdx.x; k < Q.m; k += blockDim.x) {
+        double bx = J.body[2 * k], by = J.body[2 * k + 1];
+        spoly[2 * k] = (J.cs_x * bx - J.sn_x * by) + J.cx_x;
+        spoly[2 * k + 1] = (J.sn_y * bx + J.cs_y * by) + J.cy_y;
+    }
+    __syncthreads();
+    Q.v = spoly;
     return Q;
 }
 
@@ -129,9 +138,17 @@ __device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int 
     const GeoJob& J = a.geo[lev];
     if (!J.active) return;
     int t = spread_item(lb, nb);
-    bool need = K == 0 ? geo_vertices1(a.g, J, t) : (K == 1 ? geo_faces1(a.g, J, t) : geo_cells1(a.g, J, t));
+    // the vertex stage also poses the polygon: every block poses its own copy in LDS (the
+    // level's copy is written in this launch, by the first block, for the later stages)
+    Poly Pv = J.L.poly;
+    if (K == 0) {
+        if (lb == 0)
+            for (int k = threadIdx.x; k < J.L.poly.m; k += blockDim.x) geo_pose(J, k);
+        Pv = pose_lds(J, spoly);
+    }
+    bool need = K == 0 ? geo_vertices1(a.g, J, Pv, t) : (K == 1 ? geo_faces1(a.g, J, t) : geo_cells1(a.g, J, t));
     if (!__syncthreads_or(need)) return;
-    Poly P = stage_poly(J.L.poly, spoly);
+    Poly P = K == 0 ? Pv : stage_poly(J.L.poly, spoly);
     walk_left(need, t, [&](int item, int lane) {
         if (K == 0) geo_vertex_walk(a.g, J, P, item, lane);
         if (K == 1) geo_face_chain(a.g, J, P, item, lane);
@@ -160,6 +177,8 @@ __global__ __launch_bounds__(T_WIDE) void kb_geo(const StepArgs* __restrict__ A,
 // ------------------------------------------------------------------ sweeps
 __device__ __forceinline__ bool box_empty_dev(const Box& B) { return B.i0 >= B.i1 || B.j0 >= B.j1; }
 
+__device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, int nb, double* spoly);
+
 // Time-averaged apertures of sweep s over the faces of block lb (of nb) of the sweep box;
 // faces left open by the quick tests on a many-sided polygon by their wavefront's chain
 // search.
@@ -183,6 +202,25 @@ __global__ __launch_bounds__(T_WIDE) void kb_swept(const StepArgs* __restrict__ 
     __shared__ double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
     swept_block(A[w.u], s, w.lb, w.nb, spoly);
+}
+
+// Volume fractions of both level jobs and the time-averaged apertures of both sweeps (they
+// need only the face intervals of the three levels) in one launch: a member's first
+// nb_cells blocks do the cells, the next nb_swept the first sweep's faces, the last
+// nb_swept the second sweep's.
+__global__ __launch_bounds__(T_WIDE) void kb_geo_cells_swept(const StepArgs* __restrict__ A,
+                                                             const int* __restrict__ off, int n) {
+    __shared__ double spoly[2 * LDS_VERTS];
+    Unit w = unit_of(off, n);
+    const StepArgs& a = A[w.u];
+    int lb = w.lb;
+    if (lb < a.nb_cells) {
+        geo_stage_split<2>(a, lb, a.nb_cells, spoly);
+        return;
+    }
+    lb -= a.nb_cells;
+    int s = lb >= a.nb_swept ? 1 : 0;
+    swept_block(a, s, lb - s * a.nb_swept, a.nb_swept, spoly);
 }
 
 template <typename R>
@@ -224,14 +262,19 @@ __global__ __launch_bounds__(T_BOX) void kb_cover(const StepArgs* __restrict__ A
     cover<R>(a.g, J, a.S, w.lb * T_BOX + threadIdx.x);
 }
 
+// speeds: after the last collapse round of a captured step, the box cells' wave speeds.
+template <typename R>
+__device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t);
+
 template <typename R>
 __global__ __launch_bounds__(T_BOX) void kb_fix(const StepArgs* __restrict__ A, const int* __restrict__ off, int n,
-                                                int s, int round) {
+                                                int s, int round, int speeds) {
     Unit w = unit_of(off, n);
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
-    if (box_empty_dev(J.B)) return;
-    fix<R>(a.g, J, a.S, round, a.ncol, a.status, w.lb * T_BOX + threadIdx.x);
+    int t = w.lb * T_BOX + threadIdx.x;
+    if (!box_empty_dev(J.B)) fix<R>(a.g, J, a.S, round, a.ncol, a.status, t);
+    if (speeds) box_speeds<R>(a, s, t);
 }
 
 // fold: 1 when the sweep is the last of a captured step: every tile also writes the
@@ -287,14 +330,6 @@ __device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t) {
         out[0] = bx;
         out[1] = by;
     }
-}
-
-// After the second sweep of a captured step: the box cells' wave speeds.
-template <typename R>
-__global__ __launch_bounds__(T_BOX) void kb_box_speeds(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                       int n) {
-    Unit w = unit_of(off, n);
-    box_speeds<R>(A[w.u], 1, w.lb * T_BOX + threadIdx.x);
 }
 
 // Member u's time-step maxima from its partial pairs (the dense tiles of the step's last

@@ -409,13 +409,14 @@ __device__ __forceinline__ int geo_nverts(const Box& r) { return (r.w() + 1) * (
 __device__ __forceinline__ int geo_nfaces(const Box& r) { return (r.w() + 1) * r.h() + r.w() * (r.h() + 1); }
 
 // Phase 1 of the vertex classes: thread t of the job; true = left to phase 2.
-__device__ __forceinline__ bool geo_vertices1(const Grid& g, const GeoJob& J, int t) {
+// P: the job's polygon (its posed vertices, possibly in LDS).
+__device__ __forceinline__ bool geo_vertices1(const Grid& g, const GeoJob& J, const Poly& P, int t) {
     int vw = J.reg.w() + 1;
     if (t >= geo_nverts(J.reg)) return false;
     int i = J.reg.i0 + t % vw, j = J.reg.j0 + t / vw;
     double px = vx_of(g, i), py = vy_of(g, j);
-    int c = classify_quick(J.L.poly, px, py);
-    if (c < 0 && J.L.poly.m <= SMALL_POLY) c = poly_classify<1>(J.L.poly, px, py, 0);
+    int c = classify_quick(P, px, py);
+    if (c < 0 && P.m <= SMALL_POLY) c = poly_classify<1>(P, px, py, 0);
     if (c < 0) return true;
     J.L.vcls[(size_t)j * (g.nx + 1) + i] = (int8_t)c;
     return false;
