@@ -60,7 +60,7 @@ struct Layout {
     size_t off_sQ, off_sU1, off_shas, off_sbt[2], off_swall, off_sfb, off_swv, off_sahat, off_sU2, off_sgone;
     size_t off_sf1, off_sf2, off_nbad;
     size_t off_sync;
-    size_t off_args, off_offs, off_cflout, off_gather;
+    size_t off_args, off_offs, off_cflout;
     size_t off_smax, off_status, off_ncol, off_part, off_tot, off_spd;
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
@@ -131,8 +131,7 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_sync = take(sizeof(GridSync));
     L.off_args = take(sizeof(StepArgs));
     L.off_offs = take((size_t)NKINDS * 3 * 4);
-    L.off_cflout = take(16);
-    L.off_gather = take(16);
+    L.off_cflout = take(24);  // read-back: 2 speed maxima, then status and collapse count
     L.off_smax = take(16);
     L.off_status = take(4);
     L.off_ncol = take(4);
@@ -161,10 +160,12 @@ struct Engine {
     StepArgs* d_args = nullptr;
     int* d_off = nullptr;  // NKINDS tables of (units + 1) entries, stride 2 cap_n + 1
     std::vector<int> h_off[NKINDS];
-    unsigned long long* d_cflout = nullptr;  // 2 per member
+    // one read-back region of 24 cap_n bytes: 2 speed maxima per member slot, then the
+    // status word and collapse count per member
+    unsigned long long* d_cflout = nullptr;
     unsigned long long* h_cflout = nullptr;  // pinned
-    unsigned int* d_gather = nullptr;        // status and collapse count per member
-    unsigned int* h_gather = nullptr;        // pinned
+    unsigned int* d_gather = nullptr;        // = d_cflout + 2 cap_n
+    unsigned int* h_gather = nullptr;        // = h_cflout + 2 cap_n
     hipEvent_t ev[2] = {nullptr, nullptr};   // last use of host buffer b
     bool ev_used[2] = {false, false};
     int buf = 0;
@@ -572,6 +573,7 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
         case L_S1: return geo_blocks(c, GEO_SWEPT);
         case L_CS: return geo_blocks(c, GEO_CELLS) + 2 * geo_blocks(c, GEO_SWEPT);
         case L_BOX: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
+        case L_BOXW: return (int)nblk(std::max<size_t>(L.cap, 1), T_WIDE);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
         case L_CFL: return (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(L.nc, T_WIDE));
@@ -636,40 +638,53 @@ void launch_geometry(const Engine& E, hipStream_t s) {
 // Dense launches of sweep sw: bit 0 of `which` the x-sweep kernel, bit 1 the y-sweep
 // kernel (a member's direction in this sweep picks which one does its work).  ta/tb:
 // events recorded by the launch itself around its execution (one kernel only), or null.
+// wall: the first of these launches also runs the box cells' first phase (donations and
+// wall quantities) in blocks of its own ahead of the tiles.
 template <typename R>
-void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t ta, hipEvent_t tb, int fold = 0) {
+void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t ta, hipEvent_t tb, int fold = 0,
+                  bool wall = false) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
+    int nwall = wall && !ta ? ktotal(E, L_BOXW) : 0;
+    const int* ow = koff(E, L_BOXW);
     for (int d = 0; d < 2; d++) {
         if (!((which >> d) & 1)) continue;
         int kind = d == 0 ? L_DX : L_DY;
         int blocks = ktotal(E, kind);
         if (blocks == 0) continue;
         const int* off = koff(E, kind);
-        auto go = [&](auto kern, int threads) {
-            if (ta) hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, ta, tb, 0, A, off, n, sw, fold);
-            else hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, A, off, n, sw, fold);
+        auto go = [&](auto kern, auto wkern, int threads) {
+            if (ta) {
+                hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, ta, tb, 0, A, off, n, sw, fold);
+            } else if (nwall > 0) {
+                hipLaunchKernelGGL(wkern, dim3(nwall + blocks), dim3(threads), 0, s, A, ow, nwall, off, n, sw, fold);
+                nwall = 0;
+            } else {
+                hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, A, off, n, sw, fold);
+            }
         };
         if (d == 0) {
             switch (E.tile_x) {
-                case 0: go(kb_dense_x<R, 1>, DX_T); break;
-                case 1: go(kb_dense_x<R, 2>, DX_T); break;
-                case 2: go(kb_dense_x<R, 4>, DX_T); break;
-                default: go(kb_dense_x<R, 8>, DX_T); break;
+                case 0: go(kb_dense_x<R, 1>, kb_wall_dense_x<R, 1>, DX_T); break;
+                case 1: go(kb_dense_x<R, 2>, kb_wall_dense_x<R, 2>, DX_T); break;
+                case 2: go(kb_dense_x<R, 4>, kb_wall_dense_x<R, 4>, DX_T); break;
+                default: go(kb_dense_x<R, 8>, kb_wall_dense_x<R, 8>, DX_T); break;
             }
         } else {
             switch (E.tile_y) {
-                case 0: go(kb_dense_y<R, 8>, 256); break;
-                case 1: go(kb_dense_y<R, 12>, 256); break;
+                case 0: go(kb_dense_y<R, 8>, kb_wall_dense_y<R, 8>, 256); break;
+                case 1: go(kb_dense_y<R, 12>, kb_wall_dense_y<R, 12>, 256); break;
                 default:
                     if constexpr (sizeof(R) == 4) {
-                        if (E.tile_y == 2) go(kb_dense_y<R, 16>, 256);
-                        else go(kb_dense_y<R, 24>, 256);
+                        if (E.tile_y == 2) go(kb_dense_y<R, 16>, kb_wall_dense_y<R, 16>, 256);
+                        else go(kb_dense_y<R, 24>, kb_wall_dense_y<R, 24>, 256);
                     }
                     break;
             }
         }
     }
+    if (wall && !ta && nwall > 0)  // no dense launch took the box blocks
+        klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
 }
 
 // Box phases before the dense sweep.
@@ -713,8 +728,8 @@ hipError_t engine_alloc_host(Engine& E) {
         e = hipHostMalloc((void**)&E.h_args[b], sizeof(StepArgs) * E.cap_n, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&E.ev[b], hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, 16 * E.cap_n, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_gather, 8 * E.cap_n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, 24 * (size_t)E.cap_n, hipHostMallocDefault);
+    if (e == hipSuccess) E.h_gather = (unsigned int*)(E.h_cflout + 2 * (size_t)E.cap_n);
     int dev = 0, khz = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
@@ -731,7 +746,6 @@ void engine_free(Engine& E) {
         E.ev[b] = nullptr;
     }
     if (E.h_cflout) (void)hipHostFree(E.h_cflout);
-    if (E.h_gather) (void)hipHostFree(E.h_gather);
     E.h_cflout = nullptr;
     E.h_gather = nullptr;
 }
@@ -799,14 +813,12 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
         // the second sweep's dense tiles and its last collapse round leave partial maxima of
         // the new state's wave speeds; one block per member combines them
         for (int sw = 0; sw < 2; sw++) {
-            launch_box_pre<R>(E, s, sw, false);
-            launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw);
+            launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw, true);
             launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1, sw);
         }
         klaunch(kb_speed_combine, n, 256, s, A, koff(E, L_DX), koff(E, L_DY), koff(E, L_BOX), E.d_gather);
     }
-    (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)n, hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(E.h_gather, E.d_gather, 8 * (size_t)n, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)E.cap_n + 8 * (size_t)n, hipMemcpyDeviceToHost, s);
 }
 
 // Launches the captured step graph of host buffer b (capturing it first if needed).
@@ -917,7 +929,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     E.d_args = at<StepArgs>(c, lay.off_args);
     E.d_off = at<int>(c, lay.off_offs);
     E.d_cflout = at<unsigned long long>(c, lay.off_cflout);
-    E.d_gather = at<unsigned int>(c, lay.off_gather);
+    E.d_gather = (unsigned int*)(E.d_cflout + 2);
     E.d_sync = at<GridSync>(c, lay.off_sync);
     E.tile_x = 0;  // one row per x-sweep block
     E.tile_y = 1;  // 12-row y-sweep tiles
@@ -1485,7 +1497,7 @@ cc_status cc_timing_read(cc_ctx* c, double* h_out, int32_t n) {
 size_t cc_batch_workspace_bytes(int32_t max_instances) {
     if (max_instances < 1) return 0;
     size_t n = (size_t)max_instances;
-    return up(n * sizeof(StepArgs)) + up((size_t)NKINDS * (2 * n + 1) * sizeof(int)) + up(16 * n) + up(8 * n) +
+    return up(n * sizeof(StepArgs)) + up((size_t)NKINDS * (2 * n + 1) * sizeof(int)) + up(24 * n) +
            up(sizeof(GridSync));
 }
 
@@ -1507,9 +1519,8 @@ cc_status cc_batch_create(int32_t max_instances, int32_t precision, void* d_ws, 
     E.d_off = (int*)(b->ws + o);
     o += up((size_t)NKINDS * (2 * n + 1) * sizeof(int));
     E.d_cflout = (unsigned long long*)(b->ws + o);
-    o += up(16 * n);
-    E.d_gather = (unsigned int*)(b->ws + o);
-    o += up(8 * n);
+    E.d_gather = (unsigned int*)(E.d_cflout + 2 * n);
+    o += up(24 * n);
     E.d_sync = (GridSync*)(b->ws + o);
     E.tile_x = 0;
     E.tile_y = 1;

@@ -38,6 +38,7 @@ enum LaunchKind {
     L_POSE, L_V1, L_F1, L_C1,  // geometry stages (both level jobs)
     L_S1, L_BOX, L_DX, L_DY, L_CFL, L_CFLF,  // sweeps and time step
     L_CS,  // volume fractions of both levels and the apertures of both sweeps
+    L_BOXW,  // box cells, T_WIDE per block (launched beside the dense tiles)
     NKINDS
 };
 constexpr int T_WIDE = 256;  // geometry and aperture stages, dense, time step
@@ -56,13 +57,15 @@ __device__ __forceinline__ int find_unit(const int* __restrict__ off, int n, int
 struct Unit {
     int u, lb, nb;  // unit, block within the unit, blocks of the unit
 };
-__device__ __forceinline__ Unit unit_of(const int* __restrict__ off, int n) {
+// Unit of block b of a launch.
+__device__ __forceinline__ Unit unit_at(const int* __restrict__ off, int n, int b) {
     Unit r;
-    r.u = n == 1 ? 0 : find_unit(off, n, blockIdx.x);
-    r.lb = blockIdx.x - off[r.u];
+    r.u = n == 1 ? 0 : find_unit(off, n, b);
+    r.lb = b - off[r.u];
     r.nb = off[r.u + 1] - off[r.u];
     return r;
 }
+__device__ __forceinline__ Unit unit_of(const int* __restrict__ off, int n) { return unit_at(off, n, blockIdx.x); }
 
 // ------------------------------------------------------------------ geometry
 // Level job lev: pose the polygon (thread t of its vertices).
@@ -283,28 +286,70 @@ __device__ __forceinline__ unsigned long long* fold_target(const StepArgs& a, in
     return fold ? a.spd : nullptr;
 }
 
+// Dense tiles of sweep s, block b of the launch's dense part (the whole block calls it).
 template <typename R, int RB>
-__global__ __launch_bounds__(DX_T) void kb_dense_x(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                   int n, int s, int fold) {
-    __shared__ R lds[dense_x_lds<R>() / sizeof(R)];
-    Unit w = unit_of(off, n);
+__device__ __forceinline__ void dense_x_block(const StepArgs* __restrict__ A, const int* __restrict__ off, int n,
+                                              int b, int s, int fold, R* lds) {
+    Unit w = unit_at(off, n, b);
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     if (J.dir != 0 || w.lb >= dense_x_blocks<RB>(a.g.nx, a.g.ny)) return;
     unsigned long long* cfl = fold_target(a, fold);
     dense_x<R, R, RB>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl);
 }
-
 template <typename R, int TR>
-__global__ __launch_bounds__(256) void kb_dense_y(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                  int n, int s, int fold) {
-    __shared__ R lds[DenseYTile<R, TR>::lds_bytes / sizeof(R)];
-    Unit w = unit_of(off, n);
+__device__ __forceinline__ void dense_y_block(const StepArgs* __restrict__ A, const int* __restrict__ off, int n,
+                                              int b, int s, int fold, R* lds) {
+    Unit w = unit_at(off, n, b);
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     if (J.dir != 1 || w.lb >= dense_y_blocks<TR>(a.g.nx, a.g.ny)) return;
     unsigned long long* cfl = fold_target(a, fold);
     dense_y<R, R, TR>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl);
+}
+
+template <typename R, int RB>
+__global__ __launch_bounds__(DX_T) void kb_dense_x(const StepArgs* __restrict__ A, const int* __restrict__ off,
+                                                   int n, int s, int fold) {
+    __shared__ R lds[dense_x_lds<R>() / sizeof(R)];
+    dense_x_block<R, RB>(A, off, n, blockIdx.x, s, fold, lds);
+}
+
+template <typename R, int TR>
+__global__ __launch_bounds__(256) void kb_dense_y(const StepArgs* __restrict__ A, const int* __restrict__ off,
+                                                  int n, int s, int fold) {
+    __shared__ R lds[DenseYTile<R, TR>::lds_bytes / sizeof(R)];
+    dense_y_block<R, TR>(A, off, n, blockIdx.x, s, fold, lds);
+}
+
+// The box cells' first phase of sweep s (donations and wall quantities) in the same launch
+// as the dense tiles: the two touch disjoint data (the tiles read the state and write the
+// cells outside the box; the box phase reads the state and geometry and writes box-local
+// staging), so the box's latency-bound cells run while the tiles stream.  The first nwall
+// blocks are box blocks (T_WIDE cells each, table off_wall), the rest dense blocks.
+template <typename R, int RB>
+__global__ __launch_bounds__(DX_T) void kb_wall_dense_x(const StepArgs* __restrict__ A,
+                                                        const int* __restrict__ off_wall, int nwall,
+                                                        const int* __restrict__ off, int n, int s, int fold) {
+    __shared__ R lds[dense_x_lds<R>() / sizeof(R)];
+    if ((int)blockIdx.x < nwall) {
+        Unit w = unit_at(off_wall, n, blockIdx.x);
+        stagewall_body<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x);
+        return;
+    }
+    dense_x_block<R, RB>(A, off, n, blockIdx.x - nwall, s, fold, lds);
+}
+template <typename R, int TR>
+__global__ __launch_bounds__(256) void kb_wall_dense_y(const StepArgs* __restrict__ A,
+                                                       const int* __restrict__ off_wall, int nwall,
+                                                       const int* __restrict__ off, int n, int s, int fold) {
+    __shared__ R lds[DenseYTile<R, TR>::lds_bytes / sizeof(R)];
+    if ((int)blockIdx.x < nwall) {
+        Unit w = unit_at(off_wall, n, blockIdx.x);
+        stagewall_body<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x);
+        return;
+    }
+    dense_y_block<R, TR>(A, off, n, blockIdx.x - nwall, s, fold, lds);
 }
 
 // Wave speeds of box cell t of the member's sweep s (end level, state as stored); the
