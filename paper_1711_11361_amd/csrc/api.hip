@@ -695,19 +695,19 @@ void launch_box_pre(const Engine& E, hipStream_t s, int sw, bool swept = true) {
     if (swept) klaunch(kb_swept, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
     klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
 }
-// Box phases after the dense sweep (`which` as for the dense launches); speeds: the last
-// collapse round also leaves the box cells' wave-speed partials.
+// Box phases after the dense sweep (`which` as for the dense launches): patch update,
+// covering, both collapse rounds.  last: the sweep ends a captured step; covering leaves the
+// box cells' wave-speed partials and the collapse launch combines the member's partials.
 template <typename R>
-void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int speeds = 0) {
+void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int last = 0) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
     int nb = ktotal(E, L_BOX);
     const int* ob = koff(E, L_BOX);
     if (which & 1) klaunch(kb_patch<0, R>, nb, T_BOX, s, A, ob, n, sw);
     if (which & 2) klaunch(kb_patch<1, R>, nb, T_BOX, s, A, ob, n, sw);
-    klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw);
-    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 0, 0);
-    klaunch(kb_fix<R>, nb, T_BOX, s, A, ob, n, sw, 1, speeds);
+    klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw, last);
+    klaunch(kb_fix_block<R>, n, T_FIX, s, A, koff(E, L_DX), koff(E, L_DY), ob, sw, last, E.d_gather);
 }
 
 template <typename R>
@@ -810,13 +810,12 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
         klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
         klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
         klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
-        // the second sweep's dense tiles and its last collapse round leave partial maxima of
-        // the new state's wave speeds; one block per member combines them
+        // the second sweep's dense tiles and its covering leave partial maxima of the new
+        // state's wave speeds; its collapse launch (one block per member) combines them
         for (int sw = 0; sw < 2; sw++) {
             launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw, true);
             launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1, sw);
         }
-        klaunch(kb_speed_combine, n, 256, s, A, koff(E, L_DX), koff(E, L_DY), koff(E, L_BOX), E.d_gather);
     }
     (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)E.cap_n + 8 * (size_t)n, hipMemcpyDeviceToHost, s);
 }

@@ -256,28 +256,20 @@ __global__ __launch_bounds__(T_BOX) void kb_patch(const StepArgs* __restrict__ A
 }
 
 template <typename R>
-__global__ __launch_bounds__(T_BOX) void kb_cover(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                  int n, int s) {
-    Unit w = unit_of(off, n);
-    const StepArgs& a = A[w.u];
-    const SweepJob& J = a.sw[s];
-    if (box_empty_dev(J.B)) return;
-    cover<R>(a.g, J, a.S, w.lb * T_BOX + threadIdx.x);
-}
-
-// speeds: after the last collapse round of a captured step, the box cells' wave speeds.
-template <typename R>
 __device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t);
 
+// speeds: the sweep is the last of a captured step: the box cells' wave speeds (of the
+// covered state; the collapse rounds recompute them if they move content) go to the box
+// blocks' partial pairs.
 template <typename R>
-__global__ __launch_bounds__(T_BOX) void kb_fix(const StepArgs* __restrict__ A, const int* __restrict__ off, int n,
-                                                int s, int round, int speeds) {
+__global__ __launch_bounds__(T_BOX) void kb_cover(const StepArgs* __restrict__ A, const int* __restrict__ off,
+                                                  int n, int s, int speeds) {
     Unit w = unit_of(off, n);
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     int t = w.lb * T_BOX + threadIdx.x;
-    if (!box_empty_dev(J.B)) fix<R>(a.g, J, a.S, round, a.ncol, a.status, t);
-    if (speeds) box_speeds<R>(a, s, t);
+    if (!box_empty_dev(J.B)) cover<R>(a.g, J, a.S, t);
+    if (speeds) box_speeds<R>(a, s, t);  // reads back the thread's own cell
 }
 
 // fold: 1 when the sweep is the last of a captured step: every tile also writes the
@@ -378,10 +370,10 @@ __device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t) {
 }
 
 // Member u's time-step maxima from its partial pairs (the dense tiles of the step's last
-// sweep, then its box blocks), and its status word and collapse count gathered for one
-// read-back.  Every thread of the block calls it.
-__device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, int nbox, unsigned int* gather, int u) {
-    unsigned long long bx = 0ull, by = 0ull;
+// sweep, then its box blocks) and the block's own pair (bx, by), and its status word and
+// collapse count gathered for one read-back.  Every thread of the block calls it.
+__device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, int nbox, unsigned int* gather, int u,
+                                               unsigned long long bx = 0ull, unsigned long long by = 0ull) {
     for (int k = threadIdx.x; k < ndense + nbox; k += blockDim.x) {
         int q = k < ndense ? k : a.spd_dense + (k - ndense);
         unsigned long long x = a.spd[2 * q], y = a.spd[2 * q + 1];
@@ -398,14 +390,44 @@ __device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, in
     }
 }
 
-// One block per member.
-__global__ __launch_bounds__(256) void kb_speed_combine(const StepArgs* __restrict__ A, const int* __restrict__ off_dx,
-                                                        const int* __restrict__ off_dy, const int* __restrict__ off_box,
-                                                        unsigned int* __restrict__ gather) {
+// Both collapse rounds of sweep s (reading R28) for every member, one block per member:
+// both return at once unless covering left a bad cell, which is rare, so one block walks
+// the whole box, with a block barrier between the rounds.  last: the sweep is the last of
+// a captured step; the block then also combines the member's wave-speed partials (the box
+// cells' speeds recomputed here when a round moved content) and gathers its status words.
+constexpr int T_FIX = 1024;
+template <typename R>
+__global__ __launch_bounds__(T_FIX) void kb_fix_block(const StepArgs* __restrict__ A, const int* __restrict__ off_dx,
+                                                      const int* __restrict__ off_dy,
+                                                      const int* __restrict__ off_box, int s, int last,
+                                                      unsigned int* __restrict__ gather) {
     int u = blockIdx.x;
     const StepArgs& a = A[u];
+    const SweepJob& J = a.sw[s];
+    int cells = box_empty_dev(J.B) ? 0 : J.B.w() * J.B.h();
+    bool bad = cells > 0 && __hip_atomic_load(&a.S.nbad[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (bad)
+        for (int round = 0; round < 2; round++) {
+            for (int t = threadIdx.x; t < cells; t += blockDim.x) fix<R>(a.g, J, a.S, round, a.ncol, a.status, t);
+            __syncthreads();  // the round's flags and contents, for the next round and the speeds
+        }
+    if (!last) return;
+    unsigned long long bx = 0ull, by = 0ull;
+    if (bad) {
+        const R* U = (const R*)J.Uout;
+        size_t nc = (size_t)a.g.nx * a.g.ny;
+        for (int t = threadIdx.x; t < cells; t += blockDim.x) {
+            int i = J.B.i0 + t % J.B.w(), j = J.B.j0 + t / J.B.w();
+            size_t k = (size_t)j * a.g.nx + i;
+            R uu[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) uu[m] = U[m * nc + k];
+            speed_bits(uu, J.Le.alpha[k], a.g.gamma, bx, by);
+        }
+    }
     const int* od = a.sw[1].dir == 0 ? off_dx : off_dy;
-    combine_speeds(a, od[u + 1] - od[u], off_box[u + 1] - off_box[u], gather, u);
+    // with recomputed box speeds the box blocks' partials (of the covered state) are skipped
+    combine_speeds(a, od[u + 1] - od[u], bad ? 0 : off_box[u + 1] - off_box[u], gather, u, bx, by);
 }
 
 // ------------------------------------------------------------------ time step

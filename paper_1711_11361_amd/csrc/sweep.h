@@ -694,7 +694,9 @@ __device__ void fix(const Grid& g, const SweepJob& J, const Stage& S, int round,
     const int8_t* fin = round == 0 ? S.f1 : S.f2;
     double* Xout = S.Q;
     int8_t* fout = S.f2;
-    if (S.nbad[round] == 0u) return;
+    // the counter is read past the L1 cache: round 1 of a one-block launch reads what
+    // round 0 counted with atomics in the same launch
+    if (__hip_atomic_load(&S.nbad[round], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
     if (t >= B.w() * B.h()) return;
     int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
     int b = bidx(B, i, j), cap = S.cap;
