@@ -132,6 +132,19 @@ cc_status cc_step(cc_ctx* ctx, double dt);
  * over live cells and |u_wall| over the body's vertices.  Synchronises; h_dt: host. */
 cc_status cc_cfl_dt(cc_ctx* ctx, double cfl, double* h_dt);
 
+/* nsteps CFL steps planned on the device (Sec. 4 time step, Sec. 2.3.4 poses): each step
+ * takes dt = cfl * min(hx / Sx, hy / Sy) from the state it starts from, exactly as
+ * cc_cfl_dt, then runs the split step as cc_step; a block at the head of every step
+ * computes dt, the poses, regions and sweep boxes on the device, so the host queues all
+ * steps without waiting between them.  Results equal those of cc_cfl_dt + cc_step bit for
+ * bit for a body that does not turn (a turning body's angle uses the device's sin and
+ * cos).  Host outputs, each nullable: h_dt (nsteps doubles) the steps' dt, h_step_ms
+ * (nsteps floats) each step's device time from events between the steps, h_done the steps
+ * completed.  Stops at the first step that cc_cfl_dt or cc_step would refuse, with the
+ * same status (the state is then that after the last completed step).  Uses the per-phase
+ * launches whatever the launch mode.  Not for a context in a batch.  Synchronizes. */
+cc_status cc_advance(cc_ctx* ctx, int32_t nsteps, double cfl, double* h_dt, float* h_step_ms, int32_t* h_done);
+
 /* Conservation totals sum(U) hx hy per component, FP64, deterministic order.  Host out. */
 cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
 

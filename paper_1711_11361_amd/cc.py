@@ -60,6 +60,7 @@ _sig = {
     "cc_end_step": (C.c_int, [_vp]),
     "cc_step": (C.c_int, [_vp, _d]),
     "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
+    "cc_advance": (C.c_int, [_vp, _i32, _d, C.POINTER(_d), C.POINTER(C.c_float), C.POINTER(_i32)]),
     "cc_totals": (C.c_int, [_vp, C.POINTER(_d)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
@@ -182,6 +183,22 @@ def cc_cfl_dt(ctx, cfl):
     out = _d()
     _check(ctx, _lib.cc_cfl_dt(ctx, cfl, C.byref(out)))
     return out.value
+
+
+def cc_advance(ctx, nsteps, cfl, want_dt=True, want_ms=False):
+    """Returns (steps done, dts or None, per-step device ms or None); raises CCError when a
+    step is refused (the exception carries .done, the steps completed before it)."""
+    dts = (_d * max(nsteps, 1))() if want_dt else None
+    ms = (C.c_float * max(nsteps, 1))() if want_ms else None
+    done = _i32()
+    st = _lib.cc_advance(ctx, nsteps, cfl, dts, ms, C.byref(done))
+    if st != CC_OK:
+        raw = _lib.cc_last_error(ctx)
+        err = CCError(st, raw.decode() if raw else "")
+        err.done = done.value
+        raise err
+    n = done.value
+    return n, (np.array(dts[:n]) if want_dt else None), (np.array(ms[:n]) if want_ms else None)
 
 
 def cc_totals(ctx):
@@ -386,6 +403,11 @@ class Solver:
 
     def cfl_dt(self, cfl):
         return cc_cfl_dt(self.ctx, cfl)
+
+    def advance(self, nsteps, cfl, want_ms=False):
+        """nsteps CFL steps planned on the device; returns (dts, per-step ms or None)."""
+        _, dts, ms = cc_advance(self.ctx, nsteps, cfl, True, want_ms)
+        return dts, ms
 
     def totals(self):
         return cc_totals(self.ctx)

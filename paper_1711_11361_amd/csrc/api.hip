@@ -14,6 +14,7 @@
 #include "cc_device.h"
 #include "engine.h"
 #include "persist.h"
+#include "plan.h"
 #include "geometry.h"
 #include "reduce.h"
 #include "sweep.h"
@@ -51,6 +52,8 @@ int dense_blocks(int dir, int v, int nx, int ny) {
 }
 
 // --------------------------------------------------------------------------- workspace
+constexpr int DTLOG = 1024;  // steps of one device-planned run between read-backs
+
 struct Layout {
     size_t nc, nvx, nfx, nfy, cap, capf;
     size_t u_bytes;
@@ -62,6 +65,7 @@ struct Layout {
     size_t off_sync;
     size_t off_args, off_offs, off_cflout;
     size_t off_smax, off_status, off_ncol, off_part, off_tot, off_spd;
+    size_t off_pconst, off_pstate, off_dtlog;
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
     int spd_dense;   // partial speed pairs reserved for dense tiles (the most any tile shape uses)
@@ -139,6 +143,9 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_tot = take(4 * 8);
     L.spd_dense = std::max(dense_blocks(0, 0, c->nx, c->ny), dense_blocks(1, 0, c->nx, c->ny));
     L.off_spd = take((size_t)2 * 8 * ((size_t)L.spd_dense + (std::max<size_t>(L.cap, 1) + T_BOX - 1) / T_BOX));
+    L.off_pconst = take(sizeof(PlanConst));
+    L.off_pstate = take(sizeof(PlanState));
+    L.off_dtlog = take((size_t)DTLOG * 8);
     L.total = o;
     return L;
 }
@@ -172,6 +179,7 @@ struct Engine {
     int tile_x = 0, tile_y = 1;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gkey[2] = {-1, -1};
+    hipGraphExec_t pexec[2] = {nullptr, nullptr};  // device-planned step, by its first direction
     int mode = 0;                       // 0: one launch per phase; 1: one persistent launch per sweep
     GridSync* d_sync = nullptr;         // barrier counters of the persistent sweep launches
     unsigned long long wait_ticks = 0;  // barrier wait limit (wall-clock ticks)
@@ -188,6 +196,7 @@ struct cc_ctx {
     int m;
     std::vector<double> bverts;
     double ref_x, ref_y, theta0, vx, vy, amp, omega;
+    Cert cert0;  // discs of the body turned by theta0 (used while it does not turn)
     int cur;  // U[cur] holds the level-n state
     Level lev[3];
     Box lbox[3];  // region of each slot that may differ from all-fluid
@@ -209,6 +218,7 @@ struct cc_ctx {
     // wave speeds of the current state, reduced and read back by the last captured step
     bool speeds_ready;
     int speeds_buf;
+    int advanced;  // steps completed by the last cc_advance
     std::string err;
 };
 
@@ -258,9 +268,6 @@ bool fp32(const cc_ctx* c) { return c->cfg.precision == CC_FP32_GEOM64; }
 
 // Rigid pose at time t: rotation by theta(t) about the body-frame origin, then the origin
 // at ref + v t.  The device poses with the same formula from (cs, sn, cx, cy).
-struct Pose {
-    double cs, sn, cx, cy;
-};
 Pose pose_at(const cc_ctx* c, double t) {
     double th = c->theta0 + c->amp * std::sin(c->omega * t);
     return Pose{std::cos(th), std::sin(th), c->ref_x + c->vx * t, c->ref_y + c->vy * t};
@@ -273,8 +280,44 @@ void pose_xy(const cc_ctx* c, const Pose& px, const Pose& py, double* out) {
     }
 }
 
-// Bounding box, certificate discs and cell box of a posed polygon.
-void poly_info(const cc_ctx* c, const double* pv, Poly& P, Box& cells) {
+// Certificate discs of a posed convex polygon pv (m >= 8): about the vertex centroid, a
+// disc inside the polygon (radius: the least distance to an edge line) and one containing
+// it (the largest vertex distance), shrunk and grown by a relative 1e-6 (Cert); none when
+// the polygon is too thin for them to help.
+Cert poly_cert(const double* pv, int m) {
+    Cert q{0.0, 0.0, -1.0, 0.0};
+    if (m < 8) return q;
+    double sx = 0.0, sy = 0.0;
+    for (int k = 0; k < m; k++) {
+        sx += pv[2 * k];
+        sy += pv[2 * k + 1];
+    }
+    double cx = sx / m, cy = sy / m;
+    double rin = INFINITY, rr = 0.0;
+    for (int k = 0; k < m; k++) {
+        int k1 = k + 1 == m ? 0 : k + 1;
+        double ex = pv[2 * k1] - pv[2 * k], ey = pv[2 * k1 + 1] - pv[2 * k + 1];
+        double l2 = ex * ex + ey * ey;
+        if (l2 > 0.0) rin = std::min(rin, (ex * (cy - pv[2 * k + 1]) - ey * (cx - pv[2 * k])) / std::sqrt(l2));
+        double dx = pv[2 * k] - cx, dy = pv[2 * k + 1] - cy;
+        rr = std::max(rr, dx * dx + dy * dy);
+    }
+    double rout = std::sqrt(rr);
+    if (rin > 1e-7 * rout && std::isfinite(rin)) {
+        q.cx = cx;
+        q.cy = cy;
+        q.rin2 = (rin * (1.0 - 1e-6)) * (rin * (1.0 - 1e-6));
+        q.rout2 = (rout * (1.0 + 1e-6)) * (rout * (1.0 + 1e-6));
+    }
+    return q;
+}
+
+// Bounding box, certificate discs and cell box of a polygon posed with x from pose px and
+// y from pose py.  A body that does not turn is only translated from step to step, which
+// moves its discs with it: their radii and the centroid's offset from the pose origin are
+// computed once (the rounding of the posed coordinates, ~1e-16 of their size, stays far
+// inside the 1e-6 margins); a turning body's discs are computed from its posed vertices.
+void poly_info(const cc_ctx* c, const double* pv, const Pose& px, const Pose& py, Poly& P, Box& cells) {
     int m = c->m;
     P.m = m;
     P.xmin = P.ymin = INFINITY;
@@ -292,55 +335,18 @@ void poly_info(const cc_ctx* c, const double* pv, Poly& P, Box& cells) {
         if (pv[2 * k] < pv[2 * P.il]) P.il = k;
         if (pv[2 * k] > pv[2 * P.ir]) P.ir = k;
     }
-    P.rin2 = -1.0;
-    P.rout2 = 0.0;
-    P.cx = P.cy = 0.0;
-    if (m >= 8) {
-        double sx = 0.0, sy = 0.0;
-        for (int k = 0; k < m; k++) {
-            sx += pv[2 * k];
-            sy += pv[2 * k + 1];
-        }
-        double cx = sx / m, cy = sy / m;
-        double rin = INFINITY, rout = 0.0;
-        for (int k = 0; k < m; k++) {
-            int k1 = (k + 1) % m;
-            double ex = pv[2 * k1] - pv[2 * k], ey = pv[2 * k1 + 1] - pv[2 * k + 1];
-            double len = std::hypot(ex, ey);
-            if (len > 0.0) {
-                double sd = (ex * (cy - pv[2 * k + 1]) - ey * (cx - pv[2 * k])) / len;
-                rin = std::min(rin, sd);
-            }
-            rout = std::max(rout, std::hypot(pv[2 * k] - cx, pv[2 * k + 1] - cy));
-        }
-        if (rin > 1e-7 * rout && std::isfinite(rin)) {
-            P.cx = cx;
-            P.cy = cy;
-            P.rin2 = (rin * (1.0 - 1e-6)) * (rin * (1.0 - 1e-6));
-            P.rout2 = (rout * (1.0 + 1e-6)) * (rout * (1.0 + 1e-6));
-        }
+    Cert q = c->amp == 0.0 ? c->cert0 : poly_cert(pv, m);
+    if (c->amp == 0.0 && q.rin2 >= 0.0) {
+        q.cx += px.cx;
+        q.cy += py.cy;
     }
-    if (m == 0 || P.xmax < c->cfg.x_lo || P.xmin > c->cfg.x_hi || P.ymax < c->cfg.y_lo || P.ymin > c->cfg.y_hi) {
-        cells = Box{0, 0, 0, 0};
-        return;
-    }
-    int i0 = (int)std::floor((P.xmin - c->cfg.x_lo) / c->hx) - 2;
-    int i1 = (int)std::floor((P.xmax - c->cfg.x_lo) / c->hx) + 3;
-    int j0 = (int)std::floor((P.ymin - c->cfg.y_lo) / c->hy) - 2;
-    int j1 = (int)std::floor((P.ymax - c->cfg.y_lo) / c->hy) + 3;
-    cells.i0 = std::max(i0, 0);
-    cells.i1 = std::min(i1, c->g.nx);
-    cells.j0 = std::max(j0, 0);
-    cells.j1 = std::min(j1, c->g.ny);
-    if (cells.i0 >= cells.i1 || cells.j0 >= cells.j1) cells = Box{0, 0, 0, 0};
-}
-
-bool box_empty(const Box& b) { return b.i0 >= b.i1 || b.j0 >= b.j1; }
-
-Box box_union(const Box& a, const Box& b) {
-    if (box_empty(a)) return b;
-    if (box_empty(b)) return a;
-    return Box{std::min(a.i0, b.i0), std::max(a.i1, b.i1), std::min(a.j0, b.j0), std::max(a.j1, b.j1)};
+    P.cx = q.cx;
+    P.cy = q.cy;
+    P.rin2 = q.rin2;
+    P.rout2 = q.rout2;
+    cells = m == 0 ? Box{0, 0, 0, 0}
+                   : cells_of_bbox(P.xmin, P.xmax, P.ymin, P.ymax, c->cfg.x_lo, c->cfg.x_hi, c->cfg.y_lo,
+                                   c->cfg.y_hi, c->hx, c->hy, c->g.nx, c->g.ny);
 }
 
 bool geo_fits(const cc_ctx* c, const Box& r) { return box_empty(r) || (r.w() <= c->lay.gw && r.h() <= c->lay.gh); }
@@ -447,17 +453,7 @@ void set_geo(cc_ctx* c, GeoJob& J, int slot, const Box& reg, const Pose& px, con
     J.active = c->m > 0 && !box_empty(reg);
 }
 
-Box sweep_box(cc_ctx* c, const Box& a, const Box& b) {
-    Box ub = box_union(a, b);
-    Box B{0, 0, 0, 0};
-    if (!box_empty(ub)) {
-        B.i0 = std::max(ub.i0 - 3, 0);
-        B.i1 = std::min(ub.i1 + 3, c->g.nx);
-        B.j0 = std::max(ub.j0 - 3, 0);
-        B.j1 = std::min(ub.j1 + 3, c->g.ny);
-    }
-    return B;
-}
+Box sweep_box(cc_ctx* c, const Box& a, const Box& b) { return sweep_box_of(a, b, c->g.nx, c->g.ny); }
 
 void set_sweep(cc_ctx* c, SweepJob& J, int s, double dt) {
     int first = s == 0;
@@ -495,8 +491,8 @@ cc_status prepare_step(cc_ctx* c, double dt, StepArgs& a) {
         if (st != CC_OK) return st;
         Poly Pm = c->lev[c->sm].poly, P1 = c->lev[c->s1].poly;
         Box cm, c1;
-        poly_info(c, pm.data(), Pm, cm);
-        poly_info(c, p1.data(), P1, c1);
+        poly_info(c, pm.data(), mx, my, Pm, cm);
+        poly_info(c, p1.data(), q1, q1, P1, c1);
         Box rm = box_union(c->lbox[c->sm], cm), r1 = box_union(c->lbox[c->s1], c1);
         if (!geo_fits(c, rm) || !geo_fits(c, r1)) return fail(c, CC_ERR_WORKSPACE, "geometry region exceeds capacity");
         c->lev[c->sm].poly = Pm;
@@ -546,7 +542,7 @@ cc_status prepare_geometry(cc_ctx* c, double t, int slot, StepArgs& a) {
     std::vector<double> pv(2 * c->m);
     pose_xy(c, q, q, pv.data());
     Box cells;
-    poly_info(c, pv.data(), c->lev[slot].poly, cells);
+    poly_info(c, pv.data(), q, q, c->lev[slot].poly, cells);
     Box reg = box_union(c->lbox[slot], cells);
     if (geo_fits(c, reg)) {
         set_geo(c, a.geo[0], slot, reg, q, q);
@@ -587,6 +583,8 @@ void drop_graphs(Engine& E) {
         if (E.gexec[b]) (void)hipGraphExecDestroy(E.gexec[b]);
         E.gexec[b] = nullptr;
         E.gkey[b] = -1;
+        if (E.pexec[b]) (void)hipGraphExecDestroy(E.pexec[b]);
+        E.pexec[b] = nullptr;
     }
 }
 
@@ -613,6 +611,16 @@ hipError_t engine_plan(Engine& E, hipStream_t stream) {
 
 const int* koff(const Engine& E, int kind) { return E.d_off + (size_t)kind * (2 * E.cap_n + 1); }
 int ktotal(const Engine& E, int kind) { return E.h_off[kind].empty() ? 0 : E.h_off[kind].back(); }
+
+// Waits for event ev, polling it first: a step's read-back is usually due within a few
+// hundred microseconds, and a blocking wait adds the thread's wake-up to every step.
+hipError_t wait_event(hipEvent_t ev) {
+    for (int k = 0; k < 200000; k++) {
+        hipError_t e = hipEventQuery(ev);
+        if (e != hipErrorNotReady) return e;
+    }
+    return hipEventSynchronize(ev);
+}
 
 // Waits until host buffer b may be rewritten.
 hipError_t engine_hostbuf(Engine& E, int b) {
@@ -797,27 +805,64 @@ hipError_t launch_persist(const Engine& E, hipStream_t s, int sw) {
 // as its own launch); then the read-back of the wave speeds and status words into pinned
 // host memory.  dir0: the single member's first direction (only its dense kernels are
 // launched on the per-phase path), or -1.
+// The per-phase launches of a whole step (arguments already in device memory).
+template <typename R>
+void step_kernels(const Engine& E, hipStream_t s, int dir0) {
+    int which0 = dir0 < 0 ? 3 : 1 << dir0, which1 = dir0 < 0 ? 3 : 1 << (1 - dir0);
+    int n = (int)E.mem.size();
+    const StepArgs* A = E.d_args;
+    klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
+    klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
+    klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
+    // the second sweep's dense tiles and its covering leave partial maxima of the new
+    // state's wave speeds; its collapse launch (one block per member) combines them
+    for (int sw = 0; sw < 2; sw++) {
+        launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw, true);
+        launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1, sw);
+    }
+}
+
 template <typename R>
 void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
-    int which0 = dir0 < 0 ? 3 : 1 << dir0, which1 = dir0 < 0 ? 3 : 1 << (1 - dir0);
     int n = (int)E.mem.size();
     (void)engine_upload(E, s, b);
     if (persist_ok(E)) {
         (void)launch_persist<R>(E, s, 0);
         (void)launch_persist<R>(E, s, 1);
     } else {
-        const StepArgs* A = E.d_args;
-        klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
-        klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
-        klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
-        // the second sweep's dense tiles and its covering leave partial maxima of the new
-        // state's wave speeds; its collapse launch (one block per member) combines them
-        for (int sw = 0; sw < 2; sw++) {
-            launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw, true);
-            launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1, sw);
-        }
+        step_kernels<R>(E, s, dir0);
     }
     (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)E.cap_n + 8 * (size_t)n, hipMemcpyDeviceToHost, s);
+}
+
+// A device-planned step of a single context: the planning block writes the step's
+// arguments (and advances the device bookkeeping), then the per-phase launches.  dir0: the
+// step's first direction, which the host knows from the step count alone.
+template <typename R>
+void planned_sequence(const Engine& E, hipStream_t s, int dir0, const PlanConst* pc, PlanState* ps, double* dtlog) {
+    hipLaunchKernelGGL(kb_plan, dim3(1), dim3(T_PLAN), 0, s, pc, ps, E.d_args, dtlog);
+    step_kernels<R>(E, s, dir0);
+}
+
+template <typename R>
+hipError_t engine_planned_step(Engine& E, hipStream_t s, int dir0, const PlanConst* pc, PlanState* ps,
+                               double* dtlog) {
+    if (!s) {  // the null stream cannot be captured: individual launches
+        planned_sequence<R>(E, s, dir0, pc, ps, dtlog);
+        return hipGetLastError();
+    }
+    if (!E.pexec[dir0]) {
+        hipGraph_t gr;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        planned_sequence<R>(E, s, dir0, pc, ps, dtlog);
+        e = hipStreamEndCapture(s, &gr);
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(&E.pexec[dir0], gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return e;
+    }
+    return hipGraphLaunch(E.pexec[dir0], s);
 }
 
 // Launches the captured step graph of host buffer b (capturing it first if needed).
@@ -884,6 +929,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     c->g.gamma = cfg->gamma;
     c->g.alpha_min = cfg->alpha_min;
     c->m = body_m(body);
+    c->cert0 = Cert{0.0, 0.0, -1.0, 0.0};
     if (c->m > 0) {
         c->bverts.assign(body->verts, body->verts + 2 * c->m);
         c->ref_x = body->ref_x;
@@ -893,6 +939,11 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         c->vy = body->vy;
         c->amp = body->pitch_amp;
         c->omega = body->pitch_omega;
+        // discs of the body turned by theta0 about the pose origin (not translated)
+        Pose q0{std::cos(c->theta0), std::sin(c->theta0), 0.0, 0.0};
+        std::vector<double> pv(2 * (size_t)c->m);
+        pose_xy(c, q0, q0, pv.data());
+        c->cert0 = poly_cert(pv.data(), c->m);
     }
     c->cur = 0;
     c->s0 = 0;
@@ -1290,7 +1341,7 @@ cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
     if (!c || !h_dt || !(cfl > 0.0)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_cfl_dt inside a step");
     if (c->speeds_ready && !c->batch) {  // reduced and read back by the last captured step
-        HIPCHK(c, hipEventSynchronize(c->eng.ev[c->speeds_buf]));
+        HIPCHK(c, wait_event(c->eng.ev[c->speeds_buf]));
         double sx, sy;
         std::memcpy(&sx, &c->eng.h_cflout[0], 8);
         std::memcpy(&sy, &c->eng.h_cflout[1], 8);
@@ -1324,6 +1375,178 @@ cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
     if (st != CC_OK) return st;
     *h_dt = dt_from_speeds(c, cfl, sx, sy);
     return CC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void plan_const(cc_ctx* c, double cfl, PlanConst& P) {
+    std::memset(&P, 0, sizeof(P));
+    base_args(c, P.base);
+    P.body = at<double>(c, c->lay.off_body);
+    P.m = c->m;
+    P.ref_x = c->ref_x;
+    P.ref_y = c->ref_y;
+    P.theta0 = c->theta0;
+    P.vx = c->vx;
+    P.vy = c->vy;
+    P.amp = c->amp;
+    P.omega = c->omega;
+    P.cs0 = std::cos(c->theta0);
+    P.sn0 = std::sin(c->theta0);
+    P.cert0 = c->cert0;
+    P.x_lo = c->cfg.x_lo;
+    P.x_hi = c->cfg.x_hi;
+    P.y_lo = c->cfg.y_lo;
+    P.y_hi = c->cfg.y_hi;
+    P.hx = c->hx;
+    P.hy = c->hy;
+    P.nx = c->g.nx;
+    P.ny = c->g.ny;
+    P.gw = c->lay.gw;
+    P.gh = c->lay.gh;
+    P.capw = c->lay.capw;
+    P.caph = c->lay.caph;
+    P.u[0] = c->ws + c->lay.off_u[0];
+    P.u[1] = c->ws + c->lay.off_u[1];
+    P.cfl = cfl;
+}
+
+void plan_state_from(const cc_ctx* c, PlanState& S) {
+    std::memset(&S, 0, sizeof(S));
+    S.t = c->t;
+    S.step_dt = c->step_dt;
+    S.step = c->step;
+    S.parity = c->parity;
+    S.s0 = c->s0;
+    S.sm = c->sm;
+    S.s1 = c->s1;
+    S.cur = c->cur;
+    for (int k = 0; k < 3; k++) {
+        S.lbox[k] = c->lbox[k];
+        S.lev[k] = c->lev[k];
+    }
+    S.mot = c->mot;
+    S.last_sweep_box = c->last_sweep_box;
+}
+
+void plan_state_to(cc_ctx* c, const PlanState& S) {
+    c->t = S.t;
+    c->step_dt = S.step_dt;
+    c->step = S.step;
+    c->parity = S.parity;
+    c->s0 = S.s0;
+    c->s1 = S.s1;
+    for (int k = 0; k < 3; k++) {
+        c->lbox[k] = S.lbox[k];
+        c->lev[k].poly = S.lev[k].poly;
+    }
+    c->mot = S.mot;
+    c->last_sweep_box = S.last_sweep_box;
+}
+
+cc_status halt_error(cc_ctx* c, int halt) {
+    switch (halt) {
+        case HALT_STATUS:
+        case HALT_SPEEDS: {
+            unsigned long long sp[2];
+            unsigned int st = 0;
+            HIPCHK(c, hipMemcpyAsync(sp, c->eng.d_cflout, 16, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(&st, at<unsigned int>(c, c->lay.off_status), 4, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            double sx, sy;
+            std::memcpy(&sx, &sp[0], 8);
+            std::memcpy(&sy, &sp[1], 8);
+            cc_status e = status_error(c, st, sx, sy);
+            return e != CC_OK ? e : fail(c, CC_ERR_STATE, "non-finite or non-physical state");
+        }
+        case HALT_DT: return fail(c, CC_ERR_MOTION, "dt must be positive");
+        case HALT_MOTION: return fail(c, CC_ERR_MOTION, "the body moves a cell or more within one sweep");
+        case HALT_REGION: return fail(c, CC_ERR_WORKSPACE, "geometry region exceeds capacity");
+        default: return fail(c, CC_ERR_WORKSPACE, "sweep region exceeds the staging capacity");
+    }
+}
+
+template <typename R>
+cc_status advance(cc_ctx* c, int nsteps, double cfl, double* h_dt, float* h_step_ms) {
+    Engine& E = c->eng;
+    PlanConst* dpc = at<PlanConst>(c, c->lay.off_pconst);
+    PlanState* dps = at<PlanState>(c, c->lay.off_pstate);
+    double* dlog = at<double>(c, c->lay.off_dtlog);
+    PlanConst P;
+    plan_const(c, cfl, P);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpyAsync(dpc, &P, sizeof(P), hipMemcpyHostToDevice, c->stream));
+    // wave speeds of the start state: the first step's CFL condition
+    unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
+    int blocks = (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(c->lay.nc));
+    hipLaunchKernelGGL(k_cfl<R>, dim3(blocks), dim3(256), 0, c->stream, c->g, c->lev[c->s0].alpha,
+                       at<R>(c, c->lay.off_u[c->cur]), part);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, c->stream, blocks, (const unsigned long long*)part,
+                       E.d_cflout);
+    HIPCHK(c, hipGetLastError());
+    std::vector<hipEvent_t> ev;
+    if (h_step_ms) {
+        ev.assign((size_t)nsteps + 1, nullptr);
+        for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    auto drop_events = [&]() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    int done = 0, halt = 0;
+    while (done < nsteps && !halt) {
+        int n = std::min(nsteps - done, DTLOG);
+        PlanState S;
+        plan_state_from(c, S);
+        hipError_t e = hipMemcpyAsync(dps, &S, sizeof(S), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[done], c->stream);
+        for (int k = 0; k < n && e == hipSuccess; k++) {
+            e = engine_planned_step<R>(E, c->stream, (c->parity + k) & 1, dpc, dps, dlog);
+            if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[done + k + 1], c->stream);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&S, dps, sizeof(S), hipMemcpyDeviceToHost, c->stream);
+        std::vector<double> dts(n);
+        if (e == hipSuccess) e = hipMemcpyAsync(dts.data(), dlog, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            drop_events();
+            return fail(c, CC_ERR_DEVICE, std::string("device-planned steps: ") + hipGetErrorString(e));
+        }
+        plan_state_to(c, S);
+        if (h_dt) std::copy(dts.begin(), dts.begin() + S.steps, h_dt + done);
+        if (h_step_ms)
+            for (int k = 0; k < S.steps; k++)
+                if (hipEventElapsedTime(&h_step_ms[done + k], ev[done + k], ev[done + k + 1]) != hipSuccess)
+                    h_step_ms[done + k] = -1.0f;
+        done += S.steps;
+        halt = S.halt;
+    }
+    drop_events();
+    c->speeds_ready = false;
+    c->advanced = done;
+    return halt ? halt_error(c, halt) : CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_advance(cc_ctx* c, int32_t nsteps, double cfl, double* h_dt, float* h_step_ms, int32_t* h_done) {
+    if (!c) return CC_ERR_ARG;
+    cc_status st = not_in_batch(c);
+    if (st != CC_OK) return st;
+    if (h_done) *h_done = 0;
+    if (nsteps < 0 || !(cfl > 0.0) || !std::isfinite(cfl)) return fail(c, CC_ERR_ARG, "bad argument");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_advance inside a step");
+    if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
+    if (nsteps == 0) return CC_OK;
+    c->advanced = 0;
+    st = fp32(c) ? advance<float>(c, nsteps, cfl, h_dt, h_step_ms) : advance<double>(c, nsteps, cfl, h_dt, h_step_ms);
+    if (h_done) *h_done = c->advanced;
+    return st;
 }
 
 cc_status cc_totals(cc_ctx* c, double* h_totals4) {
@@ -1614,7 +1837,7 @@ cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
     BHIPCHK(b, hipEventRecord(E.ev[buf], b->stream));
     E.ev_used[buf] = true;
     E.buf = 1 - buf;
-    BHIPCHK(b, hipEventSynchronize(E.ev[buf]));
+    BHIPCHK(b, wait_event(E.ev[buf]));
     for (int k = 0; k < n; k++) {
         cc_ctx* c = E.mem[k];
         c->in_step = true;

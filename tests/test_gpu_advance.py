@@ -1,0 +1,113 @@
+"""Steps planned on the device (cc_advance: the CFL time step, poses, regions and sweep
+boxes computed by a block at the head of each step) against the host-planned path
+(cc_cfl_dt + cc_step): the same time steps and states, bit for bit, for bodies that do not
+turn; for a pitching body, whose angle comes from the device's sin and cos, agreement to
+round-off; the same refusal at the same step; the host's bookkeeping (clock, step count,
+direction order, level regions) taken over exactly, so host and device steps interleave."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1711_11361_amd import cc  # noqa: E402
+from paper_1711_11361_amd import workloads as W  # noqa: E402
+
+
+def solver(w, precision):
+    s = cc.Solver(w["grid"], w["body"], precision=precision)
+    s.set_prim(w["prim"])
+    return s
+
+
+def fixed_bodies():
+    yield "cylinder", W.cylinder(nx=128, ny=64)
+    yield "piston", W.piston()
+    yield "triangle", W.triangle_case(3, nx=96, ny=48)
+    yield "nobody", {**W.cylinder(nx=61, ny=29), "body": None}
+    for k in range(40):
+        r = W.serving_request(k)
+        if r["body"]["pitch_amp"] == 0.0 and r["grid"]["nx"] * r["grid"]["ny"] <= 256 * 128:
+            yield f"req{k}", r
+            break
+
+
+def host_steps(s, cfl, n):
+    dts = []
+    for _ in range(n):
+        dt = s.cfl_dt(cfl)
+        s.step(dt)
+        dts.append(dt)
+    return np.array(dts)
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+@pytest.mark.parametrize("name,w", list(fixed_bodies()), ids=[c[0] for c in fixed_bodies()])
+def test_device_planned_steps_equal_host_planned(name, w, precision):
+    n = 9
+    a, b = solver(w, precision), solver(w, precision)
+    da = host_steps(a, w["cfl"], n)
+    db, ms = b.advance(n, w["cfl"], want_ms=True)
+    assert np.array_equal(da, db), (name, da, db)
+    assert np.array_equal(a.get_u(), b.get_u()), name
+    ia, ib = a.info(), b.info()
+    for key in ("t", "steps", "parity", "status", "collapses", "box_cells"):
+        assert ia[key] == ib[key], (name, key, ia[key], ib[key])
+    assert ms.shape == (n,) and np.all(ms > 0.0)
+    # the host's bookkeeping continues from the device's: further steps either way agree
+    da2 = host_steps(a, w["cfl"], 3)
+    db2 = host_steps(b, w["cfl"], 3)
+    assert np.array_equal(da2, db2)
+    assert np.array_equal(a.get_u(), b.get_u()), name
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+def test_interleaved_host_and_device_steps(precision):
+    w = W.cylinder(nx=128, ny=64)
+    a, b = solver(w, precision), solver(w, precision)
+    da = host_steps(a, w["cfl"], 10)
+    d1 = host_steps(b, w["cfl"], 3)
+    d2, _ = b.advance(4, w["cfl"])
+    d3 = host_steps(b, w["cfl"], 3)
+    assert np.array_equal(da, np.concatenate([d1, d2, d3]))
+    assert np.array_equal(a.get_u(), b.get_u())
+
+
+def test_pitching_body_agrees_to_round_off():
+    w = W.naca(nx=96, ny=96)
+    w["body"]["pitch_amp"] = np.radians(8.0)
+    w["body"]["pitch_omega"] = 2.0
+    a, b = solver(w, cc.CC_FP64), solver(w, cc.CC_FP64)
+    n = 8
+    da = host_steps(a, w["cfl"], n)
+    db, _ = b.advance(n, w["cfl"])
+    assert np.abs(da - db).max() <= 1e-13 * da.max()
+    Ua, Ub = a.get_u(), b.get_u()
+    err = max(np.abs(Ua[k] - Ub[k]).max() / np.abs(Ua[k]).max() for k in range(4))
+    assert err <= 1e-10, err
+    assert a.info()["steps"] == b.info()["steps"] == n
+
+
+def test_refusal_at_the_same_step():
+    # a body faster than every signal of the gas at CFL 1.5 moves more than a cell per sweep
+    w = W.cylinder(nx=64, ny=32, speed=6.0)
+    a, b = solver(w, cc.CC_FP64), solver(w, cc.CC_FP64)
+    dt = a.cfl_dt(1.5)
+    with pytest.raises(cc.CCError) as ea:
+        a.step(dt)
+    with pytest.raises(cc.CCError) as eb:
+        b.advance(3, 1.5)
+    assert ea.value.status == eb.value.status == cc.CC_ERR_MOTION
+    assert eb.value.done == 0
+    assert np.array_equal(a.get_u(), b.get_u())
+    assert b.info()["steps"] == 0
+    # a smaller CFL number still steps afterwards, the same way on both paths
+    da = host_steps(a, 0.3, 2)
+    db, _ = b.advance(2, 0.3)
+    assert np.array_equal(da, db)
+    assert np.array_equal(a.get_u(), b.get_u())
