@@ -2,9 +2,12 @@
 
 Workload: circular cylinder (radius 0.1, 1024-gon) crossing a stationary Mach-2 shock on
 [0,2]x[0,1] with 1024 x 512 cells, moving at +1.0 along x, CFL 0.8.  One step = the CFL
-time step (device reduction, read back) + the full split step (stage and end geometry,
-two sweeps with every cut-cell operation).  Timed after W warm-up steps, K steps
-bracketed by device synchronisation; value = cells x steps / time.
+time step of its start state + the full split step (stage and end geometry, two sweeps
+with every cut-cell operation).  The timed steps are planned on the device (cc_advance:
+dt, poses and boxes computed at the head of each captured step, no host round trip
+between steps); the host-planned rate (dt read back before each step) is reported beside
+it.  Timed after W warm-up steps, K steps bracketed by device synchronisation; value =
+cells x steps / time.
 
 Reported: cell-updates/s of the FP32-state / FP64-geometry mode (headline) and of the FP64
 mode, p50/p99 step latency, the roofline of the dominant kernel (the dense sweep) from HIP
@@ -31,19 +34,26 @@ def run_mode(precision, steps, warmup, w):
     s.set_prim(w["prim"])
     tiles = s.autotune()
     cfl = w["cfl"]
-    for _ in range(warmup):
+    # host-planned steps (cc_cfl_dt read back, then the captured step), for comparison
+    for _ in range(10):
         s.step(s.cfl_dt(cfl))
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    # timed region: each step is the CFL reduction plus one replay of the captured step graph
-    t0 = time.perf_counter()
-    for k in range(steps):
-        ev[k][0].record(s.stream)
+    nh = min(steps, 100)
+    h0 = time.perf_counter()
+    for _ in range(nh):
         s.step(s.cfl_dt(cfl))
-        ev[k][1].record(s.stream)
+    torch.cuda.synchronize()
+    host_ms = 1e3 * (time.perf_counter() - h0) / nh
+    s.advance(warmup, cfl)
+    torch.cuda.synchronize()
+    # timed region: K device-planned steps (each: the CFL reduction of its start state, the
+    # time step, the poses and boxes, and the split step), queued without host round trips;
+    # cc_advance returns after the last one has finished
+    t0 = time.perf_counter()
+    _, ms = s.advance(steps, cfl, want_ms=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    lat = np.asarray(ms, dtype=np.float64)
     info = s.info()
     if info["status"] != 0:
         raise RuntimeError(f"device status {info['status']}")
@@ -68,6 +78,7 @@ def run_mode(precision, steps, warmup, w):
     cells = w["grid"]["nx"] * w["grid"]["ny"]
     T = t1 - t0
     return {"value": cells * steps / T, "ms_per_step": 1e3 * T / steps, "lat": lat, "timing": tim,
+            "host_planned_ms_per_step": host_ms,
             "t_end": info["t"], "collapses": info["collapses"], "box_cells": info["box_cells"],
             "tiles": {"x_rows_per_block": info["tile_x_rows"], "y_rows_per_tile": info["tile_y_rows"]}}
 
@@ -230,7 +241,9 @@ def main():
         "config": {"workload": "cylinder r=0.1 crossing a stationary Mach-2 shock, 1024x512 on [0,2]x[0,1], "
                                "body speed 1.0, CFL 0.8", "grid": [nx, ny], "cells": nx * ny},
         "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)), "p99": float(np.percentile(r32["lat"], 99))},
+        "host_planned_ms_per_step": r32["host_planned_ms_per_step"],
         "fp64": {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+                 "host_planned_ms_per_step": r64["host_planned_ms_per_step"],
                  "latency_ms": {"p50": float(np.percentile(r64["lat"], 50)),
                                 "p99": float(np.percentile(r64["lat"], 99))},
                  "roofline": roofline(r64, 8)},

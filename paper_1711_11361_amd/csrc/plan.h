@@ -101,95 +101,78 @@ __device__ inline Pose pose_at_dev(const PlanConst& P, double t) {
     return Pose{cos(th), sin(th), P.ref_x + P.vx * t, P.ref_y + P.vy * t};
 }
 
-// Per-thread partial results over the body's vertices.
-struct VAcc {
-    int bad;
-    double sx, sy;  // vertex speeds at the step's start
-    double xmin[2], xmax[2], ymin[2], ymax[2];  // stage polygon (0) and end polygon (1)
-    double yb[2], yt[2], xl[2], xr[2];
-    int ib[2], it[2], il[2], ir[2];
-    double sumx[2], sumy[2];
-};
+// A body has at most 2048 vertices: eight per thread.
+constexpr int T_PLAN = 256;
+constexpr int PLAN_VPT = 8;
 
-__device__ inline void vacc_init(VAcc& a, double sx, double sy) {
-    a.bad = 0;
-    a.sx = sx;
-    a.sy = sy;
-    for (int q = 0; q < 2; q++) {
-        a.xmin[q] = a.ymin[q] = INFINITY;
-        a.xmax[q] = a.ymax[q] = -INFINITY;
-        a.yb[q] = a.xl[q] = INFINITY;
-        a.yt[q] = a.xr[q] = -INFINITY;
-        a.ib[q] = a.it[q] = a.il[q] = a.ir[q] = 0x7fffffff;
-        a.sumx[q] = a.sumy[q] = 0.0;
-    }
-}
-
-// Least value, then least index (the first vertex among equals, as a sequential scan with
-// strict comparisons keeps).
-__device__ inline void arg_lo(double& v, int& k, double v2, int k2) {
+// (value, index) pairs ordered by value, then index: the least pair is the first vertex
+// among those with the least value, as a sequential scan with strict comparisons keeps.
+__device__ inline void lexmin(double& v, int& k, double v2, int k2) {
     if (v2 < v || (v2 == v && k2 < k)) {
         v = v2;
         k = k2;
     }
 }
-__device__ inline void arg_hi(double& v, int& k, double v2, int k2) {
-    if (v2 > v || (v2 == v && k2 < k)) {
-        v = v2;
-        k = k2;
-    }
-}
 
-__device__ inline void vacc_merge(VAcc& a, const VAcc& b) {
-    a.bad |= b.bad;
-    a.sx = fmax(a.sx, b.sx);
-    a.sy = fmax(a.sy, b.sy);
-    for (int q = 0; q < 2; q++) {
-        a.xmin[q] = fmin(a.xmin[q], b.xmin[q]);
-        a.xmax[q] = fmax(a.xmax[q], b.xmax[q]);
-        a.ymin[q] = fmin(a.ymin[q], b.ymin[q]);
-        a.ymax[q] = fmax(a.ymax[q], b.ymax[q]);
-        arg_lo(a.yb[q], a.ib[q], b.yb[q], b.ib[q]);
-        arg_hi(a.yt[q], a.it[q], b.yt[q], b.it[q]);
-        arg_lo(a.xl[q], a.il[q], b.xl[q], b.il[q]);
-        arg_hi(a.xr[q], a.ir[q], b.xr[q], b.ir[q]);
-        a.sumx[q] += b.sumx[q];
-        a.sumy[q] += b.sumy[q];
-    }
-}
-
-constexpr int T_PLAN = 256;
-
-// Block reduction of a trivially copyable accumulator through LDS (every thread calls it;
-// thread 0 holds the result).
-template <class A, class F>
-__device__ inline void block_reduce(A& a, A* sh, F merge) {
-    sh[threadIdx.x] = a;
-    __syncthreads();
-    for (int w = T_PLAN / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) merge(sh[threadIdx.x], sh[threadIdx.x + w]);
-        __syncthreads();
-    }
-    a = sh[0];
-    __syncthreads();
-}
-
-// Certificate discs of a turning body's posed polygon (the host's formula; the centroid
-// sum is taken in another order, which moves the discs by rounding only, far inside their
-// margins).
-struct CAcc {
-    double rin, rr;
+// Block reductions of F fields through LDS: every thread stores its partials, then each
+// wavefront reduces a field at a time (four loads per lane, then six exchange rounds), so
+// one exchange per round and field instead of one per round for every field.
+template <int F>
+struct PlanScratch {
+    double v[F][T_PLAN];
+    int k[F][T_PLAN];
+    double rv[F];
+    int rk[F];
 };
+constexpr int PLAN_F = 8;
 
-__device__ inline void posed(const PlanConst& P, const Pose& px, const Pose& py, int k, double& x, double& y) {
-    double bx = P.body[2 * k], by = P.body[2 * k + 1];
-    x = (px.cs * bx - px.sn * by) + px.cx;
-    y = (py.sn * bx + py.cs * by) + py.cy;
+// Least (value, index) pair of each field; the results in sc.rv / sc.rk for every thread.
+template <int F>
+__device__ inline void block_lexmin(const double* v, const int* k, PlanScratch<PLAN_F>& sc) {
+#pragma unroll
+    for (int f = 0; f < F; f++) {
+        sc.v[f][threadIdx.x] = v[f];
+        sc.k[f][threadIdx.x] = k[f];
+    }
+    __syncthreads();
+    int lane = threadIdx.x & 63;
+    for (int f = threadIdx.x >> 6; f < F; f += T_PLAN / 64) {
+        double bv = sc.v[f][lane];
+        int bk = sc.k[f][lane];
+        for (int j = lane + 64; j < T_PLAN; j += 64) lexmin(bv, bk, sc.v[f][j], sc.k[f][j]);
+        for (int off = 32; off > 0; off >>= 1) lexmin(bv, bk, __shfl_xor(bv, off, 64), __shfl_xor(bk, off, 64));
+        if (lane == 0) {
+            sc.rv[f] = bv;
+            sc.rk[f] = bk;
+        }
+    }
+    __syncthreads();
+}
+// Sum of each field (any order); the results in sc.rv for every thread.
+template <int F>
+__device__ inline void block_sum(const double* v, PlanScratch<PLAN_F>& sc) {
+#pragma unroll
+    for (int f = 0; f < F; f++) sc.v[f][threadIdx.x] = v[f];
+    __syncthreads();
+    int lane = threadIdx.x & 63;
+    for (int f = threadIdx.x >> 6; f < F; f += T_PLAN / 64) {
+        double bv = sc.v[f][lane];
+        for (int j = lane + 64; j < T_PLAN; j += 64) bv += sc.v[f][j];
+        for (int off = 32; off > 0; off >>= 1) bv += __shfl_xor(bv, off, 64);
+        if (lane == 0) sc.rv[f] = bv;
+    }
+    __syncthreads();
 }
 
-// A step that does nothing: no geometry jobs, empty sweep boxes, no dense direction.
+// Copy of n bytes (a multiple of 8) by the whole block.
+__device__ inline void block_copy(void* dst, const void* src, size_t n) {
+    for (size_t k = threadIdx.x; k < n / 8; k += blockDim.x)
+        ((unsigned long long*)dst)[k] = ((const unsigned long long*)src)[k];
+}
+
+// The parts of a step's arguments that make it do nothing: no geometry jobs, empty sweep
+// boxes, no dense direction.
 __device__ inline void null_step(const PlanConst& P, const PlanState& S, StepArgs& a) {
-    a = P.base;
     a.geo[0].active = a.geo[1].active = 0;
     for (int s = 0; s < 2; s++) {
         a.sw[s].B = Box{0, 0, 0, 0};
@@ -203,44 +186,68 @@ __device__ inline void null_step(const PlanConst& P, const PlanState& S, StepArg
 // clock advanced, direction order reversed).  One block of T_PLAN threads.
 __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ PC, PlanState* __restrict__ PS,
                                                   StepArgs* __restrict__ out, double* __restrict__ dt_log) {
-    const PlanConst& P = *PC;
+    // everything the block reads more than once is staged in LDS first (one round trip):
+    // the planning is a chain of short dependent steps, each of which would otherwise wait
+    // for memory
+    __shared__ PlanConst P;
     __shared__ PlanState S;
-    __shared__ VAcc sh[T_PLAN];
+    __shared__ PlanScratch<PLAN_F> sc;
     __shared__ double sdt;
     __shared__ int halt;
+    const double* body = PC->body;
+    int m = PC->m;
+    double bxv[PLAN_VPT], byv[PLAN_VPT];
+#pragma unroll
+    for (int r = 0; r < PLAN_VPT; r++) {
+        int k = threadIdx.x + r * T_PLAN;
+        bxv[r] = k < m ? body[2 * k] : 0.0;
+        byv[r] = k < m ? body[2 * k + 1] : 0.0;
+    }
+    block_copy(&P, PC, sizeof(PlanConst));
+    block_copy(&S, PS, sizeof(PlanState));
+    // the constant arguments go out first; the step's own fields are written over them
+    block_copy(out, &PC->base, sizeof(StepArgs));
+    double sx = __longlong_as_double((long long)PC->base.cfl_out[0]);
+    double sy = __longlong_as_double((long long)PC->base.cfl_out[1]);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        S = *PS;
         halt = S.halt;
         if (!halt) {
             unsigned int st = __hip_atomic_load(P.base.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (st & (1u | 2u | 8u)) halt = HALT_STATUS;
         }
+        if (!halt && !(isfinite(sx) && isfinite(sy))) halt = HALT_SPEEDS;
     }
-    __syncthreads();
-    double sx = __longlong_as_double((long long)P.base.cfl_out[0]);
-    double sy = __longlong_as_double((long long)P.base.cfl_out[1]);
-    if (!halt && threadIdx.x == 0 && !(isfinite(sx) && isfinite(sy))) halt = HALT_SPEEDS;
-    __syncthreads();
-    int m = P.m;
     double t0 = S.t;
     Pose q0 = pose_at_dev(P, t0);
-    // vertex speeds at t^n (the rigid velocity of each vertex of the posed body)
-    if (!halt && m > 0) {
+    bool turning = P.amp != 0.0;
+    auto pose_k = [&](const Pose& px, const Pose& py, int r, double& x, double& y) {
+        x = (px.cs * bxv[r] - px.sn * byv[r]) + px.cx;
+        y = (py.sn * bxv[r] + py.cs * byv[r]) + py.cy;
+    };
+    // vertex speeds at t^n: the rigid velocity of each vertex of the posed body (a body
+    // that does not turn moves every vertex with v)
+    if (m > 0 && !turning) {
+        sx = fmax(sx, fabs(P.vx));
+        sy = fmax(sy, fabs(P.vy));
+    } else if (m > 0) {
         double thd = P.amp * P.omega * cos(P.omega * t0);
         double cx = P.ref_x + P.vx * t0, cy = P.ref_y + P.vy * t0;
-        VAcc a;
-        vacc_init(a, sx, sy);
-        for (int k = threadIdx.x; k < m; k += T_PLAN) {
+        double v[2] = {-sx, -sy};  // maxima as least negated values
+        int kk[2] = {0, 0};
+#pragma unroll
+        for (int r = 0; r < PLAN_VPT; r++) {
+            if ((int)threadIdx.x + r * T_PLAN >= m) continue;
             double x, y;
-            posed(P, q0, q0, k, x, y);
+            pose_k(q0, q0, r, x, y);
             double ux = P.vx - thd * (y - cy);
             double uy = P.vy + thd * (x - cx);
-            a.sx = fmax(a.sx, fabs(ux));
-            a.sy = fmax(a.sy, fabs(uy));
+            v[0] = fmin(v[0], -fabs(ux));
+            v[1] = fmin(v[1], -fabs(uy));
         }
-        block_reduce(a, sh, vacc_merge);
-        sx = a.sx;
-        sy = a.sy;
+        block_lexmin<2>(v, kk, sc);
+        sx = -sc.rv[0];
+        sy = -sc.rv[1];
     }
     if (threadIdx.x == 0) {
         double dt = P.cfl * fmin(P.hx / sx, P.hy / sy);
@@ -253,35 +260,61 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
     Pose q1 = pose_at_dev(P, t1);
     // stage polygon: the first sweep's coordinate at t^{n+1}, the other at t^n
     Pose mx = S.parity == 0 ? q1 : q0, my = S.parity == 0 ? q0 : q1;
-    VAcc a;
-    vacc_init(a, 0.0, 0.0);
-    if (!halt && m > 0) {
-        for (int k = threadIdx.x; k < m; k += T_PLAN) {
-            double x0, y0, x1, y1, xm, ym;
-            posed(P, q0, q0, k, x0, y0);
-            posed(P, q1, q1, k, x1, y1);
-            posed(P, mx, my, k, xm, ym);
-            if (!(fabs(x1 - x0) < P.hx) || !(fabs(y1 - y0) < P.hy)) a.bad = 1;
-            double xs[2] = {xm, x1}, ys[2] = {ym, y1};
-            for (int q = 0; q < 2; q++) {
-                a.xmin[q] = fmin(a.xmin[q], xs[q]);
-                a.xmax[q] = fmax(a.xmax[q], xs[q]);
-                a.ymin[q] = fmin(a.ymin[q], ys[q]);
-                a.ymax[q] = fmax(a.ymax[q], ys[q]);
-                arg_lo(a.yb[q], a.ib[q], ys[q], k);
-                arg_hi(a.yt[q], a.it[q], ys[q], k);
-                arg_lo(a.xl[q], a.il[q], xs[q], k);
-                arg_hi(a.xr[q], a.ir[q], xs[q], k);
-                a.sumx[q] += xs[q];
-                a.sumy[q] += ys[q];
-            }
-        }
-        block_reduce(a, sh, vacc_merge);
+    // per polygon (0: stage, 1: end) the least y, greatest y, least x, greatest x with the
+    // first vertex attaining each (greatest values as least negated values)
+    double ev[PLAN_F];
+    int ek[PLAN_F];
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int f = 0; f < PLAN_F; f++) {
+        ev[f] = INFINITY;
+        ek[f] = 0x7fffffff;
     }
-    // discs of a turning body's polygons
+    int bad = 0;
+    if (!halt && m > 0) {
+#pragma unroll
+        for (int r = 0; r < PLAN_VPT; r++) {
+            int k = threadIdx.x + r * T_PLAN;
+            if (k >= m) continue;
+            double x0, y0, x1, y1, xm, ym;
+            pose_k(q0, q0, r, x0, y0);
+            pose_k(q1, q1, r, x1, y1);
+            pose_k(mx, my, r, xm, ym);
+            if (!(fabs(x1 - x0) < P.hx) || !(fabs(y1 - y0) < P.hy)) bad = 1;
+            lexmin(ev[0], ek[0], ym, k);
+            lexmin(ev[1], ek[1], -ym, k);
+            lexmin(ev[2], ek[2], xm, k);
+            lexmin(ev[3], ek[3], -xm, k);
+            lexmin(ev[4], ek[4], y1, k);
+            lexmin(ev[5], ek[5], -y1, k);
+            lexmin(ev[6], ek[6], x1, k);
+            lexmin(ev[7], ek[7], -x1, k);
+            sums[0] += xm;
+            sums[1] += ym;
+            sums[2] += x1;
+            sums[3] += y1;
+        }
+    }
+    bad = __syncthreads_or(bad);
+    if (!halt && m > 0) block_lexmin<PLAN_F>(ev, ek, sc);
+    double ext_v[PLAN_F];
+    int ext_k[PLAN_F];
+#pragma unroll
+    for (int f = 0; f < PLAN_F; f++) {
+        ext_v[f] = sc.rv[f];
+        ext_k[f] = sc.rk[f];
+    }
+    double csum[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!halt && m > 0 && turning) {
+        __syncthreads();
+        block_sum<4>(sums, sc);
+#pragma unroll
+        for (int f = 0; f < 4; f++) csum[f] = sc.rv[f];
+    }
+    // certificate discs
     Cert cq[2] = {P.cert0, P.cert0};
     if (!halt && m > 0) {
-        if (P.amp == 0.0) {
+        if (!turning) {
             if (P.cert0.rin2 >= 0.0) {
                 cq[0].cx += mx.cx;
                 cq[0].cy += my.cy;
@@ -292,148 +325,185 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
             for (int q = 0; q < 2; q++) {
                 cq[q] = Cert{0.0, 0.0, -1.0, 0.0};
                 if (m < 8) continue;
-                double cx = a.sumx[q] / m, cy = a.sumy[q] / m;
+                double cx = (q == 0 ? csum[0] : csum[2]) / m, cy = (q == 0 ? csum[1] : csum[3]) / m;
                 const Pose& px = q == 0 ? mx : q1;
                 const Pose& py = q == 0 ? my : q1;
-                CAcc c{INFINITY, 0.0};
-                for (int k = threadIdx.x; k < m; k += T_PLAN) {
+                double cv[2] = {INFINITY, -0.0};  // least distance to an edge line, least negated squared radius
+                int ck[2] = {0, 0};
+#pragma unroll
+                for (int r = 0; r < PLAN_VPT; r++) {
+                    int k = threadIdx.x + r * T_PLAN;
+                    if (k >= m) continue;
                     int k1 = k + 1 == m ? 0 : k + 1;
-                    double x, y, x1, y1;
-                    posed(P, px, py, k, x, y);
-                    posed(P, px, py, k1, x1, y1);
+                    double x, y;
+                    pose_k(px, py, r, x, y);
+                    double b1x = body[2 * k1], b1y = body[2 * k1 + 1];
+                    double x1 = (px.cs * b1x - px.sn * b1y) + px.cx;
+                    double y1 = (py.sn * b1x + py.cs * b1y) + py.cy;
                     double ex = x1 - x, ey = y1 - y;
                     double l2 = ex * ex + ey * ey;
-                    if (l2 > 0.0) c.rin = fmin(c.rin, (ex * (cy - y) - ey * (cx - x)) / sqrt(l2));
+                    if (l2 > 0.0) cv[0] = fmin(cv[0], (ex * (cy - y) - ey * (cx - x)) / sqrt(l2));
                     double dx = x - cx, dy = y - cy;
-                    c.rr = fmax(c.rr, dx * dx + dy * dy);
+                    cv[1] = fmin(cv[1], -(dx * dx + dy * dy));
                 }
-                CAcc* shc = reinterpret_cast<CAcc*>(sh);
-                block_reduce(c, shc, [](CAcc& u, const CAcc& v) {
-                    u.rin = fmin(u.rin, v.rin);
-                    u.rr = fmax(u.rr, v.rr);
-                });
-                double rout = sqrt(c.rr);
-                if (c.rin > 1e-7 * rout && isfinite(c.rin)) {
+                __syncthreads();
+                block_lexmin<2>(cv, ck, sc);
+                double rin = sc.rv[0], rout = sqrt(-sc.rv[1]);
+                if (rin > 1e-7 * rout && isfinite(rin)) {
                     cq[q].cx = cx;
                     cq[q].cy = cy;
-                    cq[q].rin2 = (c.rin * (1.0 - 1e-6)) * (c.rin * (1.0 - 1e-6));
+                    cq[q].rin2 = (rin * (1.0 - 1e-6)) * (rin * (1.0 - 1e-6));
                     cq[q].rout2 = (rout * (1.0 + 1e-6)) * (rout * (1.0 + 1e-6));
                 }
             }
         }
     }
-    if (threadIdx.x != 0) return;
-    if (!halt && m > 0 && a.bad) halt = HALT_MOTION;
+    // the step's scalars, in three stages: the two polygons and the motion (one thread
+    // each), the regions, boxes and checks (one thread), then the argument block written by
+    // the whole block (the level records are most of it)
+    __shared__ Poly spl[2];
+    __shared__ Box scb[2], sreg[2], sB[2];
+    __shared__ int slv[6];  // levels copied into: geo 0, geo 1, sweep 0 start/end, sweep 1 start/end
+    if (!halt && m > 0 && threadIdx.x < 2) {
+        bool q0s = threadIdx.x == 0;  // constant indices keep the arrays in registers
+        int q = threadIdx.x;
+        Poly Q = S.lev[q == 0 ? S.sm : S.s1].poly;
+        Q.m = m;
+        Q.ymin = q0s ? ext_v[0] : ext_v[4];
+        Q.ymax = -(q0s ? ext_v[1] : ext_v[5]);
+        Q.xmin = q0s ? ext_v[2] : ext_v[6];
+        Q.xmax = -(q0s ? ext_v[3] : ext_v[7]);
+        Q.ib = q0s ? ext_k[0] : ext_k[4];
+        Q.it = q0s ? ext_k[1] : ext_k[5];
+        Q.il = q0s ? ext_k[2] : ext_k[6];
+        Q.ir = q0s ? ext_k[3] : ext_k[7];
+        const Cert& C = q0s ? cq[0] : cq[1];
+        Q.cx = C.cx;
+        Q.cy = C.cy;
+        Q.rin2 = C.rin2;
+        Q.rout2 = C.rout2;
+        spl[q] = Q;
+        scb[q] = cells_of_bbox(Q.xmin, Q.xmax, Q.ymin, Q.ymax, P.x_lo, P.x_hi, P.y_lo, P.y_hi, P.hx, P.hy, P.nx, P.ny);
+    }
+    __shared__ Motion smot;
+    if (threadIdx.x == 64) {  // another wavefront: the motion's trigonometry runs beside the boxes
+        Motion M = S.mot;
+        if (!halt && m > 0) {
+            // rigid map of the step and the wall velocity at mid-step
+            // a body that does not turn has th1 - th0 = 0 exactly: cos 1, sin 0 (exact values)
+            double th0 = turning ? P.theta0 + P.amp * sin(P.omega * t0) : P.theta0;
+            double th1 = turning ? P.theta0 + P.amp * sin(P.omega * t1) : P.theta0;
+            M.cosd = turning ? cos(th1 - th0) : 1.0;
+            M.sind = turning ? sin(th1 - th0) : 0.0;
+            M.c0x = P.ref_x + P.vx * t0;
+            M.c0y = P.ref_y + P.vy * t0;
+            M.c1x = P.ref_x + P.vx * t1;
+            M.c1y = P.ref_y + P.vy * t1;
+            double th = t0 + 0.5 * dt;
+            M.vx = P.vx;
+            M.vy = P.vy;
+            M.thd = P.amp * P.omega * (P.omega == 0.0 ? 1.0 : cos(P.omega * th));  // cos 0 = 1
+            M.chx = P.ref_x + P.vx * th;
+            M.chy = P.ref_y + P.vy * th;
+        }
+        smot = M;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (!halt && m > 0 && bad) halt = HALT_MOTION;
+        if (!halt && m > 0) {
+            Box rm = box_union(S.lbox[S.sm], scb[0]), r1 = box_union(S.lbox[S.s1], scb[1]);
+            auto fits = [&](const Box& r) { return box_empty(r) || (r.w() <= P.gw && r.h() <= P.gh); };
+            if (!fits(rm) || !fits(r1)) {
+                halt = HALT_REGION;
+            } else {
+                S.lev[S.sm].poly = spl[0];
+                S.lev[S.s1].poly = spl[1];
+                S.lbox[S.sm] = scb[0];
+                S.lbox[S.s1] = scb[1];
+                sreg[0] = rm;
+                sreg[1] = r1;
+            }
+        }
+        if (!halt) {
+            S.mot = smot;
+            slv[0] = S.sm;
+            slv[1] = S.s1;
+            slv[2] = S.s0;
+            slv[3] = S.sm;
+            slv[4] = S.sm;
+            slv[5] = S.s1;
+            for (int s = 0; s < 2; s++) {
+                sB[s] = sweep_box_of(S.lbox[slv[2 + 2 * s]], S.lbox[slv[3 + 2 * s]], P.nx, P.ny);
+                if (!box_empty(sB[s]) && (sB[s].w() > P.capw || sB[s].h() > P.caph)) halt = HALT_SWEEP_CAP;
+            }
+        }
+    }
+    __syncthreads();
     StepArgs& A = *out;
     if (halt) {
-        null_step(P, S, A);
-        S.halt = halt;
-        *PS = S;
-        return;
-    }
-    A = P.base;
-    if (m > 0) {
-        Poly pl[2];
-        Box cb[2];
-        for (int q = 0; q < 2; q++) {
-            Poly& Q = pl[q];
-            Q = S.lev[q == 0 ? S.sm : S.s1].poly;
-            Q.m = m;
-            Q.xmin = a.xmin[q];
-            Q.xmax = a.xmax[q];
-            Q.ymin = a.ymin[q];
-            Q.ymax = a.ymax[q];
-            Q.ib = a.ib[q];
-            Q.it = a.it[q];
-            Q.il = a.il[q];
-            Q.ir = a.ir[q];
-            Q.cx = cq[q].cx;
-            Q.cy = cq[q].cy;
-            Q.rin2 = cq[q].rin2;
-            Q.rout2 = cq[q].rout2;
-            cb[q] = cells_of_bbox(Q.xmin, Q.xmax, Q.ymin, Q.ymax, P.x_lo, P.x_hi, P.y_lo, P.y_hi, P.hx, P.hy, P.nx,
-                                  P.ny);
-        }
-        Box rm = box_union(S.lbox[S.sm], cb[0]), r1 = box_union(S.lbox[S.s1], cb[1]);
-        auto fits = [&](const Box& r) { return box_empty(r) || (r.w() <= P.gw && r.h() <= P.gh); };
-        if (!fits(rm) || !fits(r1)) {
+        if (threadIdx.x == 0) {
             null_step(P, S, A);
-            S.halt = HALT_REGION;
-            *PS = S;
-            return;
+            S.halt = halt;
         }
-        S.lev[S.sm].poly = pl[0];
-        S.lev[S.s1].poly = pl[1];
-        S.lbox[S.sm] = cb[0];
-        S.lbox[S.s1] = cb[1];
-        const int slot[2] = {S.sm, S.s1};
-        const Box reg[2] = {rm, r1};
-        const Pose px[2] = {mx, q1}, py[2] = {my, q1};
-        for (int k = 0; k < 2; k++) {
-            GeoJob& J = A.geo[k];
-            J.L = S.lev[slot[k]];
-            J.reg = reg[k];
-            J.cs_x = px[k].cs;
-            J.sn_x = px[k].sn;
-            J.cx_x = px[k].cx;
-            J.cs_y = py[k].cs;
-            J.sn_y = py[k].sn;
-            J.cy_y = py[k].cy;
-            J.active = !box_empty(reg[k]);
+    } else {
+        // level records: 6 x 16 words, one word per thread
+        constexpr int LW = sizeof(Level) / 8;
+        if (threadIdx.x < 6 * LW) {
+            int r = threadIdx.x / LW, w = threadIdx.x % LW;
+            Level* dst = r == 0 ? &A.geo[0].L : r == 1 ? &A.geo[1].L : r == 2 ? &A.sw[0].Ls
+                       : r == 3 ? &A.sw[0].Le : r == 4 ? &A.sw[1].Ls : &A.sw[1].Le;
+            ((unsigned long long*)dst)[w] = ((const unsigned long long*)&S.lev[slv[r]])[w];
         }
-        // rigid map of the step and the wall velocity at mid-step
-        double th0 = P.amp == 0.0 ? P.theta0 : P.theta0 + P.amp * sin(P.omega * t0);
-        double th1 = P.amp == 0.0 ? P.theta0 : P.theta0 + P.amp * sin(P.omega * t1);
-        Motion& M = S.mot;
-        M.cosd = cos(th1 - th0);
-        M.sind = sin(th1 - th0);
-        M.c0x = P.ref_x + P.vx * t0;
-        M.c0y = P.ref_y + P.vy * t0;
-        M.c1x = P.ref_x + P.vx * t1;
-        M.c1y = P.ref_y + P.vy * t1;
-        double th = t0 + 0.5 * dt;
-        M.vx = P.vx;
-        M.vy = P.vy;
-        M.thd = P.amp * P.omega * cos(P.omega * th);
-        M.chx = P.ref_x + P.vx * th;
-        M.chy = P.ref_y + P.vy * th;
-    }
-    A.mot = S.mot;
-    for (int s = 0; s < 2; s++) {
-        SweepJob& J = A.sw[s];
-        int first = s == 0;
-        int sl = first ? S.s0 : S.sm, el = first ? S.sm : S.s1;
-        J.Ls = S.lev[sl];
-        J.Le = S.lev[el];
-        J.B = sweep_box_of(S.lbox[sl], S.lbox[el], P.nx, P.ny);
-        J.dir = first ? S.parity : 1 - S.parity;
-        J.first = first;
-        J.lam = dt / (J.dir == 0 ? P.hx : P.hy);
-        int rin = first ? S.cur : 1 - S.cur;
-        J.Uin = P.u[rin];
-        J.Uout = P.u[1 - rin];
-        if (!box_empty(J.B) && (J.B.w() > P.capw || J.B.h() > P.caph)) {
-            null_step(P, S, A);
-            S.halt = HALT_SWEEP_CAP;
-            *PS = S;
-            return;
+        int tid = (int)threadIdx.x - 6 * LW;
+        if (m > 0 && (tid == 0 || tid == 1)) {
+            GeoJob& J = A.geo[tid];
+            Pose px = tid == 0 ? mx : q1;
+            Pose py = tid == 0 ? my : q1;
+            J.reg = sreg[tid];
+            J.cs_x = px.cs;
+            J.sn_x = px.sn;
+            J.cx_x = px.cx;
+            J.cs_y = py.cs;
+            J.sn_y = py.sn;
+            J.cy_y = py.cy;
+            J.active = !box_empty(sreg[tid]);
+        }
+        if (tid == 2 || tid == 3) {
+            int s = tid - 2;
+            SweepJob& J = A.sw[s];
+            int first = s == 0;
+            J.B = sB[s];
+            J.dir = first ? S.parity : 1 - S.parity;
+            J.first = first;
+            J.lam = dt / (J.dir == 0 ? P.hx : P.hy);
+            int rin = first ? S.cur : 1 - S.cur;
+            J.Uin = P.u[rin];
+            J.Uout = P.u[1 - rin];
+        }
+        if (tid == 4) {
+            A.mot = S.mot;
+            A.step_id = (int32_t)(S.step & 0x7fffffff);
+            A.cfl_alpha = S.lev[S.s1].alpha;
+            A.cfl_U = P.u[S.cur];
         }
     }
-    A.step_id = (int32_t)(S.step & 0x7fffffff);
-    A.cfl_alpha = S.lev[S.s1].alpha;
-    A.cfl_U = P.u[S.cur];
-    S.last_sweep_box = A.sw[1].B;
-    // the step's end: slots swapped, clock advanced, the direction order reversed
-    dt_log[S.steps] = dt;
-    S.step_dt = dt;
-    int tmp = S.s0;
-    S.s0 = S.s1;
-    S.s1 = tmp;
-    S.t = t0 + dt;
-    S.step++;
-    S.parity ^= 1;
-    S.steps++;
-    *PS = S;
+    __syncthreads();  // every stage-C reader of S is done
+    if (!halt && threadIdx.x == 0) {
+        S.last_sweep_box = sB[1];
+        // the step's end: slots swapped, clock advanced, the direction order reversed
+        dt_log[S.steps] = dt;
+        S.step_dt = dt;
+        int tmp = S.s0;
+        S.s0 = S.s1;
+        S.s1 = tmp;
+        S.t = t0 + dt;
+        S.step++;
+        S.parity ^= 1;
+        S.steps++;
+    }
+    __syncthreads();
+    block_copy(PS, &S, sizeof(PlanState));
 }
 
 }  // namespace cc
