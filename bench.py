@@ -14,6 +14,7 @@ mode, p50/p99 step latency, the roofline of the dominant kernel (the dense sweep
 events on the library's stream, and the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -165,12 +166,26 @@ COPY_BYTES = 16 << 20
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "dense_sweep_1024x512_hbm_traffic.md")
 
 
+DENSE_SOURCES = ("cc_device.h", "sweep.h", "engine.h")
+
+
+def dense_fingerprint():
+    """Hash of the sources the dense-sweep kernels are compiled from."""
+    h = hashlib.sha256()
+    for f in DENSE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1711_11361_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def traffic_table():
     """Per-dispatch HBM bytes of every dense-sweep kernel variant, from the committed counter
-    summary (the JSON block in it), or {} when it is absent."""
+    summary (the JSON block in it), or {} when it is absent or was taken from other kernel
+    sources than the current ones."""
     try:
         txt = open(TRAFFIC_TABLE).read()
-        return json.loads(txt.split("```json")[1].split("```")[0])["kernels"]
+        d = json.loads(txt.split("```json")[1].split("```")[0])
+        return d["kernels"] if d.get("source") == dense_fingerprint() else {}
     except (OSError, IndexError, KeyError, ValueError):
         return {}
 

@@ -156,8 +156,9 @@ cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
 cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
 
 /* Tile tuner for the dense sweeps (the regular cells): times every tile shape of both
- * sweeps on this grid, reps launches each, from the current state into the spare state
- * buffer, and keeps the fastest for this context.  h_choice (nullable, host, 2 entries)
+ * sweeps on this grid, reps launches each (as a step launches them: beside the first box
+ * phase), from the current state into the spare state buffer, and keeps the fastest for
+ * this context (the current variant unless another is at least 3 % faster).  h_choice (nullable, host, 2 entries)
  * receives the chosen variant indices.  Needs a state and no open step (CC_ERR_ARG).
  * Synchronizes; results do not depend on the choice (every shape computes the same
  * values, bit for bit). */
