@@ -204,7 +204,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+              "(how the path would shard is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     if args.probe:
         probe()
