@@ -196,7 +196,8 @@ struct cc_ctx {
     int m;
     std::vector<double> bverts;
     double ref_x, ref_y, theta0, vx, vy, amp, omega;
-    Cert cert0;  // discs of the body turned by theta0 (used while it does not turn)
+    Cert cert0;      // discs of the body turned by theta0 (used while it does not turn)
+    Extremes ext0;   // its extreme coordinates and the vertices attaining them
     int cur;  // U[cur] holds the level-n state
     Level lev[3];
     Box lbox[3];  // region of each slot that may differ from all-fluid
@@ -312,6 +313,20 @@ Cert poly_cert(const double* pv, int m) {
     return q;
 }
 
+// Extremes of a polygon (first vertices attaining them, as a sequential scan with strict
+// comparisons finds them).
+Extremes body_extremes(const double* pv, int m) {
+    Extremes X{pv[0], pv[0], pv[1], pv[1], 0.0, 0, 0, 0, 0};
+    for (int k = 1; k < m; k++) {
+        if (pv[2 * k] < X.xlo) X.xlo = pv[2 * k], X.il = k;
+        if (pv[2 * k] > X.xhi) X.xhi = pv[2 * k], X.ir = k;
+        if (pv[2 * k + 1] < X.ylo) X.ylo = pv[2 * k + 1], X.ib = k;
+        if (pv[2 * k + 1] > X.yhi) X.yhi = pv[2 * k + 1], X.it = k;
+    }
+    X.mag = std::max(std::max(std::fabs(X.xlo), std::fabs(X.xhi)), std::max(std::fabs(X.ylo), std::fabs(X.yhi)));
+    return X;
+}
+
 // Bounding box, certificate discs and cell box of a polygon posed with x from pose px and
 // y from pose py.  A body that does not turn is only translated from step to step, which
 // moves its discs with it: their radii and the centroid's offset from the pose origin are
@@ -320,20 +335,32 @@ Cert poly_cert(const double* pv, int m) {
 void poly_info(const cc_ctx* c, const double* pv, const Pose& px, const Pose& py, Poly& P, Box& cells) {
     int m = c->m;
     P.m = m;
-    P.xmin = P.ymin = INFINITY;
-    P.xmax = P.ymax = -INFINITY;
-    for (int k = 0; k < m; k++) {
-        P.xmin = std::fmin(P.xmin, pv[2 * k]);
-        P.xmax = std::fmax(P.xmax, pv[2 * k]);
-        P.ymin = std::fmin(P.ymin, pv[2 * k + 1]);
-        P.ymax = std::fmax(P.ymax, pv[2 * k + 1]);
-    }
-    P.ib = P.it = P.il = P.ir = 0;
-    for (int k = 1; k < m; k++) {
-        if (pv[2 * k + 1] < pv[2 * P.ib + 1]) P.ib = k;
-        if (pv[2 * k + 1] > pv[2 * P.it + 1]) P.it = k;
-        if (pv[2 * k] < pv[2 * P.il]) P.il = k;
-        if (pv[2 * k] > pv[2 * P.ir]) P.ir = k;
+    if (c->amp == 0.0) {  // translated: the turned body's extremes plus the translation
+        const Extremes& X = c->ext0;
+        P.xmin = X.xlo + px.cx;
+        P.xmax = X.xhi + px.cx;
+        P.ymin = X.ylo + py.cy;
+        P.ymax = X.yhi + py.cy;
+        P.il = X.il;
+        P.ir = X.ir;
+        P.ib = X.ib;
+        P.it = X.it;
+    } else {
+        P.xmin = P.ymin = INFINITY;
+        P.xmax = P.ymax = -INFINITY;
+        for (int k = 0; k < m; k++) {
+            P.xmin = std::fmin(P.xmin, pv[2 * k]);
+            P.xmax = std::fmax(P.xmax, pv[2 * k]);
+            P.ymin = std::fmin(P.ymin, pv[2 * k + 1]);
+            P.ymax = std::fmax(P.ymax, pv[2 * k + 1]);
+        }
+        P.ib = P.it = P.il = P.ir = 0;
+        for (int k = 1; k < m; k++) {
+            if (pv[2 * k + 1] < pv[2 * P.ib + 1]) P.ib = k;
+            if (pv[2 * k + 1] > pv[2 * P.it + 1]) P.it = k;
+            if (pv[2 * k] < pv[2 * P.il]) P.il = k;
+            if (pv[2 * k] > pv[2 * P.ir]) P.ir = k;
+        }
     }
     Cert q = c->amp == 0.0 ? c->cert0 : poly_cert(pv, m);
     if (c->amp == 0.0 && q.rin2 >= 0.0) {
@@ -481,18 +508,30 @@ cc_status prepare_step(cc_ctx* c, double dt, StepArgs& a) {
     if (c->m > 0) {
         int m = c->m;
         Pose q0 = pose_at(c, c->t), q1 = pose_at(c, t1);
-        std::vector<double> p0(2 * m), p1(2 * m), pm(2 * m);
-        pose_xy(c, q0, q0, p0.data());
-        pose_xy(c, q1, q1, p1.data());
         // stage polygon: the first sweep's coordinate at t^{n+1}, the other at t^n
         Pose mx = c->parity == 0 ? q1 : q0, my = c->parity == 0 ? q0 : q1;
-        pose_xy(c, mx, my, pm.data());
-        cc_status st = check_motion(c, p0, p1);
-        if (st != CC_OK) return st;
+        // a body that does not turn needs its vertices only when its translation is close
+        // to a cell (its extremes follow from the turned body's)
+        bool turning = c->amp != 0.0;
+        bool check = turning || !(surely_within(q0.cx, q1.cx, c->hx, c->ext0.mag) &&
+                                  surely_within(q0.cy, q1.cy, c->hy, c->ext0.mag));
+        std::vector<double> p1, pm;
+        if (check) {
+            std::vector<double> p0(2 * m);
+            p1.resize(2 * m);
+            pose_xy(c, q0, q0, p0.data());
+            pose_xy(c, q1, q1, p1.data());
+            cc_status st = check_motion(c, p0, p1);
+            if (st != CC_OK) return st;
+        }
+        if (turning) {
+            pm.resize(2 * m);
+            pose_xy(c, mx, my, pm.data());
+        }
         Poly Pm = c->lev[c->sm].poly, P1 = c->lev[c->s1].poly;
         Box cm, c1;
-        poly_info(c, pm.data(), mx, my, Pm, cm);
-        poly_info(c, p1.data(), q1, q1, P1, c1);
+        poly_info(c, turning ? pm.data() : nullptr, mx, my, Pm, cm);
+        poly_info(c, turning ? p1.data() : nullptr, q1, q1, P1, c1);
         Box rm = box_union(c->lbox[c->sm], cm), r1 = box_union(c->lbox[c->s1], c1);
         if (!geo_fits(c, rm) || !geo_fits(c, r1)) return fail(c, CC_ERR_WORKSPACE, "geometry region exceeds capacity");
         c->lev[c->sm].poly = Pm;
@@ -715,7 +754,7 @@ void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int last
     if (which & 1) klaunch(kb_patch<0, R>, nb, T_BOX, s, A, ob, n, sw);
     if (which & 2) klaunch(kb_patch<1, R>, nb, T_BOX, s, A, ob, n, sw);
     klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw, last);
-    klaunch(kb_fix_block<R>, n, T_FIX, s, A, koff(E, L_DX), koff(E, L_DY), ob, sw, last, E.d_gather);
+    klaunch(kb_fix_block<R>, n, T_FIX, s, E.d_args, koff(E, L_DX), koff(E, L_DY), ob, sw, last, E.d_gather);
 }
 
 template <typename R>
@@ -835,27 +874,21 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
     (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)E.cap_n + 8 * (size_t)n, hipMemcpyDeviceToHost, s);
 }
 
-// A device-planned step of a single context: the planning block writes the step's
-// arguments (and advances the device bookkeeping), then the per-phase launches.  dir0: the
-// step's first direction, which the host knows from the step count alone.
+// A device-planned step of a single context: its arguments were written on the device
+// (by the planning launch for the first step of a run, by the previous step's last block
+// for the others), which also plans the next one.  dir0: the step's first direction, which
+// the host knows from the step count alone.
 template <typename R>
-void planned_sequence(const Engine& E, hipStream_t s, int dir0, const PlanConst* pc, PlanState* ps, double* dtlog) {
-    hipLaunchKernelGGL(kb_plan, dim3(1), dim3(T_PLAN), 0, s, pc, ps, E.d_args, dtlog);
-    step_kernels<R>(E, s, dir0);
-}
-
-template <typename R>
-hipError_t engine_planned_step(Engine& E, hipStream_t s, int dir0, const PlanConst* pc, PlanState* ps,
-                               double* dtlog) {
+hipError_t engine_planned_step(Engine& E, hipStream_t s, int dir0) {
     if (!s) {  // the null stream cannot be captured: individual launches
-        planned_sequence<R>(E, s, dir0, pc, ps, dtlog);
+        step_kernels<R>(E, s, dir0);
         return hipGetLastError();
     }
     if (!E.pexec[dir0]) {
         hipGraph_t gr;
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        planned_sequence<R>(E, s, dir0, pc, ps, dtlog);
+        step_kernels<R>(E, s, dir0);
         e = hipStreamEndCapture(s, &gr);
         if (e != hipSuccess) return e;
         e = hipGraphInstantiate(&E.pexec[dir0], gr, nullptr, nullptr, 0);
@@ -944,6 +977,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         std::vector<double> pv(2 * (size_t)c->m);
         pose_xy(c, q0, q0, pv.data());
         c->cert0 = poly_cert(pv.data(), c->m);
+        c->ext0 = body_extremes(pv.data(), c->m);
     }
     c->cur = 0;
     c->s0 = 0;
@@ -1384,6 +1418,9 @@ namespace {
 void plan_const(cc_ctx* c, double cfl, PlanConst& P) {
     std::memset(&P, 0, sizeof(P));
     base_args(c, P.base);
+    P.base.pc = at<PlanConst>(c, c->lay.off_pconst);
+    P.base.ps = at<PlanState>(c, c->lay.off_pstate);
+    P.base.dtlog = at<double>(c, c->lay.off_dtlog);
     P.body = at<double>(c, c->lay.off_body);
     P.m = c->m;
     P.ref_x = c->ref_x;
@@ -1396,6 +1433,7 @@ void plan_const(cc_ctx* c, double cfl, PlanConst& P) {
     P.cs0 = std::cos(c->theta0);
     P.sn0 = std::sin(c->theta0);
     P.cert0 = c->cert0;
+    P.ext0 = c->ext0;
     P.x_lo = c->cfg.x_lo;
     P.x_hi = c->cfg.x_hi;
     P.y_lo = c->cfg.y_lo;
@@ -1500,11 +1538,19 @@ cc_status advance(cc_ctx* c, int nsteps, double cfl, double* h_dt, float* h_step
         int n = std::min(nsteps - done, DTLOG);
         PlanState S;
         plan_state_from(c, S);
+        S.remaining = n;
         hipError_t e = hipMemcpyAsync(dps, &S, sizeof(S), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[done], c->stream);
+        // the run's first step is planned by a launch of its own, every later one by the
+        // last block of the step before it
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(kb_plan, dim3(1), dim3(T_PLAN), 0, c->stream, (const PlanConst*)dpc, dps, E.d_args,
+                               dlog);
+            e = hipGetLastError();
+        }
         for (int k = 0; k < n && e == hipSuccess; k++) {
-            e = engine_planned_step<R>(E, c->stream, (c->parity + k) & 1, dpc, dps, dlog);
+            e = engine_planned_step<R>(E, c->stream, (c->parity + k) & 1);
             if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[done + k + 1], c->stream);
         }
         if (e == hipSuccess) e = hipMemcpyAsync(&S, dps, sizeof(S), hipMemcpyDeviceToHost, c->stream);

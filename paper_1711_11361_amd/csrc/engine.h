@@ -12,6 +12,9 @@
 
 namespace cc {
 
+struct PlanConst;
+struct PlanState;
+
 struct StepArgs {
     Grid g;
     GeoJob geo[2];   // stage level and end level of the step
@@ -31,7 +34,14 @@ struct StepArgs {
     unsigned long long* cfl_out;   // 2: max (|u|+a) along x and y, as bit patterns
     unsigned long long* spd;       // partial maxima of a captured step: a pair per dense tile of
     int spd_dense;                 // the second sweep, then (from pair spd_dense on) per box block
+    // a device-planned run: the block that combines the wave speeds also plans the next
+    // step (null otherwise)
+    const PlanConst* pc;
+    PlanState* ps;
+    double* dtlog;
 };
+
+__device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, StepArgs* out, double* dt_log);
 
 // Launch kinds and their block sizes.
 enum LaunchKind {
@@ -395,9 +405,9 @@ __device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, in
 // the whole box, with a block barrier between the rounds.  last: the sweep is the last of
 // a captured step; the block then also combines the member's wave-speed partials (the box
 // cells' speeds recomputed here when a round moved content) and gathers its status words.
-constexpr int T_FIX = 1024;
+constexpr int T_FIX = 256;
 template <typename R>
-__global__ __launch_bounds__(T_FIX) void kb_fix_block(const StepArgs* __restrict__ A, const int* __restrict__ off_dx,
+__global__ __launch_bounds__(T_FIX) void kb_fix_block(StepArgs* A, const int* __restrict__ off_dx,
                                                       const int* __restrict__ off_dy,
                                                       const int* __restrict__ off_box, int s, int last,
                                                       unsigned int* __restrict__ gather) {
@@ -428,6 +438,11 @@ __global__ __launch_bounds__(T_FIX) void kb_fix_block(const StepArgs* __restrict
     const int* od = a.sw[1].dir == 0 ? off_dx : off_dy;
     // with recomputed box speeds the box blocks' partials (of the covered state) are skipped
     combine_speeds(a, od[u + 1] - od[u], bad ? 0 : off_box[u + 1] - off_box[u], gather, u, bx, by);
+    const PlanConst* pc = a.pc;
+    PlanState* ps = a.ps;
+    double* dl = a.dtlog;
+    __syncthreads();  // the combined speeds are written; the step's arguments are read no more
+    if (pc) plan_block(pc, ps, &A[u], dl);
 }
 
 // ------------------------------------------------------------------ time step

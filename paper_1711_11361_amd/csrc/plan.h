@@ -21,6 +21,25 @@ struct Cert {
     double cx, cy, rin2, rout2;
 };
 
+// Extreme coordinates of the body turned by theta0 about the pose origin, and the first
+// vertices attaining them.  A body that does not turn is only translated: rounding is
+// monotone, so each posed extreme is the turned extreme plus the translation, rounded, and
+// is attained at the same vertex (a vertex that ties with it after rounding is an extreme
+// as well).  mag: the largest of their magnitudes.
+struct Extremes {
+    double xlo, xhi, ylo, yhi, mag;
+    int il, ir, ib, it;
+};
+
+// True when a translation from c0 to c1 surely moves every vertex by less than h along
+// that axis, the rounding of the posed coordinates included (mag: the turned body's
+// largest coordinate magnitude); false means: check the vertices one by one.
+__host__ __device__ inline bool surely_within(double c0, double c1, double h, double mag) {
+    double d = fabs(c1 - c0);
+    double C = fmax(fabs(c0), fabs(c1));
+    return d + 0x1p-49 * (mag + C + d) < h;
+}
+
 __host__ __device__ inline bool box_empty(const Box& b) { return b.i0 >= b.i1 || b.j0 >= b.j1; }
 
 __host__ __device__ inline Box box_union(const Box& a, const Box& b) {
@@ -77,6 +96,7 @@ struct PlanConst {
     double ref_x, ref_y, theta0, vx, vy, amp, omega;
     double cs0, sn0;  // cos and sin of theta0 (the pose of a body that does not turn)
     Cert cert0;       // discs of the body turned by theta0 about the pose origin
+    Extremes ext0;    // its extreme coordinates
     double x_lo, x_hi, y_lo, y_hi, hx, hy;
     int nx, ny, gw, gh, capw, caph;
     char* u[2];  // the two state buffers
@@ -89,6 +109,7 @@ struct PlanState {
     long long step;
     int parity, s0, sm, s1, cur;
     int halt, steps;  // halt code; steps planned in this run
+    int remaining;    // steps still to plan in this run
     Box lbox[3];
     Level lev[3];
     Motion mot;
@@ -114,9 +135,10 @@ __device__ inline void lexmin(double& v, int& k, double v2, int k2) {
     }
 }
 
-// Block reductions of F fields through LDS: every thread stores its partials, then each
-// wavefront reduces a field at a time (four loads per lane, then six exchange rounds), so
-// one exchange per round and field instead of one per round for every field.
+// Block reductions of F fields through LDS: the first T_PLAN threads store their partials,
+// then each wavefront of the block reduces a field at a time (four loads per lane, then six
+// exchange rounds), so one exchange per round and field instead of one per round for every
+// field.
 template <int F>
 struct PlanScratch {
     double v[F][T_PLAN];
@@ -129,14 +151,16 @@ constexpr int PLAN_F = 8;
 // Least (value, index) pair of each field; the results in sc.rv / sc.rk for every thread.
 template <int F>
 __device__ inline void block_lexmin(const double* v, const int* k, PlanScratch<PLAN_F>& sc) {
+    if (threadIdx.x < T_PLAN) {
 #pragma unroll
-    for (int f = 0; f < F; f++) {
-        sc.v[f][threadIdx.x] = v[f];
-        sc.k[f][threadIdx.x] = k[f];
+        for (int f = 0; f < F; f++) {
+            sc.v[f][threadIdx.x] = v[f];
+            sc.k[f][threadIdx.x] = k[f];
+        }
     }
     __syncthreads();
     int lane = threadIdx.x & 63;
-    for (int f = threadIdx.x >> 6; f < F; f += T_PLAN / 64) {
+    for (int f = threadIdx.x >> 6; f < F; f += blockDim.x / 64) {
         double bv = sc.v[f][lane];
         int bk = sc.k[f][lane];
         for (int j = lane + 64; j < T_PLAN; j += 64) lexmin(bv, bk, sc.v[f][j], sc.k[f][j]);
@@ -151,11 +175,13 @@ __device__ inline void block_lexmin(const double* v, const int* k, PlanScratch<P
 // Sum of each field (any order); the results in sc.rv for every thread.
 template <int F>
 __device__ inline void block_sum(const double* v, PlanScratch<PLAN_F>& sc) {
+    if (threadIdx.x < T_PLAN) {
 #pragma unroll
-    for (int f = 0; f < F; f++) sc.v[f][threadIdx.x] = v[f];
+        for (int f = 0; f < F; f++) sc.v[f][threadIdx.x] = v[f];
+    }
     __syncthreads();
     int lane = threadIdx.x & 63;
-    for (int f = threadIdx.x >> 6; f < F; f += T_PLAN / 64) {
+    for (int f = threadIdx.x >> 6; f < F; f += blockDim.x / 64) {
         double bv = sc.v[f][lane];
         for (int j = lane + 64; j < T_PLAN; j += 64) bv += sc.v[f][j];
         for (int off = 32; off > 0; off >>= 1) bv += __shfl_xor(bv, off, 64);
@@ -183,9 +209,11 @@ __device__ inline void null_step(const PlanConst& P, const PlanState& S, StepArg
 
 // One step's planning: dt from the speeds the last step left (cfl_out), then the poses,
 // regions, boxes and motion of the step, then the bookkeeping of its end (slots swapped,
-// clock advanced, direction order reversed).  One block of T_PLAN threads.
-__global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ PC, PlanState* __restrict__ PS,
-                                                  StepArgs* __restrict__ out, double* __restrict__ dt_log) {
+// clock advanced, direction order reversed); nothing once the run's steps are planned.
+// The whole block calls it (at least T_PLAN threads; the first T_PLAN do the vertex work):
+// the first step of a run in a launch of its own, every later one at the end of the step
+// before it, in the block that combines that step's wave speeds.
+__device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, StepArgs* out, double* dt_log) {
     // everything the block reads more than once is staged in LDS first (one round trip):
     // the planning is a chain of short dependent steps, each of which would otherwise wait
     // for memory
@@ -196,15 +224,18 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
     __shared__ int halt;
     const double* body = PC->body;
     int m = PC->m;
+    bool worker = threadIdx.x < T_PLAN;
     double bxv[PLAN_VPT], byv[PLAN_VPT];
 #pragma unroll
     for (int r = 0; r < PLAN_VPT; r++) {
         int k = threadIdx.x + r * T_PLAN;
-        bxv[r] = k < m ? body[2 * k] : 0.0;
-        byv[r] = k < m ? body[2 * k + 1] : 0.0;
+        bxv[r] = worker && k < m ? body[2 * k] : 0.0;
+        byv[r] = worker && k < m ? body[2 * k + 1] : 0.0;
     }
-    block_copy(&P, PC, sizeof(PlanConst));
     block_copy(&S, PS, sizeof(PlanState));
+    __syncthreads();
+    if (S.remaining <= 0) return;
+    block_copy(&P, PC, sizeof(PlanConst));
     // the constant arguments go out first; the step's own fields are written over them
     block_copy(out, &PC->base, sizeof(StepArgs));
     double sx = __longlong_as_double((long long)PC->base.cfl_out[0]);
@@ -237,7 +268,7 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
         int kk[2] = {0, 0};
 #pragma unroll
         for (int r = 0; r < PLAN_VPT; r++) {
-            if ((int)threadIdx.x + r * T_PLAN >= m) continue;
+            if (!worker || (int)threadIdx.x + r * T_PLAN >= m) continue;
             double x, y;
             pose_k(q0, q0, r, x, y);
             double ux = P.vx - thd * (y - cy);
@@ -270,17 +301,22 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
         ev[f] = INFINITY;
         ek[f] = 0x7fffffff;
     }
+    // a body that does not turn is translated: its extremes follow from the turned body's,
+    // and the motion check needs the vertices only when the translation is close to a cell
+    bool check = turning || !(surely_within(q0.cx, q1.cx, P.hx, P.ext0.mag) &&
+                              surely_within(q0.cy, q1.cy, P.hy, P.ext0.mag));
     int bad = 0;
-    if (!halt && m > 0) {
+    if (!halt && m > 0 && check) {
 #pragma unroll
         for (int r = 0; r < PLAN_VPT; r++) {
             int k = threadIdx.x + r * T_PLAN;
-            if (k >= m) continue;
+            if (!worker || k >= m) continue;
             double x0, y0, x1, y1, xm, ym;
             pose_k(q0, q0, r, x0, y0);
             pose_k(q1, q1, r, x1, y1);
-            pose_k(mx, my, r, xm, ym);
             if (!(fabs(x1 - x0) < P.hx) || !(fabs(y1 - y0) < P.hy)) bad = 1;
+            if (!turning) continue;
+            pose_k(mx, my, r, xm, ym);
             lexmin(ev[0], ek[0], ym, k);
             lexmin(ev[1], ek[1], -ym, k);
             lexmin(ev[2], ek[2], xm, k);
@@ -296,13 +332,30 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
         }
     }
     bad = __syncthreads_or(bad);
-    if (!halt && m > 0) block_lexmin<PLAN_F>(ev, ek, sc);
     double ext_v[PLAN_F];
     int ext_k[PLAN_F];
+    if (!halt && m > 0 && turning) {
+        block_lexmin<PLAN_F>(ev, ek, sc);
 #pragma unroll
-    for (int f = 0; f < PLAN_F; f++) {
-        ext_v[f] = sc.rv[f];
-        ext_k[f] = sc.rk[f];
+        for (int f = 0; f < PLAN_F; f++) {
+            ext_v[f] = sc.rv[f];
+            ext_k[f] = sc.rk[f];
+        }
+    } else {
+        const Extremes& X = P.ext0;
+        const Pose* px[2] = {&mx, &q1};
+        const Pose* py[2] = {&my, &q1};
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            ext_v[4 * q + 0] = X.ylo + py[q]->cy;
+            ext_v[4 * q + 1] = -(X.yhi + py[q]->cy);
+            ext_v[4 * q + 2] = X.xlo + px[q]->cx;
+            ext_v[4 * q + 3] = -(X.xhi + px[q]->cx);
+            ext_k[4 * q + 0] = X.ib;
+            ext_k[4 * q + 1] = X.it;
+            ext_k[4 * q + 2] = X.il;
+            ext_k[4 * q + 3] = X.ir;
+        }
     }
     double csum[4] = {0.0, 0.0, 0.0, 0.0};
     if (!halt && m > 0 && turning) {
@@ -333,7 +386,7 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
 #pragma unroll
                 for (int r = 0; r < PLAN_VPT; r++) {
                     int k = threadIdx.x + r * T_PLAN;
-                    if (k >= m) continue;
+                    if (!worker || k >= m) continue;
                     int k1 = k + 1 == m ? 0 : k + 1;
                     double x, y;
                     pose_k(px, py, r, x, y);
@@ -489,6 +542,7 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
         }
     }
     __syncthreads();  // every stage-C reader of S is done
+    if (threadIdx.x == 0) S.remaining--;
     if (!halt && threadIdx.x == 0) {
         S.last_sweep_box = sB[1];
         // the step's end: slots swapped, clock advanced, the direction order reversed
@@ -504,6 +558,10 @@ __global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* __restrict__ 
     }
     __syncthreads();
     block_copy(PS, &S, sizeof(PlanState));
+}
+
+__global__ __launch_bounds__(T_PLAN) void kb_plan(const PlanConst* PC, PlanState* PS, StepArgs* out, double* dt_log) {
+    plan_block(PC, PS, out, dt_log);
 }
 
 }  // namespace cc
