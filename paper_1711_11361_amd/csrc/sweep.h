@@ -190,31 +190,44 @@ __device__ int donors(const Grid& g, const Level& Ls, const R* U, int i, int j, 
 }
 
 // ------------------------------------------------------------------ wall quantities
-__device__ __forceinline__ bool cell_cut(const Grid& g, const Level& L, int i, int j) {
-    double b[4] = {beta_x(g, L, i, j), beta_x(g, L, i + 1, j), beta_y(g, L, i, j), beta_y(g, L, i, j + 1)};
+// The solid intervals of the four faces of cell (i, j) in a level: x-faces i and i + 1,
+// y-faces j and j + 1 (loaded together, so that their latencies overlap).
+struct CellFaces {
+    double2 f[4];
+};
+__device__ __forceinline__ CellFaces cell_faces(const Grid& g, const Level& L, int i, int j) {
+    CellFaces c;
+    c.f[0] = L.fx[(size_t)j * (g.nx + 1) + i];
+    c.f[1] = L.fx[(size_t)j * (g.nx + 1) + i + 1];
+    c.f[2] = L.fy[(size_t)j * g.nx + i];
+    c.f[3] = L.fy[(size_t)(j + 1) * g.nx + i];
+    return c;
+}
+__device__ __forceinline__ bool cell_cut_f(const CellFaces& c) {
     int ones = 0, zeros = 0;
+#pragma unroll
     for (int k = 0; k < 4; k++) {
-        ones += b[k] == 1.0;
-        zeros += b[k] == 0.0;
+        double b = interval_beta(c.f[k]);
+        ones += b == 1.0;
+        zeros += b == 0.0;
     }
     return ones != 4 && zeros != 4;
 }
 
 // Mean of the boundary crossing points on the cell's faces; cell centre if none.
-__device__ void wall_point(const Grid& g, const Level& L, int i, int j, double* wx, double* wy) {
+__device__ void wall_point(const Grid& g, const CellFaces& c, int i, int j, double* wx, double* wy) {
     double sx = 0.0, sy = 0.0;
     int n = 0;
+#pragma unroll
     for (int e = 0; e < 4; e++) {
-        double2 iv;
+        double2 iv = c.f[e];
         double ox, oy, dx, dy;
         if (e < 2) {
-            iv = L.fx[(size_t)j * (g.nx + 1) + i + e];
             ox = vx_of(g, i + e);
             oy = vy_of(g, j);
             dx = 0.0;
             dy = g.hy;
         } else {
-            iv = L.fy[(size_t)(j + e - 2) * g.nx + i];
             ox = vx_of(g, i);
             oy = vy_of(g, j + e - 2);
             dx = g.hx;
@@ -282,10 +295,18 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
     int i = B.i0 + t % B.w(), j = B.j0 + t / B.w();
     size_t nc = (size_t)g.nx * g.ny, k = (size_t)j * g.nx + i;
     int cap = S.cap;
+    // everything the cell's own quantities need, loaded up front
     double as = Ls.alpha[k], ae = Le.alpha[k];
     double u[4];
 #pragma unroll
     for (int m = 0; m < 4; m++) u[m] = (double)U[m * nc + k];
+    CellFaces fs = cell_faces(g, Ls, i, j), fe = cell_faces(g, Le, i, j);
+    double bt_lo = S.bt[fidx<D>(B, i, j)];
+    double bt_hi = D == 0 ? S.bt[fidx<0>(B, i + 1, j)] : S.bt[fidx<1>(B, i, j + 1)];
+    int32_t stamp = C.stamp[k];
+    double qb_old[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) qb_old[m] = C.qb[m * nc + k];
     bool uncovered = as == 0.0 && ae > 0.0;
     bool emptied = as > 0.0 && ae > 0.0 && !(u[0] > 0.0);
     double q[4] = {0, 0, 0, 0};
@@ -317,16 +338,24 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
             }
         }
     } else if (as > 0.0 && u[0] > 0.0) {
-        // a live cell may donate to emptied neighbours (visited in increasing cell order)
+        // a live cell may donate to emptied neighbours (visited in increasing cell order);
+        // the neighbours' fractions and densities are loaded together first (indices
+        // clamped into the grid; the ones outside it are skipped below)
+        unsigned emptied = 0u;  // bit q: neighbour q (row-major in the 3 x 3 block) is emptied
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            int li = min(max(i + q % 3 - 1, 0), g.nx - 1), lj = min(max(j + q / 3 - 1, 0), g.ny - 1);
+            size_t l = (size_t)lj * g.nx + li;
+            if (Ls.alpha[l] > 0.0 && Le.alpha[l] > 0.0 && !((double)U[l] > 0.0)) emptied |= 1u << q;
+        }
         double take = 0.0;
         for (int dj = -1; dj <= 1; dj++)
             for (int di = -1; di <= 1; di++) {
                 if (di == 0 && dj == 0) continue;
                 int li = i + di, lj = j + dj;
                 if (li < 0 || li >= g.nx || lj < 0 || lj >= g.ny) continue;
-                size_t l = (size_t)lj * g.nx + li;
-                double asl = Ls.alpha[l], ael = Le.alpha[l];
-                if (!(asl > 0.0 && ael > 0.0 && !((double)U[l] > 0.0))) continue;
+                if (!((emptied >> ((dj + 1) * 3 + (di + 1))) & 1u)) continue;
+                double asl = Ls.alpha[(size_t)lj * g.nx + li];
                 int don[8];
                 int nd = donors(g, Ls, U, li, lj, don);
                 bool mine = false;
@@ -353,15 +382,15 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
     double ab = 0.5 * (as + ae);
     double bw, be, bs, bn;
     if (D == 0) {
-        bw = S.bt[fidx<0>(B, i, j)];
-        be = S.bt[fidx<0>(B, i + 1, j)];
-        bs = 0.5 * (beta_y(g, Ls, i, j) + beta_y(g, Le, i, j));
-        bn = 0.5 * (beta_y(g, Ls, i, j + 1) + beta_y(g, Le, i, j + 1));
+        bw = bt_lo;
+        be = bt_hi;
+        bs = 0.5 * (interval_beta(fs.f[2]) + interval_beta(fe.f[2]));
+        bn = 0.5 * (interval_beta(fs.f[3]) + interval_beta(fe.f[3]));
     } else {
-        bw = 0.5 * (beta_x(g, Ls, i, j) + beta_x(g, Le, i, j));
-        be = 0.5 * (beta_x(g, Ls, i + 1, j) + beta_x(g, Le, i + 1, j));
-        bs = S.bt[fidx<1>(B, i, j)];
-        bn = S.bt[fidx<1>(B, i, j + 1)];
+        bw = 0.5 * (interval_beta(fs.f[0]) + interval_beta(fe.f[0]));
+        be = 0.5 * (interval_beta(fs.f[1]) + interval_beta(fe.f[1]));
+        bs = bt_lo;
+        bn = bt_hi;
     }
     double Nx = (bw - be) * g.hy, Ny = (bs - bn) * g.hx;
     bool wall = ab > 0.0 && (Nx != 0.0 || Ny != 0.0);
@@ -370,17 +399,17 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
         double nn = sqrt(Nx * Nx + Ny * Ny);
         double nxu = Nx / nn, nyu = Ny / nn;
         double wx, wy;
-        bool cs = cell_cut(g, Ls, i, j), ce = cell_cut(g, Le, i, j);
+        bool cs = cell_cut_f(fs), ce = cell_cut_f(fe);
         if (cs && ce) {
             double ax, ay, bx2, by2;
-            wall_point(g, Ls, i, j, &ax, &ay);
-            wall_point(g, Le, i, j, &bx2, &by2);
+            wall_point(g, fs, i, j, &ax, &ay);
+            wall_point(g, fe, i, j, &bx2, &by2);
             wx = 0.5 * (ax + bx2);
             wy = 0.5 * (ay + by2);
         } else if (cs) {
-            wall_point(g, Ls, i, j, &wx, &wy);
+            wall_point(g, fs, i, j, &wx, &wy);
         } else {
-            wall_point(g, Le, i, j, &wx, &wy);
+            wall_point(g, fe, i, j, &wx, &wy);
         }
         double uwx = M.vx - M.thd * (wy - M.chy);
         double uwy = M.vy + M.thd * (wx - M.chx);
@@ -399,7 +428,7 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
             double usx = (u - un * nxu) + wn * nxu;
             double usy = (v - un * nyu) + wn * nyu;
             double qb[4];
-            if (first || C.stamp[k] != step_id) {
+            if (first || stamp != step_id) {
                 qb[0] = rst;
                 qb[1] = rst * usx;
                 qb[2] = rst * usy;
@@ -409,7 +438,7 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
                     C.stamp[k] = step_id;
                 }
             } else {
-                for (int m = 0; m < 4; m++) qb[m] = C.qb[m * nc + k];
+                for (int m = 0; m < 4; m++) qb[m] = qb_old[m];
             }
             double ua = (D == 0 ? qb[1] : qb[2]) / qb[0];
             double us = D == 0 ? usx : usy;
@@ -629,9 +658,21 @@ __device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t) {
     int b = bidx(B, i, j), cap = S.cap;
     size_t nc = (size_t)g.nx * g.ny, k = (size_t)j * g.nx + i;
     double acc[4] = {0, 0, 0, 0};
-    if (!S.gone[b]) {
-        for (int m = 0; m < 4; m++) acc[m] = S.U2[m * cap + b];
-        double aer = Le.alpha[k];
+    // the cell's own values and its neighbours' emptied flags, loaded together (neighbour
+    // indices clamped into the box; the ones outside it are skipped below)
+    int8_t gone_b = S.gone[b];
+    double u2[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) u2[m] = S.U2[m * cap + b];
+    double aer = Le.alpha[k];
+    unsigned gn = 0u;  // bit q: neighbour q (row-major in the 3 x 3 block) was emptied
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+        int ci = min(max(i + q % 3 - 1, B.i0), B.i1 - 1), cj = min(max(j + q / 3 - 1, B.j0), B.j1 - 1);
+        if (S.gone[bidx(B, ci, cj)]) gn |= 1u << q;
+    }
+    if (!gone_b) {
+        for (int m = 0; m < 4; m++) acc[m] = u2[m];
         if (aer > 0.0) {
             for (int dj = -1; dj <= 1; dj++)
                 for (int di = -1; di <= 1; di++) {
@@ -639,7 +680,7 @@ __device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t) {
                     int ci = i + di, cj = j + dj;
                     if (!B.has(ci, cj)) continue;
                     int cb = bidx(B, ci, cj);
-                    if (!S.gone[cb]) continue;
+                    if (!((gn >> ((dj + 1) * 3 + (di + 1))) & 1u)) continue;
                     // recipients of the emptied cell (ci, cj)
                     int rec[8], nr = 0;
                     for (int pass = 0; pass < 2 && nr == 0; pass++) {
@@ -668,8 +709,8 @@ __device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t) {
         Uout[m * nc + k] = (R)acc[m];
         S.U1[m * cap + b] = acc[m];
     }
-    int8_t f = S.gone[b] ? 2 : 0;
-    if (!f && Le.alpha[k] > 0.0 && inadmissible_content(acc)) {
+    int8_t f = gone_b ? 2 : 0;
+    if (!f && aer > 0.0 && inadmissible_content(acc)) {
         f = 1;
         atomicAdd(&S.nbad[0], 1u);
     }
