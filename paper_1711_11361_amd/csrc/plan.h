@@ -444,10 +444,14 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
         if (!halt && m > 0) {
             // rigid map of the step and the wall velocity at mid-step
             // a body that does not turn has th1 - th0 = 0 exactly: cos 1, sin 0 (exact values)
-            double th0 = turning ? P.theta0 + P.amp * sin(P.omega * t0) : P.theta0;
-            double th1 = turning ? P.theta0 + P.amp * sin(P.omega * t1) : P.theta0;
-            M.cosd = turning ? cos(th1 - th0) : 1.0;
-            M.sind = turning ? sin(th1 - th0) : 0.0;
+            M.cosd = 1.0;
+            M.sind = 0.0;
+            if (turning) {
+                double th0 = P.theta0 + P.amp * sin(P.omega * t0);
+                double th1 = P.theta0 + P.amp * sin(P.omega * t1);
+                M.cosd = cos(th1 - th0);
+                M.sind = sin(th1 - th0);
+            }
             M.c0x = P.ref_x + P.vx * t0;
             M.c0y = P.ref_y + P.vy * t0;
             M.c1x = P.ref_x + P.vx * t1;
@@ -455,7 +459,9 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
             double th = t0 + 0.5 * dt;
             M.vx = P.vx;
             M.vy = P.vy;
-            M.thd = P.amp * P.omega * (P.omega == 0.0 ? 1.0 : cos(P.omega * th));  // cos 0 = 1
+            double ct = 1.0;  // cos 0
+            if (P.omega != 0.0) ct = cos(P.omega * th);
+            M.thd = P.amp * P.omega * ct;
             M.chx = P.ref_x + P.vx * th;
             M.chy = P.ref_y + P.vy * th;
         }
