@@ -111,3 +111,23 @@ def test_refusal_at_the_same_step():
     db, _ = b.advance(2, 0.3)
     assert np.array_equal(da, db)
     assert np.array_equal(a.get_u(), b.get_u())
+
+
+@pytest.mark.parametrize("name", ["cylinder_1024x512", "naca_4096x4096"])
+def test_full_size_device_planned_steps(name):
+    """The benchmark's grid (bit for bit) and the pitching aerofoil's (round-off)."""
+    w = W.cylinder() if name.startswith("cylinder") else W.naca()
+    a, b = solver(w, cc.CC_FP32_GEOM64), solver(w, cc.CC_FP32_GEOM64)
+    n = 4
+    da = host_steps(a, w["cfl"], n)
+    db, _ = b.advance(n, w["cfl"])
+    Ua, Ub = a.get_u(), b.get_u()
+    if name.startswith("cylinder"):
+        assert np.array_equal(da, db) and np.array_equal(Ua, Ub)
+    else:
+        assert np.abs(da - db).max() <= 1e-12 * da.max()
+        err = max(np.abs(Ua[k] - Ub[k]).max() / np.abs(Ua[k]).max() for k in range(4))
+        assert err <= 1e-5, err  # FP32 state: one rounding of the state apart at most
+    assert a.info()["status"] == b.info()["status"] == 0
+    a.close()
+    b.close()
