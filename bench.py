@@ -77,8 +77,19 @@ def run_mode(precision, steps, warmup, w):
     U = s.get_u()
     assert np.isfinite(U).all()
     cells = w["grid"]["nx"] * w["grid"]["ny"]
+    fluid = int((s.geometry_dump(0)["alpha"] > 0.0).sum())  # cells with fluid at the end
+    # surface loads of the end state (force and moment on the body), timed per call
+    loads = s.surface_loads()
+    nl = 50
+    l0 = time.perf_counter()
+    for _ in range(nl):
+        s.surface_loads()
+    loads_us = 1e6 * (time.perf_counter() - l0) / nl
     T = t1 - t0
-    return {"value": cells * steps / T, "ms_per_step": 1e3 * T / steps, "lat": lat, "timing": tim,
+    return {"value": cells * steps / T, "fluid_value": fluid * steps / T, "fluid_cells": fluid,
+            "loads": {"force": [float(loads[0]), float(loads[1])], "moment": float(loads[2]),
+                      "us_per_call": loads_us},
+            "ms_per_step": 1e3 * T / steps, "lat": lat, "timing": tim,
             "host_planned_ms_per_step": host_ms,
             "t_end": info["t"], "collapses": info["collapses"], "box_cells": info["box_cells"],
             "tiles": {"x_rows_per_block": info["tile_x_rows"], "y_rows_per_tile": info["tile_y_rows"]}}
@@ -257,6 +268,9 @@ def main():
                                "body speed 1.0, CFL 0.8", "grid": [nx, ny], "cells": nx * ny},
         "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)), "p99": float(np.percentile(r32["lat"], 99))},
         "host_planned_ms_per_step": r32["host_planned_ms_per_step"],
+        "fluid_cell_updates_per_s": r32["fluid_value"],
+        "fluid_cells": r32["fluid_cells"],
+        "surface_loads": r32["loads"],
         "fp64": {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
                  "host_planned_ms_per_step": r64["host_planned_ms_per_step"],
                  "latency_ms": {"p50": float(np.percentile(r64["lat"], 50)),

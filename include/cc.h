@@ -145,6 +145,17 @@ cc_status cc_cfl_dt(cc_ctx* ctx, double cfl, double* h_dt);
  * launches whatever the launch mode.  Not for a context in a batch.  Synchronizes. */
 cc_status cc_advance(cc_ctx* ctx, int32_t nsteps, double cfl, double* h_dt, float* h_step_ms, int32_t* h_done);
 
+/* Surface loads at level n (post-processing of the pitching aerofoil of Sec. 3.6): the sum
+ * over cells with fluid content of p* N, where p* is the wall pressure of the wall Riemann
+ * problem (Eq. riemann_wallvel, HLLC with Davis speeds, reading R9) between the cell state
+ * U/alpha and its mirror image moving with the body at the cell's wall point, and N the
+ * level's effective wall normal ((beta_W - beta_E) hy, (beta_S - beta_N) hx), pointing
+ * into the body (reading R12).  h_out4 (host, 4 doubles): Fx, Fy, the moment Mz about the
+ * body's pose origin, and sum p* |N| (the scale against which the rounding of the other
+ * three is measured).  Deterministic summation order; zeros without a body.  Needs a state
+ * and no open step (CC_ERR_ARG).  Synchronizes. */
+cc_status cc_surface_loads(cc_ctx* ctx, double* h_out4);
+
 /* Conservation totals sum(U) hx hy per component, FP64, deterministic order.  Host out. */
 cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
 

@@ -1350,3 +1350,39 @@ double ccref_clip_area(const double* poly, int m, double ox, double oy, double w
     free(b2);
     return a;
 }
+
+/* Surface loads at level n (post-processing of the pitching aerofoil of Sec. 3.6; reading:
+ * the sum over the cells with fluid content of p* N, p* the wall pressure of the wall
+ * Riemann problem (Eq. riemann_wallvel, reading R9) between the cell state U/alpha and its
+ * mirror image moving with the body at the cell's wall point, N the level's effective wall
+ * normal ((beta_W - beta_E) hy, (beta_S - beta_N) hx), pointing into the body, reading
+ * R12).  out4: Fx, Fy, the moment about the body's pose origin, and sum p* |N|.  Plain
+ * sums in row-major cell order. */
+int ccref_surface_loads(const ccref_ctx* c, double* out4) {
+    for (int k = 0; k < 4; k++) out4[k] = 0.0;
+    if (c->m == 0) return 0;
+    const level_t* L = &c->L[c->s0];
+    size_t nc = (size_t)c->cfg.nx * c->cfg.ny;
+    double cx = c->ref_x + c->vx * c->t, cy = c->ref_y + c->vy * c->t;
+    for (int j = 0; j < c->cfg.ny; j++)
+        for (int i = 0; i < c->cfg.nx; i++) {
+            size_t k = CIDX(c, i, j);
+            double a = L->alpha[k];
+            if (!(a > 0.0) || !(c->U[k] > 0.0)) continue;
+            double Nx = (beta_x(c, L, i, j) - beta_x(c, L, i + 1, j)) * c->hy;
+            double Ny = (beta_y(c, L, i, j) - beta_y(c, L, i, j + 1)) * c->hx;
+            if (Nx == 0.0 && Ny == 0.0) continue;
+            double q[4];
+            for (int m = 0; m < 4; m++) q[m] = c->U[m * nc + k] / a;
+            double nn = sqrt(Nx * Nx + Ny * Ny);
+            double wx, wy, uwx, uwy, ps, rs;
+            wall_point(c, L, i, j, &wx, &wy);
+            body_velocity(c, c->t, wx, wy, &uwx, &uwy);
+            wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, c->cfg.gamma, &ps, &rs);
+            out4[0] += ps * Nx;
+            out4[1] += ps * Ny;
+            out4[2] += (wx - cx) * (ps * Ny) - (wy - cy) * (ps * Nx);
+            out4[3] += ps * nn;
+        }
+    return 0;
+}

@@ -59,6 +59,7 @@ def lib():
         L.ccref_cfl_dt.restype = d
         L.ccref_cfl_dt.argtypes = [vp, d]
         L.ccref_totals.argtypes = [vp, p]
+        L.ccref_surface_loads.argtypes = [vp, p]
         L.ccref_budget.argtypes = [vp, p, p, p]
         L.ccref_sweep.argtypes = [vp, i, d]
         L.ccref_begin_step.argtypes = [vp, d]
@@ -283,6 +284,12 @@ class Oracle:
     def totals(self):
         out = np.zeros(4)
         lib().ccref_totals(self._h, _dp(out))
+        return out
+
+    def surface_loads(self):
+        """(Fx, Fy, Mz about the pose origin, sum p*|N|) of the gas on the body at level n."""
+        out = np.zeros(4)
+        lib().ccref_surface_loads(self._h, _dp(out))
         return out
 
     def budget(self):

@@ -62,6 +62,7 @@ _sig = {
     "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
     "cc_advance": (C.c_int, [_vp, _i32, _d, C.POINTER(_d), C.POINTER(C.c_float), C.POINTER(_i32)]),
     "cc_totals": (C.c_int, [_vp, C.POINTER(_d)]),
+    "cc_surface_loads": (C.c_int, [_vp, C.POINTER(_d)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
     "cc_set_tiles": (C.c_int, [_vp, _i32, _i32]),
@@ -199,6 +200,12 @@ def cc_advance(ctx, nsteps, cfl, want_dt=True, want_ms=False):
         raise err
     n = done.value
     return n, (np.array(dts[:n]) if want_dt else None), (np.array(ms[:n]) if want_ms else None)
+
+
+def cc_surface_loads(ctx):
+    out = (_d * 4)()
+    _check(ctx, _lib.cc_surface_loads(ctx, out))
+    return np.array(out[:])
 
 
 def cc_totals(ctx):
@@ -411,6 +418,10 @@ class Solver:
 
     def totals(self):
         return cc_totals(self.ctx)
+
+    def surface_loads(self):
+        """(Fx, Fy, Mz about the pose origin, sum p*|N|) of the gas on the body at level n."""
+        return cc_surface_loads(self.ctx)
 
     def info(self):
         return cc_info(self.ctx)

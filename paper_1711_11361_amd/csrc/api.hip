@@ -15,6 +15,7 @@
 #include "engine.h"
 #include "persist.h"
 #include "plan.h"
+#include "loads.h"
 #include "geometry.h"
 #include "reduce.h"
 #include "sweep.h"
@@ -1614,6 +1615,38 @@ cc_status cc_totals(cc_ctx* c, double* h_totals4) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double area = c->hx * c->hy;
     for (int k = 0; k < 4; k++) h_totals4[k] = h[k] * area;
+    return CC_OK;
+}
+
+cc_status cc_surface_loads(cc_ctx* c, double* h_out4) {
+    if (!c || !h_out4) return fail(c, CC_ERR_ARG, "bad argument");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_surface_loads inside a step");
+    if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
+    for (int k = 0; k < 4; k++) h_out4[k] = 0.0;
+    const Box& reg = c->lbox[c->s0];
+    if (c->m == 0 || box_empty(reg)) return CC_OK;
+    LoadsArgs a;
+    a.g = c->g;
+    a.L = c->lev[c->s0];
+    a.reg = reg;
+    a.vx = c->vx;
+    a.vy = c->vy;
+    a.thd = c->amp * c->omega * std::cos(c->omega * c->t);
+    a.cx = c->ref_x + c->vx * c->t;
+    a.cy = c->ref_y + c->vy * c->t;
+    int blocks = (int)std::min<size_t>(LOADS_MAX_BLOCKS, nblk((size_t)reg.w() * reg.h(), LOADS_T));
+    double* part = at<double>(c, c->lay.off_part);
+    double* out = at<double>(c, c->lay.off_tot);
+    if (fp32(c))
+        hipLaunchKernelGGL(k_loads<float>, dim3(blocks), dim3(LOADS_T), 0, c->stream, a,
+                           (const float*)at<float>(c, c->lay.off_u[c->cur]), part);
+    else
+        hipLaunchKernelGGL(k_loads<double>, dim3(blocks), dim3(LOADS_T), 0, c->stream, a,
+                           (const double*)at<double>(c, c->lay.off_u[c->cur]), part);
+    hipLaunchKernelGGL(k_loads_final, dim3(1), dim3(64), 0, c->stream, blocks, (const double*)part, out);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(h_out4, out, 32, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return CC_OK;
 }
 

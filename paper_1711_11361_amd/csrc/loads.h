@@ -1,0 +1,78 @@
+// Surface loads: force and moment of the gas on the body at level n, from the cut cells'
+// wall pressures (post-processing of the pitching-aerofoil case of Sec. 3.6).  Per cell
+// with fluid content and a wall: p* of the wall Riemann problem (Eq. riemann_wallvel with
+// HLLC/Davis speeds, reading R9) between the cell state U/alpha and its mirror image moving
+// with the body at the cell's wall point, times the level's effective wall normal
+// N = ((beta_W - beta_E) h_y, (beta_S - beta_N) h_x) (reading R12; pointing into the body).
+// Sums: Fx, Fy, Mz about the body's pose origin, and sum p* |N| (the scale against which
+// the rounding of the other three is measured).  Deterministic order: per thread over a
+// fixed stride, per block through a fixed tree, per launch over the blocks in order.
+#pragma once
+#include "sweep.h"
+
+namespace cc {
+
+constexpr int LOADS_T = 256;
+constexpr int LOADS_MAX_BLOCKS = 128;
+
+struct LoadsArgs {
+    Grid g;
+    Level L;    // level n
+    Box reg;    // the cells that may differ from fluid
+    double vx, vy, thd, cx, cy;  // rigid velocity v + thd z x (X - c) at time t
+};
+
+template <typename R>
+__global__ __launch_bounds__(LOADS_T) void k_loads(LoadsArgs a, const R* __restrict__ U, double* __restrict__ part) {
+    const Grid& g = a.g;
+    int w = a.reg.w(), h = a.reg.h();
+    int cells = w > 0 && h > 0 ? w * h : 0;
+    size_t nc = (size_t)g.nx * g.ny;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = blockIdx.x * LOADS_T + threadIdx.x; t < cells; t += gridDim.x * LOADS_T) {
+        int i = a.reg.i0 + t % w, j = a.reg.j0 + t / w;
+        size_t k = (size_t)j * g.nx + i;
+        double al = a.L.alpha[k];
+        double u0 = (double)U[k];
+        if (!(al > 0.0) || !(u0 > 0.0)) continue;
+        CellFaces f = cell_faces(g, a.L, i, j);
+        double Nx = (interval_beta(f.f[0]) - interval_beta(f.f[1])) * g.hy;
+        double Ny = (interval_beta(f.f[2]) - interval_beta(f.f[3])) * g.hx;
+        if (Nx == 0.0 && Ny == 0.0) continue;
+        double q[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k] / al;
+        double nn = sqrt(Nx * Nx + Ny * Ny);
+        double wx, wy;
+        wall_point(g, f, i, j, &wx, &wy);
+        double uwx = a.vx - a.thd * (wy - a.cy);
+        double uwy = a.vy + a.thd * (wx - a.cx);
+        double ps, rs;
+        wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, g.gamma, &ps, &rs);
+        acc[0] += ps * Nx;
+        acc[1] += ps * Ny;
+        acc[2] += (wx - a.cx) * (ps * Ny) - (wy - a.cy) * (ps * Nx);
+        acc[3] += ps * nn;
+    }
+    __shared__ double sh[4][LOADS_T];
+#pragma unroll
+    for (int m = 0; m < 4; m++) sh[m][threadIdx.x] = acc[m];
+    __syncthreads();
+    for (int s = LOADS_T / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int m = 0; m < 4; m++) sh[m][threadIdx.x] += sh[m][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// The blocks' partial sums in block order (one thread per quantity).
+__global__ void k_loads_final(int nblocks, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x >= 4) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; b++) s += part[4 * b + threadIdx.x];
+    out[threadIdx.x] = s;
+}
+
+}  // namespace cc

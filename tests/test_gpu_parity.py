@@ -240,3 +240,34 @@ def test_every_tile_shape_gives_identical_results(precision):
     assert 0 <= tx < 4 and 0 <= ty < len(ys)
     with pytest.raises(cc.CCError):
         s.set_tiles(0, 9)
+
+
+def loads_cases():
+    """(name, workload, oracle steps before the comparison)."""
+    yield "piston30", W.piston(), 40
+    yield "piston_aligned", W.piston(angle_deg=0.0), 40
+    yield "cylinder", W.cylinder(nx=128, ny=64), 30
+    w = W.naca(nx=96, ny=96)
+    w["body"]["pitch_amp"] = math.radians(8.0)
+    w["body"]["pitch_omega"] = 2.0
+    yield "naca_pitch", w, 10
+    yield "req3", W.serving_request(3), 10
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+@pytest.mark.parametrize("name,w,nsteps", list(loads_cases()), ids=[c[0] for c in loads_cases()])
+def test_surface_loads_match_oracle(name, w, nsteps, precision):
+    """Force and moment on the body from identical states: round-off in FP64 (the sums run
+    in another order), the state's FP32 rounding otherwise; relative to sum p*|N|."""
+    o, s = pair(w, precision)
+    for _ in range(nsteps):
+        o.step(o.cfl_dt(w["cfl"]))
+    s.set_clock(o.t, o.steps)
+    s.set_u(o.get_u())
+    lo, lg = o.surface_loads(), s.surface_loads()
+    g = w["grid"]
+    size = max(g["x_hi"] - g["x_lo"], g["y_hi"] - g["y_lo"])
+    tol = 1e-12 if precision == cc.CC_FP64 else 1e-5
+    assert lo[3] > 0.0
+    assert abs(lg[0] - lo[0]) <= tol * lo[3] and abs(lg[1] - lo[1]) <= tol * lo[3], (name, lg, lo)
+    assert abs(lg[2] - lo[2]) <= tol * lo[3] * size and abs(lg[3] - lo[3]) <= tol * lo[3], (name, lg, lo)
