@@ -457,7 +457,6 @@ void base_args(cc_ctx* c, StepArgs& a) {
     for (int k = 0; k < 2; k++) {
         a.bt[k] = at<double>(c, c->lay.off_sbt[k]);
     }
-    a.cfl_part = at<unsigned long long>(c, c->lay.off_part);
     a.cfl_out = at<unsigned long long>(c, c->lay.off_cflout);
     a.nb_cells = geo_blocks(c, GEO_CELLS);
     a.nb_swept = geo_blocks(c, GEO_SWEPT);
@@ -566,8 +565,6 @@ cc_status prepare_step(cc_ctx* c, double dt, StepArgs& a) {
             return fail(c, CC_ERR_WORKSPACE, "sweep region exceeds the staging capacity");
     }
     a.step_id = (int32_t)(c->step & 0x7fffffff);
-    a.cfl_alpha = c->lev[c->s1].alpha;
-    a.cfl_U = c->ws + c->lay.off_u[c->cur];
     c->step_dt = dt;
     c->last_sweep_box = a.sw[1].B;
     return CC_OK;
@@ -612,8 +609,6 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
         case L_BOXW: return (int)nblk(std::max<size_t>(L.cap, 1), T_WIDE);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
-        case L_CFL: return (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(L.nc, T_WIDE));
-        case L_CFLF: return 1;
     }
     return 0;
 }
@@ -756,14 +751,6 @@ void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int last
     if (which & 2) klaunch(kb_patch<1, R>, nb, T_BOX, s, A, ob, n, sw);
     klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw, last);
     klaunch(kb_fix_block<R>, n, T_FIX, s, E.d_args, koff(E, L_DX), koff(E, L_DY), ob, sw, last, E.d_gather);
-}
-
-template <typename R>
-void launch_cfl(const Engine& E, hipStream_t s) {
-    int n = (int)E.mem.size();
-    const StepArgs* A = E.d_args;
-    klaunch(kb_cfl<R>, ktotal(E, L_CFL), T_WIDE, s, A, koff(E, L_CFL), n);
-    klaunch(kb_cfl_final, n, T_WIDE, s, A, koff(E, L_CFL), n);
 }
 
 hipError_t engine_upload(Engine& E, hipStream_t s, int b) {

@@ -27,10 +27,7 @@ struct StepArgs {
     double* bt[2];  // time-averaged apertures of each sweep (box-local faces)
     int nb_cells, nb_swept;  // blocks of the cell stage (both levels) and of one sweep's apertures
     int32_t step_id;
-    // time-step reduction of the state after the step
-    const double* cfl_alpha;
-    const void* cfl_U;
-    unsigned long long* cfl_part;  // 2 per block
+    // wave-speed maxima of the state after the step
     unsigned long long* cfl_out;   // 2: max (|u|+a) along x and y, as bit patterns
     unsigned long long* spd;       // partial maxima of a captured step: a pair per dense tile of
     int spd_dense;                 // the second sweep, then (from pair spd_dense on) per box block
@@ -46,7 +43,7 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
 // Launch kinds and their block sizes.
 enum LaunchKind {
     L_POSE, L_V1, L_F1, L_C1,  // geometry stages (both level jobs)
-    L_S1, L_BOX, L_DX, L_DY, L_CFL, L_CFLF,  // sweeps and time step
+    L_S1, L_BOX, L_DX, L_DY,  // sweeps
     L_CS,  // volume fractions of both levels and the apertures of both sweeps
     L_BOXW,  // box cells, T_WIDE per block (launched beside the dense tiles)
     NKINDS
@@ -443,33 +440,6 @@ __global__ __launch_bounds__(T_FIX) void kb_fix_block(StepArgs* A, const int* __
     double* dl = a.dtlog;
     __syncthreads();  // the combined speeds are written; the step's arguments are read no more
     if (pc) plan_block(pc, ps, &A[u], dl);
-}
-
-// ------------------------------------------------------------------ time step
-// Per-block maxima of |u|+a along x and y over the live cells of each instance (bit
-// patterns of non-negative doubles order like the values; NaN sorts above infinity), then
-// one block per instance combines its partials.
-template <typename R>
-__global__ __launch_bounds__(T_WIDE) void kb_cfl(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                 int n) {
-    Unit w = unit_of(off, n);
-    const StepArgs& a = A[w.u];
-    cfl_block<R>(a.g, a.cfl_alpha, (const R*)a.cfl_U, a.cfl_part, w.lb, w.nb);
-}
-
-__global__ __launch_bounds__(T_WIDE) void kb_cfl_final(const StepArgs* __restrict__ A,
-                                                       const int* __restrict__ off_cfl, int n) {
-    const StepArgs& a = A[blockIdx.x];
-    int nparts = off_cfl[blockIdx.x + 1] - off_cfl[blockIdx.x];
-    cfl_combine(nparts, a.cfl_part, a.cfl_out);
-}
-
-// Status word and collapse count of every instance, gathered for one read-back.
-__global__ void kb_gather(const StepArgs* __restrict__ A, int n, unsigned int* __restrict__ out) {
-    int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    out[2 * u] = *A[u].status;
-    out[2 * u + 1] = *A[u].ncol;
 }
 
 }  // namespace cc

@@ -543,8 +543,6 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
         if (tid == 4) {
             A.mot = S.mot;
             A.step_id = (int32_t)(S.step & 0x7fffffff);
-            A.cfl_alpha = S.lev[S.s1].alpha;
-            A.cfl_U = P.u[S.cur];
         }
     }
     __syncthreads();  // every stage-C reader of S is done
