@@ -237,6 +237,16 @@ cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status);
 cc_status cc_batch_last_dt(cc_batch* b, double cfl, double* h_dt, int32_t* h_status);
 /* Time steps from each member's current state (cc_cfl_dt per member). */
 cc_status cc_batch_cfl_dt(cc_batch* b, double cfl, double* h_dt);
+/* nsteps CFL steps of every member planned on the device, as cc_advance does for one
+ * context (Sec. 4 time step, Sec. 2.3.4 poses), each member with its own time step, in one
+ * launch per phase over all members; results equal those of the members advanced alone.
+ * Host outputs, each nullable: h_dt (members x nsteps doubles, member-major) the time
+ * steps, h_step_ms (nsteps floats) each step's device time, h_done (one per member) the
+ * steps completed.  A member whose step would be refused stops there (its later steps do
+ * nothing) while the others run on; the first such member's status is returned and
+ * cc_batch_last_error names it.  Synchronizes. */
+cc_status cc_batch_advance(cc_batch* b, int32_t nsteps, double cfl, double* h_dt, float* h_step_ms,
+                           int32_t* h_done);
 const char* cc_batch_last_error(const cc_batch* b);
 
 #ifdef __cplusplus

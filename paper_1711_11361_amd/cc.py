@@ -81,6 +81,7 @@ _sig = {
     "cc_batch_step": (C.c_int, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
     "cc_batch_last_dt": (C.c_int, [_vp, _d, C.POINTER(_d), C.POINTER(_i32)]),
     "cc_batch_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
+    "cc_batch_advance": (C.c_int, [_vp, _i32, _d, C.POINTER(_d), C.POINTER(C.c_float), C.POINTER(_i32)]),
     "cc_batch_last_error": (C.c_char_p, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -306,6 +307,23 @@ def cc_batch_last_dt(b, cfl, n):
     return list(d[:n]), list(st[:n])
 
 
+def cc_batch_advance(b, nsteps, cfl, n, want_ms=False):
+    """Returns (per-member time steps as a list of arrays, per-step ms or None, done list);
+    raises CCError on a refused step (with .done, the per-member steps completed)."""
+    dts = (_d * max(n * nsteps, 1))()
+    ms = (C.c_float * max(nsteps, 1))() if want_ms else None
+    done = (_i32 * max(n, 1))()
+    st = _lib.cc_batch_advance(b, nsteps, cfl, dts, ms, done)
+    dn = list(done[:n])
+    if st != CC_OK:
+        raw = _lib.cc_batch_last_error(b)
+        err = CCError(st, raw.decode() if raw else "")
+        err.done = dn
+        raise err
+    out = [np.array(dts[k * nsteps: k * nsteps + dn[k]]) for k in range(n)]
+    return out, (np.array(ms[:nsteps]) if want_ms else None), dn
+
+
 def cc_batch_cfl_dt(b, cfl, n):
     d = (_d * max(n, 1))()
     _bcheck(b, _lib.cc_batch_cfl_dt(b, cfl, d))
@@ -517,3 +535,9 @@ class Batch:
 
     def cfl_dt(self, cfl):
         return cc_batch_cfl_dt(self.b, cfl, len(self.members))
+
+    def advance(self, nsteps, cfl, want_ms=False):
+        """nsteps CFL steps of every member planned on the device; returns (per-member
+        time steps, per-step ms or None)."""
+        dts, ms, _ = cc_batch_advance(self.b, nsteps, cfl, len(self.members), want_ms)
+        return dts, ms

@@ -180,7 +180,7 @@ struct Engine {
     int tile_x = 0, tile_y = 1;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gkey[2] = {-1, -1};
-    hipGraphExec_t pexec[2] = {nullptr, nullptr};  // device-planned step, by its first direction
+    hipGraphExec_t pexec[3] = {nullptr, nullptr, nullptr};  // device-planned step, by first direction + 1
     int mode = 0;                       // 0: one launch per phase; 1: one persistent launch per sweep
     GridSync* d_sync = nullptr;         // barrier counters of the persistent sweep launches
     unsigned long long wait_ticks = 0;  // barrier wait limit (wall-clock ticks)
@@ -618,8 +618,10 @@ void drop_graphs(Engine& E) {
         if (E.gexec[b]) (void)hipGraphExecDestroy(E.gexec[b]);
         E.gexec[b] = nullptr;
         E.gkey[b] = -1;
-        if (E.pexec[b]) (void)hipGraphExecDestroy(E.pexec[b]);
-        E.pexec[b] = nullptr;
+    }
+    for (auto& g : E.pexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
     }
 }
 
@@ -862,28 +864,29 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
     (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)E.cap_n + 8 * (size_t)n, hipMemcpyDeviceToHost, s);
 }
 
-// A device-planned step of a single context: its arguments were written on the device
-// (by the planning launch for the first step of a run, by the previous step's last block
-// for the others), which also plans the next one.  dir0: the step's first direction, which
-// the host knows from the step count alone.
+// A device-planned step: its arguments were written on the device (by the planning launch
+// for the first step of a run, by the previous step's last block for the others), which
+// also plans the next one.  dir0: a single member's first direction, which the host knows
+// from the step count alone; -1 for a batch (both dense kernels).
 template <typename R>
 hipError_t engine_planned_step(Engine& E, hipStream_t s, int dir0) {
     if (!s) {  // the null stream cannot be captured: individual launches
         step_kernels<R>(E, s, dir0);
         return hipGetLastError();
     }
-    if (!E.pexec[dir0]) {
+    hipGraphExec_t& gx = E.pexec[dir0 + 1];
+    if (!gx) {
         hipGraph_t gr;
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
         step_kernels<R>(E, s, dir0);
         e = hipStreamEndCapture(s, &gr);
         if (e != hipSuccess) return e;
-        e = hipGraphInstantiate(&E.pexec[dir0], gr, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         if (e != hipSuccess) return e;
     }
-    return hipGraphLaunch(E.pexec[dir0], s);
+    return hipGraphLaunch(gx, s);
 }
 
 // Launches the captured step graph of host buffer b (capturing it first if needed).
@@ -1472,13 +1475,14 @@ void plan_state_to(cc_ctx* c, const PlanState& S) {
     c->last_sweep_box = S.last_sweep_box;
 }
 
-cc_status halt_error(cc_ctx* c, int halt) {
+// speeds: where the run kept the context's wave-speed maxima.
+cc_status halt_error(cc_ctx* c, int halt, const unsigned long long* speeds) {
     switch (halt) {
         case HALT_STATUS:
         case HALT_SPEEDS: {
             unsigned long long sp[2];
             unsigned int st = 0;
-            HIPCHK(c, hipMemcpyAsync(sp, c->eng.d_cflout, 16, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(sp, speeds, 16, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipMemcpyAsync(&st, at<unsigned int>(c, c->lay.off_status), 4, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             double sx, sy;
@@ -1494,74 +1498,142 @@ cc_status halt_error(cc_ctx* c, int halt) {
     }
 }
 
+// Device-planned steps of every member of engine E (a context's own engine: one member):
+// member k's arguments at E.d_args + k, its speed maxima at E.d_cflout + 2k.  h_dt: member
+// k's time steps at h_dt[k nsteps ...]; done[k]: its completed steps; bad: the first member
+// that stopped early (-1: none), whose error the return value and its message give.
 template <typename R>
-cc_status advance(cc_ctx* c, int nsteps, double cfl, double* h_dt, float* h_step_ms) {
-    Engine& E = c->eng;
-    PlanConst* dpc = at<PlanConst>(c, c->lay.off_pconst);
-    PlanState* dps = at<PlanState>(c, c->lay.off_pstate);
-    double* dlog = at<double>(c, c->lay.off_dtlog);
-    PlanConst P;
-    plan_const(c, cfl, P);
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpyAsync(dpc, &P, sizeof(P), hipMemcpyHostToDevice, c->stream));
-    // wave speeds of the start state: the first step's CFL condition
-    unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
-    int blocks = (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(c->lay.nc));
-    hipLaunchKernelGGL(k_cfl<R>, dim3(blocks), dim3(256), 0, c->stream, c->g, c->lev[c->s0].alpha,
-                       at<R>(c, c->lay.off_u[c->cur]), part);
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, c->stream, blocks, (const unsigned long long*)part,
-                       E.d_cflout);
-    HIPCHK(c, hipGetLastError());
-    std::vector<hipEvent_t> ev;
-    if (h_step_ms) {
-        ev.assign((size_t)nsteps + 1, nullptr);
-        for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
-    }
-    auto drop_events = [&]() {
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
+cc_status advance_members(Engine& E, hipStream_t s, int nsteps, double cfl, double* h_dt, float* h_step_ms,
+                          std::vector<int>& done, int& bad) {
+    int n = (int)E.mem.size();
+    bool single = n == 1 && E.cap_n == 1;
+    cc_ctx* c0 = E.mem[0];
+    done.assign(n, 0);
+    bad = -1;
+    auto dev_fail = [&](hipError_t e) {
+        return fail(c0, CC_ERR_DEVICE, std::string("device-planned steps: ") + hipGetErrorString(e));
     };
-    int done = 0, halt = 0;
-    while (done < nsteps && !halt) {
-        int n = std::min(nsteps - done, DTLOG);
-        PlanState S;
-        plan_state_from(c, S);
-        S.remaining = n;
-        hipError_t e = hipMemcpyAsync(dps, &S, sizeof(S), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[done], c->stream);
-        // the run's first step is planned by a launch of its own, every later one by the
-        // last block of the step before it
+    hipError_t e = hipStreamSynchronize(s);
+    for (int k = 0; k < n && e == hipSuccess; k++) {
+        cc_ctx* c = E.mem[k];
+        PlanConst P;
+        plan_const(c, cfl, P);
+        P.base.cfl_out = E.d_cflout + 2 * k;
+        e = hipMemcpy(at<PlanConst>(c, c->lay.off_pconst), &P, sizeof(P), hipMemcpyHostToDevice);
+        // wave speeds of the start state: the first step's CFL condition
+        unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
+        int blocks = (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(c->lay.nc));
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(kb_plan, dim3(1), dim3(T_PLAN), 0, c->stream, (const PlanConst*)dpc, dps, E.d_args,
-                               dlog);
+            hipLaunchKernelGGL(k_cfl<R>, dim3(blocks), dim3(256), 0, s, c->g, c->lev[c->s0].alpha,
+                               at<R>(c, c->lay.off_u[c->cur]), part);
+            hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, s, blocks, (const unsigned long long*)part,
+                               E.d_cflout + 2 * k);
             e = hipGetLastError();
         }
-        for (int k = 0; k < n && e == hipSuccess; k++) {
-            e = engine_planned_step<R>(E, c->stream, (c->parity + k) & 1);
-            if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[done + k + 1], c->stream);
-        }
-        if (e == hipSuccess) e = hipMemcpyAsync(&S, dps, sizeof(S), hipMemcpyDeviceToHost, c->stream);
-        std::vector<double> dts(n);
-        if (e == hipSuccess) e = hipMemcpyAsync(dts.data(), dlog, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) return dev_fail(e);
+    std::vector<hipEvent_t> ev;
+    auto drop_events = [&]() {
+        for (auto& x : ev)
+            if (x) (void)hipEventDestroy(x);
+    };
+    if (h_step_ms) {
+        ev.assign((size_t)nsteps + 1, nullptr);
+        for (auto& x : ev)
+            if ((e = hipEventCreate(&x)) != hipSuccess) break;
         if (e != hipSuccess) {
             drop_events();
-            return fail(c, CC_ERR_DEVICE, std::string("device-planned steps: ") + hipGetErrorString(e));
+            return dev_fail(e);
         }
-        plan_state_to(c, S);
-        if (h_dt) std::copy(dts.begin(), dts.begin() + S.steps, h_dt + done);
+    }
+    int base = 0;
+    bool running = true;
+    std::vector<int> halted(n, 0);
+    while (base < nsteps && running) {
+        int m = std::min(nsteps - base, DTLOG);
+        std::vector<PlanState> S(n);
+        for (int k = 0; k < n && e == hipSuccess; k++) {
+            plan_state_from(E.mem[k], S[k]);
+            S[k].remaining = m;
+            S[k].halt = halted[k];  // a member that stopped stays stopped
+            e = hipMemcpy(at<PlanState>(E.mem[k], E.mem[k]->lay.off_pstate), &S[k], sizeof(PlanState),
+                          hipMemcpyHostToDevice);
+        }
+        if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[base], s);
+        // the run's first step of each member is planned by a launch of its own, every later
+        // one by the last block of the step before it
+        for (int k = 0; k < n && e == hipSuccess; k++) {
+            cc_ctx* c = E.mem[k];
+            hipLaunchKernelGGL(kb_plan, dim3(1), dim3(T_PLAN), 0, s, (const PlanConst*)at<PlanConst>(c, c->lay.off_pconst),
+                               at<PlanState>(c, c->lay.off_pstate), E.d_args + k, at<double>(c, c->lay.off_dtlog));
+            e = hipGetLastError();
+        }
+        for (int i = 0; i < m && e == hipSuccess; i++) {
+            e = engine_planned_step<R>(E, s, single ? (c0->parity + i) & 1 : -1);
+            if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[base + i + 1], s);
+        }
+        std::vector<double> dts((size_t)n * m);
+        for (int k = 0; k < n && e == hipSuccess; k++) {
+            cc_ctx* c = E.mem[k];
+            e = hipMemcpyAsync(&S[k], at<PlanState>(c, c->lay.off_pstate), sizeof(PlanState), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(dts.data() + (size_t)k * m, at<double>(c, c->lay.off_dtlog), (size_t)m * 8,
+                                   hipMemcpyDeviceToHost, s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            drop_events();
+            return dev_fail(e);
+        }
+        running = false;
+        for (int k = 0; k < n; k++) {
+            cc_ctx* c = E.mem[k];
+            plan_state_to(c, S[k]);
+            if (h_dt)
+                std::copy(dts.begin() + (size_t)k * m, dts.begin() + (size_t)k * m + S[k].steps,
+                          h_dt + (size_t)k * nsteps + done[k]);
+            done[k] += S[k].steps;
+            halted[k] = S[k].halt;
+            if (S[k].halt) {
+                if (bad < 0) bad = k;
+            } else {
+                running = true;
+            }
+        }
         if (h_step_ms)
-            for (int k = 0; k < S.steps; k++)
-                if (hipEventElapsedTime(&h_step_ms[done + k], ev[done + k], ev[done + k + 1]) != hipSuccess)
-                    h_step_ms[done + k] = -1.0f;
-        done += S.steps;
-        halt = S.halt;
+            for (int i = 0; i < m; i++)
+                if (hipEventElapsedTime(&h_step_ms[base + i], ev[base + i], ev[base + i + 1]) != hipSuccess)
+                    h_step_ms[base + i] = -1.0f;
+        base += m;
     }
     drop_events();
-    c->speeds_ready = false;
-    c->advanced = done;
-    return halt ? halt_error(c, halt) : CC_OK;
+    for (cc_ctx* c : E.mem) c->speeds_ready = false;
+    if (bad < 0) return CC_OK;
+    return halt_error(E.mem[bad], halted[bad], E.d_cflout + 2 * bad);
+}
+
+template <typename R>
+cc_status advance(cc_ctx* c, int nsteps, double cfl, double* h_dt, float* h_step_ms) {
+    std::vector<int> done;
+    int bad = -1;
+    cc_status st = advance_members<R>(c->eng, c->stream, nsteps, cfl, h_dt, h_step_ms, done, bad);
+    c->advanced = done.empty() ? 0 : done[0];
+    return st;
+}
+
+template <typename R>
+cc_status batch_advance(cc_batch* b, int nsteps, double cfl, double* h_dt, float* h_step_ms, int32_t* h_done) {
+    Engine& E = b->eng;
+    std::vector<int> done;
+    int bad = -1;
+    cc_status st = advance_members<R>(E, b->stream, nsteps, cfl, h_dt, h_step_ms, done, bad);
+    if (h_done)
+        for (size_t k = 0; k < done.size(); k++) h_done[k] = done[k];
+    if (st != CC_OK) {
+        int k = bad >= 0 ? bad : 0;
+        b->err = "member " + std::to_string(k) + ": " + E.mem[k]->err;
+    }
+    return st;
 }
 
 }  // namespace
@@ -1918,6 +1990,18 @@ cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
         if (h_status) h_status[k] = (int32_t)E.h_gather[2 * k];
     }
     return CC_OK;
+}
+
+cc_status cc_batch_advance(cc_batch* b, int32_t nsteps, double cfl, double* h_dt, float* h_step_ms,
+                           int32_t* h_done) {
+    if (!b || nsteps < 0 || !(cfl > 0.0) || !std::isfinite(cfl)) return CC_ERR_ARG;
+    Engine& E = b->eng;
+    int n = (int)E.mem.size();
+    if (h_done)
+        for (int k = 0; k < n; k++) h_done[k] = 0;
+    if (n == 0 || nsteps == 0) return CC_OK;
+    return E.prec == CC_FP32_GEOM64 ? batch_advance<float>(b, nsteps, cfl, h_dt, h_step_ms, h_done)
+                                    : batch_advance<double>(b, nsteps, cfl, h_dt, h_step_ms, h_done);
 }
 
 cc_status cc_batch_cfl_dt(cc_batch* b, double cfl, double* h_dt) {

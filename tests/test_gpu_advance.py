@@ -131,3 +131,58 @@ def test_full_size_device_planned_steps(name):
     assert a.info()["status"] == b.info()["status"] == 0
     a.close()
     b.close()
+
+
+def small_mix():
+    out = []
+    for k in range(40):
+        r = W.serving_request(k)
+        if r["grid"]["nx"] * r["grid"]["ny"] <= 256 * 128:
+            out.append(r)
+        if len(out) == 6:
+            break
+    return out
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+def test_batch_advance_equals_members_advanced_alone(precision):
+    """A batch of mixed requests (turning and translating bodies, both direction orders
+    after an odd step) planned on the device equals each member advanced alone, bit for
+    bit; and, for the members that do not turn, the host-planned batch step."""
+    reqs = small_mix()
+    cfl = reqs[0]["cfl"]
+    alone = [solver(w, precision) for w in reqs]
+    mem = [solver(w, precision) for w in reqs]
+    host = [solver(w, precision) for w in reqs]
+    # one host step first, so that the members' direction orders differ from the batch's start
+    for s in alone + mem + host:
+        s.step(s.cfl_dt(cfl))
+    n = 7
+    da = [s.advance(n, cfl)[0] for s in alone]
+    b = cc.Batch(len(mem), precision)
+    for s in mem:
+        b.add(s)
+    db, ms = b.advance(n, cfl, want_ms=True)
+    assert ms.shape == (n,) and np.all(ms > 0)
+    hb = cc.Batch(len(host), precision)
+    for s in host:
+        hb.add(s)
+    dh = []
+    d = hb.cfl_dt(cfl)
+    for _ in range(n):
+        dh.append(d)
+        hb.step(d)
+        d, st = hb.last_dt(cfl)
+    for k, (w, a, m, h) in enumerate(zip(reqs, alone, mem, host)):
+        assert np.array_equal(da[k], db[k]), k
+        assert np.array_equal(a.get_u(), m.get_u()), k
+        assert a.info()["steps"] == m.info()["steps"]
+        if w["body"]["pitch_amp"] == 0.0:
+            assert np.array_equal(np.array([x[k] for x in dh]), db[k]), k
+            assert np.array_equal(h.get_u(), m.get_u()), k
+    for s in mem:
+        b.remove(s)
+    for s in host:
+        hb.remove(s)
+    b.close()
+    hb.close()
