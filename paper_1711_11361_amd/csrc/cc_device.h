@@ -21,6 +21,16 @@ struct Grid {
     double alpha_min;  // small-cell threshold: cut cells with a smaller volume fraction are solid
 };
 
+// Global-memory view of a pointer.  Pointers that reach a kernel through an argument block
+// in device memory have no provable address space, so the compiler emits flat accesses for
+// them, and a flat access counts against the LDS completion counter as well: every wait for
+// LDS data would also wait for the loads in flight.  The streaming kernels access the state
+// through these views.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* to_global(T* p) { return (gmem<T>*)p; }
+
 // Cell index box, half-open [i0, i1) x [j0, j1).
 struct Box {
     int i0, i1, j0, j1;
@@ -158,13 +168,16 @@ __device__ __forceinline__ void hllc32(const float ql[4], const float qr[4], flo
         for (int k = 0; k < 4; k++) f[k] = fk[k];
         return;
     }
-    // star state on the upwind side: c = rho_K (S_K - u_K) / (S_K - S*)
-    float c = mk * rcp32(sk - ss);
+    // star state on the upwind side: c = rho_K (S_K - u_K) / (S_K - S*); the energy's
+    // p_K / (rho_K (S_K - u_K)) term times c is p_K / (S_K - S*), so one reciprocal serves
+    float rs = rcp32(sk - ss);
+    float c = mk * rs;
+    float ds = ss - uk;
     float us[4];
     us[0] = c;
     us[n] = c * ss;
     us[t] = c * (q[t] * irk);
-    us[3] = c * __builtin_fmaf(ss - uk, __builtin_fmaf(pk, rcp32(mk), ss), q[3] * irk);
+    us[3] = __builtin_fmaf(c, __builtin_fmaf(ds, ss, q[3] * irk), ds * pk * rs);
 #pragma unroll
     for (int k = 0; k < 4; k++) f[k] = __builtin_fmaf(sk, us[k] - q[k], fk[k]);
 }
@@ -200,13 +213,32 @@ __device__ __forceinline__ void muscl32(const float qm[4], const float q[4], con
             el[k] = ql[k] + c;
             er[k] = qr[k] + c;
         }
-        float pel = pressure32(el, rcp32(el[0]), gm1), per = pressure32(er, rcp32(er[0]), gm1);
-        ok = el[0] > 0.0f && pel > 0.0f && er[0] > 0.0f && per > 0.0f;
+        // p > 0 with rho > 0 is 2 rho E > |m|^2 (no reciprocal needed for the test)
+        ok = el[0] > 0.0f && er[0] > 0.0f &&
+             __builtin_fmaf(el[1], el[1], el[2] * el[2]) < 2.0f * el[0] * el[3] &&
+             __builtin_fmaf(er[1], er[1], er[2] * er[2]) < 2.0f * er[0] * er[3];
     }
     if (!ok) {
 #pragma unroll
         for (int k = 0; k < 4; k++) el[k] = er[k] = q[k];
     }
+}
+
+// Signal speeds |u|+a and |v|+a of a regular cell's FP32 state as bit patterns of
+// non-negative floats (they order like the values, as unsigned integers; NaN maps to the
+// quiet NaN above infinity), and the conversion of such a pattern to the FP64 one of the
+// same value.  Float to double is exact and monotone, so the maximum of converted patterns
+// is the converted maximum.
+__device__ __forceinline__ void speed_bits32(const float u[4], float g, unsigned& bx, unsigned& by) {
+    float ir = rcp32(u[0]);
+    float uu = u[1] * ir, vv = u[2] * ir;
+    float c = __builtin_amdgcn_sqrtf(g * pressure32(u, ir, g - 1.0f) * ir);
+    float sx = fabsf(uu) + c, sy = fabsf(vv) + c;
+    bx = sx != sx ? 0x7fc00000u : __float_as_uint(sx);
+    by = sy != sy ? 0x7fc00000u : __float_as_uint(sy);
+}
+__device__ __forceinline__ unsigned long long bits32_to_64(unsigned b) {
+    return b > 0x7f800000u ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong((double)__uint_as_float(b));
 }
 
 // Signal speeds |u|+a and |v|+a of a stored state u (conserved per cell volume) with volume
@@ -222,10 +254,18 @@ __device__ __forceinline__ void speed_bits(const R u[4], double alpha, double ga
     double sx, sy;
     if (alpha == 1.0) {
         R g = (R)gam;
-        R uu = qdiv(u[1], u[0]), vv = qdiv(u[2], u[0]);
-        R c = qsqrt(qdiv(g * pressure(u, g), u[0]));
-        sx = (double)(fabs(uu) + c);
-        sy = (double)(fabs(vv) + c);
+        if constexpr (sizeof(R) == 4) {
+            unsigned x, y;
+            speed_bits32(u, g, x, y);
+            bx = bits32_to_64(x);
+            by = bits32_to_64(y);
+            return;
+        } else {
+            R uu = qdiv(u[1], u[0]), vv = qdiv(u[2], u[0]);
+            R c = qsqrt(qdiv(g * pressure(u, g), u[0]));
+            sx = (double)(fabs(uu) + c);
+            sy = (double)(fabs(vv) + c);
+        }
     } else {
         double q[4];
 #pragma unroll

@@ -866,15 +866,66 @@ __device__ __forceinline__ void block_max_to(unsigned long long bx, unsigned lon
     __syncthreads();
 }
 
+// Running maxima of the regular cells' speeds a dense tile writes, flushed as the block's
+// partial pair of FP64 bit patterns.  FP32 states keep 32-bit patterns until the flush (one
+// integer maximum per step of the wavefront reduction instead of a 64-bit compare and two
+// selects); the flushed pair equals the maximum of speed_bits over the same cells.
+template <typename R>
+struct SpeedMax {
+    unsigned long long x = 0ull, y = 0ull;
+    __device__ __forceinline__ void add(const R u[4], double gam) {
+        unsigned long long bx, by;
+        speed_bits(u, 1.0, gam, bx, by);
+        x = bx > x ? bx : x;
+        y = by > y ? by : y;
+    }
+    __device__ __forceinline__ void flush(unsigned long long* out) { block_max_to(x, y, out); }
+};
+template <>
+struct SpeedMax<float> {
+    unsigned x = 0u, y = 0u;
+    __device__ __forceinline__ void add(const float u[4], double gam) {
+        if (!(u[0] > 0.0f)) return;  // no gas: speed 0
+        unsigned bx, by;
+        speed_bits32(u, (float)gam, bx, by);
+        x = max(x, bx);
+        y = max(y, by);
+    }
+    __device__ __forceinline__ void flush(unsigned long long* out) {
+        __shared__ unsigned sx_[16], sy_[16];
+        for (int off = 32; off > 0; off >>= 1) {
+            x = max(x, (unsigned)__shfl_xor((int)x, off, 64));
+            y = max(y, (unsigned)__shfl_xor((int)y, off, 64));
+        }
+        int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            sx_[w] = x;
+            sy_[w] = y;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = 1; q < (int)(blockDim.x >> 6); q++) {
+                x = max(x, sx_[q]);
+                y = max(y, sy_[q]);
+            }
+            out[0] = bits32_to_64(x);
+            out[1] = bits32_to_64(y);
+        }
+        __syncthreads();
+    }
+};
+
 // lds: dense_x_lds<T>() bytes; cfl: when not null, the maxima of the written cells' speeds
 // go to this block's partial pair cfl[2 lb .. 2 lb + 1].
 template <typename R, typename T, int RB>
-__device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U, R* __restrict__ Uout, Box B, T lam,
+__device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_, R* __restrict__ Uout_, Box B, T lam,
                                         int lb, T* lds, unsigned long long* cfl) {
+    const gmem<R>* __restrict__ U = to_global(U_);
+    gmem<R>* __restrict__ Uout = to_global(Uout_);
     T(*sq)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds);
     T(*ser)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds + 4 * DX_T);
     T(*sf)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds + 8 * DX_T);
-    unsigned long long cx = 0ull, cy = 0ull;
+    SpeedMax<R> sm;
     int tid = threadIdx.x;
     int nx = g.nx, ny = g.ny;
     int gx = (nx + DX_OUT - 1) / DX_OUT;
@@ -936,15 +987,10 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U, 
             for (int m = 0; m < 4; m++) un[m] = (R)update(q[m], lam, sf[m][tid], sf[m][tid + 1]);
 #pragma unroll
             for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
-            if (cfl) {
-                unsigned long long bx, by;
-                speed_bits(un, 1.0, g.gamma, bx, by);
-                cx = bx > cx ? bx : cx;
-                cy = by > cy ? by : cy;
-            }
+            if (cfl) sm.add(un, g.gamma);
         }
     }
-    if (cfl) block_max_to(cx, cy, cfl + 2 * lb);
+    if (cfl) sm.flush(cfl + 2 * lb);
     __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
@@ -966,8 +1012,10 @@ __host__ __device__ constexpr int dense_y_blocks(int nx, int ny) {
 }
 
 template <typename R, typename T, int TR>
-__device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, R* __restrict__ Uout, Box B, T lam,
+__device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U_, R* __restrict__ Uout_, Box B, T lam,
                                         int lb, T* lds, unsigned long long* cfl) {
+    const gmem<R>* __restrict__ U = to_global(U_);
+    gmem<R>* __restrict__ Uout = to_global(Uout_);
     using Tile = DenseYTile<T, TR>;
     constexpr int ROWS = Tile::ROWS, ITS = Tile::ITS;
     // staged states, then face fluxes (row r: face below cell r); evolved states at the
@@ -1024,7 +1072,7 @@ __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, 
         for (int m = 0; m < 4; m++) sq[m][r][lane] = F[m];
     }
     __syncthreads();
-    unsigned long long cx = 0ull, cy = 0ull;
+    SpeedMax<R> sm;
     bool colbox = i >= B.i0 && i < B.i1;
 #pragma unroll
     for (int it = 0; it < ITS; it++) {
@@ -1039,14 +1087,9 @@ __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U, 
         for (int m = 0; m < 4; m++) un[m] = (R)update(qc[it][m], lam, sq[m][r][lane], sq[m][r + 1][lane]);
 #pragma unroll
         for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
-        if (cfl) {
-            unsigned long long bx, by;
-            speed_bits(un, 1.0, g.gamma, bx, by);
-            cx = bx > cx ? bx : cx;
-            cy = by > cy ? by : cy;
-        }
+        if (cfl) sm.add(un, g.gamma);
     }
-    if (cfl) block_max_to(cx, cy, cfl + 2 * lb);
+    if (cfl) sm.flush(cfl + 2 * lb);
     __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
