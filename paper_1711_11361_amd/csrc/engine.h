@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void kb_dense_y(const StepArgs* __restrict__ A
 // staging), so the box's latency-bound cells run while the tiles stream.  The first nwall
 // blocks are box blocks (T_WIDE cells each, table off_wall), the rest dense blocks.
 template <typename R, int RB>
-__global__ __launch_bounds__(DX_T) __attribute__((amdgpu_waves_per_eu(5))) void kb_wall_dense_x(const StepArgs* __restrict__ A,
+__global__ __launch_bounds__(DX_T) __attribute__((amdgpu_waves_per_eu(4))) void kb_wall_dense_x(const StepArgs* __restrict__ A,
                                                         const int* __restrict__ off_wall, int nwall,
                                                         const int* __restrict__ off, int n, int s, int fold) {
     __shared__ R lds[dense_x_lds<R>() / sizeof(R)];
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(DX_T) __attribute__((amdgpu_waves_per_eu(5))) void 
     dense_x_block<R, RB>(A, off, n, blockIdx.x - nwall, s, fold, lds);
 }
 template <typename R, int TR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void kb_wall_dense_y(const StepArgs* __restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kb_wall_dense_y(const StepArgs* __restrict__ A,
                                                        const int* __restrict__ off_wall, int nwall,
                                                        const int* __restrict__ off, int n, int s, int fold) {
     __shared__ R lds[DenseYTile<R, TR>::lds_bytes / sizeof(R)];
