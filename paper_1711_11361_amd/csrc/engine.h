@@ -429,7 +429,10 @@ __global__ __launch_bounds__(T_FIX) void kb_fix_block(StepArgs* A, const int* __
             R uu[4];
 #pragma unroll
             for (int m = 0; m < 4; m++) uu[m] = U[m * nc + k];
-            speed_bits(uu, J.Le.alpha[k], a.g.gamma, bx, by);
+            unsigned long long cx, cy;
+            speed_bits(uu, J.Le.alpha[k], a.g.gamma, cx, cy);
+            bx = cx > bx ? cx : bx;
+            by = cy > by ? cy : by;
         }
     }
     const int* od = a.sw[1].dir == 0 ? off_dx : off_dy;

@@ -51,6 +51,30 @@ def test_graph_step_equals_individual_launches(precision, mode):
 
 
 @pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+def test_folded_speeds_after_collapse_rounds(precision):
+    """A cylinder started impulsively into gas at rest, moving down and to the right, has
+    its fastest gas in the lower front of its box and collapses cut cells in its first
+    steps.  When a step's last sweep ran collapse rounds, its combine block recomputes the
+    speeds of the box cells (about nine per thread here), and the time step from the
+    folded speeds must equal a separate reduction of the state."""
+    g = W.grid(128, 128, 0.0, 2.0, 0.0, 1.0, alpha_min=W.SMALL_CELL)
+    bd = W.body(W.circle(0.2, 40), ref=(0.5, 0.5), vel=(2.0, -1.2))
+    w = {"grid": g, "body": bd, "prim": W.uniform_prim(g, 1.0, 0.0, 0.0, 1.0)}
+    a, b = solver(w, precision), solver(w, precision)
+    for _ in range(5):
+        dt = a.cfl_dt(0.5)  # folded into the previous captured step
+        assert dt == b.cfl_dt(0.5)  # separate reduction
+        a.step(dt)
+        b.begin_step(dt)
+        for d in (b.parity, 1 - b.parity):
+            b.sweep(d, dt)
+        b.end_step()
+    assert a.info()["collapses"] == b.info()["collapses"] > 0
+    assert np.array_equal(a.get_u(), b.get_u())
+    assert a.cfl_dt(0.5) == b.cfl_dt(0.5)
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
 @pytest.mark.parametrize("mode", [cc.CC_LAUNCH_PER_PHASE, cc.CC_LAUNCH_PERSISTENT])
 def test_batch_equals_members_alone(precision, mode):
     reqs = small_requests()
