@@ -181,6 +181,7 @@ struct Engine {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gkey[2] = {-1, -1};
     hipGraphExec_t pexec[3] = {nullptr, nullptr, nullptr};  // device-planned step, by first direction + 1
+    hipGraphExec_t pexec_run[3] = {nullptr, nullptr, nullptr};  // PLANNED_RUN such steps, the same way
     int mode = 0;                       // 0: one launch per phase; 1: one persistent launch per sweep
     GridSync* d_sync = nullptr;         // barrier counters of the persistent sweep launches
     unsigned long long wait_ticks = 0;  // barrier wait limit (wall-clock ticks)
@@ -623,6 +624,10 @@ void drop_graphs(Engine& E) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
     }
+    for (auto& g : E.pexec_run) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
 }
 
 // Offsets of every launch kind for the current members; uploads them (stream-ordered,
@@ -868,18 +873,23 @@ void step_sequence(Engine& E, hipStream_t s, int b, int dir0) {
 // for the first step of a run, by the previous step's last block for the others), which
 // also plans the next one.  dir0: a single member's first direction, which the host knows
 // from the step count alone; -1 for a batch (both dense kernels).
+// nsteps: 1, or PLANNED_RUN consecutive steps in one graph (directions alternating from
+// dir0; a batch keeps -1): one graph launch, and one gap between graphs, per PLANNED_RUN
+// steps.
+constexpr int PLANNED_RUN = 4;
 template <typename R>
-hipError_t engine_planned_step(Engine& E, hipStream_t s, int dir0) {
+hipError_t engine_planned_step(Engine& E, hipStream_t s, int dir0, int nsteps = 1) {
     if (!s) {  // the null stream cannot be captured: individual launches
-        step_kernels<R>(E, s, dir0);
+        for (int k = 0; k < nsteps; k++) step_kernels<R>(E, s, dir0 < 0 ? -1 : (dir0 + k) & 1);
         return hipGetLastError();
     }
-    hipGraphExec_t& gx = E.pexec[dir0 + 1];
+    if (nsteps != 1 && nsteps != PLANNED_RUN) return hipErrorInvalidValue;
+    hipGraphExec_t& gx = nsteps == 1 ? E.pexec[dir0 + 1] : E.pexec_run[dir0 + 1];
     if (!gx) {
         hipGraph_t gr;
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        step_kernels<R>(E, s, dir0);
+        for (int k = 0; k < nsteps; k++) step_kernels<R>(E, s, dir0 < 0 ? -1 : (dir0 + k) & 1);
         e = hipStreamEndCapture(s, &gr);
         if (e != hipSuccess) return e;
         e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
@@ -1568,9 +1578,12 @@ cc_status advance_members(Engine& E, hipStream_t s, int nsteps, double cfl, doub
                                at<PlanState>(c, c->lay.off_pstate), E.d_args + k, at<double>(c, c->lay.off_dtlog));
             e = hipGetLastError();
         }
-        for (int i = 0; i < m && e == hipSuccess; i++) {
-            e = engine_planned_step<R>(E, s, single ? (c0->parity + i) & 1 : -1);
+        for (int i = 0; i < m && e == hipSuccess;) {
+            // runs of steps in one graph unless every step is timed on its own
+            int k = ev.empty() && m - i >= PLANNED_RUN ? PLANNED_RUN : 1;
+            e = engine_planned_step<R>(E, s, single ? (c0->parity + i) & 1 : -1, k);
             if (!ev.empty() && e == hipSuccess) e = hipEventRecord(ev[base + i + 1], s);
+            i += k;
         }
         std::vector<double> dts((size_t)n * m);
         for (int k = 0; k < n && e == hipSuccess; k++) {

@@ -44,19 +44,25 @@ def host_steps(s, cfl, n):
     return np.array(dts)
 
 
+@pytest.mark.parametrize("timed", [True, False], ids=["per_step_graphs", "runs_of_steps"])
 @pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
 @pytest.mark.parametrize("name,w", list(fixed_bodies()), ids=[c[0] for c in fixed_bodies()])
-def test_device_planned_steps_equal_host_planned(name, w, precision):
+def test_device_planned_steps_equal_host_planned(name, w, precision, timed):
+    """Timed runs launch one graph per step (events between steps); untimed runs launch
+    graphs of several steps and single steps for the remainder (9 = 4 + 4 + 1)."""
     n = 9
     a, b = solver(w, precision), solver(w, precision)
     da = host_steps(a, w["cfl"], n)
-    db, ms = b.advance(n, w["cfl"], want_ms=True)
+    db, ms = b.advance(n, w["cfl"], want_ms=timed)
     assert np.array_equal(da, db), (name, da, db)
     assert np.array_equal(a.get_u(), b.get_u()), name
     ia, ib = a.info(), b.info()
     for key in ("t", "steps", "parity", "status", "collapses", "box_cells"):
         assert ia[key] == ib[key], (name, key, ia[key], ib[key])
-    assert ms.shape == (n,) and np.all(ms > 0.0)
+    if timed:
+        assert ms.shape == (n,) and np.all(ms > 0.0)
+    else:
+        assert ms is None
     # the host's bookkeeping continues from the device's: further steps either way agree
     da2 = host_steps(a, w["cfl"], 3)
     db2 = host_steps(b, w["cfl"], 3)
@@ -144,8 +150,9 @@ def small_mix():
     return out
 
 
+@pytest.mark.parametrize("timed", [True, False], ids=["per_step_graphs", "runs_of_steps"])
 @pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
-def test_batch_advance_equals_members_advanced_alone(precision):
+def test_batch_advance_equals_members_advanced_alone(precision, timed):
     """A batch of mixed requests (turning and translating bodies, both direction orders
     after an odd step) planned on the device equals each member advanced alone, bit for
     bit; and, for the members that do not turn, the host-planned batch step."""
@@ -162,8 +169,8 @@ def test_batch_advance_equals_members_advanced_alone(precision):
     b = cc.Batch(len(mem), precision)
     for s in mem:
         b.add(s)
-    db, ms = b.advance(n, cfl, want_ms=True)
-    assert ms.shape == (n,) and np.all(ms > 0)
+    db, ms = b.advance(n, cfl, want_ms=timed)
+    assert ms is None if not timed else (ms.shape == (n,) and np.all(ms > 0))
     hb = cc.Batch(len(host), precision)
     for s in host:
         hb.add(s)
