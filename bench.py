@@ -98,7 +98,8 @@ def run_mode(precision, steps, warmup, w):
             "ms_per_step": 1e3 * T / steps, "lat": lat, "timing": tim,
             "host_planned_ms_per_step": host_ms,
             "t_end": info["t"], "collapses": info["collapses"], "box_cells": info["box_cells"],
-            "tiles": {"x_rows_per_block": info["tile_x_rows"], "y_rows_per_tile": info["tile_y_rows"]}}
+            "tiles": {"x_rows_per_block": info["tile_x_rows"], "y_rows_per_tile": info["tile_y_rows"],
+                      "y_column_walk": info["tile_y_walk"]}}
 
 
 def batched(w, instances, steps, warmup):
@@ -212,9 +213,9 @@ def probe():
         for _ in range(10):
             s.step(s.cfl_dt(w["cfl"]))
         cc.cc_timing(s.ctx, 1)  # individual launches: one dispatch per dense sweep
-        ny_variants = 4 if prec == cc.CC_FP32_GEOM64 else 2
-        for v in range(4):
-            s.set_tiles(v, min(v, ny_variants - 1))
+        ys = [0, 1, 2, 3, 4, 5] if prec == cc.CC_FP32_GEOM64 else [0, 1, 4]
+        for k, ty in enumerate(ys):
+            s.set_tiles(min(k, 3), ty)
             for _ in range(2):
                 s.step(s.cfl_dt(w["cfl"]))
         cc.cc_timing_read(s.ctx)
@@ -295,7 +296,8 @@ def main():
         alg = nx * ny * 4 * 2 * bytes_per_value  # read + write of the state, one sweep
         ach = alg / avg_s / 1e9
         rows = r["tiles"]["x_rows_per_block"] if kern == "dense_x" else r["tiles"]["y_rows_per_tile"]
-        name = f"kb_{kern}<{'float' if bytes_per_value == 4 else 'double'}, {rows}>"
+        kname = "dense_yc" if kern == "dense_y" and r["tiles"]["y_column_walk"] else kern
+        name = f"kb_{kname}<{'float' if bytes_per_value == 4 else 'double'}, {rows}>"
         t = table.get(name)
         return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),

@@ -159,11 +159,12 @@ cc_status cc_surface_loads(cc_ctx* ctx, double* h_out4);
 /* Conservation totals sum(U) hx hy per component, FP64, deterministic order.  Host out. */
 cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
 
-/* Host info vector (n entries used, up to 9): time, steps, parity, device status bits
+/* Host info vector (n entries used, up to 10): time, steps, parity, device status bits
  * (1: a cell became fluid without donors; 2: a cell stayed inadmissible after collapsing;
  * 8: a grid-barrier wait of a persistent launch ran out),
  * collapsed-cell count, sweep box cells of the last sweep, staging capacity, rows per block
- * of the dense x-sweep, rows per tile of the dense y-sweep.  Synchronizes. */
+ * of the dense x-sweep, rows per tile of the dense y-sweep, 1 if that sweep walks columns
+ * (else 0).  Synchronizes. */
 cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
 
 /* Tile tuner for the dense sweeps (the regular cells): times every tile shape of both
@@ -175,8 +176,10 @@ cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
  * values, bit for bit). */
 cc_status cc_autotune(cc_ctx* ctx, int32_t reps, int32_t* h_choice);
 /* Set the dense-sweep tile variants directly: tile_x indexes rows per x-sweep block
- * {1, 2, 4, 8}, tile_y rows per y-sweep tile {8, 12, 16, 24} (16 and 24 only with FP32
- * state: the tile lives in 64 KiB of LDS).  CC_ERR_ARG for an index out of range. */
+ * {1, 2, 4, 8}; tile_y 0-3 rows per 64-column y-sweep tile staged in LDS {8, 12, 16, 24}
+ * (16 and 24 only with FP32 state: the tile lives in 64 KiB of LDS), 4-5 column walks of
+ * 256 columns x {4, 8} rows with the states in registers (8 only with FP32 state).  CC_ERR_ARG for an index out
+ * of range. */
 cc_status cc_set_tiles(cc_ctx* ctx, int32_t tile_x, int32_t tile_y);
 
 /* How cc_step launches a whole step (results are identical, bit for bit, in both modes).

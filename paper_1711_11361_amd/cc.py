@@ -216,11 +216,12 @@ def cc_totals(ctx):
 
 
 def cc_info(ctx):
-    out = (_d * 9)()
-    _check(ctx, _lib.cc_info(ctx, out, 9))
+    out = (_d * 10)()
+    _check(ctx, _lib.cc_info(ctx, out, 10))
     v = out[:]
     return {"t": v[0], "steps": int(v[1]), "parity": int(v[2]), "status": int(v[3]), "collapses": int(v[4]),
-            "box_cells": int(v[5]), "capacity": int(v[6]), "tile_x_rows": int(v[7]), "tile_y_rows": int(v[8])}
+            "box_cells": int(v[5]), "capacity": int(v[6]), "tile_x_rows": int(v[7]), "tile_y_rows": int(v[8]),
+            "tile_y_walk": bool(v[9])}
 
 
 def cc_set_tiles(ctx, tile_x, tile_y):

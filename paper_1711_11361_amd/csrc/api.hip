@@ -33,14 +33,17 @@ size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Dense-sweep tile variants: rows per block of the x-sweep, rows per tile of the y-sweep
 // (the y tile lives in LDS: (2 TR + 7) x 64 x 4 values, kept within 64 KiB).
-constexpr int NX_VARIANTS = 4, NY_VARIANTS = 4;
+// y-sweep variants 0-3: 64-column tiles staged in LDS; 4-5: column walks of 256 columns
+constexpr int NX_VARIANTS = 4, NY_VARIANTS = 6;
 constexpr int X_RB[NX_VARIANTS] = {1, 2, 4, 8};
-constexpr int Y_TR[NY_VARIANTS] = {8, 12, 16, 24};
+constexpr int Y_TR[NY_VARIANTS] = {8, 12, 16, 24, 4, 8};
+constexpr bool y_walk(int v) { return v >= 4; }
 
 bool dense_variant_ok(int prec, int dir, int v) {
     size_t rs = prec == CC_FP32_GEOM64 ? 4 : 8;
     if (dir == 0) return v >= 0 && v < NX_VARIANTS;
     if (v < 0 || v >= NY_VARIANTS) return false;
+    if (y_walk(v)) return rs == 4 || Y_TR[v] <= 4;  // an FP64 walk of 8 rows spills registers
     return (size_t)(2 * Y_TR[v] + 7) * 64 * 4 * rs <= 65536;
 }
 int dense_blocks(int dir, int v, int nx, int ny) {
@@ -49,6 +52,7 @@ int dense_blocks(int dir, int v, int nx, int ny) {
         return ((nx + DX_OUT - 1) / DX_OUT) * ((ny + rb - 1) / rb);
     }
     int tr = Y_TR[v];
+    if (y_walk(v)) return ((nx + DYC_T - 1) / DYC_T) * ((ny + tr - 1) / tr);
     return ((nx + 63) / 64) * ((ny + tr - 1) / tr);
 }
 
@@ -724,6 +728,8 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
             switch (E.tile_y) {
                 case 0: go(kb_dense_y<R, 8>, kb_wall_dense_y<R, 8>, 256); break;
                 case 1: go(kb_dense_y<R, 12>, kb_wall_dense_y<R, 12>, 256); break;
+                case 4: go(kb_dense_yc<R, 4>, kb_wall_dense_yc<R, 4>, DYC_T); break;
+                case 5: go(kb_dense_yc<R, 8>, kb_wall_dense_yc<R, 8>, DYC_T); break;
                 default:
                     if constexpr (sizeof(R) == 4) {
                         if (E.tile_y == 2) go(kb_dense_y<R, 16>, kb_wall_dense_y<R, 16>, 256);
@@ -1728,10 +1734,10 @@ cc_status cc_info(cc_ctx* c, double* h_out, int32_t n) {
     HIPCHK(c, hipMemcpyAsync(&dev[0], c->ws + c->lay.off_status, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&dev[1], c->ws + c->lay.off_ncol, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double v[9] = {c->t, (double)c->step, (double)c->parity, (double)dev[0], (double)dev[1],
-                   (double)c->last_sweep_box.w() * c->last_sweep_box.h(), (double)c->lay.cap,
-                   (double)X_RB[c->eng.tile_x], (double)Y_TR[c->eng.tile_y]};
-    for (int k = 0; k < n && k < 9; k++) h_out[k] = v[k];
+    double v[10] = {c->t, (double)c->step, (double)c->parity, (double)dev[0], (double)dev[1],
+                    (double)c->last_sweep_box.w() * c->last_sweep_box.h(), (double)c->lay.cap,
+                    (double)X_RB[c->eng.tile_x], (double)Y_TR[c->eng.tile_y], y_walk(c->eng.tile_y) ? 1.0 : 0.0};
+    for (int k = 0; k < n && k < 10; k++) h_out[k] = v[k];
     return CC_OK;
 }
 

@@ -307,6 +307,17 @@ __device__ __forceinline__ void dense_y_block(const StepArgs* __restrict__ A, co
     dense_y<R, R, TR>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl);
 }
 
+template <typename R, int RW>
+__device__ __forceinline__ void dense_yc_block(const StepArgs* __restrict__ A, const int* __restrict__ off, int n,
+                                               int b, int s, int fold) {
+    Unit w = unit_at(off, n, b);
+    const StepArgs& a = A[w.u];
+    const SweepJob& J = a.sw[s];
+    if (J.dir != 1 || w.lb >= dense_yc_blocks<RW>(a.g.nx, a.g.ny)) return;
+    unsigned long long* cfl = fold_target(a, fold);
+    dense_yc<R, R, RW>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, cfl);
+}
+
 template <typename R, int RB>
 __global__ __launch_bounds__(DX_T) void kb_dense_x(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                    int n, int s, int fold) {
@@ -319,6 +330,12 @@ __global__ __launch_bounds__(256) void kb_dense_y(const StepArgs* __restrict__ A
                                                   int n, int s, int fold) {
     __shared__ R lds[DenseYTile<R, TR>::lds_bytes / sizeof(R)];
     dense_y_block<R, TR>(A, off, n, blockIdx.x, s, fold, lds);
+}
+
+template <typename R, int RW>
+__global__ __launch_bounds__(DYC_T) void kb_dense_yc(const StepArgs* __restrict__ A, const int* __restrict__ off,
+                                                     int n, int s, int fold) {
+    dense_yc_block<R, RW>(A, off, n, blockIdx.x, s, fold);
 }
 
 // The box cells' first phase of sweep s (donations and wall quantities) in the same launch
@@ -349,6 +366,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         return;
     }
     dense_y_block<R, TR>(A, off, n, blockIdx.x - nwall, s, fold, lds);
+}
+
+template <typename R, int RW>
+__global__ __launch_bounds__(DYC_T) __attribute__((amdgpu_waves_per_eu(4))) void kb_wall_dense_yc(
+    const StepArgs* __restrict__ A, const int* __restrict__ off_wall, int nwall, const int* __restrict__ off, int n,
+    int s, int fold) {
+    if ((int)blockIdx.x < nwall) {
+        Unit w = unit_at(off_wall, n, blockIdx.x);
+        stagewall_body<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x);
+        return;
+    }
+    dense_yc_block<R, RW>(A, off, n, blockIdx.x - nwall, s, fold);
 }
 
 // Wave speeds of box cell t of the member's sweep s (end level, state as stored); the
