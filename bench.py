@@ -146,11 +146,29 @@ def batched(w, instances, steps, warmup):
         b.remove(s)
         s.close()
     b.close()
+    # the same copies as plain FP64 contexts, each advanced with launches of its own, one
+    # after the other: the per-instance comparison for the batched FP32-state rate
+    s64 = []
+    for _ in range(instances):
+        s = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP64)
+        s.set_prim(w["prim"])
+        s.advance(warmup, w["cfl"])
+        s64.append(s)
+    n64 = min(steps, 100)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for s in s64:
+        s.advance(n64, w["cfl"])
+    torch.cuda.synchronize()
+    T64 = time.perf_counter() - p0
+    for s in s64:
+        s.close()
     lat = np.asarray(lat, dtype=np.float64)
     return {"instances": instances, "precision": "f32 state, f64 geometry", "planning": "device",
             "cell_updates_per_s": cells * steps / T, "ms_per_iteration": 1e3 * T / steps,
             "host_planned_ms_per_iteration": host_ms,
-            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "per_instance_fp64": {"cell_updates_per_s": cells * n64 / T64, "steps_each": n64}}
 
 
 def cpu_baseline(w, budget_s=15.0):
