@@ -602,7 +602,7 @@ int units_of(int, int n) { return n; }
 int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     const Layout& L = c->lay;
     int m = c->m;
-    if (m == 0 && (kind <= L_BOX || kind == L_CS)) return 0;
+    if (m == 0 && (kind <= L_BOX || kind == L_CS || kind == L_PX || kind == L_PY)) return 0;
     switch (kind) {
         case L_POSE: return (int)nblk((size_t)m, T_WIDE);
         case L_V1: return geo_blocks(c, GEO_VERTS);
@@ -612,6 +612,8 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
         case L_CS: return geo_blocks(c, GEO_CELLS) + 2 * geo_blocks(c, GEO_SWEPT);
         case L_BOX: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
         case L_BOXW: return (int)nblk(std::max<size_t>(L.cap, 1), T_WIDE);
+        case L_PX: return std::max(patch_line_blocks<0>(L.capw, L.caph), 1);
+        case L_PY: return std::max(patch_line_blocks<1>(L.capw, L.caph), 1);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
     }
@@ -760,8 +762,8 @@ void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int last
     const StepArgs* A = E.d_args;
     int nb = ktotal(E, L_BOX);
     const int* ob = koff(E, L_BOX);
-    if (which & 1) klaunch(kb_patch<0, R>, nb, T_BOX, s, A, ob, n, sw);
-    if (which & 2) klaunch(kb_patch<1, R>, nb, T_BOX, s, A, ob, n, sw);
+    if (which & 1) klaunch(kb_patch_lines<0, R>, ktotal(E, L_PX), PL_T, s, A, koff(E, L_PX), n, sw);
+    if (which & 2) klaunch(kb_patch_lines<1, R>, ktotal(E, L_PY), PL_T, s, A, koff(E, L_PY), n, sw);
     klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw, last);
     klaunch(kb_fix_block<R>, n, T_FIX, s, E.d_args, koff(E, L_DX), koff(E, L_DY), ob, sw, last, E.d_gather);
 }

@@ -46,6 +46,7 @@ enum LaunchKind {
     L_S1, L_BOX, L_DX, L_DY,  // sweeps
     L_CS,  // volume fractions of both levels and the apertures of both sweeps
     L_BOXW,  // box cells, T_WIDE per block (launched beside the dense tiles)
+    L_PX, L_PY,  // box line segments of the x / y sweep's patch update
     NKINDS
 };
 constexpr int T_WIDE = 256;  // geometry and aperture stages, dense, time step
@@ -250,16 +251,20 @@ __global__ __launch_bounds__(T_BOX) void kb_stagewall(const StepArgs* __restrict
     stagewall_body<R>(A[w.u], s, w.lb * T_BOX + threadIdx.x);
 }
 
-// One kernel per direction (members whose sweep runs the other way return at once): the
-// update is the largest body, and one direction per kernel keeps it in registers.
+
+// The patch update by line segments of the sweep direction (block lb of the member's
+// patch_line_blocks<D>).  One kernel per direction (members whose sweep runs the other way
+// return at once): the update is the largest body, and one direction per kernel keeps it
+// in registers.
 template <int D, typename R>
-__global__ __launch_bounds__(T_BOX) void kb_patch(const StepArgs* __restrict__ A, const int* __restrict__ off,
-                                                  int n, int s) {
+__global__ __launch_bounds__(PL_T) void kb_patch_lines(const StepArgs* __restrict__ A, const int* __restrict__ off,
+                                                       int n, int s) {
+    __shared__ PatchLds sh;
     Unit w = unit_of(off, n);
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     if (J.dir != D || box_empty_dev(J.B)) return;
-    patch<D, R>(a.g, J, stage_of(a, s), a.ncol, w.lb * T_BOX + threadIdx.x);
+    patch_line<D, R>(a.g, J, stage_of(a, s), a.ncol, w.lb, sh);
 }
 
 template <typename R>

@@ -638,6 +638,112 @@ __device__ void patch(const Grid& g, const SweepJob& J, const Stage& S, unsigned
 }
 
 
+// The same update by line segments: a block of PL_T threads covers PL_OUT consecutive box
+// cells of one line in the sweep direction plus two cells each side; every thread fetches
+// one cell, and each cell's reconstruction and each face's stabilised flux are computed
+// once and exchanged through LDS (the per-cell form above computes three reconstructions
+// and two face fluxes per cell).  Face f lies between cells f-1 and f; its flux takes the
+// left cell as inside the domain when f > 0 and the right one when f < n, which is what
+// the per-cell form passes for a cell's lower and upper face.  Results are identical.
+constexpr int PL_T = 64;
+constexpr int PL_OUT = PL_T - 4;
+
+template <int D>
+__host__ __device__ constexpr int patch_line_blocks(int capw, int caph) {
+    return D == 0 ? caph * ((capw + PL_OUT - 1) / PL_OUT) : capw * ((caph + PL_OUT - 1) / PL_OUT);
+}
+
+struct PatchLds {
+    double q[4][PL_T];
+    double er[4][PL_T];
+    double phi[4][PL_T];
+    bool has[PL_T];
+};
+
+// lb: the block's index within the member (uniform over the block; every thread calls it)
+template <int D, typename R>
+__device__ void patch_line(const Grid& g, const SweepJob& J, const Stage& S, unsigned int* ncollapse, int lb,
+                           PatchLds& sh) {
+    const Level& Ls = J.Ls;
+    const Level& Le = J.Le;
+    const Box& B = J.B;
+    const R* U = (const R*)J.Uin;
+    double lam = J.lam;
+    int len = D == 0 ? B.w() : B.h();
+    int nlines = D == 0 ? B.h() : B.w();
+    int segs = (len + PL_OUT - 1) / PL_OUT;
+    if (lb >= nlines * segs) return;  // uniform over the block
+    int line = (D == 0 ? B.j0 : B.i0) + lb / segs;
+    int first = D == 0 ? B.i0 : B.j0;
+    int x = threadIdx.x;
+    int p = first + (lb % segs) * PL_OUT - 2 + x;  // this thread's cell along the line
+    int n = D == 0 ? g.nx : g.ny;
+    double gam = g.gamma;
+    CellData c;
+    fetch_cell<D>(g, U, B, S, line, p, n, c);
+#pragma unroll
+    for (int m = 0; m < 4; m++) sh.q[m][x] = c.q[m];
+    sh.has[x] = c.has;
+    __syncthreads();
+    double el[4] = {0, 0, 0, 0}, er[4] = {0, 0, 0, 0};
+    if (x >= 1 && x < PL_T - 1 && c.has) {
+        double qm[4], qp[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            qm[m] = sh.q[m][x - 1];
+            qp[m] = sh.q[m][x + 1];
+        }
+        bool ok = sh.has[x - 1] && sh.has[x + 1];
+        muscl<double, D>(qm, c.q, qp, ok, lam, gam, el, er);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; m++) sh.er[m][x] = er[m];
+    __syncthreads();
+    WallData wl, wr;
+    fetch_wall<D>(B, S, line, p, n, wr);
+    double btf = 1.0, btp = 1.0;
+    if (x >= 2 && x < PL_T - 1) {  // faces 2 .. PL_T-2: the lower and upper faces of the updated cells
+        double btm = face_bt<D>(B, S, line, p - 1);
+        btf = face_bt<D>(B, S, line, p);
+        btp = face_bt<D>(B, S, line, p + 1);
+        fetch_wall<D>(B, S, line, p - 1, n, wl);
+        double erl[4], phi[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) erl[m] = sh.er[m][x - 1];
+        bool act = btf > 0.0 && sh.has[x - 1] && c.has;
+        face_phi<D>(btf, btm, btp, erl, el, act, wl, wr, p > 0, p < n, gam, phi);
+#pragma unroll
+        for (int m = 0; m < 4; m++) sh.phi[m][x] = phi[m];
+    }
+    __syncthreads();
+    if (x < 2 || x >= PL_T - 2 || p >= first + len) return;
+    int i = D == 0 ? p : line, j = D == 0 ? line : p;
+    int b = bidx(B, i, j), cap = S.cap;
+    size_t k = (size_t)j * g.nx + i;
+    double as = Ls.alpha[k], ae = Le.alpha[k];
+    double u2[4] = {0, 0, 0, 0};
+    if (c.has) {
+        double W[4] = {0, 0, 0, 0};
+        if (wr.wall) {
+            double db = btp - btf;
+            for (int m = 0; m < 4; m++) W[m] = db * wr.wv[m];
+        }
+        for (int m = 0; m < 4; m++) u2[m] = c.u1[m] + lam * ((sh.phi[m][x] - sh.phi[m][x + 1]) + W[m]);
+    }
+    int gone = 0;
+    if (as > 0.0 && ae == 0.0) {
+        gone = 1;
+    } else if (ae > 0.0 && c.has) {
+        double r = u2[0], e = u2[3];
+        if (!(r > 0.0) || !(e - 0.5 * (u2[1] * u2[1] + u2[2] * u2[2]) / r > 0.0)) {
+            gone = 2;
+            atomicAdd(ncollapse, 1u);
+        }
+    }
+    for (int m = 0; m < 4; m++) S.U2[m * cap + b] = u2[m];
+    S.gone[b] = (int8_t)gone;
+}
+
 // Content (conserved amounts) that is present but not an admissible gas state.
 __device__ __forceinline__ bool inadmissible_content(const double* u) {
     if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0 && u[3] == 0.0) return false;
