@@ -118,17 +118,30 @@ __device__ __forceinline__ Poly pose_lds(const GeoJob& J, double* spoly) {
     return Q;
 }
 
-// Items of one block left to a polygon walk: each wavefront walks its own lanes' items one
-// at a time, all 64 lanes sharing the polygon's edges.  walk(item, lane).
+// Items of one block left to a polygon walk, walked one at a time by a whole wavefront (all
+// 64 lanes sharing the polygon's edges).  The block's items are listed in LDS (wavefront by
+// wavefront, lanes in order) and dealt round-robin to its wavefronts, so a wavefront whose
+// lanes drew several boundary items shares them with the others: the slowest wavefront
+// walks ceil(items / wavefronts) of them.  Every thread of the block (at most T_WIDE)
+// calls it.  walk(item, lane).
 template <class W>
 __device__ __forceinline__ void walk_left(bool need, int t, W&& walk) {
-    int lane = threadIdx.x & (WAVE - 1);
+    __shared__ int items[T_WIDE];
+    __shared__ int wcount[T_WIDE / WAVE];
+    int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
     unsigned long long mask = __ballot(need);
-    while (mask) {
-        int l = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        walk(__shfl(t, l, WAVE), lane);
+    if (lane == 0) wcount[wv] = __popcll(mask);
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int k = 0; k < nw; k++) {
+        int c = wcount[k];
+        base += k < wv ? c : 0;
+        total += c;
     }
+    if (need) items[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
+    __syncthreads();
+    for (int q = wv; q < total; q += nw) walk(items[q], lane);
+    __syncthreads();  // the list may be rebuilt by the next call
 }
 
 // Item of lane l of wavefront w among the W wavefronts of a job's nb blocks: lanes take
