@@ -33,7 +33,9 @@ def run_mode(precision, steps, warmup, w):
 
     s = cc.Solver(w["grid"], w["body"], precision=precision)
     s.set_prim(w["prim"])
-    tiles = s.autotune()
+    # default tiles (1-row x-sweep blocks, 8-row y-sweep tiles), not the tuner's pick: on
+    # this grid every shape gives the same step time within noise, and a fixed choice keeps
+    # the timed kernels the same from run to run (and under the profiler)
     cfl = w["cfl"]
     # host-planned steps (cc_cfl_dt read back, then the captured step), for comparison
     for _ in range(10):
