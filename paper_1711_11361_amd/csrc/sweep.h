@@ -183,7 +183,8 @@ __device__ int donors(const Grid& g, const Level& Ls, const R* U, int i, int j, 
             int ii = i + c_d8[q][0], jj = j + c_d8[q][1];
             if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny) continue;
             size_t kk = (size_t)jj * g.nx + ii;
-            if (Ls.alpha[kk] > 0.0 && (double)U[kk] > 0.0) don[nd++] = (int)kk;
+            double a = Ls.alpha[kk], r = (double)U[kk];  // both loads in flight together
+            if ((a > 0.0) & (r > 0.0)) don[nd++] = (int)kk;
         }
     }
     return nd;
@@ -339,14 +340,16 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
         }
     } else if (as > 0.0 && u[0] > 0.0) {
         // a live cell may donate to emptied neighbours (visited in increasing cell order);
-        // the neighbours' fractions and densities are loaded together first (indices
-        // clamped into the grid; the ones outside it are skipped below)
+        // the neighbours' fractions and densities are loaded together first, all three
+        // unconditionally (a short-circuit test would make each load wait for the one
+        // before; indices clamped into the grid, the ones outside it are skipped below)
         unsigned emptied = 0u;  // bit q: neighbour q (row-major in the 3 x 3 block) is emptied
 #pragma unroll
         for (int q = 0; q < 9; q++) {
             int li = min(max(i + q % 3 - 1, 0), g.nx - 1), lj = min(max(j + q / 3 - 1, 0), g.ny - 1);
             size_t l = (size_t)lj * g.nx + li;
-            if (Ls.alpha[l] > 0.0 && Le.alpha[l] > 0.0 && !((double)U[l] > 0.0)) emptied |= 1u << q;
+            double a_s = Ls.alpha[l], a_e = Le.alpha[l], r = (double)U[l];
+            if ((a_s > 0.0) & (a_e > 0.0) & !(r > 0.0)) emptied |= 1u << q;
         }
         double take = 0.0;
         for (int dj = -1; dj <= 1; dj++)
