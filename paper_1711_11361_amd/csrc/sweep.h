@@ -190,6 +190,47 @@ __device__ int donors(const Grid& g, const Level& Ls, const R* U, int i, int j, 
     return nd;
 }
 
+// The donor set of receiver (i, j) as donors() finds it, with the sums of the donors'
+// fractions and contents in donor order.  With FP32 state the face neighbours' fractions
+// and contents are loaded in one round (the usual case); the eight-neighbour set, needed
+// only when no face neighbour qualifies, goes through donors(), and so does every FP64
+// state (its twenty loads in flight spill registers in the kernels this runs in).
+template <typename R>
+__device__ __forceinline__ int donor_sums(const Grid& g, const Level& Ls, const R* U, int i, int j, size_t nc,
+                                          double& sa, double su[4]) {
+    sa = 0.0;
+    su[0] = su[1] = su[2] = su[3] = 0.0;
+    if constexpr (sizeof(R) == 4) {
+        double a[4], c[4][4];
+        bool in[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            int ii = i + c_d8[q][0], jj = j + c_d8[q][1];
+            in[q] = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny;
+            size_t kk = in[q] ? (size_t)jj * g.nx + ii : (size_t)j * g.nx + i;
+            a[q] = Ls.alpha[kk];
+#pragma unroll
+            for (int m = 0; m < 4; m++) c[q][m] = (double)U[m * nc + kk];
+        }
+        int nd = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (in[q] && (a[q] > 0.0) && (c[q][0] > 0.0)) {
+                nd++;
+                sa += a[q];
+#pragma unroll
+                for (int m = 0; m < 4; m++) su[m] += c[q][m];
+            }
+        if (nd > 0) return nd;
+    }
+    int don[8];
+    int nd = donors(g, Ls, U, i, j, don);
+    for (int qd = 0; qd < nd; qd++) sa += Ls.alpha[don[qd]];
+    for (int m = 0; m < 4; m++)
+        for (int qd = 0; qd < nd; qd++) su[m] += (double)U[m * nc + don[qd]];
+    return nd;
+}
+
 // ------------------------------------------------------------------ wall quantities
 // The solid intervals of the four faces of cell (i, j) in a level: x-faces i and i + 1,
 // y-faces j and j + 1 (loaded together, so that their latencies overlap).
@@ -314,29 +355,17 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
     double u1[4] = {u[0], u[1], u[2], u[3]};
     int has = 0;
     if (uncovered || emptied) {
-        int don[8];
-        int nd = donors(g, Ls, U, i, j, don);
+        double sa, su[4];
+        int nd = donor_sums(g, Ls, U, i, j, nc, sa, su);
         if (nd == 0) {
             atomicOr(status, 1u);
+        } else if (uncovered) {
+            for (int m = 0; m < 4; m++) q[m] = su[m] / sa;
+            has = 1;
+            u1[0] = u1[1] = u1[2] = u1[3] = 0.0;
         } else {
-            double sa = 0.0;
-            for (int qd = 0; qd < nd; qd++) sa += Ls.alpha[don[qd]];
-            if (uncovered) {
-                for (int m = 0; m < 4; m++) {
-                    double su = 0.0;
-                    for (int qd = 0; qd < nd; qd++) su += (double)U[m * nc + don[qd]];
-                    q[m] = su / sa;
-                }
-                has = 1;
-                u1[0] = u1[1] = u1[2] = u1[3] = 0.0;
-            } else {
-                double sig = as / (as + sa);
-                for (int m = 0; m < 4; m++) {
-                    double su = 0.0;
-                    for (int qd = 0; qd < nd; qd++) su += (double)U[m * nc + don[qd]];
-                    u1[m] = sig * su;
-                }
-            }
+            double sig = as / (as + sa);
+            for (int m = 0; m < 4; m++) u1[m] = sig * su[m];
         }
     } else if (as > 0.0 && u[0] > 0.0) {
         // a live cell may donate to emptied neighbours (visited in increasing cell order);
