@@ -258,18 +258,22 @@ __device__ __forceinline__ int chain_edges(const Poly& P, int a, int b) {
 }
 // First position q in [0, len] of the chain from vertex a at which pred(vertex) holds, for
 // a predicate that is false and then true along the chain; len + 1 when it never holds.
-// The 64 lanes of the wavefront test 64 positions per round and narrow the range to the
-// gap between the last false and the first true one (two or three rounds for a polygon of
-// up to 4096 vertices).  Every lane of the wavefront calls it with the same arguments.
-template <class F>
+// The G lanes of a lane group (G = 64: the whole wavefront; 32 or 16: searches of different
+// chains or predicates side by side in one wavefront) test G positions per round and
+// narrow the range to the gap between the last false and the first true one (two or three
+// rounds for 64 lanes and up to 4096 vertices).  Every lane of the group calls it with the
+// same arguments; the answer does not depend on G.
+template <int G = WAVE, class F>
 __device__ __forceinline__ int chain_first(const Poly& P, int a, int len, int lane, F&& pred) {
+    int gl = lane & (G - 1), gb = lane & (WAVE - G);  // lane within the group, group's first lane
     int lo = 0, hi = len + 1;  // the answer lies in [lo, hi]; hi stands for "true"
     while (lo < hi) {
         int span = hi - lo;
-        int step = (span + WAVE - 1) / WAVE;
-        int p = lo + lane * step;
+        int step = (span + G - 1) / G;
+        int p = lo + gl * step;
         bool t = p < hi && pred(chain_vertex(P, a, p));
-        unsigned long long mask = __ballot(t);
+        unsigned long long mask = __ballot(t) >> gb;
+        if (G < WAVE) mask &= (1ull << (G & (WAVE - 1))) - 1ull;
         int tested = (span - 1) / step;  // highest lane with a position below hi
         if (mask == 0ull) {
             lo = lo + tested * step + 1;
@@ -292,13 +296,22 @@ __device__ double poly_clip_area_chains(const Poly& P, double ox, double oy, dou
     const double* v = P.v;
     auto X = [&](int k) { return v[2 * k] - ox; };
     auto Y = [&](int k) { return v[2 * k + 1] - oy; };
-    // right side: lower chain il -> ir (x rising), upper chain ir -> il (x falling)
+    // right side: lower chain il -> ir (x rising), upper chain ir -> il (x falling); the two
+    // searches run side by side in the two halves of the wavefront
     double yb = -INFINITY, yt = INFINITY;
     int found = 0;
+    int qx;
+    {
+        int chain = lane >> 5;
+        int a = chain == 0 ? P.il : P.ir, b = chain == 0 ? P.ir : P.il;
+        qx = chain_first<32>(P, a, chain_edges(P, a, b), lane,
+                             [&](int k) { return chain == 0 ? !(X(k) < w) : X(k) < w; });
+    }
+    int qxs[2] = {__shfl(qx, 0, WAVE), __shfl(qx, 32, WAVE)};
     for (int chain = 0; chain < 2; chain++) {
         int a = chain == 0 ? P.il : P.ir, b = chain == 0 ? P.ir : P.il;
         int len = chain_edges(P, a, b);
-        int q = chain_first(P, a, len, lane, [&](int k) { return chain == 0 ? !(X(k) < w) : X(k) < w; });
+        int q = qxs[chain];
         if (q > 0 && q <= len) {
             int k = chain_vertex(P, a, q - 1), k1 = chain_vertex(P, a, q);
             double ax = X(k), ay = Y(k), dx = X(k1) - ax, dy = Y(k1) - ay;
@@ -315,14 +328,23 @@ __device__ double poly_clip_area_chains(const Poly& P, double ox, double oy, dou
         right_solid = hi > lo ? hi - lo : 0.0;
     }
     double acc = 0.0;
+    // right chain ib -> it (y rising): from the first edge whose end reaches y >= 0 to the
+    // last whose start has y <= h; left chain it -> ib (y falling): from the first edge whose
+    // end has y <= h to the last whose start has y >= 0.  The four searches (two per chain)
+    // run side by side in the four quarters of the wavefront.
+    int qy;
+    {
+        int chain = lane >> 5, second = (lane >> 4) & 1;
+        int a = chain == 0 ? P.ib : P.it, b = chain == 0 ? P.it : P.ib;
+        qy = chain_first<16>(P, a, chain_edges(P, a, b), lane, [&](int k) {
+            return second == 0 ? (chain == 0 ? !(Y(k) < 0.0) : !(Y(k) > h)) : (chain == 0 ? Y(k) > h : Y(k) < 0.0);
+        });
+    }
+    int qys[4] = {__shfl(qy, 0, WAVE), __shfl(qy, 16, WAVE), __shfl(qy, 32, WAVE), __shfl(qy, 48, WAVE)};
     for (int chain = 0; chain < 2; chain++) {
-        // right chain ib -> it (y rising): from the first edge whose end reaches y >= 0 to the
-        // last whose start has y <= h; left chain it -> ib (y falling): from the first edge
-        // whose end has y <= h to the last whose start has y >= 0
         int a = chain == 0 ? P.ib : P.it, b = chain == 0 ? P.it : P.ib;
         int len = chain_edges(P, a, b);
-        int q0 = chain_first(P, a, len, lane, [&](int k) { return chain == 0 ? !(Y(k) < 0.0) : !(Y(k) > h); });
-        int q1 = chain_first(P, a, len, lane, [&](int k) { return chain == 0 ? Y(k) > h : Y(k) < 0.0; });
+        int q0 = qys[2 * chain], q1 = qys[2 * chain + 1];
         int p0 = q0 > 0 ? q0 - 1 : 0, p1 = q1 - 1 < len - 1 ? q1 - 1 : len - 1;
         for (int p = p0 + lane; p <= p1; p += WAVE) {
             int k = chain_vertex(P, a, p), k1 = chain_vertex(P, a, p + 1);
