@@ -49,6 +49,12 @@ typedef struct {
 
 enum { FLUID = 0, SOLID = 1 };
 
+/* Sweep record of the traced cell (ccref_trace): standard fluxes F of its low and high
+ * faces (4 + 4), stabilised fluxes Phi of those faces (4 + 4), its boundary flux F^B (4),
+ * its state Q (4), then alpha_s, alpha_e, the time-averaged apertures of its low and high
+ * faces, the shielded volume, the wall flag and the state flag (7). */
+#define TRACE_N 31
+
 typedef struct {
     int8_t* vcls;  /* (ny+1)*(nx+1) vertex classes */
     double* fx;    /* 2*ny*(nx+1) solid intervals of x-faces (face (i,j) between cells (i-1,j),(i,j)) */
@@ -81,6 +87,12 @@ typedef struct {
     double bnd[4], wall[4], lost[4];
     int status;
     int64_t ncollapse; /* cells emptied because their update was not admissible */
+    /* test hooks: a cell whose sweep quantities the next sweeps record, and the record */
+    int trace_i, trace_j;
+    double trace[TRACE_N];
+    /* oracle-only option: a cell that becomes fluid takes content from its donors as
+     * printed (Eq. cutCellInitialisationDonorCellUpdate) instead of only a state (R13) */
+    int uncover_moves_content;
 } ccref_ctx;
 
 /* ------------------------------------------------------------------------------------ */
@@ -533,6 +545,7 @@ ccref_ctx* ccref_create(const ccref_config* cfg, const ccref_body* body) {
     c->s0 = 0;
     c->sm = 1;
     c->s1 = 2;
+    c->trace_i = c->trace_j = -1;
     return c;
 }
 
@@ -886,7 +899,19 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
             }
             double sa = 0.0;
             for (int q = 0; q < nd; q++) sa += Ls->alpha[don[q]];
-            if (uncovered) {
+            if (uncovered && c->uncover_moves_content) {
+                /* as printed: the new cell's content is the fraction sigma of its donors'
+                 * content, sigma = alpha_e / (alpha_e + sum alpha_s of the donors), which the
+                 * donors give up; its state is that content over its new volume */
+                double sig = ael / (ael + sa);
+                uncov[l] = 2;
+                for (int m = 0; m < 4; m++) {
+                    double su = 0.0;
+                    for (int q = 0; q < nd; q++) su += c->U[m * nc + don[q]];
+                    U1[m * nc + l] = sig * su;
+                }
+                for (int q = 0; q < nd; q++) take[don[q]] += sig;
+            } else if (uncovered) {
                 uncov[l] = 1;
                 for (int m = 0; m < 4; m++) {
                     double su = 0.0;
@@ -938,9 +963,12 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
             e->as = Ls->alpha[k];
             e->ae = Le->alpha[k];
             e->ab = 0.5 * (e->as + e->ae);
-            if (uncov[k]) {
+            if (uncov[k] == 1) {
                 has[k] = 1;
                 for (int m = 0; m < 4; m++) Q[m * nc + k] = Qinit[m * nc + k];
+            } else if (uncov[k] == 2) {
+                has[k] = 1;
+                for (int m = 0; m < 4; m++) Q[m * nc + k] = U1[m * nc + k] / e->ae;
             } else if (e->as > 0.0 && U1[k] > 0.0) { /* live: open volume and content */
                 has[k] = 1;
                 for (int m = 0; m < 4; m++) Q[m * nc + k] = U1[m * nc + k] / e->as;
@@ -1129,6 +1157,24 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
             }
             for (int m = 0; m < 4; m++)
                 U2[m * nc + k] = U1[m * nc + k] + lam * ((PHI[p][m] - PHI[p + 1][m]) + W[m]);
+            if ((dir == 0 ? p : line) == c->trace_i && (dir == 0 ? line : p) == c->trace_j) {
+                double* r = c->trace;
+                for (int m = 0; m < 4; m++) {
+                    r[m] = F[p][m];
+                    r[4 + m] = F[p + 1][m];
+                    r[8 + m] = PHI[p][m];
+                    r[12 + m] = PHI[p + 1][m];
+                    r[16 + m] = e->wall ? e->fb[m] : 0.0;
+                    r[20 + m] = Q[m * nc + k];
+                }
+                r[24] = e->as;
+                r[25] = e->ae;
+                r[26] = bt[p];
+                r[27] = bt[p + 1];
+                r[28] = e->ahat;
+                r[29] = e->wall;
+                r[30] = has[k];
+            }
         }
         for (int m = 0; m < 4; m++) c->bnd[m] += lam * (PHI[0][m] - PHI[n][m]) * area;
 #undef CELL
@@ -1340,6 +1386,33 @@ void ccref_muscl(const double* qm, const double* q, const double* qp, int ok, do
 void ccref_wall_riemann(const double* q, double nx, double ny, double wx, double wy, double g,
                         double* out2) {
     wall_riemann(q, nx, ny, wx, wy, g, out2, out2 + 1);
+}
+/* Rigid-body velocity of the body point at (x, y) at time t (out2: ux, uy). */
+void ccref_body_velocity(const ccref_ctx* c, double t, double x, double y, double* out2) {
+    body_velocity(c, t, x, y, out2, out2 + 1);
+}
+/* Displacement along d of the point (x, y) under the rigid map of the open step. */
+double ccref_step_disp(const ccref_ctx* c, int d, double x, double y) {
+    return c->in_step ? step_disp(c, d, x, y) : NAN;
+}
+/* Record the sweep quantities of cell (i, j) in every later sweep (i < 0: stop). */
+int ccref_trace(ccref_ctx* c, int i, int j) {
+    c->trace_i = i;
+    c->trace_j = j;
+    for (int k = 0; k < TRACE_N; k++) c->trace[k] = NAN;
+    return 0;
+}
+int ccref_trace_get(const ccref_ctx* c, double* out) {
+    for (int k = 0; k < TRACE_N; k++) out[k] = c->trace[k];
+    return TRACE_N;
+}
+/* Oracle-only options.  1: a cell that becomes fluid takes content from its donors as
+ * printed (Eqs. cutCellInitialisation, cutCellInitialisationDonorCellUpdate) instead of a
+ * state only (reading R13); kept to show why R13 is used. */
+int ccref_set_option(ccref_ctx* c, int opt, int value) {
+    if (opt != 1) return 1;
+    c->uncover_moves_content = value != 0;
+    return 0;
 }
 /* Area of the posed polygon clipped to a rectangle (for tests). */
 double ccref_clip_area(const double* poly, int m, double ox, double oy, double w, double h) {

@@ -78,6 +78,13 @@ def lib():
         L.ccref_clip_area.restype = d
         L.ccref_clip_area.argtypes = [p, i, d, d, d, d]
         L.ccref_face_intervals.argtypes = [vp, i, p, p]
+        L.ccref_body_velocity.argtypes = [vp, d, d, d, p]
+        L.ccref_body_velocity.restype = None
+        L.ccref_step_disp.argtypes = [vp, i, d, d]
+        L.ccref_step_disp.restype = d
+        L.ccref_trace.argtypes = [vp, i, i]
+        L.ccref_trace_get.argtypes = [vp, p]
+        L.ccref_set_option.argtypes = [vp, i, i]
     return _lib
 
 
@@ -296,6 +303,32 @@ class Oracle:
         b, w, l = np.zeros(4), np.zeros(4), np.zeros(4)
         lib().ccref_budget(self._h, _dp(b), _dp(w), _dp(l))
         return b, w, l
+
+    # test hooks
+    def body_velocity(self, t, x, y):
+        out = np.zeros(2)
+        lib().ccref_body_velocity(self._h, t, x, y, _dp(out))
+        return out
+
+    def step_disp(self, d, x, y):
+        """Displacement along d of (x, y) under the rigid map of the open step."""
+        return lib().ccref_step_disp(self._h, d, x, y)
+
+    def trace(self, i, j):
+        """Record the sweep quantities of cell (i, j) in the following sweeps."""
+        lib().ccref_trace(self._h, i, j)
+
+    def trace_get(self):
+        r = np.zeros(31)
+        lib().ccref_trace_get(self._h, _dp(r))
+        return {"F_lo": r[0:4], "F_hi": r[4:8], "phi_lo": r[8:12], "phi_hi": r[12:16], "FB": r[16:20],
+                "Q": r[20:24], "alpha_s": r[24], "alpha_e": r[25], "bt_lo": r[26], "bt_hi": r[27],
+                "ahat": r[28], "wall": bool(r[29]), "has": bool(r[30])}
+
+    def set_uncover_moves_content(self, on):
+        """Oracle-only: cells that become fluid take content from their donors as printed
+        (instead of a state only, reading R13)."""
+        lib().ccref_set_option(self._h, 1, int(bool(on)))
 
     def run(self, cfl, nsteps=None, t_end=None, dts=None):
         """Advance with the CFL time step; returns the list of dt used."""

@@ -159,8 +159,12 @@ def test_end_time_parity_config1():
         den = np.abs(Uo[k]).sum()
         if den > 0:
             assert np.abs(Ug[k] - Uo[k]).sum() / den <= 1e-9, k
+    # totals are sums of U times the cell area, so |Tg - To| <= area sum|Ug - Uo| per
+    # component: the end-time L1 bar above bounds them by 1e-9 area sum|Uo|
     To, Tg = o.totals(), s.totals()
-    assert np.abs(Tg - To).max() <= 1e-11 * np.abs(To).max()
+    area = (w["grid"]["x_hi"] - w["grid"]["x_lo"]) / o.nx * (w["grid"]["y_hi"] - w["grid"]["y_lo"]) / o.ny
+    for k in range(4):
+        assert abs(Tg[k] - To[k]) <= 1e-9 * area * np.abs(Uo[k]).sum(), k
 
 
 def test_fp32_state_against_fp64_oracle():
