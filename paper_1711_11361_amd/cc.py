@@ -355,6 +355,14 @@ class Solver:
         self._ws_ptr = (base + 255) // 256 * 256
         self.ctx = cc_create(self._cfg, self._body, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
 
+    @staticmethod
+    def device_bytes(grid, body=None, precision=CC_FP64):
+        """Device memory one Solver allocates: the library's workspace (plus the alignment
+        pad) and the FP64 input/output buffer of four planes."""
+        cfg = make_config(grid, precision)
+        b, _ = make_body(body)
+        return cc_workspace_bytes(cfg, b) + 256 + 4 * 8 * grid["nx"] * grid["ny"]
+
     def close(self):
         if getattr(self, "ctx", None):
             cc_destroy(self.ctx)

@@ -79,6 +79,36 @@ struct Layout {
 
 int body_m(const cc_body* b) { return b && b->nverts > 0 && b->verts ? b->nverts : 0; }
 
+// True for a polygon of at least three finite vertices whose every turn is to the left
+// (or straight on), with a positive signed area and one full turn in total (a polygon
+// that winds round twice turns left everywhere too); repeated vertices are allowed.  The
+// geometry's chain searches assume a convex polygon in counter-clockwise order.
+bool convex_ccw(const double* v, int m) {
+    if (m < 3) return false;
+    std::vector<double> ex, ey;  // the edges of nonzero length, in order
+    double area2 = 0.0;
+    for (int k = 0; k < m; k++) {
+        int k1 = (k + 1) % m;
+        double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+        if (!std::isfinite(ax) || !std::isfinite(ay)) return false;
+        if (bx != ax || by != ay) {
+            ex.push_back(bx - ax);
+            ey.push_back(by - ay);
+        }
+        area2 += ax * by - bx * ay;
+    }
+    size_t n = ex.size();
+    if (n < 3 || !(area2 > 0.0)) return false;
+    double turn = 0.0;
+    for (size_t k = 0; k < n; k++) {
+        size_t k1 = (k + 1) % n;
+        double cr = ex[k] * ey[k1] - ey[k] * ex[k1];
+        if (cr < 0.0) return false;
+        turn += std::atan2(cr, ex[k] * ex[k1] + ey[k] * ey[k1]);
+    }
+    return std::fabs(turn - 2.0 * M_PI) < 1e-6;
+}
+
 Layout make_layout(const cc_config* c, const cc_body* b) {
     Layout L{};
     size_t nx = c->nx, ny = c->ny;
@@ -951,6 +981,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     if (body && body->nverts > 0 && !body->verts) return create_fail(nullptr, CC_ERR_ARG, "body without vertices");
     if (body && body->nverts > LDS_VERTS)
         return create_fail(nullptr, CC_ERR_UNSUPPORTED, "body polygon with more than 2048 vertices");
+    if (body && body->nverts > 0 && !convex_ccw(body->verts, body->nverts))
+        return create_fail(nullptr, CC_ERR_ARG, "body polygon is not convex and counter-clockwise with 3 or more vertices");
     Layout lay = make_layout(cfg, body);
     if (!d_ws || ws_bytes < lay.total || ((uintptr_t)d_ws % ALIGN) != 0)
         return create_fail(nullptr, CC_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
@@ -1057,7 +1089,18 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
 
 cc_status cc_destroy(cc_ctx* c) {
     if (!c) return CC_ERR_ARG;
-    if (c->batch) cc_batch_remove(c->batch, c);
+    if (c->batch) {
+        // leave the batch whatever the removal reports: the batch must never keep a
+        // pointer to a destroyed context
+        cc_batch* b = c->batch;
+        if (cc_batch_remove(b, c) != CC_OK) {
+            (void)hipStreamSynchronize(b->stream);
+            auto& mem = b->eng.mem;
+            mem.erase(std::remove(mem.begin(), mem.end(), c), mem.end());
+            c->batch = nullptr;
+            (void)engine_plan(b->eng, b->stream);
+        }
+    }
     (void)hipStreamSynchronize(c->stream);
     engine_free(c->eng);
     for (auto& p : c->pending) {

@@ -48,9 +48,8 @@ def make_requests(n, rate=50.0, steps=500, seed=0, first=0):
 
 
 def workspace_bytes(work, precision):
-    cfg = cc.make_config(work["grid"], precision)
-    body, _ = cc.make_body(work["body"])
-    return cc.cc_workspace_bytes(cfg, body)
+    """Device bytes a request holds while admitted: everything its Solver allocates."""
+    return cc.Solver.device_bytes(work["grid"], work["body"], precision)
 
 
 class Server:
