@@ -159,6 +159,26 @@ cc_status cc_surface_loads(cc_ctx* ctx, double* h_out4);
 /* Conservation totals sum(U) hx hy per component, FP64, deterministic order.  Host out. */
 cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the totals of cc_totals for a state
+ * held outside any context, computed by the same kernels in the same order (so the two
+ * agree bit for bit for the same state), written to device memory.  It allocates nothing:
+ * the partial sums go to a scratch array of 4 x 1024 doubles (32 KiB) that the library
+ * keeps in each device's memory from the first call on that device until the process
+ * ends.  All calls on one device share that array, so calls that overlap in time on one
+ * device (from different streams or threads) race: serialise them.
+ *   d_u: device, 4 planes (rho, rho u, rho v, E per unit cell volume) of nx*ny values,
+ *        FP64 for precision CC_FP64, FP32 for CC_FP32_GEOM64; read only;
+ *   hx, hy: cell sizes (the totals are sums times hx hy);
+ *   hip_stream: a hipStream_t of the current device (NULL = default stream);
+ *   d_out4: device, 4 doubles, written asynchronously on hip_stream.
+ * Returns at once (asynchronous).  CC_ERR_ARG for null pointers, sizes below 1 or an
+ * unknown precision; CC_ERR_UNSUPPORTED above CC_TOTALS_STATE_MAX_CELLS cells;
+ * CC_ERR_DEVICE if the launch fails.  cc_last_error(NULL) gives the message. */
+#define CC_TOTALS_STATE_MAX_CELLS 2147483647
+cc_status cc_totals_state(const void* d_u, int32_t precision, int32_t nx, int32_t ny, double hx, double hy,
+                          void* hip_stream, double* d_out4);
+
 /* Host info vector (n entries used, up to 10): time, steps, parity, device status bits
  * (1: a cell became fluid without donors; 2: a cell stayed inadmissible after collapsing;
  * 8: a grid-barrier wait of a persistent launch ran out),

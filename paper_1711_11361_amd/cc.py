@@ -62,6 +62,7 @@ _sig = {
     "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
     "cc_advance": (C.c_int, [_vp, _i32, _d, C.POINTER(_d), C.POINTER(C.c_float), C.POINTER(_i32)]),
     "cc_totals": (C.c_int, [_vp, C.POINTER(_d)]),
+    "cc_totals_state": (C.c_int, [_vp, _i32, _i32, _i32, _d, _d, _vp, _vp]),
     "cc_surface_loads": (C.c_int, [_vp, C.POINTER(_d)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
@@ -213,6 +214,13 @@ def cc_totals(ctx):
     out = (_d * 4)()
     _check(ctx, _lib.cc_totals(ctx, out))
     return np.array(out[:])
+
+
+def cc_totals_state(d_u, precision, nx, ny, hx, hy, stream, d_out4):
+    """Totals of a state held outside any context (device pointers), asynchronous on
+    `stream`; allocates nothing."""
+    _check(None, _lib.cc_totals_state(_vp(d_u), int(precision), int(nx), int(ny), float(hx), float(hy),
+                                      _vp(stream), _vp(d_out4)))
 
 
 def cc_info(ctx):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -268,7 +269,9 @@ struct cc_batch {
 
 namespace {
 
-thread_local std::string g_create_err;  // message of the last failed cc_create on this thread
+// message of the last failed call without a context (cc_create, cc_totals_state) on this
+// thread; cc_last_error(NULL) returns it
+thread_local std::string g_create_err;
 
 cc_status fail(cc_ctx* c, cc_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -1731,13 +1734,79 @@ cc_status cc_totals(cc_ctx* c, double* h_totals4) {
     else
         hipLaunchKernelGGL(k_sum_partial<double>, dim3(NPART, 4), dim3(RT), 0, c->stream, nc, 4,
                            at<double>(c, c->lay.off_u[c->cur]), chunk, part);
-    hipLaunchKernelGGL(k_sum_final, dim3(4), dim3(RT), 0, c->stream, NPART, (const double*)part, tot);
+    hipLaunchKernelGGL(k_sum_final, dim3(4), dim3(RT), 0, c->stream, NPART, (const double*)part, 1.0, tot);
     HIPCHK(c, hipGetLastError());
     double h[4];
     HIPCHK(c, hipMemcpyAsync(h, tot, 32, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double area = c->hx * c->hy;
     for (int k = 0; k < 4; k++) h_totals4[k] = h[k] * area;
+    return CC_OK;
+}
+
+}  // extern "C"
+
+// Scratch of cc_totals_state: the per-block partial sums (4 components x NPART blocks) of
+// the deterministic sum.  Every device the library runs on holds its own copy until the
+// process ends.  Host code must not use this name as a device address (on the host it is
+// only a stand-in for the symbol); it uses the address hipGetSymbolAddress returns for
+// the current device.
+static __device__ __align__(256) double scratch[4 * NPART];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+// Device address of the current device's scratch array, looked up on the first call on
+// that device (with the device current) and kept.
+hipError_t scratch_address(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_totals_state(const void* d_u, int32_t precision, int32_t nx, int32_t ny, double hx, double hy,
+                          void* hip_stream, double* d_out4) {
+    auto bad = [](cc_status st, const char* msg) {
+        g_create_err = msg;
+        return st;
+    };
+    if (!d_u || !d_out4 || nx < 1 || ny < 1 || (precision != CC_FP64 && precision != CC_FP32_GEOM64) ||
+        !std::isfinite(hx) || !std::isfinite(hy))
+        return bad(CC_ERR_ARG, "bad argument");
+    size_t nc = (size_t)nx * (size_t)ny;
+    if (nc > (size_t)CC_TOTALS_STATE_MAX_CELLS)
+        return bad(CC_ERR_UNSUPPORTED, "state larger than CC_TOTALS_STATE_MAX_CELLS cells");
+    double* part = nullptr;
+    hipError_t e = scratch_address(&part);
+    if (e != hipSuccess) return bad(CC_ERR_DEVICE, "scratch address lookup failed");
+    hipStream_t s = (hipStream_t)hip_stream;
+    size_t chunk = (nc + NPART - 1) / NPART;
+    // the same launches as cc_totals, so the two agree bit for bit
+    if (precision == CC_FP32_GEOM64)
+        hipLaunchKernelGGL(k_sum_partial<float>, dim3(NPART, 4), dim3(RT), 0, s, nc, 4, (const float*)d_u, chunk,
+                           part);
+    else
+        hipLaunchKernelGGL(k_sum_partial<double>, dim3(NPART, 4), dim3(RT), 0, s, nc, 4, (const double*)d_u, chunk,
+                           part);
+    hipLaunchKernelGGL(k_sum_final, dim3(4), dim3(RT), 0, s, NPART, (const double*)part, hx * hy, d_out4);
+    if (hipGetLastError() != hipSuccess) return bad(CC_ERR_DEVICE, "launch failed");
     return CC_OK;
 }
 

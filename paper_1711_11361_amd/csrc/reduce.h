@@ -176,7 +176,8 @@ __global__ __launch_bounds__(RT) void k_sum_partial(size_t n, int comps, const R
     (void)comps;
 }
 
-__global__ __launch_bounds__(RT) void k_sum_final(int nblocks, const double* __restrict__ part,
+// out[c] = (sum of the partials of component c) * scale
+__global__ __launch_bounds__(RT) void k_sum_final(int nblocks, const double* __restrict__ part, double scale,
                                                   double* __restrict__ out) {
     __shared__ double s[RT];
     int c = blockIdx.x;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(RT) void k_sum_final(int nblocks, const double* __r
         if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[c] = s[0];
+    if (threadIdx.x == 0) out[c] = s[0] * scale;
 }
 
 }  // namespace cc
