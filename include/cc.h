@@ -156,8 +156,23 @@ cc_status cc_advance(cc_ctx* ctx, int32_t nsteps, double cfl, double* h_dt, floa
  * and no open step (CC_ERR_ARG).  Synchronizes. */
 cc_status cc_surface_loads(cc_ctx* ctx, double* h_out4);
 
-/* Conservation totals sum(U) hx hy per component, FP64, deterministic order.  Host out. */
-cc_status cc_totals(cc_ctx* ctx, double* h_totals4);
+/* Conservation totals sum(U) hx hy per component (rho, rho u, rho v, E), FP64,
+ * deterministic order, into h_totals4 (host).  h_budget12 (host, nullable): the
+ * conservation budget since cc_set_state (Sec. 3.3, mass-conservation error), zeros unless
+ * cc_set_budget switched it on: [0..3] the fluxes through the domain boundary (dt/h times
+ * the stabilised face fluxes of the first and last face of every line, in minus out, times
+ * the cell area), [4..7] the wall pressure terms of the cut cells (dt/h times
+ * (beta_hi - beta_lo)(F^B - u_wall Q^B) times the cell area; zero for mass), [8..11] the
+ * residuals of emptied cells that found no recipient (times the cell area).  The totals
+ * then change by boundary + wall - lost: with FP64 state to round-off, with FP32 state up to
+ * the state's rounding (the mass drift).  Synchronises. */
+cc_status cc_totals(cc_ctx* ctx, double* h_totals4, double* h_budget12);
+
+/* Track the conservation budget (on = 1) or not (0, the default).  Switching it on resets
+ * the running sums.  Tracking costs a few writes per boundary cell and a longer collapse
+ * launch per sweep; it is not available in the persistent launch mode
+ * (CC_ERR_UNSUPPORTED).  Synchronises. */
+cc_status cc_set_budget(cc_ctx* ctx, int32_t on);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): the totals of cc_totals for a state

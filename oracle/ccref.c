@@ -415,23 +415,29 @@ static void compute_level(ccref_ctx* c, const double* pv, int m, level_t* L) {
     L->m = m;
     poly_t P;
     poly_init(&P, L->poly, m);
-    double* b1 = malloc(sizeof(double) * 2 * (size_t)(m + 8));
-    double* b2 = malloc(sizeof(double) * 2 * (size_t)(m + 8));
+    /* every loop below writes each item once from the level's inputs only: the rows may
+     * run in any order (OpenMP build) with identical results */
+#pragma omp parallel for schedule(static)
     for (int j = 0; j <= ny; j++)
         for (int i = 0; i <= nx; i++) L->vcls[VIDX(c, i, j)] = (int8_t)classify(&P, vx_of(c, i), vy_of(c, j));
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i <= nx; i++) {
             size_t f = BXIDX(c, i, j);
             face_interval(&P, vx_of(c, i), vy_of(c, j), L->vcls[VIDX(c, i, j)], vx_of(c, i),
                           vy_of(c, j + 1), L->vcls[VIDX(c, i, j + 1)], &L->fx[2 * f], &L->fx[2 * f + 1]);
         }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j <= ny; j++)
         for (int i = 0; i < nx; i++) {
             size_t f = BYIDX(c, i, j);
             face_interval(&P, vx_of(c, i), vy_of(c, j), L->vcls[VIDX(c, i, j)], vx_of(c, i + 1),
                           vy_of(c, j), L->vcls[VIDX(c, i + 1, j)], &L->fy[2 * f], &L->fy[2 * f + 1]);
         }
-    for (int j = 0; j < ny; j++)
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; j++) {
+        double* b1 = malloc(sizeof(double) * 2 * (size_t)(m + 8));
+        double* b2 = malloc(sizeof(double) * 2 * (size_t)(m + 8));
         for (int i = 0; i < nx; i++) {
             double b[4] = {beta_x(c, L, i, j), beta_x(c, L, i + 1, j), beta_y(c, L, i, j),
                            beta_y(c, L, i, j + 1)};
@@ -454,8 +460,9 @@ static void compute_level(ccref_ctx* c, const double* pv, int m, level_t* L) {
             }
             L->alpha[CIDX(c, i, j)] = a;
         }
-    free(b1);
-    free(b2);
+        free(b1);
+        free(b2);
+    }
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -939,23 +946,27 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
     {
         poly_t Ps;
         poly_init(&Ps, Ls->poly, Ls->m);
-        double* b1 = malloc(sizeof(double) * 2 * (size_t)(Ls->m + 8));
-        double* b2 = malloc(sizeof(double) * 2 * (size_t)(Ls->m + 8));
-        if (dir == 0) {
-            for (int j = 0; j < ny; j++)
+        int rows = dir == 0 ? ny : ny + 1;
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < rows; j++) {
+            double* b1 = malloc(sizeof(double) * 2 * (size_t)(Ls->m + 8));
+            double* b2 = malloc(sizeof(double) * 2 * (size_t)(Ls->m + 8));
+            if (dir == 0) {
                 for (int i = 0; i <= nx; i++) btd[BXIDX(c, i, j)] = swept_beta(c, Ls, Le, &Ps, 0, i, j, b1, b2);
-        } else {
-            for (int j = 0; j <= ny; j++)
+            } else {
                 for (int i = 0; i < nx; i++) btd[BYIDX(c, i, j)] = swept_beta(c, Ls, Le, &Ps, 1, i, j, b1, b2);
+            }
+            free(b1);
+            free(b2);
         }
-        free(b1);
-        free(b2);
     }
 
     /* --- 3. per-cell sweep geometry, states and wall quantities --- */
     cellinfo* ci = calloc(nc, sizeof(cellinfo));
     double* Q = malloc(sizeof(double) * 4 * nc);
     unsigned char* has = calloc(nc, 1);
+    /* each cell's quantities depend on its own inputs only (rows in any order) */
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
             size_t k = CIDX(c, i, j);
@@ -1060,15 +1071,20 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
     int bclo = dir == 0 ? c->cfg.bc[0] : c->cfg.bc[2];
     int bchi = dir == 0 ? c->cfg.bc[1] : c->cfg.bc[3];
     int nd = 1 + dir;
-    /* per-line buffers with two ghost cells on each side: index p+2 for cell p */
-    double(*lq)[4] = malloc(sizeof(double[4]) * (n + 4));
-    unsigned char* lh = malloc(n + 4);
-    double(*el)[4] = malloc(sizeof(double[4]) * (n + 4));
-    double(*er)[4] = malloc(sizeof(double[4]) * (n + 4));
-    double(*F)[4] = malloc(sizeof(double[4]) * (n + 1));
-    double(*PHI)[4] = malloc(sizeof(double[4]) * (n + 1));
-    double* bt = malloc(sizeof(double) * (n + 1));
+    /* budget terms per line, added up in line order after the loop (lines are independent
+     * and may run in any order) */
+    double(*lbnd)[4] = calloc((size_t)nl, sizeof(double[4]));
+    double(*lwall)[4] = calloc((size_t)nl, sizeof(double[4]));
+#pragma omp parallel for schedule(static)
     for (int line = 0; line < nl; line++) {
+        /* per-line buffers with two ghost cells on each side: index p+2 for cell p */
+        double(*lq)[4] = malloc(sizeof(double[4]) * (n + 4));
+        unsigned char* lh = malloc(n + 4);
+        double(*el)[4] = malloc(sizeof(double[4]) * (n + 4));
+        double(*er)[4] = malloc(sizeof(double[4]) * (n + 4));
+        double(*F)[4] = malloc(sizeof(double[4]) * (n + 1));
+        double(*PHI)[4] = malloc(sizeof(double[4]) * (n + 1));
+        double* bt = malloc(sizeof(double) * (n + 1));
 #define CELL(p) (dir == 0 ? CIDX(c, (p), line) : CIDX(c, line, (p)))
         for (int p = 0; p < n; p++) {
             size_t k = CELL(p);
@@ -1153,7 +1169,7 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
                 double db = bt[p + 1] - bt[p];
                 double ud = dir == 0 ? e->uwx : e->uwy;
                 for (int m = 0; m < 4; m++) W[m] = db * (e->fb[m] - ud * e->qb[m]);
-                for (int m = 0; m < 4; m++) c->wall[m] += lam * W[m] * area;
+                for (int m = 0; m < 4; m++) lwall[line][m] += lam * W[m] * area;
             }
             for (int m = 0; m < 4; m++)
                 U2[m * nc + k] = U1[m * nc + k] + lam * ((PHI[p][m] - PHI[p + 1][m]) + W[m]);
@@ -1176,16 +1192,23 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
                 r[30] = has[k];
             }
         }
-        for (int m = 0; m < 4; m++) c->bnd[m] += lam * (PHI[0][m] - PHI[n][m]) * area;
+        for (int m = 0; m < 4; m++) lbnd[line][m] = lam * (PHI[0][m] - PHI[n][m]) * area;
 #undef CELL
+        free(lq);
+        free(lh);
+        free(el);
+        free(er);
+        free(F);
+        free(PHI);
+        free(bt);
     }
-    free(lq);
-    free(lh);
-    free(el);
-    free(er);
-    free(F);
-    free(PHI);
-    free(bt);
+    for (int line = 0; line < nl; line++)
+        for (int m = 0; m < 4; m++) {
+            c->bnd[m] += lbnd[line][m];
+            c->wall[m] += lwall[line][m];
+        }
+    free(lbnd);
+    free(lwall);
 
     /* --- 5. collapse: a live cell whose updated content is not an admissible gas state
      *        (rho <= 0 or p <= 0) is emptied like a covered cell and refilled at the start

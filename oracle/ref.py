@@ -25,15 +25,17 @@ class _Body(C.Structure):
                 ("pitch_omega", C.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        _lib = C.CDLL(_build.ensure_built())
+def lib(parallel=False):
+    """The oracle library: the plain build, or (parallel) the OpenMP build of the same
+    source, which gives identical results on all host cores."""
+    L = _libs.get(parallel)
+    if L is None:
+        L = C.CDLL(_build.ensure_built(parallel))
+        _libs[parallel] = L
         d, i, p, vp = C.c_double, C.c_int, C.POINTER(C.c_double), C.c_void_p
-        L = _lib
         L.ccref_create.restype = vp
         L.ccref_create.argtypes = [C.POINTER(_Config), C.POINTER(_Body)]
         L.ccref_destroy.argtypes = [vp]
@@ -85,7 +87,7 @@ def lib():
         L.ccref_trace.argtypes = [vp, i, i]
         L.ccref_trace_get.argtypes = [vp, p]
         L.ccref_set_option.argtypes = [vp, i, i]
-    return _lib
+    return L
 
 
 def _dp(a):
@@ -138,7 +140,8 @@ def wall_riemann(q, n, uw, gamma=1.4):
 class Oracle:
     """One oracle simulation: a grid, a rigid body and the level-n state."""
 
-    def __init__(self, grid, body=None):
+    def __init__(self, grid, body=None, parallel=False):
+        self._L = lib(parallel)
         self.grid = dict(grid)
         cfg = _Config()
         cfg.nx, cfg.ny = grid["nx"], grid["ny"]
@@ -165,14 +168,14 @@ class Oracle:
         else:
             b.nverts = 0
         self.m = b.nverts
-        h = lib().ccref_create(C.byref(cfg), C.byref(b))
+        h = self._L.ccref_create(C.byref(cfg), C.byref(b))
         if not h:
             raise ValueError("oracle: invalid configuration")
         self._h = C.c_void_p(h)
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().ccref_destroy(self._h)
+            self._L.ccref_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -184,61 +187,61 @@ class Oracle:
     # state
     def set_prim(self, prim, t0=0.0):
         prim = _f64(prim).reshape(4, self.ny, self.nx)
-        lib().ccref_set_prim(self._h, _dp(prim), t0)
+        self._L.ccref_set_prim(self._h, _dp(prim), t0)
 
     def set_clock(self, t, step):
         """Resume at time t after `step` split steps (sweep order and level-n geometry of an
         uninterrupted run); set the state afterwards."""
-        if lib().ccref_set_clock(self._h, float(t), int(step)) != 0:
+        if self._L.ccref_set_clock(self._h, float(t), int(step)) != 0:
             raise ValueError("bad step count")
 
     def set_u(self, U):
         U = _f64(U).reshape(4, self.ny, self.nx)
-        lib().ccref_set_u(self._h, _dp(U))
+        self._L.ccref_set_u(self._h, _dp(U))
 
     def get_u(self):
         U = np.zeros((4, self.ny, self.nx))
-        lib().ccref_get_u(self._h, _dp(U))
+        self._L.ccref_get_u(self._h, _dp(U))
         return U
 
     def get_prim(self):
         P = np.zeros((4, self.ny, self.nx))
-        lib().ccref_get_prim(self._h, _dp(P))
+        self._L.ccref_get_prim(self._h, _dp(P))
         return P
 
     @property
     def t(self):
-        return lib().ccref_time(self._h)
+        return self._L.ccref_time(self._h)
 
     @property
     def steps(self):
-        return lib().ccref_steps(self._h)
+        return self._L.ccref_steps(self._h)
 
     @property
     def parity(self):
-        return lib().ccref_parity(self._h)
+        return self._L.ccref_parity(self._h)
 
     @property
     def status(self):
-        return lib().ccref_status(self._h)
+        return self._L.ccref_status(self._h)
 
     @property
     def collapses(self):
-        return lib().ccref_collapses(self._h)
+        return self._L.ccref_collapses(self._h)
 
     # geometry
     def pose(self, t):
         out = np.zeros(2 * max(self.m, 1))
-        lib().ccref_pose(self._h, t, _dp(out))
+        self._L.ccref_pose(self._h, t, _dp(out))
         return out[: 2 * self.m].reshape(-1, 2)
 
     def geometry(self, t, which=0):
-        if lib().ccref_geometry(self._h, t, which):
+        if self._L.ccref_geometry(self._h, t, which):
             raise ValueError("bad level")
 
     def geometry_poly(self, posed, which=0):
         posed = _f64(np.asarray(posed).reshape(-1))
-        if lib().ccref_geometry_poly(self._h, _dp(posed), len(posed) // 2, which):
+        if self._L.ccref_geometry_poly(self._h, _dp(posed), len(posed) // 2, which):
             raise ValueError("bad level")
 
     def geometry_dump(self, which=0):
@@ -247,80 +250,80 @@ class Oracle:
         al = np.zeros((ny, nx))
         bx = np.zeros((ny, nx + 1))
         by = np.zeros((ny + 1, nx))
-        lib().ccref_geometry_dump(self._h, which, vc.ctypes.data_as(C.POINTER(C.c_int8)),
+        self._L.ccref_geometry_dump(self._h, which, vc.ctypes.data_as(C.POINTER(C.c_int8)),
                                   _dp(al), _dp(bx), _dp(by))
         return {"vcls": vc, "alpha": al, "bx": bx, "by": by}
 
     def wall_point(self, i, j, which=0):
         out = np.zeros(2)
-        ok = lib().ccref_wall_point(self._h, which, i, j, _dp(out))
+        ok = self._L.ccref_wall_point(self._h, which, i, j, _dp(out))
         return out if ok else None
 
     def face_intervals(self, which=0):
         nx, ny = self.nx, self.ny
         fx = np.zeros((ny, nx + 1, 2))
         fy = np.zeros((ny + 1, nx, 2))
-        lib().ccref_face_intervals(self._h, which, _dp(fx), _dp(fy))
+        self._L.ccref_face_intervals(self._h, which, _dp(fx), _dp(fy))
         return fx, fy
 
     # time stepping
     def wave_speeds(self):
         out = np.zeros(2)
-        lib().ccref_wave_speeds(self._h, _dp(out))
+        self._L.ccref_wave_speeds(self._h, _dp(out))
         return out
 
     def cfl_dt(self, cfl):
-        return lib().ccref_cfl_dt(self._h, cfl)
+        return self._L.ccref_cfl_dt(self._h, cfl)
 
     def begin_step(self, dt):
-        if lib().ccref_begin_step(self._h, dt):
+        if self._L.ccref_begin_step(self._h, dt):
             raise RuntimeError("begin_step refused")
 
     def sweep(self, d, dt):
-        if lib().ccref_sweep(self._h, d, dt):
+        if self._L.ccref_sweep(self._h, d, dt):
             raise RuntimeError("sweep refused")
 
     def end_step(self):
-        if lib().ccref_end_step(self._h):
+        if self._L.ccref_end_step(self._h):
             raise RuntimeError("end_step refused")
 
     def step(self, dt):
-        if lib().ccref_step(self._h, dt):
+        if self._L.ccref_step(self._h, dt):
             raise RuntimeError("step refused")
 
     def totals(self):
         out = np.zeros(4)
-        lib().ccref_totals(self._h, _dp(out))
+        self._L.ccref_totals(self._h, _dp(out))
         return out
 
     def surface_loads(self):
         """(Fx, Fy, Mz about the pose origin, sum p*|N|) of the gas on the body at level n."""
         out = np.zeros(4)
-        lib().ccref_surface_loads(self._h, _dp(out))
+        self._L.ccref_surface_loads(self._h, _dp(out))
         return out
 
     def budget(self):
         b, w, l = np.zeros(4), np.zeros(4), np.zeros(4)
-        lib().ccref_budget(self._h, _dp(b), _dp(w), _dp(l))
+        self._L.ccref_budget(self._h, _dp(b), _dp(w), _dp(l))
         return b, w, l
 
     # test hooks
     def body_velocity(self, t, x, y):
         out = np.zeros(2)
-        lib().ccref_body_velocity(self._h, t, x, y, _dp(out))
+        self._L.ccref_body_velocity(self._h, t, x, y, _dp(out))
         return out
 
     def step_disp(self, d, x, y):
         """Displacement along d of (x, y) under the rigid map of the open step."""
-        return lib().ccref_step_disp(self._h, d, x, y)
+        return self._L.ccref_step_disp(self._h, d, x, y)
 
     def trace(self, i, j):
         """Record the sweep quantities of cell (i, j) in the following sweeps."""
-        lib().ccref_trace(self._h, i, j)
+        self._L.ccref_trace(self._h, i, j)
 
     def trace_get(self):
         r = np.zeros(31)
-        lib().ccref_trace_get(self._h, _dp(r))
+        self._L.ccref_trace_get(self._h, _dp(r))
         return {"F_lo": r[0:4], "F_hi": r[4:8], "phi_lo": r[8:12], "phi_hi": r[12:16], "FB": r[16:20],
                 "Q": r[20:24], "alpha_s": r[24], "alpha_e": r[25], "bt_lo": r[26], "bt_hi": r[27],
                 "ahat": r[28], "wall": bool(r[29]), "has": bool(r[30])}
@@ -328,7 +331,7 @@ class Oracle:
     def set_uncover_moves_content(self, on):
         """Oracle-only: cells that become fluid take content from their donors as printed
         (instead of a state only, reading R13)."""
-        lib().ccref_set_option(self._h, 1, int(bool(on)))
+        self._L.ccref_set_option(self._h, 1, int(bool(on)))
 
     def run(self, cfl, nsteps=None, t_end=None, dts=None):
         """Advance with the CFL time step; returns the list of dt used."""

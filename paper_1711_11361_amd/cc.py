@@ -61,7 +61,8 @@ _sig = {
     "cc_step": (C.c_int, [_vp, _d]),
     "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
     "cc_advance": (C.c_int, [_vp, _i32, _d, C.POINTER(_d), C.POINTER(C.c_float), C.POINTER(_i32)]),
-    "cc_totals": (C.c_int, [_vp, C.POINTER(_d)]),
+    "cc_totals": (C.c_int, [_vp, C.POINTER(_d), C.POINTER(_d)]),
+    "cc_set_budget": (C.c_int, [_vp, _i32]),
     "cc_totals_state": (C.c_int, [_vp, _i32, _i32, _i32, _d, _d, _vp, _vp]),
     "cc_surface_loads": (C.c_int, [_vp, C.POINTER(_d)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
@@ -210,10 +211,19 @@ def cc_surface_loads(ctx):
     return np.array(out[:])
 
 
-def cc_totals(ctx):
+def cc_totals(ctx, with_budget=False):
+    """Totals (4 components); with_budget: also (boundary, wall, lost), 4 components each."""
     out = (_d * 4)()
-    _check(ctx, _lib.cc_totals(ctx, out))
-    return np.array(out[:])
+    bud = (_d * 12)() if with_budget else None
+    _check(ctx, _lib.cc_totals(ctx, out, bud))
+    if not with_budget:
+        return np.array(out[:])
+    b = np.array(bud[:])
+    return np.array(out[:]), (b[0:4], b[4:8], b[8:12])
+
+
+def cc_set_budget(ctx, on):
+    _check(ctx, _lib.cc_set_budget(ctx, int(bool(on))))
 
 
 def cc_totals_state(d_u, precision, nx, ny, hx, hy, stream, d_out4):
@@ -453,6 +463,14 @@ class Solver:
 
     def totals(self):
         return cc_totals(self.ctx)
+
+    def set_budget(self, on=True):
+        """Track the conservation budget from now on (resets it)."""
+        cc_set_budget(self.ctx, on)
+
+    def budget(self):
+        """(boundary, wall, lost) since the state was set, as the oracle's budget()."""
+        return cc_totals(self.ctx, True)[1]
 
     def surface_loads(self):
         """(Fx, Fy, Mz about the pose origin, sum p*|N|) of the gas on the body at level n."""

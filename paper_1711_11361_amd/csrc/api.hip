@@ -72,6 +72,8 @@ struct Layout {
     size_t off_args, off_offs, off_cflout;
     size_t off_smax, off_status, off_ncol, off_part, off_tot, off_spd;
     size_t off_pconst, off_pstate, off_dtlog;
+    size_t off_budget, off_bslot;
+    int bs_patch, bs_cover;  // offsets (doubles) of the patch and covering budget slots
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
     int spd_dense;   // partial speed pairs reserved for dense tiles (the most any tile shape uses)
@@ -182,6 +184,15 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_pconst = take(sizeof(PlanConst));
     L.off_pstate = take(sizeof(PlanState));
     L.off_dtlog = take((size_t)DTLOG * 8);
+    // budget: running sums, and the per-sweep slots (dense: two per line of either sweep;
+    // patch segments: 12 doubles each; covering blocks: 4 each)
+    L.off_budget = take(16 * 8);
+    size_t dense_slots = 2 * std::max(nx, ny);
+    size_t patch_blocks = m > 0 ? (size_t)std::max(patch_line_blocks<0>(L.capw, L.caph), patch_line_blocks<1>(L.capw, L.caph)) : 1;
+    size_t cover_blocks = (std::max<size_t>(L.cap, 1) + T_BOX - 1) / T_BOX;
+    L.bs_patch = (int)(BS_DENSE + 4 * dense_slots);
+    L.bs_cover = (int)(L.bs_patch + 12 * patch_blocks);
+    L.off_bslot = take(8 * ((size_t)L.bs_cover + 4 * cover_blocks));
     L.total = o;
     return L;
 }
@@ -257,6 +268,7 @@ struct cc_ctx {
     bool speeds_ready;
     int speeds_buf;
     int advanced;  // steps completed by the last cc_advance
+    bool budget_on;  // the conservation budget is tracked (cc_set_budget)
     std::string err;
 };
 
@@ -500,6 +512,10 @@ void base_args(cc_ctx* c, StepArgs& a) {
     a.nb_swept = geo_blocks(c, GEO_SWEPT);
     a.spd = at<unsigned long long>(c, c->lay.off_spd);
     a.spd_dense = c->lay.spd_dense;
+    a.bs.base = c->budget_on ? at<double>(c, c->lay.off_bslot) : nullptr;
+    a.bs.patch = c->lay.bs_patch;
+    a.bs.cover = c->lay.bs_cover;
+    a.budget = at<double>(c, c->lay.off_budget);
     for (int k = 0; k < 2; k++) {
         GeoJob& J = a.geo[k];
         J.body = at<double>(c, c->lay.off_body);
@@ -1031,6 +1047,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     c->speeds_ready = false;
     c->speeds_buf = 0;
     c->batch = nullptr;
+    c->budget_on = false;
     c->in_step = c->have_state = false;
     c->t = 0.0;
     c->step = 0;
@@ -1083,6 +1100,7 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_smax, 0, 16, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_status, 0, 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_ncol, 0, 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_budget, 0, 16 * 8, c->stream);
     if (e == hipSuccess) e = engine_plan(E, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
@@ -1203,9 +1221,23 @@ cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
                            at<double>(c, c->lay.off_u[0]));
     HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_status, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_ncol, 0, 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_budget, 0, 16 * 8, c->stream));
     if (c->m > 0) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
     HIPCHK(c, hipGetLastError());
     c->have_state = true;
+    return CC_OK;
+}
+
+cc_status cc_set_budget(cc_ctx* c, int32_t on) {
+    if (!c || (on != 0 && on != 1)) return fail(c, CC_ERR_ARG, "bad argument");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_set_budget inside a step");
+    if (on && (c->eng.mode == CC_LAUNCH_PERSISTENT || (c->batch && c->batch->eng.mode == CC_LAUNCH_PERSISTENT)))
+        return fail(c, CC_ERR_UNSUPPORTED, "the budget is not tracked in the persistent launch mode");
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // captured steps hold the argument blocks of the old setting
+    if (c->batch) HIPCHK(c, hipStreamSynchronize(c->batch->stream));
+    c->budget_on = on != 0;
+    HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_budget, 0, 16 * 8, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return CC_OK;
 }
 
@@ -1722,8 +1754,12 @@ cc_status cc_advance(cc_ctx* c, int32_t nsteps, double cfl, double* h_dt, float*
     return st;
 }
 
-cc_status cc_totals(cc_ctx* c, double* h_totals4) {
+cc_status cc_totals(cc_ctx* c, double* h_totals4, double* h_budget12) {
     if (!c || !h_totals4) return fail(c, CC_ERR_ARG, "bad argument");
+    if (h_budget12) {
+        if (c->batch) HIPCHK(c, hipStreamSynchronize(c->batch->stream));
+        HIPCHK(c, hipMemcpyAsync(h_budget12, c->ws + c->lay.off_budget, 12 * 8, hipMemcpyDeviceToHost, c->stream));
+    }
     size_t nc = c->lay.nc;
     size_t chunk = (nc + NPART - 1) / NPART;
     double* part = at<double>(c, c->lay.off_part);
@@ -1947,6 +1983,8 @@ cc_status cc_set_launch_mode(cc_ctx* c, int32_t mode) {
     if (!c) return CC_ERR_ARG;
     if (mode != CC_LAUNCH_PER_PHASE && mode != CC_LAUNCH_PERSISTENT) return fail(c, CC_ERR_ARG, "unknown launch mode");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_set_launch_mode inside a step");
+    if (mode == CC_LAUNCH_PERSISTENT && c->budget_on)
+        return fail(c, CC_ERR_UNSUPPORTED, "the budget is not tracked in the persistent launch mode");
     HIPCHK(c, hipStreamSynchronize(c->stream));  // the captured graphs are about to be destroyed
     c->eng.mode = mode;
     HIPCHK(c, engine_plan(c->eng, c->stream));
@@ -2048,6 +2086,8 @@ cc_status cc_batch_add(cc_batch* b, cc_ctx* c) {
     if (c->cfg.precision != E.prec) return bfail(b, CC_ERR_ARG, "precision differs from the batch's");
     if ((int)E.mem.size() >= E.cap_n) return bfail(b, CC_ERR_WORKSPACE, "batch is full");
     if (!c->have_state || c->in_step) return bfail(b, CC_ERR_ARG, "context needs a state and no open step");
+    if (c->budget_on && E.mode == CC_LAUNCH_PERSISTENT)
+        return bfail(b, CC_ERR_UNSUPPORTED, "the context tracks its budget (not in the persistent mode)");
     BHIPCHK(b, hipStreamSynchronize(c->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     E.mem.push_back(c);
@@ -2084,6 +2124,9 @@ int32_t cc_batch_size(const cc_batch* b) { return b ? (int32_t)b->eng.mem.size()
 cc_status cc_batch_set_launch_mode(cc_batch* b, int32_t mode) {
     if (!b) return CC_ERR_ARG;
     if (mode != CC_LAUNCH_PER_PHASE && mode != CC_LAUNCH_PERSISTENT) return bfail(b, CC_ERR_ARG, "unknown launch mode");
+    if (mode == CC_LAUNCH_PERSISTENT)
+        for (cc_ctx* c : b->eng.mem)
+            if (c->budget_on) return bfail(b, CC_ERR_UNSUPPORTED, "a member tracks its budget (not in the persistent mode)");
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     b->eng.mode = mode;
     BHIPCHK(b, engine_plan(b->eng, b->stream));
@@ -2168,11 +2211,5 @@ cc_status cc_batch_last_dt(cc_batch* b, double cfl, double* h_dt, int32_t* h_sta
 
 const char* cc_batch_last_error(const cc_batch* b) { return b ? b->err.c_str() : ""; }
 
-#ifdef CC_PHASE_TRACE
-// Development aid: the phase clock of the last persistent sweep launches (2 x 18 ticks).
-int cc_phase_trace(unsigned long long* h_out) {
-    return hipMemcpyFromSymbol(h_out, HIP_SYMBOL(g_phase_trace), sizeof(g_phase_trace)) == hipSuccess ? 0 : 2;
-}
-#endif
 
 }  // extern "C"

@@ -36,6 +36,11 @@ struct StepArgs {
     const PlanConst* pc;
     PlanState* ps;
     double* dtlog;
+    // conservation budget (bs.base null: not tracked): per-sweep slots, and the running
+    // sums since the state was set: domain-boundary fluxes, wall terms, residuals without
+    // recipients (4 components each, times the cell area)
+    BudgetSlots bs;
+    double* budget;
 };
 
 __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, StepArgs* out, double* dt_log);
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(PL_T) void kb_patch_lines(const StepArgs* __restric
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     if (J.dir != D || box_empty_dev(J.B)) return;
-    patch_line<D, R>(a.g, J, stage_of(a, s), a.ncol, w.lb, sh);
+    patch_line<D, R>(a.g, J, stage_of(a, s), a.ncol, w.lb, sh, a.bs);
 }
 
 template <typename R>
@@ -293,7 +298,17 @@ __global__ __launch_bounds__(T_BOX) void kb_cover(const StepArgs* __restrict__ A
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     int t = w.lb * T_BOX + threadIdx.x;
-    if (!box_empty_dev(J.B)) cover<R>(a.g, J, a.S, t);
+    if (!box_empty_dev(J.B)) {
+        double lost[4] = {0.0, 0.0, 0.0, 0.0};
+        cover<R>(a.g, J, a.S, t, lost, a.bs.base != nullptr);
+        if (a.bs.base) {  // T_BOX is one wavefront
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                double v = wave_sum(lost[m]);
+                if (threadIdx.x == 0) a.bs.base[a.bs.cover + 4 * w.lb + m] = v;
+            }
+        }
+    }
     if (speeds) box_speeds<R>(a, s, t);  // reads back the thread's own cell
 }
 
@@ -312,7 +327,7 @@ __device__ __forceinline__ void dense_x_block(const StepArgs* __restrict__ A, co
     const SweepJob& J = a.sw[s];
     if (J.dir != 0 || w.lb >= dense_x_blocks<RB>(a.g.nx, a.g.ny)) return;
     unsigned long long* cfl = fold_target(a, fold);
-    dense_x<R, R, RB>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl);
+    dense_x<R, R, RB>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl, a.bs.base);
 }
 template <typename R, int TR>
 __device__ __forceinline__ void dense_y_block(const StepArgs* __restrict__ A, const int* __restrict__ off, int n,
@@ -322,7 +337,7 @@ __device__ __forceinline__ void dense_y_block(const StepArgs* __restrict__ A, co
     const SweepJob& J = a.sw[s];
     if (J.dir != 1 || w.lb >= dense_y_blocks<TR>(a.g.nx, a.g.ny)) return;
     unsigned long long* cfl = fold_target(a, fold);
-    dense_y<R, R, TR>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl);
+    dense_y<R, R, TR>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, lds, cfl, a.bs.base);
 }
 
 template <typename R, int RW>
@@ -333,7 +348,7 @@ __device__ __forceinline__ void dense_yc_block(const StepArgs* __restrict__ A, c
     const SweepJob& J = a.sw[s];
     if (J.dir != 1 || w.lb >= dense_yc_blocks<RW>(a.g.nx, a.g.ny)) return;
     unsigned long long* cfl = fold_target(a, fold);
-    dense_yc<R, R, RW>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, cfl);
+    dense_yc<R, R, RW>(a.g, (const R*)J.Uin, (R*)J.Uout, J.B, (R)J.lam, w.lb, cfl, a.bs.base);
 }
 
 template <typename R, int RB>
@@ -444,12 +459,68 @@ __device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, in
     }
 }
 
+constexpr int T_FIX = 256;  // threads of the per-member collapse block
+
+// Adds the sweep's budget to the member's running sums: the fluxes through the domain
+// boundary (dense slots, then the patch segments' end faces) times dt/h and the cell
+// area, the wall terms likewise, and the residuals without recipients (covering blocks,
+// then the collapse rounds' `lost` of each thread) times the cell area.  Each thread sums
+// a fixed subset of the slots, then the block adds the threads' sums in a fixed tree, so
+// the result does not depend on timing.  Every thread of the block calls it.
+__device__ __forceinline__ void sweep_budget(const StepArgs& a, const SweepJob& J, int cells, const double* lost) {
+    const double* bs = a.bs.base;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) acc[q] = 0.0;  // lo, hi, wall, lost (4 components each)
+    int nd = (int)bs[0];
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        int side = k & 1;
+#pragma unroll
+        for (int m = 0; m < 4; m++) acc[4 * side + m] += bs[BS_DENSE + 4 * k + m];
+    }
+    int np = 0, ncov = 0;
+    if (cells > 0) {
+        int len = J.dir == 0 ? J.B.w() : J.B.h(), nlines = J.dir == 0 ? J.B.h() : J.B.w();
+        np = nlines * ((len + PL_OUT - 1) / PL_OUT);
+        ncov = (cells + T_BOX - 1) / T_BOX;
+    }
+    for (int k = threadIdx.x; k < np; k += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 12; q++) acc[q] += bs[a.bs.patch + 12 * k + q];
+    for (int k = threadIdx.x; k < ncov; k += blockDim.x)
+#pragma unroll
+        for (int m = 0; m < 4; m++) acc[12 + m] += bs[a.bs.cover + 4 * k + m];
+#pragma unroll
+    for (int m = 0; m < 4; m++) acc[12 + m] += lost[m];
+    __shared__ double red[16][T_FIX / 64];
+    int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        double v = wave_sum(acc[q]);
+        if ((threadIdx.x & 63) == 0) red[q][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[16];
+        for (int q = 0; q < 16; q++) {
+            tot[q] = red[q][0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); w++) tot[q] += red[q][w];
+        }
+        double area = a.g.hx * a.g.hy, f = J.lam * area;
+        for (int m = 0; m < 4; m++) {
+            a.budget[m] += f * (tot[m] - tot[4 + m]);
+            a.budget[4 + m] += f * tot[8 + m];
+            a.budget[8 + m] += area * tot[12 + m];
+        }
+    }
+    __syncthreads();
+}
+
 // Both collapse rounds of sweep s (reading R28) for every member, one block per member:
 // both return at once unless covering left a bad cell, which is rare, so one block walks
 // the whole box, with a block barrier between the rounds.  last: the sweep is the last of
 // a captured step; the block then also combines the member's wave-speed partials (the box
 // cells' speeds recomputed here when a round moved content) and gathers its status words.
-constexpr int T_FIX = 256;
 template <typename R>
 __global__ __launch_bounds__(T_FIX) void kb_fix_block(StepArgs* A, const int* __restrict__ off_dx,
                                                       const int* __restrict__ off_dy,
@@ -460,11 +531,14 @@ __global__ __launch_bounds__(T_FIX) void kb_fix_block(StepArgs* A, const int* __
     const SweepJob& J = a.sw[s];
     int cells = box_empty_dev(J.B) ? 0 : J.B.w() * J.B.h();
     bool bad = cells > 0 && __hip_atomic_load(&a.S.nbad[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    double lost[4] = {0.0, 0.0, 0.0, 0.0};  // this thread's collapsed cells without recipients
     if (bad)
         for (int round = 0; round < 2; round++) {
-            for (int t = threadIdx.x; t < cells; t += blockDim.x) fix<R>(a.g, J, a.S, round, a.ncol, a.status, t);
+            for (int t = threadIdx.x; t < cells; t += blockDim.x)
+                fix<R>(a.g, J, a.S, round, a.ncol, a.status, t, lost, a.bs.base != nullptr);
             __syncthreads();  // the round's flags and contents, for the next round and the speeds
         }
+    if (a.bs.base) sweep_budget(a, J, cells, lost);
     if (!last) return;
     unsigned long long bx = 0ull, by = 0ull;
     if (bad) {

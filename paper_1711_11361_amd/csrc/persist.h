@@ -156,15 +156,6 @@ __device__ __forceinline__ void each_box(const PArgs& p, F&& f) {
     }
 }
 
-#ifdef CC_PHASE_TRACE
-// Development aid (not built by default): wall-clock time at which block 0 leaves each
-// barrier, and at which the last block finishes, per sweep launch.
-__device__ unsigned long long g_phase_trace[2][MAX_BARRIERS + 2];
-#define PHASE_MARK(s, k) \
-    if (blockIdx.x == 0 && threadIdx.x == 0) g_phase_trace[s][k] = wall_clock64()
-#else
-#define PHASE_MARK(s, k)
-#endif
 
 template <typename R, int RB, int TR>
 __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
@@ -176,46 +167,46 @@ __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
     // blocks with work in the current phase: the first phase of sweep 0 poses the polygons,
     // that of sweep 1 is the stage-and-wall phase over the box cells
     int prv = busy(s == 0 ? wide_ext(p, L_POSE) : box_ext(p));
-    PHASE_MARK(s, 0);
     if (s == 0) {
         for (int lev = 0; lev < 2; lev++)
             each_wide(p, L_POSE, [&](const StepArgs& a, int lb, int) { pose_body(a, lev, lb * T_WIDE + tid); });
-        { int nx_ = busy(wide_ext(p, L_V1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+        { int nx_ = busy(wide_ext(p, L_V1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
         each_wide(p, L_V1, [&](const StepArgs& a, int lb, int nb) { geo_stage_split<0>(a, lb, nb, spoly); });
-        { int nx_ = busy(wide_ext(p, L_F1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+        { int nx_ = busy(wide_ext(p, L_F1)); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
         each_wide(p, L_F1, [&](const StepArgs& a, int lb, int nb) { geo_stage_split<1>(a, lb, nb, spoly); });
-        { int nx_ = busy(imax(wide_ext(p, L_C1), wide_ext(p, L_S1))); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+        { int nx_ = busy(imax(wide_ext(p, L_C1), wide_ext(p, L_S1))); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
         // cells, and the apertures of both sweeps (they need the faces of all three levels)
         each_wide(p, L_C1, [&](const StepArgs& a, int lb, int nb) { geo_stage_split<2>(a, lb, nb, spoly); });
         for (int sw = 0; sw < 2; sw++)
             each_wide(p, L_S1, [&](const StepArgs& a, int lb, int nb) { swept_block(a, sw, lb, nb, spoly); });
-        { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+        { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
     }
     each_box(p, [&](const StepArgs& a, int t) { stagewall_body<R>(a, s, t); });
-    { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+    { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
     each_box(p, [&](const StepArgs& a, int t) {
         const SweepJob& J = a.sw[s];
         if (box_empty_dev(J.B)) return;
         if (J.dir == 0) patch<0, R>(a.g, J, stage_of(a, s), a.ncol, t);
         else patch<1, R>(a.g, J, stage_of(a, s), a.ncol, t);
     });
-    { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+    { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
     each_box(p, [&](const StepArgs& a, int t) {
         const SweepJob& J = a.sw[s];
         if (box_empty_dev(J.B)) return;
-        cover<R>(a.g, J, a.S, t);
+        double lost[4];
+        cover<R>(a.g, J, a.S, t, lost);
     });
-    { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+    { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
     for (int round = 0; round < 2; round++) {
         each_box(p, [&](const StepArgs& a, int t) {
             const SweepJob& J = a.sw[s];
             if (box_empty_dev(J.B)) return;
-            fix<R>(a.g, J, a.S, round, a.ncol, a.status, t);
+            double lost[4];
+            fix<R>(a.g, J, a.S, round, a.ncol, a.status, t, lost);
         });
-        if (round == 0 || s == 1) { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; PHASE_MARK(s, bar); }
+        if (round == 0 || s == 1) { int nx_ = busy(box_ext(p)); grid_barrier(p, bar++, prv, nx_); prv = nx_; }
     }
     if (s == 1) each_box(p, [&](const StepArgs& a, int t) { box_speeds<R>(a, s, t); });
-    PHASE_MARK(s, MAX_BARRIERS);
     drain_tiles<R, RB, TR>(p, lds);  // the dense tiles not taken yet
     // the last block to finish resets the tile queue and, after the second sweep, gathers
     // the status words (with the barrier error flag) for one read-back
@@ -228,9 +219,6 @@ __global__ __launch_bounds__(256) void kb_sweep(PArgs p) {
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-#ifdef CC_PHASE_TRACE
-    if (tid == 0) g_phase_trace[s][MAX_BARRIERS + 1] = wall_clock64();
-#endif
     if (s == 1) {
         const int* od = ptab(p, L_DX);
         const int* oy = ptab(p, L_DY);

@@ -490,6 +490,25 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
     }
 }
 
+// ------------------------------------------------------------------ budget slots
+// Conservation budget of a sweep (Sec. 3.3: the change of the totals is what crossed the
+// domain boundary, plus the wall pressure terms, minus residuals that found no recipient).
+// Blocks that own such terms write partial sums to slots of their own (no atomics); the
+// member's collapse block adds the slots up in a fixed order at the end of the sweep.
+// Layout of a member's slot array (doubles):
+//   [0]                     number of dense boundary slots the sweep's dense launch wrote
+//                           (two per line of the sweep)
+//   [BS_DENSE + 4 k + m]    dense boundary slot k = 2 line + side: the flux of component m
+//                           through the line's low (side 0) or high (side 1) domain face
+//                           when the dense tiles update that cell, else 0
+//   [bs_patch + 12 b + ...] patch segment b: low face, high face (as above), wall terms
+//   [bs_cover + 4 b + m]    covering block b: residual without recipients
+constexpr int BS_DENSE = 8;
+struct BudgetSlots {
+    double* base;  // null: the budget is not tracked
+    int patch, cover;  // offsets of the patch and covering parts
+};
+
 // ------------------------------------------------------------------ patch (box update)
 struct CellData {
     double q[4];
@@ -692,10 +711,13 @@ struct PatchLds {
     bool has[PL_T];
 };
 
-// lb: the block's index within the member (uniform over the block; every thread calls it)
+// lb: the block's index within the member (uniform over the block; every thread calls it).
+// bs: budget slots (base null: not tracked): the block's slot gets the stabilised fluxes
+// through the domain's low and high faces of its line (when it updates the end cells) and
+// the sum of its cells' wall terms.
 template <int D, typename R>
 __device__ void patch_line(const Grid& g, const SweepJob& J, const Stage& S, unsigned int* ncollapse, int lb,
-                           PatchLds& sh) {
+                           PatchLds& sh, const BudgetSlots& bs) {
     const Level& Ls = J.Ls;
     const Level& Le = J.Le;
     const Box& B = J.B;
@@ -748,20 +770,34 @@ __device__ void patch_line(const Grid& g, const SweepJob& J, const Stage& S, uns
         for (int m = 0; m < 4; m++) sh.phi[m][x] = phi[m];
     }
     __syncthreads();
-    if (x < 2 || x >= PL_T - 2 || p >= first + len) return;
+    bool mine = !(x < 2 || x >= PL_T - 2 || p >= first + len);  // a cell this block updates
+    double W[4] = {0, 0, 0, 0};
+    if (mine && c.has && wr.wall) {
+        double db = btp - btf;
+        for (int m = 0; m < 4; m++) W[m] = db * wr.wv[m];
+    }
+    if (bs.base) {  // one wavefront: lane sums in a fixed order
+        double* slot = bs.base + bs.patch + 12 * lb;
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            double lo = wave_sum(mine && p == 0 ? sh.phi[m][x] : 0.0);
+            double hi = wave_sum(mine && p == n - 1 ? sh.phi[m][x + 1] : 0.0);
+            double wt = wave_sum(W[m]);
+            if (x == 0) {
+                slot[m] = lo;
+                slot[4 + m] = hi;
+                slot[8 + m] = wt;
+            }
+        }
+    }
+    if (!mine) return;
     int i = D == 0 ? p : line, j = D == 0 ? line : p;
     int b = bidx(B, i, j), cap = S.cap;
     size_t k = (size_t)j * g.nx + i;
     double as = Ls.alpha[k], ae = Le.alpha[k];
     double u2[4] = {0, 0, 0, 0};
-    if (c.has) {
-        double W[4] = {0, 0, 0, 0};
-        if (wr.wall) {
-            double db = btp - btf;
-            for (int m = 0; m < 4; m++) W[m] = db * wr.wv[m];
-        }
+    if (c.has)
         for (int m = 0; m < 4; m++) u2[m] = c.u1[m] + lam * ((sh.phi[m][x] - sh.phi[m][x + 1]) + W[m]);
-    }
     int gone = 0;
     if (as > 0.0 && ae == 0.0) {
         gone = 1;
@@ -783,11 +819,32 @@ __device__ __forceinline__ bool inadmissible_content(const double* u) {
     return !(r > 0.0) || !(u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) / r > 0.0);
 }
 
+// Number of recipients of emptied box cell (ci, cj) in a round whose flags are `fl`: its
+// face neighbours with end volume whose flag is 0 (not emptied, not bad), else such
+// neighbours among all eight (cells outside the box have flag 0).
+__device__ __forceinline__ int recipient_count(const Grid& g, const Level& Le, const Box& B, const int8_t* fl,
+                                               int ci, int cj) {
+    int nr = 0;
+    for (int pass = 0; pass < 2 && nr == 0; pass++) {
+        int cnt = pass == 0 ? 4 : 8;
+        for (int q = 0; q < cnt; q++) {
+            int ii = ci + c_d8[q][0], jj = cj + c_d8[q][1];
+            if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny) continue;
+            int8_t fk = B.has(ii, jj) ? fl[bidx(B, ii, jj)] : (int8_t)0;
+            if (Le.alpha[(size_t)jj * g.nx + ii] > 0.0 && fk == 0) nr++;
+        }
+    }
+    return nr;
+}
+
 // Covering (Eqs. massDeficitEquation, cutCellCoverDonation): each emptied cell's residual
 // goes to its face neighbours that stay fluid (else its eight neighbours) in proportion to
 // their end volume.  Gathered per recipient in increasing order of the emptied cell.
+// want_lost: lost[] gets the residual of this thread's cell when it is emptied and has no
+// recipient (it leaves the grid's totals); lost[] is left as it is otherwise.
 template <typename R>
-__device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t) {
+__device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t, double (&lost)[4],
+                      bool want_lost = false) {
     const Level& Le = J.Le;
     const Box& B = J.B;
     R* Uout = (R*)J.Uout;
@@ -803,6 +860,8 @@ __device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t) {
 #pragma unroll
     for (int m = 0; m < 4; m++) u2[m] = S.U2[m * cap + b];
     double aer = Le.alpha[k];
+    if (want_lost && gone_b && recipient_count(g, Le, B, S.gone, i, j) == 0)
+        for (int m = 0; m < 4; m++) lost[m] = u2[m];
     unsigned gn = 0u;  // bit q: neighbour q (row-major in the 3 x 3 block) was emptied
 #pragma unroll
     for (int q = 0; q < 9; q++) {
@@ -862,9 +921,10 @@ __device__ void cover(const Grid& g, const SweepJob& J, const Stage& S, int t) {
 // the bad cell.  Round 0 flags the cells still bad for round 1; round 1 reports any cell
 // still bad (status bit 2).  Both rounds return at once when the previous stage found no
 // bad cell.
+// want_lost: the content of a bad cell without recipients is added to lost[].
 template <typename R>
 __device__ void fix(const Grid& g, const SweepJob& J, const Stage& S, int round, unsigned int* ncollapse,
-                    unsigned int* status, int t) {
+                    unsigned int* status, int t, double (&lost)[4], bool want_lost = false) {
     const Level& Le = J.Le;
     const Box& B = J.B;
     R* Uout = (R*)J.Uout;
@@ -884,6 +944,8 @@ __device__ void fix(const Grid& g, const SweepJob& J, const Stage& S, int round,
     double acc[4] = {0, 0, 0, 0};
     if (f == 1) {
         atomicAdd(ncollapse, 1u);
+        if (want_lost && recipient_count(g, Le, B, fin, i, j) == 0)
+            for (int m = 0; m < 4; m++) lost[m] += Xin[m * cap + b];
     } else {
         for (int m = 0; m < 4; m++) acc[m] = Xin[m * cap + b];
         double aer = Le.alpha[k];
@@ -1054,10 +1116,11 @@ struct SpeedMax<float> {
 };
 
 // lds: dense_x_lds<T>() bytes; cfl: when not null, the maxima of the written cells' speeds
-// go to this block's partial pair cfl[2 lb .. 2 lb + 1].
+// go to this block's partial pair cfl[2 lb .. 2 lb + 1]; bud: when not null, the budget
+// slots (the fluxes through the domain's low and high x-faces of the block's rows).
 template <typename R, typename T, int RB>
 __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_, R* __restrict__ Uout_, Box B, T lam,
-                                        int lb, T* lds, unsigned long long* cfl) {
+                                        int lb, T* lds, unsigned long long* cfl, double* bud = nullptr) {
     const gmem<R>* __restrict__ U = to_global(U_);
     gmem<R>* __restrict__ Uout = to_global(Uout_);
     T(*sq)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds);
@@ -1075,6 +1138,10 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_,
     bool writer = tid >= 2 && tid < DX_T - 2 && i >= 0 && i < nx;
     bool colbox = i >= B.i0 && i < B.i1;
     T gam = (T)g.gamma;
+    // budget: the threads of columns 0 and nx - 1 record the fluxes through the domain's
+    // low and high faces of each row (zero for rows whose cell the box phases update)
+    bool bedge = bud && writer && (i == 0 || i == nx - 1);
+    if (bud && lb == 0 && tid == 0) bud[0] = (double)(2 * ny);
     T qn[4];
     {
         size_t kk = (size_t)j0 * nx + src;
@@ -1127,6 +1194,15 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_,
             for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
             if (cfl) sm.add(un, g.gamma);
         }
+        if (bedge) {
+            bool upd = !(colbox && j >= B.j0 && j < B.j1);
+            if (i == 0)
+#pragma unroll
+                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * j) + m] = upd ? (double)sf[m][tid] : 0.0;
+            if (i == nx - 1)
+#pragma unroll
+                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * j + 1) + m] = upd ? (double)sf[m][tid + 1] : 0.0;
+        }
     }
     if (cfl) sm.flush(cfl + 2 * lb);
     __syncthreads();  // the caller may reuse the LDS for its next tile
@@ -1151,7 +1227,7 @@ __host__ __device__ constexpr int dense_y_blocks(int nx, int ny) {
 
 template <typename R, typename T, int TR>
 __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U_, R* __restrict__ Uout_, Box B, T lam,
-                                        int lb, T* lds, unsigned long long* cfl) {
+                                        int lb, T* lds, unsigned long long* cfl, double* bud = nullptr) {
     const gmem<R>* __restrict__ U = to_global(U_);
     gmem<R>* __restrict__ Uout = to_global(Uout_);
     using Tile = DenseYTile<T, TR>;
@@ -1212,12 +1288,25 @@ __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U_,
     __syncthreads();
     SpeedMax<R> sm;
     bool colbox = i >= B.i0 && i < B.i1;
+    if (bud && lb == 0 && threadIdx.x == 0) bud[0] = (double)(2 * nx);
 #pragma unroll
     for (int it = 0; it < ITS; it++) {
         int r = 1 + w + 4 * it;
         if (r > TR + 1) break;
         if (r < 2) continue;
         int jj = jt + r - 2;
+        if (bud && i < nx && (jj == 0 || jj == ny - 1)) {
+            // budget: the fluxes through the domain's low and high faces of column i (zero
+            // when the box phases update that cell)
+            bool upd = !(colbox && jj >= B.j0 && jj < B.j1);
+            if (jj == 0)
+#pragma unroll
+                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * i) + m] = upd ? (double)sq[m][r][lane] : 0.0;
+            if (jj == ny - 1)
+#pragma unroll
+                for (int m = 0; m < 4; m++)
+                    bud[BS_DENSE + 4 * (2 * i + 1) + m] = upd ? (double)sq[m][r + 1][lane] : 0.0;
+        }
         if (i >= nx || jj >= ny || (colbox && jj >= B.j0 && jj < B.j1)) continue;
         size_t k = (size_t)jj * nx + i;
         R un[4];
@@ -1247,7 +1336,7 @@ __host__ __device__ constexpr int dense_yc_blocks(int nx, int ny) {
 
 template <typename R, typename T, int RW>
 __device__ __forceinline__ void dense_yc(const Grid& g, const R* __restrict__ U_, R* __restrict__ Uout_, Box B,
-                                         T lam, int lb, unsigned long long* cfl) {
+                                         T lam, int lb, unsigned long long* cfl, double* bud = nullptr) {
     const gmem<R>* __restrict__ U = to_global(U_);
     gmem<R>* __restrict__ Uout = to_global(Uout_);
     int nx = g.nx, ny = g.ny;
@@ -1276,12 +1365,23 @@ __device__ __forceinline__ void dense_yc(const Grid& g, const R* __restrict__ U_
     for (int m = 0; m < 4; m++) erp[m] = er[m];
     SpeedMax<R> sm;
     bool colbox = i >= B.i0 && i < B.i1;
+    if (bud && lb == 0 && threadIdx.x == 0) bud[0] = (double)(2 * nx);
 #pragma unroll
     for (int r = 0; r < RW; r++) {
         int j = j0 + r;
         if (j >= ny) break;  // uniform over the block
         muscl<T, 1>(q[r + 2], q[r + 3], q[r + 4], true, lam, gam, el, er);  // row j + 1
         hllc<T, 1>(erp, el, gam, fhi);                                       // face above row j
+        if (bud && i < nx && (j == 0 || j == ny - 1)) {
+            // budget, as in the tiled sweep
+            bool upd = !(colbox && j >= B.j0 && j < B.j1);
+            if (j == 0)
+#pragma unroll
+                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * i) + m] = upd ? (double)flo[m] : 0.0;
+            if (j == ny - 1)
+#pragma unroll
+                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * i + 1) + m] = upd ? (double)fhi[m] : 0.0;
+        }
         if (i < nx && !(colbox && j >= B.j0 && j < B.j1)) {
             size_t k = (size_t)j * nx + i;
             R un[4];
