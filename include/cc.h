@@ -114,9 +114,12 @@ cc_status cc_get_state(cc_ctx* ctx, double* d_out, int32_t what);
 cc_status cc_geometry(cc_ctx* ctx, double t, int32_t level);
 /* Copy a level out (device pointers, any may be NULL): vertex classes (int8,
  * (ny+1)*(nx+1), 1 = solid), volume fractions (nx*ny), x-face apertures (ny*(nx+1)),
- * y-face apertures ((ny+1)*nx). */
+ * y-face apertures ((ny+1)*nx), and the cut-cell list (Sec. 2.1: cells the wall cuts, here
+ * the cells whose four faces are neither all open nor all closed): d_cut (int32, room for
+ * nx*ny entries) receives their linear indices j*nx + i in increasing order and d_ncut (one
+ * int32) their number; give both or neither (CC_ERR_ARG).  Asynchronous. */
 cc_status cc_geometry_dump(cc_ctx* ctx, int32_t level, int8_t* d_vcls, double* d_alpha, double* d_bx,
-                           double* d_by);
+                           double* d_by, int32_t* d_cut, int32_t* d_ncut);
 
 /* Split step in parts: cc_begin_step poses the body at t + dt and builds the stage level
  * (the first sweep's direction moves the polygon, the other coordinate stays) and level
@@ -128,9 +131,13 @@ cc_status cc_end_step(cc_ctx* ctx);
 /* One full split step of size dt. */
 cc_status cc_step(cc_ctx* ctx, double dt);
 
-/* Global time step dt = cfl * min(hx / Sx, hy / Sy), S the largest signal speed |u|+a
- * over live cells and |u_wall| over the body's vertices.  Synchronises; h_dt: host. */
-cc_status cc_cfl_dt(cc_ctx* ctx, double cfl, double* h_dt);
+/* Global time step (Sec. 4: from the regular cell size) dt = cfl * min(hx / Sx, hy / Sy),
+ * S the largest signal speed |u|+a over live cells and |u_wall| over the body's vertices.
+ * h_dt (host, nullable): written after synchronising; errors of the state are returned.
+ * d_dt (device, nullable): written asynchronously on the context's stream, the same value
+ * bit for bit, or 0 when the state is not finite or the status word reports an error (the
+ * error surfaces at the next synchronising call).  At least one of them (CC_ERR_ARG). */
+cc_status cc_cfl_dt(cc_ctx* ctx, double cfl, double* h_dt, double* d_dt);
 
 /* nsteps CFL steps planned on the device (Sec. 4 time step, Sec. 2.3.4 poses): each step
  * takes dt = cfl * min(hx / Sx, hy / Sy) from the state it starts from, exactly as
@@ -205,11 +212,14 @@ cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
 /* Tile tuner for the dense sweeps (the regular cells): times every tile shape of both
  * sweeps on this grid, reps launches each (as a step launches them: beside the first box
  * phase), from the current state into the spare state buffer, and keeps the fastest for
- * this context (the current variant unless another is at least 3 % faster).  h_choice (nullable, host, 2 entries)
- * receives the chosen variant indices.  Needs a state and no open step (CC_ERR_ARG).
+ * this context (the current variant unless another is at least 3 % faster).  h_choice
+ * (nullable, host, 2 entries) receives the chosen variant indices.  cache_path (nullable):
+ * a text file of earlier choices, one line "key tile_x tile_y" per configuration (the key
+ * names the device, the precision and the grid); a configuration found there is applied
+ * without timing, a new choice is appended.  Needs a state and no open step (CC_ERR_ARG).
  * Synchronizes; results do not depend on the choice (every shape computes the same
  * values, bit for bit). */
-cc_status cc_autotune(cc_ctx* ctx, int32_t reps, int32_t* h_choice);
+cc_status cc_autotune(cc_ctx* ctx, int32_t reps, int32_t* h_choice, const char* cache_path);
 /* Set the dense-sweep tile variants directly: tile_x indexes rows per x-sweep block
  * {1, 2, 4, 8}; tile_y 0-3 rows per 64-column y-sweep tile staged in LDS {8, 12, 16, 24}
  * (16 and 24 only with FP32 state: the tile lives in 64 KiB of LDS), 4-5 column walks of
@@ -263,6 +273,10 @@ cc_status cc_batch_remove(cc_batch* b, cc_ctx* ctx);
 int32_t cc_batch_size(const cc_batch* b);
 /* Dense-sweep tile variants used by every member (as cc_set_tiles). */
 cc_status cc_batch_set_tiles(cc_batch* b, int32_t tile_x, int32_t tile_y);
+/* Tile tuner for the batch's dense launches (as cc_autotune, with every member's grid in
+ * the launches and in the cache key, in membership order).  Needs members (CC_ERR_ARG).
+ * Synchronizes. */
+cc_status cc_batch_autotune(cc_batch* b, int32_t reps, int32_t* h_choice, const char* cache_path);
 /* Launch mode of the batch's steps (as cc_set_launch_mode). */
 cc_status cc_batch_set_launch_mode(cc_batch* b, int32_t mode);
 /* One split step of every member, member k with time step h_dt[k] (host, in membership

@@ -677,6 +677,19 @@ int ccref_geometry_dump(const ccref_ctx* c, int which, int8_t* vcls, double* alp
     return 0;
 }
 
+/* Cut cells of a level (neither all four faces open nor all four closed), as linear
+ * indices j*nx + i in increasing order; *n receives their number.  out: nx*ny entries. */
+int ccref_cut_list(const ccref_ctx* c, int which, int32_t* out, int32_t* n) {
+    int s = slot_of(c, which);
+    if (s < 0) return 1;
+    int k = 0;
+    for (int j = 0; j < c->cfg.ny; j++)
+        for (int i = 0; i < c->cfg.nx; i++)
+            if (cell_is_cut(c, &c->L[s], i, j)) out[k++] = (int32_t)CIDX(c, i, j);
+    *n = k;
+    return 0;
+}
+
 /* Solid intervals of the faces of a level (2 doubles per face). */
 int ccref_face_intervals(const ccref_ctx* c, int which, double* fx, double* fy) {
     size_t nx = c->cfg.nx, ny = c->cfg.ny;

@@ -87,6 +87,7 @@ def lib(parallel=False):
         L.ccref_trace.argtypes = [vp, i, i]
         L.ccref_trace_get.argtypes = [vp, p]
         L.ccref_set_option.argtypes = [vp, i, i]
+        L.ccref_cut_list.argtypes = [vp, i, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     return L
 
 
@@ -253,6 +254,13 @@ class Oracle:
         self._L.ccref_geometry_dump(self._h, which, vc.ctypes.data_as(C.POINTER(C.c_int8)),
                                   _dp(al), _dp(bx), _dp(by))
         return {"vcls": vc, "alpha": al, "bx": bx, "by": by}
+
+    def cut_list(self, which=0):
+        """Linear indices (j nx + i, increasing) of the level's cut cells."""
+        out = np.zeros(self.nx * self.ny, dtype=np.int32)
+        n = C.c_int32()
+        self._L.ccref_cut_list(self._h, which, out.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n))
+        return out[: n.value].copy()
 
     def wall_point(self, i, j, which=0):
         out = np.zeros(2)

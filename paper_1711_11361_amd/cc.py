@@ -54,19 +54,19 @@ _sig = {
     "cc_set_u": (C.c_int, [_vp, _vp]),
     "cc_get_state": (C.c_int, [_vp, _vp, _i32]),
     "cc_geometry": (C.c_int, [_vp, _d, _i32]),
-    "cc_geometry_dump": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "cc_geometry_dump": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cc_begin_step": (C.c_int, [_vp, _d]),
     "cc_sweep": (C.c_int, [_vp, _i32, _d]),
     "cc_end_step": (C.c_int, [_vp]),
     "cc_step": (C.c_int, [_vp, _d]),
-    "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
+    "cc_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d), _vp]),
     "cc_advance": (C.c_int, [_vp, _i32, _d, C.POINTER(_d), C.POINTER(C.c_float), C.POINTER(_i32)]),
     "cc_totals": (C.c_int, [_vp, C.POINTER(_d), C.POINTER(_d)]),
     "cc_set_budget": (C.c_int, [_vp, _i32]),
     "cc_totals_state": (C.c_int, [_vp, _i32, _i32, _i32, _d, _d, _vp, _vp]),
     "cc_surface_loads": (C.c_int, [_vp, C.POINTER(_d)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
-    "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32)]),
+    "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32), C.c_char_p]),
     "cc_set_tiles": (C.c_int, [_vp, _i32, _i32]),
     "cc_set_launch_mode": (C.c_int, [_vp, _i32]),
     "cc_timing": (C.c_int, [_vp, _i32]),
@@ -79,6 +79,7 @@ _sig = {
     "cc_batch_remove": (C.c_int, [_vp, _vp]),
     "cc_batch_size": (_i32, [_vp]),
     "cc_batch_set_tiles": (C.c_int, [_vp, _i32, _i32]),
+    "cc_batch_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32), C.c_char_p]),
     "cc_batch_set_launch_mode": (C.c_int, [_vp, _i32]),
     "cc_batch_step": (C.c_int, [_vp, C.POINTER(_d), C.POINTER(_i32)]),
     "cc_batch_last_dt": (C.c_int, [_vp, _d, C.POINTER(_d), C.POINTER(_i32)]),
@@ -163,8 +164,9 @@ def cc_geometry(ctx, t, level):
     _check(ctx, _lib.cc_geometry(ctx, t, level))
 
 
-def cc_geometry_dump(ctx, level, d_vcls, d_alpha, d_bx, d_by):
-    _check(ctx, _lib.cc_geometry_dump(ctx, level, _vp(d_vcls), _vp(d_alpha), _vp(d_bx), _vp(d_by)))
+def cc_geometry_dump(ctx, level, d_vcls, d_alpha, d_bx, d_by, d_cut=None, d_ncut=None):
+    _check(ctx, _lib.cc_geometry_dump(ctx, level, _vp(d_vcls), _vp(d_alpha), _vp(d_bx), _vp(d_by), _vp(d_cut),
+                                      _vp(d_ncut)))
 
 
 def cc_begin_step(ctx, dt):
@@ -183,9 +185,13 @@ def cc_step(ctx, dt):
     _check(ctx, _lib.cc_step(ctx, dt))
 
 
-def cc_cfl_dt(ctx, cfl):
+def cc_cfl_dt(ctx, cfl, d_dt=None):
+    """Host time step; with d_dt (a device pointer) only the asynchronous device output."""
+    if d_dt is not None:
+        _check(ctx, _lib.cc_cfl_dt(ctx, cfl, None, _vp(d_dt)))
+        return None
     out = _d()
-    _check(ctx, _lib.cc_cfl_dt(ctx, cfl, C.byref(out)))
+    _check(ctx, _lib.cc_cfl_dt(ctx, cfl, C.byref(out), None))
     return out.value
 
 
@@ -246,9 +252,15 @@ def cc_set_tiles(ctx, tile_x, tile_y):
     _check(ctx, _lib.cc_set_tiles(ctx, int(tile_x), int(tile_y)))
 
 
-def cc_autotune(ctx, reps=20):
+def cc_autotune(ctx, reps=20, cache_path=None):
     out = (_i32 * 2)()
-    _check(ctx, _lib.cc_autotune(ctx, int(reps), out))
+    _check(ctx, _lib.cc_autotune(ctx, int(reps), out, cache_path.encode() if cache_path else None))
+    return out[0], out[1]
+
+
+def cc_batch_autotune(b, reps=20, cache_path=None):
+    out = (_i32 * 2)()
+    _bcheck(b, _lib.cc_batch_autotune(b, int(reps), out, cache_path.encode() if cache_path else None))
     return out[0], out[1]
 
 
@@ -437,9 +449,13 @@ class Solver:
             al = t.empty((ny, nx), dtype=t.float64, device=self.device)
             bx = t.empty((ny, nx + 1), dtype=t.float64, device=self.device)
             by = t.empty((ny + 1, nx), dtype=t.float64, device=self.device)
-            cc_geometry_dump(self.ctx, level, vc.data_ptr(), al.data_ptr(), bx.data_ptr(), by.data_ptr())
+            cut = t.empty(nx * ny, dtype=t.int32, device=self.device)
+            ncut = t.empty(1, dtype=t.int32, device=self.device)
+            cc_geometry_dump(self.ctx, level, vc.data_ptr(), al.data_ptr(), bx.data_ptr(), by.data_ptr(),
+                             cut.data_ptr(), ncut.data_ptr())
+            n = int(ncut.cpu().item())
             return {"vcls": vc.cpu().numpy(), "alpha": al.cpu().numpy(), "bx": bx.cpu().numpy(),
-                    "by": by.cpu().numpy()}
+                    "by": by.cpu().numpy(), "cut": cut[:n].cpu().numpy()}
 
     def begin_step(self, dt):
         cc_begin_step(self.ctx, dt)
@@ -485,9 +501,14 @@ class Solver:
     def set_launch_mode(self, mode):
         cc_set_launch_mode(self.ctx, mode)
 
-    def autotune(self, reps=20):
-        """Pick the fastest dense-sweep tile shapes for this grid (needs a state)."""
-        return cc_autotune(self.ctx, reps)
+    def autotune(self, reps=20, cache_path=None):
+        """Pick the fastest dense-sweep tile shapes for this grid (needs a state); with a
+        cache file, a configuration tuned before is taken from it."""
+        return cc_autotune(self.ctx, reps, cache_path)
+
+    def cfl_dt_device(self, cfl, out):
+        """The time step into a one-element FP64 device tensor, asynchronously."""
+        cc_cfl_dt(self.ctx, cfl, out.data_ptr())
 
     @property
     def parity(self):
@@ -556,6 +577,9 @@ class Batch:
 
     def set_tiles(self, tile_x, tile_y):
         cc_batch_set_tiles(self.b, tile_x, tile_y)
+
+    def autotune(self, reps=20, cache_path=None):
+        return cc_batch_autotune(self.b, reps, cache_path)
 
     def set_launch_mode(self, mode):
         cc_batch_set_launch_mode(self.b, mode)

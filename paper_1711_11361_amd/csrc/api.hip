@@ -20,6 +20,7 @@
 #include "geometry.h"
 #include "reduce.h"
 #include "sweep.h"
+#include "lists.h"
 
 using namespace cc;
 
@@ -1186,10 +1187,26 @@ cc_status cc_geometry(cc_ctx* c, double t, int32_t level) {
     return geometry_at(c, t, slot);
 }
 
-cc_status cc_geometry_dump(cc_ctx* c, int32_t level, int8_t* d_vcls, double* d_alpha, double* d_bx, double* d_by) {
+cc_status cc_geometry_dump(cc_ctx* c, int32_t level, int8_t* d_vcls, double* d_alpha, double* d_bx, double* d_by,
+                           int32_t* d_cut, int32_t* d_ncut) {
     if (!c || level < 0 || level > 2) return fail(c, CC_ERR_ARG, "bad level");
+    if ((d_cut == nullptr) != (d_ncut == nullptr)) return fail(c, CC_ERR_ARG, "cut list needs both outputs");
     int slot = level == 0 ? c->s0 : level == 1 ? c->sm : c->s1;
     const Level& L = c->lev[slot];
+    if (d_cut) {
+        const Box& R = c->lbox[slot];
+        int cells = box_empty(R) ? 0 : R.w() * R.h();
+        if (cells == 0) {
+            HIPCHK(c, hipMemsetAsync(d_ncut, 0, sizeof(int32_t), c->stream));
+        } else {
+            int chunk = (cells + CUT_BLOCKS - 1) / CUT_BLOCKS, nb = (cells + chunk - 1) / chunk;
+            int* counts = at<int>(c, c->lay.off_part);  // 4 KiB of the reduction scratch
+            hipLaunchKernelGGL(k_cut_count, dim3(nb), dim3(CUT_T), 0, c->stream, c->g, L, R, chunk, counts);
+            hipLaunchKernelGGL(k_cut_scan, dim3(1), dim3(CUT_T), 0, c->stream, nb, counts, (int*)d_ncut);
+            hipLaunchKernelGGL(k_cut_write, dim3(nb), dim3(CUT_T), 0, c->stream, c->g, L, R, chunk,
+                               (const int*)counts, (int*)d_cut);
+        }
+    }
     if (d_vcls) HIPCHK(c, hipMemcpyAsync(d_vcls, L.vcls, c->lay.nvx, hipMemcpyDeviceToDevice, c->stream));
     if (d_alpha) HIPCHK(c, hipMemcpyAsync(d_alpha, L.alpha, c->lay.nc * 8, hipMemcpyDeviceToDevice, c->stream));
     if (d_bx)
@@ -1428,21 +1445,30 @@ cc_status cc_step(cc_ctx* c, double dt) {
 
 namespace {
 
+// Largest speeds |u_x|, |u_y| of the body's vertices at the context's time (0 without a
+// body): the wall's part of the CFL condition.
+void wall_speeds(cc_ctx* c, double& wsx, double& wsy) {
+    wsx = wsy = 0.0;
+    if (c->m == 0) return;
+    std::vector<double> pv(2 * c->m);
+    Pose q = pose_at(c, c->t);
+    pose_xy(c, q, q, pv.data());
+    double thd = c->amp * c->omega * std::cos(c->omega * c->t);
+    double cx = c->ref_x + c->vx * c->t, cy = c->ref_y + c->vy * c->t;
+    for (int k = 0; k < c->m; k++) {
+        double ux = c->vx - thd * (pv[2 * k + 1] - cy);
+        double uy = c->vy + thd * (pv[2 * k] - cx);
+        wsx = std::fmax(wsx, std::fabs(ux));
+        wsy = std::fmax(wsy, std::fabs(uy));
+    }
+}
+
 // Wave speeds (bit patterns from the reduction) plus the body's vertex speeds -> dt.
 double dt_from_speeds(cc_ctx* c, double cfl, double sx, double sy) {
-    if (c->m > 0) {
-        std::vector<double> pv(2 * c->m);
-        Pose q = pose_at(c, c->t);
-        pose_xy(c, q, q, pv.data());
-        double thd = c->amp * c->omega * std::cos(c->omega * c->t);
-        double cx = c->ref_x + c->vx * c->t, cy = c->ref_y + c->vy * c->t;
-        for (int k = 0; k < c->m; k++) {
-            double ux = c->vx - thd * (pv[2 * k + 1] - cy);
-            double uy = c->vy + thd * (pv[2 * k] - cx);
-            sx = std::fmax(sx, std::fabs(ux));
-            sy = std::fmax(sy, std::fabs(uy));
-        }
-    }
+    double wsx, wsy;
+    wall_speeds(c, wsx, wsy);
+    sx = std::fmax(sx, wsx);
+    sy = std::fmax(sy, wsy);
     return cfl * std::fmin(c->hx / sx, c->hy / sy);
 }
 
@@ -1458,9 +1484,30 @@ cc_status status_error(cc_ctx* c, unsigned int status, double sx, double sy) {
 
 extern "C" {
 
-cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt) {
-    if (!c || !h_dt || !(cfl > 0.0)) return fail(c, CC_ERR_ARG, "bad argument");
+cc_status cc_cfl_dt(cc_ctx* c, double cfl, double* h_dt, double* d_dt) {
+    if (!c || (!h_dt && !d_dt) || !(cfl > 0.0)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_cfl_dt inside a step");
+    if (d_dt) {  // asynchronous: the reduction and the time step on the device
+        unsigned long long* smax = at<unsigned long long>(c, c->lay.off_smax);
+        unsigned long long* part = at<unsigned long long>(c, c->lay.off_part);
+        const double* al = c->lev[c->s0].alpha;
+        int blocks = (int)std::min<size_t>(CFL_MAX_BLOCKS, nblk(c->lay.nc));
+        if (fp32(c))
+            hipLaunchKernelGGL(k_cfl<float>, dim3(blocks), dim3(256), 0, c->stream, c->g, al,
+                               at<float>(c, c->lay.off_u[c->cur]), part);
+        else
+            hipLaunchKernelGGL(k_cfl<double>, dim3(blocks), dim3(256), 0, c->stream, c->g, al,
+                               at<double>(c, c->lay.off_u[c->cur]), part);
+        hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(256), 0, c->stream, blocks, (const unsigned long long*)part,
+                           smax);
+        double wsx, wsy;
+        wall_speeds(c, wsx, wsy);
+        hipLaunchKernelGGL(k_cfl_dt, dim3(1), dim3(64), 0, c->stream, (const unsigned long long*)smax,
+                           (const unsigned int*)at<unsigned int>(c, c->lay.off_status), wsx, wsy, c->hx, c->hy, cfl,
+                           d_dt);
+        HIPCHK(c, hipGetLastError());
+        if (!h_dt) return CC_OK;
+    }
     if (c->speeds_ready && !c->batch) {  // reduced and read back by the last captured step
         HIPCHK(c, wait_event(c->eng.ev[c->speeds_buf]));
         double sx, sy;
@@ -1895,13 +1942,9 @@ cc_status cc_info(cc_ctx* c, double* h_out, int32_t n) {
 
 namespace {
 
-// Times every valid tile variant of both dense sweeps on this grid (reps launches each,
-// from the current state into the spare state buffer, which the next sweep overwrites)
-// and keeps the fastest (the current variant unless another is at least 3 % faster).
-template <typename R>
-cc_status tune_dense(cc_ctx* c, int reps) {
-    Engine& E = c->eng;
-    StepArgs a;
+// Tuning arguments of a context: both sweeps over the whole grid (no box), from the current
+// state into the spare state buffer, which the next sweep overwrites.
+void tune_args(cc_ctx* c, StepArgs& a) {
     base_args(c, a);
     for (int s = 0; s < 2; s++) {
         SweepJob& J = a.sw[s];
@@ -1911,40 +1954,48 @@ cc_status tune_dense(cc_ctx* c, int reps) {
         J.Uin = c->ws + c->lay.off_u[c->cur];
         J.Uout = c->ws + c->lay.off_u[1 - c->cur];
     }
-    // the launch plan is rebuilt below, which destroys the captured step graphs: let every
-    // launch of them finish first
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    cc_status st = own_upload(c, a);
-    if (st != CC_OK) return st;
+}
+
+// Times every valid tile variant of both dense sweeps for the members of engine E (their
+// tuning arguments already in device memory), reps launches each, as a step launches them
+// (beside the first box phase, whose idle blocks set the launch's occupancy), and keeps
+// the fastest: the current variant unless another is at least 3 % faster, so that timing
+// noise between near-equal shapes does not flip the choice.  The launch plan is rebuilt
+// for every variant, which destroys the captured step graphs: the caller has drained the
+// stream.  err: set on failure.
+template <typename R>
+bool tune_engine(Engine& E, hipStream_t s, int reps, std::string& err) {
     hipEvent_t ea, eb;
-    HIPCHK(c, hipEventCreate(&ea));
-    HIPCHK(c, hipEventCreate(&eb));
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+        err = "event create";
+        return false;
+    }
+    bool ok = true;
     int keep[2] = {E.tile_x, E.tile_y};
-    for (int dir = 0; dir < 2 && st == CC_OK; dir++) {
+    for (int dir = 0; dir < 2 && ok; dir++) {
         int nv = dir == 0 ? NX_VARIANTS : NY_VARIANTS, best = -1;
         float best_ms = 0.0f;
-        // the current variant is timed first and is only replaced by one at least 3 % faster,
-        // so that timing noise between near-equal shapes does not flip the choice
         for (int i = -1; i < nv; i++) {
             int v = i < 0 ? keep[dir] : i;
             if ((i >= 0 && v == keep[dir]) || !dense_variant_ok(E.prec, dir, v)) continue;
             (dir == 0 ? E.tile_x : E.tile_y) = v;
-            if (engine_plan(E, c->stream) != hipSuccess) {
-                st = fail(c, CC_ERR_DEVICE, "tile plan");
+            if (engine_plan(E, s) != hipSuccess) {
+                err = "tile plan";
+                ok = false;
                 break;
             }
-            // timed as the step launches them: with the (here idle) box blocks of the first
-            // box phase ahead of the tiles, whose registers set the launch's occupancy
-            launch_dense<R>(E, c->stream, dir, 1 << dir, nullptr, nullptr, 0, true);  // warm-up
+            launch_dense<R>(E, s, dir, 1 << dir, nullptr, nullptr, 0, true);  // warm-up
             float ms = 0.0f;
-            if (hipEventRecord(ea, c->stream) != hipSuccess) {
-                st = fail(c, CC_ERR_DEVICE, "event record");
+            if (hipEventRecord(ea, s) != hipSuccess) {
+                err = "event record";
+                ok = false;
                 break;
             }
-            for (int r = 0; r < reps; r++) launch_dense<R>(E, c->stream, dir, 1 << dir, nullptr, nullptr, 0, true);
-            if (hipEventRecord(eb, c->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+            for (int r = 0; r < reps; r++) launch_dense<R>(E, s, dir, 1 << dir, nullptr, nullptr, 0, true);
+            if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
                 hipEventElapsedTime(&ms, ea, eb) != hipSuccess || hipGetLastError() != hipSuccess) {
-                st = fail(c, CC_ERR_DEVICE, "tile timing failed");
+                err = "tile timing failed";
+                ok = false;
                 break;
             }
             if (best < 0 || ms < 0.97f * best_ms) {
@@ -1957,24 +2008,112 @@ cc_status tune_dense(cc_ctx* c, int reps) {
     }
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
-    if (engine_plan(E, c->stream) != hipSuccess) return fail(c, CC_ERR_DEVICE, "tile plan");
-    return st;
+    if (engine_plan(E, s) != hipSuccess && ok) {
+        err = "tile plan";
+        ok = false;
+    }
+    return ok;
+}
+
+// Tile-choice cache: one line per tuned configuration, "key tile_x tile_y", the key naming
+// the device, the precision and the members' grids (a batch's in membership order).
+std::string tune_key(int prec, const std::vector<cc_ctx*>& mem) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (auto& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    std::string k = arch + "/p" + std::to_string(prec);
+    for (const cc_ctx* c : mem) k += "/" + std::to_string(c->g.nx) + "x" + std::to_string(c->g.ny);
+    return k;
+}
+
+bool tune_cache_read(const char* path, const std::string& key, int prec, int& tx, int& ty) {
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char kbuf[4096];
+    int a = 0, b = 0;
+    bool found = false;
+    while (std::fscanf(f, "%4095s %d %d", kbuf, &a, &b) == 3)
+        if (key == kbuf && dense_variant_ok(prec, 0, a) && dense_variant_ok(prec, 1, b)) {
+            tx = a;
+            ty = b;
+            found = true;  // the last entry for the key wins
+        }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_write(const char* path, const std::string& key, int tx, int ty) {
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d\n", key.c_str(), tx, ty);
+    std::fclose(f);
 }
 
 }  // namespace
 
 extern "C" {
 
-cc_status cc_autotune(cc_ctx* c, int32_t reps, int32_t* h_choice) {
+cc_status cc_autotune(cc_ctx* c, int32_t reps, int32_t* h_choice, const char* cache_path) {
     if (!c || reps < 1) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step || !c->have_state) return fail(c, CC_ERR_ARG, "cc_autotune needs a state and no open step");
     cc_status st = not_in_batch(c);
     if (st != CC_OK) return st;
-    st = fp32(c) ? tune_dense<float>(c, reps) : tune_dense<double>(c, reps);
-    if (st != CC_OK) return st;
+    Engine& E = c->eng;
+    std::string key = tune_key(E.prec, E.mem);
+    int tx = 0, ty = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the captured graphs are about to be destroyed
+    if (tune_cache_read(cache_path, key, E.prec, tx, ty)) {
+        E.tile_x = tx;
+        E.tile_y = ty;
+        HIPCHK(c, engine_plan(E, c->stream));
+    } else {
+        StepArgs a;
+        tune_args(c, a);
+        if ((st = own_upload(c, a)) != CC_OK) return st;
+        std::string err;
+        bool ok = fp32(c) ? tune_engine<float>(E, c->stream, reps, err) : tune_engine<double>(E, c->stream, reps, err);
+        if (!ok) return fail(c, CC_ERR_DEVICE, err);
+        tune_cache_write(cache_path, key, E.tile_x, E.tile_y);
+    }
     if (h_choice) {
-        h_choice[0] = c->eng.tile_x;
-        h_choice[1] = c->eng.tile_y;
+        h_choice[0] = E.tile_x;
+        h_choice[1] = E.tile_y;
+    }
+    return CC_OK;
+}
+
+cc_status cc_batch_autotune(cc_batch* b, int32_t reps, int32_t* h_choice, const char* cache_path) {
+    if (!b || reps < 1) return CC_ERR_ARG;
+    Engine& E = b->eng;
+    int n = (int)E.mem.size();
+    if (n == 0) return bfail(b, CC_ERR_ARG, "cc_batch_autotune needs members");
+    std::string key = tune_key(E.prec, E.mem);
+    int tx = 0, ty = 0;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));  // the captured graphs are about to be destroyed
+    if (tune_cache_read(cache_path, key, E.prec, tx, ty)) {
+        E.tile_x = tx;
+        E.tile_y = ty;
+        BHIPCHK(b, engine_plan(E, b->stream));
+    } else {
+        int buf = E.buf;
+        BHIPCHK(b, engine_hostbuf(E, buf));
+        for (int k = 0; k < n; k++) tune_args(E.mem[k], E.h_args[buf][k]);
+        BHIPCHK(b, engine_upload(E, b->stream, buf));
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        std::string err;
+        bool ok = E.prec == CC_FP32_GEOM64 ? tune_engine<float>(E, b->stream, reps, err)
+                                           : tune_engine<double>(E, b->stream, reps, err);
+        if (!ok) return bfail(b, CC_ERR_DEVICE, err);
+        tune_cache_write(cache_path, key, E.tile_x, E.tile_y);
+    }
+    if (h_choice) {
+        h_choice[0] = E.tile_x;
+        h_choice[1] = E.tile_y;
     }
     return CC_OK;
 }
@@ -2184,7 +2323,7 @@ cc_status cc_batch_cfl_dt(cc_batch* b, double cfl, double* h_dt) {
     if (!b || !h_dt || !(cfl > 0.0)) return CC_ERR_ARG;
     Engine& E = b->eng;
     for (size_t k = 0; k < E.mem.size(); k++) {
-        cc_status st = cc_cfl_dt(E.mem[k], cfl, &h_dt[k]);
+        cc_status st = cc_cfl_dt(E.mem[k], cfl, &h_dt[k], nullptr);
         if (st != CC_OK) {
             b->err = "member " + std::to_string(k) + ": " + E.mem[k]->err;
             return st;
