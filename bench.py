@@ -1,17 +1,27 @@
 """Benchmark of the split step on one MI355X.
 
-Workload: circular cylinder (radius 0.1, 1024-gon) crossing a stationary Mach-2 shock on
-[0,2]x[0,1] with 1024 x 512 cells, moving at +1.0 along x, CFL 0.8.  One step = the CFL
-time step of its start state + the full split step (stage and end geometry, two sweeps
-with every cut-cell operation).  The timed steps are planned on the device (cc_advance:
-dt, poses and boxes computed at the head of each captured step, no host round trip
-between steps); the host-planned rate (dt read back before each step) is reported beside
-it.  Timed after W warm-up steps, K steps bracketed by device synchronisation; value =
-cells x steps / time.
+Headline workload: circular cylinder (radius 0.1, 1024-gon) crossing a stationary Mach-2
+shock on [0,2]x[0,1] with 1024 x 512 cells, moving at +1.0 along x, CFL 0.8.  One step =
+the CFL time step of its start state + the full split step (stage and end geometry, two
+sweeps with every cut-cell operation).  The timed steps are planned on the device
+(cc_advance: dt, poses and boxes computed at the head of each captured step, no host round
+trip between steps).  Timed after W warm-up steps, K steps bracketed by device
+synchronisation; value = cells x steps / time, FP32 state with FP64 geometry (the FP64 mode
+beside it).
 
-Reported: cell-updates/s of the FP32-state / FP64-geometry mode (headline) and of the FP64
-mode, p50/p99 step latency, the roofline of the dominant kernel (the dense sweep) from HIP
-events on the library's stream, and the FP64 CPU oracle timed on a bounded sample.
+Also reported, each measured in this run:
+* the roofline of the dominant kernel: the merged first-box-phase + dense-sweep launch the
+  captured step runs, its duration from HIP events around that very launch (the step's
+  launches issued one by one, same kernels, grids and arguments), and the whole step's
+  fraction of the HBM roofline;
+* accuracy of the FP32 state on the same workload: relative L1 of density against the FP64
+  path with identical time steps, and the mass drift of both (from the conservation budget);
+* the other configurations: the inclined piston (200 x 20, FP64), 16 triangle seeds at
+  2048 x 1024 stepped as one batch (FP32), the pitching NACA 0012 at 4096 x 4096 (FP32 and
+  FP64, tuned tiles), each with its rate and roofline;
+* copies of the headline workload stepped as one batch against per-instance FP64 launches;
+* the FP64 CPU oracle on a bounded sample of the headline workload, one thread and all
+  host cores.
 """
 import argparse
 import hashlib
@@ -26,22 +36,63 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def run_mode(precision, steps, warmup, w):
+def rate(cells, steps, seconds):
+    return cells * steps / seconds
+
+
+def timed_kernels(step_fn, nsteps, enable, read):
+    """Average duration (us) of the dense launches of each direction over nsteps steps
+    issued one by one with events around every dense launch."""
+    enable(1)
+    read()
+    for _ in range(nsteps):
+        step_fn()
+    t = read()
+    enable(0)
+    return {k: (1e3 * t[k][0] / t[k][1] if t[k][1] > 0 else None) for k in ("dense_x", "dense_y")}
+
+
+def roofline(kern_us, cells, bytes_per_value, table, names):
+    """Roofline of the slower dense launch: algorithmic bytes (read and write of the
+    4-component state of every cell, per sweep) over its average duration."""
+    kern = max((k for k in kern_us if kern_us[k]), key=lambda k: kern_us[k])
+    us = kern_us[kern]
+    alg = cells * 4 * 2 * bytes_per_value
+    ach = alg / (us * 1e-6) / 1e9
+    name = names[kern]
+    t = table.get(name)
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": None if t is None else t["fetch_bytes"] + t["write_bytes"],
+            "kernel": name, "algorithmic_bytes": alg, "avg_launch_us": round(us, 2),
+            "other_dense_us": {k: round(v, 2) for k, v in kern_us.items() if k != kern and v}}
+
+
+def kernel_names(s, prec32):
+    info = s.info()
+    r = "float" if prec32 else "double"
+    y = f"kb_wall_dense_yc<{r}, {info['tile_y_rows']}>" if info["tile_y_walk"] else \
+        f"kb_wall_dense_y<{r}, {info['tile_y_rows']}>"
+    return {"dense_x": f"kb_wall_dense_x<{r}, {info['tile_x_rows']}>", "dense_y": y}
+
+
+def run_mode(precision, steps, warmup, w, table, tune_cache=None):
     import numpy as np
     import torch
     from paper_1711_11361_amd import cc
 
     s = cc.Solver(w["grid"], w["body"], precision=precision)
     s.set_prim(w["prim"])
-    # default tiles (1-row x-sweep blocks, 8-row y-sweep tiles), not the tuner's pick: on
-    # this grid every shape gives the same step time within noise, and a fixed choice keeps
-    # the timed kernels the same from run to run (and under the profiler)
+    prec32 = precision == cc.CC_FP32_GEOM64
+    if tune_cache is not None:
+        s.autotune(reps=5, cache_path=tune_cache)
     cfl = w["cfl"]
+    cells = w["grid"]["nx"] * w["grid"]["ny"]
     # host-planned steps (cc_cfl_dt read back, then the captured step), for comparison
-    for _ in range(10):
+    for _ in range(5):
         s.step(s.cfl_dt(cfl))
     torch.cuda.synchronize()
-    nh = min(steps, 100)
+    nh = min(steps, 50)
     h0 = time.perf_counter()
     for _ in range(nh):
         s.step(s.cfl_dt(cfl))
@@ -55,60 +106,170 @@ def run_mode(precision, steps, warmup, w):
     t0 = time.perf_counter()
     s.advance(steps, cfl)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    T = time.perf_counter() - t0
     info = s.info()
     if info["status"] != 0:
         raise RuntimeError(f"device status {info['status']}")
-    # latency pass after the timed region: an event pair around every step (the events
-    # themselves cost about a microsecond per step, so they stay out of the throughput run)
-    _, ms = s.advance(min(steps, 200), cfl, want_ms=True)
+    # latency pass after the timed region: an event pair around every step
+    _, ms = s.advance(min(steps, 100), cfl, want_ms=True)
     lat = np.asarray(ms, dtype=np.float64)
+    # kernel pass: the captured step's launches issued one by one, events around each dense
+    # (merged first box phase + tiles) launch
+    kern_us = timed_kernels(lambda: s.step(s.cfl_dt(cfl)), min(steps, 50), lambda m: cc.cc_timing(s.ctx, m),
+                            lambda: cc.cc_timing_read(s.ctx))
+    # phase breakdown of single sweeps (events between the box and geometry launches)
+    cc.cc_timing(s.ctx, 2)
+    cc.cc_timing_read(s.ctx)
+    nph = min(steps, 20)
+    for _ in range(nph):
+        s.step(s.cfl_dt(cfl))
+    ph = cc.cc_timing_read(s.ctx)
+    cc.cc_timing(s.ctx, 0)
     info = s.info()
     if info["status"] != 0:
         raise RuntimeError(f"device status {info['status']}")
-    # kernel timing pass (same kernels and grids, launched one by one): every dense-sweep
-    # launch records its own start and stop events
-    nt = min(steps, 100)
-    cc.cc_timing(s.ctx, 1)
-    cc.cc_timing_read(s.ctx)
-    for _ in range(nt):
-        s.step(s.cfl_dt(cfl))
-    tim = cc.cc_timing_read(s.ctx)
-    # phase breakdown: events bracket the box and geometry phases
-    cc.cc_timing(s.ctx, 2)
-    for _ in range(nt):
-        s.step(s.cfl_dt(cfl))
-    phases = cc.cc_timing_read(s.ctx)
-    cc.cc_timing(s.ctx, 0)
-    tim["box"], tim["geometry"] = phases["box"], phases["geometry"]
-    tim["phase_steps"] = nt
-    U = s.get_u()
-    assert np.isfinite(U).all()
+    out = {"value": rate(cells, steps, T), "ms_per_step": 1e3 * T / steps, "host_planned_ms_per_step": host_ms,
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+           "t_end": info["t"], "collapses": info["collapses"],
+           "tiles": {"x_rows_per_block": info["tile_x_rows"], "y_rows_per_tile": info["tile_y_rows"],
+                     "y_column_walk": info["tile_y_walk"]},
+           "box_phases_us_per_step": round(1e3 * ph["box"][0] / nph, 2),
+           "geometry_us_per_step": round(1e3 * ph["geometry"][0] / nph, 2)}
+    bpv = 4 if prec32 else 8
+    out["roofline"] = roofline(kern_us, cells, bpv, table, kernel_names(s, prec32))
+    step_bytes = cells * 2 * 4 * 2 * bpv
+    ach = step_bytes / (out["ms_per_step"] * 1e-3) / 1e9
+    out["step_roofline"] = {"algorithmic_bytes": step_bytes, "achieved": round(ach, 1), "unit": "GB/s",
+                            "frac": round(ach / HBM_PEAK_GBS, 4)}
+    out["solver"] = s
+    return out
+
+
+def accuracy(w, nsteps):
+    """FP32 state against the FP64 path on the same workload with identical time steps:
+    relative L1 of density (volume-weighted), and the mass drift of each (change of the
+    mass total minus the conservation budget, per initial mass)."""
+    import numpy as np
+    from paper_1711_11361_amd import cc
+
+    res = {}
+    s32 = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP32_GEOM64)
+    s32.set_prim(w["prim"])
+    s32.set_budget(True)
+    T0 = s32.totals()
+    dts, _ = s32.advance(nsteps, w["cfl"])
+    s64 = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP64)
+    s64.set_prim(w["prim"])
+    s64.set_budget(True)
+    for dt in dts:
+        s64.step(dt)
+    for name, s in (("f32", s32), ("f64", s64)):
+        T1, (bnd, wall, lost) = cc.cc_totals(s.ctx, True)
+        res[name] = abs((T1[0] - T0[0]) - bnd[0] - wall[0] + lost[0]) / T0[0]
+    al = s64.geometry_dump(0)["alpha"]
+    U32, U64 = s32.get_u(), s64.get_u()
+    m = (al > 0) & (U64[0] > 0) & (U32[0] > 0)
+    l1 = float((np.abs(U32[0][m] - U64[0][m])).sum() / U64[0][m].sum())
+    s32.close()
+    s64.close()
+    return {"steps": nsteps, "fp32_l1_density_vs_fp64": l1, "mass_drift": {"f32": res["f32"], "f64": res["f64"]},
+            "note": "same workload from t=0 with the conservation budget tracked, the FP64 path given the FP32 "
+                    "run's time steps"}
+
+
+def piston_leg(steps, warmup):
+    """Config 1: the inclined piston, 200 x 20, FP64 (launch-bound at 4000 cells)."""
+    import torch
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    w = W.piston()
+    s = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP64)
+    s.set_prim(w["prim"])
+    s.advance(warmup, w["cfl"])
+    torch.cuda.synchronize()
+    n = min(steps, 150)  # the run to t = 0.5 takes about 190 steps
+    t0 = time.perf_counter()
+    s.advance(n, w["cfl"])
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
     cells = w["grid"]["nx"] * w["grid"]["ny"]
-    fluid = int((s.geometry_dump(0)["alpha"] > 0.0).sum())  # cells with fluid at the end
-    # surface loads of the end state (force and moment on the body), timed per call
-    loads = s.surface_loads()
-    nl = 50
-    l0 = time.perf_counter()
-    for _ in range(nl):
-        s.surface_loads()
-    loads_us = 1e6 * (time.perf_counter() - l0) / nl
-    T = t1 - t0
-    return {"value": cells * steps / T, "fluid_value": fluid * steps / T, "fluid_cells": fluid,
-            "loads": {"force": [float(loads[0]), float(loads[1])], "moment": float(loads[2]),
-                      "us_per_call": loads_us},
-            "ms_per_step": 1e3 * T / steps, "lat": lat, "timing": tim,
-            "host_planned_ms_per_step": host_ms,
-            "t_end": info["t"], "collapses": info["collapses"], "box_cells": info["box_cells"],
-            "tiles": {"x_rows_per_block": info["tile_x_rows"], "y_rows_per_tile": info["tile_y_rows"],
-                      "y_column_walk": info["tile_y_walk"]}}
+    s.close()
+    return {"workload": "inclined piston (30 degrees) into gas at rest, 200x20 on [0,1]x[0,0.1], FP64",
+            "value": rate(cells, n, T), "unit": "cell-updates/s", "ms_per_step": 1e3 * T / n, "steps": n}
+
+
+def triangle_batch_leg(steps, warmup, table, seeds=16):
+    """Config 3: 16 triangle seeds at 2048 x 1024 stepped as one batch, FP32 state."""
+    import numpy as np
+    import torch
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    ws = [W.triangle_case(k) for k in range(seeds)]
+    sol = []
+    b = cc.Batch(seeds, cc.CC_FP32_GEOM64)
+    for w in ws:
+        s = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP32_GEOM64)
+        s.set_prim(w["prim"])
+        b.add(s)
+        sol.append(s)
+    b.advance(warmup, 0.8)
+    torch.cuda.synchronize()
+    n = min(steps, 100)
+    t0 = time.perf_counter()
+    b.advance(n, 0.8)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    _, lat = b.advance(min(n, 50), 0.8, want_ms=True)
+
+    def step():
+        dts = b.cfl_dt(0.8)
+        b.step(dts)
+
+    kern_us = timed_kernels(step, 10, lambda m: cc.cc_batch_timing(b.b, m), lambda: cc.cc_batch_timing_read(b.b))
+    cells = sum(w["grid"]["nx"] * w["grid"]["ny"] for w in ws)
+    names = {"dense_x": "kb_wall_dense_x<float, 1>", "dense_y": "kb_wall_dense_y<float, 8>"}
+    rf = roofline(kern_us, cells, 4, table, names)
+    for s in sol:
+        b.remove(s)
+        s.close()
+    b.close()
+    lat = np.asarray(lat, dtype=np.float64)
+    step_bytes = cells * 64
+    ach = step_bytes / (T / n) / 1e9
+    return {"workload": f"{seeds} triangle seeds crossing the Mach-2 shock, 2048x1024 each, one batch, "
+                        "FP32 state / FP64 geometry",
+            "value": rate(cells, n, T), "unit": "cell-updates/s", "ms_per_iteration": 1e3 * T / n, "steps": n,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "roofline": rf,
+            "step_roofline": {"algorithmic_bytes": step_bytes, "achieved": round(ach, 1), "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4)}}
+
+
+def naca_leg(steps, warmup, table):
+    """Config 4: the pitching NACA 0012 at 4096 x 4096, tiles tuned, captured steps."""
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    w = W.naca()
+    out = {"workload": "NACA 0012 pitching 2 deg at reduced frequency 0.1 in a Mach-0.7 stream, 4096x4096 on "
+                       "[-2,4]x[-3,3], tiles tuned"}
+    cache = os.path.join("/tmp", f"cc_tiles_{os.getpid()}.txt")
+    n = min(steps, 100)
+    for prec, key in ((cc.CC_FP32_GEOM64, "f32"), (cc.CC_FP64, "f64")):
+        r = run_mode(prec, n, warmup, w, table, tune_cache=cache)
+        r.pop("solver").close()
+        r["steps"] = n
+        out[key] = r
+    out["value"] = out["f32"]["value"]
+    out["unit"] = "cell-updates/s"
+    return out
 
 
 def batched(w, instances, steps, warmup):
-    """Several independent copies of the workload stepped as one batch (one launch per
-    phase over all of them; device-planned steps): aggregate cell-updates/s.  The single
-    workload's launches are latency-bound and leave most of the chip idle; a batch fills
-    it.  Reported beside the headline, not as it."""
+    """Copies of the headline workload stepped as one batch (device-planned), and the same
+    copies as plain FP64 contexts advanced one after another with launches of their own."""
     import numpy as np
     import torch
     from paper_1711_11361_amd import cc
@@ -121,35 +282,18 @@ def batched(w, instances, steps, warmup):
     b = cc.Batch(instances, cc.CC_FP32_GEOM64)
     for s in sol:
         b.add(s)
-    # host-planned iterations (time steps read back before each), for comparison
-    dts = b.cfl_dt(w["cfl"])
-    for _ in range(warmup):
-        b.step(dts)
-        dts, st = b.last_dt(w["cfl"])
-    torch.cuda.synchronize()
-    nh = min(steps, 100)
-    h0 = time.perf_counter()
-    for _ in range(nh):
-        b.step(dts)
-        dts, st = b.last_dt(w["cfl"])
-        if any(st):
-            raise RuntimeError(f"device status {st}")
-    host_ms = 1e3 * (time.perf_counter() - h0) / nh
-    # timed: device-planned iterations queued without host round trips
     b.advance(warmup, w["cfl"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.advance(steps, w["cfl"])
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    _, lat = b.advance(min(steps, 100), w["cfl"], want_ms=True)  # latency pass
+    _, lat = b.advance(min(steps, 100), w["cfl"], want_ms=True)
     cells = w["grid"]["nx"] * w["grid"]["ny"] * instances
     for s in sol:
         b.remove(s)
         s.close()
     b.close()
-    # the same copies as plain FP64 contexts, each advanced with launches of its own, one
-    # after the other: the per-instance comparison for the batched FP32-state rate
     s64 = []
     for _ in range(instances):
         s = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP64)
@@ -168,32 +312,52 @@ def batched(w, instances, steps, warmup):
     lat = np.asarray(lat, dtype=np.float64)
     return {"instances": instances, "precision": "f32 state, f64 geometry", "planning": "device",
             "cell_updates_per_s": cells * steps / T, "ms_per_iteration": 1e3 * T / steps,
-            "host_planned_ms_per_iteration": host_ms,
             "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
             "per_instance_fp64": {"cell_updates_per_s": cells * n64 / T64, "steps_each": n64}}
 
 
-def cpu_baseline(w, budget_s=15.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The FP64 oracle as it stands, on a bounded sample of the headline workload from t=0:
+    the plain build on one thread, and the OpenMP build of the same source on all host
+    threads (identical results)."""
     from oracle import ref
-    o = ref.Oracle(w["grid"], w["body"])
-    o.set_prim(w["prim"])
     cells = w["grid"]["nx"] * w["grid"]["ny"]
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        o.step(o.cfl_dt(w["cfl"]))
-        n += 1
-    T = time.perf_counter() - t0
-    return {"value": cells * n / T, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} steps of the same 1024x512 workload from t=0 (FP64 C oracle, one thread, "
-                      f"{T:.1f} s)"}
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    res = {}
+    for parallel in (False, True):
+        o = ref.Oracle(w["grid"], w["body"], parallel=parallel)
+        o.set_prim(w["prim"])
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            o.step(o.cfl_dt(w["cfl"]))
+            n += 1
+        T = time.perf_counter() - t0
+        o.close()
+        res[parallel] = (rate(cells, n, T), n, T)
+    v, n, T = res[True]
+    v1, n1, T1 = res[False]
+    return {"value": v, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the same 1024x512 workload from t=0 ({T:.1f} s, FP64 C oracle, OpenMP over "
+                      f"rows and lines, {threads} threads)",
+            "single_thread": {"value": v1, "sample": f"{n1} steps ({T1:.1f} s, one thread)"},
+            "host": {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count()}}
 
 
 def serving(n, budget_gib, slots):
     """The serving mix: n requests (Poisson arrivals at 50/s, 500 steps each) served once
     batched in FP32 state / FP64 geometry and once as plain per-request FP64 launches."""
     import numpy as np
-    from paper_1711_11361_amd import cc
     from paper_1711_11361_amd import serving as S
 
     # first use of both modes (module load, graph capture paths) outside the measured runs
@@ -219,29 +383,27 @@ def serving(n, budget_gib, slots):
 
 
 def probe():
-    """Dispatches for counter runs (one process, eager launches): every dense-sweep tile
-    variant on the 1024x512 cylinder in both precisions, then a plain 16 MiB fill and a
-    16 MiB device copy whose counter readings scale FETCH_SIZE and WRITE_SIZE to bytes."""
+    """Dispatches for counter runs (one process, the step's launches one by one): the dense
+    launches of the headline workload in both precisions and of the 4096 x 4096 aerofoil in
+    FP32, then a plain 16 MiB fill and a 16 MiB device copy whose counter readings scale
+    FETCH_SIZE and WRITE_SIZE to bytes."""
     import torch
     from paper_1711_11361_amd import cc
     from paper_1711_11361_amd import workloads as W
 
-    w = W.cylinder()
-    for prec in (cc.CC_FP32_GEOM64, cc.CC_FP64):
-        s = cc.Solver(w["grid"], w["body"], precision=prec)
-        s.set_prim(w["prim"])
-        for _ in range(10):
-            s.step(s.cfl_dt(w["cfl"]))
-        cc.cc_timing(s.ctx, 1)  # individual launches: one dispatch per dense sweep
-        ys = [0, 1, 2, 3, 4, 5] if prec == cc.CC_FP32_GEOM64 else [0, 1, 4]
-        for k, ty in enumerate(ys):
-            s.set_tiles(min(k, 3), ty)
+    for w, precs in ((W.cylinder(), (cc.CC_FP32_GEOM64, cc.CC_FP64)), (W.naca(), (cc.CC_FP32_GEOM64,))):
+        for prec in precs:
+            s = cc.Solver(w["grid"], w["body"], precision=prec)
+            s.set_prim(w["prim"])
+            for _ in range(4):
+                s.step(s.cfl_dt(w["cfl"]))
+            cc.cc_timing(s.ctx, 1)  # the step's launches one by one
             for _ in range(2):
                 s.step(s.cfl_dt(w["cfl"]))
-        cc.cc_timing_read(s.ctx)
-        cc.cc_timing(s.ctx, 0)
-        print("probe", "fp32" if prec == cc.CC_FP32_GEOM64 else "fp64", s.info(), flush=True)
-        s.close()
+            cc.cc_timing_read(s.ctx)
+            cc.cc_timing(s.ctx, 0)
+            print("probe", w["name"], "fp32" if prec == cc.CC_FP32_GEOM64 else "fp64", s.info(), flush=True)
+            s.close()
     a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     a.fill_(1.0)
     b = torch.empty_like(a)
@@ -252,9 +414,7 @@ def probe():
 
 
 COPY_BYTES = 16 << 20
-TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "dense_sweep_1024x512_hbm_traffic.md")
-
-
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "dense_sweep_hbm_traffic.md")
 DENSE_SOURCES = ("cc_device.h", "sweep.h", "engine.h")
 
 
@@ -268,9 +428,8 @@ def dense_fingerprint():
 
 
 def traffic_table():
-    """Per-dispatch HBM bytes of every dense-sweep kernel variant, from the committed counter
-    summary (the JSON block in it), or {} when it is absent or was taken from other kernel
-    sources than the current ones."""
+    """Per-dispatch HBM bytes of the dense launches from the committed counter summary (its
+    JSON block), or {} when it is absent or was taken from other kernel sources."""
     try:
         txt = open(TRAFFIC_TABLE).read()
         d = json.loads(txt.split("```json")[1].split("```")[0])
@@ -285,8 +444,9 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the legs of the other configurations")
     ap.add_argument("--serving", type=int, default=0,
-                    help="requests of the serving mix (0: skip; off by default, see the design notes)")
+                    help="requests of the serving mix (0: skip)")
     ap.add_argument("--probe", action="store_true", help="dispatches for rocprofv3 counter runs only")
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--slots", type=int, default=64)
@@ -298,38 +458,21 @@ def main():
     if args.probe:
         probe()
         return
-    import numpy as np
     from paper_1711_11361_amd import cc
     from paper_1711_11361_amd import workloads as W
 
     w = W.cylinder()
     table = traffic_table()
     nx, ny = w["grid"]["nx"], w["grid"]["ny"]
-    r32 = run_mode(cc.CC_FP32_GEOM64, args.steps, args.warmup, w)
-    r64 = run_mode(cc.CC_FP64, args.steps, args.warmup, w)
-
-    def roofline(r, bytes_per_value):
-        tim = r["timing"]
-        kern = max(("dense_x", "dense_y"), key=lambda k: tim[k][0])
-        ms, cnt = tim[kern]
-        avg_s = ms / cnt / 1e3
-        alg = nx * ny * 4 * 2 * bytes_per_value  # read + write of the state, one sweep
-        ach = alg / avg_s / 1e9
-        rows = r["tiles"]["x_rows_per_block"] if kern == "dense_x" else r["tiles"]["y_rows_per_tile"]
-        kname = "dense_yc" if kern == "dense_y" and r["tiles"]["y_column_walk"] else kern
-        name = f"kb_{kname}<{'float' if bytes_per_value == 4 else 'double'}, {rows}>"
-        t = table.get(name)
-        return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None if t is None else t["fetch_bytes"] + t["write_bytes"],
-                "algorithmic_bytes": alg,
-                "avg_launch_us": round(avg_s * 1e6, 2),
-                "other_dense_us": round(1e3 * tim["dense_y" if kern == "dense_x" else "dense_x"][0] /
-                                        max(tim["dense_y" if kern == "dense_x" else "dense_x"][1], 1), 2),
-                "box_kernels_us_per_step": round(1e3 * tim["box"][0] / tim["phase_steps"], 2),
-                "geometry_us_per_step": round(1e3 * tim["geometry"][0] / tim["phase_steps"], 2),
-                "tiles": r["tiles"]}
-
+    r32 = run_mode(cc.CC_FP32_GEOM64, args.steps, args.warmup, w, table)
+    s32 = r32.pop("solver")
+    fluid = int((s32.geometry_dump(0)["alpha"] > 0.0).sum())  # cells with fluid at the end
+    loads = s32.surface_loads()
+    s32.close()
+    r64 = run_mode(cc.CC_FP64, args.steps, args.warmup, w, table)
+    r64.pop("solver").close()
+    print(f"headline done: {r32['ms_per_step']:.4f} ms/step FP32, {r64['ms_per_step']:.4f} FP64", file=sys.stderr,
+          flush=True)
     out = {
         "metric": "cell-updates/s per split step (FP32+FP64-geom vs FP64) + p50/p99 step latency",
         "value": r32["value"],
@@ -345,20 +488,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cylinder r=0.1 crossing a stationary Mach-2 shock, 1024x512 on [0,2]x[0,1], "
                                "body speed 1.0, CFL 0.8", "grid": [nx, ny], "cells": nx * ny},
-        "latency_ms": {"p50": float(np.percentile(r32["lat"], 50)), "p99": float(np.percentile(r32["lat"], 99))},
+        "latency_ms": r32["latency_ms"],
         "host_planned_ms_per_step": r32["host_planned_ms_per_step"],
-        "fluid_cell_updates_per_s": r32["fluid_value"],
-        "fluid_cells": r32["fluid_cells"],
-        "surface_loads": r32["loads"],
-        "fp64": {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
-                 "host_planned_ms_per_step": r64["host_planned_ms_per_step"],
-                 "latency_ms": {"p50": float(np.percentile(r64["lat"], 50)),
-                                "p99": float(np.percentile(r64["lat"], 99))},
-                 "roofline": roofline(r64, 8)},
-        "roofline": roofline(r32, 4),
+        "fluid_cell_updates_per_s": fluid * args.steps / (r32["ms_per_step"] * 1e-3 * args.steps),
+        "fluid_cells": fluid,
+        "surface_loads": {"force": [float(loads[0]), float(loads[1])], "moment": float(loads[2])},
+        "roofline": r32["roofline"],
+        "step_roofline": r32["step_roofline"],
+        "phases_us_per_step": {"box": r32["box_phases_us_per_step"], "geometry": r32["geometry_us_per_step"]},
+        "fp64": {k: r64[k] for k in ("value", "ms_per_step", "host_planned_ms_per_step", "latency_ms", "roofline",
+                                     "step_roofline")},
+        "tiles": r32["tiles"],
         "sim_time_reached": r32["t_end"],
     }
-    out["batched"] = [batched(w, k, min(args.steps, 200), min(args.warmup, 20)) for k in (4, 16)]
+    out["fp64"]["dtype"] = "f64"
+    out["accuracy"] = accuracy(w, 200)
+    print("accuracy done", file=sys.stderr, flush=True)
+    if not args.no_configs:
+        out["configs"] = {"piston_200x20": piston_leg(args.steps, min(args.warmup, 10))}
+        out["configs"]["triangle_16x2048x1024_batched"] = triangle_batch_leg(args.steps, min(args.warmup, 10), table)
+        print("triangle batch done", file=sys.stderr, flush=True)
+        out["configs"]["naca_4096x4096"] = naca_leg(args.steps, min(args.warmup, 10), table)
+        print("naca done", file=sys.stderr, flush=True)
+        out["batched_copies"] = [batched(w, k, min(args.steps, 200), min(args.warmup, 20)) for k in (4, 16)]
     if args.serving > 0:
         out["serving"] = serving(args.serving, args.budget_gib, args.slots)
     if not args.no_cpu:

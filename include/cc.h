@@ -237,11 +237,14 @@ cc_status cc_set_tiles(cc_ctx* ctx, int32_t tile_x, int32_t tile_y);
 typedef enum { CC_LAUNCH_PER_PHASE = 0, CC_LAUNCH_PERSISTENT = 1 } cc_launch_mode;
 cc_status cc_set_launch_mode(cc_ctx* ctx, int32_t mode);
 
-/* Timing with HIP events on the context's stream.  mode bit 0: each dense-sweep launch
- * records its own start/stop events (no extra stream commands, so the interval is the
- * kernel's execution); bit 1: events bracket the box-kernel and geometry phases (extra
- * stream commands).  0 stops recording.  cc_timing_read returns, since the last read,
- * pairs (total ms, count) for: dense x, dense y, box phases, geometry (8 doubles). */
+/* Timing with HIP events on the context's stream.  mode bit 0: cc_step issues the
+ * captured step's launches one by one (same kernels, grids and arguments) and each dense
+ * launch (the merged first box phase and dense tiles) records its own start/stop events
+ * (no extra stream commands, so the interval is that kernel's execution); single sweeps
+ * (cc_sweep) time their separate dense launches the same way.  Bit 1: cc_step runs single
+ * sweeps and events bracket their box-kernel and geometry phases (extra stream commands).
+ * 0 stops recording.  cc_timing_read returns, since the last read, pairs (total ms,
+ * count) for: dense x, dense y, box phases, geometry (8 doubles). */
 cc_status cc_timing(cc_ctx* ctx, int32_t mode);
 cc_status cc_timing_read(cc_ctx* ctx, double* h_out, int32_t n);
 
@@ -300,6 +303,11 @@ cc_status cc_batch_cfl_dt(cc_batch* b, double cfl, double* h_dt);
 cc_status cc_batch_advance(cc_batch* b, int32_t nsteps, double cfl, double* h_dt, float* h_step_ms,
                            int32_t* h_done);
 const char* cc_batch_last_error(const cc_batch* b);
+/* Timing of a batch's steps (mode bit 0, as cc_timing: cc_batch_step issues the captured
+ * step's launches one by one with events around each dense launch; 0 stops), and the
+ * pairs (total ms, count) of dense x, dense y, box, geometry since the last read. */
+cc_status cc_batch_timing(cc_batch* b, int32_t mode);
+cc_status cc_batch_timing_read(cc_batch* b, double* h_out, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -86,6 +86,8 @@ _sig = {
     "cc_batch_cfl_dt": (C.c_int, [_vp, _d, C.POINTER(_d)]),
     "cc_batch_advance": (C.c_int, [_vp, _i32, _d, C.POINTER(_d), C.POINTER(C.c_float), C.POINTER(_i32)]),
     "cc_batch_last_error": (C.c_char_p, [_vp]),
+    "cc_batch_timing": (C.c_int, [_vp, _i32]),
+    "cc_batch_timing_read": (C.c_int, [_vp, C.POINTER(_d), _i32]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -282,6 +284,17 @@ def cc_timing(ctx, enable):
 def cc_timing_read(ctx):
     out = (_d * 8)()
     _check(ctx, _lib.cc_timing_read(ctx, out, 8))
+    v = out[:]
+    return {"dense_x": (v[0], v[1]), "dense_y": (v[2], v[3]), "box": (v[4], v[5]), "geometry": (v[6], v[7])}
+
+
+def cc_batch_timing(b, enable):
+    _bcheck(b, _lib.cc_batch_timing(b, int(enable)))
+
+
+def cc_batch_timing_read(b):
+    out = (_d * 8)()
+    _bcheck(b, _lib.cc_batch_timing_read(b, out, 8))
     v = out[:]
     return {"dense_x": (v[0], v[1]), "dense_y": (v[2], v[3]), "box": (v[4], v[5]), "geometry": (v[6], v[7])}
 

@@ -232,6 +232,12 @@ struct Engine {
     int mode = 0;                       // 0: one launch per phase; 1: one persistent launch per sweep
     GridSync* d_sync = nullptr;         // barrier counters of the persistent sweep launches
     unsigned long long wait_ticks = 0;  // barrier wait limit (wall-clock ticks)
+    // timing (cc_timing, cc_batch_timing): bit 0 a whole step's launches one by one, the
+    // dense (merged wall + dense) launches bracketed by events of their own; bit 1 events
+    // around the box and geometry phases of single sweeps.  Event pairs recorded and not
+    // read yet, and spare ones.
+    int timing = 0;
+    std::vector<TimedPair> pending, pool;
 };
 
 }  // namespace
@@ -262,9 +268,6 @@ struct cc_ctx {
     Box last_sweep_box;
     Engine eng;  // launch plan of this context's own calls
     cc_batch* batch;  // batch this context belongs to, if any
-    // timing: bit 0 dense sweeps, bit 1 box and geometry phases
-    int timing;
-    std::vector<TimedPair> pending, pool;
     // wave speeds of the current state, reduced and read back by the last captured step
     bool speeds_ready;
     int speeds_buf;
@@ -433,23 +436,30 @@ bool geo_fits(const cc_ctx* c, const Box& r) { return box_empty(r) || (r.w() <= 
 unsigned nblk(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
 unsigned nblk(size_t n) { return nblk(n, TPB); }
 
-void tstart(cc_ctx* c, int kind, TimedPair& tp) {
-    if (!(c->timing & 2)) return;
-    if (c->pool.empty()) {
+// An event pair of kind `kind` (0 dense x, 1 dense y, 2 box phases, 3 geometry) from the
+// engine's spares, recorded as pending.
+TimedPair engine_pair(Engine& E, int kind) {
+    if (E.pool.empty()) {
         TimedPair p;
         (void)hipEventCreate(&p.a);
         (void)hipEventCreate(&p.b);
-        c->pool.push_back(p);
+        E.pool.push_back(p);
     }
-    tp = c->pool.back();
-    c->pool.pop_back();
+    TimedPair tp = E.pool.back();
+    E.pool.pop_back();
     tp.kind = kind;
+    E.pending.push_back(tp);
+    return tp;
+}
+
+void tstart(cc_ctx* c, int kind, TimedPair& tp) {
+    if (!(c->eng.timing & 2)) return;
+    tp = engine_pair(c->eng, kind);
     (void)hipEventRecord(tp.a, c->stream);
 }
 void tstop(cc_ctx* c, TimedPair& tp) {
-    if (!(c->timing & 2)) return;
+    if (!(c->eng.timing & 2)) return;
     (void)hipEventRecord(tp.b, c->stream);
-    c->pending.push_back(tp);
 }
 
 cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vector<double>& p1) {
@@ -751,7 +761,7 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
                   bool wall = false) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    int nwall = wall && !ta ? ktotal(E, L_BOXW) : 0;
+    int nwall = wall ? ktotal(E, L_BOXW) : 0;
     const int* ow = koff(E, L_BOXW);
     for (int d = 0; d < 2; d++) {
         if (!((which >> d) & 1)) continue;
@@ -760,11 +770,16 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
         if (blocks == 0) continue;
         const int* off = koff(E, kind);
         auto go = [&](auto kern, auto wkern, int threads) {
-            if (ta) {
-                hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, ta, tb, 0, A, off, n, sw, fold);
-            } else if (nwall > 0) {
-                hipLaunchKernelGGL(wkern, dim3(nwall + blocks), dim3(threads), 0, s, A, ow, nwall, off, n, sw, fold);
+            if (nwall > 0) {  // the box blocks ahead of the tiles in one launch
+                if (ta)
+                    hipExtLaunchKernelGGL(wkern, dim3(nwall + blocks), dim3(threads), 0, s, ta, tb, 0, A, ow, nwall, off,
+                                          n, sw, fold);
+                else
+                    hipLaunchKernelGGL(wkern, dim3(nwall + blocks), dim3(threads), 0, s, A, ow, nwall, off, n, sw,
+                                       fold);
                 nwall = 0;
+            } else if (ta) {
+                hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, ta, tb, 0, A, off, n, sw, fold);
             } else {
                 hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, A, off, n, sw, fold);
             }
@@ -791,7 +806,7 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
             }
         }
     }
-    if (wall && !ta && nwall > 0)  // no dense launch took the box blocks
+    if (wall && nwall > 0)  // no dense launch took the box blocks
         klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
 }
 
@@ -839,6 +854,13 @@ hipError_t engine_alloc_host(Engine& E) {
 
 void engine_free(Engine& E) {
     drop_graphs(E);
+    for (auto* v : {&E.pending, &E.pool})
+        for (auto& p : *v) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+    E.pending.clear();
+    E.pool.clear();
     for (int b = 0; b < 2; b++) {
         if (E.h_args[b]) (void)hipHostFree(E.h_args[b]);
         if (E.ev[b]) (void)hipEventDestroy(E.ev[b]);
@@ -912,6 +934,60 @@ void step_kernels(const Engine& E, hipStream_t s, int dir0) {
         launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw, true);
         launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1, sw);
     }
+}
+
+// The same launches one by one, each dense (merged wall + dense) launch bracketed by an
+// event pair of its own (timing bit 0): their kernel times are those of the captured step.
+// Members that sweep the other way get a launch of the other kernel, timed separately.
+template <typename R>
+void step_kernels_timed(Engine& E, hipStream_t s, int dir0) {
+    int which0 = dir0 < 0 ? 3 : 1 << dir0, which1 = dir0 < 0 ? 3 : 1 << (1 - dir0);
+    int n = (int)E.mem.size();
+    const StepArgs* A = E.d_args;
+    klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
+    klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
+    klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
+    for (int sw = 0; sw < 2; sw++) {
+        int which = sw == 0 ? which0 : which1;
+        bool wall = true;
+        for (int d = 0; d < 2; d++) {
+            if (!((which >> d) & 1)) continue;
+            TimedPair tp = engine_pair(E, d);
+            launch_dense<R>(E, s, sw, 1 << d, tp.a, tp.b, sw, wall);
+            wall = false;
+        }
+        launch_box_post<R>(E, s, sw, which, sw);
+    }
+}
+
+template <typename R>
+void step_sequence_timed(Engine& E, hipStream_t s, int b, int dir0) {
+    int n = (int)E.mem.size();
+    (void)engine_upload(E, s, b);
+    step_kernels_timed<R>(E, s, dir0);
+    (void)hipMemcpyAsync(E.h_cflout, E.d_cflout, 16 * (size_t)E.cap_n + 8 * (size_t)n, hipMemcpyDeviceToHost, s);
+}
+
+// Reads and recycles the engine's pending event pairs: per kind (dense x, dense y, box,
+// geometry) the summed milliseconds and the count, in out[2 kind], out[2 kind + 1].
+hipError_t engine_timing_read(Engine& E, hipStream_t s, double* out, int n) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    double sum[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    for (auto& p : E.pending) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return e;
+        sum[p.kind] += ms;
+        cnt[p.kind] += 1.0;
+        E.pool.push_back(p);
+    }
+    E.pending.clear();
+    for (int k = 0; k < 4 && 2 * k + 1 < n; k++) {
+        out[2 * k] = sum[k];
+        out[2 * k + 1] = cnt[k];
+    }
+    return hipSuccess;
 }
 
 template <typename R>
@@ -1044,7 +1120,6 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     c->s0 = 0;
     c->sm = 1;
     c->s1 = 2;
-    c->timing = 0;
     c->speeds_ready = false;
     c->speeds_buf = 0;
     c->batch = nullptr;
@@ -1125,14 +1200,6 @@ cc_status cc_destroy(cc_ctx* c) {
     }
     (void)hipStreamSynchronize(c->stream);
     engine_free(c->eng);
-    for (auto& p : c->pending) {
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
-    }
-    for (auto& p : c->pool) {
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
-    }
     delete c;
     return CC_OK;
 }
@@ -1339,19 +1406,10 @@ cc_status own_sweep(cc_ctx* c, int s) {
     launch_box_pre<R>(E, c->stream, s);
     tstop(c, tb);
     hipEvent_t ta = nullptr, tz = nullptr;
-    if (c->timing & 1) {
-        if (c->pool.empty()) {
-            TimedPair p;
-            (void)hipEventCreate(&p.a);
-            (void)hipEventCreate(&p.b);
-            c->pool.push_back(p);
-        }
-        TimedPair tp = c->pool.back();
-        c->pool.pop_back();
-        tp.kind = dir;
+    if (c->eng.timing & 1) {
+        TimedPair tp = engine_pair(c->eng, dir);
         ta = tp.a;
         tz = tp.b;
-        c->pending.push_back(tp);
     }
     launch_dense<R>(E, c->stream, s, 1 << dir, ta, tz);
     tstart(c, 2, tb);
@@ -1394,16 +1452,22 @@ cc_status cc_end_step(cc_ctx* c) {
 
 namespace {
 
-// Whole step through the context's own captured graph.
+// Whole step through the context's own captured graph (timed: the same launches one by one,
+// the dense launches bracketed by events).
 template <typename R>
-cc_status own_graph_step(cc_ctx* c, double dt) {
+cc_status own_graph_step(cc_ctx* c, double dt, bool timed = false) {
     Engine& E = c->eng;
     int b = E.buf;
     HIPCHK(c, engine_hostbuf(E, b));
     cc_status st = prepare_step(c, dt, E.h_args[b][0]);
     if (st != CC_OK) return st;
     int dir0 = E.h_args[b][0].sw[0].dir;
-    HIPCHK(c, engine_graph_step<R>(E, c->stream, b, dir0));
+    if (timed) {
+        step_sequence_timed<R>(E, c->stream, b, dir0);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        HIPCHK(c, engine_graph_step<R>(E, c->stream, b, dir0));
+    }
     HIPCHK(c, hipEventRecord(E.ev[b], c->stream));
     E.ev_used[b] = true;
     E.buf = 1 - b;
@@ -1422,7 +1486,7 @@ cc_status cc_step(cc_ctx* c, double dt) {
     if (!c) return CC_ERR_ARG;
     cc_status st = not_in_batch(c);
     if (st != CC_OK) return st;
-    if (c->timing) {  // timing needs the individual launches
+    if (c->eng.timing & 2) {  // phase timing needs the single sweeps' launches
         if ((st = cc_begin_step(c, dt)) != CC_OK) return st;
         int d1 = c->parity, d2 = 1 - c->parity;
         if ((st = cc_sweep(c, d1, dt)) != CC_OK) return st;
@@ -1436,7 +1500,8 @@ cc_status cc_step(cc_ctx* c, double dt) {
         if ((st = cc_sweep(c, d2, dt)) != CC_OK) return st;
         return cc_end_step(c);
     }
-    st = fp32(c) ? own_graph_step<float>(c, dt) : own_graph_step<double>(c, dt);
+    bool timed = (c->eng.timing & 1) != 0;
+    st = fp32(c) ? own_graph_step<float>(c, dt, timed) : own_graph_step<double>(c, dt, timed);
     if (st != CC_OK) return st;
     return cc_end_step(c);
 }
@@ -2144,26 +2209,25 @@ cc_status cc_set_tiles(cc_ctx* c, int32_t tile_x, int32_t tile_y) {
 
 cc_status cc_timing(cc_ctx* c, int32_t enable) {
     if (!c) return CC_ERR_ARG;
-    c->timing = enable & 3;
+    c->eng.timing = enable & 3;
     return CC_OK;
 }
 
 cc_status cc_timing_read(cc_ctx* c, double* h_out, int32_t n) {
     if (!c || !h_out) return fail(c, CC_ERR_ARG, "bad argument");
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    double sum[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
-    for (auto& p : c->pending) {
-        float ms = 0.0f;
-        HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
-        sum[p.kind] += ms;
-        cnt[p.kind] += 1.0;
-        c->pool.push_back(p);
-    }
-    c->pending.clear();
-    for (int k = 0; k < 4 && 2 * k + 1 < n; k++) {
-        h_out[2 * k] = sum[k];
-        h_out[2 * k + 1] = cnt[k];
-    }
+    HIPCHK(c, engine_timing_read(c->eng, c->stream, h_out, n));
+    return CC_OK;
+}
+
+cc_status cc_batch_timing(cc_batch* b, int32_t enable) {
+    if (!b) return CC_ERR_ARG;
+    b->eng.timing = enable & 1;
+    return CC_OK;
+}
+
+cc_status cc_batch_timing_read(cc_batch* b, double* h_out, int32_t n) {
+    if (!b || !h_out) return CC_ERR_ARG;
+    BHIPCHK(b, engine_timing_read(b->eng, b->stream, h_out, n));
     return CC_OK;
 }
 
@@ -2289,8 +2353,15 @@ cc_status cc_batch_step(cc_batch* b, const double* h_dt, int32_t* h_status) {
         // the members' results land in the batch's gather arrays
         E.h_args[buf][k].cfl_out = E.d_cflout + 2 * k;
     }
-    hipError_t e = E.prec == CC_FP32_GEOM64 ? engine_graph_step<float>(E, b->stream, buf, -1)
-                                            : engine_graph_step<double>(E, b->stream, buf, -1);
+    hipError_t e = hipSuccess;
+    if (E.timing & 1) {
+        if (E.prec == CC_FP32_GEOM64) step_sequence_timed<float>(E, b->stream, buf, -1);
+        else step_sequence_timed<double>(E, b->stream, buf, -1);
+        e = hipGetLastError();
+    } else {
+        e = E.prec == CC_FP32_GEOM64 ? engine_graph_step<float>(E, b->stream, buf, -1)
+                                     : engine_graph_step<double>(E, b->stream, buf, -1);
+    }
     if (e != hipSuccess) return bfail(b, CC_ERR_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
     BHIPCHK(b, hipEventRecord(E.ev[buf], b->stream));
     E.ev_used[buf] = true;

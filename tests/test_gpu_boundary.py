@@ -72,3 +72,49 @@ def test_batch_tuner_with_cache(tmp_path):
     c1 = s.autotune(reps=2, cache_path=cache)
     assert s.autotune(reps=2, cache_path=cache) == c1
     assert os.path.getsize(cache) > 0
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+def test_timed_steps_equal_captured_steps(precision):
+    """The timing mode issues the captured step's launches one by one with events around the
+    dense launches: the same results bit for bit, for a context and a batch, and one timed
+    dense launch per sweep (per direction present in a batch)."""
+    w = W.cylinder(nx=200, ny=96)
+    runs = []
+    for timed in (False, True):
+        s = cc.Solver(w["grid"], w["body"], precision=precision)
+        s.set_prim(w["prim"])
+        cc.cc_timing(s.ctx, 1 if timed else 0)
+        for _ in range(6):
+            s.step(s.cfl_dt(w["cfl"]))
+        t = cc.cc_timing_read(s.ctx)
+        runs.append(s.get_u())
+        if timed:
+            assert t["dense_x"][1] == 6 and t["dense_y"][1] == 6 and t["dense_x"][0] > 0 and t["dense_y"][0] > 0
+    assert np.array_equal(runs[0], runs[1])
+    # a batch whose members sweep in different orders (one started a step later)
+    res = []
+    for timed in (False, True):
+        b = cc.Batch(2, precision)
+        sol = []
+        for lag in (0, 1):
+            s = cc.Solver(w["grid"], w["body"], precision=precision)
+            s.set_prim(w["prim"])
+            for _ in range(lag):
+                s.step(s.cfl_dt(w["cfl"]))
+            b.add(s)
+            sol.append(s)
+        cc.cc_batch_timing(b.b, 1 if timed else 0)
+        dts = b.cfl_dt(w["cfl"])
+        for _ in range(4):
+            b.step(dts)
+            dts, _ = b.last_dt(w["cfl"])
+        t = cc.cc_batch_timing_read(b.b)
+        if timed:
+            assert t["dense_x"][1] == 8 and t["dense_y"][1] == 8
+        res.append([s.get_u() for s in sol])
+        for s in sol:
+            b.remove(s)
+        b.close()
+    for a, c in zip(res[0], res[1]):
+        assert np.array_equal(a, c)
