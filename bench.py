@@ -445,6 +445,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the legs of the other configurations")
+    ap.add_argument("--legs", default="piston,triangle,naca,batched",
+                    help="legs of the other configurations to run (comma list of piston, triangle, naca, batched)")
     ap.add_argument("--serving", type=int, default=0,
                     help="requests of the serving mix (0: skip)")
     ap.add_argument("--probe", action="store_true", help="dispatches for rocprofv3 counter runs only")
@@ -504,12 +506,17 @@ def main():
     out["fp64"]["dtype"] = "f64"
     out["accuracy"] = accuracy(w, 200)
     print("accuracy done", file=sys.stderr, flush=True)
-    if not args.no_configs:
-        out["configs"] = {"piston_200x20": piston_leg(args.steps, min(args.warmup, 10))}
+    legs = set(args.legs.split(",")) if not args.no_configs else set()
+    out["configs"] = {}
+    if "piston" in legs:
+        out["configs"]["piston_200x20"] = piston_leg(args.steps, min(args.warmup, 10))
+    if "triangle" in legs:
         out["configs"]["triangle_16x2048x1024_batched"] = triangle_batch_leg(args.steps, min(args.warmup, 10), table)
         print("triangle batch done", file=sys.stderr, flush=True)
+    if "naca" in legs:
         out["configs"]["naca_4096x4096"] = naca_leg(args.steps, min(args.warmup, 10), table)
         print("naca done", file=sys.stderr, flush=True)
+    if "batched" in legs:
         out["batched_copies"] = [batched(w, k, min(args.steps, 200), min(args.warmup, 20)) for k in (4, 16)]
     if args.serving > 0:
         out["serving"] = serving(args.serving, args.budget_gib, args.slots)

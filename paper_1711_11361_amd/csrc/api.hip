@@ -472,9 +472,12 @@ cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vect
 }
 
 // Blocks of a geometry or aperture stage launch of one context (0 without a body): one
-// thread per item, and for a many-sided body at least about one wavefront per boundary
-// item of the region (those take a wavefront's chain search each); the geometry stages run
-// both level jobs side by side, each on its own half.
+// thread per item of the capacity, at most GEO_BLOCK_CAP blocks per level job (a larger
+// region takes several passes: capacities follow the body's circumscribed circle, which
+// for a long body is far larger than its box), and for a many-sided body at least about
+// one wavefront per boundary item of the region (those take a wavefront's chain search
+// each); the geometry stages run both level jobs side by side, each on its own half.
+constexpr size_t GEO_BLOCK_CAP = 512;
 enum GeoStage { GEO_VERTS, GEO_FACES, GEO_CELLS, GEO_SWEPT };
 int geo_blocks(const cc_ctx* c, GeoStage st) {
     const Layout& L = c->lay;
@@ -487,7 +490,7 @@ int geo_blocks(const cc_ctx* c, GeoStage st) {
         default: items = std::max((size_t)(L.capw + 1) * L.caph, (size_t)L.capw * (L.caph + 1)); break;
     }
     size_t walkers = c->m > SMALL_POLY ? std::min<size_t>(256, (size_t)(L.gw + L.gh)) : 0;
-    int b = (int)std::max<size_t>(nblk(items, T_WIDE), walkers);
+    int b = (int)std::max<size_t>(std::min<size_t>(nblk(items, T_WIDE), GEO_BLOCK_CAP), walkers);
     return st == GEO_SWEPT ? b : 2 * b;
 }
 
@@ -659,9 +662,16 @@ cc_status prepare_geometry(cc_ctx* c, double t, int slot, StepArgs& a) {
 // ------------------------------------------------------------------ engine bookkeeping
 int units_of(int, int n) { return n; }
 
+// Box launches take at most BOX_BLOCK_CAP blocks of T_BOX cells (BOXW_BLOCK_CAP of T_WIDE,
+// PATCH_BLOCK_CAP line segments) per member and loop over larger boxes; the persistent mode
+// walks the uncapped tables.
+constexpr int BOX_BLOCK_CAP = 2048, BOXW_BLOCK_CAP = 512, PATCH_BLOCK_CAP = 2048;
+
 int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     const Layout& L = c->lay;
     int m = c->m;
+    bool capped = E.mode != CC_LAUNCH_PERSISTENT;
+    auto cap = [&](int b, int most) { return capped ? std::min(b, most) : b; };
     if (m == 0 && (kind <= L_BOX || kind == L_CS || kind == L_PX || kind == L_PY)) return 0;
     switch (kind) {
         case L_POSE: return (int)nblk((size_t)m, T_WIDE);
@@ -670,10 +680,10 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
         case L_C1: return geo_blocks(c, GEO_CELLS);
         case L_S1: return geo_blocks(c, GEO_SWEPT);
         case L_CS: return geo_blocks(c, GEO_CELLS) + 2 * geo_blocks(c, GEO_SWEPT);
-        case L_BOX: return (int)nblk(std::max<size_t>(L.cap, 1), T_BOX);
-        case L_BOXW: return (int)nblk(std::max<size_t>(L.cap, 1), T_WIDE);
-        case L_PX: return std::max(patch_line_blocks<0>(L.capw, L.caph), 1);
-        case L_PY: return std::max(patch_line_blocks<1>(L.capw, L.caph), 1);
+        case L_BOX: return cap((int)nblk(std::max<size_t>(L.cap, 1), T_BOX), BOX_BLOCK_CAP);
+        case L_BOXW: return cap((int)nblk(std::max<size_t>(L.cap, 1), T_WIDE), BOXW_BLOCK_CAP);
+        case L_PX: return cap(std::max(patch_line_blocks<0>(L.capw, L.caph), 1), PATCH_BLOCK_CAP);
+        case L_PY: return cap(std::max(patch_line_blocks<1>(L.capw, L.caph), 1), PATCH_BLOCK_CAP);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
     }

@@ -162,27 +162,37 @@ __device__ __forceinline__ int spread_item(int lb, int nb) {
 // tests leave open on a many-sided polygon are finished by the wavefront that holds them,
 // with the polygon staged in LDS: faces and cells by chain search, vertex classes by walks
 // over all edges.  The whole block calls it.
+// The job's items are taken nb T_WIDE at a time (the launch grid is capped, so a large
+// region takes several passes).
 template <int K>
 __device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int lb, int nb, double* spoly) {
     const GeoJob& J = a.geo[lev];
     if (!J.active) return;
-    int t = spread_item(lb, nb);
     // the vertex stage also poses the polygon: every block poses its own copy in LDS (the
     // level's copy is written in this launch, by the first block, for the later stages)
-    Poly Pv = J.L.poly;
+    Poly P = J.L.poly;
+    bool staged = false;
     if (K == 0) {
         if (lb == 0)
             for (int k = threadIdx.x; k < J.L.poly.m; k += blockDim.x) geo_pose(J, k);
-        Pv = pose_lds(J, spoly);
+        P = pose_lds(J, spoly);
+        staged = true;
     }
-    bool need = K == 0 ? geo_vertices1(a.g, J, Pv, t) : (K == 1 ? geo_faces1(a.g, J, t) : geo_cells1(a.g, J, t));
-    if (!__syncthreads_or(need)) return;
-    Poly P = K == 0 ? Pv : stage_poly(J.L.poly, spoly);
-    walk_left(need, t, [&](int item, int lane) {
-        if (K == 0) geo_vertex_walk(a.g, J, P, item, lane);
-        if (K == 1) geo_face_chain(a.g, J, P, item, lane);
-        if (K == 2) geo_cell_chain(a.g, J, P, item, lane);
-    });
+    int items = K == 0 ? geo_nverts(J.reg) : (K == 1 ? geo_nfaces(J.reg) : J.reg.w() * J.reg.h());
+    for (int base = 0; base < items; base += nb * T_WIDE) {
+        int t = spread_item(lb, nb) + base;
+        bool need = K == 0 ? geo_vertices1(a.g, J, P, t) : (K == 1 ? geo_faces1(a.g, J, t) : geo_cells1(a.g, J, t));
+        if (!__syncthreads_or(need)) continue;
+        if (!staged) {
+            P = stage_poly(J.L.poly, spoly);
+            staged = true;
+        }
+        walk_left(need, t, [&](int item, int lane) {
+            if (K == 0) geo_vertex_walk(a.g, J, P, item, lane);
+            if (K == 1) geo_face_chain(a.g, J, P, item, lane);
+            if (K == 2) geo_cell_chain(a.g, J, P, item, lane);
+        });
+    }
     __syncthreads();  // the staged polygon may be overwritten next
 }
 
@@ -215,14 +225,22 @@ __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, in
     const SweepJob& J = a.sw[s];
     if (box_empty_dev(J.B)) return;
     Stage S = stage_of(a, s);
-    int t = spread_item(lb, nb);
-    bool need = J.dir == 0 ? swept1<0>(a.g, J, a.mot, S, t) : swept1<1>(a.g, J, a.mot, S, t);
-    if (!__syncthreads_or(need)) return;
-    Poly P = stage_poly(J.Ls.poly, spoly);
-    walk_left(need, t, [&](int item, int lane) {
-        if (J.dir == 0) swept_chain<0>(a.g, J, P, a.mot, S, item, lane);
-        else swept_chain<1>(a.g, J, P, a.mot, S, item, lane);
-    });
+    int items = J.dir == 0 ? (J.B.w() + 1) * J.B.h() : J.B.w() * (J.B.h() + 1);
+    bool staged = false;
+    Poly P = J.Ls.poly;
+    for (int base = 0; base < items; base += nb * T_WIDE) {  // the grid is capped: several passes
+        int t = spread_item(lb, nb) + base;
+        bool need = J.dir == 0 ? swept1<0>(a.g, J, a.mot, S, t) : swept1<1>(a.g, J, a.mot, S, t);
+        if (!__syncthreads_or(need)) continue;
+        if (!staged) {
+            P = stage_poly(J.Ls.poly, spoly);
+            staged = true;
+        }
+        walk_left(need, t, [&](int item, int lane) {
+            if (J.dir == 0) swept_chain<0>(a.g, J, P, a.mot, S, item, lane);
+            else swept_chain<1>(a.g, J, P, a.mot, S, item, lane);
+        });
+    }
     __syncthreads();  // the staged polygon may be overwritten next
 }
 
@@ -262,11 +280,23 @@ __device__ __forceinline__ void stagewall_body(const StepArgs& a, int s, int t) 
     else stagewall<1, R>(a.g, J, a.mot, S, a.C, a.status, a.step_id, t);
 }
 
+// Box cells t, t + stride, ... of sweep s (the launch grid is capped; at least the first
+// call runs, which clears the sweep's counters).
+template <typename R>
+__device__ __forceinline__ void stagewall_loop(const StepArgs& a, int s, int t, int stride) {
+    const SweepJob& J = a.sw[s];
+    int cells = box_empty_dev(J.B) ? 0 : J.B.w() * J.B.h();
+    do {
+        stagewall_body<R>(a, s, t);
+        t += stride;
+    } while (t < cells);
+}
+
 template <typename R>
 __global__ __launch_bounds__(T_BOX) void kb_stagewall(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                       int n, int s) {
     Unit w = unit_of(off, n);
-    stagewall_body<R>(A[w.u], s, w.lb * T_BOX + threadIdx.x);
+    stagewall_loop<R>(A[w.u], s, w.lb * T_BOX + threadIdx.x, w.nb * T_BOX);
 }
 
 
@@ -282,7 +312,10 @@ __global__ __launch_bounds__(PL_T) void kb_patch_lines(const StepArgs* __restric
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
     if (J.dir != D || box_empty_dev(J.B)) return;
-    patch_line<D, R>(a.g, J, stage_of(a, s), a.ncol, w.lb, sh, a.bs);
+    int len = D == 0 ? J.B.w() : J.B.h(), nlines = D == 0 ? J.B.h() : J.B.w();
+    int total = nlines * ((len + PL_OUT - 1) / PL_OUT);
+    for (int lb = w.lb; lb < total; lb += w.nb)  // the grid is capped: several segments per block
+        patch_line<D, R>(a.g, J, stage_of(a, s), a.ncol, lb, sh, a.bs);
 }
 
 template <typename R>
@@ -297,19 +330,21 @@ __global__ __launch_bounds__(T_BOX) void kb_cover(const StepArgs* __restrict__ A
     Unit w = unit_of(off, n);
     const StepArgs& a = A[w.u];
     const SweepJob& J = a.sw[s];
-    int t = w.lb * T_BOX + threadIdx.x;
-    if (!box_empty_dev(J.B)) {
+    int cells = box_empty_dev(J.B) ? 0 : J.B.w() * J.B.h();
+    // 64 cells (one wavefront, one partial slot) at a time; the grid is capped
+    for (int base = w.lb * T_BOX; base < cells; base += w.nb * T_BOX) {
+        int t = base + threadIdx.x;
         double lost[4] = {0.0, 0.0, 0.0, 0.0};
         cover<R>(a.g, J, a.S, t, lost, a.bs.base != nullptr);
         if (a.bs.base) {  // T_BOX is one wavefront
 #pragma unroll
             for (int m = 0; m < 4; m++) {
                 double v = wave_sum(lost[m]);
-                if (threadIdx.x == 0) a.bs.base[a.bs.cover + 4 * w.lb + m] = v;
+                if (threadIdx.x == 0) a.bs.base[a.bs.cover + 4 * (base >> 6) + m] = v;
             }
         }
+        if (speeds) box_speeds<R>(a, s, t);  // reads back the thread's own cell
     }
-    if (speeds) box_speeds<R>(a, s, t);  // reads back the thread's own cell
 }
 
 // fold: 1 when the sweep is the last of a captured step: every tile also writes the
@@ -383,7 +418,7 @@ __global__ __launch_bounds__(DX_T) __attribute__((amdgpu_waves_per_eu(4))) void 
     __shared__ R lds[dense_x_lds<R>() / sizeof(R)];
     if ((int)blockIdx.x < nwall) {
         Unit w = unit_at(off_wall, n, blockIdx.x);
-        stagewall_body<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x);
+        stagewall_loop<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x, w.nb * T_WIDE);
         return;
     }
     dense_x_block<R, RB>(A, off, n, blockIdx.x - nwall, s, fold, lds);
@@ -395,7 +430,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ R lds[DenseYTile<R, TR>::lds_bytes / sizeof(R)];
     if ((int)blockIdx.x < nwall) {
         Unit w = unit_at(off_wall, n, blockIdx.x);
-        stagewall_body<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x);
+        stagewall_loop<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x, w.nb * T_WIDE);
         return;
     }
     dense_y_block<R, TR>(A, off, n, blockIdx.x - nwall, s, fold, lds);
@@ -407,7 +442,7 @@ __global__ __launch_bounds__(DYC_T) __attribute__((amdgpu_waves_per_eu(4))) void
     int s, int fold) {
     if ((int)blockIdx.x < nwall) {
         Unit w = unit_at(off_wall, n, blockIdx.x);
-        stagewall_body<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x);
+        stagewall_loop<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x, w.nb * T_WIDE);
         return;
     }
     dense_yc_block<R, RW>(A, off, n, blockIdx.x - nwall, s, fold);
@@ -557,8 +592,10 @@ __global__ __launch_bounds__(T_FIX) void kb_fix_block(StepArgs* A, const int* __
         }
     }
     const int* od = a.sw[1].dir == 0 ? off_dx : off_dy;
-    // with recomputed box speeds the box blocks' partials (of the covered state) are skipped
-    combine_speeds(a, od[u + 1] - od[u], bad ? 0 : off_box[u + 1] - off_box[u], gather, u, bx, by);
+    // with recomputed box speeds the box cells' partials (of the covered state) are skipped;
+    // otherwise one pair per 64 box cells
+    combine_speeds(a, od[u + 1] - od[u], bad ? 0 : (cells + T_BOX - 1) / T_BOX, gather, u, bx, by);
+    (void)off_box;
     const PlanConst* pc = a.pc;
     PlanState* ps = a.ps;
     double* dl = a.dtlog;
