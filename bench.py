@@ -156,16 +156,17 @@ def accuracy(w, nsteps):
     s32 = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP32_GEOM64)
     s32.set_prim(w["prim"])
     s32.set_budget(True)
-    T0 = s32.totals()
+    T0 = {"f32": s32.totals()}
     dts, _ = s32.advance(nsteps, w["cfl"])
     s64 = cc.Solver(w["grid"], w["body"], precision=cc.CC_FP64)
     s64.set_prim(w["prim"])
     s64.set_budget(True)
+    T0["f64"] = s64.totals()
     for dt in dts:
         s64.step(dt)
     for name, s in (("f32", s32), ("f64", s64)):
         T1, (bnd, wall, lost) = cc.cc_totals(s.ctx, True)
-        res[name] = abs((T1[0] - T0[0]) - bnd[0] - wall[0] + lost[0]) / T0[0]
+        res[name] = abs((T1[0] - T0[name][0]) - bnd[0] - wall[0] + lost[0]) / T0[name][0]
     al = s64.geometry_dump(0)["alpha"]
     U32, U64 = s32.get_u(), s64.get_u()
     m = (al > 0) & (U64[0] > 0) & (U32[0] > 0)
