@@ -77,7 +77,7 @@ struct Layout {
     int bs_patch, bs_cover;  // offsets (doubles) of the patch and covering budget slots
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
-    int spd_dense;   // partial speed pairs reserved for dense tiles (the most any tile shape uses)
+    int spd_dense;   // speed slot pairs the dense tiles share (NSPD)
     int gw, gh;      // geometry-region capacity (cells)
 };
 
@@ -180,7 +180,7 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_ncol = take(4);
     L.off_part = take(std::max<size_t>(4 * NPART * 8, 2 * CFL_MAX_BLOCKS * 8));
     L.off_tot = take(4 * 8);
-    L.spd_dense = std::max(dense_blocks(0, 0, c->nx, c->ny), dense_blocks(1, 0, c->nx, c->ny));
+    L.spd_dense = NSPD;
     L.off_spd = take((size_t)2 * 8 * ((size_t)L.spd_dense + (std::max<size_t>(L.cap, 1) + T_BOX - 1) / T_BOX));
     L.off_pconst = take(sizeof(PlanConst));
     L.off_pstate = take(sizeof(PlanState));
@@ -1184,6 +1184,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_sync, 0, sizeof(GridSync), c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_nbad, 0, 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_smax, 0, 16, c->stream);
+    // the dense tiles' speed slots start at zero (every combine leaves them so)
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_spd, 0, (size_t)16 * NSPD, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_status, 0, 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_ncol, 0, 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + lay.off_budget, 0, 16 * 8, c->stream);

@@ -29,8 +29,9 @@ struct StepArgs {
     int32_t step_id;
     // wave-speed maxima of the state after the step
     unsigned long long* cfl_out;   // 2: max (|u|+a) along x and y, as bit patterns
-    unsigned long long* spd;       // partial maxima of a captured step: a pair per dense tile of
-    int spd_dense;                 // the second sweep, then (from pair spd_dense on) per box block
+    unsigned long long* spd;       // partial maxima of a captured step: NSPD slot pairs the dense
+    int spd_dense;                 // tiles of the second sweep share, then (from pair spd_dense
+                                   // on) a pair per box block
     // a device-planned run: the block that combines the wave speeds also plans the next
     // step (null otherwise)
     const PlanConst* pc;
@@ -95,28 +96,51 @@ __device__ __forceinline__ Stage stage_of(const StepArgs& a, int s) {
     return S;
 }
 
-// The polygon of a block, staged in LDS when it fits (every wavefront of the block walks
-// all its edges for each of its items).
+// The polygon of a block, staged in LDS (at most LDS_VERTS vertices, which cc_create
+// checks; every item of the block left to an edge loop or a chain search reads it many
+// times).  A thread has four vertex loads (16 bytes each) in flight at a time.
 constexpr int LDS_VERTS = 2048;
 constexpr size_t POLY_LDS = (size_t)2 * LDS_VERTS * sizeof(double);
 __device__ __forceinline__ Poly stage_poly(const Poly& P, double* spoly) {
     Poly Q = P;
-    if (P.m <= LDS_VERTS) {
-        for (int k = threadIdx.x; k < 2 * P.m; k += blockDim.x) spoly[k] = P.v[k];
-        __syncthreads();
-        Q.v = spoly;
+    const double2* src = reinterpret_cast<const double2*>(P.v);
+    double2* dst = reinterpret_cast<double2*>(spoly);
+    int m = P.m, nt = blockDim.x;
+    for (int k0 = threadIdx.x; k0 < m; k0 += 4 * nt) {
+        int k1 = k0 + nt, k2 = k0 + 2 * nt, k3 = k0 + 3 * nt;
+        double2 a0 = src[k0], a1, a2, a3;
+        if (k1 < m) a1 = src[k1];
+        if (k2 < m) a2 = src[k2];
+        if (k3 < m) a3 = src[k3];
+        dst[k0] = a0;
+        if (k1 < m) dst[k1] = a1;
+        if (k2 < m) dst[k2] = a2;
+        if (k3 < m) dst[k3] = a3;
     }
+    __syncthreads();
+    Q.v = spoly;
     return Q;
 }
 
-// The polygon of level job J posed in LDS (at most LDS_VERTS vertices, which cc_create
-// checks), with the same formula as the copy in the level.
+// The polygon of level job J posed in LDS, with the same formula as the copy in the level.
 __device__ __forceinline__ Poly pose_lds(const GeoJob& J, double* spoly) {
     Poly Q = J.L.poly;
-    for (int k = threadIdx.x; k < Q.m; k += blockDim.x) {
-        double bx = J.body[2 * k], by = J.body[2 * k + 1];
-        spoly[2 * k] = (J.cs_x * bx - J.sn_x * by) + J.cx_x;
-        spoly[2 * k + 1] = (J.sn_y * bx + J.cs_y * by) + J.cy_y;
+    const double2* src = reinterpret_cast<const double2*>(J.body);
+    double2* dst = reinterpret_cast<double2*>(spoly);
+    int m = Q.m, nt = blockDim.x;
+    auto pose = [&](double2 b) {
+        return make_double2((J.cs_x * b.x - J.sn_x * b.y) + J.cx_x, (J.sn_y * b.x + J.cs_y * b.y) + J.cy_y);
+    };
+    for (int k0 = threadIdx.x; k0 < m; k0 += 4 * nt) {
+        int k1 = k0 + nt, k2 = k0 + 2 * nt, k3 = k0 + 3 * nt;
+        double2 a0 = src[k0], a1, a2, a3;
+        if (k1 < m) a1 = src[k1];
+        if (k2 < m) a2 = src[k2];
+        if (k3 < m) a3 = src[k3];
+        dst[k0] = pose(a0);
+        if (k1 < m) dst[k1] = pose(a1);
+        if (k2 < m) dst[k2] = pose(a2);
+        if (k3 < m) dst[k3] = pose(a3);
     }
     __syncthreads();
     Q.v = spoly;
@@ -129,9 +153,9 @@ __device__ __forceinline__ Poly pose_lds(const GeoJob& J, double* spoly) {
 // lanes drew several boundary items shares them with the others: the slowest wavefront
 // walks ceil(items / wavefronts) of them.  Every thread of the block (at most T_WIDE)
 // calls it.  walk(item, lane).
-template <class W>
-__device__ __forceinline__ void walk_left(bool need, int t, W&& walk) {
-    __shared__ int items[T_WIDE];
+// The block's items with need set, listed in LDS (wavefront by wavefront, lanes in order);
+// returns their count.  Every thread of the block calls it.
+__device__ __forceinline__ int list_left(bool need, int t, int* items) {
     __shared__ int wcount[T_WIDE / WAVE];
     int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
     unsigned long long mask = __ballot(need);
@@ -145,7 +169,23 @@ __device__ __forceinline__ void walk_left(bool need, int t, W&& walk) {
     }
     if (need) items[base + __popcll(mask & ((1ull << lane) - 1ull))] = t;
     __syncthreads();
+    return total;
+}
+template <class W>
+__device__ __forceinline__ void walk_left(bool need, int t, W&& walk) {
+    __shared__ int items[T_WIDE];
+    int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    int total = list_left(need, t, items);
     for (int q = wv; q < total; q += nw) walk(items[q], lane);
+    __syncthreads();  // the list may be rebuilt by the next call
+}
+// The same list taken one item per thread, packed into the block's first wavefronts (so that
+// few lanes of a wavefront idle beside the ones with items).  each(item).
+template <class E>
+__device__ __forceinline__ void each_left(bool need, int t, E&& each) {
+    __shared__ int items[T_WIDE];
+    int total = list_left(need, t, items);
+    if ((int)threadIdx.x < total) each(items[threadIdx.x]);
     __syncthreads();  // the list may be rebuilt by the next call
 }
 
@@ -157,11 +197,17 @@ __device__ __forceinline__ int spread_item(int lb, int nb) {
     return (int)(threadIdx.x & (WAVE - 1)) * waves + lb * (T_WIDE / WAVE) + (int)(threadIdx.x / WAVE);
 }
 
+// A block's items left to a chain search go one per thread when at least this many are
+// left (and the chains are monotone), else one at a time to a wavefront: a thread's
+// bisections and edge run take several times a wavefront's latency for one item, but run
+// side by side.
+constexpr int THREAD_ITEMS = 32;
+
 // Stage K of level job lev (0: vertex classes, 1: face intervals, 2: volume fractions; each
 // needs the previous one), block lb of the job's nb: one thread per item.  Items the quick
-// tests leave open on a many-sided polygon are finished by the wavefront that holds them,
-// with the polygon staged in LDS: faces and cells by chain search, vertex classes by walks
-// over all edges.  The whole block calls it.
+// tests leave open on a many-sided polygon are finished with the polygon staged in LDS:
+// vertex classes a tile of vertices per wavefront (geo_vertex_tile), faces and cells by
+// chain search (THREAD_ITEMS).  The whole block calls it.
 // The job's items are taken nb T_WIDE at a time (the launch grid is capped, so a large
 // region takes several passes).
 template <int K>
@@ -172,25 +218,46 @@ __device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int 
     // level's copy is written in this launch, by the first block, for the later stages)
     Poly P = J.L.poly;
     bool staged = false;
+    int mono = -1;  // the chains are monotone: 1, not: 0, not checked: -1
     if (K == 0) {
         if (lb == 0)
             for (int k = threadIdx.x; k < J.L.poly.m; k += blockDim.x) geo_pose(J, k);
         P = pose_lds(J, spoly);
         staged = true;
+        if (P.m > SMALL_POLY) {
+            __shared__ __attribute__((aligned(16))) unsigned short unc[T_WIDE / WAVE][UNC_CAP];
+            int wv = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
+            int tiles = geo_vertex_tiles(J.reg);
+            for (int q = lb * nwv + wv; q < tiles; q += nb * nwv)
+                geo_vertex_tile(a.g, J, P, q, unc[wv], threadIdx.x & (WAVE - 1));
+            __syncthreads();  // the staged polygon may be overwritten next
+            return;
+        }
     }
     int items = K == 0 ? geo_nverts(J.reg) : (K == 1 ? geo_nfaces(J.reg) : J.reg.w() * J.reg.h());
     for (int base = 0; base < items; base += nb * T_WIDE) {
         int t = spread_item(lb, nb) + base;
         bool need = K == 0 ? geo_vertices1(a.g, J, P, t) : (K == 1 ? geo_faces1(a.g, J, t) : geo_cells1(a.g, J, t));
-        if (!__syncthreads_or(need)) continue;
+        int nneed = __syncthreads_count(need);
+        if (nneed == 0) continue;
         if (!staged) {
             P = stage_poly(J.L.poly, spoly);
             staged = true;
         }
+        Poly Pl = P;
+        Pl.v = spoly;  // the staged copy (known to be in LDS)
+        if (nneed >= THREAD_ITEMS && mono < 0) mono = chains_monotone(Pl);  // checked once, when needed
+        if (mono > 0 && nneed >= THREAD_ITEMS) {
+            each_left(need, t, [&](int item) {
+                if (K == 1) geo_face_thread(a.g, J, Pl, item);
+                if (K == 2) geo_cell_thread(a.g, J, Pl, item);
+            });
+            continue;
+        }
         walk_left(need, t, [&](int item, int lane) {
-            if (K == 0) geo_vertex_walk(a.g, J, P, item, lane);
-            if (K == 1) geo_face_chain(a.g, J, P, item, lane);
-            if (K == 2) geo_cell_chain(a.g, J, P, item, lane);
+            if (K == 0) geo_vertex_walk(a.g, J, Pl, item, lane);
+            if (K == 1) geo_face_chain(a.g, J, Pl, item, lane);
+            if (K == 2) geo_cell_chain(a.g, J, Pl, item, lane);
         });
     }
     __syncthreads();  // the staged polygon may be overwritten next
@@ -208,7 +275,7 @@ __device__ __forceinline__ void geo_stage_split(const StepArgs& a, int lb, int n
 // Stage K of both level jobs of every member.
 template <int K>
 __global__ __launch_bounds__(T_WIDE) void kb_geo(const StepArgs* __restrict__ A, const int* __restrict__ off, int n) {
-    __shared__ double spoly[2 * LDS_VERTS];
+    __shared__ __attribute__((aligned(16))) double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
     geo_stage_split<K>(A[w.u], w.lb, w.nb, spoly);
 }
@@ -219,26 +286,37 @@ __device__ __forceinline__ bool box_empty_dev(const Box& B) { return B.i0 >= B.i
 __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, int nb, double* spoly);
 
 // Time-averaged apertures of sweep s over the faces of block lb (of nb) of the sweep box;
-// faces left open by the quick tests on a many-sided polygon by their wavefront's chain
-// search.
+// faces left open by the quick tests on a many-sided polygon by chain search (THREAD_ITEMS).
 __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, int nb, double* spoly) {
     const SweepJob& J = a.sw[s];
     if (box_empty_dev(J.B)) return;
     Stage S = stage_of(a, s);
     int items = J.dir == 0 ? (J.B.w() + 1) * J.B.h() : J.B.w() * (J.B.h() + 1);
     bool staged = false;
+    int mono = -1;
     Poly P = J.Ls.poly;
     for (int base = 0; base < items; base += nb * T_WIDE) {  // the grid is capped: several passes
         int t = spread_item(lb, nb) + base;
         bool need = J.dir == 0 ? swept1<0>(a.g, J, a.mot, S, t) : swept1<1>(a.g, J, a.mot, S, t);
-        if (!__syncthreads_or(need)) continue;
+        int nneed = __syncthreads_count(need);
+        if (nneed == 0) continue;
         if (!staged) {
             P = stage_poly(J.Ls.poly, spoly);
             staged = true;
         }
+        Poly Pl = P;
+        Pl.v = spoly;  // the staged copy (known to be in LDS)
+        if (nneed >= THREAD_ITEMS && mono < 0) mono = chains_monotone(Pl);  // checked once, when needed
+        if (mono > 0 && nneed >= THREAD_ITEMS) {
+            each_left(need, t, [&](int item) {
+                if (J.dir == 0) swept_thread<0>(a.g, J, Pl, a.mot, S, item);
+                else swept_thread<1>(a.g, J, Pl, a.mot, S, item);
+            });
+            continue;
+        }
         walk_left(need, t, [&](int item, int lane) {
-            if (J.dir == 0) swept_chain<0>(a.g, J, P, a.mot, S, item, lane);
-            else swept_chain<1>(a.g, J, P, a.mot, S, item, lane);
+            if (J.dir == 0) swept_chain<0>(a.g, J, Pl, a.mot, S, item, lane);
+            else swept_chain<1>(a.g, J, Pl, a.mot, S, item, lane);
         });
     }
     __syncthreads();  // the staged polygon may be overwritten next
@@ -246,7 +324,7 @@ __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, in
 
 __global__ __launch_bounds__(T_WIDE) void kb_swept(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                    int n, int s) {
-    __shared__ double spoly[2 * LDS_VERTS];
+    __shared__ __attribute__((aligned(16))) double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
     swept_block(A[w.u], s, w.lb, w.nb, spoly);
 }
@@ -257,7 +335,7 @@ __global__ __launch_bounds__(T_WIDE) void kb_swept(const StepArgs* __restrict__ 
 // nb_swept the second sweep's.
 __global__ __launch_bounds__(T_WIDE) void kb_geo_cells_swept(const StepArgs* __restrict__ A,
                                                              const int* __restrict__ off, int n) {
-    __shared__ double spoly[2 * LDS_VERTS];
+    __shared__ __attribute__((aligned(16))) double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
     const StepArgs& a = A[w.u];
     int lb = w.lb;
@@ -478,9 +556,16 @@ __device__ __forceinline__ void box_speeds(const StepArgs& a, int s, int t) {
 // collapse count gathered for one read-back.  Every thread of the block calls it.
 __device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, int nbox, unsigned int* gather, int u,
                                                unsigned long long bx = 0ull, unsigned long long by = 0ull) {
-    for (int k = threadIdx.x; k < ndense + nbox; k += blockDim.x) {
-        int q = k < ndense ? k : a.spd_dense + (k - ndense);
+    // the dense tiles used slot pairs 0 .. min(ndense, NSPD) - 1; each is read and reset to
+    // zero by one thread, ready for the next step
+    int nd = ndense < NSPD ? ndense : NSPD;
+    for (int k = threadIdx.x; k < nd + nbox; k += blockDim.x) {
+        int q = k < nd ? k : a.spd_dense + (k - nd);
         unsigned long long x = a.spd[2 * q], y = a.spd[2 * q + 1];
+        if (k < nd) {
+            a.spd[2 * q] = 0ull;
+            a.spd[2 * q + 1] = 0ull;
+        }
         bx = x > bx ? x : bx;
         by = y > by ? y : by;
     }

@@ -405,6 +405,130 @@ __device__ double2 poly_seg_clip_chains(const Poly& P, double ax, double ay, dou
     return make_double2(tl, th);
 }
 
+// ------------------------------------------------------------------ one thread per item
+// The chain searches above done by one thread (bisection) instead of a wavefront, for a
+// polygon whose four chains are monotone in its stored coordinates (chains_monotone).  A
+// predicate that is false and then true along such a chain has one first true position,
+// which every search finds, so each item is given the edges the wavefront search gives it.
+
+// First position q in [0, len] of the chain from vertex a at which pred holds, len + 1 when
+// it never holds (pred false and then true along the chain).
+template <class F>
+__device__ __forceinline__ int chain_first_seq(const Poly& P, int a, int len, F&& pred) {
+    int lo = 0, hi = len + 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (pred(chain_vertex(P, a, mid))) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// True when y never decreases from ib to it nor increases from it back to ib, and x never
+// decreases from il to ir nor increases from ir back to il, in the stored coordinates (a
+// posed convex polygon can lose this by rounding where neighbouring vertices are almost
+// level).  Every thread of the block calls it.
+__device__ __forceinline__ bool chains_monotone(const Poly& P) {
+    const double* v = P.v;
+    int ly = chain_edges(P, P.ib, P.it), lx = chain_edges(P, P.il, P.ir);
+    int bad = 0;
+    for (int k = threadIdx.x; k < P.m; k += blockDim.x) {
+        int k1 = k + 1 == P.m ? 0 : k + 1;
+        int qy = k - P.ib, qx = k - P.il;
+        qy += qy < 0 ? P.m : 0;
+        qx += qx < 0 ? P.m : 0;
+        double y0 = v[2 * k + 1], y1 = v[2 * k1 + 1], x0 = v[2 * k], x1 = v[2 * k1];
+        bool oky = qy < ly ? y1 >= y0 : y1 <= y0;
+        bool okx = qx < lx ? x1 >= x0 : x1 <= x0;
+        bad |= !(oky && okx);
+    }
+    return !__syncthreads_or(bad);
+}
+
+// poly_clip_area_chains by one thread: the same crossings and runs of edges; the edge
+// contributions are summed in chain order.
+__device__ double poly_clip_area_chains_t(const Poly& P, double ox, double oy, double w, double h) {
+    const double* v = P.v;
+    auto X = [&](int k) { return v[2 * k] - ox; };
+    auto Y = [&](int k) { return v[2 * k + 1] - oy; };
+    double yb = -INFINITY, yt = INFINITY;
+    int found = 0;
+    for (int chain = 0; chain < 2; chain++) {
+        int a = chain == 0 ? P.il : P.ir, b = chain == 0 ? P.ir : P.il;
+        int len = chain_edges(P, a, b);
+        int q = chain_first_seq(P, a, len, [&](int k) { return chain == 0 ? !(X(k) < w) : X(k) < w; });
+        if (q > 0 && q <= len) {
+            int k = chain_vertex(P, a, q - 1), k1 = chain_vertex(P, a, q);
+            double ax = X(k), ay = Y(k), dx = X(k1) - ax, dy = Y(k1) - ay;
+            double t = (w - ax) / dx;
+            double y = ay + t * dy;
+            found = 1;
+            if (dx > 0.0) yb = fmax(yb, y);
+            else yt = fmin(yt, y);
+        }
+    }
+    double right_solid = 0.0;
+    if (found) {
+        double lo = fmax(0.0, yb), hi = fmin(h, yt);
+        right_solid = hi > lo ? hi - lo : 0.0;
+    }
+    double acc = 0.0;
+    for (int chain = 0; chain < 2; chain++) {
+        int a = chain == 0 ? P.ib : P.it, b = chain == 0 ? P.it : P.ib;
+        int len = chain_edges(P, a, b);
+        int q0 = chain_first_seq(P, a, len, [&](int k) { return chain == 0 ? !(Y(k) < 0.0) : !(Y(k) > h); });
+        int q1 = chain_first_seq(P, a, len, [&](int k) { return chain == 0 ? Y(k) > h : Y(k) < 0.0; });
+        int p0 = q0 > 0 ? q0 - 1 : 0, p1 = q1 - 1 < len - 1 ? q1 - 1 : len - 1;
+        for (int p = p0; p <= p1; p++) {
+            int k = chain_vertex(P, a, p), k1 = chain_vertex(P, a, p + 1);
+            acc += edge_area(X(k), Y(k), X(k1), Y(k1), w, h);
+        }
+    }
+    return acc + w * right_solid;
+}
+
+// poly_seg_clip_chains by one thread: the same candidate edges, and the full edge loop
+// when the segment's line meets no chain crossing.
+__device__ double2 poly_seg_clip_chains_t(const Poly& P, double ax, double ay, double bx, double by) {
+    const double* v = P.v;
+    bool vertical = ax == bx;
+    double c = vertical ? ax : ay;
+    int cand[2] = {-1, -1};
+    for (int chain = 0; chain < 2; chain++) {
+        int a, b;
+        if (vertical) {
+            a = chain == 0 ? P.il : P.ir;
+            b = chain == 0 ? P.ir : P.il;
+        } else {
+            a = chain == 0 ? P.ib : P.it;
+            b = chain == 0 ? P.it : P.ib;
+        }
+        int len = chain_edges(P, a, b);
+        int q = chain_first_seq(P, a, len, [&](int k) {
+            bool below = (vertical ? v[2 * k] : v[2 * k + 1]) < c;
+            return chain == 0 ? !below : below;
+        });
+        if (q > 0 && q <= len) cand[chain] = chain_vertex(P, a, q - 1);
+    }
+    if (cand[0] < 0 && cand[1] < 0) return poly_seg_clip<1>(P, ax, ay, bx, by, 0);
+    double tl = 0.0, th = 1.0;
+    for (int e = 0; e < 6; e++) {
+        if (cand[e / 3] < 0) continue;
+        int k = cand[e / 3] + (e % 3) - 1;
+        k = k < 0 ? k + P.m : (k >= P.m ? k - P.m : k);
+        int k1 = k + 1 == P.m ? 0 : k + 1;
+        double ex = v[2 * k], ey = v[2 * k + 1], fx = v[2 * k1], fy = v[2 * k1 + 1];
+        double g0 = orient(ex, ey, fx, fy, ax, ay), g1 = orient(ex, ey, fx, fy, bx, by);
+        if (g0 < 0.0 && g1 < 0.0) return make_double2(0.0, 0.0);
+        if (g0 >= 0.0 && g1 >= 0.0) continue;
+        double t = g0 / (g0 - g1);
+        if (g0 < 0.0) tl = fmax(tl, t);
+        else th = fmin(th, t);
+    }
+    if (!(tl < th)) return make_double2(0.0, 0.0);
+    return make_double2(tl, th);
+}
+
 // ------------------------------------------------------------------ one level
 // Geometry job of one level: the destination slot and the cell region recomputed (its
 // vertices and faces are those of the region's closure).  The vertices are posed on the
@@ -449,6 +573,90 @@ __device__ __forceinline__ void geo_vertex_walk(const Grid& g, const GeoJob& J, 
     int i = J.reg.i0 + t % vw, j = J.reg.j0 + t / vw;
     int c = poly_classify<WAVE>(P, vx_of(g, i), vy_of(g, j), lane);
     if (lane == 0) J.L.vcls[(size_t)j * (g.nx + 1) + i] = (int8_t)c;
+}
+
+// Vertex classes of a many-sided polygon, VT x VT vertices of the region per wavefront.
+// Over the rectangle R spanned by a tile's vertices an edge's orientation value is affine
+// in the vertex, so its exact least and greatest values are taken at corners of R; its
+// rounding error is below 5 units in the last place of |dx| |py - ay| + |dy| |px - ax|,
+// which is greatest at a corner as well.  An edge whose corner values clear twice that
+// bound (with room to spare) is settled for the whole tile: negative at every vertex of R
+// (every vertex of the tile is fluid), or non-negative at all of them (it cannot make any
+// vertex fluid).  The tile's open vertices are then tested against the other edges only,
+// with the formula of the full test, so every class equals that of the full test.
+constexpr int VT = 8;
+constexpr int UNC_CAP = 512;  // edges a tile tests vertex by vertex; beyond: the full test
+__device__ void geo_vertex_tile(const Grid& g, const GeoJob& J, const Poly& P, int q, unsigned short* list,
+                                int lane) {
+    int vw = J.reg.w() + 1, vh = J.reg.h() + 1;
+    int ntx = (vw + VT - 1) / VT;
+    int ti = J.reg.i0 + (q % ntx) * VT, tj = J.reg.j0 + (q / ntx) * VT;
+    int ie = min(ti + VT, J.reg.i0 + vw) - 1, je = min(tj + VT, J.reg.j0 + vh) - 1;  // last vertex of the tile
+    int i = ti + lane % VT, j = tj + lane / VT;
+    bool act = i <= ie && j <= je;
+    double px = vx_of(g, i), py = vy_of(g, j);
+    int c = act ? classify_quick(P, px, py) : FLUID;
+    bool need = act && c < 0;
+    if (__any(need)) {
+        double x0 = vx_of(g, ti), x1 = vx_of(g, ie), y0 = vy_of(g, tj), y1 = vy_of(g, je);
+        const double* v = P.v;
+        int cnt = 0;
+        bool neg = false;
+        for (int base = 0; base < P.m; base += WAVE) {
+            int k = base + lane;
+            int cls = 0;  // 0: non-negative on R, 1: undecided, 2: negative on R
+            if (k < P.m) {
+                int k1 = k + 1 == P.m ? 0 : k + 1;
+                double ax = v[2 * k], ay = v[2 * k + 1], bx = v[2 * k1], by = v[2 * k1 + 1];
+                double o00 = orient(ax, ay, bx, by, x0, y0), o10 = orient(ax, ay, bx, by, x1, y0);
+                double o01 = orient(ax, ay, bx, by, x0, y1), o11 = orient(ax, ay, bx, by, x1, y1);
+                double my = fmax(fabs(y0 - ay), fabs(y1 - ay)), mx = fmax(fabs(x0 - ax), fabs(x1 - ax));
+                double thr = (fabs(bx - ax) * my + fabs(by - ay) * mx) * 0x1p-48;
+                double lo = fmin(fmin(o00, o10), fmin(o01, o11)), hi = fmax(fmax(o00, o10), fmax(o01, o11));
+                cls = lo > thr ? 0 : (hi < -thr ? 2 : 1);
+            }
+            neg = neg || __any(cls == 2);
+            unsigned long long mk = __ballot(cls == 1);
+            int pos = cnt + __popcll(mk & ((1ull << lane) - 1ull));
+            if (cls == 1 && pos < UNC_CAP) list[pos] = (unsigned short)k;
+            cnt += __popcll(mk);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (need) {
+            if (neg) {
+                c = FLUID;
+            } else if (cnt <= UNC_CAP) {
+                // eight edges a round (their loads in flight together), the rest one by one
+                bool out = false;
+                int r = 0;
+                for (; r + 8 <= cnt && !out; r += 8) {
+                    uint4 w4 = *reinterpret_cast<const uint4*>(list + r);
+                    unsigned int wd[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        int k = (int)((wd[e >> 1] >> (16 * (e & 1))) & 0xffffu);
+                        int k1 = k + 1 == P.m ? 0 : k + 1;
+                        out |= orient(v[2 * k], v[2 * k + 1], v[2 * k1], v[2 * k1 + 1], px, py) < 0.0;
+                    }
+                }
+                for (; r < cnt && !out; r++) {
+                    int k = list[r];
+                    int k1 = k + 1 == P.m ? 0 : k + 1;
+                    out = orient(v[2 * k], v[2 * k + 1], v[2 * k1], v[2 * k1 + 1], px, py) < 0.0;
+                }
+                c = out ? FLUID : SOLID;
+            } else {
+                c = poly_classify<1>(P, px, py, 0);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // the list is rewritten by the wavefront's next tile
+    }
+    if (act) J.L.vcls[(size_t)j * (g.nx + 1) + i] = (int8_t)c;
+}
+__device__ __forceinline__ int geo_vertex_tiles(const Box& r) {
+    return ((r.w() + 1 + VT - 1) / VT) * ((r.h() + 1 + VT - 1) / VT);
 }
 
 // Face t of the region closure: x-faces first, then y-faces.
@@ -508,6 +716,15 @@ __device__ __forceinline__ void geo_face_chain(const Grid& g, const GeoJob& J, c
     if (lane == 0) geo_store_face(g, J, xf, i, j, iv);
 }
 
+// The same face by its own thread (a polygon with monotone chains).
+__device__ __forceinline__ void geo_face_thread(const Grid& g, const GeoJob& J, const Poly& P, int t) {
+    bool xf;
+    int i, j, ca, cb;
+    double ax, ay, bx, by;
+    geo_face_ends(g, J, t, xf, i, j, ax, ay, ca, bx, by, cb);
+    geo_store_face(g, J, xf, i, j, poly_seg_clip_chains_t(P, ax, ay, bx, by));
+}
+
 // Volume fractions: open when all four faces are open, closed when all four are closed,
 // otherwise 1 - (polygon area in the cell)/(hx hy); cut cells below the small-cell
 // threshold count as solid.  true = left to the chain search of a many-sided polygon.
@@ -549,6 +766,13 @@ __device__ __forceinline__ void geo_cell_chain(const Grid& g, const GeoJob& J, c
     int i = J.reg.i0 + t % cw, j = J.reg.j0 + t / cw;
     double s = poly_clip_area_chains(P, vx_of(g, i), vy_of(g, j), g.hx, g.hy, lane);
     if (lane == 0) J.L.alpha[(size_t)j * g.nx + i] = alpha_of_area(g, s);
+}
+
+// The same cell by its own thread (a polygon with monotone chains).
+__device__ __forceinline__ void geo_cell_thread(const Grid& g, const GeoJob& J, const Poly& P, int t) {
+    int cw = J.reg.w();
+    int i = J.reg.i0 + t % cw, j = J.reg.j0 + t / cw;
+    J.L.alpha[(size_t)j * g.nx + i] = alpha_of_area(g, poly_clip_area_chains_t(P, vx_of(g, i), vy_of(g, j), g.hx, g.hy));
 }
 
 }  // namespace cc

@@ -165,6 +165,19 @@ __device__ void swept_chain(const Grid& g, const SweepJob& J, const Poly& P, con
     if (lane == 0) S.bt[fidx<D>(B, i, j)] = strip_beta(a, st);
 }
 
+// The same face by its own thread (a start polygon with monotone chains).
+template <int D>
+__device__ void swept_thread(const Grid& g, const SweepJob& J, const Poly& P, const Motion& M, const Stage& S,
+                             int t) {
+    const Box& B = J.B;
+    int fw = D == 0 ? B.w() + 1 : B.w();
+    int i = B.i0 + t % fw, j = B.j0 + t / fw;
+    double r;
+    Strip st;
+    swept_quick<D>(g, J, M, i, j, r, st);
+    S.bt[fidx<D>(B, i, j)] = strip_beta(poly_clip_area_chains_t(P, st.x0, st.y0, st.sw, st.sh), st);
+}
+
 // ------------------------------------------------------------------ stage (donations)
 // Oracle-order neighbour offsets: four face neighbours, then the diagonals.
 __constant__ int c_d8[8][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {1, -1}, {-1, 1}, {1, 1}};
@@ -1044,9 +1057,16 @@ __device__ __forceinline__ void wave_max_pair(unsigned long long& bx, unsigned l
     }
 }
 
+// Dense tiles fold their speed maxima into this many shared slot pairs per member (tile lb
+// into pair lb mod NSPD) with atomic maxima; the block that combines them resets them to
+// zero, so between steps every slot holds zero.  The maximum does not depend on the order.
+constexpr int NSPD = 256;
+
 // Block maximum of a per-thread bit-pattern pair, written by thread 0 to out[0..1] (a
-// block's own slot: no atomics).  Every thread of the block calls it.
-__device__ __forceinline__ void block_max_to(unsigned long long bx, unsigned long long by, unsigned long long* out) {
+// block's own slot), or merged into them with atomic maxima (atomic: a shared slot).
+// Every thread of the block calls it.
+__device__ __forceinline__ void block_max_to(unsigned long long bx, unsigned long long by, unsigned long long* out,
+                                             bool atomic = false) {
     __shared__ unsigned long long sx_[16], sy_[16];
     wave_max_pair(bx, by);
     int w = threadIdx.x >> 6;
@@ -1060,14 +1080,19 @@ __device__ __forceinline__ void block_max_to(unsigned long long bx, unsigned lon
             bx = sx_[q] > bx ? sx_[q] : bx;
             by = sy_[q] > by ? sy_[q] : by;
         }
-        out[0] = bx;
-        out[1] = by;
+        if (atomic) {
+            atomicMax(out, bx);
+            atomicMax(out + 1, by);
+        } else {
+            out[0] = bx;
+            out[1] = by;
+        }
     }
     __syncthreads();
 }
 
-// Running maxima of the regular cells' speeds a dense tile writes, flushed as the block's
-// partial pair of FP64 bit patterns.  FP32 states keep 32-bit patterns until the flush (one
+// Running maxima of the regular cells' speeds a dense tile writes, merged into the block's
+// shared slot pair as FP64 bit patterns.  FP32 states keep 32-bit patterns until the flush (one
 // integer maximum per step of the wavefront reduction instead of a 64-bit compare and two
 // selects); the flushed pair equals the maximum of speed_bits over the same cells.
 template <typename R>
@@ -1079,7 +1104,7 @@ struct SpeedMax {
         x = bx > x ? bx : x;
         y = by > y ? by : y;
     }
-    __device__ __forceinline__ void flush(unsigned long long* out) { block_max_to(x, y, out); }
+    __device__ __forceinline__ void flush(unsigned long long* out) { block_max_to(x, y, out, true); }
 };
 template <>
 struct SpeedMax<float> {
@@ -1108,16 +1133,16 @@ struct SpeedMax<float> {
                 x = max(x, sx_[q]);
                 y = max(y, sy_[q]);
             }
-            out[0] = bits32_to_64(x);
-            out[1] = bits32_to_64(y);
+            atomicMax(out, bits32_to_64(x));
+            atomicMax(out + 1, bits32_to_64(y));
         }
         __syncthreads();
     }
 };
 
 // lds: dense_x_lds<T>() bytes; cfl: when not null, the maxima of the written cells' speeds
-// go to this block's partial pair cfl[2 lb .. 2 lb + 1]; bud: when not null, the budget
-// slots (the fluxes through the domain's low and high x-faces of the block's rows).
+// are merged into the slot pair (lb mod NSPD) of cfl; bud: when not null, the budget slots
+// (the fluxes through the domain's low and high x-faces of the block's rows).
 template <typename R, typename T, int RB>
 __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_, R* __restrict__ Uout_, Box B, T lam,
                                         int lb, T* lds, unsigned long long* cfl, double* bud = nullptr) {
@@ -1204,7 +1229,7 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_,
                 for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * j + 1) + m] = upd ? (double)sf[m][tid + 1] : 0.0;
         }
     }
-    if (cfl) sm.flush(cfl + 2 * lb);
+    if (cfl) sm.flush(cfl + 2 * (lb % NSPD));
     __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
@@ -1316,7 +1341,7 @@ __device__ __forceinline__ void dense_y(const Grid& g, const R* __restrict__ U_,
         for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
         if (cfl) sm.add(un, g.gamma);
     }
-    if (cfl) sm.flush(cfl + 2 * lb);
+    if (cfl) sm.flush(cfl + 2 * (lb % NSPD));
     __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
@@ -1397,7 +1422,7 @@ __device__ __forceinline__ void dense_yc(const Grid& g, const R* __restrict__ U_
             erp[m] = er[m];
         }
     }
-    if (cfl) sm.flush(cfl + 2 * lb);
+    if (cfl) sm.flush(cfl + 2 * (lb % NSPD));
 }
 
 }  // namespace cc
