@@ -49,7 +49,7 @@ typedef enum {
     CC_ERR_ARG = 1,         /* invalid argument or call order */
     CC_ERR_DEVICE = 2,      /* HIP runtime error */
     CC_ERR_WORKSPACE = 3,   /* workspace too small, or the body outgrew the staging capacity */
-    CC_ERR_STATE = 4,       /* non-finite/non-physical state or a cell without donors */
+    CC_ERR_STATE = 4,       /* non-finite/non-physical state, or a cut cell left inadmissible */
     CC_ERR_MOTION = 5,      /* the body moves one cell or more within a sweep, or dt <= 0 */
     CC_ERR_UNSUPPORTED = 6
 } cc_status;
@@ -202,8 +202,9 @@ cc_status cc_totals_state(const void* d_u, int32_t precision, int32_t nx, int32_
                           void* hip_stream, double* d_out4);
 
 /* Host info vector (n entries used, up to 10): time, steps, parity, device status bits
- * (1: a cell became fluid without donors; 2: a cell stayed inadmissible after collapsing;
- * 8: a grid-barrier wait of a persistent launch ran out),
+ * (1: a cell turned fluid, or was emptied, with no donor next to it — reported only: the
+ * cell keeps no content until a donor appears; 2: a cell stayed inadmissible after
+ * collapsing; 8: a grid-barrier wait of a persistent launch ran out; 2 and 8 are errors),
  * collapsed-cell count, sweep box cells of the last sweep, staging capacity, rows per block
  * of the dense x-sweep, rows per tile of the dense y-sweep, 1 if that sweep walks columns
  * (else 0).  Synchronizes. */

@@ -1549,8 +1549,10 @@ double dt_from_speeds(cc_ctx* c, double cfl, double sx, double sy) {
     return cfl * std::fmin(c->hx / sx, c->hy / sy);
 }
 
+// Status bit 1 (a cell turned fluid, or was emptied, with no donor next to it) is reported
+// but refuses nothing: such a cell keeps no content, its faces carry nothing, and it takes
+// content from the first donor that appears (the oracle runs on the same way).
 cc_status status_error(cc_ctx* c, unsigned int status, double sx, double sy) {
-    if (status & 1u) return fail(c, CC_ERR_STATE, "a cell became fluid without donor neighbours");
     if (status & 2u) return fail(c, CC_ERR_STATE, "a cut cell stayed inadmissible after two collapse rounds");
     if (status & 8u) return fail(c, CC_ERR_DEVICE, "a grid barrier of the persistent sweep timed out");
     if (!std::isfinite(sx) || !std::isfinite(sy)) return fail(c, CC_ERR_STATE, "non-finite or non-physical state");

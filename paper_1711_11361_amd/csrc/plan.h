@@ -245,7 +245,7 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
         halt = S.halt;
         if (!halt) {
             unsigned int st = __hip_atomic_load(P.base.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (st & (1u | 2u | 8u)) halt = HALT_STATUS;
+            if (st & (2u | 8u)) halt = HALT_STATUS;  // bit 1 is only reported
         }
         if (!halt && !(isfinite(sx) && isfinite(sy))) halt = HALT_SPEEDS;
     }

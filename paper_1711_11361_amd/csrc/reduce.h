@@ -157,12 +157,13 @@ __global__ __launch_bounds__(256) void k_cfl_final(int nparts, const unsigned lo
 // dt = cfl min(hx / Sx, hy / Sy) on the device from the reduced speed maxima (bit
 // patterns) and the body's largest vertex speeds along x and y (computed by the host for
 // the same time), with the host path's operations, so both give the same dt; 0 when the
-// state is not finite or the status word holds an error (bits 1, 2, 8).
+// state is not finite or the status word holds an error (bits 2 and 8; bit 1 is only a
+// report).
 __global__ void k_cfl_dt(const unsigned long long* __restrict__ smax, const unsigned int* __restrict__ status,
                          double wsx, double wsy, double hx, double hy, double cfl, double* __restrict__ out) {
     if (threadIdx.x != 0) return;
     double sx = __longlong_as_double((long long)smax[0]), sy = __longlong_as_double((long long)smax[1]);
-    bool bad = (*status & 11u) != 0u || !isfinite(sx) || !isfinite(sy);
+    bool bad = (*status & 10u) != 0u || !isfinite(sx) || !isfinite(sy);
     sx = fmax(sx, wsx);
     sy = fmax(sy, wsy);
     *out = bad ? 0.0 : cfl * fmin(hx / sx, hy / sy);

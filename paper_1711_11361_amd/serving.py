@@ -121,7 +121,7 @@ class Server:
                 self.batch.step([r.dt for r in active])
                 nxt, st2 = self.batch.last_dt(self.cfl)
                 for r, d, st in zip(active, nxt, st2):
-                    if st != 0 or not (d > 0):
+                    if (st & ~1) or not (d > 0):  # bit 0 is only reported
                         raise RuntimeError(f"request {r.rid}: device status {st}")
                     r.dt = d
             else:

@@ -70,6 +70,13 @@ def geometry_cases():
         yield f"triangle{seed}", W.triangle_case(seed, nx=96, ny=48)
     w = W.naca(nx=96, ny=96)
     yield "naca", w
+    # many edges per item: vertex tiles and chain searches one item per thread
+    w = W.naca(nx=512, ny=512)
+    w["body"]["pitch_amp"] = math.radians(8.0)
+    w["body"]["pitch_omega"] = 2.0
+    yield "naca_fine_pitch", w
+    # a 2048-gon a few cells across: more uncertain edges per vertex tile than the tile lists
+    yield "circle2048_coarse", W.cylinder(nx=32, ny=16, radius=0.3, n_poly=2048)
     for k in (0, 1, 2, 3, 7, 11):
         r = W.serving_request(k)
         yield f"req{k}", r
