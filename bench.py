@@ -363,24 +363,52 @@ def serving(n, budget_gib, slots):
 
     # first use of both modes (module load, graph capture paths) outside the measured runs
     for mode in ("batched", "plain"):
-        S.Server(mode, slots=4).run(S.make_requests(4, rate=1e9, steps=3, seed=99, first=10000))
+        srv = S.Server(mode, slots=4)
+        srv.run(S.make_requests(4, rate=1e9, steps=3, seed=99, first=10000))
+        srv.close()
     check = set(range(0, n, 16))  # requests whose end states are compared between the modes
     out = {}
     res = {}
     for mode in ("batched", "plain"):
         reqs = S.make_requests(n, rate=50.0, steps=500, seed=0)
         srv = S.Server(mode, budget_bytes=budget_gib * (1 << 30), slots=slots, keep_results=check)
-        out[mode] = srv.run(reqs)
+        try:
+            out[mode] = srv.run(reqs)
+        except Exception as e:  # reported in the line; the run releases its contexts first
+            out[mode] = {"error": f"{type(e).__name__}: {e}"}
+            return out
+        finally:
+            srv.close()
         res[mode] = {r.rid: r.result[0] for r in reqs if r.result is not None}
-    l1 = []
+    l1 = {}
     for rid in sorted(res["plain"]):
         a, b = res["batched"][rid].astype(np.float64), res["plain"][rid]
-        l1.append(float(np.abs(a - b).sum() / np.abs(b).sum()))
-    out["fp32_vs_fp64_l1_density"] = {"max": max(l1), "requests_compared": len(l1)}
+        den = np.abs(b).sum()
+        l1[rid] = float(np.abs(a - b).sum() / den) if den > 0 else float(np.abs(a).sum())
+    worst = max(l1, key=l1.get)
+    out["fp32_vs_fp64_l1_density"] = {"max": l1[worst], "worst_request": worst,
+                                      "median": float(np.median(list(l1.values()))),
+                                      "requests_compared": len(l1), "per_request": l1}
     out["speedup_cell_updates"] = out["batched"]["cell_updates_per_s"] / out["plain"]["cell_updates_per_s"]
     out["config"] = {"requests": n, "arrivals_per_s": 50.0, "steps_each": 500, "budget_gib": budget_gib,
                      "slots": slots}
     return out
+
+
+def serving_child(n, budget_gib, slots, timeout_s=900):
+    """The serving mix in a child process of its own (its own device context and memory
+    pool), so that whatever happens there cannot take the rest of the line with it."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--serving-only", "--serving", str(n), "--budget-gib",
+           str(budget_gib), "--slots", str(slots)]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        return {"error": f"serving run exceeded {timeout_s} s"}
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"serving run ended with status {r.returncode}", "stderr_tail": r.stderr[-2000:]}
+    return json.loads(lines[-1])
 
 
 def probe():
@@ -448,8 +476,10 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the legs of the other configurations")
     ap.add_argument("--legs", default="piston,triangle,naca,batched",
                     help="legs of the other configurations to run (comma list of piston, triangle, naca, batched)")
-    ap.add_argument("--serving", type=int, default=0,
-                    help="requests of the serving mix (0: skip)")
+    ap.add_argument("--serving", type=int, default=256,
+                    help="requests of the serving mix, run in a child process (0: skip)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving mix and print its JSON (the child of the default run)")
     ap.add_argument("--probe", action="store_true", help="dispatches for rocprofv3 counter runs only")
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--slots", type=int, default=64)
@@ -460,6 +490,9 @@ def main():
         sys.exit(2)
     if args.probe:
         probe()
+        return
+    if args.serving_only:
+        print(json.dumps(serving(args.serving, args.budget_gib, args.slots)), flush=True)
         return
     from paper_1711_11361_amd import cc
     from paper_1711_11361_amd import workloads as W
@@ -520,7 +553,8 @@ def main():
     if "batched" in legs:
         out["batched_copies"] = [batched(w, k, min(args.steps, 200), min(args.warmup, 20)) for k in (4, 16)]
     if args.serving > 0:
-        out["serving"] = serving(args.serving, args.budget_gib, args.slots)
+        out["serving"] = serving_child(args.serving, args.budget_gib, args.slots)
+        print("serving done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

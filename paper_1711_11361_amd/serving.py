@@ -66,6 +66,12 @@ class Server:
         self.time_scale = time_scale  # arrivals are replayed time_scale times faster
         self.batch = cc.Batch(slots, self.precision) if mode == "batched" else None
 
+    def close(self):
+        """Destroys the batch (every request must have been released)."""
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
+
     def _admit(self, r):
         if r.work["cfl"] != self.cfl:
             raise ValueError("every request of a server uses the server's CFL number")
@@ -86,9 +92,24 @@ class Server:
         r.solver = None
 
     def run(self, requests):
+        """Serves the requests to completion.  On an error every admitted request is
+        released (its context leaves the batch and is destroyed) before the error
+        propagates, so no device context outlives the call."""
+        active = []
+        try:
+            return self._run(requests, active)
+        except BaseException:
+            for r in active:
+                try:
+                    self._release(r)
+                except Exception:
+                    pass
+            raise
+
+    def _run(self, requests, active):
         import torch
         pending = sorted(requests, key=lambda r: r.arrival)
-        active, done = [], []
+        done = []
         used = 0
         lat = []
         peak = 0

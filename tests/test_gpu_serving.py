@@ -61,3 +61,25 @@ def test_plain_mode_matches_fp64_alone():
     assert rep["requests"] == 3
     for r in reqs:
         assert np.array_equal(r.result, alone(r, cc.CC_FP64)), r.rid
+
+
+def test_large_requests_the_same_alone_and_in_the_mix():
+    """The mix's larger grids (512 x 512 and 1024 x 512) under continuous batching."""
+    out, k = [], 0
+    while len(out) < 4:
+        r = serving.Request(k, serving.W.serving_request(k), 0.0, 8)
+        g = r.work["grid"]
+        if g["nx"] * g["ny"] >= 512 * 512:
+            out.append(r)
+        k += 1
+    for j, r in enumerate(out):
+        r.steps = 8 + 3 * j
+    assert {(r.work["grid"]["nx"], r.work["grid"]["ny"]) for r in out} == {(512, 512), (1024, 512)}
+    budget = 2 * max(serving.workspace_bytes(r.work, cc.CC_FP32_GEOM64) for r in out)
+    srv = serving.Server("batched", budget_bytes=budget, slots=2, keep_results=True)
+    rep = srv.run(out)
+    srv.close()
+    assert rep["requests"] == 4 and rep["max_concurrent"] == 2
+    for r in out:
+        assert r.done == r.steps
+        assert np.array_equal(r.result, alone(r, cc.CC_FP32_GEOM64)), r.rid
