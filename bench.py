@@ -52,15 +52,16 @@ def timed_kernels(step_fn, nsteps, enable, read):
     return {k: (1e3 * t[k][0] / t[k][1] if t[k][1] > 0 else None) for k in ("dense_x", "dense_y")}
 
 
-def roofline(kern_us, cells, bytes_per_value, table, names):
+def roofline(kern_us, cells, bytes_per_value, table, names, grid=None):
     """Roofline of the slower dense launch: algorithmic bytes (read and write of the
-    4-component state of every cell, per sweep) over its average duration."""
+    4-component state of every cell, per sweep) over its average duration; traffic: the
+    counter bytes of the same launch on the same grid (`grid` "NXxNY"), when measured."""
     kern = max((k for k in kern_us if kern_us[k]), key=lambda k: kern_us[k])
     us = kern_us[kern]
     alg = cells * 4 * 2 * bytes_per_value
     ach = alg / (us * 1e-6) / 1e9
     name = names[kern]
-    t = table.get(name)
+    t = table.get(f"{name}@{grid}") if grid else None
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": None if t is None else t["fetch_bytes"] + t["write_bytes"],
@@ -108,7 +109,7 @@ def run_mode(precision, steps, warmup, w, table, tune_cache=None):
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     info = s.info()
-    if info["status"] != 0:
+    if info["status"] & ~1:  # bit 0 (a cell with no donor) is only reported
         raise RuntimeError(f"device status {info['status']}")
     # latency pass after the timed region: an event pair around every step
     _, ms = s.advance(min(steps, 100), cfl, want_ms=True)
@@ -126,7 +127,7 @@ def run_mode(precision, steps, warmup, w, table, tune_cache=None):
     ph = cc.cc_timing_read(s.ctx)
     cc.cc_timing(s.ctx, 0)
     info = s.info()
-    if info["status"] != 0:
+    if info["status"] & ~1:  # bit 0 (a cell with no donor) is only reported
         raise RuntimeError(f"device status {info['status']}")
     out = {"value": rate(cells, steps, T), "ms_per_step": 1e3 * T / steps, "host_planned_ms_per_step": host_ms,
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -136,7 +137,8 @@ def run_mode(precision, steps, warmup, w, table, tune_cache=None):
            "box_phases_us_per_step": round(1e3 * ph["box"][0] / nph, 2),
            "geometry_us_per_step": round(1e3 * ph["geometry"][0] / nph, 2)}
     bpv = 4 if prec32 else 8
-    out["roofline"] = roofline(kern_us, cells, bpv, table, kernel_names(s, prec32))
+    out["roofline"] = roofline(kern_us, cells, bpv, table, kernel_names(s, prec32),
+                               f"{w['grid']['nx']}x{w['grid']['ny']}")
     step_bytes = cells * 2 * 4 * 2 * bpv
     ach = step_bytes / (out["ms_per_step"] * 1e-3) / 1e9
     out["step_roofline"] = {"algorithmic_bytes": step_bytes, "achieved": round(ach, 1), "unit": "GB/s",
@@ -257,7 +259,7 @@ def naca_leg(steps, warmup, table):
     out = {"workload": "NACA 0012 pitching 2 deg at reduced frequency 0.1 in a Mach-0.7 stream, 4096x4096 on "
                        "[-2,4]x[-3,3], tiles tuned"}
     cache = os.path.join("/tmp", f"cc_tiles_{os.getpid()}.txt")
-    n = min(steps, 100)
+    n = 500 if steps >= 50 else steps  # a 500-step window (about 0.25 s FP32, 0.45 s FP64)
     for prec, key in ((cc.CC_FP32_GEOM64, "f32"), (cc.CC_FP64, "f64")):
         r = run_mode(prec, n, warmup, w, table, tune_cache=cache)
         r.pop("solver").close()
@@ -414,23 +416,30 @@ def serving_child(n, budget_gib, slots, timeout_s=900):
 def probe():
     """Dispatches for counter runs (one process, the step's launches one by one): the dense
     launches of the headline workload in both precisions and of the 4096 x 4096 aerofoil in
-    FP32, then a plain 16 MiB fill and a 16 MiB device copy whose counter readings scale
-    FETCH_SIZE and WRITE_SIZE to bytes."""
+    FP32 and FP64, then a plain 512 MiB fill and five 512 MiB device copies (larger than the
+    last-level cache) whose counter readings scale FETCH_SIZE and WRITE_SIZE to bytes."""
     import torch
     from paper_1711_11361_amd import cc
     from paper_1711_11361_amd import workloads as W
 
-    for w, precs in ((W.cylinder(), (cc.CC_FP32_GEOM64, cc.CC_FP64)), (W.naca(), (cc.CC_FP32_GEOM64,))):
+    # (workload, precisions, tile pairs): the default tiles, and on the aerofoil also the
+    # shapes its tuner picks (4-row x blocks, 8-row y column walks)
+    for w, precs, tiles in ((W.cylinder(), (cc.CC_FP32_GEOM64, cc.CC_FP64), ((0, 0),)),
+                            (W.naca(), (cc.CC_FP32_GEOM64, cc.CC_FP64), ((0, 0), (2, 5)))):
         for prec in precs:
             s = cc.Solver(w["grid"], w["body"], precision=prec)
             s.set_prim(w["prim"])
             for _ in range(4):
                 s.step(s.cfl_dt(w["cfl"]))
-            cc.cc_timing(s.ctx, 1)  # the step's launches one by one
-            for _ in range(2):
-                s.step(s.cfl_dt(w["cfl"]))
-            cc.cc_timing_read(s.ctx)
-            cc.cc_timing(s.ctx, 0)
+            for tx, ty in tiles:
+                if prec == cc.CC_FP64 and ty == 5:
+                    ty = 4  # an FP64 column walk takes 4 rows
+                s.set_tiles(tx, ty)
+                cc.cc_timing(s.ctx, 1)  # the step's launches one by one
+                for _ in range(2):
+                    s.step(s.cfl_dt(w["cfl"]))
+                cc.cc_timing_read(s.ctx)
+                cc.cc_timing(s.ctx, 0)
             print("probe", w["name"], "fp32" if prec == cc.CC_FP32_GEOM64 else "fp64", s.info(), flush=True)
             s.close()
     a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
@@ -442,7 +451,7 @@ def probe():
     print("probe done", flush=True)
 
 
-COPY_BYTES = 16 << 20
+COPY_BYTES = 512 << 20
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "dense_sweep_hbm_traffic.md")
 DENSE_SOURCES = ("cc_device.h", "sweep.h", "engine.h")
 
