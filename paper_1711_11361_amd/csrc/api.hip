@@ -238,6 +238,10 @@ struct Engine {
     // read yet, and spare ones.
     int timing = 0;
     std::vector<TimedPair> pending, pool;
+    // the box cells' first phase runs in the leading blocks of the sweep's y launch when
+    // there is one, else of its x launch when merge_x, else as a launch of its own before
+    // the dense launches (see engine_plan)
+    bool merge_x = true;
 };
 
 }  // namespace
@@ -708,8 +712,19 @@ void drop_graphs(Engine& E) {
 
 // Offsets of every launch kind for the current members; uploads them (stream-ordered,
 // from pageable memory, so the call returns after the copy has been staged).
+// The box's first phase shares a dense launch, where its latency-bound blocks run beside
+// the tiles instead of in a launch of their own.  The y kernels hold a column's states in
+// registers anyway, so they take it at no cost.  The x kernel alone needs few registers,
+// and on large grids the merged kernel's registers (set by the box code) halve the tiles'
+// occupancy, which costs more than a launch: the 4096 x 4096 x sweep takes 163 us merged
+// against 108 us alone (FP32, 4-row blocks), while the box phase alone takes about 12 us.
+constexpr size_t MERGE_WALL_CELLS = (size_t)1 << 21;
+
 hipError_t engine_plan(Engine& E, hipStream_t stream) {
     int n = (int)E.mem.size();
+    size_t cells = 0;
+    for (const cc_ctx* c : E.mem) cells += (size_t)c->g.nx * c->g.ny;
+    E.merge_x = cells <= MERGE_WALL_CELLS;
     int stride = 2 * E.cap_n + 1;
     std::vector<int> all((size_t)NKINDS * stride, 0);
     for (int k = 0; k < NKINDS; k++) {
@@ -818,6 +833,21 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
     }
     if (wall && nwall > 0)  // no dense launch took the box blocks
         klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
+}
+
+// The dense launches of sweep sw (`which` as for launch_dense) with the box cells' first
+// phase placed as engine_plan decided.  ta/tb (nullable): event pairs of the x and y
+// launches, from tp(d).
+template <typename R, class TP>
+void launch_sweep_dense(const Engine& E, hipStream_t s, int sw, int which, int fold, TP&& tp) {
+    int n = (int)E.mem.size();
+    bool wall_y = (which & 2) != 0, wall_x = !wall_y && E.merge_x;
+    if (!wall_x && !wall_y) klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, E.d_args, koff(E, L_BOX), n, sw);
+    for (int d = 0; d < 2; d++) {
+        if (!((which >> d) & 1)) continue;
+        TimedPair p = tp(d);
+        launch_dense<R>(E, s, sw, 1 << d, p.a, p.b, fold, d == 0 ? wall_x : wall_y);
+    }
 }
 
 // Box phases before the dense sweep.
@@ -941,7 +971,7 @@ void step_kernels(const Engine& E, hipStream_t s, int dir0) {
     // the second sweep's dense tiles and its covering leave partial maxima of the new
     // state's wave speeds; its collapse launch (one block per member) combines them
     for (int sw = 0; sw < 2; sw++) {
-        launch_dense<R>(E, s, sw, sw == 0 ? which0 : which1, nullptr, nullptr, sw, true);
+        launch_sweep_dense<R>(E, s, sw, sw == 0 ? which0 : which1, sw, [](int) { return TimedPair{nullptr, nullptr, 0}; });
         launch_box_post<R>(E, s, sw, sw == 0 ? which0 : which1, sw);
     }
 }
@@ -959,13 +989,7 @@ void step_kernels_timed(Engine& E, hipStream_t s, int dir0) {
     klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
     for (int sw = 0; sw < 2; sw++) {
         int which = sw == 0 ? which0 : which1;
-        bool wall = true;
-        for (int d = 0; d < 2; d++) {
-            if (!((which >> d) & 1)) continue;
-            TimedPair tp = engine_pair(E, d);
-            launch_dense<R>(E, s, sw, 1 << d, tp.a, tp.b, sw, wall);
-            wall = false;
-        }
+        launch_sweep_dense<R>(E, s, sw, which, sw, [&](int d) { return engine_pair(E, d); });
         launch_box_post<R>(E, s, sw, which, sw);
     }
 }
@@ -2063,14 +2087,15 @@ bool tune_engine(Engine& E, hipStream_t s, int reps, std::string& err) {
                 ok = false;
                 break;
             }
-            launch_dense<R>(E, s, dir, 1 << dir, nullptr, nullptr, 0, true);  // warm-up
+            launch_dense<R>(E, s, dir, 1 << dir, nullptr, nullptr, 0, dir == 1 || E.merge_x);  // warm-up
             float ms = 0.0f;
             if (hipEventRecord(ea, s) != hipSuccess) {
                 err = "event record";
                 ok = false;
                 break;
             }
-            for (int r = 0; r < reps; r++) launch_dense<R>(E, s, dir, 1 << dir, nullptr, nullptr, 0, true);
+            for (int r = 0; r < reps; r++)
+                launch_dense<R>(E, s, dir, 1 << dir, nullptr, nullptr, 0, dir == 1 || E.merge_x);
             if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
                 hipEventElapsedTime(&ms, ea, eb) != hipSuccess || hipGetLastError() != hipSuccess) {
                 err = "tile timing failed";

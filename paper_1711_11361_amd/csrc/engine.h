@@ -467,8 +467,7 @@ __device__ __forceinline__ void dense_yc_block(const StepArgs* __restrict__ A, c
 template <typename R, int RB>
 __global__ __launch_bounds__(DX_T) void kb_dense_x(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                    int n, int s, int fold) {
-    __shared__ R lds[dense_x_lds<R>() / sizeof(R)];
-    dense_x_block<R, RB>(A, off, n, blockIdx.x, s, fold, lds);
+    dense_x_block<R, RB>(A, off, n, blockIdx.x, s, fold, nullptr);
 }
 
 template <typename R, int TR>
@@ -493,13 +492,12 @@ template <typename R, int RB>
 __global__ __launch_bounds__(DX_T) __attribute__((amdgpu_waves_per_eu(4))) void kb_wall_dense_x(const StepArgs* __restrict__ A,
                                                         const int* __restrict__ off_wall, int nwall,
                                                         const int* __restrict__ off, int n, int s, int fold) {
-    __shared__ R lds[dense_x_lds<R>() / sizeof(R)];
     if ((int)blockIdx.x < nwall) {
         Unit w = unit_at(off_wall, n, blockIdx.x);
         stagewall_loop<R>(A[w.u], s, w.lb * T_WIDE + threadIdx.x, w.nb * T_WIDE);
         return;
     }
-    dense_x_block<R, RB>(A, off, n, blockIdx.x - nwall, s, fold, lds);
+    dense_x_block<R, RB>(A, off, n, blockIdx.x - nwall, s, fold, nullptr);
 }
 template <typename R, int TR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kb_wall_dense_y(const StepArgs* __restrict__ A,

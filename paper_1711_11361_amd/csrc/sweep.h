@@ -1034,11 +1034,15 @@ __device__ __forceinline__ int ghost_src(int p, int n, int bclo, int bchi, bool&
     return src < 0 ? 0 : (src >= n ? n - 1 : src);
 }
 
-// x-sweep: a block covers DX_OUT = 252 cells of RB consecutive rows (one thread per cell
-// plus a two-cell halo each side); the evolved face states and face fluxes are exchanged
-// through LDS; the next row is loaded while the current one is computed.
+// x-sweep: a block covers DX_OUT = 240 cells of RB consecutive rows.  Each of its four
+// wavefronts takes 60 of them plus a two-cell halo each side (one lane per cell) and
+// passes the neighbours' states, evolved face states and face fluxes between lanes by
+// shuffles: no LDS and no barriers, so the wavefronts of a block never wait for each other
+// (the halo lanes repeat 4 of every 64 cells' reconstructions).  The next row is loaded
+// while the current one is computed.
 constexpr int DX_T = 256;
-constexpr int DX_OUT = DX_T - 4;
+constexpr int DX_WOUT = WAVE - 4;                // cells a wavefront writes
+constexpr int DX_OUT = (DX_T / WAVE) * DX_WOUT;  // cells a block writes per row
 
 template <int RB>
 __host__ __device__ constexpr int dense_x_blocks(int nx, int ny) {
@@ -1046,7 +1050,7 @@ __host__ __device__ constexpr int dense_x_blocks(int nx, int ny) {
 }
 
 template <typename T>
-__host__ __device__ constexpr size_t dense_x_lds() { return (size_t)12 * DX_T * sizeof(T); }
+__host__ __device__ constexpr size_t dense_x_lds() { return 0; }  // lane shuffles, no LDS
 
 // Maximum of a per-lane bit-pattern pair over the wavefront (every lane gets it).
 __device__ __forceinline__ void wave_max_pair(unsigned long long& bx, unsigned long long& by) {
@@ -1140,27 +1144,26 @@ struct SpeedMax<float> {
     }
 };
 
-// lds: dense_x_lds<T>() bytes; cfl: when not null, the maxima of the written cells' speeds
-// are merged into the slot pair (lb mod NSPD) of cfl; bud: when not null, the budget slots
-// (the fluxes through the domain's low and high x-faces of the block's rows).
+// lds: unused (kept for the callers that share a tile loop with LDS-staged kernels); cfl:
+// when not null, the maxima of the written cells' speeds are merged into the slot pair
+// (lb mod NSPD) of cfl; bud: when not null, the budget slots (the fluxes through the
+// domain's low and high x-faces of the block's rows).  Every thread of the block calls it.
 template <typename R, typename T, int RB>
 __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_, R* __restrict__ Uout_, Box B, T lam,
                                         int lb, T* lds, unsigned long long* cfl, double* bud = nullptr) {
+    (void)lds;  // the x-sweep exchanges values by lane shuffles
     const gmem<R>* __restrict__ U = to_global(U_);
     gmem<R>* __restrict__ Uout = to_global(Uout_);
-    T(*sq)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds);
-    T(*ser)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds + 4 * DX_T);
-    T(*sf)[DX_T] = reinterpret_cast<T(*)[DX_T]>(lds + 8 * DX_T);
     SpeedMax<R> sm;
-    int tid = threadIdx.x;
+    int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     int nx = g.nx, ny = g.ny;
     int gx = (nx + DX_OUT - 1) / DX_OUT;
-    int i = (lb % gx) * DX_OUT - 2 + tid;
+    int i = (lb % gx) * DX_OUT + wv * DX_WOUT - 2 + lane;
     int j0 = (lb / gx) * RB;
     size_t nc = (size_t)nx * ny;
     bool mir;
     int src = ghost_src(i, nx, g.bc[0], g.bc[1], mir);
-    bool writer = tid >= 2 && tid < DX_T - 2 && i >= 0 && i < nx;
+    bool writer = lane >= 2 && lane < WAVE - 2 && i >= 0 && i < nx;
     bool colbox = i >= B.i0 && i < B.i1;
     T gam = (T)g.gamma;
     // budget: the threads of columns 0 and nx - 1 record the fluxes through the domain's
@@ -1185,36 +1188,26 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_,
             for (int m = 0; m < 4; m++) qn[m] = (T)U[m * nc + kk];
         }
         if (mir) q[1] = -q[1];
+        // lane l holds cell i: its reconstruction needs cells i - 1 and i + 1 (lanes 0 and
+        // 63 get their own values, unused); face i - 1/2 needs cell i - 1's evolved right
+        // state; the update needs face i + 1/2's flux from lane l + 1
+        T qm[4], qp[4], el[4], er[4], erl[4], F[4], Fr[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++) sq[m][tid] = q[m];
-        __syncthreads();
-        T el[4], er[4];
-        if (tid >= 1 && tid < DX_T - 1) {
-            T qm[4], qp[4];
-#pragma unroll
-            for (int m = 0; m < 4; m++) {
-                qm[m] = sq[m][tid - 1];
-                qp[m] = sq[m][tid + 1];
-            }
-            muscl<T, 0>(qm, q, qp, true, lam, gam, el, er);
-#pragma unroll
-            for (int m = 0; m < 4; m++) ser[m][tid] = er[m];
+        for (int m = 0; m < 4; m++) {
+            qm[m] = __shfl_up(q[m], 1, WAVE);
+            qp[m] = __shfl_down(q[m], 1, WAVE);
         }
-        __syncthreads();
-        if (tid >= 2 && tid < DX_T - 1) {
-            T erl[4], F[4];
+        muscl<T, 0>(qm, q, qp, true, lam, gam, el, er);
 #pragma unroll
-            for (int m = 0; m < 4; m++) erl[m] = ser[m][tid - 1];
-            hllc<T, 0>(erl, el, gam, F);
+        for (int m = 0; m < 4; m++) erl[m] = __shfl_up(er[m], 1, WAVE);
+        hllc<T, 0>(erl, el, gam, F);
 #pragma unroll
-            for (int m = 0; m < 4; m++) sf[m][tid] = F[m];
-        }
-        __syncthreads();
+        for (int m = 0; m < 4; m++) Fr[m] = __shfl_down(F[m], 1, WAVE);
         if (writer && !(colbox && j >= B.j0 && j < B.j1)) {
             size_t k = (size_t)j * nx + i;
             R un[4];
 #pragma unroll
-            for (int m = 0; m < 4; m++) un[m] = (R)update(q[m], lam, sf[m][tid], sf[m][tid + 1]);
+            for (int m = 0; m < 4; m++) un[m] = (R)update(q[m], lam, F[m], Fr[m]);
 #pragma unroll
             for (int m = 0; m < 4; m++) Uout[m * nc + k] = un[m];
             if (cfl) sm.add(un, g.gamma);
@@ -1223,14 +1216,13 @@ __device__ __forceinline__ void dense_x(const Grid& g, const R* __restrict__ U_,
             bool upd = !(colbox && j >= B.j0 && j < B.j1);
             if (i == 0)
 #pragma unroll
-                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * j) + m] = upd ? (double)sf[m][tid] : 0.0;
+                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * j) + m] = upd ? (double)F[m] : 0.0;
             if (i == nx - 1)
 #pragma unroll
-                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * j + 1) + m] = upd ? (double)sf[m][tid + 1] : 0.0;
+                for (int m = 0; m < 4; m++) bud[BS_DENSE + 4 * (2 * j + 1) + m] = upd ? (double)Fr[m] : 0.0;
         }
     }
     if (cfl) sm.flush(cfl + 2 * (lb % NSPD));
-    __syncthreads();  // the caller may reuse the LDS for its next tile
 }
 
 // y-sweep: a block covers 64 columns x TR rows.  The tile and its two-row halos (TR + 4
