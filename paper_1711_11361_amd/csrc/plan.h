@@ -114,6 +114,11 @@ struct PlanState {
     Level lev[3];
     Motion mot;
     Box last_sweep_box;
+    // a turning body's angle terms at time trig_t (the end of the last planned step, the
+    // start of the next): sin and cos of omega t, and cos and sin of the pose angle there;
+    // trig_ok = 0 (as the host writes it) means none
+    int trig_ok;
+    double trig_t, sin_w, cos_w, cs_th, sn_th;
 };
 
 __device__ inline Pose pose_at_dev(const PlanConst& P, double t) {
@@ -250,8 +255,26 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
         if (!halt && !(isfinite(sx) && isfinite(sy))) halt = HALT_SPEEDS;
     }
     double t0 = S.t;
-    Pose q0 = pose_at_dev(P, t0);
     bool turning = P.amp != 0.0;
+    int lane = threadIdx.x & 63;
+    // a turning body's angle terms at t0: those the last planned step left for its end,
+    // else computed (sincos per lane, the same value in every lane)
+    double s0w = 0.0, c0w = 1.0, cth0 = 1.0, sth0 = 0.0;
+    Pose q0;
+    if (!turning) {
+        q0 = pose_at_dev(P, t0);
+    } else {
+        if (S.trig_ok && S.trig_t == t0) {
+            s0w = S.sin_w;
+            c0w = S.cos_w;
+            cth0 = S.cs_th;
+            sth0 = S.sn_th;
+        } else {
+            sincos(P.omega * t0, &s0w, &c0w);
+            sincos(P.theta0 + P.amp * s0w, &sth0, &cth0);
+        }
+        q0 = Pose{cth0, sth0, P.ref_x + P.vx * t0, P.ref_y + P.vy * t0};
+    }
     auto pose_k = [&](const Pose& px, const Pose& py, int r, double& x, double& y) {
         x = (px.cs * bxv[r] - px.sn * byv[r]) + px.cx;
         y = (py.sn * bxv[r] + py.cs * byv[r]) + py.cy;
@@ -262,7 +285,7 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
         sx = fmax(sx, fabs(P.vx));
         sy = fmax(sy, fabs(P.vy));
     } else if (m > 0) {
-        double thd = P.amp * P.omega * cos(P.omega * t0);
+        double thd = P.amp * P.omega * c0w;
         double cx = P.ref_x + P.vx * t0, cy = P.ref_y + P.vy * t0;
         double v[2] = {-sx, -sy};  // maxima as least negated values
         int kk[2] = {0, 0};
@@ -288,7 +311,27 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
     __syncthreads();
     double dt = sdt;
     double t1 = t0 + dt;
-    Pose q1 = pose_at_dev(P, t1);
+    // a turning body's angle terms at t1 and for the step's motion, in two rounds of one
+    // sincos per lane (lane 0: omega t1, then the pose angle th1; lane 1: omega at mid-step,
+    // then th1 - th0), shared across the wavefront
+    double s1w = 0.0, c1w = 1.0, cth1 = 1.0, sth1 = 0.0, cmid = 1.0, cosd = 1.0, sind = 0.0;
+    Pose q1;
+    if (!turning) {
+        q1 = pose_at_dev(P, t1);
+    } else {
+        double sa, ca, sb, cb;
+        sincos(lane == 0 ? P.omega * t1 : P.omega * (t0 + 0.5 * dt), &sa, &ca);
+        s1w = __shfl(sa, 0, 64);
+        c1w = __shfl(ca, 0, 64);
+        cmid = __shfl(ca, 1, 64);
+        double th0 = P.theta0 + P.amp * s0w, th1 = P.theta0 + P.amp * s1w;
+        sincos(lane == 0 ? th1 : th1 - th0, &sb, &cb);
+        sth1 = __shfl(sb, 0, 64);
+        cth1 = __shfl(cb, 0, 64);
+        sind = __shfl(sb, 1, 64);
+        cosd = __shfl(cb, 1, 64);
+        q1 = Pose{cth1, sth1, P.ref_x + P.vx * t1, P.ref_y + P.vy * t1};
+    }
     // stage polygon: the first sweep's coordinate at t^{n+1}, the other at t^n
     Pose mx = S.parity == 0 ? q1 : q0, my = S.parity == 0 ? q0 : q1;
     // per polygon (0: stage, 1: end) the least y, greatest y, least x, greatest x with the
@@ -375,38 +418,44 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
                 cq[1].cy += q1.cy;
             }
         } else {
-            for (int q = 0; q < 2; q++) {
-                cq[q] = Cert{0.0, 0.0, -1.0, 0.0};
-                if (m < 8) continue;
-                double cx = (q == 0 ? csum[0] : csum[2]) / m, cy = (q == 0 ? csum[1] : csum[3]) / m;
-                const Pose& px = q == 0 ? mx : q1;
-                const Pose& py = q == 0 ? my : q1;
-                double cv[2] = {INFINITY, -0.0};  // least distance to an edge line, least negated squared radius
-                int ck[2] = {0, 0};
+            // both polygons' discs from one pass over the edges
+            double cxq[2] = {csum[0] / m, csum[2] / m}, cyq[2] = {csum[1] / m, csum[3] / m};
+            cq[0] = cq[1] = Cert{0.0, 0.0, -1.0, 0.0};
+            if (m >= 8) {
+                // per polygon: least distance to an edge line, least negated squared radius
+                double cv[4] = {INFINITY, -0.0, INFINITY, -0.0};
+                int ck[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int r = 0; r < PLAN_VPT; r++) {
                     int k = threadIdx.x + r * T_PLAN;
                     if (!worker || k >= m) continue;
                     int k1 = k + 1 == m ? 0 : k + 1;
-                    double x, y;
-                    pose_k(px, py, r, x, y);
                     double b1x = body[2 * k1], b1y = body[2 * k1 + 1];
-                    double x1 = (px.cs * b1x - px.sn * b1y) + px.cx;
-                    double y1 = (py.sn * b1x + py.cs * b1y) + py.cy;
-                    double ex = x1 - x, ey = y1 - y;
-                    double l2 = ex * ex + ey * ey;
-                    if (l2 > 0.0) cv[0] = fmin(cv[0], (ex * (cy - y) - ey * (cx - x)) / sqrt(l2));
-                    double dx = x - cx, dy = y - cy;
-                    cv[1] = fmin(cv[1], -(dx * dx + dy * dy));
+#pragma unroll
+                    for (int q = 0; q < 2; q++) {
+                        const Pose& px = q == 0 ? mx : q1;
+                        const Pose& py = q == 0 ? my : q1;
+                        double x, y;
+                        pose_k(px, py, r, x, y);
+                        double x1 = (px.cs * b1x - px.sn * b1y) + px.cx;
+                        double y1 = (py.sn * b1x + py.cs * b1y) + py.cy;
+                        double ex = x1 - x, ey = y1 - y;
+                        double l2 = ex * ex + ey * ey;
+                        if (l2 > 0.0) cv[2 * q] = fmin(cv[2 * q], (ex * (cyq[q] - y) - ey * (cxq[q] - x)) / sqrt(l2));
+                        double dx = x - cxq[q], dy = y - cyq[q];
+                        cv[2 * q + 1] = fmin(cv[2 * q + 1], -(dx * dx + dy * dy));
+                    }
                 }
                 __syncthreads();
-                block_lexmin<2>(cv, ck, sc);
-                double rin = sc.rv[0], rout = sqrt(-sc.rv[1]);
-                if (rin > 1e-7 * rout && isfinite(rin)) {
-                    cq[q].cx = cx;
-                    cq[q].cy = cy;
-                    cq[q].rin2 = (rin * (1.0 - 1e-6)) * (rin * (1.0 - 1e-6));
-                    cq[q].rout2 = (rout * (1.0 + 1e-6)) * (rout * (1.0 + 1e-6));
+                block_lexmin<4>(cv, ck, sc);
+                for (int q = 0; q < 2; q++) {
+                    double rin = sc.rv[2 * q], rout = sqrt(-sc.rv[2 * q + 1]);
+                    if (rin > 1e-7 * rout && isfinite(rin)) {
+                        cq[q].cx = cxq[q];
+                        cq[q].cy = cyq[q];
+                        cq[q].rin2 = (rin * (1.0 - 1e-6)) * (rin * (1.0 - 1e-6));
+                        cq[q].rout2 = (rout * (1.0 + 1e-6)) * (rout * (1.0 + 1e-6));
+                    }
                 }
             }
         }
@@ -444,14 +493,8 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
         if (!halt && m > 0) {
             // rigid map of the step and the wall velocity at mid-step
             // a body that does not turn has th1 - th0 = 0 exactly: cos 1, sin 0 (exact values)
-            M.cosd = 1.0;
-            M.sind = 0.0;
-            if (turning) {
-                double th0 = P.theta0 + P.amp * sin(P.omega * t0);
-                double th1 = P.theta0 + P.amp * sin(P.omega * t1);
-                M.cosd = cos(th1 - th0);
-                M.sind = sin(th1 - th0);
-            }
+            M.cosd = cosd;
+            M.sind = sind;
             M.c0x = P.ref_x + P.vx * t0;
             M.c0y = P.ref_y + P.vy * t0;
             M.c1x = P.ref_x + P.vx * t1;
@@ -460,7 +503,8 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
             M.vx = P.vx;
             M.vy = P.vy;
             double ct = 1.0;  // cos 0
-            if (P.omega != 0.0) ct = cos(P.omega * th);
+            if (turning) ct = cmid;
+            else if (P.omega != 0.0) ct = cos(P.omega * th);
             M.thd = P.amp * P.omega * ct;
             M.chx = P.ref_x + P.vx * th;
             M.chy = P.ref_y + P.vy * th;
@@ -556,6 +600,12 @@ __device__ __forceinline__ void plan_block(const PlanConst* PC, PlanState* PS, S
         S.s0 = S.s1;
         S.s1 = tmp;
         S.t = t0 + dt;
+        S.trig_ok = turning ? 1 : 0;
+        S.trig_t = S.t;
+        S.sin_w = s1w;
+        S.cos_w = c1w;
+        S.cs_th = cth1;
+        S.sn_th = sth1;
         S.step++;
         S.parity ^= 1;
         S.steps++;
