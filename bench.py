@@ -74,7 +74,8 @@ def kernel_names(s, prec32):
     r = "float" if prec32 else "double"
     y = f"kb_wall_dense_yc<{r}, {info['tile_y_rows']}>" if info["tile_y_walk"] else \
         f"kb_wall_dense_y<{r}, {info['tile_y_rows']}>"
-    return {"dense_x": f"kb_wall_dense_x<{r}, {info['tile_x_rows']}>", "dense_y": y}
+    x = "kb_wall_dense_x" if info["x_with_box"] else "kb_dense_x"
+    return {"dense_x": f"{x}<{r}, {info['tile_x_rows']}>", "dense_y": y}
 
 
 def run_mode(precision, steps, warmup, w, table, tune_cache=None):
@@ -232,7 +233,9 @@ def triangle_batch_leg(steps, warmup, table, seeds=16):
 
     kern_us = timed_kernels(step, 10, lambda m: cc.cc_batch_timing(b.b, m), lambda: cc.cc_batch_timing_read(b.b))
     cells = sum(w["grid"]["nx"] * w["grid"]["ny"] for w in ws)
-    names = {"dense_x": "kb_wall_dense_x<float, 1>", "dense_y": "kb_wall_dense_y<float, 8>"}
+    # the library gives an x sweep over more than 2^21 cells per launch its dense kernel alone
+    x = "kb_dense_x" if cells > (1 << 21) else "kb_wall_dense_x"
+    names = {"dense_x": f"{x}<float, 1>", "dense_y": "kb_wall_dense_y<float, 8>"}
     rf = roofline(kern_us, cells, 4, table, names)
     for s in sol:
         b.remove(s)

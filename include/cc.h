@@ -201,13 +201,15 @@ cc_status cc_set_budget(cc_ctx* ctx, int32_t on);
 cc_status cc_totals_state(const void* d_u, int32_t precision, int32_t nx, int32_t ny, double hx, double hy,
                           void* hip_stream, double* d_out4);
 
-/* Host info vector (n entries used, up to 10): time, steps, parity, device status bits
+/* Host info vector (n entries used, up to 11): time, steps, parity, device status bits
  * (1: a cell turned fluid, or was emptied, with no donor next to it — reported only: the
  * cell keeps no content until a donor appears; 2: a cell stayed inadmissible after
  * collapsing; 8: a grid-barrier wait of a persistent launch ran out; 2 and 8 are errors),
  * collapsed-cell count, sweep box cells of the last sweep, staging capacity, rows per block
  * of the dense x-sweep, rows per tile of the dense y-sweep, 1 if that sweep walks columns
- * (else 0).  Synchronizes. */
+ * (else 0), 1 if an x sweep's dense launch also runs the box cells' first phase (small
+ * grids; else that phase has a launch of its own before it; a y sweep's dense launch always
+ * runs it).  Synchronizes. */
 cc_status cc_info(cc_ctx* ctx, double* h_out, int32_t n);
 
 /* Tile tuner for the dense sweeps (the regular cells): times every tile shape of both

@@ -242,12 +242,12 @@ def cc_totals_state(d_u, precision, nx, ny, hx, hy, stream, d_out4):
 
 
 def cc_info(ctx):
-    out = (_d * 10)()
-    _check(ctx, _lib.cc_info(ctx, out, 10))
+    out = (_d * 11)()
+    _check(ctx, _lib.cc_info(ctx, out, 11))
     v = out[:]
     return {"t": v[0], "steps": int(v[1]), "parity": int(v[2]), "status": int(v[3]), "collapses": int(v[4]),
             "box_cells": int(v[5]), "capacity": int(v[6]), "tile_x_rows": int(v[7]), "tile_y_rows": int(v[8]),
-            "tile_y_walk": bool(v[9])}
+            "tile_y_walk": bool(v[9]), "x_with_box": bool(v[10])}
 
 
 def cc_set_tiles(ctx, tile_x, tile_y):

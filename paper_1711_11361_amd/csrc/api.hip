@@ -2034,10 +2034,11 @@ cc_status cc_info(cc_ctx* c, double* h_out, int32_t n) {
     HIPCHK(c, hipMemcpyAsync(&dev[0], c->ws + c->lay.off_status, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&dev[1], c->ws + c->lay.off_ncol, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double v[10] = {c->t, (double)c->step, (double)c->parity, (double)dev[0], (double)dev[1],
+    double v[11] = {c->t, (double)c->step, (double)c->parity, (double)dev[0], (double)dev[1],
                     (double)c->last_sweep_box.w() * c->last_sweep_box.h(), (double)c->lay.cap,
-                    (double)X_RB[c->eng.tile_x], (double)Y_TR[c->eng.tile_y], y_walk(c->eng.tile_y) ? 1.0 : 0.0};
-    for (int k = 0; k < n && k < 10; k++) h_out[k] = v[k];
+                    (double)X_RB[c->eng.tile_x], (double)Y_TR[c->eng.tile_y], y_walk(c->eng.tile_y) ? 1.0 : 0.0,
+                    c->eng.merge_x ? 1.0 : 0.0};
+    for (int k = 0; k < n && k < 11; k++) h_out[k] = v[k];
     return CC_OK;
 }
 
