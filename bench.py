@@ -419,16 +419,16 @@ def serving_child(n, budget_gib, slots, timeout_s=900):
 def probe():
     """Dispatches for counter runs (one process, the step's launches one by one): the dense
     launches of the headline workload in both precisions and of the 4096 x 4096 aerofoil in
-    FP32 and FP64, then a plain 512 MiB fill and five 512 MiB device copies (larger than the
+    FP32 and FP64 (every x-block height), then a plain 512 MiB fill and five 512 MiB device copies (larger than the
     last-level cache) whose counter readings scale FETCH_SIZE and WRITE_SIZE to bytes."""
     import torch
     from paper_1711_11361_amd import cc
     from paper_1711_11361_amd import workloads as W
 
-    # (workload, precisions, tile pairs): the default tiles, and on the aerofoil also the
-    # shapes its tuner picks (4-row x blocks, 8-row y column walks)
+    # (workload, precisions, tile pairs): the default tiles, and on the aerofoil also every
+    # x-block height with the y column walks its tuner picks
     for w, precs, tiles in ((W.cylinder(), (cc.CC_FP32_GEOM64, cc.CC_FP64), ((0, 0),)),
-                            (W.naca(), (cc.CC_FP32_GEOM64, cc.CC_FP64), ((0, 0), (2, 5)))):
+                            (W.naca(), (cc.CC_FP32_GEOM64, cc.CC_FP64), ((0, 0), (1, 5), (2, 5), (3, 5)))):
         for prec in precs:
             s = cc.Solver(w["grid"], w["body"], precision=prec)
             s.set_prim(w["prim"])
