@@ -144,3 +144,39 @@ def test_batch_refuses_misuse():
         B.add(solver(reqs[2], cc.CC_FP64))  # full
     with pytest.raises(cc.CCError):
         s64.step(1e-4)  # stepped by its batch
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+def test_large_batch_with_its_own_box_launch_equals_members_alone(precision):
+    """Five 1024 x 512 cylinders (2.6 M cells) in one batch: its x sweeps run the box cells'
+    first phase in a launch of its own, the members alone in the x launch; the results are
+    the same bit for bit."""
+    ws = []
+    for q in range(5):
+        w = W.cylinder()
+        w["body"]["vel"] = (0.6 + 0.2 * q, 0.05 * (q - 2))
+        ws.append(w)
+    alone = []
+    for w in ws:
+        s = solver(w, precision)
+        assert s.info()["x_with_box"]
+        dts = []
+        for _ in range(4):
+            dt = s.cfl_dt(w["cfl"])
+            dts.append(dt)
+            s.step(dt)
+        alone.append((dts, s.get_u()))
+        s.close()
+    b = cc.Batch(len(ws), precision)
+    members = []
+    for w in ws:
+        s = solver(w, precision)
+        b.add(s)
+        members.append(s)
+    for k in range(4):
+        b.step([a[0][k] for a in alone])
+    for q, s in enumerate(members):
+        assert np.array_equal(s.get_u(), alone[q][1]), q
+        b.remove(s)
+        s.close()
+    b.close()
