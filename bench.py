@@ -25,6 +25,7 @@ Also reported, each measured in this run:
 """
 import argparse
 import hashlib
+import math
 import json
 import os
 import sys
@@ -273,6 +274,50 @@ def naca_leg(steps, warmup, table):
     return out
 
 
+def naca_lift_series(n=1024, cycles=3, per_cycle=48):
+    """Config 4's pitching aerofoil on an n x n grid over `cycles` pitch periods (device-
+    planned steps, FP32 state): lift, drag and moment coefficients C = F / (rho U^2 c / 2)
+    (moment about the quarter chord, counter-clockwise positive) from the surface loads
+    against the angle of attack, sampled per_cycle times a period (the last period
+    reported), and the range of the wall cells' pressure coefficients at the end."""
+    import numpy as np
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    w = W.naca(nx=n, ny=n)
+    b = w["body"]
+    s = cc.Solver(w["grid"], b, precision=cc.CC_FP32_GEOM64)
+    s.set_prim(w["prim"])
+    U, rho, chord = 0.7, 1.0, 1.0  # the free stream of the workload
+    q = 0.5 * rho * U * U * chord
+    period = 2.0 * math.pi / b["pitch_omega"]
+    dt0 = s.cfl_dt(w["cfl"])
+    chunk = max(1, int(period / dt0 / per_cycle))
+    samples = []
+    t0 = time.perf_counter()
+    while s.info()["t"] < cycles * period:
+        s.advance(chunk, w["cfl"])
+        t = s.info()["t"]
+        fx, fy, mz, _ = s.surface_loads()
+        # the pose angle turns the body counter-clockwise, which lowers the leading edge (on
+        # the upstream side): the angle of attack is its negative
+        aoa = -math.degrees(b["theta0"] + b["pitch_amp"] * math.sin(b["pitch_omega"] * t))
+        samples.append((t, aoa, fy / q, fx / q, mz / (q * chord)))
+    wall = time.perf_counter() - t0
+    r = s.surface_pressure()
+    cp = (r[:, 3] - 1.0 / 1.4) / q  # free-stream pressure 1/gamma
+    steps = s.info()["steps"]
+    s.close()
+    last = [x for x in samples if x[0] >= (cycles - 1) * period]
+    return {"workload": f"NACA 0012 pitching 2 deg at reduced frequency 0.1, Mach 0.7, {n}x{n}, FP32 state",
+            "cycles": cycles, "steps": steps, "wall_s": round(wall, 2),
+            "last_cycle": {"angle_of_attack_deg": [round(x[1], 4) for x in last],
+                           "c_l": [round(x[2], 5) for x in last],
+                           "c_d": [round(x[3], 5) for x in last], "c_m": [round(x[4], 5) for x in last]},
+            "c_l_range": [round(min(x[2] for x in last), 5), round(max(x[2] for x in last), 5)],
+            "wall_cells": int(len(cp)), "cp_range": [round(float(cp.min()), 4), round(float(cp.max()), 4)]}
+
+
 def batched(w, instances, steps, warmup):
     """Copies of the headline workload stepped as one batch (device-planned), and the same
     copies as plain FP64 contexts advanced one after another with launches of their own."""
@@ -486,8 +531,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the legs of the other configurations")
-    ap.add_argument("--legs", default="piston,triangle,naca,batched",
-                    help="legs of the other configurations to run (comma list of piston, triangle, naca, batched)")
+    ap.add_argument("--legs", default="piston,triangle,naca,lift,batched",
+                    help="legs of the other configurations to run (comma list of piston, triangle, naca, lift, "
+                         "batched)")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving mix, run in a child process (0: skip)")
     ap.add_argument("--serving-only", action="store_true",
@@ -562,6 +608,9 @@ def main():
     if "naca" in legs:
         out["configs"]["naca_4096x4096"] = naca_leg(args.steps, min(args.warmup, 10), table)
         print("naca done", file=sys.stderr, flush=True)
+    if "lift" in legs:
+        out["naca_lift"] = naca_lift_series()
+        print("lift series done", file=sys.stderr, flush=True)
     if "batched" in legs:
         out["batched_copies"] = [batched(w, k, min(args.steps, 200), min(args.warmup, 20)) for k in (4, 16)]
     if args.serving > 0:

@@ -163,6 +163,17 @@ cc_status cc_advance(cc_ctx* ctx, int32_t nsteps, double cfl, double* h_dt, floa
  * and no open step (CC_ERR_ARG).  Synchronizes. */
 cc_status cc_surface_loads(cc_ctx* ctx, double* h_out4);
 
+/* Wall pressure distribution at level n (the surface pressure of the pitching aerofoil,
+ * Sec. 3.6; from it the pressure coefficient of each wall cell): for every cell with fluid
+ * content and a non-zero effective wall normal, in increasing linear index j nx + i, six
+ * doubles: that index, the wall point x and y, p* of the wall Riemann problem (Eq.
+ * riemann_wallvel, reading R9) and the normal N (Nx, Ny; |N| the wall length, pointing into
+ * the body) -- the terms whose sums cc_surface_loads returns.  d_out (device, caller-owned,
+ * 6 * max_records doubles; may be null when max_records is 0) receives the first
+ * max_records records; *h_n (host) the number of wall cells, also when it exceeds
+ * max_records (call with 0 to size the buffer).  Synchronizes. */
+cc_status cc_surface_pressure(cc_ctx* ctx, double* d_out, int32_t max_records, int32_t* h_n);
+
 /* Conservation totals sum(U) hx hy per component (rho, rho u, rho v, E), FP64,
  * deterministic order, into h_totals4 (host).  h_budget12 (host, nullable): the
  * conservation budget since cc_set_state (Sec. 3.3, mass-conservation error), zeros unless

@@ -1460,6 +1460,45 @@ double ccref_clip_area(const double* poly, int m, double ox, double oy, double w
     return a;
 }
 
+/* Wall pressure distribution at level n (the surface pressure of the pitching aerofoil,
+ * Sec. 3.6): for every cell with fluid content and a non-zero effective wall normal, in
+ * increasing linear index j nx + i, six values: the index, the wall point (x, y), p* of the
+ * wall Riemann problem and the normal N (Nx, Ny) -- the terms ccref_surface_loads sums.
+ * Writes at most max records to out (6 max doubles); returns the number of records. */
+int ccref_surface_pressure(const ccref_ctx* c, double* out, int max) {
+    if (c->m == 0) return 0;
+    const level_t* L = &c->L[c->s0];
+    size_t nc = (size_t)c->cfg.nx * c->cfg.ny;
+    int n = 0;
+    for (int j = 0; j < c->cfg.ny; j++)
+        for (int i = 0; i < c->cfg.nx; i++) {
+            size_t k = CIDX(c, i, j);
+            double a = L->alpha[k];
+            if (!(a > 0.0) || !(c->U[k] > 0.0)) continue;
+            double Nx = (beta_x(c, L, i, j) - beta_x(c, L, i + 1, j)) * c->hy;
+            double Ny = (beta_y(c, L, i, j) - beta_y(c, L, i, j + 1)) * c->hx;
+            if (Nx == 0.0 && Ny == 0.0) continue;
+            double q[4];
+            for (int m = 0; m < 4; m++) q[m] = c->U[m * nc + k] / a;
+            double nn = sqrt(Nx * Nx + Ny * Ny);
+            double wx, wy, uwx, uwy, ps, rs;
+            wall_point(c, L, i, j, &wx, &wy);
+            body_velocity(c, c->t, wx, wy, &uwx, &uwy);
+            wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, c->cfg.gamma, &ps, &rs);
+            if (n < max) {
+                double* r = out + 6 * (size_t)n;
+                r[0] = (double)k;
+                r[1] = wx;
+                r[2] = wy;
+                r[3] = ps;
+                r[4] = Nx;
+                r[5] = Ny;
+            }
+            n++;
+        }
+    return n;
+}
+
 /* Surface loads at level n (post-processing of the pitching aerofoil of Sec. 3.6; reading:
  * the sum over the cells with fluid content of p* N, p* the wall pressure of the wall
  * Riemann problem (Eq. riemann_wallvel, reading R9) between the cell state U/alpha and its

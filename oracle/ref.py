@@ -62,6 +62,8 @@ def lib(parallel=False):
         L.ccref_cfl_dt.argtypes = [vp, d]
         L.ccref_totals.argtypes = [vp, p]
         L.ccref_surface_loads.argtypes = [vp, p]
+        L.ccref_surface_pressure.restype = i
+        L.ccref_surface_pressure.argtypes = [vp, p, i]
         L.ccref_budget.argtypes = [vp, p, p, p]
         L.ccref_sweep.argtypes = [vp, i, d]
         L.ccref_begin_step.argtypes = [vp, d]
@@ -309,6 +311,13 @@ class Oracle:
         out = np.zeros(4)
         self._L.ccref_surface_loads(self._h, _dp(out))
         return out
+
+    def surface_pressure(self):
+        """Wall cells at level n in increasing index: rows (index, wall x, wall y, p*, Nx, Ny)."""
+        n = self._L.ccref_surface_pressure(self._h, None, 0)
+        out = np.zeros((max(n, 1), 6))
+        self._L.ccref_surface_pressure(self._h, _dp(out), n)
+        return out[:n]
 
     def budget(self):
         b, w, l = np.zeros(4), np.zeros(4), np.zeros(4)

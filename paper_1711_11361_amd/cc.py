@@ -65,6 +65,7 @@ _sig = {
     "cc_set_budget": (C.c_int, [_vp, _i32]),
     "cc_totals_state": (C.c_int, [_vp, _i32, _i32, _i32, _d, _d, _vp, _vp]),
     "cc_surface_loads": (C.c_int, [_vp, C.POINTER(_d)]),
+    "cc_surface_pressure": (C.c_int, [_vp, C.c_void_p, _i32, C.POINTER(_i32)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32), C.c_char_p]),
     "cc_set_tiles": (C.c_int, [_vp, _i32, _i32]),
@@ -217,6 +218,14 @@ def cc_surface_loads(ctx):
     out = (_d * 4)()
     _check(ctx, _lib.cc_surface_loads(ctx, out))
     return np.array(out[:])
+
+
+def cc_surface_pressure(ctx, d_out, max_records):
+    """Number of wall cells at level n; the first max_records records (6 doubles each) go to
+    device pointer d_out."""
+    n = _i32(0)
+    _check(ctx, _lib.cc_surface_pressure(ctx, d_out, int(max_records), C.byref(n)))
+    return n.value
 
 
 def cc_totals(ctx, with_budget=False):
@@ -504,6 +513,15 @@ class Solver:
     def surface_loads(self):
         """(Fx, Fy, Mz about the pose origin, sum p*|N|) of the gas on the body at level n."""
         return cc_surface_loads(self.ctx)
+
+    def surface_pressure(self):
+        """Wall cells at level n in increasing index: rows (index, wall x, wall y, p*, Nx, Ny)."""
+        n = cc_surface_pressure(self.ctx, None, 0)
+        with self._on_stream():
+            out = self.torch.empty((max(n, 1), 6), dtype=self.torch.float64, device=self.device)
+            n2 = cc_surface_pressure(self.ctx, out.data_ptr(), n)
+            assert n2 == n
+            return out[:n].cpu().numpy()
 
     def info(self):
         return cc_info(self.ctx)

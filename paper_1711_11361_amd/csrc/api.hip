@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/cc.h"
@@ -1304,9 +1305,10 @@ cc_status cc_geometry_dump(cc_ctx* c, int32_t level, int8_t* d_vcls, double* d_a
         } else {
             int chunk = (cells + CUT_BLOCKS - 1) / CUT_BLOCKS, nb = (cells + chunk - 1) / chunk;
             int* counts = at<int>(c, c->lay.off_part);  // 4 KiB of the reduction scratch
-            hipLaunchKernelGGL(k_cut_count, dim3(nb), dim3(CUT_T), 0, c->stream, c->g, L, R, chunk, counts);
+            CutCells pred{c->g, L};
+            hipLaunchKernelGGL(k_list_count<CutCells>, dim3(nb), dim3(CUT_T), 0, c->stream, pred, R, chunk, counts);
             hipLaunchKernelGGL(k_cut_scan, dim3(1), dim3(CUT_T), 0, c->stream, nb, counts, (int*)d_ncut);
-            hipLaunchKernelGGL(k_cut_write, dim3(nb), dim3(CUT_T), 0, c->stream, c->g, L, R, chunk,
+            hipLaunchKernelGGL(k_list_write<CutCells>, dim3(nb), dim3(CUT_T), 0, c->stream, pred, R, chunk,
                                (const int*)counts, (int*)d_cut);
         }
     }
@@ -2024,6 +2026,48 @@ cc_status cc_surface_loads(cc_ctx* c, double* h_out4) {
     hipLaunchKernelGGL(k_loads_final, dim3(1), dim3(64), 0, c->stream, blocks, (const double*)part, out);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(h_out4, out, 32, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return CC_OK;
+}
+
+cc_status cc_surface_pressure(cc_ctx* c, double* d_out, int32_t max_records, int32_t* h_n) {
+    if (!c || !h_n || max_records < 0 || (max_records > 0 && !d_out)) return fail(c, CC_ERR_ARG, "bad argument");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_surface_pressure inside a step");
+    if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
+    *h_n = 0;
+    const Box& R = c->lbox[c->s0];
+    if (c->m == 0 || box_empty(R)) return CC_OK;
+    LoadsArgs a;
+    a.g = c->g;
+    a.L = c->lev[c->s0];
+    a.reg = R;
+    a.vx = c->vx;
+    a.vy = c->vy;
+    a.thd = c->amp * c->omega * std::cos(c->omega * c->t);
+    a.cx = c->ref_x + c->vx * c->t;
+    a.cy = c->ref_y + c->vy * c->t;
+    int cells = R.w() * R.h();
+    int chunk = (cells + CUT_BLOCKS - 1) / CUT_BLOCKS, nb = (cells + chunk - 1) / chunk;
+    int* counts = at<int>(c, c->lay.off_part);  // 4 KiB of the reduction scratch
+    int* total = at<int>(c, c->lay.off_tot);
+    // the list of wall cells (at most the region's cells) in the box staging, unused
+    // outside a step: 4 B per cell against its 32 B per capacity cell
+    int* list = at<int>(c, c->lay.off_sQ);
+    auto run = [&](auto* U) {
+        using R_ = std::remove_const_t<std::remove_pointer_t<decltype(U)>>;
+        WallCells<R_> pred{c->g, a.L, U};
+        hipLaunchKernelGGL(k_list_count<WallCells<R_>>, dim3(nb), dim3(CUT_T), 0, c->stream, pred, R, chunk, counts);
+        hipLaunchKernelGGL(k_cut_scan, dim3(1), dim3(CUT_T), 0, c->stream, nb, counts, total);
+        hipLaunchKernelGGL(k_list_write<WallCells<R_>>, dim3(nb), dim3(CUT_T), 0, c->stream, pred, R, chunk,
+                           (const int*)counts, list);
+        if (max_records > 0)
+            hipLaunchKernelGGL(k_wall_records<R_>, dim3(nblk((size_t)max_records, LOADS_T)), dim3(LOADS_T), 0,
+                               c->stream, a, U, (const int*)list, (const int*)total, (int)max_records, d_out);
+    };
+    if (fp32(c)) run((const float*)at<float>(c, c->lay.off_u[c->cur]));
+    else run((const double*)at<double>(c, c->lay.off_u[c->cur]));
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(h_n, total, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return CC_OK;
 }

@@ -1,9 +1,10 @@
-// Compacted list of the cut cells of a level (cells whose four faces are neither all open
-// nor all closed), as linear indices j nx + i in increasing order.  Cut cells lie in the
-// level's region box, so only the box is scanned: the box is cut into CUT_BLOCKS contiguous
-// chunks of its row-major cell order (which is increasing in j nx + i), each block counts
-// its chunk's cut cells, one block turns the counts into offsets, and each block writes its
-// chunk's cells in order.  The result does not depend on timing.
+// Compacted lists of the cells of a box that satisfy a predicate, as linear indices j nx + i
+// in increasing order: the cut cells of a level (cells whose four faces are neither all open
+// nor all closed) and the wall cells of the surface pressure.  Both lie in the level's
+// region box, so only the box is scanned: the box is cut into CUT_BLOCKS contiguous chunks
+// of its row-major cell order (which is increasing in j nx + i), each block counts its
+// chunk's cells, one block turns the counts into offsets, and each block writes its chunk's
+// cells in order.  The result does not depend on timing.
 #pragma once
 #include "sweep.h"
 
@@ -11,20 +12,29 @@ namespace cc {
 
 constexpr int CUT_T = 256, CUT_BLOCKS = 1024;
 
-__device__ __forceinline__ bool box_cell_cut(const Grid& g, const Level& L, const Box& R, int t, int& lin) {
+// The cut cells of level L.
+struct CutCells {
+    Grid g;
+    Level L;
+    __device__ __forceinline__ bool operator()(int i, int j) const { return cell_cut_f(cell_faces(g, L, i, j)); }
+};
+
+template <class P>
+__device__ __forceinline__ bool box_cell_in(const P& pred, const Box& R, int t, int& lin) {
     int i = R.i0 + t % R.w(), j = R.j0 + t / R.w();
-    lin = j * g.nx + i;
-    return cell_cut_f(cell_faces(g, L, i, j));
+    lin = j * pred.g.nx + i;
+    return pred(i, j);
 }
 
 // Block b: its chunk of the box's cells, [b chunk, (b + 1) chunk).
-__global__ __launch_bounds__(CUT_T) void k_cut_count(Grid g, Level L, Box R, int chunk, int* __restrict__ counts) {
+template <class P>
+__global__ __launch_bounds__(CUT_T) void k_list_count(P pred, Box R, int chunk, int* __restrict__ counts) {
     int cells = R.w() * R.h();
     int t0 = blockIdx.x * chunk, t1 = min(t0 + chunk, cells);
     int n = 0;
     for (int t = t0 + (int)threadIdx.x; t < t1; t += CUT_T) {
         int lin;
-        n += box_cell_cut(g, L, R, t, lin) ? 1 : 0;
+        n += box_cell_in(pred, R, t, lin) ? 1 : 0;
     }
     __shared__ int s[CUT_T];
     s[threadIdx.x] = n;
@@ -62,10 +72,11 @@ __global__ __launch_bounds__(CUT_T) void k_cut_scan(int nb, int* __restrict__ co
     }
 }
 
-// Block b writes its chunk's cut cells from offset counts[b] on, in increasing order:
-// CUT_T cells at a time, each wavefront's cut lanes counted with a ballot.
-__global__ __launch_bounds__(CUT_T) void k_cut_write(Grid g, Level L, Box R, int chunk,
-                                                     const int* __restrict__ counts, int* __restrict__ out) {
+// Block b writes its chunk's listed cells from offset counts[b] on, in increasing order:
+// CUT_T cells at a time, each wavefront's listed lanes counted with a ballot.
+template <class P>
+__global__ __launch_bounds__(CUT_T) void k_list_write(P pred, Box R, int chunk, const int* __restrict__ counts,
+                                                      int* __restrict__ out) {
     __shared__ int wsum[CUT_T / WAVE];
     int cells = R.w() * R.h();
     int t0 = blockIdx.x * chunk, t1 = min(t0 + chunk, cells);
@@ -73,7 +84,7 @@ __global__ __launch_bounds__(CUT_T) void k_cut_write(Grid g, Level L, Box R, int
     int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     for (int s0 = t0; s0 < t1; s0 += CUT_T) {
         int t = s0 + (int)threadIdx.x, lin = 0;
-        bool cut = t < t1 && box_cell_cut(g, L, R, t, lin);
+        bool cut = t < t1 && box_cell_in(pred, R, t, lin);
         unsigned long long mask = __ballot(cut);
         if (lane == 0) wsum[wv] = __popcll(mask);
         __syncthreads();

@@ -22,37 +22,54 @@ struct LoadsArgs {
     double vx, vy, thd, cx, cy;  // rigid velocity v + thd z x (X - c) at time t
 };
 
+// A wall cell: fluid content and a non-zero effective wall normal (Nx, Ny).
+__device__ __forceinline__ bool wall_cell(const Grid& g, const Level& L, double al, double u0, int i, int j,
+                                          CellFaces& f, double& Nx, double& Ny) {
+    if (!(al > 0.0) || !(u0 > 0.0)) return false;
+    f = cell_faces(g, L, i, j);
+    Nx = (interval_beta(f.f[0]) - interval_beta(f.f[1])) * g.hy;
+    Ny = (interval_beta(f.f[2]) - interval_beta(f.f[3])) * g.hx;
+    return !(Nx == 0.0 && Ny == 0.0);
+}
+
+// p* of wall cell (i, j) (linear index k) and its wall point (wx, wy).
+template <typename R>
+__device__ __forceinline__ double wall_pressure(const LoadsArgs& a, const R* __restrict__ U, int i, int j,
+                                                size_t k, double al, const CellFaces& f, double Nx, double Ny,
+                                                double& wx, double& wy) {
+    const Grid& g = a.g;
+    size_t nc = (size_t)g.nx * g.ny;
+    double q[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k] / al;
+    double nn = sqrt(Nx * Nx + Ny * Ny);
+    wall_point(g, f, i, j, &wx, &wy);
+    double uwx = a.vx - a.thd * (wy - a.cy);
+    double uwy = a.vy + a.thd * (wx - a.cx);
+    double ps, rs;
+    wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, g.gamma, &ps, &rs);
+    return ps;
+}
+
 template <typename R>
 __global__ __launch_bounds__(LOADS_T) void k_loads(LoadsArgs a, const R* __restrict__ U, double* __restrict__ part) {
     const Grid& g = a.g;
     int w = a.reg.w(), h = a.reg.h();
     int cells = w > 0 && h > 0 ? w * h : 0;
-    size_t nc = (size_t)g.nx * g.ny;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int t = blockIdx.x * LOADS_T + threadIdx.x; t < cells; t += gridDim.x * LOADS_T) {
         int i = a.reg.i0 + t % w, j = a.reg.j0 + t / w;
         size_t k = (size_t)j * g.nx + i;
         double al = a.L.alpha[k];
-        double u0 = (double)U[k];
-        if (!(al > 0.0) || !(u0 > 0.0)) continue;
-        CellFaces f = cell_faces(g, a.L, i, j);
-        double Nx = (interval_beta(f.f[0]) - interval_beta(f.f[1])) * g.hy;
-        double Ny = (interval_beta(f.f[2]) - interval_beta(f.f[3])) * g.hx;
-        if (Nx == 0.0 && Ny == 0.0) continue;
-        double q[4];
-#pragma unroll
-        for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k] / al;
-        double nn = sqrt(Nx * Nx + Ny * Ny);
+        CellFaces f;
+        double Nx, Ny;
+        if (!wall_cell(g, a.L, al, (double)U[k], i, j, f, Nx, Ny)) continue;
         double wx, wy;
-        wall_point(g, f, i, j, &wx, &wy);
-        double uwx = a.vx - a.thd * (wy - a.cy);
-        double uwy = a.vy + a.thd * (wx - a.cx);
-        double ps, rs;
-        wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, g.gamma, &ps, &rs);
+        double ps = wall_pressure(a, U, i, j, k, al, f, Nx, Ny, wx, wy);
         acc[0] += ps * Nx;
         acc[1] += ps * Ny;
         acc[2] += (wx - a.cx) * (ps * Ny) - (wy - a.cy) * (ps * Nx);
-        acc[3] += ps * nn;
+        acc[3] += ps * sqrt(Nx * Nx + Ny * Ny);
     }
     __shared__ double sh[4][LOADS_T];
 #pragma unroll
@@ -73,6 +90,46 @@ __global__ void k_loads_final(int nblocks, const double* __restrict__ part, doub
     double s = 0.0;
     for (int b = 0; b < nblocks; b++) s += part[4 * b + threadIdx.x];
     out[threadIdx.x] = s;
+}
+
+// The wall cells of level L for the list kernels (lists.h).
+template <typename R>
+struct WallCells {
+    Grid g;
+    Level L;
+    const R* U;
+    __device__ __forceinline__ bool operator()(int i, int j) const {
+        size_t k = (size_t)j * g.nx + i;
+        CellFaces f;
+        double Nx, Ny;
+        return wall_cell(g, L, L.alpha[k], (double)U[k], i, j, f, Nx, Ny);
+    }
+};
+
+// Record t of the wall pressure distribution: listed cell list[t] (t < min(*n, max)) as
+// six values: linear index, wall point x and y, p*, Nx, Ny.
+template <typename R>
+__global__ __launch_bounds__(LOADS_T) void k_wall_records(LoadsArgs a, const R* __restrict__ U,
+                                                          const int* __restrict__ list, const int* __restrict__ n,
+                                                          int max, double* __restrict__ out) {
+    int t = blockIdx.x * LOADS_T + threadIdx.x;
+    int cnt = *n < max ? *n : max;
+    if (t >= cnt) return;
+    int k = list[t];
+    int i = k % a.g.nx, j = k / a.g.nx;
+    double al = a.L.alpha[k];
+    CellFaces f;
+    double Nx = 0.0, Ny = 0.0;
+    (void)wall_cell(a.g, a.L, al, (double)U[k], i, j, f, Nx, Ny);
+    double wx, wy;
+    double ps = wall_pressure(a, U, i, j, (size_t)k, al, f, Nx, Ny, wx, wy);
+    double* r = out + 6 * (size_t)t;
+    r[0] = (double)k;
+    r[1] = wx;
+    r[2] = wy;
+    r[3] = ps;
+    r[4] = Nx;
+    r[5] = Ny;
 }
 
 }  // namespace cc

@@ -368,3 +368,25 @@ def test_surface_loads_match_oracle(name, w, nsteps, precision):
     assert lo[3] > 0.0
     assert abs(lg[0] - lo[0]) <= tol * lo[3] and abs(lg[1] - lo[1]) <= tol * lo[3], (name, lg, lo)
     assert abs(lg[2] - lo[2]) <= tol * lo[3] * size and abs(lg[3] - lo[3]) <= tol * lo[3], (name, lg, lo)
+
+
+@pytest.mark.parametrize("precision", [cc.CC_FP64, cc.CC_FP32_GEOM64])
+@pytest.mark.parametrize("name,w,nsteps", list(loads_cases()), ids=[c[0] for c in loads_cases()])
+def test_surface_pressure_matches_oracle(name, w, nsteps, precision):
+    """The wall pressure distribution from identical states: the same wall cells in the
+    same order (bit-exact indices), wall points and normals to round-off, p* to round-off in
+    FP64 and to the state's FP32 rounding otherwise (relative to the largest p*)."""
+    o, s = pair(w, precision)
+    for _ in range(nsteps):
+        o.step(o.cfl_dt(w["cfl"]))
+    s.set_clock(o.t, o.steps)
+    s.set_u(o.get_u())
+    ro, rg = o.surface_pressure(), s.surface_pressure()
+    assert len(ro) > 0 and np.array_equal(rg[:, 0], ro[:, 0]), name
+    g = w["grid"]
+    size = max(g["x_hi"] - g["x_lo"], g["y_hi"] - g["y_lo"])
+    h = size / max(g["nx"], g["ny"])
+    assert np.abs(rg[:, 1:3] - ro[:, 1:3]).max() <= 1e-12 * size, name
+    assert np.abs(rg[:, 4:6] - ro[:, 4:6]).max() <= 1e-12 * h, name
+    tol = 1e-12 if precision == cc.CC_FP64 else 1e-5
+    assert np.abs(rg[:, 3] - ro[:, 3]).max() <= tol * np.abs(ro[:, 3]).max(), name

@@ -8,7 +8,9 @@ what the geometry and the gas dynamics fix:
   normals telescope to the face's length inside the domain, L = H / cos(angle), and the
   moment about the face's mid point vanishes (the cells are point-symmetric about it);
 * a piston driven into gas at rest feels the exact post-shock pressure on its face
-  (Sec. 3.2's piston problem).
+  (Sec. 3.2's piston problem);
+* the wall pressure distribution lists the terms the loads sum: at rest every wall cell's
+  p* is the gas pressure, and the records' sums reproduce the force and moment.
 """
 import math
 
@@ -63,3 +65,32 @@ def test_no_body_no_loads():
     w = {**W.cylinder(nx=32, ny=16), "body": None}
     o = make(w)
     assert np.array_equal(o.surface_loads(), np.zeros(4))
+
+
+def test_pressure_distribution_lists_the_terms_of_the_loads():
+    # at rest: p* = p in every wall cell, the normals sum to zero around the closed body
+    w = W.cylinder(nx=128, ny=64, speed=0.0, alpha_min=0.0)
+    o = make(w, W.uniform_prim(w["grid"], 1.0, 0.0, 0.0, 1.3))
+    r = o.surface_pressure()
+    assert len(r) > 30 and np.all(np.diff(r[:, 0]) > 0)  # increasing cell index
+    assert np.abs(r[:, 3] - 1.3).max() <= 1e-13
+    # a moving, pitching body in a stream: the records' sums are the loads
+    w = W.naca(nx=192, ny=192)
+    w["body"]["pitch_amp"] = math.radians(6.0)
+    w["body"]["pitch_omega"] = 1.5
+    o = make(w)
+    for _ in range(6):
+        o.step(o.cfl_dt(w["cfl"]))
+    r = o.surface_pressure()
+    fx, fy, mz, scale = o.surface_loads()
+    cx, cy = w["body"]["ref"]
+    assert abs((r[:, 3] * r[:, 4]).sum() - fx) <= 1e-13 * scale
+    assert abs((r[:, 3] * r[:, 5]).sum() - fy) <= 1e-13 * scale
+    m = ((r[:, 1] - cx) * (r[:, 3] * r[:, 5]) - (r[:, 2] - cy) * (r[:, 3] * r[:, 4])).sum()
+    assert abs(m - mz) <= 1e-13 * scale
+    # wall points lie in their cells
+    g = w["grid"]
+    hx, hy = (g["x_hi"] - g["x_lo"]) / g["nx"], (g["y_hi"] - g["y_lo"]) / g["ny"]
+    i, j = r[:, 0].astype(int) % g["nx"], r[:, 0].astype(int) // g["nx"]
+    assert np.all(r[:, 1] >= g["x_lo"] + i * hx - 1e-12) and np.all(r[:, 1] <= g["x_lo"] + (i + 1) * hx + 1e-12)
+    assert np.all(r[:, 2] >= g["y_lo"] + j * hy - 1e-12) and np.all(r[:, 2] <= g["y_lo"] + (j + 1) * hy + 1e-12)
