@@ -55,21 +55,36 @@ enum { FLUID = 0, SOLID = 1 };
  * faces, the shielded volume, the wall flag and the state flag (7). */
 #define TRACE_N 31
 
+/* Several bodies (reading R30): the solid region is the union of up to CCREF_MAX_BODIES
+ * closed convex polygons, each with its own prescribed motion.  Bodies must not meet
+ * inside one face or one cell: a face with solid parts from two bodies, a cell with
+ * solid area from two bodies, or a wall cell cut by one body at the sweep's start and by
+ * another at its end sets status bit 4. */
+#define CCREF_MAX_BODIES 4
+
 typedef struct {
     int8_t* vcls;  /* (ny+1)*(nx+1) vertex classes */
     double* fx;    /* 2*ny*(nx+1) solid intervals of x-faces (face (i,j) between cells (i-1,j),(i,j)) */
     double* fy;    /* 2*(ny+1)*nx solid intervals of y-faces (face (i,j) between cells (i,j-1),(i,j)) */
     double* alpha; /* ny*nx volume fractions */
-    double* poly;  /* posed polygon of this level */
-    int m;
+    int np;        /* posed polygons of this level (one per body) */
+    double* poly[CCREF_MAX_BODIES];
+    int m[CCREF_MAX_BODIES];
+    int8_t* cbody; /* several bodies: the body cutting each cut cell, -1 elsewhere (else NULL) */
 } level_t;
+
+typedef struct {
+    int m;              /* polygon vertex count, 0 = no body */
+    double* bverts;     /* body-frame polygon */
+    double ref_x, ref_y, theta0, vx, vy, amp, omega;
+    double cosd, sind, c0x, c0y, c1x, c1y; /* rigid map of the current step */
+} body_t;
 
 typedef struct {
     ccref_config cfg;
     double hx, hy;
-    int m;              /* polygon vertex count, 0 = no body */
-    double* bverts;     /* body-frame polygon */
-    double ref_x, ref_y, theta0, vx, vy, amp, omega;
+    int nb;             /* bodies (1 for a context without a body: B[0].m = 0) */
+    body_t B[CCREF_MAX_BODIES];
     double* U;          /* 4*ny*nx conserved amount per unit CELL volume, planes rho,mx,my,E */
     level_t L[3];       /* level slots */
     int s0, sm, s1;     /* slots of level n, stage level, level n+1 */
@@ -79,7 +94,6 @@ typedef struct {
     /* step-in-progress bookkeeping */
     int in_step, sweeps_done;
     double step_dt;
-    double cosd, sind, c0x, c0y, c1x, c1y; /* rigid map of the step */
     /* cell state stored on the step's first sweep (advective boundary state, per cell) */
     double* Q0;
     int64_t* stamp0;
@@ -409,35 +423,97 @@ static void wall_point(const ccref_ctx* c, const level_t* L, int i, int j, doubl
     *wy = sy / (double)n;
 }
 
-static void compute_level(ccref_ctx* c, const double* pv, int m, level_t* L) {
+/* Closed bounding boxes of polygon P and of the rectangle [x0, x1] x [y0, y1] are disjoint. */
+static int rect_misses(const poly_t* P, double x0, double y0, double x1, double y1) {
+    return P->m == 0 || x1 < P->xmin || x0 > P->xmax || y1 < P->ymin || y0 > P->ymax;
+}
+
+/* Solid interval of the face A->B with several bodies (reading R30): the one body whose
+ * polygon meets the face in a segment of positive length (ends classified against that
+ * body); *bad is set when two bodies do.  With one body: face_interval with the level's
+ * vertex classes (ca, cb). */
+static void face_interval_any(const poly_t* P, int np, double ax, double ay, int ca, double bx,
+                              double by, int cb, double* lo, double* hi, int* bad) {
+    if (np == 1) {
+        face_interval(&P[0], ax, ay, ca, bx, by, cb, lo, hi);
+        return;
+    }
+    *lo = 0.0;
+    *hi = 0.0;
+    int hits = 0;
+    for (int b = 0; b < np; b++) {
+        double l, h;
+        face_interval(&P[b], ax, ay, classify(&P[b], ax, ay), bx, by, classify(&P[b], bx, by), &l, &h);
+        if (h > l) {
+            if (hits == 0) {
+                *lo = l;
+                *hi = h;
+            }
+            hits++;
+        }
+    }
+    if (hits > 1) *bad = 1;
+}
+
+/* Body of cut cell (i, j) with several bodies: the first whose polygon covers part of the
+ * cell (area[b] > 0), else the first that closes part of one of its faces, else 0. */
+static int cell_body(const ccref_ctx* c, const poly_t* P, int np, const double* area, int i, int j) {
+    for (int b = 0; b < np; b++)
+        if (area[b] > 0.0) return b;
+    double x0 = vx_of(c, i), x1 = vx_of(c, i + 1), y0 = vy_of(c, j), y1 = vy_of(c, j + 1);
+    double seg[4][4] = {{x0, y0, x0, y1}, {x1, y0, x1, y1}, {x0, y0, x1, y0}, {x0, y1, x1, y1}};
+    for (int b = 0; b < np; b++)
+        for (int e = 0; e < 4; e++) {
+            const double* q = seg[e];
+            double l, h;
+            face_interval(&P[b], q[0], q[1], classify(&P[b], q[0], q[1]), q[2], q[3],
+                          classify(&P[b], q[2], q[3]), &l, &h);
+            if (h > l) return b;
+        }
+    return 0;
+}
+
+/* Geometry of a level from np posed polygons (one per body). */
+static void compute_level(ccref_ctx* c, const double* const* pv, const int* pm, int np, level_t* L) {
     int nx = c->cfg.nx, ny = c->cfg.ny;
-    memcpy(L->poly, pv, sizeof(double) * 2 * (size_t)m);
-    L->m = m;
-    poly_t P;
-    poly_init(&P, L->poly, m);
+    poly_t P[CCREF_MAX_BODIES];
+    int mmax = 1;
+    L->np = np;
+    for (int b = 0; b < np; b++) {
+        L->poly[b] = realloc(L->poly[b], sizeof(double) * 2 * (size_t)(pm[b] > 0 ? pm[b] : 1));
+        if (pm[b] > 0) memcpy(L->poly[b], pv[b], sizeof(double) * 2 * (size_t)pm[b]);
+        L->m[b] = pm[b];
+        poly_init(&P[b], L->poly[b], pm[b]);
+        if (pm[b] > mmax) mmax = pm[b];
+    }
+    int bad = 0;
     /* every loop below writes each item once from the level's inputs only: the rows may
      * run in any order (OpenMP build) with identical results */
 #pragma omp parallel for schedule(static)
     for (int j = 0; j <= ny; j++)
-        for (int i = 0; i <= nx; i++) L->vcls[VIDX(c, i, j)] = (int8_t)classify(&P, vx_of(c, i), vy_of(c, j));
-#pragma omp parallel for schedule(static)
+        for (int i = 0; i <= nx; i++) {
+            int cls = FLUID;
+            for (int b = 0; b < np && cls == FLUID; b++) cls = classify(&P[b], vx_of(c, i), vy_of(c, j));
+            L->vcls[VIDX(c, i, j)] = (int8_t)cls;
+        }
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i <= nx; i++) {
             size_t f = BXIDX(c, i, j);
-            face_interval(&P, vx_of(c, i), vy_of(c, j), L->vcls[VIDX(c, i, j)], vx_of(c, i),
-                          vy_of(c, j + 1), L->vcls[VIDX(c, i, j + 1)], &L->fx[2 * f], &L->fx[2 * f + 1]);
+            face_interval_any(P, np, vx_of(c, i), vy_of(c, j), L->vcls[VIDX(c, i, j)], vx_of(c, i),
+                              vy_of(c, j + 1), L->vcls[VIDX(c, i, j + 1)], &L->fx[2 * f], &L->fx[2 * f + 1], &bad);
         }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int j = 0; j <= ny; j++)
         for (int i = 0; i < nx; i++) {
             size_t f = BYIDX(c, i, j);
-            face_interval(&P, vx_of(c, i), vy_of(c, j), L->vcls[VIDX(c, i, j)], vx_of(c, i + 1),
-                          vy_of(c, j), L->vcls[VIDX(c, i + 1, j)], &L->fy[2 * f], &L->fy[2 * f + 1]);
+            face_interval_any(P, np, vx_of(c, i), vy_of(c, j), L->vcls[VIDX(c, i, j)], vx_of(c, i + 1),
+                              vy_of(c, j), L->vcls[VIDX(c, i + 1, j)], &L->fy[2 * f], &L->fy[2 * f + 1], &bad);
         }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int j = 0; j < ny; j++) {
-        double* b1 = malloc(sizeof(double) * 2 * (size_t)(m + 8));
-        double* b2 = malloc(sizeof(double) * 2 * (size_t)(m + 8));
+        double* b1 = malloc(sizeof(double) * 2 * (size_t)(mmax + 8));
+        double* b2 = malloc(sizeof(double) * 2 * (size_t)(mmax + 8));
         for (int i = 0; i < nx; i++) {
             double b[4] = {beta_x(c, L, i, j), beta_x(c, L, i + 1, j), beta_y(c, L, i, j),
                            beta_y(c, L, i, j + 1)};
@@ -447,45 +523,68 @@ static void compute_level(ccref_ctx* c, const double* pv, int m, level_t* L) {
                 zeros += b[k] == 0.0;
             }
             double a;
+            int body = -1;
             if (ones == 4) {
                 a = 1.0;
             } else if (zeros == 4) {
                 a = 0.0;
             } else {
-                double s = clip_area(L->poly, m, vx_of(c, i), vy_of(c, j), c->hx, c->hy, b1, b2);
+                double s;
+                if (np == 1) {
+                    s = clip_area(L->poly[0], pm[0], vx_of(c, i), vy_of(c, j), c->hx, c->hy, b1, b2);
+                } else {
+                    /* several bodies: the solid area is the sum of the bodies' areas in the
+                     * cell, at most one of which may be positive */
+                    double ab[CCREF_MAX_BODIES];
+                    int hits = 0;
+                    s = 0.0;
+                    for (int q = 0; q < np; q++) {
+                        ab[q] = 0.0;
+                        if (!rect_misses(&P[q], vx_of(c, i), vy_of(c, j), vx_of(c, i) + c->hx, vy_of(c, j) + c->hy))
+                            ab[q] = clip_area(L->poly[q], pm[q], vx_of(c, i), vy_of(c, j), c->hx, c->hy, b1, b2);
+                        hits += ab[q] > 0.0;
+                        s += ab[q];
+                    }
+                    if (hits > 1) bad = 1;
+                    body = cell_body(c, P, np, ab, i, j);
+                }
                 a = 1.0 - s / (c->hx * c->hy);
                 if (a < 0.0) a = 0.0;
                 if (a > 1.0) a = 1.0;
                 if (a < c->cfg.alpha_min) a = 0.0; /* small-cell threshold (reading R19) */
             }
             L->alpha[CIDX(c, i, j)] = a;
+            if (L->cbody) L->cbody[CIDX(c, i, j)] = (int8_t)body;
         }
         free(b1);
         free(b2);
     }
+    if (bad) c->status |= 4;
 }
 
 /* ------------------------------------------------------------------------------------ */
 /* Body pose and prescribed rigid motion.                                               */
 /* theta(t) = theta0 + A sin(omega t), centre c(t) = ref + v t.                          */
 /* ------------------------------------------------------------------------------------ */
-static void pose(const ccref_ctx* c, double t, double* out) {
-    double th = c->theta0 + c->amp * sin(c->omega * t);
+static void pose(const ccref_ctx* c, int b, double t, double* out) {
+    const body_t* B = &c->B[b];
+    double th = B->theta0 + B->amp * sin(B->omega * t);
     double cs = cos(th), sn = sin(th);
-    double cx = c->ref_x + c->vx * t, cy = c->ref_y + c->vy * t;
-    for (int k = 0; k < c->m; k++) {
-        double bx = c->bverts[2 * k], by = c->bverts[2 * k + 1];
+    double cx = B->ref_x + B->vx * t, cy = B->ref_y + B->vy * t;
+    for (int k = 0; k < B->m; k++) {
+        double bx = B->bverts[2 * k], by = B->bverts[2 * k + 1];
         out[2 * k] = (cs * bx - sn * by) + cx;
         out[2 * k + 1] = (sn * bx + cs * by) + cy;
     }
 }
 
 /* Rigid-body velocity at point (x, y) at time t. */
-static void body_velocity(const ccref_ctx* c, double t, double x, double y, double* ux, double* uy) {
-    double thd = c->amp * c->omega * cos(c->omega * t);
-    double cx = c->ref_x + c->vx * t, cy = c->ref_y + c->vy * t;
-    *ux = c->vx - thd * (y - cy);
-    *uy = c->vy + thd * (x - cx);
+static void body_velocity(const ccref_ctx* c, int b, double t, double x, double y, double* ux, double* uy) {
+    const body_t* B = &c->B[b];
+    double thd = B->amp * B->omega * cos(B->omega * t);
+    double cx = B->ref_x + B->vx * t, cy = B->ref_y + B->vy * t;
+    *ux = B->vx - thd * (y - cy);
+    *uy = B->vy + thd * (x - cx);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -497,9 +596,12 @@ static int level_alloc(ccref_ctx* c, level_t* L) {
     L->fx = calloc(2 * ny * (nx + 1), sizeof(double));
     L->fy = calloc(2 * (ny + 1) * nx, sizeof(double));
     L->alpha = calloc(nx * ny, sizeof(double));
-    L->poly = calloc(2 * (size_t)(c->m > 0 ? c->m : 1), sizeof(double));
-    L->m = 0;
-    return L->vcls && L->fx && L->fy && L->alpha && L->poly;
+    L->np = 0;
+    if (c->nb > 1) {
+        L->cbody = malloc(nx * ny);
+        if (L->cbody) memset(L->cbody, 0xff, nx * ny);
+    }
+    return L->vcls && L->fx && L->fy && L->alpha && (c->nb == 1 || L->cbody);
 }
 
 void ccref_destroy(ccref_ctx* c) {
@@ -509,34 +611,44 @@ void ccref_destroy(ccref_ctx* c) {
         free(c->L[s].fx);
         free(c->L[s].fy);
         free(c->L[s].alpha);
-        free(c->L[s].poly);
+        free(c->L[s].cbody);
+        for (int b = 0; b < CCREF_MAX_BODIES; b++) free(c->L[s].poly[b]);
     }
     free(c->U);
-    free(c->bverts);
+    for (int b = 0; b < CCREF_MAX_BODIES; b++) free(c->B[b].bverts);
     free(c->Q0);
     free(c->stamp0);
     free(c);
 }
 
-ccref_ctx* ccref_create(const ccref_config* cfg, const ccref_body* body) {
+/* A context with nbodies bodies (0 or NULL: none; several: reading R30, each with at
+ * least three vertices). */
+ccref_ctx* ccref_create_bodies(const ccref_config* cfg, const ccref_body* bodies, int nbodies) {
     if (cfg->nx < 1 || cfg->ny < 1 || !(cfg->x_hi > cfg->x_lo) || !(cfg->y_hi > cfg->y_lo)) return NULL;
     if (!(cfg->alpha_min >= 0.0 && cfg->alpha_min < 0.5)) return NULL;
+    if (nbodies < 0 || nbodies > CCREF_MAX_BODIES || (nbodies > 0 && !bodies)) return NULL;
+    for (int b = 0; nbodies > 1 && b < nbodies; b++)
+        if (bodies[b].nverts < 3) return NULL;
     ccref_ctx* c = calloc(1, sizeof(ccref_ctx));
     if (!c) return NULL;
     c->cfg = *cfg;
     c->hx = (cfg->x_hi - cfg->x_lo) / (double)cfg->nx;
     c->hy = (cfg->y_hi - cfg->y_lo) / (double)cfg->ny;
-    c->m = body ? body->nverts : 0;
-    if (c->m > 0) {
-        c->bverts = malloc(sizeof(double) * 2 * c->m);
-        memcpy(c->bverts, body->verts, sizeof(double) * 2 * c->m);
-        c->ref_x = body->ref_x;
-        c->ref_y = body->ref_y;
-        c->theta0 = body->theta0;
-        c->vx = body->vx;
-        c->vy = body->vy;
-        c->amp = body->pitch_amp;
-        c->omega = body->pitch_omega;
+    c->nb = nbodies > 1 ? nbodies : 1;
+    for (int b = 0; b < nbodies; b++) {
+        const ccref_body* body = &bodies[b];
+        body_t* B = &c->B[b];
+        B->m = body->nverts > 0 ? body->nverts : 0;
+        if (B->m == 0) continue;
+        B->bverts = malloc(sizeof(double) * 2 * B->m);
+        memcpy(B->bverts, body->verts, sizeof(double) * 2 * B->m);
+        B->ref_x = body->ref_x;
+        B->ref_y = body->ref_y;
+        B->theta0 = body->theta0;
+        B->vx = body->vx;
+        B->vy = body->vy;
+        B->amp = body->pitch_amp;
+        B->omega = body->pitch_omega;
     }
     size_t nc = (size_t)cfg->nx * cfg->ny;
     c->U = calloc(4 * nc, sizeof(double));
@@ -556,12 +668,30 @@ ccref_ctx* ccref_create(const ccref_config* cfg, const ccref_body* body) {
     return c;
 }
 
-static void level_at_time(ccref_ctx* c, double t, level_t* L) {
-    double* pv = malloc(sizeof(double) * 2 * (c->m > 0 ? c->m : 1));
-    pose(c, t, pv);
-    compute_level(c, pv, c->m, L);
-    free(pv);
+ccref_ctx* ccref_create(const ccref_config* cfg, const ccref_body* body) {
+    return ccref_create_bodies(cfg, body, body ? 1 : 0);
 }
+
+/* The bodies posed at time t (x coordinates at tx, y coordinates at ty: the stage level of
+ * a split step mixes the two, reading R11) and the level's geometry from them. */
+static void level_posed(ccref_ctx* c, double tx, double ty, level_t* L) {
+    double* pv[CCREF_MAX_BODIES];
+    int pm[CCREF_MAX_BODIES];
+    for (int b = 0; b < c->nb; b++) {
+        int m = c->B[b].m;
+        pm[b] = m;
+        pv[b] = malloc(sizeof(double) * 2 * (m > 0 ? m : 1));
+        double* py = malloc(sizeof(double) * 2 * (m > 0 ? m : 1));
+        pose(c, b, tx, pv[b]);
+        pose(c, b, ty, py);
+        for (int k = 0; k < m; k++) pv[b][2 * k + 1] = py[2 * k + 1];
+        free(py);
+    }
+    compute_level(c, (const double* const*)pv, pm, c->nb, L);
+    for (int b = 0; b < c->nb; b++) free(pv[b]);
+}
+
+static void level_at_time(ccref_ctx* c, double t, level_t* L) { level_posed(c, t, t, L); }
 
 /* Initial state from primitive fields (rho, u, v, p) given per cell: U = alpha * Q. */
 int ccref_set_prim(ccref_ctx* c, const double* prim, double t0) {
@@ -640,17 +770,17 @@ static int slot_of(const ccref_ctx* c, int which) {
     return which == 0 ? c->s0 : which == 1 ? c->sm : which == 2 ? c->s1 : -1;
 }
 
-/* Posed polygon at time t into out (2*m doubles); returns m. */
+/* Posed polygon of body 0 at time t into out (2*m doubles); returns m. */
 int ccref_pose(const ccref_ctx* c, double t, double* out) {
-    pose(c, t, out);
-    return c->m;
+    pose(c, 0, t, out);
+    return c->B[0].m;
 }
 
 /* Geometry of an arbitrary posed polygon into slot (for geometry tests). */
 int ccref_geometry_poly(ccref_ctx* c, const double* posed, int m, int which) {
     int slot = slot_of(c, which);
     if (slot < 0) return 1;
-    compute_level(c, posed, m, &c->L[slot]);
+    compute_level(c, &posed, &m, 1, &c->L[slot]);
     return 0;
 }
 /* Geometry of the body posed at time t into slot. */
@@ -728,12 +858,14 @@ int ccref_wave_speeds(const ccref_ctx* c, double* sxy) {
         sx = fmax(sx, fabs(u) + a);
         sy = fmax(sy, fabs(v) + a);
     }
-    if (c->m > 0) {
-        double* pv = malloc(sizeof(double) * 2 * c->m);
-        pose(c, c->t, pv);
-        for (int k = 0; k < c->m; k++) {
+    for (int b = 0; b < c->nb; b++) {
+        int m = c->B[b].m;
+        if (m == 0) continue;
+        double* pv = malloc(sizeof(double) * 2 * m);
+        pose(c, b, c->t, pv);
+        for (int k = 0; k < m; k++) {
             double ux, uy;
-            body_velocity(c, c->t, pv[2 * k], pv[2 * k + 1], &ux, &uy);
+            body_velocity(c, b, c->t, pv[2 * k], pv[2 * k + 1], &ux, &uy);
             sx = fmax(sx, fabs(ux));
             sy = fmax(sy, fabs(uy));
         }
@@ -823,12 +955,13 @@ static double beta_avg_y(const ccref_ctx* c, const level_t* Ls, const level_t* L
     return 0.5 * (beta_y(c, Ls, i, j) + beta_y(c, Le, i, j));
 }
 
-/* Displacement, in direction d, of the body point at (x, y) under the step's rigid map
- * M(X) = R(theta1 - theta0) (X - c0) + c1. */
-static double step_disp(const ccref_ctx* c, int d, double x, double y) {
-    double dx = x - c->c0x, dy = y - c->c0y;
-    if (d == 0) return ((c->cosd * dx - c->sind * dy) + c->c1x) - x;
-    return ((c->sind * dx + c->cosd * dy) + c->c1y) - y;
+/* Displacement, in direction d, of the point at (x, y) of body b under the step's rigid
+ * map M(X) = R(theta1 - theta0) (X - c0) + c1. */
+static double step_disp(const ccref_ctx* c, int b, int d, double x, double y) {
+    const body_t* B = &c->B[b];
+    double dx = x - B->c0x, dy = y - B->c0y;
+    if (d == 0) return ((B->cosd * dx - B->sind * dy) + B->c1x) - x;
+    return ((B->sind * dx + B->cosd * dy) + B->c1y) - y;
 }
 
 /* Exact time average over the sweep of the aperture of a face normal to the sweep
@@ -843,7 +976,7 @@ static double swept_beta(const ccref_ctx* c, const level_t* Ls, const level_t* L
     if (Ps->m == 0) return 0.5 * (bs + be);
     double X = vx_of(c, i), Y = vy_of(c, j);
     double h = dir == 0 ? c->hx : c->hy, hf = dir == 0 ? c->hy : c->hx;
-    double D = dir == 0 ? step_disp(c, 0, X, Y + 0.5 * c->hy) : step_disp(c, 1, X + 0.5 * c->hx, Y);
+    double D = dir == 0 ? step_disp(c, 0, 0, X, Y + 0.5 * c->hy) : step_disp(c, 0, 1, X + 0.5 * c->hx, Y);
     if (!(fabs(D) > 1e-12 * h)) return 0.5 * (bs + be);
     double w = fabs(D);
     double x0, y0, sw, sh;
@@ -861,6 +994,54 @@ static double swept_beta(const ccref_ctx* c, const level_t* Ls, const level_t* L
     if (x0 + sw < Ps->xmin || x0 > Ps->xmax || y0 + sh < Ps->ymin || y0 > Ps->ymax) return 1.0;
     double a = clip_area(Ps->v, Ps->m, x0, y0, sw, sh, b1, b2);
     double bt = 1.0 - a / (w * hf);
+    if (bt < 0.0) bt = 0.0;
+    if (bt > 1.0) bt = 1.0;
+    return bt;
+}
+
+/* The same with several bodies (reading R30): each body moves by its own displacement D_b
+ * at the face's midpoint, so the face's solid length integrated over the sweep is the sum
+ * over the bodies of area(P_b at level s inside the strip of width |D_b|) / |D_b|, times
+ * the sweep's duration; a body that does not move there contributes the average of its
+ * solid fractions of the face at the two levels. */
+static double seg_solid(const poly_t* P, double ax, double ay, double bx, double by) {
+    double l, h;
+    face_interval(P, ax, ay, classify(P, ax, ay), bx, by, classify(P, bx, by), &l, &h);
+    return h > l ? h - l : 0.0;
+}
+static double swept_beta_bodies(const ccref_ctx* c, const level_t* Ls, const level_t* Le,
+                                const poly_t* Ps, const poly_t* Pe, int dir, int i, int j,
+                                double* b1, double* b2) {
+    double bs = dir == 0 ? beta_x(c, Ls, i, j) : beta_y(c, Ls, i, j);
+    double be = dir == 0 ? beta_x(c, Le, i, j) : beta_y(c, Le, i, j);
+    if (bs == 0.0 && be == 0.0) return 0.0; /* covered throughout (bodies apart) */
+    double X = vx_of(c, i), Y = vy_of(c, j);
+    double h = dir == 0 ? c->hx : c->hy, hf = dir == 0 ? c->hy : c->hx;
+    double ax = X, ay = Y, fx = dir == 0 ? X : X + c->hx, fy = dir == 0 ? Y + c->hy : Y;
+    double solid = 0.0;
+    for (int b = 0; b < Ls->np; b++) {
+        double D = dir == 0 ? step_disp(c, b, 0, X, Y + 0.5 * c->hy) : step_disp(c, b, 1, X + 0.5 * c->hx, Y);
+        if (!(fabs(D) > 1e-12 * h)) {
+            solid += 0.5 * (seg_solid(&Ps[b], ax, ay, fx, fy) + seg_solid(&Pe[b], ax, ay, fx, fy));
+            continue;
+        }
+        double w = fabs(D);
+        double x0, y0, sw, sh;
+        if (dir == 0) {
+            x0 = D > 0.0 ? X - D : X;
+            y0 = Y;
+            sw = w;
+            sh = hf;
+        } else {
+            x0 = X;
+            y0 = D > 0.0 ? Y - D : Y;
+            sw = hf;
+            sh = w;
+        }
+        if (rect_misses(&Ps[b], x0, y0, x0 + sw, y0 + sh)) continue;
+        solid += clip_area(Ps[b].v, Ps[b].m, x0, y0, sw, sh, b1, b2) / (w * hf);
+    }
+    double bt = 1.0 - solid;
     if (bt < 0.0) bt = 0.0;
     if (bt > 1.0) bt = 1.0;
     return bt;
@@ -957,17 +1138,27 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
     size_t nfd = dir == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
     double* btd = malloc(sizeof(double) * nfd);
     {
-        poly_t Ps;
-        poly_init(&Ps, Ls->poly, Ls->m);
+        poly_t Ps[CCREF_MAX_BODIES], Pe[CCREF_MAX_BODIES];
+        int mmax = 1;
+        for (int b = 0; b < Ls->np; b++) {
+            poly_init(&Ps[b], Ls->poly[b], Ls->m[b]);
+            poly_init(&Pe[b], Le->poly[b], Le->m[b]);
+            if (Ls->m[b] > mmax) mmax = Ls->m[b];
+        }
         int rows = dir == 0 ? ny : ny + 1;
+        int multi = Ls->np > 1;
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < rows; j++) {
-            double* b1 = malloc(sizeof(double) * 2 * (size_t)(Ls->m + 8));
-            double* b2 = malloc(sizeof(double) * 2 * (size_t)(Ls->m + 8));
+            double* b1 = malloc(sizeof(double) * 2 * (size_t)(mmax + 8));
+            double* b2 = malloc(sizeof(double) * 2 * (size_t)(mmax + 8));
             if (dir == 0) {
-                for (int i = 0; i <= nx; i++) btd[BXIDX(c, i, j)] = swept_beta(c, Ls, Le, &Ps, 0, i, j, b1, b2);
+                for (int i = 0; i <= nx; i++)
+                    btd[BXIDX(c, i, j)] = multi ? swept_beta_bodies(c, Ls, Le, Ps, Pe, 0, i, j, b1, b2)
+                                                : swept_beta(c, Ls, Le, &Ps[0], 0, i, j, b1, b2);
             } else {
-                for (int i = 0; i < nx; i++) btd[BYIDX(c, i, j)] = swept_beta(c, Ls, Le, &Ps, 1, i, j, b1, b2);
+                for (int i = 0; i < nx; i++)
+                    btd[BYIDX(c, i, j)] = multi ? swept_beta_bodies(c, Ls, Le, Ps, Pe, 1, i, j, b1, b2)
+                                                : swept_beta(c, Ls, Le, &Ps[0], 1, i, j, b1, b2);
             }
             free(b1);
             free(b2);
@@ -978,8 +1169,9 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
     cellinfo* ci = calloc(nc, sizeof(cellinfo));
     double* Q = malloc(sizeof(double) * 4 * nc);
     unsigned char* has = calloc(nc, 1);
+    int bad_body = 0;
     /* each cell's quantities depend on its own inputs only (rows in any order) */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(| : bad_body)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
             size_t k = CIDX(c, i, j);
@@ -1031,7 +1223,15 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
             } else {
                 wall_point(c, Le, i, j, &wx, &wy);
             }
-            body_velocity(c, thalf, wx, wy, &e->uwx, &e->uwy);
+            /* the body that cuts the cell (several bodies: the one cutting it at level s,
+             * else at level e; reading R30) */
+            int body = 0;
+            if (Ls->cbody) {
+                int bs_ = Ls->cbody[k], be_ = Le->cbody[k];
+                body = cs && bs_ >= 0 ? bs_ : (be_ >= 0 ? be_ : 0);
+                if (cs && ce && bs_ >= 0 && be_ >= 0 && bs_ != be_) bad_body = 1;
+            }
+            body_velocity(c, body, thalf, wx, wy, &e->uwx, &e->uwy);
             double blo = dir == 0 ? bw : bs, bhi = dir == 0 ? be : bn;
             double mn = blo < bhi ? blo : bhi;
             double sh = fabs(bhi - blo);
@@ -1076,6 +1276,8 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
             e->fb[2] = ua * qb[2] + (dir == 1 ? pst : 0.0);
             e->fb[3] = ua * qb[3] + pst * us;
         }
+
+    if (bad_body) c->status |= 4;
 
     /* --- 4. line-by-line: standard fluxes, stabilised fluxes, update --- */
     double* U2 = malloc(sizeof(double) * 4 * nc);
@@ -1352,36 +1554,22 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
 int ccref_begin_step(ccref_ctx* c, double dt) {
     if (c->in_step || !(dt > 0.0)) return 1;
     double t1 = c->t + dt;
-    int m = c->m > 0 ? c->m : 1;
-    double* p0 = malloc(sizeof(double) * 2 * m);
-    double* p1 = malloc(sizeof(double) * 2 * m);
-    double* pm = malloc(sizeof(double) * 2 * m);
-    pose(c, c->t, p0);
-    pose(c, t1, p1);
-    for (int k = 0; k < c->m; k++) {
-        if (c->parity == 0) {
-            pm[2 * k] = p1[2 * k];
-            pm[2 * k + 1] = p0[2 * k + 1];
-        } else {
-            pm[2 * k] = p0[2 * k];
-            pm[2 * k + 1] = p1[2 * k + 1];
-        }
+    if (c->parity == 0)
+        level_posed(c, t1, c->t, &c->L[c->sm]);
+    else
+        level_posed(c, c->t, t1, &c->L[c->sm]);
+    level_at_time(c, t1, &c->L[c->s1]);
+    for (int b = 0; b < c->nb; b++) {
+        body_t* B = &c->B[b];
+        double th0 = B->theta0 + B->amp * sin(B->omega * c->t);
+        double th1 = B->theta0 + B->amp * sin(B->omega * t1);
+        B->cosd = cos(th1 - th0);
+        B->sind = sin(th1 - th0);
+        B->c0x = B->ref_x + B->vx * c->t;
+        B->c0y = B->ref_y + B->vy * c->t;
+        B->c1x = B->ref_x + B->vx * t1;
+        B->c1y = B->ref_y + B->vy * t1;
     }
-    compute_level(c, pm, c->m, &c->L[c->sm]);
-    compute_level(c, p1, c->m, &c->L[c->s1]);
-    {
-        double th0 = c->theta0 + c->amp * sin(c->omega * c->t);
-        double th1 = c->theta0 + c->amp * sin(c->omega * t1);
-        c->cosd = cos(th1 - th0);
-        c->sind = sin(th1 - th0);
-        c->c0x = c->ref_x + c->vx * c->t;
-        c->c0y = c->ref_y + c->vy * c->t;
-        c->c1x = c->ref_x + c->vx * t1;
-        c->c1y = c->ref_y + c->vy * t1;
-    }
-    free(p0);
-    free(p1);
-    free(pm);
     c->in_step = 1;
     c->sweeps_done = 0;
     c->step_dt = dt;
@@ -1425,11 +1613,11 @@ void ccref_wall_riemann(const double* q, double nx, double ny, double wx, double
 }
 /* Rigid-body velocity of the body point at (x, y) at time t (out2: ux, uy). */
 void ccref_body_velocity(const ccref_ctx* c, double t, double x, double y, double* out2) {
-    body_velocity(c, t, x, y, out2, out2 + 1);
+    body_velocity(c, 0, t, x, y, out2, out2 + 1);
 }
 /* Displacement along d of the point (x, y) under the rigid map of the open step. */
 double ccref_step_disp(const ccref_ctx* c, int d, double x, double y) {
-    return c->in_step ? step_disp(c, d, x, y) : NAN;
+    return c->in_step ? step_disp(c, 0, d, x, y) : NAN;
 }
 /* Record the sweep quantities of cell (i, j) in every later sweep (i < 0: stop). */
 int ccref_trace(ccref_ctx* c, int i, int j) {
@@ -1466,7 +1654,7 @@ double ccref_clip_area(const double* poly, int m, double ox, double oy, double w
  * wall Riemann problem and the normal N (Nx, Ny) -- the terms ccref_surface_loads sums.
  * Writes at most max records to out (6 max doubles); returns the number of records. */
 int ccref_surface_pressure(const ccref_ctx* c, double* out, int max) {
-    if (c->m == 0) return 0;
+    if (c->nb == 1 && c->B[0].m == 0) return 0;
     const level_t* L = &c->L[c->s0];
     size_t nc = (size_t)c->cfg.nx * c->cfg.ny;
     int n = 0;
@@ -1483,7 +1671,7 @@ int ccref_surface_pressure(const ccref_ctx* c, double* out, int max) {
             double nn = sqrt(Nx * Nx + Ny * Ny);
             double wx, wy, uwx, uwy, ps, rs;
             wall_point(c, L, i, j, &wx, &wy);
-            body_velocity(c, c->t, wx, wy, &uwx, &uwy);
+            body_velocity(c, L->cbody ? L->cbody[k] : 0, c->t, wx, wy, &uwx, &uwy);
             wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, c->cfg.gamma, &ps, &rs);
             if (n < max) {
                 double* r = out + 6 * (size_t)n;
@@ -1505,18 +1693,22 @@ int ccref_surface_pressure(const ccref_ctx* c, double* out, int max) {
  * mirror image moving with the body at the cell's wall point, N the level's effective wall
  * normal ((beta_W - beta_E) hy, (beta_S - beta_N) hx), pointing into the body, reading
  * R12).  out4: Fx, Fy, the moment about the body's pose origin, and sum p* |N|.  Plain
- * sums in row-major cell order. */
-int ccref_surface_loads(const ccref_ctx* c, double* out4) {
+ * sums in row-major cell order.  With several bodies: the loads on body b (the wall cells
+ * the body cuts at level n). */
+int ccref_surface_loads_body(const ccref_ctx* c, int b, double* out4) {
     for (int k = 0; k < 4; k++) out4[k] = 0.0;
-    if (c->m == 0) return 0;
+    if (b < 0 || b >= c->nb) return 1;
+    if (c->B[b].m == 0) return 0;
     const level_t* L = &c->L[c->s0];
     size_t nc = (size_t)c->cfg.nx * c->cfg.ny;
-    double cx = c->ref_x + c->vx * c->t, cy = c->ref_y + c->vy * c->t;
+    const body_t* B = &c->B[b];
+    double cx = B->ref_x + B->vx * c->t, cy = B->ref_y + B->vy * c->t;
     for (int j = 0; j < c->cfg.ny; j++)
         for (int i = 0; i < c->cfg.nx; i++) {
             size_t k = CIDX(c, i, j);
             double a = L->alpha[k];
             if (!(a > 0.0) || !(c->U[k] > 0.0)) continue;
+            if (L->cbody && L->cbody[k] != b) continue;
             double Nx = (beta_x(c, L, i, j) - beta_x(c, L, i + 1, j)) * c->hy;
             double Ny = (beta_y(c, L, i, j) - beta_y(c, L, i, j + 1)) * c->hx;
             if (Nx == 0.0 && Ny == 0.0) continue;
@@ -1525,12 +1717,25 @@ int ccref_surface_loads(const ccref_ctx* c, double* out4) {
             double nn = sqrt(Nx * Nx + Ny * Ny);
             double wx, wy, uwx, uwy, ps, rs;
             wall_point(c, L, i, j, &wx, &wy);
-            body_velocity(c, c->t, wx, wy, &uwx, &uwy);
+            body_velocity(c, b, c->t, wx, wy, &uwx, &uwy);
             wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, c->cfg.gamma, &ps, &rs);
             out4[0] += ps * Nx;
             out4[1] += ps * Ny;
             out4[2] += (wx - cx) * (ps * Ny) - (wy - cy) * (ps * Nx);
             out4[3] += ps * nn;
         }
+    return 0;
+}
+
+int ccref_surface_loads(const ccref_ctx* c, double* out4) { return ccref_surface_loads_body(c, 0, out4); }
+
+int ccref_nbodies(const ccref_ctx* c) { return c->nb; }
+
+/* Body of each cut cell of a level with several bodies (-1 elsewhere); returns 1 for a
+ * context with one body. */
+int ccref_cell_bodies(const ccref_ctx* c, int which, int8_t* out) {
+    int s = slot_of(c, which);
+    if (s < 0 || !c->L[s].cbody) return 1;
+    memcpy(out, c->L[s].cbody, (size_t)c->cfg.nx * c->cfg.ny);
     return 0;
 }

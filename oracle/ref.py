@@ -38,6 +38,11 @@ def lib(parallel=False):
         d, i, p, vp = C.c_double, C.c_int, C.POINTER(C.c_double), C.c_void_p
         L.ccref_create.restype = vp
         L.ccref_create.argtypes = [C.POINTER(_Config), C.POINTER(_Body)]
+        L.ccref_create_bodies.restype = vp
+        L.ccref_create_bodies.argtypes = [C.POINTER(_Config), C.POINTER(_Body), i]
+        L.ccref_surface_loads_body.argtypes = [vp, i, p]
+        L.ccref_nbodies.argtypes = [vp]
+        L.ccref_cell_bodies.argtypes = [vp, i, C.POINTER(C.c_int8)]
         L.ccref_destroy.argtypes = [vp]
         L.ccref_set_prim.argtypes = [vp, p, d]
         L.ccref_set_u.argtypes = [vp, p]
@@ -140,10 +145,24 @@ def wall_riemann(q, n, uw, gamma=1.4):
 
 
 # ---------------------------------------------------------------- simulation context
-class Oracle:
-    """One oracle simulation: a grid, a rigid body and the level-n state."""
+def _fill_body(b, body):
+    """Fill a _Body from a body dict; returns the vertex array it points to."""
+    verts = _f64(np.asarray(body["verts"]).reshape(-1))
+    b.nverts = len(verts) // 2
+    b.verts = _dp(verts)
+    b.ref_x, b.ref_y = body.get("ref", (0.0, 0.0))
+    b.theta0 = body.get("theta0", 0.0)
+    b.vx, b.vy = body.get("vel", (0.0, 0.0))
+    b.pitch_amp = body.get("pitch_amp", 0.0)
+    b.pitch_omega = body.get("pitch_omega", 0.0)
+    return verts
 
-    def __init__(self, grid, body=None, parallel=False):
+
+class Oracle:
+    """One oracle simulation: a grid, a rigid body (or `bodies`, a list of up to four
+    body dicts, each with its own motion) and the level-n state."""
+
+    def __init__(self, grid, body=None, parallel=False, bodies=None):
         self._L = lib(parallel)
         self.grid = dict(grid)
         cfg = _Config()
@@ -157,6 +176,15 @@ class Oracle:
         cfg.alpha_min = grid.get("alpha_min", 0.0)
         self.nx, self.ny = cfg.nx, cfg.ny
         self.gamma = cfg.gamma
+        if bodies is not None:
+            arr = (_Body * len(bodies))()
+            self._verts = [_fill_body(arr[k], bd) for k, bd in enumerate(bodies)]
+            self.m = sum(arr[k].nverts for k in range(len(bodies)))
+            h = self._L.ccref_create_bodies(C.byref(cfg), arr, len(bodies))
+            if not h:
+                raise ValueError("oracle: invalid configuration")
+            self._h = C.c_void_p(h)
+            return
         b = _Body()
         self._verts = None
         if body is not None and len(body["verts"]) > 0:
@@ -310,6 +338,24 @@ class Oracle:
         """(Fx, Fy, Mz about the pose origin, sum p*|N|) of the gas on the body at level n."""
         out = np.zeros(4)
         self._L.ccref_surface_loads(self._h, _dp(out))
+        return out
+
+    def body_loads(self, b):
+        """surface_loads of body b of a context with several bodies (the wall cells it cuts)."""
+        out = np.zeros(4)
+        if self._L.ccref_surface_loads_body(self._h, int(b), _dp(out)) != 0:
+            raise ValueError("no such body")
+        return out
+
+    @property
+    def nbodies(self):
+        return self._L.ccref_nbodies(self._h)
+
+    def cell_bodies(self, which=0):
+        """Body cutting each cut cell of a level (-1 elsewhere); several bodies only."""
+        out = np.zeros((self.ny, self.nx), dtype=np.int8)
+        if self._L.ccref_cell_bodies(self._h, which, out.ctypes.data_as(C.POINTER(C.c_int8))) != 0:
+            raise ValueError("one body: no cell bodies")
         return out
 
     def surface_pressure(self):

@@ -14,7 +14,11 @@ Workloads (non-dimensional stand-ins for the paper's SI set-ups):
                   orientation and speed drawn per seed;
 * ``naca``     -- a NACA 0012 aerofoil pitching about its quarter chord in a Mach-0.7
                   free stream (Sec. 3.4);
-* ``serving_request`` -- the mixed request population of the serving benchmark.
+* ``serving_request`` -- the mixed request population of the serving benchmark;
+* ``channel``  -- two parallel walls at 30 degrees moving together along +x, a density
+                  pulse advected along the channel (Sec. 3.1), with its exact solution;
+* ``piston_tube`` -- a rectangular piston driven along the inside of a static open-ended
+                  tube wall (two bodies in relative motion; the planar form of Sec. 3.5).
 """
 import math
 
@@ -111,6 +115,29 @@ def naca00(thickness, chord=1.0, n_side=512, pivot=0.25):
 def half_plane_quad(L=2.0):
     """A large quad standing in for the half-plane {x_b <= 0} of the body frame."""
     return np.array([[-L, -L], [0.0, -L], [0.0, L], [-L, L]])
+
+
+def clipped_half_plane(normal, offset, box):
+    """The convex polygon {x in box : normal . x <= offset}, counter-clockwise, for a box
+    (x0, x1, y0, y1) (a wall's solid side, cut off well outside the domain)."""
+    x0, x1, y0, y1 = box
+    pts = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+    nx_, ny_ = normal
+    out = []
+    for k in range(4):
+        a, b = pts[k - 1], pts[k]
+        da = nx_ * a[0] + ny_ * a[1] - offset
+        db = nx_ * b[0] + ny_ * b[1] - offset
+        if (da <= 0.0) != (db <= 0.0):
+            t = da / (da - db)
+            out.append((a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1])))
+        if db <= 0.0:
+            out.append(b)
+    return np.array(out, dtype=np.float64)
+
+
+def rectangle(x0, x1, y0, y1):
+    return np.array([[x0, y0], [x1, y0], [x1, y1], [x0, y1]], dtype=np.float64)
 
 
 def body(verts, ref=(0.0, 0.0), theta0=0.0, vel=(0.0, 0.0), pitch_amp=0.0, pitch_omega=0.0):
@@ -219,3 +246,68 @@ def serving_request(k):
         prim = uniform_prim(g, 1.0, 0.0, 0.0, 1.0)
     return {"name": f"req{k}", "grid": g, "body": b, "prim": prim, "cfl": 0.8, "steps": 500,
             "kind": kind, "motion": motion}
+
+
+# --------------------------------------------------------------------------- several bodies
+def channel(ny=32, angle_deg=30.0, width=0.25, speed=0.5, flow=1.0, amp=0.5, sigma=0.1, cfl=0.5):
+    """Sloped channel (Sec. 3.1): domain [-1.5, 1.5] x [-0.5, 0.5] (3 ny x ny square cells),
+    two parallel walls at `angle_deg` to the x axis, `width` apart about the origin, both
+    moving with velocity (speed, 0); their solid sides are half-planes cut off far outside
+    the domain.  Gas: p = 1, velocity (speed, 0) + flow t (t the channel direction), and a
+    density pulse rho = 1 + amp exp(-(s / sigma)^2) of the distance s along t from the
+    origin (uniform across the channel).  The exact solution advects the initial field with
+    the gas velocity (channel_exact).  The pulse shape is not given in the paper (reading)."""
+    g = grid(3 * ny, ny, -1.5, 1.5, -0.5, 0.5)
+    a = math.radians(angle_deg)
+    t = (math.cos(a), math.sin(a))
+    n = (-math.sin(a), math.cos(a))
+    box = (-5.0, 5.0, -4.0, 4.0)
+    lower = clipped_half_plane(n, -0.5 * width, box)
+    upper = clipped_half_plane((-n[0], -n[1]), -0.5 * width, box)
+    bodies = [body(lower, vel=(speed, 0.0)), body(upper, vel=(speed, 0.0))]
+    vel = (speed + flow * t[0], flow * t[1])
+    w = {"name": "channel", "grid": g, "bodies": bodies, "cfl": cfl, "t_end": 0.5,
+         "dir": t, "normal": n, "width": width, "speed": speed, "vel": vel, "amp": amp, "sigma": sigma}
+    w["prim"] = channel_exact(w, 0.0)
+    return w
+
+
+def channel_exact(w, t):
+    """Primitive fields of the channel's exact solution at time t, at the cell centres."""
+    g = w["grid"]
+    X, Y = cell_centres(g)
+    d = w["dir"]
+    s = d[0] * (X - w["vel"][0] * t) + d[1] * (Y - w["vel"][1] * t)
+    prim = np.empty((4, g["ny"], g["nx"]))
+    prim[0] = 1.0 + w["amp"] * np.exp(-(s / w["sigma"]) ** 2)
+    prim[1], prim[2], prim[3] = w["vel"][0], w["vel"][1], 1.0
+    return prim
+
+
+def channel_inside(w, t, margin=0.0):
+    """Cells whose centre lies inside the channel at time t, at least `margin` from both walls."""
+    g = w["grid"]
+    X, Y = cell_centres(g)
+    n = w["normal"]
+    d = n[0] * (X - w["speed"] * t) + n[1] * Y
+    return np.abs(d) < 0.5 * w["width"] - margin
+
+
+def piston_tube(ny=128, mach_s=1.76, gap=1.0 / 16.0, wall=0.125):
+    """Two bodies in relative motion, the planar form of the open-ended shock tube of
+    Sec. 3.5 (the axisymmetric source terms are not modelled): lengths in tube diameters D,
+    the half-tube above the reflective centre line y = 0.  Domain [0, 10] x [0, 4]
+    (2.5 ny x ny cells); a static tube wall [-1, 6] x [0.5, 0.5 + wall] (its open end at
+    x = 6); a rectangular piston [0.25, 0.5] x [-1, 0.5 - gap] moving along +x at the speed
+    that drives a shock of Mach `mach_s` into gas at rest (rho = 1, p = 1).  The piston
+    clears the tube wall by `gap` (reading: no cell may hold both bodies)."""
+    g = grid(int(2.5 * ny), ny, 0.0, 10.0, 0.0, 4.0, bc=(0, 0, 1, 0))
+    a0 = math.sqrt(GAMMA)
+    S = mach_s * a0
+    k = (S * S - a0 * a0) / (2.0 * S)
+    up = 4.0 * k / (GAMMA + 1.0)
+    tube = body(rectangle(-1.0, 6.0, 0.5, 0.5 + wall))
+    piston_b = body(rectangle(0.25, 0.5, -1.0, 0.5 - gap), vel=(up, 0.0))
+    return {"name": "piston_tube", "grid": g, "bodies": [tube, piston_b],
+            "prim": uniform_prim(g, 1.0, 0.0, 0.0, 1.0), "cfl": 0.8, "piston_speed": up,
+            "shock_speed": S}
