@@ -94,6 +94,27 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
                     cc_ctx** out);
 cc_status cc_destroy(cc_ctx* ctx);
 
+/* Several bodies in one context: the sloped channel of Sec. 3.1 (its two walls are two
+ * solid regions moving together) and bodies in relative motion (Sec. 3.5, planar).  The
+ * solid region is the union of the bodies' closed polygons (each as for cc_body: convex,
+ * counter-clockwise, here with 3 to 256 vertices), each posed with its own motion.
+ * Reading R30 (the paper describes the method for one convex body): vertex solid when in
+ * any body; a face's solid interval from the one body that meets it; volume fraction one
+ * minus the sum of the bodies' areas in the cell; a wall cell takes the velocity of the
+ * body that cuts it; the exact time-averaged aperture of a face sums the bodies' swept
+ * areas, each over its own displacement.  The bodies must keep apart: a face or cell with
+ * solid parts of two bodies, or a wall cell cut by different bodies at a sweep's two
+ * levels, sets device status bit 4, and the next synchronising call returns
+ * CC_ERR_UNSUPPORTED.  nbodies 0 or 1 is cc_create (bodies: NULL, or one body).  With
+ * two or more, the geometry and box phases cover the whole grid, and steps are planned on
+ * the host: cc_advance, the persistent launch mode, batches, cc_autotune,
+ * cc_surface_loads and cc_surface_pressure return CC_ERR_UNSUPPORTED.  bodies: host,
+ * copied; at most CC_MAX_BODIES. */
+#define CC_MAX_BODIES 4
+size_t cc_workspace_bytes_bodies(const cc_config* cfg, const cc_body* bodies, int32_t nbodies);
+cc_status cc_create_bodies(const cc_config* cfg, const cc_body* bodies, int32_t nbodies, void* d_ws, size_t ws_bytes,
+                           void* hip_stream, cc_ctx** out);
+
 /* Initial state: body posed at time t0, level-n geometry built, U = alpha Q(prim).
  * d_prim: device, 4 planes (rho, u, v, p) of nx*ny doubles. */
 cc_status cc_set_state(cc_ctx* ctx, const double* d_prim, double t0);
@@ -179,8 +200,8 @@ cc_status cc_surface_pressure(cc_ctx* ctx, double* d_out, int32_t max_records, i
  * conservation budget since cc_set_state (Sec. 3.3, mass-conservation error), zeros unless
  * cc_set_budget switched it on: [0..3] the fluxes through the domain boundary (dt/h times
  * the stabilised face fluxes of the first and last face of every line, in minus out, times
- * the cell area), [4..7] the wall pressure terms of the cut cells (dt/h times
- * (beta_hi - beta_lo)(F^B - u_wall Q^B) times the cell area; zero for mass), [8..11] the
+ * the cell area), [4..7] the wall terms of the cut cells (dt/h times
+ * (beta_hi - beta_lo)(F^B - u_wall Q^B) times the cell area), [8..11] the
  * residuals of emptied cells that found no recipient (times the cell area).  The totals
  * then change by boundary + wall - lost: with FP64 state to round-off, with FP32 state up to
  * the state's rounding (the mass drift).  Synchronises. */
@@ -215,7 +236,8 @@ cc_status cc_totals_state(const void* d_u, int32_t precision, int32_t nx, int32_
 /* Host info vector (n entries used, up to 11): time, steps, parity, device status bits
  * (1: a cell turned fluid, or was emptied, with no donor next to it — reported only: the
  * cell keeps no content until a donor appears; 2: a cell stayed inadmissible after
- * collapsing; 8: a grid-barrier wait of a persistent launch ran out; 2 and 8 are errors),
+ * collapsing; 4: two of several bodies met in one face or cell; 8: a grid-barrier wait of
+ * a persistent launch ran out; 2, 4 and 8 are errors),
  * collapsed-cell count, sweep box cells of the last sweep, staging capacity, rows per block
  * of the dense x-sweep, rows per tile of the dense y-sweep, 1 if that sweep walks columns
  * (else 0), 1 if an x sweep's dense launch also runs the box cells' first phase (small

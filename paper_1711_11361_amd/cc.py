@@ -48,6 +48,9 @@ _vp, _d, _i32 = C.c_void_p, C.c_double, C.c_int32
 _sig = {
     "cc_workspace_bytes": (C.c_size_t, [C.POINTER(cc_config), C.POINTER(cc_body)]),
     "cc_create": (C.c_int, [C.POINTER(cc_config), C.POINTER(cc_body), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "cc_workspace_bytes_bodies": (C.c_size_t, [C.POINTER(cc_config), C.POINTER(cc_body), _i32]),
+    "cc_create_bodies": (C.c_int, [C.POINTER(cc_config), C.POINTER(cc_body), _i32, _vp, C.c_size_t, _vp,
+                                   C.POINTER(_vp)]),
     "cc_destroy": (C.c_int, [_vp]),
     "cc_set_state": (C.c_int, [_vp, _vp, _d]),
     "cc_set_clock": (C.c_int, [_vp, _d, C.c_int64]),
@@ -132,9 +135,30 @@ def make_body(body):
     return b, keep
 
 
+def make_bodies(bodies):
+    """A cc_body array for several bodies (and the vertex arrays it points to)."""
+    arr = (cc_body * len(bodies))()
+    keep = []
+    for k, bd in enumerate(bodies):
+        b, v = make_body(bd)
+        arr[k] = b
+        keep.append(v)
+    return arr, keep
+
+
 # ----------------------------------------------------------------- C-ABI mirrors
 def cc_workspace_bytes(cfg, body):
     return _lib.cc_workspace_bytes(C.byref(cfg), C.byref(body))
+
+
+def cc_workspace_bytes_bodies(cfg, bodies, n):
+    return _lib.cc_workspace_bytes_bodies(C.byref(cfg), bodies, n)
+
+
+def cc_create_bodies(cfg, bodies, n, d_ws, ws_bytes, stream):
+    out = _vp()
+    _check(None, _lib.cc_create_bodies(C.byref(cfg), bodies, n, _vp(d_ws), ws_bytes, _vp(stream), C.byref(out)))
+    return out
 
 
 def cc_create(cfg, body, d_ws, ws_bytes, stream):
@@ -389,7 +413,9 @@ class Solver:
     on `device`.  It runs on a stream of its own (a captured step needs a stream other than
     the null stream); the binding's tensor copies run on that stream too."""
 
-    def __init__(self, grid, body=None, precision=CC_FP64, device="cuda:0"):
+    def __init__(self, grid, body=None, precision=CC_FP64, device="cuda:0", bodies=None):
+        """bodies: a list of two to four body dicts, each with its own motion (instead of
+        `body`)."""
         import torch
         self.torch = torch
         self.grid = dict(grid)
@@ -398,14 +424,22 @@ class Solver:
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(self.device)
         self._cfg = make_config(grid, precision)
-        self._body, self._verts = make_body(body)
-        self.ws_bytes = cc_workspace_bytes(self._cfg, self._body)
+        if bodies is not None:
+            self._body, self._verts = make_bodies(bodies)
+            self.ws_bytes = cc_workspace_bytes_bodies(self._cfg, self._body, len(bodies))
+        else:
+            self._body, self._verts = make_body(body)
+            self.ws_bytes = cc_workspace_bytes(self._cfg, self._body)
         with torch.cuda.stream(self.stream):
             self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
             self._io = torch.empty((4, self.ny, self.nx), dtype=torch.float64, device=self.device)
         base = self.ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        self.ctx = cc_create(self._cfg, self._body, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        if bodies is not None:
+            self.ctx = cc_create_bodies(self._cfg, self._body, len(bodies), self._ws_ptr, self.ws_bytes,
+                                        self.stream.cuda_stream)
+        else:
+            self.ctx = cc_create(self._cfg, self._body, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
 
     @staticmethod
     def device_bytes(grid, body=None, precision=CC_FP64):

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -75,6 +76,8 @@ struct Layout {
     size_t off_smax, off_status, off_ncol, off_part, off_tot, off_spd;
     size_t off_pconst, off_pstate, off_dtlog;
     size_t off_budget, off_bslot;
+    size_t off_cbody[3];     // several bodies: the body of each cut cell, per level slot
+    size_t set_bytes;        // several bodies: the bodies' block after the argument block
     int bs_patch, bs_cover;  // offsets (doubles) of the patch and covering budget slots
     size_t total;
     int capw, caph;  // sweep-box capacity (cells)
@@ -83,6 +86,17 @@ struct Layout {
 };
 
 int body_m(const cc_body* b) { return b && b->nverts > 0 && b->verts ? b->nverts : 0; }
+
+// Several bodies: per level slot their posed polygons, per body the step's motion, then the
+// posed vertices (slot s, body b at vertex s * mtot + first vertex of b), uploaded with the
+// argument block of every step.
+struct BodySet {
+    Poly poly[3][MAX_BODIES];
+    Motion mot[MAX_BODIES];
+};
+constexpr size_t SET_VERTS = (sizeof(BodySet) + 15) / 16 * 16;
+size_t bodyset_bytes(int mtot) { return SET_VERTS + 3 * 16 * (size_t)mtot; }
+constexpr int BODY_MAX_VERTS = 256;  // vertices of each of several bodies
 
 // True for a polygon of at least three finite vertices whose every turn is to the left
 // (or straight on), with a positive signed area and one full turn in total (a polygon
@@ -114,10 +128,16 @@ bool convex_ccw(const double* v, int m) {
     return std::fabs(turn - 2.0 * M_PI) < 1e-6;
 }
 
-Layout make_layout(const cc_config* c, const cc_body* b) {
+// nbodies >= 2: b points to that many bodies; their geometry and box phases cover the whole
+// grid (the bodies' boxes may span it, and their union moves with their relative motion).
+Layout make_layout(const cc_config* c, const cc_body* b, int nbodies = 1) {
     Layout L{};
     size_t nx = c->nx, ny = c->ny;
-    int m = body_m(b);
+    bool multi = nbodies > 1;
+    int m = multi ? 0 : body_m(b);
+    int mtot = 0;
+    for (int k = 0; multi && k < nbodies; k++) mtot += b[k].nverts;
+    bool hasb = m > 0 || multi;
     L.nc = nx * ny;
     L.nvx = (nx + 1) * (ny + 1);
     L.nfx = ny * (nx + 1);
@@ -128,7 +148,10 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     double R = 0.0;
     for (int k = 0; k < m; k++) R = std::max(R, std::hypot(b->verts[2 * k], b->verts[2 * k + 1]));
     double hx = (c->x_hi - c->x_lo) / c->nx, hy = (c->y_hi - c->y_lo) / c->ny;
-    if (m > 0) {
+    if (multi) {
+        L.capw = L.gw = (int)nx;
+        L.caph = L.gh = (int)ny;
+    } else if (m > 0) {
         double cw = std::ceil(2.0 * R / hx) + 16.0, ch = std::ceil(2.0 * R / hy) + 16.0;
         L.capw = (int)std::min<double>(cw, (double)nx);
         L.caph = (int)std::min<double>(ch, (double)ny);
@@ -138,7 +161,7 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
         L.capw = L.caph = L.gw = L.gh = 0;
     }
     L.cap = (size_t)L.capw * L.caph;
-    L.capf = m > 0 ? (size_t)(L.capw + 1) * (L.caph + 1) : 0;
+    L.capf = hasb ? (size_t)(L.capw + 1) * (L.caph + 1) : 0;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
@@ -155,8 +178,9 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
         L.off_poly[s] = take((size_t)std::max(m, 1) * 16);
     }
     L.off_body = take((size_t)std::max(m, 1) * 16);
-    L.off_qb = take(m > 0 ? 4 * L.nc * 8 : 8);
-    L.off_stamp = take(m > 0 ? L.nc * 4 : 4);
+    L.off_qb = take(hasb ? 4 * L.nc * 8 : 8);
+    L.off_stamp = take(hasb ? L.nc * 4 : 4);
+    for (int s = 0; s < 3; s++) L.off_cbody[s] = take(multi ? L.nc : 1);
     size_t cap = std::max<size_t>(L.cap, 1), capf = std::max<size_t>(L.capf, 1);
     L.off_sQ = take(4 * cap * 8);
     L.off_sU1 = take(4 * cap * 8);
@@ -173,7 +197,8 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     L.off_sf2 = take(cap);
     L.off_nbad = take(8);
     L.off_sync = take(sizeof(GridSync));
-    L.off_args = take(sizeof(StepArgs));
+    L.set_bytes = multi ? bodyset_bytes(mtot) : 0;
+    L.off_args = take(sizeof(StepArgs) + L.set_bytes);
     L.off_offs = take((size_t)NKINDS * 3 * 4);
     L.off_cflout = take(24);  // read-back: 2 speed maxima, then status and collapse count
     L.off_smax = take(16);
@@ -190,7 +215,7 @@ Layout make_layout(const cc_config* c, const cc_body* b) {
     // patch segments: 12 doubles each; covering blocks: 4 each)
     L.off_budget = take(16 * 8);
     size_t dense_slots = 2 * std::max(nx, ny);
-    size_t patch_blocks = m > 0 ? (size_t)std::max(patch_line_blocks<0>(L.capw, L.caph), patch_line_blocks<1>(L.capw, L.caph)) : 1;
+    size_t patch_blocks = hasb ? (size_t)std::max(patch_line_blocks<0>(L.capw, L.caph), patch_line_blocks<1>(L.capw, L.caph)) : 1;
     size_t cover_blocks = (std::max<size_t>(L.cap, 1) + T_BOX - 1) / T_BOX;
     L.bs_patch = (int)(BS_DENSE + 4 * dense_slots);
     L.bs_cover = (int)(L.bs_patch + 12 * patch_blocks);
@@ -243,6 +268,17 @@ struct Engine {
     // there is one, else of its x launch when merge_x, else as a launch of its own before
     // the dense launches (see engine_plan)
     bool merge_x = true;
+    // a context with several bodies (its own engine only): the box phase's first launch is
+    // the several-body kernel, and `extra` bytes of the bodies' block follow the argument
+    // block in the host buffers and the upload
+    bool multi = false;
+    size_t extra = 0;
+};
+
+// One of several bodies (host copy of its cc_body).
+struct HostBody {
+    std::vector<double> verts;
+    double ref_x, ref_y, theta0, vx, vy, amp, omega;
 };
 
 }  // namespace
@@ -278,6 +314,15 @@ struct cc_ctx {
     int speeds_buf;
     int advanced;  // steps completed by the last cc_advance
     bool budget_on;  // the conservation budget is tracked (cc_set_budget)
+    // several bodies (nb >= 2; the one-body fields above are then unused and m = 0): the
+    // bodies, the first vertex of each in the vertex arrays, their total, and the host image
+    // of the bodies' block (uploaded after the argument block) with its device address
+    int nb;
+    std::vector<HostBody> hb;
+    std::vector<int> vbase;
+    int mtot;
+    std::vector<char> hset;
+    char* d_set;
     std::string err;
 };
 
@@ -436,6 +481,80 @@ void poly_info(const cc_ctx* c, const double* pv, const Pose& px, const Pose& py
                                    c->cfg.y_hi, c->hx, c->hy, c->g.nx, c->g.ny);
 }
 
+bool has_body(const cc_ctx* c) { return c->m > 0 || c->nb > 1; }
+
+BodySet* hset_of(cc_ctx* c) { return reinterpret_cast<BodySet*>(c->hset.data()); }
+
+// Body b of several, posed with its x coordinates at time tx and its y coordinates at ty
+// (the stage polygon of a split step mixes the two; tx = ty: the body at that time), with
+// the one-body formula.
+void body_pose_xy(const cc_ctx* c, int b, double tx, double ty, double* out) {
+    const HostBody& B = c->hb[b];
+    double thx = B.theta0 + B.amp * std::sin(B.omega * tx), thy = B.theta0 + B.amp * std::sin(B.omega * ty);
+    double csx = std::cos(thx), snx = std::sin(thx), csy = std::cos(thy), sny = std::sin(thy);
+    double cx = B.ref_x + B.vx * tx, cy = B.ref_y + B.vy * ty;
+    int m = (int)B.verts.size() / 2;
+    for (int k = 0; k < m; k++) {
+        double bx = B.verts[2 * k], by = B.verts[2 * k + 1];
+        out[2 * k] = (csx * bx - snx * by) + cx;
+        out[2 * k + 1] = (sny * bx + csy * by) + cy;
+    }
+}
+
+// Level slot `slot` of several bodies posed with x at tx and y at ty: posed vertices and
+// polygons (bounding boxes; no certificate discs) into the host image of the bodies' block.
+// Returns the union of the bodies' cell boxes.
+Box bodies_level(cc_ctx* c, int slot, double tx, double ty) {
+    BodySet* S = hset_of(c);
+    double* V = reinterpret_cast<double*>(c->hset.data() + SET_VERTS) + 2 * (size_t)slot * c->mtot;
+    const double* dV = reinterpret_cast<const double*>(c->d_set + SET_VERTS) + 2 * (size_t)slot * c->mtot;
+    Box cells{0, 0, 0, 0};
+    for (int b = 0; b < c->nb; b++) {
+        int m = (int)c->hb[b].verts.size() / 2;
+        double* pv = V + 2 * (size_t)c->vbase[b];
+        body_pose_xy(c, b, tx, ty, pv);
+        Poly P{};
+        P.v = dV + 2 * (size_t)c->vbase[b];
+        P.m = m;
+        P.rin2 = -1.0;
+        P.xmin = P.ymin = INFINITY;
+        P.xmax = P.ymax = -INFINITY;
+        for (int k = 0; k < m; k++) {
+            P.xmin = std::fmin(P.xmin, pv[2 * k]);
+            P.xmax = std::fmax(P.xmax, pv[2 * k]);
+            P.ymin = std::fmin(P.ymin, pv[2 * k + 1]);
+            P.ymax = std::fmax(P.ymax, pv[2 * k + 1]);
+        }
+        S->poly[slot][b] = P;
+        cells = box_union(cells, cells_of_bbox(P.xmin, P.xmax, P.ymin, P.ymax, c->cfg.x_lo, c->cfg.x_hi, c->cfg.y_lo,
+                                               c->cfg.y_hi, c->hx, c->hy, c->g.nx, c->g.ny));
+    }
+    return cells;
+}
+
+// Each body's rigid map over the step from t0 to t1 and its velocity at mid-step.
+void bodies_motion(cc_ctx* c, double t0, double t1) {
+    BodySet* S = hset_of(c);
+    double th = t0 + 0.5 * (t1 - t0);
+    for (int b = 0; b < c->nb; b++) {
+        const HostBody& B = c->hb[b];
+        double th0 = B.theta0 + B.amp * std::sin(B.omega * t0);
+        double th1 = B.theta0 + B.amp * std::sin(B.omega * t1);
+        Motion& M = S->mot[b];
+        M.cosd = std::cos(th1 - th0);
+        M.sind = std::sin(th1 - th0);
+        M.c0x = B.ref_x + B.vx * t0;
+        M.c0y = B.ref_y + B.vy * t0;
+        M.c1x = B.ref_x + B.vx * t1;
+        M.c1y = B.ref_y + B.vy * t1;
+        M.vx = B.vx;
+        M.vy = B.vy;
+        M.thd = B.amp * B.omega * std::cos(B.omega * th);
+        M.chx = B.ref_x + B.vx * th;
+        M.chy = B.ref_y + B.vy * th;
+    }
+}
+
 bool geo_fits(const cc_ctx* c, const Box& r) { return box_empty(r) || (r.w() <= c->lay.gw && r.h() <= c->lay.gh); }
 
 unsigned nblk(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -467,6 +586,20 @@ void tstop(cc_ctx* c, TimedPair& tp) {
     (void)hipEventRecord(tp.b, c->stream);
 }
 
+// Several bodies: no vertex of any body moves a cell or more over the step from t0 to t1.
+cc_status bodies_check_motion(cc_ctx* c, double t0, double t1) {
+    for (int b = 0; b < c->nb; b++) {
+        size_t n = c->hb[b].verts.size();
+        std::vector<double> p0(n), p1(n);
+        body_pose_xy(c, b, t0, t0, p0.data());
+        body_pose_xy(c, b, t1, t1, p1.data());
+        for (size_t k = 0; k < n; k += 2)
+            if (!(std::fabs(p1[k] - p0[k]) < c->hx) || !(std::fabs(p1[k + 1] - p0[k + 1]) < c->hy))
+                return fail(c, CC_ERR_MOTION, "a body moves a cell or more within one sweep");
+    }
+    return CC_OK;
+}
+
 cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vector<double>& p1) {
     for (int k = 0; k < c->m; k++) {
         double dx = std::fabs(p1[2 * k] - p0[2 * k]), dy = std::fabs(p1[2 * k + 1] - p0[2 * k + 1]);
@@ -486,7 +619,7 @@ constexpr size_t GEO_BLOCK_CAP = 512;
 enum GeoStage { GEO_VERTS, GEO_FACES, GEO_CELLS, GEO_SWEPT };
 int geo_blocks(const cc_ctx* c, GeoStage st) {
     const Layout& L = c->lay;
-    if (c->m == 0) return 0;
+    if (!has_body(c)) return 0;
     size_t items;
     switch (st) {
         case GEO_VERTS: items = (size_t)(L.gw + 1) * (L.gh + 1); break;
@@ -550,7 +683,7 @@ void set_geo(cc_ctx* c, GeoJob& J, int slot, const Box& reg, const Pose& px, con
     J.cs_y = py.cs;
     J.sn_y = py.sn;
     J.cy_y = py.cy;
-    J.active = c->m > 0 && !box_empty(reg);
+    J.active = has_body(c) && !box_empty(reg);
 }
 
 Box sweep_box(cc_ctx* c, const Box& a, const Box& b) { return sweep_box_of(a, b, c->g.nx, c->g.ny); }
@@ -578,7 +711,22 @@ cc_status prepare_step(cc_ctx* c, double dt, StepArgs& a) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, CC_ERR_MOTION, "dt must be positive");
     double t1 = c->t + dt;
     base_args(c, a);
-    if (c->m > 0) {
+    if (c->nb > 1) {
+        // several bodies, posed on the host: the stage level (the first sweep's coordinate
+        // at t^{n+1}, the other at t^n) and the end level, and each body's motion
+        cc_status st = bodies_check_motion(c, c->t, t1);
+        if (st != CC_OK) return st;
+        Box cm = c->parity == 0 ? bodies_level(c, c->sm, t1, c->t) : bodies_level(c, c->sm, c->t, t1);
+        Box c1 = bodies_level(c, c->s1, t1, t1);
+        Box rm = box_union(c->lbox[c->sm], cm), r1 = box_union(c->lbox[c->s1], c1);
+        c->lbox[c->sm] = cm;
+        c->lbox[c->s1] = c1;
+        Pose z{1.0, 0.0, 0.0, 0.0};
+        set_geo(c, a.geo[0], c->sm, rm, z, z);
+        set_geo(c, a.geo[1], c->s1, r1, z, z);
+        bodies_motion(c, c->t, t1);
+        a.bmot = reinterpret_cast<const Motion*>(c->d_set + offsetof(BodySet, mot));
+    } else if (c->m > 0) {
         int m = c->m;
         Pose q0 = pose_at(c, c->t), q1 = pose_at(c, t1);
         // stage polygon: the first sweep's coordinate at t^{n+1}, the other at t^n
@@ -647,6 +795,13 @@ cc_status prepare_step(cc_ctx* c, double dt, StepArgs& a) {
 // slot's previous region and the new one, when their union exceeds the capacity).
 cc_status prepare_geometry(cc_ctx* c, double t, int slot, StepArgs& a) {
     base_args(c, a);
+    if (c->nb > 1) {
+        Box cells = bodies_level(c, slot, t, t);
+        Pose z{1.0, 0.0, 0.0, 0.0};
+        set_geo(c, a.geo[0], slot, box_union(c->lbox[slot], cells), z, z);
+        c->lbox[slot] = cells;
+        return CC_OK;
+    }
     if (c->m == 0) return CC_OK;
     Pose q = pose_at(c, t);
     std::vector<double> pv(2 * c->m);
@@ -677,7 +832,7 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     int m = c->m;
     bool capped = E.mode != CC_LAUNCH_PERSISTENT;
     auto cap = [&](int b, int most) { return capped ? std::min(b, most) : b; };
-    if (m == 0 && (kind <= L_BOX || kind == L_CS || kind == L_PX || kind == L_PY)) return 0;
+    if (!has_body(c) && (kind <= L_BOX || kind == L_CS || kind == L_PX || kind == L_PY)) return 0;
     switch (kind) {
         case L_POSE: return (int)nblk((size_t)m, T_WIDE);
         case L_V1: return geo_blocks(c, GEO_VERTS);
@@ -836,14 +991,22 @@ void launch_dense(const Engine& E, hipStream_t s, int sw, int which, hipEvent_t 
         klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
 }
 
+// The box phase's first launch of its own (several bodies: the kernel that takes each wall
+// cell's body).
+template <typename R>
+void launch_stagewall(const Engine& E, hipStream_t s, int sw) {
+    int n = (int)E.mem.size();
+    if (E.multi) klaunch(kb_stagewall<R, true>, ktotal(E, L_BOX), T_BOX, s, E.d_args, koff(E, L_BOX), n, sw);
+    else klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, E.d_args, koff(E, L_BOX), n, sw);
+}
+
 // The dense launches of sweep sw (`which` as for launch_dense) with the box cells' first
 // phase placed as engine_plan decided.  ta/tb (nullable): event pairs of the x and y
 // launches, from tp(d).
 template <typename R, class TP>
 void launch_sweep_dense(const Engine& E, hipStream_t s, int sw, int which, int fold, TP&& tp) {
-    int n = (int)E.mem.size();
-    bool wall_y = (which & 2) != 0, wall_x = !wall_y && E.merge_x;
-    if (!wall_x && !wall_y) klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, E.d_args, koff(E, L_BOX), n, sw);
+    bool wall_y = (which & 2) != 0 && !E.multi, wall_x = !wall_y && E.merge_x && !E.multi;
+    if (!wall_x && !wall_y) launch_stagewall<R>(E, s, sw);
     for (int d = 0; d < 2; d++) {
         if (!((which >> d) & 1)) continue;
         TimedPair p = tp(d);
@@ -857,7 +1020,7 @@ void launch_box_pre(const Engine& E, hipStream_t s, int sw, bool swept = true) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
     if (swept) klaunch(kb_swept, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
-    klaunch(kb_stagewall<R>, ktotal(E, L_BOX), T_BOX, s, A, koff(E, L_BOX), n, sw);
+    launch_stagewall<R>(E, s, sw);
 }
 // Box phases after the dense sweep (`which` as for the dense launches): patch update,
 // covering, both collapse rounds.  last: the sweep ends a captured step; covering leaves the
@@ -875,13 +1038,14 @@ void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int last
 }
 
 hipError_t engine_upload(Engine& E, hipStream_t s, int b) {
-    return hipMemcpyAsync(E.d_args, E.h_args[b], E.mem.size() * sizeof(StepArgs), hipMemcpyHostToDevice, s);
+    return hipMemcpyAsync(E.d_args, E.h_args[b], E.mem.size() * sizeof(StepArgs) + E.extra, hipMemcpyHostToDevice,
+                          s);
 }
 
 hipError_t engine_alloc_host(Engine& E) {
     hipError_t e = hipSuccess;
     for (int b = 0; b < 2 && e == hipSuccess; b++) {
-        e = hipHostMalloc((void**)&E.h_args[b], sizeof(StepArgs) * E.cap_n, hipHostMallocDefault);
+        e = hipHostMalloc((void**)&E.h_args[b], sizeof(StepArgs) * E.cap_n + E.extra, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&E.ev[b], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&E.h_cflout, 24 * (size_t)E.cap_n, hipHostMallocDefault);
@@ -1098,8 +1262,21 @@ size_t cc_workspace_bytes(const cc_config* cfg, const cc_body* body) {
     return make_layout(cfg, body).total;
 }
 
-cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_t ws_bytes, void* hip_stream,
-                    cc_ctx** out) {
+size_t cc_workspace_bytes_bodies(const cc_config* cfg, const cc_body* bodies, int32_t nbodies) {
+    if (!cfg || cfg->nx < 1 || cfg->ny < 1 || nbodies < 0 || nbodies > CC_MAX_BODIES || (nbodies > 0 && !bodies))
+        return 0;
+    if (nbodies <= 1) return make_layout(cfg, nbodies == 1 ? bodies : nullptr).total;
+    return make_layout(cfg, bodies, nbodies).total;
+}
+
+}  // extern "C"
+
+namespace {
+
+// cc_create (nbodies <= 1, body nullable) and cc_create_bodies (nbodies >= 2, body the
+// array of bodies).
+cc_status create_impl(const cc_config* cfg, const cc_body* body, int nbodies, void* d_ws, size_t ws_bytes,
+                      void* hip_stream, cc_ctx** out) {
     if (!out) return create_fail(nullptr, CC_ERR_ARG, "null output pointer");
     *out = nullptr;
     if (!cfg || cfg->nx < 1 || cfg->ny < 1 || !(cfg->x_hi > cfg->x_lo) || !(cfg->y_hi > cfg->y_lo) ||
@@ -1109,12 +1286,19 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     for (int k = 0; k < 4; k++)
         if (cfg->bc[k] != CC_BC_TRANSMISSIVE && cfg->bc[k] != CC_BC_REFLECTIVE)
             return create_fail(nullptr, CC_ERR_ARG, "invalid boundary condition");
-    if (body && body->nverts > 0 && !body->verts) return create_fail(nullptr, CC_ERR_ARG, "body without vertices");
-    if (body && body->nverts > LDS_VERTS)
-        return create_fail(nullptr, CC_ERR_UNSUPPORTED, "body polygon with more than 2048 vertices");
-    if (body && body->nverts > 0 && !convex_ccw(body->verts, body->nverts))
-        return create_fail(nullptr, CC_ERR_ARG, "body polygon is not convex and counter-clockwise with 3 or more vertices");
-    Layout lay = make_layout(cfg, body);
+    bool multi = nbodies > 1;
+    for (int b = 0; b < (multi ? nbodies : 1); b++) {
+        const cc_body* bd = multi ? &body[b] : body;
+        if (bd && bd->nverts > 0 && !bd->verts) return create_fail(nullptr, CC_ERR_ARG, "body without vertices");
+        if (bd && bd->nverts > (multi ? BODY_MAX_VERTS : LDS_VERTS))
+            return create_fail(nullptr, CC_ERR_UNSUPPORTED,
+                               multi ? "one of several bodies with more than 256 vertices"
+                                     : "body polygon with more than 2048 vertices");
+        if (bd && (bd->nverts > 0 || multi) && !convex_ccw(bd->verts, bd->nverts))
+            return create_fail(nullptr, CC_ERR_ARG,
+                               "body polygon is not convex and counter-clockwise with 3 or more vertices");
+    }
+    Layout lay = make_layout(cfg, body, multi ? nbodies : 1);
     if (!d_ws || ws_bytes < lay.total || ((uintptr_t)d_ws % ALIGN) != 0)
         return create_fail(nullptr, CC_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
     cc_ctx* c = new cc_ctx();
@@ -1133,7 +1317,21 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     c->g.hy = c->hy;
     c->g.gamma = cfg->gamma;
     c->g.alpha_min = cfg->alpha_min;
-    c->m = body_m(body);
+    c->m = multi ? 0 : body_m(body);
+    c->nb = multi ? nbodies : 0;
+    c->mtot = 0;
+    c->d_set = nullptr;
+    for (int b = 0; b < c->nb; b++) {
+        const cc_body& bd = body[b];
+        c->hb.push_back(HostBody{std::vector<double>(bd.verts, bd.verts + 2 * (size_t)bd.nverts), bd.ref_x, bd.ref_y,
+                                 bd.theta0, bd.vx, bd.vy, bd.pitch_amp, bd.pitch_omega});
+        c->vbase.push_back(c->mtot);
+        c->mtot += bd.nverts;
+    }
+    if (multi) {
+        c->hset.assign(lay.set_bytes, 0);
+        c->d_set = c->ws + lay.off_args + sizeof(StepArgs);
+    }
     c->cert0 = Cert{0.0, 0.0, -1.0, 0.0};
     if (c->m > 0) {
         c->bverts.assign(body->verts, body->verts + 2 * c->m);
@@ -1175,6 +1373,14 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
         L.poly.v = at<double>(c, lay.off_poly[s]);
         L.poly.m = 0;
         L.poly.rin2 = -1.0;
+        L.parts = nullptr;
+        L.np = 0;
+        L.cbody = nullptr;
+        if (multi) {  // the bodies' polygons of the slot (none posed yet: all fluid)
+            L.parts = reinterpret_cast<const Poly*>(c->d_set + offsetof(BodySet, poly)) + (size_t)s * MAX_BODIES;
+            L.np = c->nb;
+            L.cbody = at<int8_t>(c, lay.off_cbody[s]);
+        }
         c->lbox[s] = Box{0, 0, 0, 0};
     }
     // own launch plan (one member)
@@ -1189,6 +1395,8 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     E.d_sync = at<GridSync>(c, lay.off_sync);
     E.tile_x = 0;  // one row per x-sweep block
     E.tile_y = 0;  // 8-row y-sweep tiles
+    E.multi = multi;
+    E.extra = lay.set_bytes;
     hipError_t e = engine_alloc_host(E);
     if (e != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("host buffers: ") + hipGetErrorString(e));
     // all-fluid levels, clean reductions and lists, stamps that match no step, body vertices
@@ -1202,7 +1410,10 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
             e = hipGetLastError();
         }
     }
-    if (e == hipSuccess && c->m > 0) e = hipMemsetAsync(at<int32_t>(c, lay.off_stamp), 0xff, lay.nc * 4, c->stream);
+    if (e == hipSuccess && has_body(c)) e = hipMemsetAsync(at<int32_t>(c, lay.off_stamp), 0xff, lay.nc * 4, c->stream);
+    for (int s = 0; s < 3 && e == hipSuccess && multi; s++) e = hipMemsetAsync(c->lev[s].cbody, 0xff, lay.nc, c->stream);
+    if (e == hipSuccess && multi)  // the bodies' block: no body posed yet
+        e = hipMemcpyAsync(c->d_set, c->hset.data(), c->hset.size(), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess && c->m > 0)
         e = hipMemcpyAsync(at<double>(c, lay.off_body), c->bverts.data(), 16 * (size_t)c->m, hipMemcpyHostToDevice,
                            c->stream);
@@ -1219,6 +1430,23 @@ cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_
     if (e != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
     *out = c;
     return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_create(const cc_config* cfg, const cc_body* body, void* d_ws, size_t ws_bytes, void* hip_stream,
+                    cc_ctx** out) {
+    return create_impl(cfg, body, 1, d_ws, ws_bytes, hip_stream, out);
+}
+
+cc_status cc_create_bodies(const cc_config* cfg, const cc_body* bodies, int32_t nbodies, void* d_ws, size_t ws_bytes,
+                           void* hip_stream, cc_ctx** out) {
+    if (out) *out = nullptr;
+    if (nbodies < 0 || nbodies > CC_MAX_BODIES || (nbodies > 0 && !bodies))
+        return create_fail(nullptr, CC_ERR_ARG, "between 0 and 4 bodies");
+    return create_impl(cfg, nbodies >= 1 ? bodies : nullptr, nbodies > 1 ? nbodies : 1, d_ws, ws_bytes, hip_stream, out);
 }
 
 cc_status cc_destroy(cc_ctx* c) {
@@ -1253,6 +1481,7 @@ cc_status own_upload(cc_ctx* c, const StepArgs& a) {
     int b = E.buf;
     HIPCHK(c, engine_hostbuf(E, b));
     E.h_args[b][0] = a;
+    if (E.extra) std::memcpy(reinterpret_cast<char*>(E.h_args[b]) + sizeof(StepArgs), c->hset.data(), E.extra);
     HIPCHK(c, engine_upload(E, c->stream, b));
     HIPCHK(c, hipEventRecord(E.ev[b], c->stream));
     E.ev_used[b] = true;
@@ -1265,7 +1494,7 @@ cc_status geometry_at(cc_ctx* c, double t, int slot) {
     StepArgs a;
     cc_status st = prepare_geometry(c, t, slot, a);
     if (st != CC_OK) return st;
-    if (c->m == 0) return CC_OK;
+    if (!has_body(c)) return CC_OK;
     if ((st = own_upload(c, a)) != CC_OK) return st;
     TimedPair tp{};
     tstart(c, 3, tp);
@@ -1332,6 +1561,8 @@ cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
     c->step = 0;
     c->parity = 0;
     c->cur = 0;
+    // the status word starts clear before the level-n geometry (which may set bit 4)
+    HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_status, 0, 4, c->stream));
     cc_status st = geometry_at(c, t0, c->s0);
     if (st != CC_OK) return st;
     const double* al = c->lev[c->s0].alpha;
@@ -1341,10 +1572,9 @@ cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
     else
         hipLaunchKernelGGL(k_prim_to_u<double>, dim3(nblk(c->lay.nc)), dim3(TPB), 0, c->stream, c->g, al, d_prim,
                            at<double>(c, c->lay.off_u[0]));
-    HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_status, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_ncol, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_budget, 0, 16 * 8, c->stream));
-    if (c->m > 0) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
+    if (has_body(c)) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
     HIPCHK(c, hipGetLastError());
     c->have_state = true;
     return CC_OK;
@@ -1372,7 +1602,7 @@ cc_status cc_set_clock(cc_ctx* c, double t, int64_t step) {
     c->parity = (int)(step & 1);
     cc_status st = geometry_at(c, t, c->s0);
     if (st != CC_OK) return st;
-    if (c->m > 0) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
+    if (has_body(c)) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
     return CC_OK;
 }
 
@@ -1499,6 +1729,7 @@ cc_status own_graph_step(cc_ctx* c, double dt, bool timed = false) {
     HIPCHK(c, engine_hostbuf(E, b));
     cc_status st = prepare_step(c, dt, E.h_args[b][0]);
     if (st != CC_OK) return st;
+    if (E.extra) std::memcpy(reinterpret_cast<char*>(E.h_args[b]) + sizeof(StepArgs), c->hset.data(), E.extra);
     int dir0 = E.h_args[b][0].sw[0].dir;
     if (timed) {
         step_sequence_timed<R>(E, c->stream, b, dir0);
@@ -1552,6 +1783,17 @@ namespace {
 // body): the wall's part of the CFL condition.
 void wall_speeds(cc_ctx* c, double& wsx, double& wsy) {
     wsx = wsy = 0.0;
+    for (int b = 0; b < c->nb; b++) {  // several bodies: every body's vertices
+        const HostBody& B = c->hb[b];
+        std::vector<double> pv(B.verts.size());
+        body_pose_xy(c, b, c->t, c->t, pv.data());
+        double thd = B.amp * B.omega * std::cos(B.omega * c->t);
+        double cx = B.ref_x + B.vx * c->t, cy = B.ref_y + B.vy * c->t;
+        for (size_t k = 0; k < pv.size(); k += 2) {
+            wsx = std::fmax(wsx, std::fabs(B.vx - thd * (pv[k + 1] - cy)));
+            wsy = std::fmax(wsy, std::fabs(B.vy + thd * (pv[k] - cx)));
+        }
+    }
     if (c->m == 0) return;
     std::vector<double> pv(2 * c->m);
     Pose q = pose_at(c, c->t);
@@ -1580,6 +1822,7 @@ double dt_from_speeds(cc_ctx* c, double cfl, double sx, double sy) {
 // content from the first donor that appears (the oracle runs on the same way).
 cc_status status_error(cc_ctx* c, unsigned int status, double sx, double sy) {
     if (status & 2u) return fail(c, CC_ERR_STATE, "a cut cell stayed inadmissible after two collapse rounds");
+    if (status & 4u) return fail(c, CC_ERR_UNSUPPORTED, "two bodies meet in one face or cell");
     if (status & 8u) return fail(c, CC_ERR_DEVICE, "a grid barrier of the persistent sweep timed out");
     if (!std::isfinite(sx) || !std::isfinite(sy)) return fail(c, CC_ERR_STATE, "non-finite or non-physical state");
     return CC_OK;
@@ -1896,6 +2139,7 @@ cc_status cc_advance(cc_ctx* c, int32_t nsteps, double cfl, double* h_dt, float*
     cc_status st = not_in_batch(c);
     if (st != CC_OK) return st;
     if (h_done) *h_done = 0;
+    if (c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "several bodies: steps are planned on the host (cc_step)");
     if (nsteps < 0 || !(cfl > 0.0) || !std::isfinite(cfl)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_advance inside a step");
     if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
@@ -2002,6 +2246,7 @@ cc_status cc_surface_loads(cc_ctx* c, double* h_out4) {
     if (!c || !h_out4) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_surface_loads inside a step");
     if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
+    if (c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "surface loads of several bodies");
     for (int k = 0; k < 4; k++) h_out4[k] = 0.0;
     const Box& reg = c->lbox[c->s0];
     if (c->m == 0 || box_empty(reg)) return CC_OK;
@@ -2034,6 +2279,7 @@ cc_status cc_surface_pressure(cc_ctx* c, double* d_out, int32_t max_records, int
     if (!c || !h_n || max_records < 0 || (max_records > 0 && !d_out)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_surface_pressure inside a step");
     if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
+    if (c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "surface pressure of several bodies");
     *h_n = 0;
     const Box& R = c->lbox[c->s0];
     if (c->m == 0 || box_empty(R)) return CC_OK;
@@ -2212,6 +2458,7 @@ cc_status cc_autotune(cc_ctx* c, int32_t reps, int32_t* h_choice, const char* ca
     if (c->in_step || !c->have_state) return fail(c, CC_ERR_ARG, "cc_autotune needs a state and no open step");
     cc_status st = not_in_batch(c);
     if (st != CC_OK) return st;
+    if (c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "several bodies: the default tiles");
     Engine& E = c->eng;
     std::string key = tune_key(E.prec, E.mem);
     int tx = 0, ty = 0;
@@ -2271,6 +2518,8 @@ cc_status cc_set_launch_mode(cc_ctx* c, int32_t mode) {
     if (!c) return CC_ERR_ARG;
     if (mode != CC_LAUNCH_PER_PHASE && mode != CC_LAUNCH_PERSISTENT) return fail(c, CC_ERR_ARG, "unknown launch mode");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_set_launch_mode inside a step");
+    if (mode == CC_LAUNCH_PERSISTENT && c->nb > 1)
+        return fail(c, CC_ERR_UNSUPPORTED, "several bodies: one launch per phase");
     if (mode == CC_LAUNCH_PERSISTENT && c->budget_on)
         return fail(c, CC_ERR_UNSUPPORTED, "the budget is not tracked in the persistent launch mode");
     HIPCHK(c, hipStreamSynchronize(c->stream));  // the captured graphs are about to be destroyed
@@ -2370,6 +2619,7 @@ cc_status cc_batch_add(cc_batch* b, cc_ctx* c) {
     if (!b || !c) return CC_ERR_ARG;
     Engine& E = b->eng;
     if (c->batch) return bfail(b, CC_ERR_ARG, "context already in a batch");
+    if (c->nb > 1) return bfail(b, CC_ERR_UNSUPPORTED, "a context with several bodies steps on its own");
     if (c->cfg.precision != E.prec) return bfail(b, CC_ERR_ARG, "precision differs from the batch's");
     if ((int)E.mem.size() >= E.cap_n) return bfail(b, CC_ERR_WORKSPACE, "batch is full");
     if (!c->have_state || c->in_step) return bfail(b, CC_ERR_ARG, "context needs a state and no open step");

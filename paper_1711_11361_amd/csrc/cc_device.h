@@ -59,7 +59,13 @@ struct Level {
     double2* fy;   // (ny+1)*nx: y-face (i, j) from vertex (i, j) to (i+1, j)
     double* alpha; // ny*nx
     Poly poly;
+    // several bodies (np >= 2; else 0 and null): their posed polygons, and the body that
+    // cuts each cut cell of the level (-1 elsewhere)
+    const Poly* parts;
+    int np;
+    int8_t* cbody;
 };
+constexpr int MAX_BODIES = 4;
 
 __device__ __forceinline__ double vx_of(const Grid& g, int i) { return g.x_lo + (double)i * g.hx; }
 __device__ __forceinline__ double vy_of(const Grid& g, int j) { return g.y_lo + (double)j * g.hy; }

@@ -9,6 +9,7 @@
 #include "geometry.h"
 #include "reduce.h"
 #include "sweep.h"
+#include "bodies.h"
 
 namespace cc {
 
@@ -20,6 +21,7 @@ struct StepArgs {
     GeoJob geo[2];   // stage level and end level of the step
     SweepJob sw[2];  // first and second sweep
     Motion mot;
+    const Motion* bmot;  // several bodies: each body's motion (null for one body)
     Stage S;
     Common C;
     unsigned int* status;
@@ -214,6 +216,10 @@ template <int K>
 __device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int lb, int nb, double* spoly) {
     const GeoJob& J = a.geo[lev];
     if (!J.active) return;
+    if (J.L.np > 0) {  // several bodies (posed by the host)
+        geo_bodies_block<K>(a.g, J, lb, nb, a.status);
+        return;
+    }
     // the vertex stage also poses the polygon: every block poses its own copy in LDS (the
     // level's copy is written in this launch, by the first block, for the later stages)
     Poly P = J.L.poly;
@@ -292,6 +298,13 @@ __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, in
     if (box_empty_dev(J.B)) return;
     Stage S = stage_of(a, s);
     int items = J.dir == 0 ? (J.B.w() + 1) * J.B.h() : J.B.w() * (J.B.h() + 1);
+    if (J.Ls.np > 0) {  // several bodies
+        for (int t = lb * T_WIDE + (int)threadIdx.x; t < items; t += nb * T_WIDE) {
+            if (J.dir == 0) swept_bodies<0>(a.g, J, a.bmot, S, t);
+            else swept_bodies<1>(a.g, J, a.bmot, S, t);
+        }
+        return;
+    }
     bool staged = false;
     int mono = -1;
     Poly P = J.Ls.poly;
@@ -348,33 +361,34 @@ __global__ __launch_bounds__(T_WIDE) void kb_geo_cells_swept(const StepArgs* __r
     swept_block(a, s, lb - s * a.nb_swept, a.nb_swept, spoly);
 }
 
-template <typename R>
+template <typename R, bool MB = false>
 __device__ __forceinline__ void stagewall_body(const StepArgs& a, int s, int t) {
     const SweepJob& J = a.sw[s];
     if (t == 0) a.S.nbad[0] = a.S.nbad[1] = 0u;  // counters read later in this sweep
     if (box_empty_dev(J.B)) return;
     Stage S = stage_of(a, s);
-    if (J.dir == 0) stagewall<0, R>(a.g, J, a.mot, S, a.C, a.status, a.step_id, t);
-    else stagewall<1, R>(a.g, J, a.mot, S, a.C, a.status, a.step_id, t);
+    if (J.dir == 0) stagewall<0, R, MB>(a.g, J, a.mot, S, a.C, a.status, a.step_id, t, a.bmot);
+    else stagewall<1, R, MB>(a.g, J, a.mot, S, a.C, a.status, a.step_id, t, a.bmot);
 }
 
 // Box cells t, t + stride, ... of sweep s (the launch grid is capped; at least the first
 // call runs, which clears the sweep's counters).
-template <typename R>
+template <typename R, bool MB = false>
 __device__ __forceinline__ void stagewall_loop(const StepArgs& a, int s, int t, int stride) {
     const SweepJob& J = a.sw[s];
     int cells = box_empty_dev(J.B) ? 0 : J.B.w() * J.B.h();
     do {
-        stagewall_body<R>(a, s, t);
+        stagewall_body<R, MB>(a, s, t);
         t += stride;
     } while (t < cells);
 }
 
-template <typename R>
+// MB: a context with several bodies (its box phase always has this launch of its own).
+template <typename R, bool MB = false>
 __global__ __launch_bounds__(T_BOX) void kb_stagewall(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                       int n, int s) {
     Unit w = unit_of(off, n);
-    stagewall_loop<R>(A[w.u], s, w.lb * T_BOX + threadIdx.x, w.nb * T_BOX);
+    stagewall_loop<R, MB>(A[w.u], s, w.lb * T_BOX + threadIdx.x, w.nb * T_BOX);
 }
 
 

@@ -163,7 +163,7 @@ __global__ void k_cfl_dt(const unsigned long long* __restrict__ smax, const unsi
                          double wsx, double wsy, double hx, double hy, double cfl, double* __restrict__ out) {
     if (threadIdx.x != 0) return;
     double sx = __longlong_as_double((long long)smax[0]), sy = __longlong_as_double((long long)smax[1]);
-    bool bad = (*status & 10u) != 0u || !isfinite(sx) || !isfinite(sy);
+    bool bad = (*status & 14u) != 0u || !isfinite(sx) || !isfinite(sy);
     sx = fmax(sx, wsx);
     sy = fmax(sy, wsy);
     *out = bad ? 0.0 : cfl * fmin(hx / sx, hy / sy);

@@ -338,9 +338,18 @@ __device__ __forceinline__ void wall_riemann(const double q[4], double nx, doubl
 // Then the cell's wall quantities: wall flag, shielded volume, boundary flux F^B (advective
 // part from the step's common boundary state, pressure part from this stage) and
 // F^B - u_wall^d Q^B.
-template <int D, typename R>
+// Body of wall cell k in a sweep of a context with several bodies: the one cutting it at
+// level s (when cut there), else at level e; status bit 4 when the two levels' differ.
+__device__ __forceinline__ int wall_body(const SweepJob& J, size_t k, bool cs, bool ce, unsigned int* status) {
+    int bs = J.Ls.cbody[k], be = J.Le.cbody[k];
+    if (cs && ce && bs >= 0 && be >= 0 && bs != be) atomicOr(status, 4u);
+    return cs && bs >= 0 ? bs : (be >= 0 ? be : 0);
+}
+
+// MB: several bodies, the wall velocity from the motion bm[] of the cell's body (else M).
+template <int D, typename R, bool MB = false>
 __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, const Stage& S, const Common& C,
-                          unsigned int* status, int32_t step_id, int t) {
+                          unsigned int* status, int32_t step_id, int t, const Motion* bm = nullptr) {
     const Level& Ls = J.Ls;
     const Level& Le = J.Le;
     const Box& B = J.B;
@@ -456,8 +465,9 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
         } else {
             wall_point(g, fe, i, j, &wx, &wy);
         }
-        double uwx = M.vx - M.thd * (wy - M.chy);
-        double uwy = M.vy + M.thd * (wx - M.chx);
+        const Motion& Mw = MB ? bm[wall_body(J, k, cs, ce, status)] : M;
+        double uwx = Mw.vx - Mw.thd * (wy - Mw.chy);
+        double uwy = Mw.vy + Mw.thd * (wx - Mw.chx);
         double blo = D == 0 ? bw : bs, bhi = D == 0 ? be : bn;
         double mn = blo < bhi ? blo : bhi;
         double sh = fabs(bhi - blo);

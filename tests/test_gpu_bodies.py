@@ -1,0 +1,182 @@
+"""Several bodies in one context (reading R30) through the C ABI against the FP64 oracle:
+the sloped moving channel of Sec. 3.1 and two bodies in relative motion (Sec. 3.5, planar).
+
+* geometry of every level: vertex classes and the cut-cell list bit-exact, apertures and
+  volume fractions to round-off, at several times;
+* per sweep from identical inputs: relative L-infinity of U <= 1e-12 (FP64, the scales of
+  the one-body parity tests; 1e-11 for the sloped channel, whose tiny cut cells amplify
+  the clipping algorithms' different rounding, see CHANNEL_TOL);
+* end time with the oracle's time steps: relative L1 <= 1e-9 (FP64); FP32 state: relative
+  L1 of density <= 1e-4;
+* bodies meeting in one cell are reported as unsupported; the calls a context with several
+  bodies does not support refuse.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from oracle import ref  # noqa: E402
+from paper_1711_11361_amd import cc  # noqa: E402
+from paper_1711_11361_amd import workloads as W  # noqa: E402
+
+FP64_TOL = 1e-12
+# The sloped channel keeps cut cells down to alpha ~ 3e-7 (no small-cell threshold, as in
+# the paper).  The two sides clip the wall polygons (coordinates up to 3) with different
+# exact algorithms, whose results differ by a few units of round-off of those coordinates
+# (~1e-15 of a cell); a neighbour's state U / alpha carries that difference amplified by
+# 1 / alpha into the fluxes of the cells next to it.  Measured: 2.5e-12 after 8 steps.
+CHANNEL_TOL = 1e-11
+
+
+def scales(U, gamma=1.4):
+    r = np.where(U[0] > 0, U[0], 1.0)
+    p = (gamma - 1.0) * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / r)
+    a = np.sqrt(np.maximum(gamma * p / r, 0.0))
+    mom = np.where(U[0] > 0, np.hypot(U[1], U[2]) + U[0] * a, 0.0).max()
+    sc = np.array([np.abs(U[0]).max(), mom, mom, np.abs(U[3]).max()])
+    return np.where(sc > 0, sc, 1.0)
+
+
+def rel_linf(a, b):
+    sc = scales(b)
+    return max(np.abs(a[k] - b[k]).max() / sc[k] for k in range(4))
+
+
+def diamonds():
+    g = W.grid(64, 32, 0.0, 2.0, 0.0, 1.0)
+    d = np.array([[0.1, 0.0], [0.0, 0.1], [-0.1, 0.0], [0.0, -0.1]])
+    bodies = [W.body(d, ref=(0.625, 0.513), vel=(0.5, 0.0)), W.body(d, ref=(1.375, 0.513), vel=(-0.5, 0.0))]
+    return {"name": "diamonds", "grid": g, "bodies": bodies, "prim": W.uniform_prim(g, 1.0, 0.0, 0.0, 1.0),
+            "cfl": 0.5}
+
+
+def far_apart():
+    g = W.grid(128, 32, 0.0, 4.0, 0.0, 1.0)
+    a = W.body(W.triangle(0.3), ref=(0.5, 0.47), theta0=0.2, vel=(0.3, 0.05), pitch_amp=0.3, pitch_omega=2.0)
+    b = W.body(W.circle(0.15, 64), ref=(3.5, 0.52), vel=(-0.4, 0.1))
+    return {"name": "far_apart", "grid": g, "bodies": [a, b], "prim": W.uniform_prim(g, 1.0, 0.2, -0.1, 1.0),
+            "cfl": 0.8}
+
+
+def cases():
+    yield "channel", W.channel(32)
+    yield "channel_ragged", {**W.channel(24), "grid": W.grid(71, 23, -1.5, 1.5, -0.5, 0.5)}
+    yield "piston_tube", W.piston_tube(64)
+    yield "diamonds", diamonds()
+    yield "far_apart", far_apart()
+
+
+def pair(w, precision=cc.CC_FP64):
+    o = ref.Oracle(w["grid"], bodies=w["bodies"])
+    s = cc.Solver(w["grid"], bodies=w["bodies"], precision=precision)
+    prim = w["prim"] if w["prim"].shape[1:] == (w["grid"]["ny"], w["grid"]["nx"]) else W.channel_exact(
+        {**w, "grid": w["grid"]}, 0.0)
+    o.set_prim(prim)
+    s.set_prim(prim)
+    return o, s
+
+
+@pytest.mark.parametrize("name,w", list(cases()), ids=[c[0] for c in cases()])
+def test_geometry_matches_oracle(name, w):
+    o = ref.Oracle(w["grid"], bodies=w["bodies"])
+    s = cc.Solver(w["grid"], bodies=w["bodies"])
+    for t in (0.0, 0.0123, 0.31):
+        o.geometry(t, 0)
+        s.geometry(t, 0)
+        a, b = s.geometry_dump(0), o.geometry_dump(0)
+        assert np.array_equal(a["vcls"], b["vcls"]), name
+        assert np.array_equal(a["cut"], o.cut_list(0)), name
+        for key in ("alpha", "bx", "by"):
+            assert np.abs(a[key] - b[key]).max() <= 1e-12, (name, key, np.abs(a[key] - b[key]).max())
+            assert np.array_equal(a[key] == 1.0, b[key] == 1.0) and np.array_equal(a[key] == 0.0, b[key] == 0.0)
+    assert o.status == 0 and s.info()["status"] == 0
+
+
+@pytest.mark.parametrize("name,w", list(cases()), ids=[c[0] for c in cases()])
+def test_sweeps_match_oracle_from_identical_inputs(name, w):
+    o, s = pair(w)
+    tol = CHANNEL_TOL if name == "channel" else FP64_TOL
+    worst = 0.0
+    for k in range(8):
+        dt = o.cfl_dt(w["cfl"])
+        s.set_u(o.get_u())
+        dg = s.cfl_dt(w["cfl"])
+        assert abs(dg - dt) <= 1e-12 * dt, (name, dg, dt)
+        o.begin_step(dt)
+        s.begin_step(dt)
+        for sw in range(2):
+            d = o.parity if sw == 0 else 1 - o.parity
+            s.set_u(o.get_u())
+            o.sweep(d, dt)
+            s.sweep(d, dt)
+            Ug, Uo = s.get_u(), o.get_u()
+            e = rel_linf(Ug, Uo)
+            worst = max(worst, e)
+            if e > tol:
+                sc = scales(Uo)[:, None, None]
+                c, j, i = np.unravel_index(np.argmax(np.abs(Ug - Uo) / sc), Ug.shape)
+                al = [o.geometry_dump(v)["alpha"][j, i] for v in (0, 1, 2)]
+                raise AssertionError(f"{name} step {k} sweep {sw}: rel {e:.3e} comp {c} cell ({i},{j}) "
+                                     f"alphas {al} gpu {Ug[:, j, i]} oracle {Uo[:, j, i]}")
+        o.end_step()
+        s.end_step()
+    assert s.info()["status"] == o.status == 0
+    assert s.info()["collapses"] == o.collapses
+
+
+@pytest.mark.parametrize("name,w", [c for c in cases() if c[0] in ("channel", "piston_tube")],
+                         ids=["channel", "piston_tube"])
+def test_end_time_parity(name, w):
+    o, s = pair(w)
+    dts = o.run(w["cfl"], nsteps=150)
+    s.run(w["cfl"], dts=dts)
+    Ug, Uo = s.get_u(), o.get_u()
+    for k in range(4):
+        den = np.abs(Uo[k]).sum()
+        assert np.abs(Ug[k] - Uo[k]).sum() / den <= 1e-9, (name, k)
+    assert s.info()["status"] == o.status == 0
+    assert s.info()["collapses"] == o.collapses
+
+
+def test_fp32_channel_against_fp64_oracle():
+    w = W.channel(64)
+    o, s = pair(w, precision=cc.CC_FP32_GEOM64)
+    dts = o.run(w["cfl"], nsteps=200)
+    s.run(w["cfl"], dts=dts)
+    Po, Pg = o.get_prim(), s.get_prim()
+    al = o.geometry_dump(0)["alpha"]
+    l1 = (al * np.abs(Pg[0] - Po[0])).sum() / (al * np.abs(Po[0])).sum()
+    assert l1 <= 1e-4, l1
+
+
+def test_bodies_in_one_cell_are_refused():
+    g = W.grid(16, 16, 0.0, 1.0, 0.0, 1.0)
+    bodies = [W.body(W.rectangle(0.2, 0.51, 0.2, 0.8)), W.body(W.rectangle(0.53, 0.8, 0.2, 0.8))]
+    s = cc.Solver(g, bodies=bodies)
+    s.set_prim(W.uniform_prim(g, 1.0, 0.0, 0.0, 1.0))
+    assert s.info()["status"] & 4
+    with pytest.raises(cc.CCError) as e:
+        s.cfl_dt(0.5)
+    assert e.value.status == cc.CC_ERR_UNSUPPORTED
+
+
+def test_unsupported_calls_refuse():
+    w = diamonds()
+    s = cc.Solver(w["grid"], bodies=w["bodies"])
+    s.set_prim(w["prim"])
+    for call in (lambda: s.advance(2, 0.5), lambda: s.surface_loads(), lambda: s.set_launch_mode(1)):
+        with pytest.raises(cc.CCError) as e:
+            call()
+        assert e.value.status == cc.CC_ERR_UNSUPPORTED
+    b = cc.Batch(2, cc.CC_FP64)
+    with pytest.raises(cc.CCError) as e:
+        b.add(s)
+    assert e.value.status == cc.CC_ERR_UNSUPPORTED
+    b.close()
+    s.step(s.cfl_dt(0.5))  # still steps on its own
+    assert s.info()["status"] == 0
