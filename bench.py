@@ -318,6 +318,97 @@ def naca_lift_series(n=1024, cycles=3, per_cycle=48):
             "wall_cells": int(len(cp)), "cp_range": [round(float(cp.min()), 4), round(float(cp.max()), 4)]}
 
 
+def run_to(s, cfl, t_end):
+    """Host-planned CFL steps of a context with several bodies up to time t_end; returns
+    (steps, seconds)."""
+    import torch
+    n = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = 0.0
+    while t < t_end - 1e-12:
+        dt = min(s.cfl_dt(cfl), t_end - t)
+        s.step(dt)
+        t += dt
+        n += 1
+    torch.cuda.synchronize()
+    return n, time.perf_counter() - t0
+
+
+def channel_leg():
+    """Sloped moving channel (Sec. 3.1): a density pulse advected along two parallel walls at
+    30 degrees that move together along +x, FP64, to t = 0.5; error norms of the density
+    against the exact (advected) solution over full cells and their orders, at a fixed CFL
+    number and with the CFL number halved per refinement (Eq. CFLvarying)."""
+    import numpy as np
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    def one(ny, cfl):
+        w = W.channel(ny, cfl=cfl)
+        s = cc.Solver(w["grid"], bodies=w["bodies"], precision=cc.CC_FP64)
+        s.set_prim(w["prim"])
+        n, T = run_to(s, cfl, w["t_end"])
+        st = s.info()["status"]
+        P = s.get_prim()
+        full = s.geometry_dump(0)["alpha"] == 1.0
+        s.close()
+        ex = W.channel_exact(w, w["t_end"])
+        e = np.abs(P[0][full] - ex[0][full])
+        h2 = (3.0 / w["grid"]["nx"]) * (1.0 / ny)
+        cells = w["grid"]["nx"] * ny
+        print(f"channel {w['grid']['nx']}x{ny} cfl {cfl}: {n} steps in {T:.2f} s", file=sys.stderr, flush=True)
+        return {"grid": [w["grid"]["nx"], ny], "cfl": cfl, "steps": n, "status": int(st),
+                "L1": float(e.sum() * h2), "L2": float(np.sqrt((e * e).sum() * h2)), "Linf": float(e.max()),
+                "cell_updates_per_s": rate(cells, n, T), "ms_per_step": 1e3 * T / n}
+
+    def orders(rows):
+        for a, b in zip(rows, rows[1:]):
+            b["orders"] = {k: float(np.log2(a[k] / b[k])) for k in ("L1", "L2", "Linf")}
+        return rows
+
+    fixed = orders([one(ny, 0.5) for ny in (32, 64, 128, 256, 512)])
+    halved = orders([one(ny, 0.5 / 2 ** k) for k, ny in enumerate((128, 256, 512))])
+    return {"workload": "sloped channel (30 degrees, width 0.25) moving at 0.5 along +x, density pulse advected "
+                        "along it at 1.0, domain [-1.5,1.5]x[-0.5,0.5], FP64, t = 0.5",
+            "fixed_cfl": fixed, "cfl_halved": halved}
+
+
+def tube_leg(ny=512):
+    """Two bodies in relative motion (the planar open-ended shock tube after Sec. 3.5): a
+    piston driven at the Mach-1.76 piston speed along a static tube wall, 2.5 ny x ny cells,
+    to t = 3 (the shock has left the tube), FP32 and FP64."""
+    import numpy as np
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    out = {}
+    for name, prec in (("fp32", cc.CC_FP32_GEOM64), ("fp64", cc.CC_FP64)):
+        w = W.piston_tube(ny)
+        s = cc.Solver(w["grid"], bodies=w["bodies"], precision=prec)
+        s.set_prim(w["prim"])
+        n1, _ = run_to(s, w["cfl"], 0.2)  # warm-up
+        n, T = run_to(s, w["cfl"], 1.2)
+        P = s.get_prim()
+        full = s.geometry_dump(0)["alpha"] == 1.0
+        up, S = w["piston_speed"], w["shock_speed"]
+        X, Y = W.cell_centres(w["grid"])
+        m = (X > 0.5 + up * 1.2 + 0.2) & (X < 0.5 + S * 1.2 - 0.3) & (Y < 0.3) & full
+        n2, _ = run_to(s, w["cfl"], 1.8)
+        st = s.info()["status"]
+        s.close()
+        cells = w["grid"]["nx"] * ny
+        out[name] = {"cell_updates_per_s": rate(cells, n, T), "ms_per_step": 1e3 * T / n, "steps": n,
+                     "status": int(st), "plateau_at_t1.2": {"rho": float(P[0][m].mean()), "u": float(P[1][m].mean()),
+                                                            "p": float(P[3][m].mean())}}
+    w = W.piston_tube(ny)
+    up, S = w["piston_speed"], w["shock_speed"]
+    out["closed_form_sealed_tube"] = {"rho": S / (S - up), "u": up, "p": 1.0 + S * up}
+    out["workload"] = (f"piston (speed {up:.4f}, Mach-1.76 shock) inside a static tube wall, clearance 1/16, "
+                       f"{int(2.5 * ny)}x{ny} on [0,10]x[0,4], reflective centre line")
+    return out
+
+
 def batched(w, instances, steps, warmup):
     """Copies of the headline workload stepped as one batch (device-planned), and the same
     copies as plain FP64 contexts advanced one after another with launches of their own."""
@@ -531,9 +622,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the legs of the other configurations")
-    ap.add_argument("--legs", default="piston,triangle,naca,lift,batched",
+    ap.add_argument("--legs", default="piston,triangle,naca,lift,batched,channel,tube",
                     help="legs of the other configurations to run (comma list of piston, triangle, naca, lift, "
-                         "batched)")
+                         "batched, channel, tube)")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving mix, run in a child process (0: skip)")
     ap.add_argument("--serving-only", action="store_true",
@@ -613,6 +704,12 @@ def main():
         print("lift series done", file=sys.stderr, flush=True)
     if "batched" in legs:
         out["batched_copies"] = [batched(w, k, min(args.steps, 200), min(args.warmup, 20)) for k in (4, 16)]
+    if "channel" in legs:
+        out["sloped_channel"] = channel_leg()
+        print("channel done", file=sys.stderr, flush=True)
+    if "tube" in legs:
+        out["piston_tube"] = tube_leg()
+        print("tube done", file=sys.stderr, flush=True)
     if args.serving > 0:
         out["serving"] = serving_child(args.serving, args.budget_gib, args.slots)
         print("serving done", file=sys.stderr, flush=True)

@@ -1206,9 +1206,30 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
             double Nx = (bw - be) * c->hy, Ny = (bs - bn) * c->hx;
             e->wall = e->ab > 0.0 && (Nx != 0.0 || Ny != 0.0);
             if (!e->wall) continue;
-            double nn = sqrt(Nx * Nx + Ny * Ny);
-            e->nx = Nx / nn;
-            e->ny = Ny / nn;
+            /* unit normal: the time average of the wall's unit normal over the sweep (end of
+             * Sec. 2.3.4), the normalised sum of the unit normals of the start and end levels,
+             * each from that level's apertures (exact for a planar wall); a level where the
+             * cell has no wall adds nothing; without either, the effective vector's direction */
+            double sx = 0.0, sy = 0.0;
+            for (int lv = 0; lv < 2; lv++) {
+                const level_t* L = lv == 0 ? Ls : Le;
+                double lx = (beta_x(c, L, i, j) - beta_x(c, L, i + 1, j)) * c->hy;
+                double ly = (beta_y(c, L, i, j) - beta_y(c, L, i, j + 1)) * c->hx;
+                double ll = sqrt(lx * lx + ly * ly);
+                if (ll > 0.0) {
+                    sx += lx / ll;
+                    sy += ly / ll;
+                }
+            }
+            double nn = sqrt(sx * sx + sy * sy);
+            if (nn > 0.0) {
+                e->nx = sx / nn;
+                e->ny = sy / nn;
+            } else {
+                nn = sqrt(Nx * Nx + Ny * Ny);
+                e->nx = Nx / nn;
+                e->ny = Ny / nn;
+            }
             /* wall velocity at the mean of the level wall points, at mid-step (R24) */
             double wx, wy;
             int cs = cell_is_cut(c, Ls, i, j), ce = cell_is_cut(c, Le, i, j);

@@ -450,8 +450,29 @@ __device__ void stagewall(const Grid& g, const SweepJob& J, const Motion& M, con
     bool wall = ab > 0.0 && (Nx != 0.0 || Ny != 0.0);
     double fb[4] = {0, 0, 0, 0}, wv[4] = {0, 0, 0, 0}, ahat = 0.0;
     if (wall) {
-        double nn = sqrt(Nx * Nx + Ny * Ny);
-        double nxu = Nx / nn, nyu = Ny / nn;
+        // unit normal: the time average of the wall's unit normal over the sweep (end of
+        // Sec. 2.3.4), the normalised sum of the start and end levels' unit normals, each
+        // from that level's apertures (exact for a planar wall); a level where the cell has
+        // no wall adds nothing; without either, the effective vector's direction
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int lv = 0; lv < 2; lv++) {
+            const CellFaces& f = lv == 0 ? fs : fe;
+            double lx = (interval_beta(f.f[0]) - interval_beta(f.f[1])) * g.hy;
+            double ly = (interval_beta(f.f[2]) - interval_beta(f.f[3])) * g.hx;
+            double ll = sqrt(lx * lx + ly * ly);
+            if (ll > 0.0) {
+                sx += lx / ll;
+                sy += ly / ll;
+            }
+        }
+        double nn = sqrt(sx * sx + sy * sy);
+        if (!(nn > 0.0)) {
+            sx = Nx;
+            sy = Ny;
+            nn = sqrt(Nx * Nx + Ny * Ny);
+        }
+        double nxu = sx / nn, nyu = sy / nn;
         double wx, wy;
         bool cs = cell_cut_f(fs), ce = cell_cut_f(fe);
         if (cs && ce) {

@@ -375,7 +375,8 @@ def test_surface_loads_match_oracle(name, w, nsteps, precision):
 def test_surface_pressure_matches_oracle(name, w, nsteps, precision):
     """The wall pressure distribution from identical states: the same wall cells in the
     same order (bit-exact indices), wall points and normals to round-off, p* to round-off in
-    FP64 and to the state's FP32 rounding otherwise (relative to the largest p*)."""
+    FP64 (relative to the largest p*, and to the cell's own p* over its volume fraction) and
+    to the state's FP32 rounding otherwise."""
     o, s = pair(w, precision)
     for _ in range(nsteps):
         o.step(o.cfl_dt(w["cfl"]))
@@ -388,5 +389,12 @@ def test_surface_pressure_matches_oracle(name, w, nsteps, precision):
     h = size / max(g["nx"], g["ny"])
     assert np.abs(rg[:, 1:3] - ro[:, 1:3]).max() <= 1e-12 * size, name
     assert np.abs(rg[:, 4:6] - ro[:, 4:6]).max() <= 1e-12 * h, name
-    tol = 1e-12 if precision == cc.CC_FP64 else 1e-5
-    assert np.abs(rg[:, 3] - ro[:, 3]).max() <= tol * np.abs(ro[:, 3]).max(), name
+    if precision == cc.CC_FP64:
+        # p* follows the cell's state U / alpha, so the rounding in which the two exact
+        # clipping algorithms differ (~1e-14 of a cell in alpha for coordinates of a few
+        # units) appears divided by alpha in cells a body barely enters
+        al = o.geometry_dump(0)["alpha"].reshape(-1)[ro[:, 0].astype(np.int64)]
+        bound = 1e-12 * np.abs(ro[:, 3]).max() + 1e-13 * np.abs(ro[:, 3]) / al
+        assert (np.abs(rg[:, 3] - ro[:, 3]) <= bound).all(), name
+    else:
+        assert np.abs(rg[:, 3] - ro[:, 3]).max() <= 1e-5 * np.abs(ro[:, 3]).max(), name
