@@ -927,6 +927,12 @@ void klaunch(K kern, int blocks, int threads, hipStream_t s, Args... args) {
 void launch_geometry(const Engine& E, hipStream_t s) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
+    if (E.multi) {
+        klaunch(kb_geo<0, true>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
+        klaunch(kb_geo<1, true>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
+        klaunch(kb_geo<2, true>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), n);
+        return;
+    }
     klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
     klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
     klaunch(kb_geo<2>, ktotal(E, L_C1), T_WIDE, s, A, koff(E, L_C1), n);
@@ -1019,7 +1025,8 @@ template <typename R>
 void launch_box_pre(const Engine& E, hipStream_t s, int sw, bool swept = true) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    if (swept) klaunch(kb_swept, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
+    if (swept && E.multi) klaunch(kb_swept<true>, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
+    else if (swept) klaunch(kb_swept<>, ktotal(E, L_S1), T_WIDE, s, A, koff(E, L_S1), n, sw);
     launch_stagewall<R>(E, s, sw);
 }
 // Box phases after the dense sweep (`which` as for the dense launches): patch update,
@@ -1124,15 +1131,29 @@ hipError_t launch_persist(const Engine& E, hipStream_t s, int sw) {
 // as its own launch); then the read-back of the wave speeds and status words into pinned
 // host memory.  dir0: the single member's first direction (only its dense kernels are
 // launched on the per-phase path), or -1.
+// The geometry launches of a whole step: vertex classes, face intervals, then volume
+// fractions with both sweeps' time-averaged apertures.
+void launch_geo_step(const Engine& E, hipStream_t s) {
+    int n = (int)E.mem.size();
+    const StepArgs* A = E.d_args;
+    if (E.multi) {
+        klaunch(kb_geo<0, true>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
+        klaunch(kb_geo<1, true>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
+        klaunch(kb_geo_cells_swept<true>, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
+        return;
+    }
+    klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
+    klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
+    klaunch(kb_geo_cells_swept<>, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
+}
+
 // The per-phase launches of a whole step (arguments already in device memory).
 template <typename R>
 void step_kernels(const Engine& E, hipStream_t s, int dir0) {
     int which0 = dir0 < 0 ? 3 : 1 << dir0, which1 = dir0 < 0 ? 3 : 1 << (1 - dir0);
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
-    klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
-    klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
+    launch_geo_step(E, s);
     // the second sweep's dense tiles and its covering leave partial maxima of the new
     // state's wave speeds; its collapse launch (one block per member) combines them
     for (int sw = 0; sw < 2; sw++) {
@@ -1149,9 +1170,7 @@ void step_kernels_timed(Engine& E, hipStream_t s, int dir0) {
     int which0 = dir0 < 0 ? 3 : 1 << dir0, which1 = dir0 < 0 ? 3 : 1 << (1 - dir0);
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
-    klaunch(kb_geo<0>, ktotal(E, L_V1), T_WIDE, s, A, koff(E, L_V1), n);
-    klaunch(kb_geo<1>, ktotal(E, L_F1), T_WIDE, s, A, koff(E, L_F1), n);
-    klaunch(kb_geo_cells_swept, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
+    launch_geo_step(E, s);
     for (int sw = 0; sw < 2; sw++) {
         int which = sw == 0 ? which0 : which1;
         launch_sweep_dense<R>(E, s, sw, which, sw, [&](int d) { return engine_pair(E, d); });

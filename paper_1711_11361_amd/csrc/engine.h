@@ -212,11 +212,12 @@ constexpr int THREAD_ITEMS = 32;
 // chain search (THREAD_ITEMS).  The whole block calls it.
 // The job's items are taken nb T_WIDE at a time (the launch grid is capped, so a large
 // region takes several passes).
-template <int K>
+// MB: a context with several bodies (posed by the host; one thread per item).
+template <int K, bool MB = false>
 __device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int lb, int nb, double* spoly) {
     const GeoJob& J = a.geo[lev];
     if (!J.active) return;
-    if (J.L.np > 0) {  // several bodies (posed by the host)
+    if (MB) {
         geo_bodies_block<K>(a.g, J, lb, nb, a.status);
         return;
     }
@@ -271,34 +272,36 @@ __device__ __forceinline__ void geo_stage_block(const StepArgs& a, int lev, int 
 
 // Stage K of both level jobs of a member: the first half of its nb blocks works on level
 // job 0, the second half on job 1 (the whole block calls it).
-template <int K>
+template <int K, bool MB = false>
 __device__ __forceinline__ void geo_stage_split(const StepArgs& a, int lb, int nb, double* spoly) {
     int half = nb >> 1;
     int lev = lb >= half ? 1 : 0;
-    geo_stage_block<K>(a, lev, lb - lev * half, half, spoly);
+    geo_stage_block<K, MB>(a, lev, lb - lev * half, half, spoly);
 }
 
 // Stage K of both level jobs of every member.
-template <int K>
+template <int K, bool MB = false>
 __global__ __launch_bounds__(T_WIDE) void kb_geo(const StepArgs* __restrict__ A, const int* __restrict__ off, int n) {
     __shared__ __attribute__((aligned(16))) double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
-    geo_stage_split<K>(A[w.u], w.lb, w.nb, spoly);
+    geo_stage_split<K, MB>(A[w.u], w.lb, w.nb, spoly);
 }
 
 // ------------------------------------------------------------------ sweeps
 __device__ __forceinline__ bool box_empty_dev(const Box& B) { return B.i0 >= B.i1 || B.j0 >= B.j1; }
 
+template <bool MB = false>
 __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, int nb, double* spoly);
 
 // Time-averaged apertures of sweep s over the faces of block lb (of nb) of the sweep box;
 // faces left open by the quick tests on a many-sided polygon by chain search (THREAD_ITEMS).
+template <bool MB>
 __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, int nb, double* spoly) {
     const SweepJob& J = a.sw[s];
     if (box_empty_dev(J.B)) return;
     Stage S = stage_of(a, s);
     int items = J.dir == 0 ? (J.B.w() + 1) * J.B.h() : J.B.w() * (J.B.h() + 1);
-    if (J.Ls.np > 0) {  // several bodies
+    if (MB) {  // several bodies
         for (int t = lb * T_WIDE + (int)threadIdx.x; t < items; t += nb * T_WIDE) {
             if (J.dir == 0) swept_bodies<0>(a.g, J, a.bmot, S, t);
             else swept_bodies<1>(a.g, J, a.bmot, S, t);
@@ -335,17 +338,19 @@ __device__ __forceinline__ void swept_block(const StepArgs& a, int s, int lb, in
     __syncthreads();  // the staged polygon may be overwritten next
 }
 
+template <bool MB = false>
 __global__ __launch_bounds__(T_WIDE) void kb_swept(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                    int n, int s) {
     __shared__ __attribute__((aligned(16))) double spoly[2 * LDS_VERTS];
     Unit w = unit_of(off, n);
-    swept_block(A[w.u], s, w.lb, w.nb, spoly);
+    swept_block<MB>(A[w.u], s, w.lb, w.nb, spoly);
 }
 
 // Volume fractions of both level jobs and the time-averaged apertures of both sweeps (they
 // need only the face intervals of the three levels) in one launch: a member's first
 // nb_cells blocks do the cells, the next nb_swept the first sweep's faces, the last
 // nb_swept the second sweep's.
+template <bool MB = false>
 __global__ __launch_bounds__(T_WIDE) void kb_geo_cells_swept(const StepArgs* __restrict__ A,
                                                              const int* __restrict__ off, int n) {
     __shared__ __attribute__((aligned(16))) double spoly[2 * LDS_VERTS];
@@ -353,12 +358,12 @@ __global__ __launch_bounds__(T_WIDE) void kb_geo_cells_swept(const StepArgs* __r
     const StepArgs& a = A[w.u];
     int lb = w.lb;
     if (lb < a.nb_cells) {
-        geo_stage_split<2>(a, lb, a.nb_cells, spoly);
+        geo_stage_split<2, MB>(a, lb, a.nb_cells, spoly);
         return;
     }
     lb -= a.nb_cells;
     int s = lb >= a.nb_swept ? 1 : 0;
-    swept_block(a, s, lb - s * a.nb_swept, a.nb_swept, spoly);
+    swept_block<MB>(a, s, lb - s * a.nb_swept, a.nb_swept, spoly);
 }
 
 template <typename R, bool MB = false>
