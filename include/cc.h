@@ -107,8 +107,8 @@ cc_status cc_destroy(cc_ctx* ctx);
  * levels, sets device status bit 4, and the next synchronising call returns
  * CC_ERR_UNSUPPORTED.  nbodies 0 or 1 is cc_create (bodies: NULL, or one body).  With
  * two or more, the geometry and box phases cover the whole grid, and steps are planned on
- * the host: cc_advance, the persistent launch mode, batches, cc_autotune,
- * cc_surface_loads and cc_surface_pressure return CC_ERR_UNSUPPORTED.  bodies: host,
+ * the host: cc_advance, the persistent launch mode, batches, cc_autotune and
+ * cc_surface_loads (use cc_body_loads) return CC_ERR_UNSUPPORTED.  bodies: host,
  * copied; at most CC_MAX_BODIES. */
 #define CC_MAX_BODIES 4
 size_t cc_workspace_bytes_bodies(const cc_config* cfg, const cc_body* bodies, int32_t nbodies);
@@ -181,8 +181,15 @@ cc_status cc_advance(cc_ctx* ctx, int32_t nsteps, double cfl, double* h_dt, floa
  * into the body (reading R12).  h_out4 (host, 4 doubles): Fx, Fy, the moment Mz about the
  * body's pose origin, and sum p* |N| (the scale against which the rounding of the other
  * three is measured).  Deterministic summation order; zeros without a body.  Needs a state
- * and no open step (CC_ERR_ARG).  Synchronizes. */
+ * and no open step (CC_ERR_ARG).  Synchronizes.  A context with several bodies: CC_ERR_UNSUPPORTED
+ * (see cc_body_loads). */
 cc_status cc_surface_loads(cc_ctx* ctx, double* h_out4);
+
+/* The same loads on one body of a context with several bodies (cc_create_bodies; reading R30):
+ * the sum over the wall cells that body cuts at level n, each with its own wall velocity, and
+ * the moment about that body's pose origin.  body: 0 .. nbodies - 1 (a one-body context takes
+ * 0 and returns cc_surface_loads); CC_ERR_ARG otherwise.  Synchronizes. */
+cc_status cc_body_loads(cc_ctx* ctx, int32_t body, double* h_out4);
 
 /* Wall pressure distribution at level n (the surface pressure of the pitching aerofoil,
  * Sec. 3.6; from it the pressure coefficient of each wall cell): for every cell with fluid
@@ -192,7 +199,8 @@ cc_status cc_surface_loads(cc_ctx* ctx, double* h_out4);
  * the body) -- the terms whose sums cc_surface_loads returns.  d_out (device, caller-owned,
  * 6 * max_records doubles; may be null when max_records is 0) receives the first
  * max_records records; *h_n (host) the number of wall cells, also when it exceeds
- * max_records (call with 0 to size the buffer).  Synchronizes. */
+ * max_records (call with 0 to size the buffer).  With several bodies, every body's wall cells,
+ * each p* with the velocity of the body that cuts the cell.  Synchronizes. */
 cc_status cc_surface_pressure(cc_ctx* ctx, double* d_out, int32_t max_records, int32_t* h_n);
 
 /* Conservation totals sum(U) hx hy per component (rho, rho u, rho v, E), FP64,

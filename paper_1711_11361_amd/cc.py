@@ -68,6 +68,7 @@ _sig = {
     "cc_set_budget": (C.c_int, [_vp, _i32]),
     "cc_totals_state": (C.c_int, [_vp, _i32, _i32, _i32, _d, _d, _vp, _vp]),
     "cc_surface_loads": (C.c_int, [_vp, C.POINTER(_d)]),
+    "cc_body_loads": (C.c_int, [_vp, _i32, C.POINTER(_d)]),
     "cc_surface_pressure": (C.c_int, [_vp, C.c_void_p, _i32, C.POINTER(_i32)]),
     "cc_info": (C.c_int, [_vp, C.POINTER(_d), _i32]),
     "cc_autotune": (C.c_int, [_vp, _i32, C.POINTER(_i32), C.c_char_p]),
@@ -547,6 +548,12 @@ class Solver:
     def surface_loads(self):
         """(Fx, Fy, Mz about the pose origin, sum p*|N|) of the gas on the body at level n."""
         return cc_surface_loads(self.ctx)
+
+    def body_loads(self, body):
+        """surface_loads of one body of several (the wall cells it cuts; moment about its origin)."""
+        out = np.zeros(4)
+        _check(self.ctx, _lib.cc_body_loads(self.ctx, int(body), out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def surface_pressure(self):
         """Wall cells at level n in increasing index: rows (index, wall x, wall y, p*, Nx, Ny)."""

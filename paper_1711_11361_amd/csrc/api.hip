@@ -2261,23 +2261,39 @@ cc_status cc_totals_state(const void* d_u, int32_t precision, int32_t nx, int32_
     return CC_OK;
 }
 
-cc_status cc_surface_loads(cc_ctx* c, double* h_out4) {
+}  // extern "C"
+
+namespace {
+
+// The gas's velocity field of the bodies at the context's time, for the loads kernels.
+void loads_bodies(const cc_ctx* c, LoadsArgs& a) {
+    std::memset(a.bv, 0, sizeof(a.bv));
+    if (c->nb > 1) {
+        for (int b = 0; b < c->nb; b++) {
+            const HostBody& B = c->hb[b];
+            a.bv[b] = BodyVel{B.vx, B.vy, B.amp * B.omega * std::cos(B.omega * c->t), B.ref_x + B.vx * c->t,
+                              B.ref_y + B.vy * c->t};
+        }
+        return;
+    }
+    a.bv[0] = BodyVel{c->vx, c->vy, c->amp * c->omega * std::cos(c->omega * c->t), c->ref_x + c->vx * c->t,
+                      c->ref_y + c->vy * c->t};
+}
+
+cc_status loads_of(cc_ctx* c, int body, double* h_out4) {
     if (!c || !h_out4) return fail(c, CC_ERR_ARG, "bad argument");
-    if (c->in_step) return fail(c, CC_ERR_ARG, "cc_surface_loads inside a step");
+    if (c->in_step) return fail(c, CC_ERR_ARG, "surface loads inside a step");
     if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
-    if (c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "surface loads of several bodies");
+    if (body < 0 || body >= std::max(c->nb, 1)) return fail(c, CC_ERR_ARG, "no such body");
     for (int k = 0; k < 4; k++) h_out4[k] = 0.0;
     const Box& reg = c->lbox[c->s0];
-    if (c->m == 0 || box_empty(reg)) return CC_OK;
+    if (!has_body(c) || box_empty(reg)) return CC_OK;
     LoadsArgs a;
     a.g = c->g;
     a.L = c->lev[c->s0];
     a.reg = reg;
-    a.vx = c->vx;
-    a.vy = c->vy;
-    a.thd = c->amp * c->omega * std::cos(c->omega * c->t);
-    a.cx = c->ref_x + c->vx * c->t;
-    a.cy = c->ref_y + c->vy * c->t;
+    loads_bodies(c, a);
+    a.body = body;
     int blocks = (int)std::min<size_t>(LOADS_MAX_BLOCKS, nblk((size_t)reg.w() * reg.h(), LOADS_T));
     double* part = at<double>(c, c->lay.off_part);
     double* out = at<double>(c, c->lay.off_tot);
@@ -2294,23 +2310,30 @@ cc_status cc_surface_loads(cc_ctx* c, double* h_out4) {
     return CC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+cc_status cc_surface_loads(cc_ctx* c, double* h_out4) {
+    if (c && c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "several bodies: the loads of each (cc_body_loads)");
+    return loads_of(c, 0, h_out4);
+}
+
+cc_status cc_body_loads(cc_ctx* c, int32_t body, double* h_out4) { return loads_of(c, body, h_out4); }
+
 cc_status cc_surface_pressure(cc_ctx* c, double* d_out, int32_t max_records, int32_t* h_n) {
     if (!c || !h_n || max_records < 0 || (max_records > 0 && !d_out)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_surface_pressure inside a step");
     if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
-    if (c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "surface pressure of several bodies");
     *h_n = 0;
     const Box& R = c->lbox[c->s0];
-    if (c->m == 0 || box_empty(R)) return CC_OK;
+    if (!has_body(c) || box_empty(R)) return CC_OK;
     LoadsArgs a;
     a.g = c->g;
     a.L = c->lev[c->s0];
     a.reg = R;
-    a.vx = c->vx;
-    a.vy = c->vy;
-    a.thd = c->amp * c->omega * std::cos(c->omega * c->t);
-    a.cx = c->ref_x + c->vx * c->t;
-    a.cy = c->ref_y + c->vy * c->t;
+    loads_bodies(c, a);
+    a.body = 0;
     int cells = R.w() * R.h();
     int chunk = (cells + CUT_BLOCKS - 1) / CUT_BLOCKS, nb = (cells + chunk - 1) / chunk;
     int* counts = at<int>(c, c->lay.off_part);  // 4 KiB of the reduction scratch

@@ -15,12 +15,24 @@ namespace cc {
 constexpr int LOADS_T = 256;
 constexpr int LOADS_MAX_BLOCKS = 128;
 
+struct BodyVel {
+    double vx, vy, thd, cx, cy;  // rigid velocity v + thd z x (X - c) at time t
+};
+
 struct LoadsArgs {
     Grid g;
     Level L;    // level n
     Box reg;    // the cells that may differ from fluid
-    double vx, vy, thd, cx, cy;  // rigid velocity v + thd z x (X - c) at time t
+    BodyVel bv[MAX_BODIES];  // each body's velocity (one body: bv[0])
+    int body;   // several bodies: the wall cells of this body only, moments about its origin
 };
+
+// The body of wall cell k (several bodies: the one the level says cuts it).
+__device__ __forceinline__ int loads_body(const LoadsArgs& a, size_t k) {
+    if (!a.L.cbody) return 0;
+    int b = a.L.cbody[k];
+    return b >= 0 ? b : 0;
+}
 
 // A wall cell: fluid content and a non-zero effective wall normal (Nx, Ny).
 __device__ __forceinline__ bool wall_cell(const Grid& g, const Level& L, double al, double u0, int i, int j,
@@ -44,8 +56,9 @@ __device__ __forceinline__ double wall_pressure(const LoadsArgs& a, const R* __r
     for (int m = 0; m < 4; m++) q[m] = (double)U[m * nc + k] / al;
     double nn = sqrt(Nx * Nx + Ny * Ny);
     wall_point(g, f, i, j, &wx, &wy);
-    double uwx = a.vx - a.thd * (wy - a.cy);
-    double uwy = a.vy + a.thd * (wx - a.cx);
+    const BodyVel& v = a.bv[loads_body(a, k)];
+    double uwx = v.vx - v.thd * (wy - v.cy);
+    double uwy = v.vy + v.thd * (wx - v.cx);
     double ps, rs;
     wall_riemann(q, Nx / nn, Ny / nn, uwx, uwy, g.gamma, &ps, &rs);
     return ps;
@@ -64,11 +77,13 @@ __global__ __launch_bounds__(LOADS_T) void k_loads(LoadsArgs a, const R* __restr
         CellFaces f;
         double Nx, Ny;
         if (!wall_cell(g, a.L, al, (double)U[k], i, j, f, Nx, Ny)) continue;
+        if (a.L.cbody && a.L.cbody[k] != a.body) continue;
         double wx, wy;
         double ps = wall_pressure(a, U, i, j, k, al, f, Nx, Ny, wx, wy);
+        const BodyVel& o = a.bv[a.body];
         acc[0] += ps * Nx;
         acc[1] += ps * Ny;
-        acc[2] += (wx - a.cx) * (ps * Ny) - (wy - a.cy) * (ps * Nx);
+        acc[2] += (wx - o.cx) * (ps * Ny) - (wy - o.cy) * (ps * Nx);
         acc[3] += ps * sqrt(Nx * Nx + Ny * Ny);
     }
     __shared__ double sh[4][LOADS_T];

@@ -180,3 +180,28 @@ def test_unsupported_calls_refuse():
     b.close()
     s.step(s.cfl_dt(0.5))  # still steps on its own
     assert s.info()["status"] == 0
+
+
+@pytest.mark.parametrize("name", ["piston_tube", "diamonds", "far_apart"])
+def test_body_loads_and_pressure_match_oracle(name):
+    """Per-body loads and the wall pressure distribution from identical states (R30): the
+    bars of the one-body tests (loads to 1e-12 of sum p*|N|, p* per cell to 1e-12 of the
+    largest plus 1e-13 p*/alpha)."""
+    w = dict(cases())[name]
+    o, s = pair(w)
+    for _ in range(12):
+        o.step(o.cfl_dt(w["cfl"]))
+    s.set_clock(o.t, o.steps)
+    s.set_u(o.get_u())
+    g = w["grid"]
+    size = max(g["x_hi"] - g["x_lo"], g["y_hi"] - g["y_lo"])
+    for b in range(len(w["bodies"])):
+        lo, lg = o.body_loads(b), s.body_loads(b)
+        assert lo[3] > 0, (name, b)
+        assert abs(lg[0] - lo[0]) <= 1e-12 * lo[3] and abs(lg[1] - lo[1]) <= 1e-12 * lo[3], (name, b, lg, lo)
+        assert abs(lg[2] - lo[2]) <= 1e-12 * lo[3] * size and abs(lg[3] - lo[3]) <= 1e-12 * lo[3], (name, b)
+    ro, rg = o.surface_pressure(), s.surface_pressure()
+    assert len(ro) > 0 and np.array_equal(rg[:, 0], ro[:, 0]), name
+    al = o.geometry_dump(0)["alpha"].reshape(-1)[ro[:, 0].astype(np.int64)]
+    bound = 1e-12 * np.abs(ro[:, 3]).max() + 1e-13 * np.abs(ro[:, 3]) / al
+    assert (np.abs(rg[:, 3] - ro[:, 3]) <= bound).all(), name

@@ -11,9 +11,9 @@ and two bodies in relative motion, the planar form of Sec. 3.5).
 * a density pulse advected along the moving channel converges to the exact (advected)
   solution at better than first order, at a fixed CFL number and with the CFL number
   halved per refinement (Eq. CFLvarying);
-* two bodies far apart: near each body the flow equals that of the same body alone, bit for
-  bit (the several-body geometry, apertures, body of each cut cell and wall velocities of
-  one body are those of the one-body path);
+* two bodies far apart: near each body the flow, and the loads on it, equal those of the
+  same body alone, bit for bit (the several-body geometry, apertures, body of each cut cell
+  and wall velocities of one body are those of the one-body path);
 * two mirror-image bodies approaching each other until one cell separates them (faces
   shielded from both sides) give a mirror-image flow;
 * conservation: the change of each total over a sweep equals its budget (domain-boundary
@@ -111,6 +111,8 @@ def test_far_apart_bodies_each_act_as_alone():
         assert np.array_equal(Ub[:, :, cols], Ua[:, :, cols]), k
         moved = np.abs(Ua[:, :, cols] - Ua[:, 0:1, 0:1][:, :, :1]).max()
         assert moved > 1e-3  # the body near these columns did disturb them
+        # the loads on that body: the same wall cells in the same order
+        assert np.array_equal(both.body_loads(k), o.surface_loads()), k
 
 
 def test_mirrored_bodies_give_a_mirrored_flow():
