@@ -62,7 +62,9 @@ typedef struct {
     int32_t bc[4];      /* W, E, S, N (cc_bc) */
     int32_t precision;  /* cc_precision: FP64 state, or FP32 state and dense fluxes with FP64
                            geometry and FP64 cut-cell arithmetic */
-    int32_t reserved;   /* must be 0 */
+    int32_t options;    /* bit 0: axisymmetric about the x axis (y is the radius, y_lo >= 0; the
+                           geometric source of the axisymmetric Euler equations, Sec. 3.5, is applied
+                           before each step's first sweep; reading R33); other bits must be 0 */
     double x_lo, x_hi, y_lo, y_hi;
     double gamma;       /* ratio of specific heats (perfect gas, Sec. 2.1) */
     double alpha_min;   /* small-cell threshold: a cut cell whose volume fraction is below it

@@ -31,7 +31,7 @@ typedef struct {
     int32_t nx, ny;
     int32_t bc[4];     /* W, E, S, N : 0 transmissive (zero gradient), 1 reflective */
     int32_t precision; /* ignored by the oracle (always FP64) */
-    int32_t reserved;
+    int32_t options;   /* bit 0: axisymmetric about the x axis (y is the radius; reading R33) */
     double x_lo, x_hi, y_lo, y_hi;
     double gamma;
     double alpha_min;  /* cut cells with a smaller volume fraction count as solid (reading
@@ -626,6 +626,7 @@ void ccref_destroy(ccref_ctx* c) {
 ccref_ctx* ccref_create_bodies(const ccref_config* cfg, const ccref_body* bodies, int nbodies) {
     if (cfg->nx < 1 || cfg->ny < 1 || !(cfg->x_hi > cfg->x_lo) || !(cfg->y_hi > cfg->y_lo)) return NULL;
     if (!(cfg->alpha_min >= 0.0 && cfg->alpha_min < 0.5)) return NULL;
+    if (cfg->options & ~1 || ((cfg->options & 1) && !(cfg->y_lo >= 0.0))) return NULL;
     if (nbodies < 0 || nbodies > CCREF_MAX_BODIES || (nbodies > 0 && !bodies)) return NULL;
     for (int b = 0; nbodies > 1 && b < nbodies; b++)
         if (bodies[b].nverts < 3) return NULL;
@@ -1572,8 +1573,35 @@ int ccref_sweep(ccref_ctx* c, int dir, double dt) {
 /* Start a split step of size dt: pose the body at t^{n+1}, build the stage level (first
  * sweep's direction moves the polygon, the other coordinate stays; reading R11) and the
  * end level. */
+/* Axisymmetric form (option bit 0; reading R33; the shock tube of Sec. 3.5 uses the Euler
+ * equations in axisymmetric form): in (x, r) with r = y the equations carry the geometric
+ * source S = -(1/r) (rho v, rho u v, rho v^2, v (E + p)).  It is applied as an operator step
+ * of length dt before the split step's first sweep, to the content per cell volume (S is
+ * homogeneous of degree one in the state, so S(U) = alpha S(Q), p from U as from Q), with r
+ * the radius of the cell centre; cells without content are skipped. */
+static void axisym_source(ccref_ctx* c, double dt) {
+    size_t nc = (size_t)c->cfg.nx * c->cfg.ny;
+    double g = c->cfg.gamma;
+    for (int j = 0; j < c->cfg.ny; j++) {
+        double r = vy_of(c, j) + 0.5 * c->hy;
+        double f = dt / r;
+        for (int i = 0; i < c->cfg.nx; i++) {
+            size_t k = CIDX(c, i, j);
+            double rho = c->U[k], mx = c->U[nc + k], my = c->U[2 * nc + k], e = c->U[3 * nc + k];
+            if (!(rho > 0.0)) continue;
+            double v = my / rho;
+            double p = (g - 1.0) * (e - 0.5 * (mx * mx + my * my) / rho);
+            c->U[k] = rho - f * my;
+            c->U[nc + k] = mx - f * (mx * v);
+            c->U[2 * nc + k] = my - f * (my * v);
+            c->U[3 * nc + k] = e - f * (v * (e + p));
+        }
+    }
+}
+
 int ccref_begin_step(ccref_ctx* c, double dt) {
     if (c->in_step || !(dt > 0.0)) return 1;
+    if (c->cfg.options & 1) axisym_source(c, dt);
     double t1 = c->t + dt;
     if (c->parity == 0)
         level_posed(c, t1, c->t, &c->L[c->sm]);

@@ -13,7 +13,7 @@ from . import build as _build
 
 class _Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4),
-                ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("precision", C.c_int32), ("options", C.c_int32),
                 ("x_lo", C.c_double), ("x_hi", C.c_double), ("y_lo", C.c_double),
                 ("y_hi", C.c_double), ("gamma", C.c_double), ("alpha_min", C.c_double)]
 
@@ -174,6 +174,7 @@ class Oracle:
         cfg.y_lo, cfg.y_hi = grid["y_lo"], grid["y_hi"]
         cfg.gamma = grid.get("gamma", 1.4)
         cfg.alpha_min = grid.get("alpha_min", 0.0)
+        cfg.options = 1 if grid.get("axisymmetric", False) else 0
         self.nx, self.ny = cfg.nx, cfg.ny
         self.gamma = cfg.gamma
         if bodies is not None:

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "CC_OK", 1: "CC_ERR_ARG", 2: "CC_ERR_DEVICE", 3: "CC_ERR_WORK
 
 class cc_config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4), ("precision", C.c_int32),
-                ("reserved", C.c_int32), ("x_lo", C.c_double), ("x_hi", C.c_double), ("y_lo", C.c_double),
+                ("options", C.c_int32), ("x_lo", C.c_double), ("x_hi", C.c_double), ("y_lo", C.c_double),
                 ("y_hi", C.c_double), ("gamma", C.c_double), ("alpha_min", C.c_double)]
 
 
@@ -114,7 +114,7 @@ def make_config(grid, precision=CC_FP64):
     for k, v in enumerate(grid.get("bc", (0, 0, 0, 0))):
         c.bc[k] = v
     c.precision = precision
-    c.reserved = 0
+    c.options = 1 if grid.get("axisymmetric", False) else 0
     c.x_lo, c.x_hi, c.y_lo, c.y_hi = grid["x_lo"], grid["x_hi"], grid["y_lo"], grid["y_hi"]
     c.gamma = grid.get("gamma", 1.4)
     c.alpha_min = grid.get("alpha_min", 0.0)
