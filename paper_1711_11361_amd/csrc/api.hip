@@ -273,6 +273,10 @@ struct Engine {
     // block in the host buffers and the upload
     bool multi = false;
     size_t extra = 0;
+    // an instance in axisymmetric form (its own engine only): the source launch before the
+    // first sweep, over axi_blocks blocks
+    bool axisym = false;
+    int axi_blocks = 0;
 };
 
 // One of several bodies (host copy of its cc_body).
@@ -786,6 +790,7 @@ cc_status prepare_step(cc_ctx* c, double dt, StepArgs& a) {
             return fail(c, CC_ERR_WORKSPACE, "sweep region exceeds the staging capacity");
     }
     a.step_id = (int32_t)(c->step & 0x7fffffff);
+    a.dt = dt;
     c->step_dt = dt;
     c->last_sweep_box = a.sw[1].B;
     return CC_OK;
@@ -1147,6 +1152,12 @@ void launch_geo_step(const Engine& E, hipStream_t s) {
     klaunch(kb_geo_cells_swept<>, ktotal(E, L_CS), T_WIDE, s, A, koff(E, L_CS), n);
 }
 
+// The axisymmetric source before the step's first sweep (one instance).
+template <typename R>
+void launch_axisym(const Engine& E, hipStream_t s) {
+    if (E.axisym) klaunch(k_axisym<R>, E.axi_blocks, 256, s, (const StepArgs*)E.d_args);
+}
+
 // The per-phase launches of a whole step (arguments already in device memory).
 template <typename R>
 void step_kernels(const Engine& E, hipStream_t s, int dir0) {
@@ -1154,6 +1165,7 @@ void step_kernels(const Engine& E, hipStream_t s, int dir0) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
     launch_geo_step(E, s);
+    launch_axisym<R>(E, s);
     // the second sweep's dense tiles and its covering leave partial maxima of the new
     // state's wave speeds; its collapse launch (one block per member) combines them
     for (int sw = 0; sw < 2; sw++) {
@@ -1171,6 +1183,7 @@ void step_kernels_timed(Engine& E, hipStream_t s, int dir0) {
     int n = (int)E.mem.size();
     const StepArgs* A = E.d_args;
     launch_geo_step(E, s);
+    launch_axisym<R>(E, s);
     for (int sw = 0; sw < 2; sw++) {
         int which = sw == 0 ? which0 : which1;
         launch_sweep_dense<R>(E, s, sw, which, sw, [&](int d) { return engine_pair(E, d); });
@@ -1299,7 +1312,8 @@ cc_status create_impl(const cc_config* cfg, const cc_body* body, int nbodies, vo
     if (!out) return create_fail(nullptr, CC_ERR_ARG, "null output pointer");
     *out = nullptr;
     if (!cfg || cfg->nx < 1 || cfg->ny < 1 || !(cfg->x_hi > cfg->x_lo) || !(cfg->y_hi > cfg->y_lo) ||
-        !(cfg->gamma > 1.0) || cfg->reserved != 0 || (cfg->precision != CC_FP64 && cfg->precision != CC_FP32_GEOM64) ||
+        !(cfg->gamma > 1.0) || (cfg->options & ~1) != 0 || ((cfg->options & 1) && !(cfg->y_lo >= 0.0)) ||
+        (cfg->precision != CC_FP64 && cfg->precision != CC_FP32_GEOM64) ||
         !(cfg->alpha_min >= 0.0 && cfg->alpha_min < 0.5))
         return create_fail(nullptr, CC_ERR_ARG, "invalid configuration");
     for (int k = 0; k < 4; k++)
@@ -1416,6 +1430,8 @@ cc_status create_impl(const cc_config* cfg, const cc_body* body, int nbodies, vo
     E.tile_y = 0;  // 8-row y-sweep tiles
     E.multi = multi;
     E.extra = lay.set_bytes;
+    E.axisym = (cfg->options & 1) != 0;
+    E.axi_blocks = (int)std::min<size_t>(nblk(lay.nc, 256), 2048);
     hipError_t e = engine_alloc_host(E);
     if (e != hipSuccess) return create_fail(c, CC_ERR_DEVICE, std::string("host buffers: ") + hipGetErrorString(e));
     // all-fluid levels, clean reductions and lists, stamps that match no step, body vertices
@@ -1674,6 +1690,9 @@ cc_status cc_begin_step(cc_ctx* c, double dt) {
     tstart(c, 3, tp);
     launch_geometry(c->eng, c->stream);
     tstop(c, tp);
+    // the axisymmetric source acts on the level-n state before the first sweep
+    if (fp32(c)) launch_axisym<float>(c->eng, c->stream);
+    else launch_axisym<double>(c->eng, c->stream);
     HIPCHK(c, hipGetLastError());
     c->in_step = true;
     c->sweeps_done = 0;
@@ -2159,6 +2178,7 @@ cc_status cc_advance(cc_ctx* c, int32_t nsteps, double cfl, double* h_dt, float*
     if (st != CC_OK) return st;
     if (h_done) *h_done = 0;
     if (c->nb > 1) return fail(c, CC_ERR_UNSUPPORTED, "several bodies: steps are planned on the host (cc_step)");
+    if (c->eng.axisym) return fail(c, CC_ERR_UNSUPPORTED, "axisymmetric form: steps are planned on the host (cc_step)");
     if (nsteps < 0 || !(cfl > 0.0) || !std::isfinite(cfl)) return fail(c, CC_ERR_ARG, "bad argument");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_advance inside a step");
     if (!c->have_state) return fail(c, CC_ERR_ARG, "no state set");
@@ -2560,8 +2580,8 @@ cc_status cc_set_launch_mode(cc_ctx* c, int32_t mode) {
     if (!c) return CC_ERR_ARG;
     if (mode != CC_LAUNCH_PER_PHASE && mode != CC_LAUNCH_PERSISTENT) return fail(c, CC_ERR_ARG, "unknown launch mode");
     if (c->in_step) return fail(c, CC_ERR_ARG, "cc_set_launch_mode inside a step");
-    if (mode == CC_LAUNCH_PERSISTENT && c->nb > 1)
-        return fail(c, CC_ERR_UNSUPPORTED, "several bodies: one launch per phase");
+    if (mode == CC_LAUNCH_PERSISTENT && (c->nb > 1 || c->eng.axisym))
+        return fail(c, CC_ERR_UNSUPPORTED, "several bodies or axisymmetric form: one launch per phase");
     if (mode == CC_LAUNCH_PERSISTENT && c->budget_on)
         return fail(c, CC_ERR_UNSUPPORTED, "the budget is not tracked in the persistent launch mode");
     HIPCHK(c, hipStreamSynchronize(c->stream));  // the captured graphs are about to be destroyed
@@ -2661,7 +2681,8 @@ cc_status cc_batch_add(cc_batch* b, cc_ctx* c) {
     if (!b || !c) return CC_ERR_ARG;
     Engine& E = b->eng;
     if (c->batch) return bfail(b, CC_ERR_ARG, "context already in a batch");
-    if (c->nb > 1) return bfail(b, CC_ERR_UNSUPPORTED, "a context with several bodies steps on its own");
+    if (c->nb > 1 || c->eng.axisym)
+        return bfail(b, CC_ERR_UNSUPPORTED, "a context with several bodies or in axisymmetric form steps on its own");
     if (c->cfg.precision != E.prec) return bfail(b, CC_ERR_ARG, "precision differs from the batch's");
     if ((int)E.mem.size() >= E.cap_n) return bfail(b, CC_ERR_WORKSPACE, "batch is full");
     if (!c->have_state || c->in_step) return bfail(b, CC_ERR_ARG, "context needs a state and no open step");

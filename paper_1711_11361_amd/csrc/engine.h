@@ -22,6 +22,7 @@ struct StepArgs {
     SweepJob sw[2];  // first and second sweep
     Motion mot;
     const Motion* bmot;  // several bodies: each body's motion (null for one body)
+    double dt;           // the step's time step (host-planned steps; the axisymmetric source)
     Stage S;
     Common C;
     unsigned int* status;
@@ -378,6 +379,33 @@ __device__ __forceinline__ void stagewall_body(const StepArgs& a, int s, int t) 
 
 // Box cells t, t + stride, ... of sweep s (the launch grid is capped; at least the first
 // call runs, which clears the sweep's counters).
+// Axisymmetric form (the Euler equations of the shock tube of Sec. 3.5 in (x, r), r = y):
+// the geometric source -(1/r) (rho v, rho u v, rho v^2, v (E + p)) as an operator step of
+// length dt before the step's first sweep, on the content per cell volume (the source is
+// homogeneous of degree one in the state, so S(U) = alpha S(Q)), r the cell centre's radius;
+// cells without content are skipped.  One instance (its first sweep's input, updated in
+// place).
+template <typename R>
+__global__ __launch_bounds__(256) void k_axisym(const StepArgs* __restrict__ A) {
+    const StepArgs& a = A[0];
+    const Grid& g = a.g;
+    R* U = (R*)a.sw[0].Uin;
+    size_t nc = (size_t)g.nx * g.ny;
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < nc; k += (size_t)gridDim.x * 256) {
+        int j = (int)(k / (size_t)g.nx);
+        double r = vy_of(g, j) + 0.5 * g.hy;
+        double f = a.dt / r;
+        double rho = (double)U[k], mx = (double)U[nc + k], my = (double)U[2 * nc + k], e = (double)U[3 * nc + k];
+        if (!(rho > 0.0)) continue;
+        double v = my / rho;
+        double p = (g.gamma - 1.0) * (e - 0.5 * (mx * mx + my * my) / rho);
+        U[k] = (R)(rho - f * my);
+        U[nc + k] = (R)(mx - f * (mx * v));
+        U[2 * nc + k] = (R)(my - f * (my * v));
+        U[3 * nc + k] = (R)(e - f * (v * (e + p)));
+    }
+}
+
 template <typename R, bool MB = false>
 __device__ __forceinline__ void stagewall_loop(const StepArgs& a, int s, int t, int stride) {
     const SweepJob& J = a.sw[s];

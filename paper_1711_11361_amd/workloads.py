@@ -293,15 +293,30 @@ def channel_inside(w, t, margin=0.0):
     return np.abs(d) < 0.5 * w["width"] - margin
 
 
-def piston_tube(ny=128, mach_s=1.76, gap=1.0 / 16.0, wall=0.125):
+def uniform_expansion(ny=32, nx=8):
+    """The gas spreading away from the axis of an axisymmetric domain (x, r) in [0, nx/ny] x
+    [0, 1], reflective axis: rho = 1, u = 0, v = r, p = 1 at t = 0; the exact solution of the
+    axisymmetric equations is rho = 1/(1+t)^2, u = 0, v = r/(1+t), p = (1+t)^(-2 gamma)."""
+    g = grid(nx, ny, 0.0, nx / ny, 0.0, 1.0, bc=(0, 0, 1, 0))
+    g["axisymmetric"] = True
+    _, Y = cell_centres(g)
+    prim = np.empty((4, ny, nx))
+    prim[0], prim[1], prim[2], prim[3] = 1.0, 0.0, Y, 1.0
+    return {"name": "uniform_expansion", "grid": g, "body": None, "prim": prim, "cfl": 0.5}
+
+
+def piston_tube(ny=128, mach_s=1.76, gap=1.0 / 16.0, wall=0.125, axisymmetric=False):
     """Two bodies in relative motion, the planar form of the open-ended shock tube of
     Sec. 3.5 (the axisymmetric source terms are not modelled): lengths in tube diameters D,
     the half-tube above the reflective centre line y = 0.  Domain [0, 10] x [0, 4]
     (2.5 ny x ny cells); a static tube wall [-1, 6] x [0.5, 0.5 + wall] (its open end at
     x = 6); a rectangular piston [0.25, 0.5] x [-1, 0.5 - gap] moving along +x at the speed
     that drives a shock of Mach `mach_s` into gas at rest (rho = 1, p = 1).  The piston
-    clears the tube wall by `gap` (reading: no cell may hold both bodies)."""
+    clears the tube wall by `gap` (reading: no cell may hold both bodies).  axisymmetric: the
+    domain is the half plane (x, r) of the axisymmetric equations (the tube a cylinder, the
+    piston a disc)."""
     g = grid(int(2.5 * ny), ny, 0.0, 10.0, 0.0, 4.0, bc=(0, 0, 1, 0))
+    g["axisymmetric"] = bool(axisymmetric)
     a0 = math.sqrt(GAMMA)
     S = mach_s * a0
     k = (S * S - a0 * a0) / (2.0 * S)
