@@ -409,6 +409,53 @@ def tube_leg(ny=512):
     return out
 
 
+def tube_overpressure_leg(ny=512, t_end=4.5, every=8):
+    """The open-ended shock tube in axisymmetric form (Sec. 3.5; planar alongside): overpressure
+    history on the axis 1.5 diameters downstream of the tube's exit (the probe of Fig.
+    Piston_PressureTimeHistory), FP64, host-planned steps."""
+    import numpy as np
+    import torch
+    from paper_1711_11361_amd import cc
+    from paper_1711_11361_amd import workloads as W
+
+    out = {}
+    for name, axi in (("axisymmetric", True), ("planar", False)):
+        w = W.piston_tube(ny, axisymmetric=axi)
+        g = w["grid"]
+        s = cc.Solver(g, bodies=w["bodies"], precision=cc.CC_FP64)
+        s.set_prim(w["prim"])
+        hx = (g["x_hi"] - g["x_lo"]) / g["nx"]
+        ip = int((7.5 - g["x_lo"]) / hx)  # probe cell: x = 7.5 (1.5 D past the exit), first row
+        ts, ps = [], []
+        n, t = 0, 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while t < t_end - 1e-12:
+            dt = min(s.cfl_dt(w["cfl"]), t_end - t)
+            s.step(dt)
+            t += dt
+            n += 1
+            if n % every == 0:
+                u = s.get_u_tensor()[:, 0, ip].cpu().numpy()
+                ts.append(t)
+                ps.append(0.4 * (u[3] - 0.5 * (u[1] ** 2 + u[2] ** 2) / u[0]))
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        st = s.info()["status"]
+        s.close()
+        ps = np.array(ps) - 1.0
+        k = int(np.argmax(ps))
+        arrive = next((ts[q] for q in range(len(ps)) if ps[q] > 0.05), None)
+        out[name] = {"steps": n, "wall_s": T, "status": int(st), "peak_overpressure": float(ps[k]),
+                     "peak_time": float(ts[k]), "arrival_time": arrive,
+                     "history": [[round(a, 4), round(float(b), 4)] for a, b in zip(ts[::4], ps[::4])]}
+        print(f"tube {name}: {n} steps in {T:.2f} s, peak {ps[k]:.3f} at t = {ts[k]:.3f}", file=sys.stderr,
+              flush=True)
+    out["workload"] = (f"piston in the open-ended tube, {int(2.5 * ny)}x{ny} on [0,10]x[0,4] (lengths in tube "
+                       f"diameters), probe on the axis at x = 7.5, overpressure p - p_inf (p_inf = 1), to t = {t_end}")
+    return out
+
+
 def batched(w, instances, steps, warmup):
     """Copies of the headline workload stepped as one batch (device-planned), and the same
     copies as plain FP64 contexts advanced one after another with launches of their own."""
@@ -622,9 +669,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the legs of the other configurations")
-    ap.add_argument("--legs", default="piston,triangle,naca,lift,batched,channel,tube",
+    ap.add_argument("--legs", default="piston,triangle,naca,lift,batched,channel,tube,axisym",
                     help="legs of the other configurations to run (comma list of piston, triangle, naca, lift, "
-                         "batched, channel, tube)")
+                         "batched, channel, tube, axisym)")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving mix, run in a child process (0: skip)")
     ap.add_argument("--serving-only", action="store_true",
@@ -710,6 +757,9 @@ def main():
     if "tube" in legs:
         out["piston_tube"] = tube_leg()
         print("tube done", file=sys.stderr, flush=True)
+    if "axisym" in legs:
+        out["tube_overpressure"] = tube_overpressure_leg()
+        print("axisymmetric tube done", file=sys.stderr, flush=True)
     if args.serving > 0:
         out["serving"] = serving_child(args.serving, args.budget_gib, args.slots)
         print("serving done", file=sys.stderr, flush=True)
