@@ -55,6 +55,40 @@ def diamonds():
             "cfl": 0.5}
 
 
+def squares():
+    """Two squares approaching to 1.6 cells: from t = 0.497 faces between them are shielded
+    from both sides with s_L + s_R above the aperture (the kappa scaling of reading R2)."""
+    g = W.grid(64, 32, 0.0, 2.0, 0.0, 1.0)
+    sq = W.rectangle(-0.1, 0.1, -0.1, 0.1)
+    bodies = [W.body(sq, ref=(0.625, 0.513), vel=(0.5, 0.0)), W.body(sq, ref=(1.375, 0.513), vel=(-0.5, 0.0))]
+    return {"name": "squares", "grid": g, "bodies": bodies, "prim": W.uniform_prim(g, 1.0, 0.0, 0.0, 1.0),
+            "cfl": 0.5}
+
+
+def test_squares_closing_in_match_oracle_per_sweep():
+    """The last steps of two squares closing in (both-sided shielding with the kappa scaling),
+    every sweep from identical inputs <= 1e-12."""
+    w = squares()
+    o, s = pair(w)
+    while o.t < 0.47:
+        o.step(o.cfl_dt(w["cfl"]))
+    s.set_clock(o.t, o.steps)
+    for k in range(4):
+        dt = min(o.cfl_dt(w["cfl"]), 0.5 - o.t)
+        o.begin_step(dt)
+        s.begin_step(dt)
+        for sw in range(2):
+            d = o.parity if sw == 0 else 1 - o.parity
+            s.set_u(o.get_u())
+            o.sweep(d, dt)
+            s.sweep(d, dt)
+            e = rel_linf(s.get_u(), o.get_u())
+            assert e <= FP64_TOL, (k, sw, e)
+        o.end_step()
+        s.end_step()
+    assert o.t > 0.497 and s.info()["status"] == o.status == 0
+
+
 def far_apart():
     g = W.grid(128, 32, 0.0, 4.0, 0.0, 1.0)
     a = W.body(W.triangle(0.3), ref=(0.5, 0.47), theta0=0.2, vel=(0.3, 0.05), pitch_amp=0.3, pitch_omega=2.0)

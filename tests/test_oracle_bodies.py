@@ -14,8 +14,9 @@ and two bodies in relative motion, the planar form of Sec. 3.5).
 * two bodies far apart: near each body the flow, and the loads on it, equal those of the
   same body alone, bit for bit (the several-body geometry, apertures, body of each cut cell
   and wall velocities of one body are those of the one-body path);
-* two mirror-image bodies approaching each other until one cell separates them (faces
-  shielded from both sides) give a mirror-image flow;
+* two mirror-image bodies approaching each other until under two cells separate them
+  (faces shielded from both sides, for squares with the kappa scaling of R2) give a
+  mirror-image flow;
 * conservation: the change of each total over a sweep equals its budget (domain-boundary
   fluxes, wall terms, residuals without recipients);
 * two bodies inside one cell are reported (status bit 4).
@@ -115,11 +116,17 @@ def test_far_apart_bodies_each_act_as_alone():
         assert np.array_equal(both.body_loads(k), o.surface_loads()), k
 
 
-def test_mirrored_bodies_give_a_mirrored_flow():
+@pytest.mark.parametrize("shape", ["diamond", "square"])
+def test_mirrored_bodies_give_a_mirrored_flow(shape):
+    """Squares approaching to 1.6 cells shield the faces between them from both sides with
+    s_L + s_R above the aperture (the kappa scaling of reading R2), from t = 0.497 on."""
     g = W.grid(64, 32, 0.0, 2.0, 0.0, 1.0)  # h = 1/32: mirrored vertices are exact
-    diamond = np.array([[0.1, 0.0], [0.0, 0.1], [-0.1, 0.0], [0.0, -0.1]])
-    a = W.body(diamond, ref=(0.625, 0.5 + 0.013), vel=(0.5, 0.0))
-    b = W.body(diamond, ref=(1.375, 0.5 + 0.013), vel=(-0.5, 0.0))
+    if shape == "diamond":
+        poly = np.array([[0.1, 0.0], [0.0, 0.1], [-0.1, 0.0], [0.0, -0.1]])
+    else:
+        poly = W.rectangle(-0.1, 0.1, -0.1, 0.1)
+    a = W.body(poly, ref=(0.625, 0.5 + 0.013), vel=(0.5, 0.0))
+    b = W.body(poly, ref=(1.375, 0.5 + 0.013), vel=(-0.5, 0.0))
     prim = W.uniform_prim(g, 1.0, 0.0, 0.0, 1.0)
     o = run({"grid": g, "bodies": [a, b], "prim": prim}, t_end=0.5, cfl=0.5)
     assert o.status == 0
