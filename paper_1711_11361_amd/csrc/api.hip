@@ -215,7 +215,7 @@ Layout make_layout(const cc_config* c, const cc_body* b, int nbodies = 1) {
     // patch segments: 12 doubles each; covering blocks: 4 each)
     L.off_budget = take(16 * 8);
     size_t dense_slots = 2 * std::max(nx, ny);
-    size_t patch_blocks = hasb ? (size_t)std::max(patch_line_blocks<0>(L.capw, L.caph), patch_line_blocks<1>(L.capw, L.caph)) : 1;
+    size_t patch_blocks = hasb ? (size_t)std::max(patch_line_blocks<0>(L.capw, L.caph), patch_tile_blocks(L.capw, L.caph)) : 1;
     size_t cover_blocks = (std::max<size_t>(L.cap, 1) + T_BOX - 1) / T_BOX;
     L.bs_patch = (int)(BS_DENSE + 4 * dense_slots);
     L.bs_cover = (int)(L.bs_patch + 12 * patch_blocks);
@@ -848,7 +848,7 @@ int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
         case L_BOX: return cap((int)nblk(std::max<size_t>(L.cap, 1), T_BOX), BOX_BLOCK_CAP);
         case L_BOXW: return cap((int)nblk(std::max<size_t>(L.cap, 1), T_WIDE), BOXW_BLOCK_CAP);
         case L_PX: return cap(std::max(patch_line_blocks<0>(L.capw, L.caph), 1), PATCH_BLOCK_CAP);
-        case L_PY: return cap(std::max(patch_line_blocks<1>(L.capw, L.caph), 1), PATCH_BLOCK_CAP);
+        case L_PY: return cap(std::max(patch_tile_blocks(L.capw, L.caph), 1), PATCH_BLOCK_CAP);
         case L_DX: return dense_blocks(0, E.tile_x, c->g.nx, c->g.ny);
         case L_DY: return dense_blocks(1, E.tile_y, c->g.nx, c->g.ny);
     }
@@ -1044,7 +1044,7 @@ void launch_box_post(const Engine& E, hipStream_t s, int sw, int which, int last
     int nb = ktotal(E, L_BOX);
     const int* ob = koff(E, L_BOX);
     if (which & 1) klaunch(kb_patch_lines<0, R>, ktotal(E, L_PX), PL_T, s, A, koff(E, L_PX), n, sw);
-    if (which & 2) klaunch(kb_patch_lines<1, R>, ktotal(E, L_PY), PL_T, s, A, koff(E, L_PY), n, sw);
+    if (which & 2) klaunch(kb_patch_tiles<R>, ktotal(E, L_PY), PT_T, s, A, koff(E, L_PY), n, sw);
     klaunch(kb_cover<R>, nb, T_BOX, s, A, ob, n, sw, last);
     klaunch(kb_fix_block<R>, n, T_FIX, s, E.d_args, koff(E, L_DX), koff(E, L_DY), ob, sw, last, E.d_gather);
 }

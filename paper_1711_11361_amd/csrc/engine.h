@@ -426,9 +426,9 @@ __global__ __launch_bounds__(T_BOX) void kb_stagewall(const StepArgs* __restrict
 
 
 // The patch update by line segments of the sweep direction (block lb of the member's
-// patch_line_blocks<D>).  One kernel per direction (members whose sweep runs the other way
-// return at once): the update is the largest body, and one direction per kernel keeps it
-// in registers.
+// patch_line_blocks<D>); the x sweep's patch runs it, the y sweep's runs the tiles below.
+// One kernel per direction (members whose sweep runs the other way return at once): the
+// update is the largest body, and one direction per kernel keeps it in registers.
 template <int D, typename R>
 __global__ __launch_bounds__(PL_T) void kb_patch_lines(const StepArgs* __restrict__ A, const int* __restrict__ off,
                                                        int n, int s) {
@@ -441,6 +441,21 @@ __global__ __launch_bounds__(PL_T) void kb_patch_lines(const StepArgs* __restric
     int total = nlines * ((len + PL_OUT - 1) / PL_OUT);
     for (int lb = w.lb; lb < total; lb += w.nb)  // the grid is capped: several segments per block
         patch_line<D, R>(a.g, J, stage_of(a, s), a.ncol, lb, sh, a.bs);
+}
+
+// The y sweep's patch update by tiles of adjacent columns (block lb of the member's
+// patch_tile_blocks).
+template <typename R>
+__global__ __launch_bounds__(PT_T) void kb_patch_tiles(const StepArgs* __restrict__ A, const int* __restrict__ off,
+                                                       int n, int s) {
+    __shared__ TileLds sh;
+    Unit w = unit_of(off, n);
+    const StepArgs& a = A[w.u];
+    const SweepJob& J = a.sw[s];
+    if (J.dir != 1 || box_empty_dev(J.B)) return;
+    int total = patch_tile_blocks(J.B.w(), J.B.h());
+    for (int lb = w.lb; lb < total; lb += w.nb)  // the grid is capped: several tiles per block
+        patch_tile_y<R>(a.g, J, stage_of(a, s), a.ncol, lb, sh, a.bs);
 }
 
 template <typename R>
@@ -645,8 +660,7 @@ __device__ __forceinline__ void sweep_budget(const StepArgs& a, const SweepJob& 
     }
     int np = 0, ncov = 0;
     if (cells > 0) {
-        int len = J.dir == 0 ? J.B.w() : J.B.h(), nlines = J.dir == 0 ? J.B.h() : J.B.w();
-        np = nlines * ((len + PL_OUT - 1) / PL_OUT);
+        np = J.dir == 0 ? J.B.h() * ((J.B.w() + PL_OUT - 1) / PL_OUT) : patch_tile_blocks(J.B.w(), J.B.h());
         ncov = (cells + T_BOX - 1) / T_BOX;
     }
     for (int k = threadIdx.x; k < np; k += blockDim.x)

@@ -856,6 +856,133 @@ __device__ void patch_line(const Grid& g, const SweepJob& J, const Stage& S, uns
     S.gone[b] = (int8_t)gone;
 }
 
+// The y sweep's patch update by tiles: a block of PT_C x PT_P threads covers PT_C adjacent
+// box columns over PT_OUT consecutive rows, plus two rows each side; thread (c, r) fetches
+// the cell of column c at row r, so that a row of the tile is PT_C consecutive cells of the
+// row-major arrays (the line segments of patch_line would walk a column with one cell per
+// cache line).  The per-cell and per-face work, and its order, are patch_line's: results
+// are identical.
+constexpr int PT_C = 16, PT_P = 16, PT_OUT = PT_P - 4, PT_T = PT_C * PT_P;
+
+__host__ __device__ constexpr int patch_tile_blocks(int capw, int caph) {
+    return ((capw + PT_C - 1) / PT_C) * ((caph + PT_OUT - 1) / PT_OUT);
+}
+
+struct TileLds {
+    double q[4][PT_P][PT_C];
+    double er[4][PT_P][PT_C];
+    double phi[4][PT_P][PT_C];
+    bool has[PT_P][PT_C];
+    double red[12][PT_T / 64];
+};
+
+// lb: the block's index within the member (uniform over the block; every thread calls it).
+// bs: budget slots as for patch_line (the tile's sums, its wavefronts in order).
+template <typename R>
+__device__ void patch_tile_y(const Grid& g, const SweepJob& J, const Stage& S, unsigned int* ncollapse, int lb,
+                             TileLds& sh, const BudgetSlots& bs) {
+    constexpr int D = 1;
+    const Level& Ls = J.Ls;
+    const Level& Le = J.Le;
+    const Box& B = J.B;
+    const R* U = (const R*)J.Uin;
+    double lam = J.lam;
+    int len = B.h();
+    int ncb = (B.w() + PT_C - 1) / PT_C, segs = (len + PT_OUT - 1) / PT_OUT;
+    if (lb >= ncb * segs) return;  // uniform over the block
+    int cx = (int)threadIdx.x % PT_C, x = (int)threadIdx.x / PT_C;  // column in the tile, position along it
+    int col = B.i0 + (lb % ncb) * PT_C + cx;
+    bool colok = col < B.i1;
+    int line = colok ? col : B.i1 - 1;  // columns past the box fetch a box column and update nothing
+    int first = B.j0;
+    int p = first + (lb / ncb) * PT_OUT - 2 + x;  // this thread's cell along the column
+    int n = g.ny;
+    double gam = g.gamma;
+    CellData c;
+    fetch_cell<D>(g, U, B, S, line, p, n, c);
+#pragma unroll
+    for (int m = 0; m < 4; m++) sh.q[m][x][cx] = c.q[m];
+    sh.has[x][cx] = c.has;
+    __syncthreads();
+    double el[4] = {0, 0, 0, 0}, er[4] = {0, 0, 0, 0};
+    if (x >= 1 && x < PT_P - 1 && c.has) {
+        double qm[4], qp[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            qm[m] = sh.q[m][x - 1][cx];
+            qp[m] = sh.q[m][x + 1][cx];
+        }
+        bool ok = sh.has[x - 1][cx] && sh.has[x + 1][cx];
+        muscl<double, D>(qm, c.q, qp, ok, lam, gam, el, er);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; m++) sh.er[m][x][cx] = er[m];
+    __syncthreads();
+    WallData wl, wr;
+    fetch_wall<D>(B, S, line, p, n, wr);
+    double btf = 1.0, btp = 1.0;
+    if (x >= 2 && x < PT_P - 1) {  // the lower and upper faces of the updated cells
+        double btm = face_bt<D>(B, S, line, p - 1);
+        btf = face_bt<D>(B, S, line, p);
+        btp = face_bt<D>(B, S, line, p + 1);
+        fetch_wall<D>(B, S, line, p - 1, n, wl);
+        double erl[4], phi[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) erl[m] = sh.er[m][x - 1][cx];
+        bool act = btf > 0.0 && sh.has[x - 1][cx] && c.has;
+        face_phi<D>(btf, btm, btp, erl, el, act, wl, wr, p > 0, p < n, gam, phi);
+#pragma unroll
+        for (int m = 0; m < 4; m++) sh.phi[m][x][cx] = phi[m];
+    }
+    __syncthreads();
+    bool mine = colok && !(x < 2 || x >= PT_P - 2 || p >= first + len);  // a cell this block updates
+    double W[4] = {0, 0, 0, 0};
+    if (mine && c.has && wr.wall) {
+        double db = btp - btf;
+        for (int m = 0; m < 4; m++) W[m] = db * wr.wv[m];
+    }
+    if (bs.base) {  // per wavefront in a fixed lane order, then the wavefronts in order
+        int wv = (int)threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            double lo = wave_sum(mine && p == 0 ? sh.phi[m][x][cx] : 0.0);
+            double hi = wave_sum(mine && p == n - 1 ? sh.phi[m][x + 1][cx] : 0.0);
+            double wt = wave_sum(W[m]);
+            if ((threadIdx.x & 63) == 0) {
+                sh.red[m][wv] = lo;
+                sh.red[4 + m][wv] = hi;
+                sh.red[8 + m][wv] = wt;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 12) {
+            double v = sh.red[threadIdx.x][0];
+            for (int w = 1; w < PT_T / 64; w++) v += sh.red[threadIdx.x][w];
+            bs.base[bs.patch + 12 * lb + threadIdx.x] = v;
+        }
+    }
+    if (!mine) return;
+    int i = line, j = p;
+    int b = bidx(B, i, j), cap = S.cap;
+    size_t k = (size_t)j * g.nx + i;
+    double as = Ls.alpha[k], ae = Le.alpha[k];
+    double u2[4] = {0, 0, 0, 0};
+    if (c.has)
+        for (int m = 0; m < 4; m++) u2[m] = c.u1[m] + lam * ((sh.phi[m][x][cx] - sh.phi[m][x + 1][cx]) + W[m]);
+    int gone = 0;
+    if (as > 0.0 && ae == 0.0) {
+        gone = 1;
+    } else if (ae > 0.0 && c.has) {
+        double r = u2[0], e = u2[3];
+        if (!(r > 0.0) || !(e - 0.5 * (u2[1] * u2[1] + u2[2] * u2[2]) / r > 0.0)) {
+            gone = 2;
+            atomicAdd(ncollapse, 1u);
+        }
+    }
+    for (int m = 0; m < 4; m++) S.U2[m * cap + b] = u2[m];
+    S.gone[b] = (int8_t)gone;
+}
+
 // Content (conserved amounts) that is present but not an admissible gas state.
 __device__ __forceinline__ bool inadmissible_content(const double* u) {
     if (u[0] == 0.0 && u[1] == 0.0 && u[2] == 0.0 && u[3] == 0.0) return false;
