@@ -1539,6 +1539,17 @@ cc_status geometry_at(cc_ctx* c, double t, int slot) {
     return CC_OK;
 }
 
+// After the clock or the state is set: the current level is built at t, and so are the two
+// other level slots (a step rebuilds a slot over its previous cut-cell box joined with the
+// new one, and boxes left from another time, such as those of an earlier run of the same
+// context, would make that union exceed the region capacity).
+cc_status levels_at(cc_ctx* c, double t) {
+    cc_status st = geometry_at(c, t, c->s0);
+    for (int k = 0; k < 3 && st == CC_OK; k++)
+        if (k != c->s0 && !box_empty(c->lbox[k])) st = geometry_at(c, t, k);
+    return st;
+}
+
 cc_status not_in_batch(cc_ctx* c) {
     if (c->batch) return fail(c, CC_ERR_ARG, "the context is stepped by a batch");
     return CC_OK;
@@ -1598,7 +1609,7 @@ cc_status cc_set_state(cc_ctx* c, const double* d_prim, double t0) {
     c->cur = 0;
     // the status word starts clear before the level-n geometry (which may set bit 4)
     HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_status, 0, 4, c->stream));
-    cc_status st = geometry_at(c, t0, c->s0);
+    cc_status st = levels_at(c, t0);
     if (st != CC_OK) return st;
     const double* al = c->lev[c->s0].alpha;
     if (fp32(c))
@@ -1635,7 +1646,7 @@ cc_status cc_set_clock(cc_ctx* c, double t, int64_t step) {
     c->t = t;
     c->step = step;
     c->parity = (int)(step & 1);
-    cc_status st = geometry_at(c, t, c->s0);
+    cc_status st = levels_at(c, t);
     if (st != CC_OK) return st;
     if (has_body(c)) HIPCHK(c, hipMemsetAsync(c->ws + c->lay.off_stamp, 0xff, c->lay.nc * 4, c->stream));
     return CC_OK;

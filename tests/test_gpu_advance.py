@@ -193,3 +193,29 @@ def test_batch_advance_equals_members_advanced_alone(precision, timed):
         hb.remove(s)
     b.close()
     hb.close()
+
+
+def test_reset_of_an_advanced_context():
+    """cc_set_clock / cc_set_state on a context whose body has travelled far (its level
+    slots hold cut-cell boxes of a later time) start the run again exactly as a fresh
+    context: the same time steps and states, bit for bit, device- and host-planned."""
+    w = W.cylinder(nx=256, ny=128)
+    fresh = solver(w, cc.CC_FP64)
+    d_ref, _ = fresh.advance(40, w["cfl"])
+    u_ref = fresh.get_u()
+    fresh.close()
+    s = solver(w, cc.CC_FP64)
+    for reset in ("state", "clock", "host"):
+        s.advance(500, w["cfl"])
+        assert s.info()["t"] > 0.5  # the cylinder has moved more than 64 cells
+        if reset == "clock":
+            s.set_clock(0.0, 0)
+        s.set_prim(w["prim"])
+        if reset == "host":
+            for dt in d_ref:
+                s.step(dt)
+        else:
+            d, _ = s.advance(40, w["cfl"])
+            assert np.array_equal(np.asarray(d), np.asarray(d_ref)), reset
+        assert np.array_equal(s.get_u(), u_ref), reset
+    s.close()
