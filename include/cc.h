@@ -117,13 +117,15 @@ size_t cc_workspace_bytes_bodies(const cc_config* cfg, const cc_body* bodies, in
 cc_status cc_create_bodies(const cc_config* cfg, const cc_body* bodies, int32_t nbodies, void* d_ws, size_t ws_bytes,
                            void* hip_stream, cc_ctx** out);
 
-/* Initial state: body posed at time t0, level-n geometry built, U = alpha Q(prim).
+/* Initial state: body posed at time t0, level-n geometry built, U = alpha Q(prim); the
+ * clock starts at t0, step 0.  Also valid on a context that has already been stepped:
+ * every geometry slot is rebuilt at t0, so the run starts as on a fresh context.
  * d_prim: device, 4 planes (rho, u, v, p) of nx*ny doubles. */
 cc_status cc_set_state(cc_ctx* ctx, const double* d_prim, double t0);
 /* Resume the clock (restart from a saved state): time t after `step` completed split steps.
  * The next step sweeps x then y if `step` is even, y then x if odd (the alternation of
- * Sec. 2.3.1), and the level-n geometry is rebuilt with the body posed at t, so a state
- * saved from an uninterrupted run continues bit for bit.  The state itself is unchanged:
+ * Sec. 2.3.1), and the geometry (level n and the other two slots) is rebuilt with the body
+ * posed at t, so a state saved from an uninterrupted run continues bit for bit.  The state itself is unchanged:
  * set it afterwards with cc_set_u.  Errors: CC_ERR_ARG for step < 0 or non-finite t. */
 cc_status cc_set_clock(cc_ctx* ctx, double t, int64_t step);
 /* Replace the conserved state (device, 4 planes of nx*ny doubles, per unit cell volume). */
