@@ -249,6 +249,26 @@ def serving_request(k):
 
 
 # --------------------------------------------------------------------------- several bodies
+def wedges():
+    """Two static convex bodies facing each other across the open grid line x = 0.4 of the
+    unit square (10 x 10 cells, h = 0.1).  The left one's corner cuts cell (3, 5) in the
+    triangle (0.3, 0.5), (0.38, 0.5), (0.3, 0.57), and below it a vertical wall at x = 0.38
+    cuts column 3 from y = 0.25 to 0.5; the right one's corner cuts cell (4, 5) in the
+    triangle (0.43, 0.5), (0.5, 0.5), (0.5, 0.56), and its vertical wall at x = 0.43 cuts
+    column 4.  A smooth non-uniform state, so that the fluxes of neighbouring faces and the
+    walls differ."""
+    g = grid(10, 10, 0.0, 1.0, 0.0, 1.0)
+    a = np.array([[0.05, 0.25], [0.38, 0.25], [0.38, 0.5], [0.3, 0.57], [0.05, 0.57]])
+    b = np.array([[0.43, 0.25], [0.95, 0.25], [0.95, 0.56], [0.5, 0.56], [0.43, 0.5]])
+    X, Y = cell_centres(g)
+    prim = np.empty((4, 10, 10))
+    prim[0] = 1.0 + 0.3 * np.sin(7.0 * X + 3.0 * Y)
+    prim[1] = 0.4 + 0.3 * np.cos(5.0 * Y - 2.0 * X)
+    prim[2] = -0.3 + 0.2 * np.sin(4.0 * X * Y + 1.0)
+    prim[3] = 1.0 + 0.4 * np.cos(6.0 * X - 5.0 * Y)
+    return {"name": "wedges", "grid": g, "bodies": [body(a), body(b)], "prim": prim, "cfl": 0.8}
+
+
 def channel(ny=32, angle_deg=30.0, width=0.25, speed=0.5, flow=1.0, amp=0.5, sigma=0.1, cfl=0.5):
     """Sloped channel (Sec. 3.1): domain [-1.5, 1.5] x [-0.5, 0.5] (3 ny x ny square cells),
     two parallel walls at `angle_deg` to the x axis, `width` apart about the origin, both

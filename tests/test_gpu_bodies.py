@@ -103,6 +103,7 @@ def cases():
     yield "piston_tube", W.piston_tube(64)
     yield "diamonds", diamonds()
     yield "far_apart", far_apart()
+    yield "wedges", W.wedges()  # static; faces shielded from both sides (kappa of R2) in rows 4 and 5
 
 
 def pair(w, precision=cc.CC_FP64):

@@ -17,6 +17,10 @@ and two bodies in relative motion, the planar form of Sec. 3.5).
 * two mirror-image bodies approaching each other until under two cells separate them
   (faces shielded from both sides, for squares with the kappa scaling of R2) give a
   mirror-image flow;
+* faces shielded from both sides with s_L + s_R above the aperture (two static wedges
+  facing each other across an open face): the stabilised flux is the combination of the
+  face's flux and both cells' boundary fluxes whose weights follow by hand from the
+  geometry's closed forms and the kappa scaling of R2;
 * conservation: the change of each total over a sweep equals its budget (domain-boundary
   fluxes, wall terms, residuals without recipients);
 * two bodies inside one cell are reported (status bit 4).
@@ -201,3 +205,56 @@ def test_bodies_in_one_cell_are_reported():
     assert o2.status == 0
     cb = o2.cell_bodies(0)
     assert set(np.unique(cb)) == {-1, 0, 1}
+
+
+# faces shielded from both sides with s_L + s_R above the aperture (the kappa scaling of
+# reading R2), in the static two-wedge case; closed forms of the geometry by hand:
+#   row 5: cell (3, 5): outer aperture 0.3, the shared face open (1), alpha = 1 - 0.08 *
+#     0.07 / 2 / 0.01 = 0.72, shielded volume ahat = alpha - 0.3 = 0.42, s_L = 0.7; cell
+#     (4, 5): outer aperture 0.4, alpha = 1 - 0.07 * 0.06 / 2 / 0.01 = 0.79, ahat = 0.39,
+#     s_R = 0.6; kappa = 1 / 1.3:
+#     Phi = (1 - 0.49 / 1.3) F + (0.28 / 1.3) F^B_L + (0.21 / 1.3) F^B_R;
+#   row 4: cells (3, 4) | (4, 4) between the vertical walls at x = 0.38 and 0.43: outer
+#     apertures 0, alpha = ahat = 0.2 and 0.3, s_L = s_R = 1, kappa = 1/2:
+#     Phi = 0.25 F + 0.4 F^B_L + 0.35 F^B_R.
+# Each cell's boundary flux F^B is taken from a traced x sweep of that cell (the bodies do
+# not move, so both runs see the same face).
+WEDGE_FACES = {  # row: (alpha, low aperture, high aperture, ahat) of both cells, weights
+    5: ((0.72, 0.3, 1.0, 0.42), (0.79, 1.0, 0.4, 0.39), (1.0 - 0.49 / 1.3, 0.28 / 1.3, 0.21 / 1.3)),
+    4: ((0.2, 0.0, 1.0, 0.2), (0.3, 1.0, 0.0, 0.3), (0.25, 0.4, 0.35)),
+}
+
+
+def traced_x_sweep(w, i, j):
+    o = ref.Oracle(w["grid"], bodies=w["bodies"])
+    o.set_prim(w["prim"])
+    o.trace(i, j)
+    dt = 0.2 * o.cfl_dt(0.8)
+    o.begin_step(dt)  # step 0 sweeps x first
+    o.sweep(0, dt)
+    assert o.status == 0
+    return o.trace_get()
+
+
+@pytest.mark.parametrize("row", [5, 4])
+def test_both_sided_shielding_scales_to_the_aperture(row):
+    w = W.wedges()
+    cells, (w_f, w_l, w_r) = WEDGE_FACES[row][:2], WEDGE_FACES[row][2]
+    rl, rr = traced_x_sweep(w, 3, row), traced_x_sweep(w, 4, row)
+    for r, (alpha, lo, hi, ahat) in zip((rl, rr), cells):
+        assert r["wall"] and r["has"]
+        for key, val in (("alpha_s", alpha), ("alpha_e", alpha), ("bt_lo", lo), ("bt_hi", hi), ("ahat", ahat)):
+            assert abs(r[key] - val) < 1e-14, (row, key, r[key], val)
+    # the shared face seen from both cells
+    F, phi = rl["F_hi"], rl["phi_hi"]
+    assert np.array_equal(rr["F_lo"], F) and np.array_equal(rr["phi_lo"], phi)
+    FL, FR = rl["FB"], rr["FB"]
+    expect = w_f * F + w_l * FL + w_r * FR
+    scale = np.abs(F) + np.abs(FL) + np.abs(FR)
+    assert (np.abs(phi - expect) <= 8 * np.finfo(float).eps * scale).all(), (row, phi, expect)
+    # not vacuous: the three fluxes differ, and without the scaling (kappa = 1) the face
+    # would carry a visibly different flux
+    assert np.abs(F - FL).max() > 1e-3 and np.abs(F - FR).max() > 1e-3 and np.abs(FL - FR).max() > 1e-3
+    (_, lo_l, _, ah_l), (_, _, hi_r, ah_r) = cells
+    unscaled = F - (1.0 - lo_l - ah_l) * (F - FL) - (1.0 - hi_r - ah_r) * (F - FR)
+    assert np.abs(unscaled - phi).max() > 1e-2 * np.abs(phi).max()
