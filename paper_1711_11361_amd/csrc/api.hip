@@ -212,7 +212,7 @@ Layout make_layout(const cc_config* c, const cc_body* b, int nbodies = 1) {
     L.off_pstate = take(sizeof(PlanState));
     L.off_dtlog = take((size_t)DTLOG * 8);
     // budget: running sums, and the per-sweep slots (dense: two per line of either sweep;
-    // patch segments: 12 doubles each; covering blocks: 4 each)
+    // patch line segments and column tiles: 12 doubles each; covering blocks: 4 each)
     L.off_budget = take(16 * 8);
     size_t dense_slots = 2 * std::max(nx, ny);
     size_t patch_blocks = hasb ? (size_t)std::max(patch_line_blocks<0>(L.capw, L.caph), patch_tile_blocks(L.capw, L.caph)) : 1;
@@ -828,7 +828,7 @@ cc_status prepare_geometry(cc_ctx* c, double t, int slot, StepArgs& a) {
 int units_of(int, int n) { return n; }
 
 // Box launches take at most BOX_BLOCK_CAP blocks of T_BOX cells (BOXW_BLOCK_CAP of T_WIDE,
-// PATCH_BLOCK_CAP line segments) per member and loop over larger boxes; the persistent mode
+// PATCH_BLOCK_CAP patch segments or tiles) per member and loop over larger boxes; the persistent mode
 // walks the uncapped tables.
 constexpr int BOX_BLOCK_CAP = 2048, BOXW_BLOCK_CAP = 512, PATCH_BLOCK_CAP = 2048;
 

@@ -55,7 +55,7 @@ enum LaunchKind {
     L_S1, L_BOX, L_DX, L_DY,  // sweeps
     L_CS,  // volume fractions of both levels and the apertures of both sweeps
     L_BOXW,  // box cells, T_WIDE per block (launched beside the dense tiles)
-    L_PX, L_PY,  // box line segments of the x / y sweep's patch update
+    L_PX, L_PY,  // the patch update's blocks: box line segments (x sweep), column tiles (y sweep)
     NKINDS
 };
 constexpr int T_WIDE = 256;  // geometry and aperture stages, dense, time step
@@ -642,7 +642,7 @@ __device__ __forceinline__ void combine_speeds(const StepArgs& a, int ndense, in
 constexpr int T_FIX = 256;  // threads of the per-member collapse block
 
 // Adds the sweep's budget to the member's running sums: the fluxes through the domain
-// boundary (dense slots, then the patch segments' end faces) times dt/h and the cell
+// boundary (dense slots, then the patch blocks' end faces) times dt/h and the cell
 // area, the wall terms likewise, and the residuals without recipients (covering blocks,
 // then the collapse rounds' `lost` of each thread) times the cell area.  Each thread sums
 // a fixed subset of the slots, then the block adds the threads' sums in a fixed tree, so
