@@ -618,8 +618,10 @@ cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vect
 // region takes several passes: capacities follow the body's circumscribed circle, which
 // for a long body is far larger than its box), and for a many-sided body at least about
 // one wavefront per boundary item of the region (those take a wavefront's chain search
-// each); the geometry stages run both level jobs side by side, each on its own half.
-constexpr size_t GEO_BLOCK_CAP = 512;
+// each); the geometry stages run both level jobs side by side, each on its own half.  With
+// several bodies (no polygon staged per block, regions up to the whole grid) the cap is
+// higher.
+constexpr size_t GEO_BLOCK_CAP = 512, GEO_BLOCK_CAP_BODIES = 2048;
 enum GeoStage { GEO_VERTS, GEO_FACES, GEO_CELLS, GEO_SWEPT };
 int geo_blocks(const cc_ctx* c, GeoStage st) {
     const Layout& L = c->lay;
@@ -632,7 +634,8 @@ int geo_blocks(const cc_ctx* c, GeoStage st) {
         default: items = std::max((size_t)(L.capw + 1) * L.caph, (size_t)L.capw * (L.caph + 1)); break;
     }
     size_t walkers = c->m > SMALL_POLY ? std::min<size_t>(256, (size_t)(L.gw + L.gh)) : 0;
-    int b = (int)std::max<size_t>(std::min<size_t>(nblk(items, T_WIDE), GEO_BLOCK_CAP), walkers);
+    size_t most = c->nb > 1 ? GEO_BLOCK_CAP_BODIES : GEO_BLOCK_CAP;
+    int b = (int)std::max<size_t>(std::min<size_t>(nblk(items, T_WIDE), most), walkers);
     return st == GEO_SWEPT ? b : 2 * b;
 }
 
@@ -829,14 +832,15 @@ int units_of(int, int n) { return n; }
 
 // Box launches take at most BOX_BLOCK_CAP blocks of T_BOX cells (BOXW_BLOCK_CAP of T_WIDE,
 // PATCH_BLOCK_CAP patch segments or tiles) per member and loop over larger boxes; the persistent mode
-// walks the uncapped tables.
+// walks the uncapped tables.  Several bodies (boxes up to the whole grid): four times as many.
 constexpr int BOX_BLOCK_CAP = 2048, BOXW_BLOCK_CAP = 512, PATCH_BLOCK_CAP = 2048;
 
 int kind_blocks(const cc_ctx* c, const Engine& E, int kind) {
     const Layout& L = c->lay;
     int m = c->m;
     bool capped = E.mode != CC_LAUNCH_PERSISTENT;
-    auto cap = [&](int b, int most) { return capped ? std::min(b, most) : b; };
+    int scale = c->nb > 1 ? 4 : 1;
+    auto cap = [&](int b, int most) { return capped ? std::min(b, scale * most) : b; };
     if (!has_body(c) && (kind <= L_BOX || kind == L_CS || kind == L_PX || kind == L_PY)) return 0;
     switch (kind) {
         case L_POSE: return (int)nblk((size_t)m, T_WIDE);
