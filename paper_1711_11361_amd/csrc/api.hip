@@ -621,7 +621,7 @@ cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vect
 // each); the geometry stages run both level jobs side by side, each on its own half.  With
 // several bodies (no polygon staged per block, regions up to the whole grid) the cap is
 // higher.
-constexpr size_t GEO_BLOCK_CAP = 512, GEO_BLOCK_CAP_BODIES = 2048;
+constexpr size_t GEO_BLOCK_CAP = 256, GEO_BLOCK_CAP_BODIES = 2048;
 enum GeoStage { GEO_VERTS, GEO_FACES, GEO_CELLS, GEO_SWEPT };
 int geo_blocks(const cc_ctx* c, GeoStage st) {
     const Layout& L = c->lay;
