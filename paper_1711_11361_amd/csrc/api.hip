@@ -618,10 +618,11 @@ cc_status check_motion(cc_ctx* c, const std::vector<double>& p0, const std::vect
 // region takes several passes: capacities follow the body's circumscribed circle, which
 // for a long body is far larger than its box), and for a many-sided body at least about
 // one wavefront per boundary item of the region (those take a wavefront's chain search
-// each); the geometry stages run both level jobs side by side, each on its own half.  With
-// several bodies (no polygon staged per block, regions up to the whole grid) the cap is
-// higher.
-constexpr size_t GEO_BLOCK_CAP = 256, GEO_BLOCK_CAP_BODIES = 2048;
+// each); the geometry stages run both level jobs side by side, each on its own half.  The
+// face stage takes twice the cap of the others (measured on the 4096 x 4096 aerofoil, whose
+// blocks each stage a 1024-sided polygon); with several bodies (no polygon staged per
+// block, regions up to the whole grid) the cap is higher.
+constexpr size_t GEO_BLOCK_CAP = 256, GEO_BLOCK_CAP_FACES = 512, GEO_BLOCK_CAP_BODIES = 2048;
 enum GeoStage { GEO_VERTS, GEO_FACES, GEO_CELLS, GEO_SWEPT };
 int geo_blocks(const cc_ctx* c, GeoStage st) {
     const Layout& L = c->lay;
@@ -634,7 +635,7 @@ int geo_blocks(const cc_ctx* c, GeoStage st) {
         default: items = std::max((size_t)(L.capw + 1) * L.caph, (size_t)L.capw * (L.caph + 1)); break;
     }
     size_t walkers = c->m > SMALL_POLY ? std::min<size_t>(256, (size_t)(L.gw + L.gh)) : 0;
-    size_t most = c->nb > 1 ? GEO_BLOCK_CAP_BODIES : GEO_BLOCK_CAP;
+    size_t most = c->nb > 1 ? GEO_BLOCK_CAP_BODIES : (st == GEO_FACES ? GEO_BLOCK_CAP_FACES : GEO_BLOCK_CAP);
     int b = (int)std::max<size_t>(std::min<size_t>(nblk(items, T_WIDE), most), walkers);
     return st == GEO_SWEPT ? b : 2 * b;
 }
